@@ -1,0 +1,541 @@
+/*
+ * mcts.c -- CPU oracle of the simplified Monte Carlo Tree Search for the
+ * Da Vinci Code game (Sec. II-B and Sec. III-A of the paper).
+ *
+ * TEST INFRASTRUCTURE ONLY (see oracle.h).
+ *
+ * The four MCTS steps (selection, expansion, simulation, backpropagation)
+ * with the paper's three simplifications:
+ *   1. a node is only (tile position, guessed number); the sampled set of
+ *      plausible opponent numbers is not part of the node;
+ *   2. guessing stops after a right guess inside the tree;
+ *   3. nodes at a fixed depth threshold are not expanded further: they only
+ *      simulate and back up.
+ * The opponent tiles are a black box to the searching player, so every
+ * iteration first samples a plausible set of numbers for them (Sec. III-A);
+ * the tree is open loop over those samples.
+ *
+ * Selection uses UCT (Kocsis & Szepesvari 2006) evaluated in single precision
+ * with one IEEE rounding per operation, in this order:
+ *     n = float(N_c); q = W_c / n; e = LN[N_parent] / n; u = c * sqrt(e);
+ *     score = q + u
+ * where LN[k] = float(log(double(k))); the first child in creation order
+ * with the strictly greatest score wins.  Build with -ffp-contract=off.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+int oracle_unpack(const orc_packed *s, orc_rows *r);
+void oracle_pack(const orc_rows *r, orc_packed *s);
+
+/* local copies of the small row helpers (rules.c keeps its own static ones) */
+static int hidden_count(const orc_rows *s, int q)
+{
+    int c = 0;
+    for (int j = 0; j < s->n[q]; ++j) c += !s->rev[q][j];
+    return c;
+}
+
+static int alive_count(const orc_rows *s)
+{
+    int c = 0;
+    for (int q = 0; q < s->P; ++q) c += hidden_count(s, q) > 0;
+    return c;
+}
+
+static int first_alive(const orc_rows *s)
+{
+    for (int q = 0; q < s->P; ++q)
+        if (hidden_count(s, q) > 0) return q;
+    return -1;
+}
+
+static int next_alive_after(const orc_rows *s, int m)
+{
+    for (int k = 1; k <= s->P; ++k) {
+        int q = (m + k) % s->P;
+        if (hidden_count(s, q) > 0) return q;
+    }
+    return -1;
+}
+
+static int owner_of(const orc_rows *s, int t, int *slot)
+{
+    for (int q = 0; q < s->P; ++q)
+        for (int j = 0; j < s->n[q]; ++j)
+            if (s->tile[q][j] == t) {
+                if (slot) *slot = j;
+                return q;
+            }
+    return -1;
+}
+
+static void row_insert(orc_rows *s, int q, int t)
+{
+    int j = s->n[q];
+    while (j > 0 && s->tile[q][j - 1] > t) {
+        s->tile[q][j] = s->tile[q][j - 1];
+        s->rev[q][j] = s->rev[q][j - 1];
+        --j;
+    }
+    s->tile[q][j] = t;
+    s->rev[q][j] = 0;
+    s->n[q]++;
+}
+
+static void philox_block(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                         uint32_t out[4])
+{
+    uint32_t key[2] = {(uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32)};
+    uint32_t ctr[4] = {c0, c1, c2, c3};
+    oracle_philox(ctr, key, out);
+}
+
+/* ------------------------------------------------------------------------ */
+/* determinization                                                           */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    uint64_t seed;
+    uint32_t c1, c2, c3;
+    uint32_t n;
+} dstream;
+
+static uint32_t ds_next(dstream *d)
+{
+    uint32_t b[4];
+    philox_block(d->seed, d->n >> 2, d->c1, d->c2, d->c3, b);
+    uint32_t w = b[d->n & 3];
+    d->n++;
+    return w;
+}
+
+/* One attempt of the sampler.  For every opponent (seat order from the
+ * mover's left) and every maximal run of hidden slots between two revealed
+ * tiles (lo, hi) of its row:
+ *   right to left, U_j = largest available tile of the slot's colour below
+ *   U_{j+1} (U_{k+1} = hi) -- the largest value the slot can take while the
+ *   slots to its right can still be filled;
+ *   left to right, t_j is uniform among the available tiles of its colour in
+ *   (t_{j-1}, U_j], t_0 = lo.
+ * "Available" means: not in the mover's row, not revealed, not yet used.
+ * Returns 0 on success, 1 when some opponent's run cannot be filled.        */
+static int det_attempt(const orc_rows *root, dstream *ds, orc_rows *world)
+{
+    *world = *root;
+    int M = root->mover;
+    int avail[24];
+    for (int t = 0; t < 24; ++t) avail[t] = 1;
+    for (int q = 0; q < root->P; ++q)
+        for (int j = 0; j < root->n[q]; ++j)
+            if (q == M || root->rev[q][j]) avail[root->tile[q][j]] = 0;
+    for (int k = 1; k < root->P; ++k) {
+        int o = (M + k) % root->P;
+        int j = 0;
+        while (j < root->n[o]) {
+            if (root->rev[o][j]) { ++j; continue; }
+            int a = j;
+            while (j < root->n[o] && !root->rev[o][j]) ++j;
+            int b = j;
+            int lo = a > 0 ? root->tile[o][a - 1] : -1;
+            int hi = b < root->n[o] ? root->tile[o][b] : 24;
+            int len = b - a;
+            int U[25];
+            U[len] = hi;
+            for (int i = len - 1; i >= 0; --i) {
+                int c = root->tile[o][a + i] & 1;
+                int best = -1;
+                for (int x = 0; x < U[i + 1]; ++x)
+                    if (avail[x] && (x & 1) == c) best = x;
+                if (best < 0) return 1;
+                U[i] = best;
+            }
+            if (U[0] <= lo) return 1;
+            int prev = lo;
+            for (int i = 0; i < len; ++i) {
+                int c = root->tile[o][a + i] & 1;
+                int cand[24], nc = 0;
+                for (int x = prev + 1; x <= U[i]; ++x)
+                    if (avail[x] && (x & 1) == c) cand[nc++] = x;
+                int x = cand[oracle_mulshift(ds_next(ds), (uint32_t)nc)];
+                world->tile[o][a + i] = x;
+                avail[x] = 0;
+                prev = x;
+            }
+        }
+    }
+    world->pile_n = 0;
+    for (int t = 0; t < 24; ++t)
+        if (avail[t]) world->pile[world->pile_n++] = t;
+    return 0;
+}
+
+/* Deterministic fallback: the lexicographically smallest consistent
+ * assignment of all hidden opponent slots (opponents in seat order from the
+ * mover's left, slots left to right), found by depth-first search that tries
+ * the lowest tile first.  The true deal is consistent, so it always exists. */
+typedef struct {
+    int o, j, colour, lo, hi, seg_start;
+} dslot;
+
+static int dfs(dslot *sl, int ns, int k, int *avail, int *assign)
+{
+    if (k == ns) return 1;
+    int prev = sl[k].seg_start ? sl[k].lo : assign[k - 1];
+    for (int x = prev + 1; x < sl[k].hi; ++x) {
+        if (!avail[x] || (x & 1) != sl[k].colour) continue;
+        avail[x] = 0;
+        assign[k] = x;
+        if (dfs(sl, ns, k + 1, avail, assign)) return 1;
+        avail[x] = 1;
+    }
+    return 0;
+}
+
+static int det_fallback(const orc_rows *root, orc_rows *world)
+{
+    *world = *root;
+    int M = root->mover;
+    int avail[24];
+    for (int t = 0; t < 24; ++t) avail[t] = 1;
+    for (int q = 0; q < root->P; ++q)
+        for (int j = 0; j < root->n[q]; ++j)
+            if (q == M || root->rev[q][j]) avail[root->tile[q][j]] = 0;
+    dslot sl[24];
+    int ns = 0;
+    for (int k = 1; k < root->P; ++k) {
+        int o = (M + k) % root->P;
+        for (int j = 0; j < root->n[o]; ++j) {
+            if (root->rev[o][j]) continue;
+            int lo = -1, hi = 24;
+            for (int a = j - 1; a >= 0; --a)
+                if (root->rev[o][a]) { lo = root->tile[o][a]; break; }
+            for (int a = j + 1; a < root->n[o]; ++a)
+                if (root->rev[o][a]) { hi = root->tile[o][a]; break; }
+            sl[ns].o = o;
+            sl[ns].j = j;
+            sl[ns].colour = root->tile[o][j] & 1;
+            sl[ns].lo = lo;
+            sl[ns].hi = hi;
+            sl[ns].seg_start = (j == 0 || root->rev[o][j - 1]);
+            ++ns;
+        }
+    }
+    int assign[24];
+    if (!dfs(sl, ns, 0, avail, assign)) return 1;
+    for (int k = 0; k < ns; ++k) world->tile[sl[k].o][sl[k].j] = assign[k];
+    world->pile_n = 0;
+    for (int t = 0; t < 24; ++t)
+        if (avail[t]) world->pile[world->pile_n++] = t;
+    return 0;
+}
+
+static int determinize_rows(const orc_rows *root, uint64_t seed, uint32_t tree, uint32_t iter,
+                            orc_rows *world)
+{
+    for (uint32_t a = 0; a < 16; ++a) {
+        dstream ds = {seed, 0x80000000u + a, iter, tree, 0};
+        if (det_attempt(root, &ds, world) == 0) return (int)a;
+    }
+    if (det_fallback(root, world) == 0) return 16;
+    return -3;
+}
+
+int oracle_determinize(const orc_packed *root, uint64_t seed, uint32_t tree, uint32_t iter,
+                       orc_packed *world)
+{
+    if (oracle_validate(root)) return -2;
+    orc_rows r, w;
+    oracle_unpack(root, &r);
+    int a = determinize_rows(&r, seed, tree, iter, &w);
+    if (a >= 0) oracle_pack(&w, world);
+    return a;
+}
+
+/* ------------------------------------------------------------------------ */
+/* actions                                                                    */
+/* ------------------------------------------------------------------------ */
+/* action id = ((r-1)*24 + s)*12 + v: target seat (mover + r) mod P, slot s of
+ * the target row at guess time, guessed value v (the colour is the slot's). */
+static void legal_rows(const orc_rows *s, uint8_t *legal)
+{
+    memset(legal, 0, ORC_MAX_CHILD);
+    int m = s->mover;
+    int mine[24] = {0}, revd[24] = {0};
+    for (int j = 0; j < s->n[m]; ++j) mine[s->tile[m][j]] = 1;
+    for (int q = 0; q < s->P; ++q)
+        for (int j = 0; j < s->n[q]; ++j)
+            if (s->rev[q][j]) revd[s->tile[q][j]] = 1;
+    for (int r = 1; r < s->P; ++r) {
+        int q = (m + r) % s->P;
+        if (hidden_count(s, q) == 0) continue;
+        for (int j = 0; j < s->n[q]; ++j) {
+            if (s->rev[q][j]) continue;
+            int c = s->tile[q][j] & 1;
+            int lo = -1, hi = 24;
+            for (int a = j - 1; a >= 0; --a)
+                if (s->rev[q][a]) { lo = s->tile[q][a]; break; }
+            for (int a = j + 1; a < s->n[q]; ++a)
+                if (s->rev[q][a]) { hi = s->tile[q][a]; break; }
+            for (int v = 0; v < 12; ++v) {
+                int x = 2 * v + c;
+                if (x <= lo || x >= hi || mine[x] || revd[x]) continue;
+                legal[((r - 1) * 24 + j) * 12 + v] = 1;
+            }
+        }
+    }
+}
+
+int oracle_legal_actions(const orc_packed *ps, uint8_t legal[ORC_MAX_CHILD])
+{
+    if (oracle_validate(ps)) return -2;
+    orc_rows s;
+    oracle_unpack(ps, &s);
+    legal_rows(&s, legal);
+    return 0;
+}
+
+/* Apply a guess inside the tree (simplification 2: the turn ends after it).
+ * Chance comes from block (depth, 0xC0000000, iter, tree): word 0 picks the
+ * mover's own tile to reveal after a wrong guess when nothing was drawn,
+ * word 1 is the next player's draw.  Returns 1 if the game ended.          */
+static int apply_rows(orc_rows *s, int action, uint64_t seed, uint32_t tree, uint32_t iter,
+                      uint32_t depth, int *winner)
+{
+    uint32_t w[4];
+    philox_block(seed, depth, 0xC0000000u, iter, tree, w);
+    int m = s->mover;
+    int r = action / 288 + 1, slot = (action / 12) % 24, v = action % 12;
+    int q = (m + r) % s->P;
+    int t = s->tile[q][slot];
+    int guess = 2 * v + (t & 1);
+    if (guess == t) {
+        s->rev[q][slot] = 1;
+    } else if (s->drawn >= 0) {
+        int j = 0, o = owner_of(s, s->drawn, &j);
+        s->rev[o][j] = 1;
+    } else {
+        int H[24], nH = 0, Hj[24];
+        for (int j = 0; j < s->n[m]; ++j)
+            if (!s->rev[m][j]) { Hj[nH] = j; H[nH++] = s->tile[m][j]; }
+        (void)H;
+        s->rev[m][Hj[oracle_mulshift(w[0], (uint32_t)nH)]] = 1;
+    }
+    if (alive_count(s) == 1) {
+        *winner = first_alive(s);
+        s->phase = 1;
+        s->drawn = -1;
+        return 1;
+    }
+    int nm = next_alive_after(s, m);
+    s->mover = nm;
+    s->phase = 1;
+    s->drawn = -1;
+    if (s->pile_n > 0) {
+        int k = (int)oracle_mulshift(w[1], (uint32_t)s->pile_n);
+        int d = s->pile[k];
+        for (int j = k; j + 1 < s->pile_n; ++j) s->pile[j] = s->pile[j + 1];
+        s->pile_n--;
+        row_insert(s, nm, d);
+        s->drawn = d;
+    }
+    *winner = -1;
+    return 0;
+}
+
+int oracle_apply_action(const orc_packed *ps, int action, uint64_t seed, uint32_t tree,
+                        uint32_t iter, uint32_t depth, orc_packed *out, int *terminal,
+                        int *winner)
+{
+    if (oracle_validate(ps)) return -2;
+    if (action < 0 || action >= ORC_MAX_CHILD) return -1;
+    orc_rows s;
+    oracle_unpack(ps, &s);
+    uint8_t legal[ORC_MAX_CHILD];
+    legal_rows(&s, legal);
+    if (!legal[action]) return -1;
+    *terminal = apply_rows(&s, action, seed, tree, iter, depth, winner);
+    oracle_pack(&s, out);
+    return 0;
+}
+
+float oracle_ln_entry(uint32_t k)
+{
+    return (float)log((double)k);
+}
+
+/* ------------------------------------------------------------------------ */
+/* search                                                                     */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int action, chooser;
+    uint32_t N;
+    float W;
+    int nchild, cap;
+    int *child;
+    uint8_t *has; /* per action id: 1 if a child with that action exists */
+} onode;
+
+typedef struct {
+    onode *v;
+    int n, cap;
+} otree;
+
+static int tree_new_node(otree *t, int action, int chooser)
+{
+    if (t->n == t->cap) {
+        t->cap = t->cap ? 2 * t->cap : 64;
+        t->v = (onode *)realloc(t->v, (size_t)t->cap * sizeof(onode));
+    }
+    onode *x = &t->v[t->n];
+    memset(x, 0, sizeof(*x));
+    x->action = action;
+    x->chooser = chooser;
+    return t->n++;
+}
+
+static void node_add_child(otree *t, int parent, int child)
+{
+    onode *p = &t->v[parent];
+    if (!p->has) p->has = (uint8_t *)calloc(ORC_MAX_CHILD, 1);
+    if (p->nchild == p->cap) {
+        p->cap = p->cap ? 2 * p->cap : 8;
+        p->child = (int *)realloc(p->child, (size_t)p->cap * sizeof(int));
+    }
+    p->child[p->nchild++] = child;
+    p->has[t->v[child].action] = 1;
+}
+
+static void tree_free(otree *t)
+{
+    for (int i = 0; i < t->n; ++i) {
+        free(t->v[i].child);
+        free(t->v[i].has);
+    }
+    free(t->v);
+}
+
+int rollout_rows_wins(const orc_rows *leaf, int32_t ppl, uint64_t seed, uint32_t leaf_id,
+                      uint32_t tree_id, uint32_t wins[4]);
+
+static int search_one(const orc_rows *root, const orc_mcts_params *mp, uint64_t seed,
+                      uint32_t tr, const float *LN, int32_t *best_action,
+                      orc_child_stat *children_out)
+{
+    otree T = {0};
+    tree_new_node(&T, -1, -1);
+    int ppl = mp->playouts_per_leaf;
+    int path[64];
+    uint8_t legal[ORC_MAX_CHILD];
+    for (int i = 0; i < mp->iterations; ++i) {
+        orc_rows S;
+        if (determinize_rows(root, seed, tr, (uint32_t)i, &S) < 0) {
+            tree_free(&T);
+            return -3;
+        }
+        int node = 0, depth = 0, np = 0, terminal = 0, winner = -1;
+        path[np++] = 0;
+        for (;;) {
+            if (terminal) break;
+            if (depth >= mp->max_depth) break;
+            legal_rows(&S, legal);
+            onode *X = &T.v[node];
+            int expand = -1;
+            for (int a = 0; a < ORC_MAX_CHILD; ++a)
+                if (legal[a] && !(X->has && X->has[a])) { expand = a; break; }
+            if (expand >= 0) {
+                int c = tree_new_node(&T, expand, S.mover);
+                node_add_child(&T, node, c);
+                terminal = apply_rows(&S, expand, seed, tr, (uint32_t)i, (uint32_t)depth, &winner);
+                path[np++] = c;
+                break;
+            }
+            /* selection: strictly greater score wins, so ties keep the
+               earliest-created child */
+            X = &T.v[node];
+            float Lp = LN[X->N];
+            int best = -1;
+            float best_s = 0.0f;
+            for (int k = 0; k < X->nchild; ++k) {
+                onode *c = &T.v[X->child[k]];
+                if (!legal[c->action]) continue;
+                float n = (float)c->N;
+                float q = c->W / n;
+                float e = Lp / n;
+                float u = mp->c_uct * sqrtf(e);
+                float s = q + u;
+                if (best < 0 || s > best_s) { best = X->child[k]; best_s = s; }
+            }
+            terminal = apply_rows(&S, T.v[best].action, seed, tr, (uint32_t)i, (uint32_t)depth, &winner);
+            node = best;
+            path[np++] = best;
+            ++depth;
+        }
+        uint32_t wins[4] = {0, 0, 0, 0};
+        if (terminal) {
+            wins[winner] = (uint32_t)ppl;
+        } else {
+            rollout_rows_wins(&S, ppl, seed, (uint32_t)i, tr, wins);
+        }
+        for (int k = 0; k < np; ++k) {
+            onode *x = &T.v[path[k]];
+            x->N += (uint32_t)ppl;
+            if (k > 0) x->W += (float)wins[x->chooser];
+        }
+    }
+    onode *R = &T.v[0];
+    int best = -1;
+    uint32_t bestN = 0;
+    for (int k = 0; k < R->nchild; ++k) {
+        onode *c = &T.v[R->child[k]];
+        if (best < 0 || c->N > bestN) { best = k; bestN = c->N; }
+    }
+    *best_action = best >= 0 ? T.v[R->child[best]].action : -1;
+    if (children_out) {
+        for (int k = 0; k < ORC_MAX_CHILD; ++k) {
+            children_out[k].action = 0xFFFF;
+            children_out[k].pad = 0;
+            children_out[k].n = 0;
+            children_out[k].w = 0.0f;
+        }
+        for (int k = 0; k < R->nchild; ++k) {
+            onode *c = &T.v[R->child[k]];
+            children_out[k].action = (uint16_t)c->action;
+            children_out[k].n = c->N;
+            children_out[k].w = c->W;
+        }
+    }
+    tree_free(&T);
+    return 0;
+}
+
+int oracle_mcts_search(const orc_packed *roots, int64_t n_trees, const orc_mcts_params *mp,
+                       uint64_t seed, uint32_t tree_id_base, int32_t *best_action,
+                       orc_child_stat *root_children)
+{
+    if (n_trees < 0 || mp->iterations < 1 || mp->playouts_per_leaf < 1 || mp->max_depth < 1 ||
+        mp->max_depth > 32 || mp->leaf_eval != 0)
+        return -1;
+    for (int64_t t = 0; t < n_trees; ++t) {
+        if (oracle_validate(&roots[t])) return -2;
+        orc_rows r;
+        oracle_unpack(&roots[t], &r);
+        if (alive_count(&r) < 2) return -2;
+        if (r.phase == 0 && r.pile_n > 0) return -2;
+    }
+    uint64_t nln = (uint64_t)mp->iterations * (uint64_t)mp->playouts_per_leaf + 1;
+    float *LN = (float *)malloc(nln * sizeof(float));
+    LN[0] = 0.0f;
+    for (uint64_t k = 1; k < nln; ++k) LN[k] = oracle_ln_entry((uint32_t)k);
+    int rc = 0;
+    for (int64_t t = 0; t < n_trees && rc == 0; ++t) {
+        orc_rows r;
+        oracle_unpack(&roots[t], &r);
+        rc = search_one(&r, mp, seed, tree_id_base + (uint32_t)t, LN, &best_action[t],
+                        root_children ? root_children + t * ORC_MAX_CHILD : NULL);
+    }
+    free(LN);
+    return rc;
+}
