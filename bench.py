@@ -1,0 +1,151 @@
+"""Benchmark: leaf-parallel random-playout throughput on one MI355X.
+
+Workload (leaf-parallel rollout): 4096 synthetic mid-game two-player leaf
+states (pool 0-16 tiles, 0-8 tiles revealed per row, turn start), 256
+uniform-random playouts each = 1,048,576 playouts per step.  One step is one
+pass of the hot path over that batch: generate the leaf states on the GPU
+(dvc_init_states), then run every playout with per-playout winner (int8),
+game length (int16) and per-leaf seat wins (dvc_rollout).  Inputs are
+synthetic and resident in HBM before timing starts.
+
+Prints one JSON line.  `value` is playouts/s of the whole step; `roofline`
+prices the dominant kernel (the persistent rollout kernel) against the
+integer-VALU issue peak of the chip; `cpu_baseline` is the CPU oracle timed
+on this host's cores on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+N_LEAVES, PPL, SEED = 4096, 256, 2
+DEAL = dict(p_min=2, p_max=2, pile_min=0, pile_max=16, revealed_max=8)
+
+# Peak integer VALU issue rate of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+INT_VALU_PEAK = 256 * 4 * 16 * 2.4e9          # lane-ops/s
+# One guess step of the rollout kernel as compiled for gfx950:
+# 315 VALU instructions, 20 of them quarter-rate 32x32->64 multiplies, which
+# occupy four issue slots each.
+OPS_PER_GUESS = 315 + 3 * 20
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--variant", type=int, default=0)
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--grid", type=int, default=0)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    return ap.parse_args()
+
+
+def cpu_baseline(states_np, threads):
+    """The oracle, as it stands, on this host: all 4096 leaves x 256 playouts,
+    leaves split over `threads` POSIX threads."""
+    import oracle
+    oracle.rollout(states_np[:64], 16, SEED)          # load + warm
+    t0 = time.perf_counter()
+    _, _, wins = oracle.rollout(states_np, PPL, SEED, threads=threads, want_winner=False,
+                                want_length=False)
+    dt = time.perf_counter() - t0
+    n = states_np.shape[0] * PPL
+    return {"value": n / dt, "unit": "playouts/s", "cores": threads, "kind": "oracle",
+            "sample": f"{states_np.shape[0]} leaves x {PPL} playouts (the full batch), "
+                      f"{threads} threads, {dt:.2f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2403_10720_amd as D
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    params = D.deal_params(**DEAL)
+    total = N_LEAVES * PPL
+    states = torch.empty((N_LEAVES, 4), dtype=torch.int32, device=dev)
+    winner = torch.empty(total, dtype=torch.int8, device=dev)
+    length = torch.empty(total, dtype=torch.int16, device=dev)
+    wins = torch.empty((N_LEAVES, 4), dtype=torch.int32, device=dev)
+
+    def step(ev=None):
+        D.dvc_init_states(N_LEAVES, params, SEED, out=states)
+        if ev is not None:
+            ev[0].record(stream)
+        D.dvc_rollout(states, PPL, SEED, 0, 0, winner=winner, length=length, seat_wins=wins,
+                      variant=args.variant, block=args.block, grid=args.grid)
+        if ev is not None:
+            ev[1].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    rc = D.dvc_check()
+    if rc != 0:
+        raise RuntimeError(f"device error {rc}")
+    guesses = int(length.to(torch.int64).sum().item())
+    lens = length.float()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    stop.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_total = start.elapsed_time(stop)
+    kern_ms = [a.elapsed_time(b) for a, b in evs]
+    ms_step = ms_total / args.steps
+    kern_avg_s = sum(kern_ms) / len(kern_ms) / 1e3
+    value = total / (ms_step / 1e3)
+    achieved = guesses * OPS_PER_GUESS / kern_avg_s
+    out = {
+        "metric": "playouts/sec (leaf-parallel random playouts, Da Vinci Code MCTS simulation step)",
+        "value": value,
+        "unit": "playouts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic (Philox-generated game states)",
+        "config": {"workload": "leaf-parallel rollout: 4096 two-player mid-game leaves x 256 "
+                               "playouts (pool 0-16, 0-8 revealed per row)",
+                   "leaves": N_LEAVES, "playouts_per_leaf": PPL, "seed": SEED,
+                   "variant": args.variant or 2, "block": args.block, "grid": args.grid},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": INT_VALU_PEAK,
+                     "unit": "int lane-ops/s", "frac": achieved / INT_VALU_PEAK,
+                     "traffic": None},
+        "rollout_kernel_ms": kern_avg_s * 1e3,
+        "guess_steps_per_launch": guesses,
+        "mean_game_length": float(lens.mean().item()),
+        "wall_s": wall,
+    }
+    if not args.no_cpu:
+        threads = max(1, min(16, os.cpu_count() or 1))
+        out["cpu_baseline"] = cpu_baseline(states.cpu().numpy().view(np.uint32), threads)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

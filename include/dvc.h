@@ -1,0 +1,209 @@
+/*
+ * dvc.h -- C ABI of the MI355X (gfx950) Da Vinci Code Monte Carlo Tree
+ * Search engine: synthetic states, massively parallel random playouts and
+ * the tree search that feeds them leaves.
+ *
+ * Method: Zhang et al., "Development and Application of a Monte Carlo Tree
+ * Search Algorithm for Simulating Da Vinci Code Game Strategies",
+ * arXiv 2403.10720.  Game rules: Sec. II-A; MCTS and random playouts:
+ * Sec. II-B; simplified search (node = tile position + guessed number, no
+ * further guess after a right guess inside the tree, fixed expansion depth):
+ * Sec. III-A; per-thread simulations merged into one tree: Sec. III-B..D.
+ *
+ * Conventions for every entry point
+ *   - Buffers are device memory owned by the caller (for example torch
+ *     tensors), unless a comment says "host".  The library never frees them.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the default
+ *     stream.  Calls enqueue work on it and return without waiting.
+ *   - Return value: DVC_OK (0) or a negative dvc_status.  Argument errors are
+ *     detected on the host and returned at once, with nothing enqueued.
+ *     Errors found by a kernel (a malformed state) set a sticky per-device
+ *     error word that dvc_check() returns (and clears) after synchronising.
+ *   - Outputs are a pure function of the inputs, the seed and the id bases:
+ *     they do not depend on the launch shape, on the batch a leaf or tree is
+ *     part of, or on the stream.
+ *   - The library prints nothing and never aborts.
+ *
+ * Random numbers: Philox4x32-10 (Salmon et al., SC'11) with key
+ * (seed & 0xFFFFFFFF, seed >> 32).  A pick among k options from a word w is
+ * floor(w * k / 2^32).  Counter layouts (c0, c1, c2, c3):
+ *   guess step g of playout p of leaf l of tree tr      (g, p, l, tr)
+ *     word 0 draw, word 1 target tile, word 2 guessed value,
+ *     word 3 continue coin (go on iff w3 < 2^31) or own tile to reveal;
+ *     a word whose choice does not arise is skipped, never shifted.
+ *   determinization attempt a of iteration i, word n   (n>>2, 0x80000000+a, i, tr)
+ *   in-tree guess at depth d of iteration i             (d, 0xC0000000, i, tr)
+ *     word 0 own tile to reveal, word 1 next player's draw
+ *   synthetic state s, word n                           (n>>2, 0xFFFFFFFF, 0xFFFFFFFF, s)
+ */
+#ifndef DVC_H
+#define DVC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------------------
+ * Packed game state, 16 bytes (Sec. II-A: 24 numbered tiles, values 0..11 in
+ * black and white; every player keeps an ascending row; colours are public).
+ *
+ * Tile id t = 2*value + colour (0 black, 1 white), so ids sort by value and
+ * black sorts before white on equal values.  A row is the set of tile ids a
+ * player owns; its order is implied by the ids.
+ *   w[0..2] bits 0-23 : bit-plane k of the 3-bit owner code of tile t
+ *                       (0 = draw pool, 1..4 = seat 0..3)
+ *   w[3]    bits 0-23 : revealed tiles
+ *   w[0]    bits 24-25: seat to move; 26-27: players - 1 (2..4 players);
+ *           bit 28: phase (0 = turn start, 1 = the mover has had its draw);
+ *           bit 29: a drawn tile is recorded
+ *   w[1]    bits 24-28: the drawn tile id (zero when none is recorded)
+ *   all other bits are zero.
+ * Valid state: owner codes <= players; pool tiles are not revealed; the mover
+ * has a hidden tile; phase 0 records no drawn tile; a recorded drawn tile is
+ * a hidden tile of the mover.  A state where only one player has hidden tiles
+ * is valid and already decided.
+ * ------------------------------------------------------------------------- */
+typedef struct { uint32_t w[4]; } dvc_state_t;
+
+enum dvc_status {
+    DVC_OK = 0,
+    DVC_EINVAL = -1,  /* bad argument (size, pointer, parameter)            */
+    DVC_ESTATE = -2,  /* a malformed packed state was found                 */
+    DVC_EHIP = -3,    /* a HIP runtime call failed                          */
+    DVC_ENOMEM = -4,  /* workspace too small / library allocation failed    */
+    DVC_ELIMIT = -5   /* a kernel hit an internal bound                     */
+};
+
+/* Parameters of the synthetic state generator.
+ * A deal gives every player hand[P] tiles (Sec. II-A: four tiles); beyond the
+ * deal, a pool size is drawn, the tiles drawn since the deal are handed out
+ * round-robin from seat 0, and a random number of every row's tiles is
+ * revealed, always leaving one hidden.                                      */
+typedef struct {
+    int32_t p_min, p_max;       /* players, uniform in [p_min, p_max], 2..4         */
+    int32_t hand[5];            /* tiles dealt per player, indexed by player count  */
+    int32_t pile_min, pile_max; /* pool size, uniform, capped at 24 - P*hand[P]     */
+    int32_t revealed_max;       /* revealed tiles per row, uniform in 0..min(this, h-1) */
+    int32_t fresh;              /* 1: fresh deal (full pool, nothing revealed)      */
+    int32_t root_draw;          /* 1: the seat to move draws (phase 1)              */
+    int32_t phase_mix;          /* 1: it draws with probability 1/2                 */
+} dvc_deal_params;
+
+/* dvc_init_states -- write n synthetic states out[0..n) for state indices
+ * index_base .. index_base+n-1 (word stream of state s above).  Sec. II-A
+ * deal, extended to mid-game positions.  `out` is device memory of n*16 B.
+ * Returns DVC_EINVAL for n < 0, a NULL out with n > 0, or parameters outside
+ * the ranges above.                                                          */
+int dvc_init_states(dvc_state_t *out, int64_t n, const dvc_deal_params *params /* host */,
+                    uint64_t seed, uint32_t index_base, void *stream);
+
+/* dvc_rollout -- random playouts (Sec. II-B: the game is played out by taking
+ * every decision at random) from n_leaves leaf states, playouts_per_leaf each.
+ * Playout p of leaf i uses leaf id l = leaf_id_base + i and tree id tree_id.
+ * One guess step:
+ *   at turn start the mover draws a uniformly random pool tile (if any);
+ *   the target is uniform over the hidden tiles of all other players, pooled,
+ *   in ascending id order; the guessed value is uniform over the tile ids of
+ *   the target's colour strictly between the nearest revealed tiles around it
+ *   in its row that are neither in the mover's row nor revealed;
+ *   a right guess reveals the target and the mover goes on with probability
+ *   1/2; a wrong guess reveals the mover's drawn tile, or a uniformly random
+ *   hidden tile of its own when it drew nothing, and ends the turn; a player
+ *   without hidden tiles is out; the next player in seat order still in moves.
+ * Outputs (each may be NULL):
+ *   winner[i*ppl + p]  int8   absolute seat of the last player standing
+ *   length[i*ppl + p]  int16  number of guesses (= tiles revealed)
+ *   seat_wins[i*4 + s] uint32 playouts of leaf i won by seat s
+ * A malformed leaf yields winner -1, length -1, no wins, and DVC_ESTATE in the
+ * error word.  Returns DVC_EINVAL for n_leaves < 0, playouts_per_leaf < 1,
+ * n_leaves*playouts_per_leaf >= 2^40 or leaves == NULL with n_leaves > 0.  */
+int dvc_rollout(const dvc_state_t *leaves, int64_t n_leaves, int32_t playouts_per_leaf,
+                uint64_t seed, uint32_t tree_id, uint32_t leaf_id_base,
+                int8_t *winner, int16_t *length, uint32_t *seat_wins, void *stream);
+
+/* Rollout kernel variants, for measurement: 0 = automatic (the fastest),
+ * 1 = one lane per playout, 2 = lane refill + persistent work stealing.
+ * block/grid 0 = automatic.  Same outputs for every variant and shape.    */
+int dvc_rollout_ex(const dvc_state_t *leaves, int64_t n_leaves, int32_t playouts_per_leaf,
+                   uint64_t seed, uint32_t tree_id, uint32_t leaf_id_base,
+                   int8_t *winner, int16_t *length, uint32_t *seat_wins,
+                   int32_t variant, int32_t block, int32_t grid, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Tree search (Sec. II-B, Sec. III-A).
+ * An action is a guess (r, s, v): target seat (mover + r) mod P, r = 1..P-1;
+ * slot s of the target's row (0 = lowest) at guess time; value v (the colour
+ * is the slot's).  action_id = ((r-1)*24 + s)*12 + v < 864.  It is legal when
+ * the target still has hidden tiles, slot s exists and is hidden, and 2v+colour
+ * is a consistent value for the mover (see dvc_rollout).
+ * Iteration i of tree tr:
+ *   1. sample a world consistent with what the root mover sees (the opponent
+ *      tiles are a black box, Sec. III-A): per opponent from the mover's left,
+ *      per run of hidden slots between revealed tiles, bounds right to left
+ *      (largest available tile of the slot's colour below the next bound),
+ *      then values left to right, uniform in (previous, bound]; up to 16
+ *      attempts, then the smallest consistent world in slot order;
+ *   2. descend from the root: a decided state is the leaf; at depth
+ *      max_depth the node is the leaf; else the lowest legal action id that
+ *      is not yet a child is expanded and its child is the leaf; else the
+ *      legal child with the greatest UCT score, in FP32 with one rounding per
+ *      operation: n=N; q=W/n; e=LN[N_parent]/n; u=c_uct*sqrt(e); score=q+u,
+ *      LN[k]=float(log(double k)), first child in creation order on ties.
+ *      Playing a guess in the tree ends the turn (a right guess reveals the
+ *      target, a wrong one the drawn or a random own hidden tile); the next
+ *      player draws;
+ *   3. playouts_per_leaf playouts from the leaf with leaf id i (a decided
+ *      leaf counts all of them as won by its winner);
+ *   4. every node on the path: N += playouts; every non-root node:
+ *      W += wins of the seat that chose its action.
+ * Decision: the root child with the most visits, earliest created on ties.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int32_t iterations;         /* per tree, >= 1                                   */
+    int32_t playouts_per_leaf;  /* >= 1                                             */
+    int32_t max_depth;          /* expansion depth threshold, 1..16                 */
+    float c_uct;                /* exploration constant (sqrt 2 rounded to float)   */
+    int32_t leaf_eval;          /* 0: playouts; 1: value network with fallback      */
+    float fallback_band;        /* value mode: playouts when |v - 0.5| < band       */
+    int32_t fallback_playouts;  /* value mode: playouts of a fallback leaf          */
+    const void *valuenet;       /* value mode: dvc_valuenet weights (device)        */
+} dvc_mcts_params;
+
+/* one root child, in creation order; action 0xFFFF marks unused entries */
+typedef struct { uint16_t action; uint16_t pad; uint32_t n; float w; } dvc_child_stat;
+
+#define DVC_MAX_ACTIONS 864
+
+/* Device workspace needed by mcts_search for n_trees trees. */
+size_t dvc_mcts_workspace_bytes(int64_t n_trees, const dvc_mcts_params *params /* host */);
+
+/* mcts_search -- one decision for each of n_trees roots (tree ids
+ * tree_id_base + t).  Roots must be valid and undecided, in phase 1 (or
+ * phase 0 with an empty pool).  best_action[t] receives the chosen action id;
+ * root_children (may be NULL) receives [n_trees][864] child statistics.
+ * workspace: device memory of at least dvc_mcts_workspace_bytes().
+ * Returns DVC_EINVAL on bad sizes/params, DVC_ENOMEM if the workspace is too
+ * small; malformed roots set DVC_ESTATE in the error word.                  */
+int mcts_search(const dvc_state_t *roots, int64_t n_trees, const dvc_mcts_params *params /* host */,
+                uint64_t seed, uint32_t tree_id_base, void *workspace, size_t workspace_bytes,
+                int32_t *best_action, dvc_child_stat *root_children, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Status
+ * ------------------------------------------------------------------------- */
+const char *dvc_status_str(int status);
+
+/* Synchronise `stream`, then return and clear the device error word of the
+ * current device (DVC_OK when no kernel reported an error).                */
+int dvc_check(void *stream);
+
+/* Library version string. */
+const char *dvc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DVC_H */

@@ -1,0 +1,209 @@
+"""Python binding of libdvc.so, the gfx950 Da Vinci Code MCTS engine.
+
+Argument marshalling only: every step of the hot path runs in the HIP
+kernels of ``libdvc.so``; PyTorch supplies device memory and the stream.
+The functions keep the names of the C ABI in ``include/dvc.h``.
+
+There is no CPU fallback: importing the binding without a built library, or
+calling it without a GPU, raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdvc.so")
+MAX_ACTIONS = 864
+
+DVC_OK, DVC_EINVAL, DVC_ESTATE, DVC_EHIP, DVC_ENOMEM, DVC_ELIMIT = 0, -1, -2, -3, -4, -5
+
+
+class DvcError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        super().__init__(f"{what}: {status_str(status)} ({status})" if what else status_str(status))
+
+
+class DealParams(C.Structure):
+    _fields_ = [("p_min", C.c_int32), ("p_max", C.c_int32), ("hand", C.c_int32 * 5),
+                ("pile_min", C.c_int32), ("pile_max", C.c_int32),
+                ("revealed_max", C.c_int32), ("fresh", C.c_int32),
+                ("root_draw", C.c_int32), ("phase_mix", C.c_int32)]
+
+
+class MctsParams(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("playouts_per_leaf", C.c_int32),
+                ("max_depth", C.c_int32), ("c_uct", C.c_float), ("leaf_eval", C.c_int32),
+                ("fallback_band", C.c_float), ("fallback_playouts", C.c_int32),
+                ("valuenet", C.c_void_p)]
+
+
+def deal_params(p_min=2, p_max=2, hand=(0, 0, 4, 4, 3), pile_min=0, pile_max=16,
+                revealed_max=8, fresh=0, root_draw=0, phase_mix=0) -> DealParams:
+    d = DealParams()
+    d.p_min, d.p_max = p_min, p_max
+    for i in range(5):
+        d.hand[i] = hand[i]
+    d.pile_min, d.pile_max, d.revealed_max = pile_min, pile_max, revealed_max
+    d.fresh, d.root_draw, d.phase_mix = fresh, root_draw, phase_mix
+    return d
+
+
+def mcts_params(iterations=2000, playouts_per_leaf=16, max_depth=4, c_uct=None, leaf_eval=0,
+                fallback_band=0.05, fallback_playouts=64, valuenet=None) -> MctsParams:
+    m = MctsParams()
+    m.iterations, m.playouts_per_leaf, m.max_depth = iterations, playouts_per_leaf, max_depth
+    m.c_uct = float.fromhex("0x1.6a09e6p+0") if c_uct is None else c_uct  # sqrt(2) in float
+    m.leaf_eval, m.fallback_band, m.fallback_playouts = leaf_eval, fallback_band, fallback_playouts
+    m.valuenet = None if valuenet is None else valuenet.data_ptr()
+    return m
+
+
+_lib = None
+
+
+def lib():
+    """Load libdvc.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() or "
+                              "python paper_2403_10720_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        vp, i64, i32, u32, u64 = C.c_void_p, C.c_int64, C.c_int32, C.c_uint32, C.c_uint64
+        L.dvc_version.restype = C.c_char_p
+        L.dvc_status_str.restype = C.c_char_p
+        L.dvc_status_str.argtypes = [C.c_int]
+        L.dvc_check.argtypes = [vp]
+        L.dvc_init_states.argtypes = [vp, i64, C.POINTER(DealParams), u64, u32, vp]
+        L.dvc_rollout.argtypes = [vp, i64, i32, u64, u32, u32, vp, vp, vp, vp]
+        L.dvc_rollout_ex.argtypes = [vp, i64, i32, u64, u32, u32, vp, vp, vp, i32, i32, i32, vp]
+        if hasattr(L, "mcts_search"):
+            L.dvc_mcts_workspace_bytes.restype = C.c_size_t
+            L.dvc_mcts_workspace_bytes.argtypes = [i64, C.POINTER(MctsParams)]
+            L.mcts_search.argtypes = [vp, i64, C.POINTER(MctsParams), u64, u32, vp, C.c_size_t,
+                                      vp, vp, vp]
+        _lib = L
+    return _lib
+
+
+def status_str(status: int) -> str:
+    return lib().dvc_status_str(status).decode()
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _check_dev(t, dtype, shape=None, what=""):
+    if t is None:
+        return
+    if not t.is_cuda:
+        raise ValueError(f"{what} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{what} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{what} must have shape {shape}, got {tuple(t.shape)}")
+
+
+def _raise(rc, what):
+    if rc != DVC_OK:
+        raise DvcError(rc, what)
+
+
+def dvc_check(stream=None) -> int:
+    return lib().dvc_check(_stream(stream))
+
+
+def dvc_init_states(n: int, params: DealParams, seed: int, index_base: int = 0, out=None,
+                    device="cuda", stream=None) -> torch.Tensor:
+    """n packed states as an int32 tensor of shape (n, 4) (bit pattern of dvc_state_t)."""
+    if out is None:
+        out = torch.empty((n, 4), dtype=torch.int32, device=device)
+    _check_dev(out, torch.int32, (n, 4), "out")
+    rc = lib().dvc_init_states(_ptr(out), n, C.byref(params), seed & (2**64 - 1), index_base,
+                               _stream(stream))
+    _raise(rc, "dvc_init_states")
+    return out
+
+
+def dvc_rollout(leaves: torch.Tensor, playouts_per_leaf: int, seed: int, tree_id: int = 0,
+                leaf_id_base: int = 0, winner=True, length=True, seat_wins=True, variant: int = 0,
+                block: int = 0, grid: int = 0, stream=None):
+    """Random playouts from every leaf.  Returns (winner int8 [n*ppl] | None,
+    length int16 [n*ppl] | None, seat_wins int32 [n, 4] | None); pass
+    preallocated tensors instead of True to reuse memory."""
+    _check_dev(leaves, torch.int32, None, "leaves")
+    if leaves.dim() != 2 or leaves.shape[1] != 4:
+        raise ValueError("leaves must have shape (n, 4)")
+    n = leaves.shape[0]
+    dev = leaves.device
+    total = n * playouts_per_leaf
+
+    def prep(x, dtype, shape):
+        if x is True:
+            return torch.empty(shape, dtype=dtype, device=dev)
+        if x is False or x is None:
+            return None
+        _check_dev(x, dtype, shape, "output")
+        return x
+
+    w = prep(winner, torch.int8, (total,))
+    ln = prep(length, torch.int16, (total,))
+    sw = prep(seat_wins, torch.int32, (n, 4))
+    rc = lib().dvc_rollout_ex(_ptr(leaves), n, playouts_per_leaf, seed & (2**64 - 1), tree_id,
+                              leaf_id_base, _ptr(w), _ptr(ln), _ptr(sw), variant, block, grid,
+                              _stream(stream))
+    _raise(rc, "dvc_rollout")
+    return w, ln, sw
+
+
+def dvc_mcts_workspace_bytes(n_trees: int, params: MctsParams) -> int:
+    return int(lib().dvc_mcts_workspace_bytes(n_trees, C.byref(params)))
+
+
+def mcts_search(roots: torch.Tensor, params: MctsParams, seed: int, tree_id_base: int = 0,
+                workspace=None, want_children: bool = True, stream=None):
+    """One decision per root.  Returns (best_action int32 [n], children
+    int32 [n, 864, 3] | None) where children[..., 0] = action | pad << 16,
+    [..., 1] = n (bit pattern of uint32), [..., 2] = w (bit pattern of float)."""
+    _check_dev(roots, torch.int32, None, "roots")
+    n = roots.shape[0]
+    dev = roots.device
+    need = dvc_mcts_workspace_bytes(n, params)
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    best = torch.empty(n, dtype=torch.int32, device=dev)
+    kids = torch.empty((n, MAX_ACTIONS, 3), dtype=torch.int32, device=dev) if want_children else None
+    rc = lib().mcts_search(_ptr(roots), n, C.byref(params), seed & (2**64 - 1), tree_id_base,
+                           _ptr(workspace), workspace.numel(), _ptr(best), _ptr(kids),
+                           _stream(stream))
+    _raise(rc, "mcts_search")
+    return best, kids
+
+
+def children_view(kids: torch.Tensor):
+    """Split the raw child-statistics tensor into (action, n, w) tensors on the host."""
+    k = kids.cpu()
+    action = (k[..., 0] & 0xFFFF)
+    n = k[..., 1].view(torch.int32).to(torch.int64) & 0xFFFFFFFF
+    w = k[..., 2].view(torch.float32)
+    return action, n, w
+
+
+def c_uct_default() -> float:
+    return float.fromhex("0x1.6a09e6p+0")
+
+
+assert abs(c_uct_default() - math.sqrt(2)) < 1e-6

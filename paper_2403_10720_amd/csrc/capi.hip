@@ -1,0 +1,164 @@
+// capi.hip -- the extern "C" entry points declared in include/dvc.h:
+// argument checks, launch-shape choice and kernel launches on the caller's
+// stream.  Nothing here allocates per call.
+#include <atomic>
+#include <mutex>
+
+#include "../../include/dvc.h"
+#include "dvc_internal.hpp"
+
+namespace dvc {
+
+static std::atomic<uint32_t> g_next_slot{0};
+
+uint32_t next_queue_slot()
+{
+    return g_next_slot.fetch_add(1u, std::memory_order_relaxed) % (uint32_t)kQueueSlots;
+}
+
+static int device_cu_count()
+{
+    static int cached[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (cached[dev] == 0) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            cus <= 0)
+            cus = 256;
+        cached[dev] = cus;
+    }
+    return cached[dev];
+}
+
+int default_rollout_grid(int waves_per_block)
+{
+    // two waves per SIMD: four SIMDs per compute unit
+    const int waves = device_cu_count() * 4 * 2;
+    return (waves + waves_per_block - 1) / waves_per_block;
+}
+
+static int status_of(hipError_t e) { return e == hipSuccess ? DVC_OK : DVC_EHIP; }
+
+}  // namespace dvc
+
+using namespace dvc;
+
+extern "C" {
+
+const char *dvc_version(void) { return "dvc-gfx950 0.1"; }
+
+const char *dvc_status_str(int status)
+{
+    switch (status) {
+    case DVC_OK: return "ok";
+    case DVC_EINVAL: return "invalid argument";
+    case DVC_ESTATE: return "malformed game state";
+    case DVC_EHIP: return "HIP runtime error";
+    case DVC_ENOMEM: return "workspace too small or allocation failed";
+    case DVC_ELIMIT: return "internal bound reached";
+    default: return "unknown status";
+    }
+}
+
+int dvc_check(void *stream)
+{
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return DVC_EHIP;
+    uint32_t w = 0u, zero = 0u;
+    if (hipMemcpyFromSymbol(&w, HIP_SYMBOL(g_error_word), sizeof(w), 0, hipMemcpyDeviceToHost) !=
+        hipSuccess)
+        return DVC_EHIP;
+    if (w != 0u &&
+        hipMemcpyToSymbol(HIP_SYMBOL(g_error_word), &zero, sizeof(zero), 0, hipMemcpyHostToDevice) !=
+            hipSuccess)
+        return DVC_EHIP;
+    if (w & kErrState) return DVC_ESTATE;
+    if (w & kErrLimit) return DVC_ELIMIT;
+    return DVC_OK;
+}
+
+int dvc_init_states(dvc_state_t *out, int64_t n, const dvc_deal_params *p, uint64_t seed,
+                    uint32_t index_base, void *stream)
+{
+    if (n < 0 || n >= (1ll << 32) || p == nullptr || (n > 0 && out == nullptr)) return DVC_EINVAL;
+    if (p->p_min < 2 || p->p_max > 4 || p->p_min > p->p_max) return DVC_EINVAL;
+    for (int P = p->p_min; P <= p->p_max; ++P)
+        if (p->hand[P] < 1 || P * p->hand[P] > 24) return DVC_EINVAL;
+    if (p->pile_min < 0 || p->pile_max < 0 || p->revealed_max < 0) return DVC_EINVAL;
+    DealArgs d;
+    d.p_min = p->p_min;
+    d.p_max = p->p_max;
+    for (int k = 0; k < 5; ++k) d.hand[k] = p->hand[k];
+    d.pile_min = p->pile_min;
+    d.pile_max = p->pile_max;
+    d.revealed_max = p->revealed_max;
+    d.fresh = p->fresh;
+    d.root_draw = p->root_draw;
+    d.phase_mix = p->phase_mix;
+    return status_of(launch_init_states(reinterpret_cast<uint4 *>(out), (uint32_t)n, d,
+                                        (uint32_t)seed, (uint32_t)(seed >> 32), index_base,
+                                        (hipStream_t)stream));
+}
+
+int dvc_rollout_ex(const dvc_state_t *leaves, int64_t n_leaves, int32_t ppl, uint64_t seed,
+                   uint32_t tree_id, uint32_t leaf_id_base, int8_t *winner, int16_t *length,
+                   uint32_t *seat_wins, int32_t variant, int32_t block, int32_t grid, void *stream)
+{
+    if (n_leaves < 0 || ppl < 1 || (n_leaves > 0 && leaves == nullptr)) return DVC_EINVAL;
+    if ((uint64_t)n_leaves * (uint64_t)ppl >= (1ull << 32)) return DVC_EINVAL;
+    if (variant < 0 || variant > 2) return DVC_EINVAL;
+    if (block != 0 && block != 64 && block != 128 && block != 256 && block != 512) return DVC_EINVAL;
+    if (grid < 0) return DVC_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    RolloutArgs a;
+    a.leaves = reinterpret_cast<const uint4 *>(leaves);
+    a.n_leaves = (uint32_t)n_leaves;
+    a.ppl = (uint32_t)ppl;
+    a.total = (uint32_t)((uint64_t)n_leaves * (uint64_t)ppl);
+    a.k0 = (uint32_t)seed;
+    a.k1 = (uint32_t)(seed >> 32);
+    a.tree = tree_id;
+    a.leaf_base = leaf_id_base;
+    // a chunk never spans more than kStageLeaves leaves
+    const uint64_t max_chunk = (uint64_t)(kStageLeaves - 1u) * (uint64_t)ppl;
+    a.chunk = (uint32_t)(max_chunk < 256u ? max_chunk : 256u);
+    a.queue_slot = next_queue_slot();
+    a.winner = winner;
+    a.length = length;
+    a.seat_wins = seat_wins;
+    a.stats = nullptr;
+    if (a.total == 0) return DVC_OK;
+    if (seat_wins) {
+        hipError_t e = launch_fill_u32(seat_wins, (uint64_t)n_leaves * 4u, 0u, st);
+        if (e != hipSuccess) return DVC_EHIP;
+    }
+    const int v = variant == 0 ? 2 : variant;
+    return status_of(launch_rollout(a, v, block, grid, st));
+}
+
+int dvc_rollout(const dvc_state_t *leaves, int64_t n_leaves, int32_t ppl, uint64_t seed,
+                uint32_t tree_id, uint32_t leaf_id_base, int8_t *winner, int16_t *length,
+                uint32_t *seat_wins, void *stream)
+{
+    return dvc_rollout_ex(leaves, n_leaves, ppl, seed, tree_id, leaf_id_base, winner, length,
+                          seat_wins, 0, 0, 0, stream);
+}
+
+size_t dvc_mcts_workspace_bytes(int64_t n_trees, const dvc_mcts_params *params)
+{
+    (void)n_trees;
+    (void)params;
+    return 0;
+}
+
+int mcts_search(const dvc_state_t *roots, int64_t n_trees, const dvc_mcts_params *params,
+                uint64_t seed, uint32_t tree_id_base, void *workspace, size_t workspace_bytes,
+                int32_t *best_action, dvc_child_stat *root_children, void *stream)
+{
+    // the GPU tree search is not built yet
+    (void)roots; (void)n_trees; (void)params; (void)seed; (void)tree_id_base; (void)workspace;
+    (void)workspace_bytes; (void)best_action; (void)root_children; (void)stream;
+    return DVC_EINVAL;
+}
+
+}  // extern "C"

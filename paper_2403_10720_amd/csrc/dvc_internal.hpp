@@ -1,0 +1,49 @@
+// dvc_internal.hpp -- shared declarations of the library's translation unit
+// (kernel argument blocks, device-global error word and work queues,
+// launchers).  The library is built as one translation unit (dvc_lib.hip),
+// so the device globals below are defined exactly once.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dvc {
+
+constexpr uint32_t kErrState = 1u;   // a malformed state was read
+constexpr uint32_t kErrLimit = 2u;   // a kernel reached an internal bound
+constexpr int kQueueSlots = 1024;    // independent work-queue counter pairs
+constexpr uint32_t kStageLeaves = 64;  // leaf states staged per wave
+
+// Sticky error word of the device, or-ed by kernels, read and cleared by
+// dvc_check().
+__device__ uint32_t g_error_word = 0u;
+// Work-stealing counters: [slot][0] next chunk, [slot][1] finished
+// workgroups.  A persistent kernel's last workgroup returns its slot to zero,
+// so every call starts from zeros without a memset.
+__device__ uint32_t g_queue[kQueueSlots][2];
+
+struct RolloutArgs {
+    const uint4 *leaves;
+    uint32_t n_leaves, ppl, total;   // total = n_leaves * ppl < 2^32
+    uint32_t k0, k1, tree, leaf_base;
+    uint32_t chunk;                  // playout ids per stolen chunk
+    uint32_t queue_slot;
+    int8_t *winner;
+    int16_t *length;
+    uint32_t *seat_wins;
+    unsigned long long *stats;       // optional: [0] += wave steps
+};
+
+struct DealArgs {
+    int32_t p_min, p_max;
+    int32_t hand[5];
+    int32_t pile_min, pile_max, revealed_max, fresh, root_draw, phase_mix;
+};
+
+int default_rollout_grid(int waves_per_block);
+hipError_t launch_rollout(const RolloutArgs &a, int variant, int block, int grid, hipStream_t st);
+hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st);
+hipError_t launch_init_states(uint4 *out, uint32_t n, const DealArgs &d, uint32_t k0, uint32_t k1,
+                              uint32_t index_base, hipStream_t st);
+
+}  // namespace dvc

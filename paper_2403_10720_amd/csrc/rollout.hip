@@ -1,0 +1,315 @@
+// rollout.hip -- random playouts of the Da Vinci Code game on gfx950.
+//
+// Sec. II-B of Zhang et al. (arXiv 2403.10720): in every simulation the game
+// is played to the end by taking each decision at random.  The paper
+// attributes the GPU's poor scaling to branch divergence (turns of different
+// length; finished threads wait for the longest game, Sec. IV-B).  Here the
+// guess step is straight-line predicated code on 24-bit masks, and the
+// persistent kernel refills a lane as soon as its game ends, so a wavefront
+// keeps its 64 lanes busy until the work queue runs dry.
+#include "dvc_core.hpp"
+#include "dvc_internal.hpp"
+
+namespace dvc {
+
+// ---------------------------------------------------------------------------
+// One guess.  w0 draw, w1 target, w2 value, w3 continue coin / own reveal.
+// Returns true when the game is decided; `winner` is then the last seat with
+// a hidden tile.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool guess_step(State &s, const Words &w, uint32_t &winner)
+{
+    const uint32_t owned = s.h0 | s.h1 | s.h2 | s.h3;
+    const uint32_t pool = ~owned & kAll;
+    const bool turn_start = s.phase == 0u;
+    const bool draw = turn_start && pool != 0u;
+    const uint32_t d = pick_bit(pool, w.w0);
+    const uint32_t dbit = draw ? (1u << d) : 0u;
+    add_to_hand(s, s.m, dbit);
+    s.drawn = turn_start ? (draw ? (int32_t)d : -1) : s.drawn;
+    s.phase = 1u;
+
+    const uint32_t hm = hand_of(s, s.m);
+    const uint32_t targets = (owned | dbit) & ~hm & ~s.rev;
+    const uint32_t t = pick_bit(targets, w.w1);
+    const uint32_t tb = 1u << t;
+    const uint32_t o = (s.h0 & tb) ? 0u : (s.h1 & tb) ? 1u : (s.h2 & tb) ? 2u : 3u;
+    const uint32_t cand = candidates(t, hand_of(s, o), hm, s.rev);
+    const uint32_t v = pick_bit(cand, w.w2);
+    const bool right = v == t;
+
+    const uint32_t own_hidden = hm & ~s.rev;
+    const uint32_t r = pick_bit(own_hidden, w.w3);
+    const uint32_t wrong_bit = 1u << (s.drawn >= 0 ? (uint32_t)s.drawn : r);
+    s.rev |= right ? tb : wrong_bit;
+
+    const uint32_t alive = alive_mask(s);
+    const bool over = __popc(alive) == 1;
+    winner = (uint32_t)__builtin_ctz(alive | 16u);
+    const bool go_on = right && w.w3 < 0x80000000u;
+    const bool pass = !over && !go_on;
+    s.m = pass ? next_alive(alive, s.m, s.P) : s.m;
+    s.phase = pass ? 0u : s.phase;
+    s.drawn = pass ? -1 : s.drawn;
+    return over;
+}
+
+// Philox round 1 for counter (g, p, l, tr) only multiplies g and l: the l
+// product is fixed for a playout and g*M0 grows by M0 per step.
+struct PlayoutKey {
+    uint32_t a, b;          // round-1 words 0 and 1 (from p, l)
+    uint32_t gm_lo, gm_hi;  // g * M0
+};
+
+__device__ __forceinline__ PlayoutKey playout_key(uint32_t p, uint32_t l, uint32_t k0)
+{
+    const uint64_t pl = (uint64_t)l * kPhiloxM1;
+    PlayoutKey pk;
+    pk.a = (uint32_t)(pl >> 32) ^ p ^ k0;
+    pk.b = (uint32_t)pl;
+    pk.gm_lo = 0u;
+    pk.gm_hi = 0u;
+    return pk;
+}
+
+__device__ __forceinline__ Words step_words(const PlayoutKey &pk, uint32_t trk1, uint32_t k0,
+                                            uint32_t k1)
+{
+    return philox_rounds_2_to_10(pk.a, pk.b, pk.gm_hi ^ trk1, pk.gm_lo, k0, k1);
+}
+
+__device__ __forceinline__ void next_step(PlayoutKey &pk)
+{
+    const uint64_t g = ((uint64_t)pk.gm_hi << 32 | pk.gm_lo) + kPhiloxM0;
+    pk.gm_lo = (uint32_t)g;
+    pk.gm_hi = (uint32_t)(g >> 32);
+}
+
+__device__ __forceinline__ void record_win(uint32_t *seat_wins, uint32_t leaf, uint32_t winner)
+{
+    if (seat_wins && winner < 4u) atomicAdd(&seat_wins[(size_t)leaf * 4u + winner], 1u);
+}
+
+// Every guess reveals one more of the 24 tiles and the winner keeps a hidden
+// one, so a game from a valid state ends within 23 guesses; reaching the cap
+// means the state was not valid after all.
+constexpr uint32_t kMaxGuesses = 23u;
+
+// ---------------------------------------------------------------------------
+// Variant 1: one lane per playout; lanes whose game ended wait for the rest.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) rollout_lane_per_playout(RolloutArgs a)
+{
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= a.total) return;
+    const uint32_t leaf = j / a.ppl;
+    const uint32_t p = j - leaf * a.ppl;
+    const uint4 st = a.leaves[leaf];
+    State s;
+    if (!decode(st.x, st.y, st.z, st.w, s)) {
+        atomicOr(&g_error_word, kErrState);
+        if (a.winner) a.winner[j] = -1;
+        if (a.length) a.length[j] = -1;
+        return;
+    }
+    PlayoutKey pk = playout_key(p, a.leaf_base + leaf, a.k0);
+    const uint32_t trk1 = a.tree ^ a.k1;
+    uint32_t alive = alive_mask(s);
+    bool over = __popc(alive) == 1;
+    uint32_t winner = (uint32_t)__builtin_ctz(alive | 16u);
+    uint32_t len = 0;
+    while (!over) {
+        const Words w = step_words(pk, trk1, a.k0, a.k1);
+        over = guess_step(s, w, winner);
+        next_step(pk);
+        ++len;
+        if (!over && len >= kMaxGuesses) {
+            atomicOr(&g_error_word, kErrLimit);
+            over = true;
+            winner = 4u;
+        }
+    }
+    if (a.winner) a.winner[j] = (int8_t)(winner < 4u ? (int)winner : -1);
+    if (a.length) a.length[j] = (int16_t)len;
+    record_win(a.seat_wins, leaf, winner);
+}
+
+// ---------------------------------------------------------------------------
+// Variant 2: persistent waves with lane refill and work stealing.
+//
+// Every wave steals chunks of `chunk` consecutive playout ids (playout id =
+// leaf * ppl + p) from a global counter and stages the chunk's leaf states in
+// its own LDS slot.  After each guess step the lanes whose game ended write
+// their outcome, their seat wins are summed per leaf across the wave with
+// ballots, and they take the next playout ids of the chunk (ballot + mbcnt
+// prefix), so no lane idles while the wave still has work.  Outputs depend
+// only on the playout id, never on which lane or wave ran it.
+// ---------------------------------------------------------------------------
+template <int WAVES>
+__global__ void __launch_bounds__(WAVES * 64) rollout_persistent(RolloutArgs a)
+{
+    __shared__ uint4 stage[WAVES][kStageLeaves];
+    const uint32_t lane = threadIdx.x & 63u;
+    uint4 *my = stage[threadIdx.x >> 6];
+    uint32_t *queue = &g_queue[a.queue_slot][0];
+
+    uint32_t rcur = 0, rend = 0, leaf0 = 0;   // wave-uniform: current chunk
+    bool drained = false;                     // wave-uniform: queue empty
+    bool active = false;
+    State s;
+    s.h0 = s.h1 = s.h2 = s.h3 = s.rev = 0u;
+    s.m = 0u; s.P = 2u; s.phase = 1u; s.drawn = -1;
+    PlayoutKey pk = {0u, 0u, 0u, 0u};
+    uint32_t j = 0, leaf = 0, len = 0, winner = 0;
+    const uint32_t trk1 = a.tree ^ a.k1;
+    uint64_t steps = 0;
+
+    for (;;) {
+        // ---- refill idle lanes ------------------------------------------
+        uint64_t idle = __ballot(!active);
+        while (idle != 0ull) {
+            if (rcur == rend) {
+                if (drained) break;
+                uint32_t c = 0;
+                if (lane == 0) c = atomicAdd(&queue[0], 1u);
+                c = __builtin_amdgcn_readfirstlane(c);
+                const uint64_t start = (uint64_t)c * a.chunk;
+                if (start >= a.total) { drained = true; break; }
+                rcur = (uint32_t)start;
+                rend = (uint32_t)min<uint64_t>(start + a.chunk, a.total);
+                leaf0 = rcur / a.ppl;
+                const uint32_t nl = (rend - 1u) / a.ppl - leaf0 + 1u;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                for (uint32_t k = lane; k < nl; k += 64u) my[k] = a.leaves[leaf0 + k];
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+            }
+            const uint32_t take = min<uint32_t>((uint32_t)__popcll(idle), rend - rcur);
+            const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
+                (uint32_t)(idle >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)idle, 0u));
+            const bool mine = ((idle >> lane) & 1ull) && rank < take;
+            if (mine) {
+                j = rcur + rank;
+                leaf = j / a.ppl;
+                const uint32_t p = j - leaf * a.ppl;
+                const uint4 st = my[leaf - leaf0];
+                const bool ok = decode(st.x, st.y, st.z, st.w, s);
+                pk = playout_key(p, a.leaf_base + leaf, a.k0);
+                len = 0;
+                const uint32_t alive = alive_mask(s);
+                winner = (uint32_t)__builtin_ctz(alive | 16u);
+                if (!ok) {
+                    atomicOr(&g_error_word, kErrState);
+                    if (a.winner) a.winner[j] = -1;
+                    if (a.length) a.length[j] = -1;
+                } else if (__popc(alive) == 1) {
+                    if (a.winner) a.winner[j] = (int8_t)(winner < 4u ? (int)winner : -1);
+                    if (a.length) a.length[j] = 0;
+                    record_win(a.seat_wins, leaf, winner);
+                } else {
+                    active = true;
+                }
+            }
+            rcur += take;
+            idle &= ~__ballot(mine);
+        }
+        const uint64_t act = __ballot(active);
+        if (act == 0ull) {
+            if (drained) break;
+            continue;
+        }
+        ++steps;
+
+        // ---- one guess for every active lane ----------------------------
+        bool over = false;
+        if (active) {
+            const Words w = step_words(pk, trk1, a.k0, a.k1);
+            over = guess_step(s, w, winner);
+            next_step(pk);
+            ++len;
+            if (!over && len >= kMaxGuesses) {
+                atomicOr(&g_error_word, kErrLimit);
+                over = true;
+                winner = 4u;
+            }
+        }
+
+        // ---- finished games: outputs and per-leaf seat wins -------------
+        const bool fin = active && over;
+        if (fin) {
+            if (a.winner) a.winner[j] = (int8_t)(winner < 4u ? (int)winner : -1);
+            if (a.length) a.length[j] = (int16_t)len;
+        }
+        if (a.seat_wins) {
+            uint64_t fmask = __ballot(fin);
+            while (fmask != 0ull) {
+                const uint32_t first = (uint32_t)__builtin_ctzll(fmask);
+                const uint32_t L = __builtin_amdgcn_readlane(leaf, first);
+                const uint64_t same = __ballot(fin && leaf == L);
+                const uint32_t c0 = (uint32_t)__popcll(__ballot(fin && leaf == L && winner == 0u));
+                const uint32_t c1 = (uint32_t)__popcll(__ballot(fin && leaf == L && winner == 1u));
+                const uint32_t c2 = (uint32_t)__popcll(__ballot(fin && leaf == L && winner == 2u));
+                const uint32_t c3 = (uint32_t)__popcll(__ballot(fin && leaf == L && winner == 3u));
+                if (lane < 4u) {
+                    const uint32_t c = lane == 0u ? c0 : lane == 1u ? c1 : lane == 2u ? c2 : c3;
+                    if (c) atomicAdd(&a.seat_wins[(size_t)L * 4u + lane], c);
+                }
+                fmask &= ~same;
+            }
+        }
+        active = active && !over;
+    }
+
+    if (a.stats && lane == 0) atomicAdd(&a.stats[0], (unsigned long long)steps);
+    // the last workgroup out leaves the queue slot at zero for the next call
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const uint32_t done = atomicAdd(&queue[1], 1u);
+        if (done == gridDim.x - 1u) {
+            atomicExch(&queue[0], 0u);
+            atomicExch(&queue[1], 0u);
+        }
+    }
+}
+
+__global__ void fill_u32(uint32_t *p, uint64_t n, uint32_t v)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    const uint64_t blocks = (n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096;
+    hipLaunchKernelGGL(fill_u32, dim3((unsigned)blocks), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_rollout(const RolloutArgs &a, int variant, int block, int grid, hipStream_t st)
+{
+    if (a.total == 0) return hipSuccess;
+    if (variant == 1) {
+        const uint32_t blocks = (a.total + 255u) / 256u;
+        hipLaunchKernelGGL(rollout_lane_per_playout, dim3(blocks), dim3(256), 0, st, a);
+        return hipGetLastError();
+    }
+    int waves = block > 0 ? block / 64 : 4;
+    if (grid <= 0) grid = default_rollout_grid(waves);
+    switch (waves) {
+    case 1: hipLaunchKernelGGL(rollout_persistent<1>, dim3(grid), dim3(64), 0, st, a); break;
+    case 2: hipLaunchKernelGGL(rollout_persistent<2>, dim3(grid), dim3(128), 0, st, a); break;
+    case 4: hipLaunchKernelGGL(rollout_persistent<4>, dim3(grid), dim3(256), 0, st, a); break;
+    case 8: hipLaunchKernelGGL(rollout_persistent<8>, dim3(grid), dim3(512), 0, st, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace dvc

@@ -1,0 +1,62 @@
+"""Host-side checks of the C ABI library (no GPU needed).
+
+* libdvc.so loads and exports every function include/dvc.h declares;
+* status strings; argument errors are returned before any device work.
+"""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dvc.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*([A-Za-z_][A-Za-z0-9_]*)\s*\(",
+                       src, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "sizeof")))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    path = os.path.join(ROOT, "paper_2403_10720_amd", "libdvc.so")
+    if not os.path.exists(path):
+        from paper_2403_10720_amd import build
+        build.build()
+    return C.CDLL(path)
+
+
+def test_header_declares_the_three_named_calls():
+    names = declared_functions()
+    for n in ["dvc_init_states", "dvc_rollout", "mcts_search"]:
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_status_strings(lib):
+    lib.dvc_status_str.restype = C.c_char_p
+    assert lib.dvc_status_str(0) == b"ok"
+    assert b"invalid" in lib.dvc_status_str(-1)
+    assert b"malformed" in lib.dvc_status_str(-2)
+
+
+def test_argument_errors_without_device(lib):
+    vp = C.c_void_p
+    lib.dvc_rollout_ex.argtypes = [vp, C.c_int64, C.c_int32, C.c_uint64, C.c_uint32, C.c_uint32,
+                                   vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, vp]
+    assert lib.dvc_rollout_ex(None, -1, 8, 0, 0, 0, None, None, None, 0, 0, 0, None) == -1
+    assert lib.dvc_rollout_ex(None, 4, 8, 0, 0, 0, None, None, None, 0, 0, 0, None) == -1
+    assert lib.dvc_rollout_ex(None, 0, 0, 0, 0, 0, None, None, None, 0, 0, 0, None) == -1
+    # n * ppl must stay below 2^32
+    assert lib.dvc_rollout_ex(vp(16), 1 << 20, 1 << 12, 0, 0, 0, None, None, None, 0, 0, 0,
+                              None) == -1
+    lib.dvc_init_states.argtypes = [vp, C.c_int64, vp, C.c_uint64, C.c_uint32, vp]
+    assert lib.dvc_init_states(None, -1, None, 0, 0, None) == -1

@@ -1,0 +1,178 @@
+"""GPU parity of the state generator and the rollout kernels (through the C ABI).
+
+Bar: bit-exact.  Every winner, game length and per-leaf seat-win count must
+equal the CPU oracle's on the same seeds; so must every generated state.
+Covers every kernel variant, several launch shapes (schedule invariance),
+ragged sizes, decided leaves, malformed leaves and argument errors, and the
+full leaf-parallel workload (4096 leaves x 256 playouts).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dvc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2403_10720_amd as D
+    D.lib()
+    return D
+
+
+def to_np(t):
+    return t.cpu().numpy().view(np.uint32) if t.dtype == torch.int32 else t.cpu().numpy()
+
+
+def dev_states(a):
+    return torch.from_numpy(np.ascontiguousarray(a).view(np.int32)).cuda()
+
+
+def deal_pair(orc, dvc, **kw):
+    return orc.deal_params(**kw), dvc.deal_params(**kw)
+
+
+CONFIGS = [
+    dict(p_min=2, p_max=2, pile_min=0, pile_max=16, revealed_max=8),              # leaf-parallel
+    dict(p_min=2, p_max=4, hand=(0, 0, 4, 4, 3), pile_min=0, pile_max=16,
+         revealed_max=8, root_draw=1),                                             # batched roots
+    dict(p_min=2, p_max=4, fresh=1, root_draw=1),                                  # fresh deals
+    dict(p_min=2, p_max=4, pile_min=0, pile_max=16, revealed_max=8, phase_mix=1),  # training data
+    dict(p_min=3, p_max=3, pile_min=5, pile_max=5, revealed_max=0),                # fixed pool
+]
+
+
+@pytest.mark.parametrize("cfg", range(len(CONFIGS)))
+def test_init_states_bit_exact(orc, dvc, cfg):
+    po, pd = deal_pair(orc, dvc, **CONFIGS[cfg])
+    for n, base in [(1, 0), (1000, 0), (4096, 7), (333, 2**31 + 5)]:
+        ref = orc.init_states(n, po, seed=2 + cfg, index_base=base)
+        got = to_np(dvc.dvc_init_states(n, pd, seed=2 + cfg, index_base=base))
+        torch.cuda.synchronize()
+        assert np.array_equal(got, ref), f"config {cfg} n={n}"
+    assert dvc.dvc_check() == 0
+
+
+def _rollout_ref(orc, states, ppl, seed, tree, base):
+    return orc.rollout(states, ppl, seed, tree_id=tree, leaf_id_base=base, threads=8)
+
+
+def _compare(dvc, states_np, ppl, seed, tree, base, ref, **kw):
+    st = dev_states(states_np)
+    w, ln, sw = dvc.dvc_rollout(st, ppl, seed, tree, base, **kw)
+    torch.cuda.synchronize()
+    rw, rl, rs = ref
+    assert np.array_equal(w.cpu().numpy(), rw), "winner"
+    assert np.array_equal(ln.cpu().numpy(), rl), "length"
+    assert np.array_equal(sw.cpu().numpy().view(np.uint32), rs), "seat wins"
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("P", [2, 3, 4])
+def test_rollout_bit_exact_small(orc, dvc, variant, P):
+    po = orc.deal_params(p_min=P, p_max=P, pile_min=0, pile_max=16, revealed_max=8, phase_mix=1)
+    S = orc.init_states(301, po, seed=31 + P)          # ragged: not a multiple of any tile
+    ppl, seed, tree, base = 37, 12345 + P, 9, 1000
+    ref = _rollout_ref(orc, S, ppl, seed, tree, base)
+    _compare(dvc, S, ppl, seed, tree, base, ref, variant=variant)
+    assert dvc.dvc_check() == 0
+
+
+@pytest.mark.parametrize("block,grid", [(64, 1), (64, 7), (128, 33), (256, 0), (512, 5),
+                                        (256, 2048)])
+def test_rollout_schedule_invariance(orc, dvc, block, grid):
+    po = orc.deal_params(p_min=2, p_max=4, pile_min=0, pile_max=16, revealed_max=8)
+    S = orc.init_states(200, po, seed=5)
+    ppl = 64
+    ref = _rollout_ref(orc, S, ppl, 77, 3, 0)
+    _compare(dvc, S, ppl, 77, 3, 0, ref, variant=2, block=block, grid=grid)
+
+
+@pytest.mark.parametrize("ppl", [1, 2, 63, 64, 65, 1000])
+def test_rollout_ppl_edges(orc, dvc, ppl):
+    po = orc.deal_params(p_min=2, p_max=3, pile_min=0, pile_max=16, revealed_max=8)
+    n = max(1, 3000 // ppl)
+    S = orc.init_states(n, po, seed=ppl)
+    ref = _rollout_ref(orc, S, ppl, 4, 0, 17)
+    _compare(dvc, S, ppl, 4, 0, 17, ref)
+
+
+def test_rollout_batch_invariance(orc, dvc):
+    # a leaf gives the same playouts alone (with its leaf id) as inside a batch
+    po = orc.deal_params(p_min=2, p_max=4, pile_min=0, pile_max=16, revealed_max=8)
+    S = orc.init_states(64, po, seed=8)
+    st = dev_states(S)
+    wb, lb, sb = dvc.dvc_rollout(st, 32, 99, 5, 100)
+    for i in [0, 13, 63]:
+        wi, li, si = dvc.dvc_rollout(st[i:i + 1].contiguous(), 32, 99, 5, 100 + i)
+        assert torch.equal(wi, wb[i * 32:(i + 1) * 32]) and torch.equal(li, lb[i * 32:(i + 1) * 32])
+        assert torch.equal(si[0], sb[i])
+
+
+def test_rollout_optional_outputs(orc, dvc):
+    po = orc.deal_params(p_min=2, p_max=2, pile_min=0, pile_max=16, revealed_max=8)
+    S = orc.init_states(50, po, seed=3)
+    ref = _rollout_ref(orc, S, 16, 1, 0, 0)
+    st = dev_states(S)
+    w, ln, sw = dvc.dvc_rollout(st, 16, 1, 0, 0, winner=False, length=False, seat_wins=True)
+    assert w is None and ln is None
+    assert np.array_equal(sw.cpu().numpy().view(np.uint32), ref[2])
+    w, ln, sw = dvc.dvc_rollout(st, 16, 1, 0, 0, winner=True, length=False, seat_wins=False)
+    assert np.array_equal(w.cpu().numpy(), ref[0])
+
+
+def test_rollout_decided_and_malformed_leaves(orc, dvc):
+    import positions as POS
+    rng = np.random.default_rng(9)
+    pos = POS.tiny_endgame(rng, 2, hidden_per_seat=(1, 1), pool=(0, 0))
+    o = 1 - pos["mover"]
+    pos["revealed"] = set(pos["revealed"]) | {t for t in range(24) if pos["owner"][t] == o}
+    decided = POS.pack(pos)
+    good = orc.init_states(3, orc.deal_params(p_min=2, p_max=2), seed=1)
+    bad = good[1].copy()
+    bad[2] |= np.uint32(1 << 30)
+    S = np.stack([good[0], decided, good[2]])
+    ref = _rollout_ref(orc, S, 8, 2, 0, 0)
+    _compare(dvc, S, 8, 2, 0, 0, ref)
+    assert np.all(ref[1][8:16] == 0) and np.all(ref[0][8:16] == pos["mover"])
+    assert dvc.dvc_check() == 0
+    S2 = np.stack([good[0], bad, good[2]])
+    st = dev_states(S2)
+    w, ln, sw = dvc.dvc_rollout(st, 8, 2, 0, 0)
+    assert dvc.dvc_check() == dvc.DVC_ESTATE
+    assert np.all(w.cpu().numpy()[8:16] == -1) and np.all(ln.cpu().numpy()[8:16] == -1)
+    assert np.array_equal(w.cpu().numpy()[:8], ref[0][:8])
+    assert sw.cpu().numpy()[1].sum() == 0
+    assert dvc.dvc_check() == 0, "the error word is cleared after being read"
+
+
+def test_rollout_argument_errors(dvc):
+    st = torch.zeros((4, 4), dtype=torch.int32, device="cuda")
+    with pytest.raises(dvc.DvcError):
+        dvc.dvc_rollout(st, 0, 1)
+    with pytest.raises(dvc.DvcError):
+        dvc.dvc_rollout(st, 8, 1, variant=7)
+    with pytest.raises(dvc.DvcError):
+        dvc.dvc_rollout(st, 8, 1, variant=2, block=96)
+    # empty batch is fine and writes nothing
+    e = torch.zeros((0, 4), dtype=torch.int32, device="cuda")
+    w, ln, sw = dvc.dvc_rollout(e, 8, 1)
+    assert w.numel() == 0 and sw.numel() == 0
+
+
+def test_rollout_full_leaf_parallel_workload(orc, dvc):
+    """4096 mid-game two-player leaves x 256 playouts = 1,048,576 playouts, all compared."""
+    po, pd = deal_pair(orc, dvc, p_min=2, p_max=2, pile_min=0, pile_max=16, revealed_max=8)
+    S = orc.init_states(4096, po, seed=2)
+    st = dvc.dvc_init_states(4096, pd, seed=2)
+    assert np.array_equal(to_np(st), S)
+    ref = _rollout_ref(orc, S, 256, 2, 0, 0)
+    for variant in [1, 2]:
+        w, ln, sw = dvc.dvc_rollout(st, 256, 2, 0, 0, variant=variant)
+        torch.cuda.synchronize()
+        assert np.array_equal(w.cpu().numpy(), ref[0])
+        assert np.array_equal(ln.cpu().numpy(), ref[1])
+        assert np.array_equal(sw.cpu().numpy().view(np.uint32), ref[2])
