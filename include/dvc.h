@@ -119,13 +119,14 @@ int dvc_init_states(dvc_state_t *out, int64_t n, const dvc_deal_params *params /
  *   seat_wins[i*4 + s] uint32 playouts of leaf i won by seat s
  * A malformed leaf yields winner -1, length -1, no wins, and DVC_ESTATE in the
  * error word.  Returns DVC_EINVAL for n_leaves < 0, playouts_per_leaf < 1,
- * n_leaves*playouts_per_leaf >= 2^40 or leaves == NULL with n_leaves > 0.  */
+ * n_leaves*playouts_per_leaf >= 2^32 or leaves == NULL with n_leaves > 0.  */
 int dvc_rollout(const dvc_state_t *leaves, int64_t n_leaves, int32_t playouts_per_leaf,
                 uint64_t seed, uint32_t tree_id, uint32_t leaf_id_base,
                 int8_t *winner, int16_t *length, uint32_t *seat_wins, void *stream);
 
 /* Rollout kernel variants, for measurement: 0 = automatic (the fastest),
- * 1 = one lane per playout, 2 = lane refill + persistent work stealing.
+ * 1 = one lane per playout, 2 = lane refill + work stealing over LDS-staged
+ * leaf chunks, 3 = lane refill + work stealing over single-leaf items.
  * block/grid 0 = automatic.  Same outputs for every variant and shape.    */
 int dvc_rollout_ex(const dvc_state_t *leaves, int64_t n_leaves, int32_t playouts_per_leaf,
                    uint64_t seed, uint32_t tree_id, uint32_t leaf_id_base,

@@ -106,7 +106,7 @@ int dvc_rollout_ex(const dvc_state_t *leaves, int64_t n_leaves, int32_t ppl, uin
 {
     if (n_leaves < 0 || ppl < 1 || (n_leaves > 0 && leaves == nullptr)) return DVC_EINVAL;
     if ((uint64_t)n_leaves * (uint64_t)ppl >= (1ull << 32)) return DVC_EINVAL;
-    if (variant < 0 || variant > 2) return DVC_EINVAL;
+    if (variant < 0 || variant > 3) return DVC_EINVAL;
     if (block != 0 && block != 64 && block != 128 && block != 256 && block != 512) return DVC_EINVAL;
     if (grid < 0) return DVC_EINVAL;
     hipStream_t st = (hipStream_t)stream;
@@ -122,6 +122,13 @@ int dvc_rollout_ex(const dvc_state_t *leaves, int64_t n_leaves, int32_t ppl, uin
     // a chunk never spans more than kStageLeaves leaves
     const uint64_t max_chunk = (uint64_t)(kStageLeaves - 1u) * (uint64_t)ppl;
     a.chunk = (uint32_t)(max_chunk < 256u ? max_chunk : 256u);
+    // single-leaf items of at most one playout per lane
+    a.item_chunk = (uint32_t)(ppl < 64 ? ppl : 64);
+    a.parts = ((uint32_t)ppl + a.item_chunk - 1u) / a.item_chunk;
+    const uint64_t n_items = (uint64_t)n_leaves * a.parts;
+    if (n_items >= (1ull << 32)) return DVC_EINVAL;
+    a.n_items = (uint32_t)n_items;
+    a.batch = 128u / a.item_chunk > 0u ? 128u / a.item_chunk : 1u;
     a.queue_slot = next_queue_slot();
     a.winner = winner;
     a.length = length;
@@ -132,7 +139,7 @@ int dvc_rollout_ex(const dvc_state_t *leaves, int64_t n_leaves, int32_t ppl, uin
         hipError_t e = launch_fill_u32(seat_wins, (uint64_t)n_leaves * 4u, 0u, st);
         if (e != hipSuccess) return DVC_EHIP;
     }
-    const int v = variant == 0 ? 2 : variant;
+    const int v = variant == 0 ? 3 : variant;
     return status_of(launch_rollout(a, v, block, grid, st));
 }
 

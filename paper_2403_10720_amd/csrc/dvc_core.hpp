@@ -87,6 +87,41 @@ __device__ __forceinline__ uint32_t pick_bit(uint32_t m, uint32_t w)
     return kth_bit(m, pick(w, (uint32_t)__popc(m)));
 }
 
+// k-th set bit through a 2 KB LDS table: tab[8*b + i] is the position of the
+// i-th set bit of byte b.  Two bit counts choose the byte that holds the
+// k-th bit of the 24-bit mask, one LDS byte read finishes the search.
+constexpr uint32_t kKthTableBytes = 256u * 8u;
+
+__device__ __forceinline__ void fill_kth_table(uint8_t *tab)
+{
+    for (uint32_t i = threadIdx.x; i < kKthTableBytes; i += blockDim.x) {
+        const uint32_t b = i >> 3, k = i & 7u;
+        uint32_t pos = 0u, cnt = 0u;
+        for (uint32_t bit = 0; bit < 8u; ++bit)
+            if ((b >> bit) & 1u) {
+                if (cnt == k) pos = bit;
+                ++cnt;
+            }
+        tab[i] = (uint8_t)pos;
+    }
+}
+
+__device__ __forceinline__ uint32_t kth_bit_tab(uint32_t m, uint32_t k, const uint8_t *tab)
+{
+    const uint32_t c0 = (uint32_t)__popc(m & 0xFFu);
+    const uint32_t c01 = (uint32_t)__popc(m & 0xFFFFu);
+    const bool b2 = k >= c01, b1 = k >= c0;
+    const uint32_t sh = b2 ? 16u : (b1 ? 8u : 0u);
+    const uint32_t base = b2 ? c01 : (b1 ? c0 : 0u);
+    const uint32_t byte = (m >> sh) & 0xFFu;
+    return sh + tab[(byte << 3) | ((k - base) & 7u)];
+}
+
+__device__ __forceinline__ uint32_t pick_bit_tab(uint32_t m, uint32_t w, const uint8_t *tab)
+{
+    return kth_bit_tab(m, pick(w, (uint32_t)__popc(m)), tab);
+}
+
 // Game state in registers: one tile mask per seat (seats >= P are empty).
 struct State {
     uint32_t h0, h1, h2, h3;  // rows
@@ -97,17 +132,20 @@ struct State {
     int32_t drawn;            // tile drawn this turn, -1 none
 };
 
+// row of seat q, as two levels of selects (no branches)
 __device__ __forceinline__ uint32_t hand_of(const State &s, uint32_t q)
 {
-    return q == 0 ? s.h0 : q == 1 ? s.h1 : q == 2 ? s.h2 : s.h3;
+    const uint32_t lo = (q & 1u) ? s.h1 : s.h0;
+    const uint32_t hi = (q & 1u) ? s.h3 : s.h2;
+    return (q & 2u) ? hi : lo;
 }
 
 __device__ __forceinline__ void add_to_hand(State &s, uint32_t q, uint32_t bit)
 {
-    s.h0 |= q == 0 ? bit : 0u;
-    s.h1 |= q == 1 ? bit : 0u;
-    s.h2 |= q == 2 ? bit : 0u;
-    s.h3 |= q == 3 ? bit : 0u;
+    s.h0 |= q == 0u ? bit : 0u;
+    s.h1 |= q == 1u ? bit : 0u;
+    s.h2 |= q == 2u ? bit : 0u;
+    s.h3 |= q == 3u ? bit : 0u;
 }
 
 // Decode the packed 16-byte format; returns false for a malformed state.

@@ -26,7 +26,11 @@ struct RolloutArgs {
     const uint4 *leaves;
     uint32_t n_leaves, ppl, total;   // total = n_leaves * ppl < 2^32
     uint32_t k0, k1, tree, leaf_base;
-    uint32_t chunk;                  // playout ids per stolen chunk
+    uint32_t chunk;                  // variant 2: playout ids per stolen chunk
+    uint32_t item_chunk;             // variant 3: playouts per single-leaf item
+    uint32_t parts;                  // variant 3: items per leaf
+    uint32_t n_items;                // variant 3: n_leaves * parts
+    uint32_t batch;                  // variant 3: items per stolen batch
     uint32_t queue_slot;
     int8_t *winner;
     int16_t *length;

@@ -17,13 +17,14 @@ namespace dvc {
 // Returns true when the game is decided; `winner` is then the last seat with
 // a hidden tile.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ bool guess_step(State &s, const Words &w, uint32_t &winner)
+__device__ __forceinline__ bool guess_step(State &s, const Words &w, uint32_t &winner,
+                                           const uint8_t *tab)
 {
     const uint32_t owned = s.h0 | s.h1 | s.h2 | s.h3;
     const uint32_t pool = ~owned & kAll;
     const bool turn_start = s.phase == 0u;
     const bool draw = turn_start && pool != 0u;
-    const uint32_t d = pick_bit(pool, w.w0);
+    const uint32_t d = pick_bit_tab(pool, w.w0, tab);
     const uint32_t dbit = draw ? (1u << d) : 0u;
     add_to_hand(s, s.m, dbit);
     s.drawn = turn_start ? (draw ? (int32_t)d : -1) : s.drawn;
@@ -31,15 +32,15 @@ __device__ __forceinline__ bool guess_step(State &s, const Words &w, uint32_t &w
 
     const uint32_t hm = hand_of(s, s.m);
     const uint32_t targets = (owned | dbit) & ~hm & ~s.rev;
-    const uint32_t t = pick_bit(targets, w.w1);
+    const uint32_t t = pick_bit_tab(targets, w.w1, tab);
     const uint32_t tb = 1u << t;
     const uint32_t o = (s.h0 & tb) ? 0u : (s.h1 & tb) ? 1u : (s.h2 & tb) ? 2u : 3u;
     const uint32_t cand = candidates(t, hand_of(s, o), hm, s.rev);
-    const uint32_t v = pick_bit(cand, w.w2);
+    const uint32_t v = pick_bit_tab(cand, w.w2, tab);
     const bool right = v == t;
 
     const uint32_t own_hidden = hm & ~s.rev;
-    const uint32_t r = pick_bit(own_hidden, w.w3);
+    const uint32_t r = pick_bit_tab(own_hidden, w.w3, tab);
     const uint32_t wrong_bit = 1u << (s.drawn >= 0 ? (uint32_t)s.drawn : r);
     s.rev |= right ? tb : wrong_bit;
 
@@ -85,6 +86,21 @@ __device__ __forceinline__ void next_step(PlayoutKey &pk)
     pk.gm_hi = (uint32_t)(g >> 32);
 }
 
+// The leaf array is read-only for a whole launch, so a wave-uniform leaf
+// state is read with scalar loads through the constant address space (the
+// wait for it then does not also wait for the lanes' outstanding stores).
+typedef const __attribute__((address_space(4))) uint32_t *const_u32_ptr;
+
+__device__ __forceinline__ void load_uniform_state(const uint4 *base, uint32_t idx, uint32_t &w0,
+                                                   uint32_t &w1, uint32_t &w2, uint32_t &w3)
+{
+    const_u32_ptr p = (const_u32_ptr)((uintptr_t)base) + 4u * idx;
+    w0 = p[0];
+    w1 = p[1];
+    w2 = p[2];
+    w3 = p[3];
+}
+
 __device__ __forceinline__ void record_win(uint32_t *seat_wins, uint32_t leaf, uint32_t winner)
 {
     if (seat_wins && winner < 4u) atomicAdd(&seat_wins[(size_t)leaf * 4u + winner], 1u);
@@ -100,6 +116,9 @@ constexpr uint32_t kMaxGuesses = 23u;
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) rollout_lane_per_playout(RolloutArgs a)
 {
+    __shared__ uint8_t tab[kKthTableBytes];
+    fill_kth_table(tab);
+    __syncthreads();
     const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= a.total) return;
     const uint32_t leaf = j / a.ppl;
@@ -120,7 +139,7 @@ __global__ void __launch_bounds__(256) rollout_lane_per_playout(RolloutArgs a)
     uint32_t len = 0;
     while (!over) {
         const Words w = step_words(pk, trk1, a.k0, a.k1);
-        over = guess_step(s, w, winner);
+        over = guess_step(s, w, winner, tab);
         next_step(pk);
         ++len;
         if (!over && len >= kMaxGuesses) {
@@ -149,6 +168,9 @@ template <int WAVES>
 __global__ void __launch_bounds__(WAVES * 64) rollout_persistent(RolloutArgs a)
 {
     __shared__ uint4 stage[WAVES][kStageLeaves];
+    __shared__ uint8_t tab[kKthTableBytes];
+    fill_kth_table(tab);
+    __syncthreads();
     const uint32_t lane = threadIdx.x & 63u;
     uint4 *my = stage[threadIdx.x >> 6];
     uint32_t *queue = &g_queue[a.queue_slot][0];
@@ -225,7 +247,7 @@ __global__ void __launch_bounds__(WAVES * 64) rollout_persistent(RolloutArgs a)
         bool over = false;
         if (active) {
             const Words w = step_words(pk, trk1, a.k0, a.k1);
-            over = guess_step(s, w, winner);
+            over = guess_step(s, w, winner, tab);
             next_step(pk);
             ++len;
             if (!over && len >= kMaxGuesses) {
@@ -274,6 +296,163 @@ __global__ void __launch_bounds__(WAVES * 64) rollout_persistent(RolloutArgs a)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Variant 3: persistent waves over single-leaf work items.
+//
+// An item is up to `item_chunk` consecutive playouts of ONE leaf: item c
+// covers leaf c / parts, playouts (c % parts) * item_chunk onwards.  Waves
+// steal batches of `batch` items from a global counter and prefetch the next
+// batch id one batch ahead, so the atomic's round trip is hidden behind a
+// batch of guesses.  The item's leaf state is wave-uniform: it is loaded,
+// decoded and validated once in scalar registers and copied into every lane
+// the item refills (ballot + mbcnt prefix over the idle lanes).  A decided or
+// malformed leaf finishes its whole item at once.
+// ---------------------------------------------------------------------------
+template <int WAVES>
+__global__ void __launch_bounds__(WAVES * 64) rollout_items(RolloutArgs a)
+{
+    __shared__ uint8_t tab[kKthTableBytes];
+    fill_kth_table(tab);
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63u;
+    uint32_t *queue = &g_queue[a.queue_slot][0];
+    const uint32_t trk1 = a.tree ^ a.k1;
+
+    uint32_t item = 0, item_end = 0;         // wave-uniform: items of the current batch
+    uint32_t pending = 0;                    // lane 0: prefetched batch id
+    if (lane == 0) pending = atomicAdd(&queue[0], 1u);
+    bool drained = false;
+    uint32_t it_leaf = 0, it_p = 0, it_pend = 0, it_pa = 0, it_pb = 0;   // current item
+    State it_s;
+    it_s.h0 = it_s.h1 = it_s.h2 = it_s.h3 = it_s.rev = 0u;
+    it_s.m = 0u; it_s.P = 2u; it_s.phase = 1u; it_s.drawn = -1;
+
+    bool active = false;
+    State s = it_s;
+    PlayoutKey pk = {0u, 0u, 0u, 0u};
+    uint32_t j = 0, leaf = 0, len = 0, winner = 0;
+    uint64_t steps = 0;
+
+    for (;;) {
+        // ---- refill idle lanes from the current item --------------------
+        uint64_t idle = __ballot(!active);
+        while (idle != 0ull && !drained) {
+            if (it_p == it_pend) {
+                if (item == item_end) {
+                    const uint32_t b = __builtin_amdgcn_readfirstlane(pending);
+                    if ((uint64_t)b * a.batch >= a.n_items) { drained = true; break; }
+                    item = b * a.batch;
+                    item_end = min(item + a.batch, a.n_items);
+                    if (lane == 0) pending = atomicAdd(&queue[0], 1u);
+                }
+                const uint32_t c = item++;
+                it_leaf = c / a.parts;
+                it_p = (c - it_leaf * a.parts) * a.item_chunk;
+                it_pend = min(it_p + a.item_chunk, a.ppl);
+                uint32_t w0, w1, w2, w3;
+                load_uniform_state(a.leaves, it_leaf, w0, w1, w2, w3);
+                const bool ok = decode(w0, w1, w2, w3, it_s);
+                const uint32_t alive = alive_mask(it_s);
+                if (!ok || __popc(alive) == 1) {
+                    const int8_t wv = ok ? (int8_t)__builtin_ctz(alive) : (int8_t)-1;
+                    const int16_t lv = ok ? (int16_t)0 : (int16_t)-1;
+                    for (uint32_t p = it_p + lane; p < it_pend; p += 64u) {
+                        const uint32_t jj = it_leaf * a.ppl + p;
+                        if (a.winner) a.winner[jj] = wv;
+                        if (a.length) a.length[jj] = lv;
+                    }
+                    if (lane == 0) {
+                        if (!ok)
+                            atomicOr(&g_error_word, kErrState);
+                        else if (a.seat_wins)
+                            atomicAdd(&a.seat_wins[(size_t)it_leaf * 4u + (uint32_t)wv],
+                                      it_pend - it_p);
+                    }
+                    it_p = it_pend;
+                    continue;
+                }
+                const uint64_t pl = (uint64_t)(a.leaf_base + it_leaf) * kPhiloxM1;
+                it_pa = (uint32_t)(pl >> 32) ^ a.k0;
+                it_pb = (uint32_t)pl;
+            }
+            const uint32_t take = min<uint32_t>((uint32_t)__popcll(idle), it_pend - it_p);
+            const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
+                (uint32_t)(idle >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)idle, 0u));
+            const bool mine = ((idle >> lane) & 1ull) && rank < take;
+            if (mine) {
+                const uint32_t p = it_p + rank;
+                s = it_s;
+                pk.a = it_pa ^ p;
+                pk.b = it_pb;
+                pk.gm_lo = 0u;
+                pk.gm_hi = 0u;
+                j = it_leaf * a.ppl + p;
+                leaf = it_leaf;
+                len = 0;
+                active = true;
+            }
+            it_p += take;
+            idle &= ~__ballot(mine);
+        }
+        if (__ballot(active) == 0ull) {
+            if (drained) break;
+            continue;
+        }
+        ++steps;
+
+        // ---- one guess for every active lane ----------------------------
+        bool over = false;
+        if (active) {
+            const Words w = step_words(pk, trk1, a.k0, a.k1);
+            over = guess_step(s, w, winner, tab);
+            next_step(pk);
+            ++len;
+            if (!over && len >= kMaxGuesses) {
+                atomicOr(&g_error_word, kErrLimit);
+                over = true;
+                winner = 4u;
+            }
+        }
+
+        // ---- finished games: outputs and per-leaf seat wins -------------
+        const bool fin = active && over;
+        if (fin) {
+            if (a.winner) a.winner[j] = (int8_t)(winner < 4u ? (int)winner : -1);
+            if (a.length) a.length[j] = (int16_t)len;
+        }
+        if (a.seat_wins) {
+            uint64_t fmask = __ballot(fin);
+            while (fmask != 0ull) {
+                const uint32_t first = (uint32_t)__builtin_ctzll(fmask);
+                const uint32_t L = __builtin_amdgcn_readlane(leaf, first);
+                const bool mineL = fin && leaf == L;
+                const uint64_t same = __ballot(mineL);
+                const uint32_t c0 = (uint32_t)__popcll(__ballot(mineL && winner == 0u));
+                const uint32_t c1 = (uint32_t)__popcll(__ballot(mineL && winner == 1u));
+                const uint32_t c2 = (uint32_t)__popcll(__ballot(mineL && winner == 2u));
+                const uint32_t c3 = (uint32_t)__popcll(__ballot(mineL && winner == 3u));
+                if (lane < 4u) {
+                    const uint32_t c = lane == 0u ? c0 : lane == 1u ? c1 : lane == 2u ? c2 : c3;
+                    if (c) atomicAdd(&a.seat_wins[(size_t)L * 4u + lane], c);
+                }
+                fmask &= ~same;
+            }
+        }
+        active = active && !over;
+    }
+
+    if (a.stats && lane == 0) atomicAdd(&a.stats[0], (unsigned long long)steps);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const uint32_t done = atomicAdd(&queue[1], 1u);
+        if (done == gridDim.x - 1u) {
+            atomicExch(&queue[0], 0u);
+            atomicExch(&queue[1], 0u);
+        }
+    }
+}
+
 __global__ void fill_u32(uint32_t *p, uint64_t n, uint32_t v)
 {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -302,6 +481,16 @@ hipError_t launch_rollout(const RolloutArgs &a, int variant, int block, int grid
     }
     int waves = block > 0 ? block / 64 : 4;
     if (grid <= 0) grid = default_rollout_grid(waves);
+    if (variant == 3) {
+        switch (waves) {
+        case 1: hipLaunchKernelGGL(rollout_items<1>, dim3(grid), dim3(64), 0, st, a); break;
+        case 2: hipLaunchKernelGGL(rollout_items<2>, dim3(grid), dim3(128), 0, st, a); break;
+        case 4: hipLaunchKernelGGL(rollout_items<4>, dim3(grid), dim3(256), 0, st, a); break;
+        case 8: hipLaunchKernelGGL(rollout_items<8>, dim3(grid), dim3(512), 0, st, a); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     switch (waves) {
     case 1: hipLaunchKernelGGL(rollout_persistent<1>, dim3(grid), dim3(64), 0, st, a); break;
     case 2: hipLaunchKernelGGL(rollout_persistent<2>, dim3(grid), dim3(128), 0, st, a); break;

@@ -70,7 +70,7 @@ def _compare(dvc, states_np, ppl, seed, tree, base, ref, **kw):
     assert np.array_equal(sw.cpu().numpy().view(np.uint32), rs), "seat wins"
 
 
-@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("variant", [1, 2, 3])
 @pytest.mark.parametrize("P", [2, 3, 4])
 def test_rollout_bit_exact_small(orc, dvc, variant, P):
     po = orc.deal_params(p_min=P, p_max=P, pile_min=0, pile_max=16, revealed_max=8, phase_mix=1)
@@ -81,23 +81,25 @@ def test_rollout_bit_exact_small(orc, dvc, variant, P):
     assert dvc.dvc_check() == 0
 
 
+@pytest.mark.parametrize("variant", [2, 3])
 @pytest.mark.parametrize("block,grid", [(64, 1), (64, 7), (128, 33), (256, 0), (512, 5),
                                         (256, 2048)])
-def test_rollout_schedule_invariance(orc, dvc, block, grid):
+def test_rollout_schedule_invariance(orc, dvc, variant, block, grid):
     po = orc.deal_params(p_min=2, p_max=4, pile_min=0, pile_max=16, revealed_max=8)
     S = orc.init_states(200, po, seed=5)
-    ppl = 64
+    ppl = 100
     ref = _rollout_ref(orc, S, ppl, 77, 3, 0)
-    _compare(dvc, S, ppl, 77, 3, 0, ref, variant=2, block=block, grid=grid)
+    _compare(dvc, S, ppl, 77, 3, 0, ref, variant=variant, block=block, grid=grid)
 
 
-@pytest.mark.parametrize("ppl", [1, 2, 63, 64, 65, 1000])
-def test_rollout_ppl_edges(orc, dvc, ppl):
+@pytest.mark.parametrize("variant", [2, 3])
+@pytest.mark.parametrize("ppl", [1, 2, 63, 64, 65, 129, 1000])
+def test_rollout_ppl_edges(orc, dvc, variant, ppl):
     po = orc.deal_params(p_min=2, p_max=3, pile_min=0, pile_max=16, revealed_max=8)
     n = max(1, 3000 // ppl)
     S = orc.init_states(n, po, seed=ppl)
     ref = _rollout_ref(orc, S, ppl, 4, 0, 17)
-    _compare(dvc, S, ppl, 4, 0, 17, ref)
+    _compare(dvc, S, ppl, 4, 0, 17, ref, variant=variant)
 
 
 def test_rollout_batch_invariance(orc, dvc):
@@ -124,7 +126,8 @@ def test_rollout_optional_outputs(orc, dvc):
     assert np.array_equal(w.cpu().numpy(), ref[0])
 
 
-def test_rollout_decided_and_malformed_leaves(orc, dvc):
+@pytest.mark.parametrize("variant", [1, 2, 3])
+def test_rollout_decided_and_malformed_leaves(orc, dvc, variant):
     import positions as POS
     rng = np.random.default_rng(9)
     pos = POS.tiny_endgame(rng, 2, hidden_per_seat=(1, 1), pool=(0, 0))
@@ -136,12 +139,12 @@ def test_rollout_decided_and_malformed_leaves(orc, dvc):
     bad[2] |= np.uint32(1 << 30)
     S = np.stack([good[0], decided, good[2]])
     ref = _rollout_ref(orc, S, 8, 2, 0, 0)
-    _compare(dvc, S, 8, 2, 0, 0, ref)
+    _compare(dvc, S, 8, 2, 0, 0, ref, variant=variant)
     assert np.all(ref[1][8:16] == 0) and np.all(ref[0][8:16] == pos["mover"])
     assert dvc.dvc_check() == 0
     S2 = np.stack([good[0], bad, good[2]])
     st = dev_states(S2)
-    w, ln, sw = dvc.dvc_rollout(st, 8, 2, 0, 0)
+    w, ln, sw = dvc.dvc_rollout(st, 8, 2, 0, 0, variant=variant)
     assert dvc.dvc_check() == dvc.DVC_ESTATE
     assert np.all(w.cpu().numpy()[8:16] == -1) and np.all(ln.cpu().numpy()[8:16] == -1)
     assert np.array_equal(w.cpu().numpy()[:8], ref[0][:8])
@@ -155,6 +158,8 @@ def test_rollout_argument_errors(dvc):
         dvc.dvc_rollout(st, 0, 1)
     with pytest.raises(dvc.DvcError):
         dvc.dvc_rollout(st, 8, 1, variant=7)
+    with pytest.raises(dvc.DvcError):
+        dvc.dvc_rollout(st, 8, 1, variant=3, block=96)
     with pytest.raises(dvc.DvcError):
         dvc.dvc_rollout(st, 8, 1, variant=2, block=96)
     # empty batch is fine and writes nothing
@@ -170,7 +175,7 @@ def test_rollout_full_leaf_parallel_workload(orc, dvc):
     st = dvc.dvc_init_states(4096, pd, seed=2)
     assert np.array_equal(to_np(st), S)
     ref = _rollout_ref(orc, S, 256, 2, 0, 0)
-    for variant in [1, 2]:
+    for variant in [1, 2, 3]:
         w, ln, sw = dvc.dvc_rollout(st, 256, 2, 0, 0, variant=variant)
         torch.cuda.synchronize()
         assert np.array_equal(w.cpu().numpy(), ref[0])
