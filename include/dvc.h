@@ -126,8 +126,10 @@ int dvc_rollout(const dvc_state_t *leaves, int64_t n_leaves, int32_t playouts_pe
 
 /* Rollout kernel variants, for measurement: 0 = automatic (the fastest),
  * 1 = one lane per playout, 2 = lane refill + work stealing over LDS-staged
- * leaf chunks, 3 = lane refill + work stealing over single-leaf items.
- * block/grid 0 = automatic.  Same outputs for every variant and shape.    */
+ * leaf chunks, 3 = lane refill + work stealing over single-leaf items,
+ * 4 = several playouts per lane back to back (`grid` then gives the playouts
+ * per lane, 1/2/4).  block/grid 0 = automatic.  Same outputs for every variant
+ * and shape.                                                                */
 int dvc_rollout_ex(const dvc_state_t *leaves, int64_t n_leaves, int32_t playouts_per_leaf,
                    uint64_t seed, uint32_t tree_id, uint32_t leaf_id_base,
                    int8_t *winner, int16_t *length, uint32_t *seat_wins,
@@ -145,7 +147,7 @@ int dvc_rollout_ex(const dvc_state_t *leaves, int64_t n_leaves, int32_t playouts
  *      tiles are a black box, Sec. III-A): per opponent from the mover's left,
  *      per run of hidden slots between revealed tiles, bounds right to left
  *      (largest available tile of the slot's colour below the next bound),
- *      then values left to right, uniform in (previous, bound]; up to 16
+ *      then values left to right, uniform in (previous, bound]; up to 64
  *      attempts, then the smallest consistent world in slot order;
  *   2. descend from the root: a decided state is the leaf; at depth
  *      max_depth the node is the leaf; else the lowest legal action id that

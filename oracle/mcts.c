@@ -180,15 +180,20 @@ typedef struct {
     int o, j, colour, lo, hi, seg_start;
 } dslot;
 
-static int dfs(dslot *sl, int ns, int k, int *avail, int *assign)
+/* the search gives up (error) after this many calls */
+#define ORC_DFS_MAX_CALLS (1L << 22)
+
+static int dfs(dslot *sl, int ns, int k, int *avail, int *assign, long *calls)
 {
+    if (++*calls > ORC_DFS_MAX_CALLS) return -1;
     if (k == ns) return 1;
     int prev = sl[k].seg_start ? sl[k].lo : assign[k - 1];
     for (int x = prev + 1; x < sl[k].hi; ++x) {
         if (!avail[x] || (x & 1) != sl[k].colour) continue;
         avail[x] = 0;
         assign[k] = x;
-        if (dfs(sl, ns, k + 1, avail, assign)) return 1;
+        int r = dfs(sl, ns, k + 1, avail, assign, calls);
+        if (r != 0) return r;
         avail[x] = 1;
     }
     return 0;
@@ -224,7 +229,8 @@ static int det_fallback(const orc_rows *root, orc_rows *world)
         }
     }
     int assign[24];
-    if (!dfs(sl, ns, 0, avail, assign)) return 1;
+    long calls = 0;
+    if (dfs(sl, ns, 0, avail, assign, &calls) != 1) return 1;
     for (int k = 0; k < ns; ++k) world->tile[sl[k].o][sl[k].j] = assign[k];
     world->pile_n = 0;
     for (int t = 0; t < 24; ++t)
@@ -232,14 +238,17 @@ static int det_fallback(const orc_rows *root, orc_rows *world)
     return 0;
 }
 
+/* attempts of the random sampler before the deterministic fallback */
+#define ORC_DET_ATTEMPTS 64
+
 static int determinize_rows(const orc_rows *root, uint64_t seed, uint32_t tree, uint32_t iter,
                             orc_rows *world)
 {
-    for (uint32_t a = 0; a < 16; ++a) {
+    for (uint32_t a = 0; a < ORC_DET_ATTEMPTS; ++a) {
         dstream ds = {seed, 0x80000000u + a, iter, tree, 0};
         if (det_attempt(root, &ds, world) == 0) return (int)a;
     }
-    if (det_fallback(root, world) == 0) return 16;
+    if (det_fallback(root, world) == 0) return ORC_DET_ATTEMPTS;
     return -3;
 }
 

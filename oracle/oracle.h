@@ -109,7 +109,7 @@ int oracle_init_states(orc_packed *out, int64_t n, const orc_deal_params *p, uin
                        uint32_t index_base);
 
 /* determinized world of iteration i for the root mover; returns the attempt
- * that succeeded (0..15) or 16 for the deterministic fallback, -2 if invalid */
+ * that succeeded (0..63) or 64 for the deterministic fallback, -2 if invalid */
 int oracle_determinize(const orc_packed *root, uint64_t seed, uint32_t tree, uint32_t iter,
                        orc_packed *world);
 

@@ -2,9 +2,11 @@
 // argument checks, launch-shape choice and kernel launches on the caller's
 // stream.  Nothing here allocates per call.
 #include <atomic>
+#include <cmath>
 #include <mutex>
+#include <vector>
 
-#include "../../include/dvc.h"
+#include "dvc.h"
 #include "dvc_internal.hpp"
 
 namespace dvc {
@@ -39,6 +41,57 @@ int default_rollout_grid(int waves_per_block)
 }
 
 static int status_of(hipError_t e) { return e == hipSuccess ? DVC_OK : DVC_EHIP; }
+
+// LN[k] = float(log(double(k))): the natural-log table of the UCT score, built
+// on the host once and kept on every device that runs a search.  Tables that
+// are outgrown stay allocated (a search still running may read them).
+static std::mutex g_ln_mutex;
+static std::vector<float> g_ln_host;
+static float *g_ln_dev[64] = {nullptr};
+static uint64_t g_ln_size[64] = {0};
+
+static const float *ln_table(uint64_t need, int *status)
+{
+    std::lock_guard<std::mutex> lock(g_ln_mutex);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+        *status = DVC_EHIP;
+        return nullptr;
+    }
+    if (g_ln_size[dev] >= need) return g_ln_dev[dev];
+    uint64_t cap = 1ull << 20;
+    while (cap < need) cap <<= 1;
+    if (g_ln_host.size() < cap) {
+        const uint64_t old = g_ln_host.size();
+        g_ln_host.resize(cap);
+        for (uint64_t k = old; k < cap; ++k)
+            g_ln_host[k] = k == 0 ? 0.0f : (float)std::log((double)k);
+    }
+    float *p = nullptr;
+    if (hipMalloc(&p, cap * sizeof(float)) != hipSuccess) {
+        *status = DVC_ENOMEM;
+        return nullptr;
+    }
+    if (hipMemcpy(p, g_ln_host.data(), cap * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
+        *status = DVC_EHIP;
+        return nullptr;
+    }
+    g_ln_dev[dev] = p;
+    g_ln_size[dev] = cap;
+    return p;
+}
+
+static bool mcts_params_ok(const dvc_mcts_params *p)
+{
+    if (p == nullptr) return false;
+    if (p->iterations < 1 || p->playouts_per_leaf < 1 || p->max_depth < 1 || p->max_depth > 16)
+        return false;
+    if (!(p->c_uct >= 0.0f) || std::isinf(p->c_uct)) return false;
+    // visit counts stay exact in float
+    if ((uint64_t)p->iterations * (uint64_t)p->playouts_per_leaf >= (1ull << 24)) return false;
+    if (p->leaf_eval != 0) return false;
+    return true;
+}
 
 }  // namespace dvc
 
@@ -106,7 +159,7 @@ int dvc_rollout_ex(const dvc_state_t *leaves, int64_t n_leaves, int32_t ppl, uin
 {
     if (n_leaves < 0 || ppl < 1 || (n_leaves > 0 && leaves == nullptr)) return DVC_EINVAL;
     if ((uint64_t)n_leaves * (uint64_t)ppl >= (1ull << 32)) return DVC_EINVAL;
-    if (variant < 0 || variant > 3) return DVC_EINVAL;
+    if (variant < 0 || variant > 4) return DVC_EINVAL;
     if (block != 0 && block != 64 && block != 128 && block != 256 && block != 512) return DVC_EINVAL;
     if (grid < 0) return DVC_EINVAL;
     hipStream_t st = (hipStream_t)stream;
@@ -153,19 +206,29 @@ int dvc_rollout(const dvc_state_t *leaves, int64_t n_leaves, int32_t ppl, uint64
 
 size_t dvc_mcts_workspace_bytes(int64_t n_trees, const dvc_mcts_params *params)
 {
-    (void)n_trees;
-    (void)params;
-    return 0;
+    if (n_trees < 0 || !mcts_params_ok(params)) return 0;
+    return (size_t)n_trees * mcts_tree_words((uint32_t)params->iterations) * sizeof(uint32_t);
 }
 
 int mcts_search(const dvc_state_t *roots, int64_t n_trees, const dvc_mcts_params *params,
                 uint64_t seed, uint32_t tree_id_base, void *workspace, size_t workspace_bytes,
                 int32_t *best_action, dvc_child_stat *root_children, void *stream)
 {
-    // the GPU tree search is not built yet
-    (void)roots; (void)n_trees; (void)params; (void)seed; (void)tree_id_base; (void)workspace;
-    (void)workspace_bytes; (void)best_action; (void)root_children; (void)stream;
-    return DVC_EINVAL;
+    if (n_trees < 0 || n_trees >= (1ll << 31) || !mcts_params_ok(params)) return DVC_EINVAL;
+    if (n_trees == 0) return DVC_OK;
+    if (roots == nullptr || best_action == nullptr || workspace == nullptr) return DVC_EINVAL;
+    if (workspace_bytes < dvc_mcts_workspace_bytes(n_trees, params)) return DVC_ENOMEM;
+    int status = DVC_OK;
+    const uint64_t need = (uint64_t)params->iterations * (uint64_t)params->playouts_per_leaf + 1u;
+    const float *ln = ln_table(need, &status);
+    if (ln == nullptr) return status;
+    return status_of(launch_mcts(reinterpret_cast<const uint4 *>(roots), (uint32_t)n_trees,
+                                 (uint32_t)params->iterations, (uint32_t)params->playouts_per_leaf,
+                                 (uint32_t)params->max_depth, params->c_uct, (uint32_t)seed,
+                                 (uint32_t)(seed >> 32), tree_id_base, ln,
+                                 reinterpret_cast<uint32_t *>(workspace), best_action,
+                                 reinterpret_cast<uint32_t *>(root_children),
+                                 (hipStream_t)stream));
 }
 
 }  // extern "C"

@@ -13,6 +13,7 @@ constexpr uint32_t kErrState = 1u;   // a malformed state was read
 constexpr uint32_t kErrLimit = 2u;   // a kernel reached an internal bound
 constexpr int kQueueSlots = 1024;    // independent work-queue counter pairs
 constexpr uint32_t kStageLeaves = 64;  // leaf states staged per wave
+constexpr uint32_t kMaxActions = 864;  // ((P-1)*24 slots) * 12 values, P <= 4
 
 // Sticky error word of the device, or-ed by kernels, read and cleared by
 // dvc_check().
@@ -47,6 +48,11 @@ struct DealArgs {
 int default_rollout_grid(int waves_per_block);
 hipError_t launch_rollout(const RolloutArgs &a, int variant, int block, int grid, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st);
+size_t mcts_tree_words(uint32_t iters);
+hipError_t launch_mcts(const uint4 *roots, uint32_t n_trees, uint32_t iters, uint32_t ppl,
+                       uint32_t dmax, float c_uct, uint32_t k0, uint32_t k1, uint32_t tree_base,
+                       const float *ln, uint32_t *ws, int32_t *best, uint32_t *kids,
+                       hipStream_t st);
 hipError_t launch_init_states(uint4 *out, uint32_t n, const DealArgs &d, uint32_t k0, uint32_t k1,
                               uint32_t index_base, hipStream_t st);
 

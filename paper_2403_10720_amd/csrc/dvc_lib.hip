@@ -3,4 +3,5 @@
 // by every kernel without relocatable device code.
 #include "rollout.hip"
 #include "gen.hip"
+#include "search.hip"
 #include "capi.hip"

@@ -453,6 +453,114 @@ __global__ void __launch_bounds__(WAVES * 64) rollout_items(RolloutArgs a)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Variant 4: K playouts per lane, back to back.
+//
+// Lane g runs playout ids g, g + S, ..., g + (K-1)S (S = lanes in the grid).
+// When its game ends it starts the next one at once instead of waiting for
+// the rest of the wave; the next leaf state is loaded while the current game
+// runs, and outcomes stay packed in a register (7 bits per game) until the
+// lane's last game, so the loop issues no stores and its only memory waits
+// are for loads issued a game earlier.  Seat wins are summed across the wave
+// with ballots at the end.  Meant for launches with a few playouts per lane
+// at full occupancy; outputs equal every other variant's.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kOutError = 0x7Fu;     // packed outcome of a malformed leaf
+
+template <int K>
+__global__ void __launch_bounds__(256) rollout_static(RolloutArgs a)
+{
+    __shared__ uint8_t tab[kKthTableBytes];
+    fill_kth_table(tab);
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t S = gridDim.x * blockDim.x;
+    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t trk1 = a.tree ^ a.k1;
+
+    uint32_t k = 0, j = g, leaf = 0, len = 0, winner = 0, packed = 0u;
+    bool over = true, valid = false;
+    State s;
+    s.h0 = s.h1 = s.h2 = s.h3 = s.rev = 0u;
+    s.m = 0u; s.P = 2u; s.phase = 1u; s.drawn = -1;
+    PlayoutKey pk = {0u, 0u, 0u, 0u};
+    uint4 next_st = make_uint4(0u, 0u, 0u, 0u);
+    if (j < a.total) next_st = a.leaves[j / a.ppl];
+    bool need_start = j < a.total;
+
+    for (;;) {
+        // start the lane's next game from the prefetched state
+        if (need_start) {
+            leaf = j / a.ppl;
+            const uint32_t p = j - leaf * a.ppl;
+            valid = decode(next_st.x, next_st.y, next_st.z, next_st.w, s);
+            pk = playout_key(p, a.leaf_base + leaf, a.k0);
+            len = 0u;
+            const uint32_t alive = alive_mask(s);
+            winner = (uint32_t)__builtin_ctz(alive | 16u);
+            over = !valid || __popc(alive) == 1;
+            if (!valid) atomicOr(&g_error_word, kErrState);
+            const uint32_t jn = j + S;
+            if (k + 1u < (uint32_t)K && jn < a.total) next_st = a.leaves[jn / a.ppl];
+            need_start = false;
+        }
+        const bool live = k < (uint32_t)K && j < a.total;
+        if (__ballot(live) == 0ull) break;
+        if (live && !over) {
+            const Words w = step_words(pk, trk1, a.k0, a.k1);
+            over = guess_step(s, w, winner, tab);
+            next_step(pk);
+            ++len;
+            if (!over && len >= kMaxGuesses) {
+                atomicOr(&g_error_word, kErrLimit);
+                over = true;
+                winner = 4u;
+            }
+        }
+        if (live && over) {
+            const uint32_t code = (!valid || winner > 3u) ? kOutError : (winner | (len << 2));
+            packed |= code << (7u * k);
+            ++k;
+            j += S;
+            need_start = k < (uint32_t)K && j < a.total;
+        }
+    }
+
+    // outputs, and seat wins summed per leaf across the wave
+#pragma unroll
+    for (uint32_t kk = 0; kk < (uint32_t)K; ++kk) {
+        const uint32_t jj = g + kk * S;
+        const bool has = jj < a.total;
+        const uint32_t code = (packed >> (7u * kk)) & 0x7Fu;
+        const bool err = code == kOutError;
+        const uint32_t w = code & 3u;
+        if (has) {
+            if (a.winner) a.winner[jj] = err ? (int8_t)-1 : (int8_t)w;
+            if (a.length) a.length[jj] = err ? (int16_t)-1 : (int16_t)(code >> 2);
+        }
+        if (a.seat_wins) {
+            const uint32_t lf = has ? jj / a.ppl : 0u;
+            const bool fin = has && !err;
+            uint64_t fmask = __ballot(fin);
+            while (fmask != 0ull) {
+                const uint32_t first = (uint32_t)__builtin_ctzll(fmask);
+                const uint32_t L = __builtin_amdgcn_readlane(lf, first);
+                const bool mineL = fin && lf == L;
+                const uint64_t same = __ballot(mineL);
+                const uint32_t c0 = (uint32_t)__popcll(__ballot(mineL && w == 0u));
+                const uint32_t c1 = (uint32_t)__popcll(__ballot(mineL && w == 1u));
+                const uint32_t c2 = (uint32_t)__popcll(__ballot(mineL && w == 2u));
+                const uint32_t c3 = (uint32_t)__popcll(__ballot(mineL && w == 3u));
+                if (lane < 4u) {
+                    const uint32_t c = lane == 0u ? c0 : lane == 1u ? c1 : lane == 2u ? c2 : c3;
+                    if (c) atomicAdd(&a.seat_wins[(size_t)L * 4u + lane], c);
+                }
+                fmask &= ~same;
+            }
+        }
+    }
+}
+
 __global__ void fill_u32(uint32_t *p, uint64_t n, uint32_t v)
 {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -477,6 +585,21 @@ hipError_t launch_rollout(const RolloutArgs &a, int variant, int block, int grid
     if (variant == 1) {
         const uint32_t blocks = (a.total + 255u) / 256u;
         hipLaunchKernelGGL(rollout_lane_per_playout, dim3(blocks), dim3(256), 0, st, a);
+        return hipGetLastError();
+    }
+    if (variant == 4) {
+        // playouts per lane: enough lanes for eight waves per SIMD, at most 4
+        const uint64_t lanes8 = (uint64_t)default_rollout_grid(1) * 4u * 64u;
+        int kk = grid > 0 ? grid : (int)((a.total + lanes8 - 1) / lanes8);
+        kk = kk < 1 ? 1 : (kk > 4 ? 4 : kk);
+        if (kk == 3) kk = 4;
+        const uint32_t per_block = 256u * (uint32_t)kk;
+        const uint32_t blocks = (uint32_t)((a.total + per_block - 1u) / per_block);
+        switch (kk) {
+        case 1: hipLaunchKernelGGL(rollout_static<1>, dim3(blocks), dim3(256), 0, st, a); break;
+        case 2: hipLaunchKernelGGL(rollout_static<2>, dim3(blocks), dim3(256), 0, st, a); break;
+        default: hipLaunchKernelGGL(rollout_static<4>, dim3(blocks), dim3(256), 0, st, a); break;
+        }
         return hipGetLastError();
     }
     int waves = block > 0 ? block / 64 : 4;

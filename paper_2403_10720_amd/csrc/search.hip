@@ -1,0 +1,600 @@
+// search.hip -- Monte Carlo Tree Search for the Da Vinci Code game on gfx950.
+//
+// Sec. II-B of Zhang et al. (arXiv 2403.10720): selection, expansion,
+// simulation (random playouts) and back-propagation; Sec. III-A: a node is a
+// guess (tile position, guessed number), guessing stops after a right guess
+// inside the tree, and nodes at a fixed depth threshold are not expanded.
+// The opponents' tiles are a black box, so each iteration first samples a
+// plausible set of numbers for them.
+//
+// One wavefront owns one tree for the whole search (a persistent loop over
+// the iterations; trees are independent, so no grid-wide synchronisation):
+//   * the sampler runs 64 attempts at once, one per lane, and the lowest
+//     successful attempt wins;
+//   * at every tree level the lanes compute the legal value mask of 64 of
+//     the 72 (target, slot) pairs at once, find the lowest untried action
+//     with a ballot, or score 64 children per pass with FP32 UCT and reduce
+//     with a wavefront arg-max (ties to the earliest child);
+//   * the leaf's playouts run one per lane, seat wins are summed by ballots;
+//   * back-propagation updates the path nodes from their own lanes.
+// Tree storage lives in the caller's workspace: a node table (child list
+// head/tail, child count, a bitmap of the actions that already have a child)
+// and blocks of 64 child entries {action | chooser << 16, N, W, node id}, so a
+// node's children are scored 64 at a time with coalesced loads.
+#include "dvc_core.hpp"
+#include "dvc_internal.hpp"
+
+namespace dvc {
+
+constexpr uint32_t kNodeWords = 40;      // first block, last block, nchild, pad, 36 bitmap words
+constexpr uint32_t kBlockEntries = 64;
+constexpr uint32_t kEntryWords = 4;
+constexpr uint32_t kBlockWords = kBlockEntries * kEntryWords;
+constexpr uint32_t kTreeHeaderWords = 16;
+constexpr uint32_t kNoBlock = 0xFFFFFFFFu;
+constexpr uint32_t kDetAttempts = 64;
+constexpr uint32_t kDfsMaxCalls = 1u << 22;
+constexpr uint32_t kMaxDepthLimit = 16;
+
+__device__ __forceinline__ void set_hand(State &s, uint32_t q, uint32_t v)
+{
+    s.h0 = q == 0u ? v : s.h0;
+    s.h1 = q == 1u ? v : s.h1;
+    s.h2 = q == 2u ? v : s.h2;
+    s.h3 = q == 3u ? v : s.h3;
+}
+
+// bits strictly above `lo` (lo may be -1)
+__device__ __forceinline__ uint32_t above_bits(int32_t lo)
+{
+    return lo < 0 ? 0xFFFFFFFFu : ~((2u << (uint32_t)lo) - 1u);
+}
+
+// bits strictly below `hi` (hi <= 24)
+__device__ __forceinline__ uint32_t below_bits(uint32_t hi) { return (1u << hi) - 1u; }
+
+__device__ __forceinline__ uint32_t colour_mask(uint32_t t) { return (t & 1u) ? kWhite : kBlack; }
+
+// Sequential word stream: word n of block (n>>2, c1, c2, c3).
+struct SeqWords {
+    uint32_t k0, k1, c1, c2, c3, n;
+    Words blk;
+    __device__ uint32_t next()
+    {
+        const uint32_t slot = n & 3u;
+        if (slot == 0u) blk = philox(n >> 2, c1, c2, c3, k0, k1);
+        ++n;
+        return slot == 0u ? blk.w0 : slot == 1u ? blk.w1 : slot == 2u ? blk.w2 : blk.w3;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Sampling a world the searching player cannot tell from the real one.
+// Per opponent (seat order from the mover's left), per run of hidden slots
+// between revealed tiles (lo, hi): right to left the largest value each slot
+// may take (largest available tile of its colour below the next bound), then
+// left to right a uniform value in (previous, bound].  Available: not in the
+// mover's row, not revealed, not yet used.  Returns false if a run cannot be
+// filled.
+// ---------------------------------------------------------------------------
+__device__ bool det_attempt(const State &R, uint32_t attempt, uint32_t iter, uint32_t tr,
+                            uint32_t k0, uint32_t k1, State &out, const uint8_t *tab)
+{
+    SeqWords ws{k0, k1, 0x80000000u + attempt, iter, tr, 0u, Words{0u, 0u, 0u, 0u}};
+    uint32_t avail = ~(hand_of(R, R.m) | R.rev) & kAll;
+    out = R;
+    for (uint32_t k = 1; k < 4u; ++k) {
+        if (k >= R.P) break;
+        const uint32_t o = R.m + k >= R.P ? R.m + k - R.P : R.m + k;
+        const uint32_t row = hand_of(R, o);
+        const uint32_t revrow = row & R.rev;
+        uint32_t rem = row & ~R.rev;
+        uint32_t newrow = revrow;
+        while (rem) {
+            const uint32_t t0 = (uint32_t)__builtin_ctz(rem);
+            const uint32_t below = revrow & ((1u << t0) - 1u);
+            const uint32_t above = revrow & ~((2u << t0) - 1u);
+            const int32_t lo = below ? 31 - __builtin_clz(below) : -1;
+            const uint32_t hi = above ? (uint32_t)__builtin_ctz(above) : 24u;
+            const uint32_t seg = rem & above_bits(lo) & below_bits(hi);
+            rem &= ~seg;
+            // right to left: bounds
+            uint32_t bounds = 0u, cur = hi, x = seg;
+            while (x) {
+                const uint32_t tj = 31u - (uint32_t)__builtin_clz(x);
+                x &= ~(1u << tj);
+                const uint32_t cand = avail & colour_mask(tj) & below_bits(cur);
+                if (!cand) return false;
+                cur = 31u - (uint32_t)__builtin_clz(cand);
+                bounds |= 1u << cur;
+            }
+            if ((int32_t)cur <= lo) return false;
+            // left to right: values
+            int32_t prev = lo;
+            x = seg;
+            uint32_t bb = bounds;
+            while (x) {
+                const uint32_t tj = (uint32_t)__builtin_ctz(x);
+                x &= x - 1u;
+                const uint32_t uj = (uint32_t)__builtin_ctz(bb);
+                bb &= bb - 1u;
+                const uint32_t cand = avail & colour_mask(tj) & above_bits(prev) & below_bits(uj + 1u);
+                const uint32_t v = kth_bit_tab(cand, pick(ws.next(), (uint32_t)__popc(cand)), tab);
+                avail &= ~(1u << v);
+                newrow |= 1u << v;
+                prev = (int32_t)v;
+            }
+        }
+        set_hand(out, o, newrow);
+    }
+    return true;
+}
+
+// Deterministic fallback: the lexicographically smallest consistent world
+// (slots ordered by opponent from the mover's left, then left to right),
+// by depth-first search trying the lowest tile first.  Gives up (false)
+// after kDfsMaxCalls search calls.
+__device__ bool det_fallback(const State &R, State &out)
+{
+    uint8_t so[24], scol[24], shi[24], sseg[24];
+    int8_t slo[24], assign[24], tried[24];
+    uint32_t ns = 0;
+    for (uint32_t k = 1; k < 4u; ++k) {
+        if (k >= R.P) break;
+        const uint32_t o = R.m + k >= R.P ? R.m + k - R.P : R.m + k;
+        const uint32_t row = hand_of(R, o);
+        const uint32_t revrow = row & R.rev;
+        uint32_t rem = row & ~R.rev;
+        bool first = true;
+        int32_t last_lo = -2;
+        while (rem) {
+            const uint32_t t0 = (uint32_t)__builtin_ctz(rem);
+            rem &= rem - 1u;
+            const uint32_t below = revrow & ((1u << t0) - 1u);
+            const uint32_t above = revrow & ~((2u << t0) - 1u);
+            const int32_t lo = below ? 31 - __builtin_clz(below) : -1;
+            so[ns] = (uint8_t)o;
+            scol[ns] = (uint8_t)(t0 & 1u);
+            slo[ns] = (int8_t)lo;
+            shi[ns] = (uint8_t)(above ? (uint32_t)__builtin_ctz(above) : 24u);
+            sseg[ns] = (uint8_t)(first || lo != last_lo);
+            first = false;
+            last_lo = lo;
+            ++ns;
+        }
+    }
+    uint32_t avail = ~(hand_of(R, R.m) | R.rev) & kAll;
+    int32_t k = 0;
+    uint32_t calls = 1;
+    if (ns > 0) tried[0] = -1;
+    while (k < (int32_t)ns) {
+        const int32_t prev = sseg[k] ? slo[k] : assign[k - 1];
+        const int32_t from = tried[k] < 0 ? prev + 1 : tried[k] + 1;
+        const uint32_t cand = avail & (scol[k] ? kWhite : kBlack) & below_bits(shi[k]) &
+                              ~((1u << (uint32_t)from) - 1u);
+        if (cand) {
+            const uint32_t x = (uint32_t)__builtin_ctz(cand);
+            tried[k] = (int8_t)x;
+            assign[k] = (int8_t)x;
+            avail &= ~(1u << x);
+            ++k;
+            if (++calls > kDfsMaxCalls) return false;
+            if (k < (int32_t)ns) tried[k] = -1;
+        } else {
+            tried[k] = -1;
+            --k;
+            if (k < 0) return false;
+            avail |= 1u << (uint32_t)assign[k];
+        }
+    }
+    out = R;
+    uint32_t rows[4] = {R.h0 & R.rev, R.h1 & R.rev, R.h2 & R.rev, R.h3 & R.rev};
+    for (uint32_t j = 0; j < ns; ++j) rows[so[j]] |= 1u << (uint32_t)assign[j];
+    for (uint32_t k2 = 1; k2 < 4u; ++k2) {
+        if (k2 >= R.P) break;
+        const uint32_t o = R.m + k2 >= R.P ? R.m + k2 - R.P : R.m + k2;
+        set_hand(out, o, rows[o]);
+    }
+    return true;
+}
+
+// Legal guessed values (12-bit mask over v) of pair k = (r-1)*24 + s for the
+// mover of S: target seat (m + r) mod P still in, slot s exists and is
+// hidden, value 2v + colour is a consistent candidate.
+__device__ __forceinline__ uint32_t legal_values(const State &S, uint32_t k, const uint8_t *tab)
+{
+    const uint32_t r = k / 24u + 1u, slot = k - (k / 24u) * 24u;
+    if (r >= S.P) return 0u;
+    const uint32_t q = S.m + r >= S.P ? S.m + r - S.P : S.m + r;
+    const uint32_t row = hand_of(S, q);
+    if ((row & ~S.rev) == 0u || slot >= (uint32_t)__popc(row)) return 0u;
+    const uint32_t t = kth_bit_tab(row, slot, tab);
+    if ((S.rev >> t) & 1u) return 0u;
+    uint32_t x = candidates(t, row, hand_of(S, S.m), S.rev) >> (t & 1u);
+    x &= 0x555555u;
+    x = (x | (x >> 1)) & 0x333333u;
+    x = (x | (x >> 2)) & 0x0F0F0Fu;
+    x = (x | (x >> 4)) & 0x00FF00FFu;
+    x = (x | (x >> 8)) & 0x0000FFFFu;
+    return x & 0xFFFu;
+}
+
+// Play a guess inside the tree (the turn ends after it); chance words come
+// from block (depth, 0xC0000000, iter, tree).  Returns true if the game ended.
+__device__ __forceinline__ bool apply_action(State &S, uint32_t action, uint32_t depth,
+                                             uint32_t iter, uint32_t tr, uint32_t k0, uint32_t k1,
+                                             uint32_t &winner, const uint8_t *tab)
+{
+    const Words w = philox(depth, 0xC0000000u, iter, tr, k0, k1);
+    const uint32_t r = action / 288u + 1u;
+    const uint32_t slot = (action / 12u) % 24u;
+    const uint32_t v = action % 12u;
+    const uint32_t q = S.m + r >= S.P ? S.m + r - S.P : S.m + r;
+    const uint32_t row = hand_of(S, q);
+    const uint32_t t = kth_bit_tab(row, slot, tab);
+    const uint32_t guess = 2u * v + (t & 1u);
+    const uint32_t hm = hand_of(S, S.m);
+    const uint32_t own = pick_bit_tab(hm & ~S.rev, w.w0, tab);
+    const uint32_t wrong_bit = 1u << (S.drawn >= 0 ? (uint32_t)S.drawn : own);
+    S.rev |= guess == t ? (1u << t) : wrong_bit;
+    const uint32_t alive = alive_mask(S);
+    S.phase = 1u;
+    S.drawn = -1;
+    if (__popc(alive) == 1) {
+        winner = (uint32_t)__builtin_ctz(alive);
+        return true;
+    }
+    S.m = next_alive(alive, S.m, S.P);
+    const uint32_t pool = ~(S.h0 | S.h1 | S.h2 | S.h3) & kAll;
+    if (pool) {
+        const uint32_t d = pick_bit_tab(pool, w.w1, tab);
+        add_to_hand(S, S.m, 1u << d);
+        S.drawn = (int32_t)d;
+    }
+    return false;
+}
+
+__device__ __forceinline__ State readlane_state(const State &s, uint32_t lane)
+{
+    State r;
+    r.h0 = __builtin_amdgcn_readlane(s.h0, lane);
+    r.h1 = __builtin_amdgcn_readlane(s.h1, lane);
+    r.h2 = __builtin_amdgcn_readlane(s.h2, lane);
+    r.h3 = __builtin_amdgcn_readlane(s.h3, lane);
+    r.rev = __builtin_amdgcn_readlane(s.rev, lane);
+    r.m = __builtin_amdgcn_readlane(s.m, lane);
+    r.P = __builtin_amdgcn_readlane(s.P, lane);
+    r.phase = __builtin_amdgcn_readlane(s.phase, lane);
+    r.drawn = __builtin_amdgcn_readlane(s.drawn, lane);
+    return r;
+}
+
+// wavefront arg-max: greatest score, lowest index on ties
+__device__ __forceinline__ void wave_argmax(float &s, uint32_t &idx)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const float os = __shfl_xor(s, off, 64);
+        const uint32_t oi = __shfl_xor(idx, off, 64);
+        const bool take = os > s || (os == s && oi < idx);
+        s = take ? os : s;
+        idx = take ? oi : idx;
+    }
+}
+
+__device__ __forceinline__ void wave_argmax_u(uint32_t &n, uint32_t &idx)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const uint32_t on = __shfl_xor(n, off, 64);
+        const uint32_t oi = __shfl_xor(idx, off, 64);
+        const bool take = on > n || (on == n && oi < idx);
+        n = take ? on : n;
+        idx = take ? oi : idx;
+    }
+}
+
+struct MctsArgs {
+    const uint4 *roots;
+    uint32_t n_trees, iters, ppl, dmax;
+    float c_uct;
+    uint32_t k0, k1, tree_base;
+    const float *ln;
+    uint32_t *ws;
+    uint64_t tree_words;
+    uint32_t nodes_cap, blocks_cap;
+    int32_t *best;
+    uint32_t *kids;   // [n_trees][864][3] or null
+};
+
+__device__ __forceinline__ void write_no_children(const MctsArgs &a, uint32_t t, uint32_t lane)
+{
+    if (!a.kids) return;
+    uint32_t *k = a.kids + (size_t)t * kMaxActions * 3u;
+    for (uint32_t c = lane; c < kMaxActions; c += 64u) {
+        k[c * 3u + 0u] = 0xFFFFu;
+        k[c * 3u + 1u] = 0u;
+        k[c * 3u + 2u] = 0u;
+    }
+}
+
+__global__ void __launch_bounds__(64) mcts_tree_kernel(MctsArgs a)
+{
+    __shared__ uint8_t tab[kKthTableBytes];
+    __shared__ uint32_t legal_s[72];
+    __shared__ uint32_t path_e[kMaxDepthLimit + 1];
+    fill_kth_table(tab);
+    __syncthreads();
+    const uint32_t t = blockIdx.x;
+    const uint32_t lane = threadIdx.x;
+    const uint32_t tr = a.tree_base + t;
+    uint32_t *W = a.ws + (uint64_t)t * a.tree_words;
+    uint32_t *nodes = W + kTreeHeaderWords;
+    uint32_t *blocks = nodes + (uint64_t)a.nodes_cap * kNodeWords;
+    uint32_t *bnext = blocks + (uint64_t)a.blocks_cap * kBlockWords;
+
+    const uint4 rs = a.roots[t];
+    State R;
+    const bool ok = decode(rs.x, rs.y, rs.z, rs.w, R);
+    const uint32_t pool0 = ~(R.h0 | R.h1 | R.h2 | R.h3) & kAll;
+    if (!ok || __popc(alive_mask(R)) < 2 || (R.phase == 0u && pool0 != 0u)) {
+        if (lane == 0) {
+            atomicOr(&g_error_word, kErrState);
+            a.best[t] = -1;
+        }
+        write_no_children(a, t, lane);
+        return;
+    }
+    if (lane < kNodeWords) nodes[lane] = lane < 2u ? kNoBlock : 0u;
+    uint32_t n_nodes = 1u, n_blocks = 0u, n_root = 0u;
+    bool failed = false;
+    __syncthreads();
+
+    for (uint32_t it = 0; it < a.iters && !failed; ++it) {
+        // ---- 1. sample a world: attempt `lane`, lowest success wins ------
+        State S;
+        const bool got = det_attempt(R, lane, it, tr, a.k0, a.k1, S, tab);
+        const uint64_t okm = __ballot(got);
+        if (okm) {
+            S = readlane_state(S, (uint32_t)__builtin_ctzll(okm));
+        } else {
+            State F = R;
+            bool fok = false;
+            if (lane == 0) fok = det_fallback(R, F);
+            fok = __builtin_amdgcn_readfirstlane((uint32_t)fok) != 0u;
+            if (!fok) {
+                if (lane == 0) atomicOr(&g_error_word, kErrLimit);
+                failed = true;
+                break;
+            }
+            S = readlane_state(F, 0u);
+        }
+
+        // ---- 2. descend ----------------------------------------------------
+        uint32_t node = 0u, node_n = n_root, depth = 0u, np = 0u, winner = 0u;
+        bool term = false;
+        for (;;) {
+            if (term || depth >= a.dmax) break;
+            const uint32_t l0 = legal_values(S, lane, tab);
+            const uint32_t l1 = lane < 8u ? legal_values(S, 64u + lane, tab) : 0u;
+            legal_s[lane] = l0;
+            if (lane < 8u) legal_s[64u + lane] = l1;
+            const uint32_t *nd = nodes + (uint64_t)node * kNodeWords;
+            const uint32_t cb0 = (nd[4u + (lane >> 1)] >> ((lane & 1u) * 16u)) & 0xFFFu;
+            const uint32_t cb1 = lane < 8u ? (nd[4u + ((64u + lane) >> 1)] >> ((lane & 1u) * 16u)) & 0xFFFu : 0u;
+            const uint32_t u0 = l0 & ~cb0, u1 = l1 & ~cb1;
+            const uint64_t b0 = __ballot(u0 != 0u), b1 = __ballot(u1 != 0u);
+            __syncthreads();
+            if (b0 | b1) {
+                // expansion: the lowest legal action that has no child yet
+                uint32_t pair, vbits;
+                if (b0) {
+                    pair = (uint32_t)__builtin_ctzll(b0);
+                    vbits = __builtin_amdgcn_readlane(u0, pair);
+                } else {
+                    const uint32_t l = (uint32_t)__builtin_ctzll(b1);
+                    vbits = __builtin_amdgcn_readlane(u1, l);
+                    pair = 64u + l;
+                }
+                const uint32_t action = pair * 12u + (uint32_t)__builtin_ctz(vbits);
+                const uint32_t c = n_nodes++;
+                const uint32_t slot = nd[2];
+                uint32_t blk;
+                if ((slot & (kBlockEntries - 1u)) == 0u) {
+                    blk = n_blocks++;
+                    if (lane == 0) {
+                        bnext[blk] = kNoBlock;
+                        uint32_t *ndw = nodes + (uint64_t)node * kNodeWords;
+                        if (slot == 0u) ndw[0] = blk;
+                        else bnext[nd[1]] = blk;
+                        ndw[1] = blk;
+                    }
+                } else {
+                    blk = nd[1];
+                }
+                const uint32_t e = blk * kBlockWords + (slot & (kBlockEntries - 1u)) * kEntryWords;
+                if (lane == 0) {
+                    uint32_t *ndw = nodes + (uint64_t)node * kNodeWords;
+                    blocks[e + 0u] = action | (S.m << 16);
+                    blocks[e + 1u] = 0u;
+                    blocks[e + 2u] = 0u;
+                    blocks[e + 3u] = c;
+                    ndw[2] = slot + 1u;
+                    ndw[4u + (pair >> 1)] |= 1u << ((action % 12u) + (pair & 1u) * 16u);
+                }
+                if (lane < kNodeWords) nodes[(uint64_t)c * kNodeWords + lane] = lane < 2u ? kNoBlock : 0u;
+                path_e[np++] = e;
+                term = apply_action(S, action, depth, it, tr, a.k0, a.k1, winner, tab);
+                __syncthreads();
+                break;
+            }
+            // selection: UCT over the legal children, 64 per pass
+            const uint32_t nchild = nd[2];
+            const float lp = a.ln[node_n];
+            float best_s = -__builtin_inff();
+            uint32_t best_i = 0xFFFFFFFFu, best_e = 0u;
+            uint32_t blk = nd[0];
+            for (uint32_t base = 0; base < nchild; base += kBlockEntries) {
+                const uint32_t ci = base + lane;
+                const uint32_t e = blk * kBlockWords + lane * kEntryWords;
+                float sc = -__builtin_inff();
+                uint32_t idx = 0xFFFFFFFFu;
+                if (ci < nchild) {
+                    const uint32_t act = blocks[e] & 0xFFFFu;
+                    const uint32_t pr = act / 12u;
+                    if ((legal_s[pr] >> (act - pr * 12u)) & 1u) {
+                        const float n = (float)blocks[e + 1u];
+                        const float q = __uint_as_float(blocks[e + 2u]) / n;
+                        const float ex = lp / n;
+                        const float u = a.c_uct * sqrtf(ex);
+                        sc = q + u;
+                        idx = ci;
+                    }
+                }
+                wave_argmax(sc, idx);
+                if (idx != 0xFFFFFFFFu && (best_i == 0xFFFFFFFFu || sc > best_s)) {
+                    best_s = sc;
+                    best_i = idx;
+                    best_e = blk * kBlockWords + (idx - base) * kEntryWords;
+                }
+                if (base + kBlockEntries < nchild) blk = bnext[blk];
+            }
+            const uint32_t action = blocks[best_e] & 0xFFFFu;
+            node = blocks[best_e + 3u];
+            node_n = blocks[best_e + 1u];
+            path_e[np++] = best_e;
+            term = apply_action(S, action, depth, it, tr, a.k0, a.k1, winner, tab);
+            ++depth;
+            __syncthreads();
+        }
+
+        // ---- 3. playouts from the leaf -------------------------------------
+        uint32_t wins0 = 0u, wins1 = 0u, wins2 = 0u, wins3 = 0u;
+        if (term) {
+            wins0 = winner == 0u ? a.ppl : 0u;
+            wins1 = winner == 1u ? a.ppl : 0u;
+            wins2 = winner == 2u ? a.ppl : 0u;
+            wins3 = winner == 3u ? a.ppl : 0u;
+        } else {
+            const uint64_t pl = (uint64_t)it * kPhiloxM1;
+            const uint32_t trk1 = tr ^ a.k1;
+            for (uint32_t pb = 0; pb < a.ppl; pb += 64u) {
+                const uint32_t p = pb + lane;
+                const bool act = p < a.ppl;
+                uint32_t w = 4u;
+                if (act) {
+                    State s = S;
+                    PlayoutKey pk;
+                    pk.a = (uint32_t)(pl >> 32) ^ p ^ a.k0;
+                    pk.b = (uint32_t)pl;
+                    pk.gm_lo = 0u;
+                    pk.gm_hi = 0u;
+                    bool over = false;
+                    uint32_t len = 0u;
+                    while (!over) {
+                        const Words wd = step_words(pk, trk1, a.k0, a.k1);
+                        over = guess_step(s, wd, w, tab);
+                        next_step(pk);
+                        if (++len >= kMaxGuesses && !over) {
+                            atomicOr(&g_error_word, kErrLimit);
+                            over = true;
+                            w = 4u;
+                        }
+                    }
+                }
+                wins0 += (uint32_t)__popcll(__ballot(act && w == 0u));
+                wins1 += (uint32_t)__popcll(__ballot(act && w == 1u));
+                wins2 += (uint32_t)__popcll(__ballot(act && w == 2u));
+                wins3 += (uint32_t)__popcll(__ballot(act && w == 3u));
+            }
+        }
+
+        // ---- 4. back-propagation --------------------------------------------
+        n_root += a.ppl;
+        if (lane < np) {
+            const uint32_t e = path_e[lane];
+            const uint32_t chooser = blocks[e] >> 16;
+            const uint32_t wc = chooser == 0u ? wins0 : chooser == 1u ? wins1 : chooser == 2u ? wins2 : wins3;
+            blocks[e + 1u] += a.ppl;
+            blocks[e + 2u] = __float_as_uint(__uint_as_float(blocks[e + 2u]) + (float)wc);
+        }
+        __syncthreads();
+    }
+
+    // ---- decision and root statistics ----------------------------------------
+    if (lane == 0) {
+        W[0] = n_nodes;
+        W[1] = n_blocks;
+        W[2] = n_root;
+    }
+    if (failed) {
+        if (lane == 0) a.best[t] = -1;
+        write_no_children(a, t, lane);
+        return;
+    }
+    const uint32_t nchild = nodes[2];
+    uint32_t blk = nodes[0];
+    uint32_t best_n = 0u, best_i = 0xFFFFFFFFu, best_act = 0xFFFFu;
+    uint32_t *kid = a.kids ? a.kids + (size_t)t * kMaxActions * 3u : nullptr;
+    for (uint32_t base = 0; base < kMaxActions; base += kBlockEntries) {
+        const uint32_t ci = base + lane;
+        uint32_t act = 0xFFFFu, n = 0u, wbits = 0u;
+        if (base < nchild && ci < nchild) {
+            const uint32_t e = blk * kBlockWords + lane * kEntryWords;
+            act = blocks[e] & 0xFFFFu;
+            n = blocks[e + 1u];
+            wbits = blocks[e + 2u];
+        }
+        if (kid && ci < kMaxActions) {
+            kid[ci * 3u + 0u] = act;
+            kid[ci * 3u + 1u] = n;
+            kid[ci * 3u + 2u] = wbits;
+        }
+        uint32_t bn = ci < nchild ? n : 0u;
+        uint32_t bi = ci < nchild ? ci : 0xFFFFFFFFu;
+        wave_argmax_u(bn, bi);
+        if (bi != 0xFFFFFFFFu && (best_i == 0xFFFFFFFFu || bn > best_n)) {
+            best_n = bn;
+            best_i = bi;
+            best_act = __builtin_amdgcn_readlane(act, bi - base);
+        }
+        if (base + kBlockEntries < nchild) blk = bnext[blk];
+    }
+    if (lane == 0) a.best[t] = best_i == 0xFFFFFFFFu ? -1 : (int32_t)best_act;
+}
+
+size_t mcts_tree_words(uint32_t iters)
+{
+    const uint64_t nodes_cap = (uint64_t)iters + 1u;
+    const uint64_t blocks_cap = nodes_cap + nodes_cap / kBlockEntries + 2u;
+    return kTreeHeaderWords + nodes_cap * kNodeWords + blocks_cap * kBlockWords + blocks_cap;
+}
+
+hipError_t launch_mcts(const uint4 *roots, uint32_t n_trees, uint32_t iters, uint32_t ppl,
+                       uint32_t dmax, float c_uct, uint32_t k0, uint32_t k1, uint32_t tree_base,
+                       const float *ln, uint32_t *ws, int32_t *best, uint32_t *kids,
+                       hipStream_t st)
+{
+    if (n_trees == 0) return hipSuccess;
+    MctsArgs a;
+    a.roots = roots;
+    a.n_trees = n_trees;
+    a.iters = iters;
+    a.ppl = ppl;
+    a.dmax = dmax;
+    a.c_uct = c_uct;
+    a.k0 = k0;
+    a.k1 = k1;
+    a.tree_base = tree_base;
+    a.ln = ln;
+    a.ws = ws;
+    a.tree_words = mcts_tree_words(iters);
+    a.nodes_cap = iters + 1u;
+    a.blocks_cap = (iters + 1u) + (iters + 1u) / kBlockEntries + 2u;
+    a.best = best;
+    a.kids = kids;
+    hipLaunchKernelGGL(mcts_tree_kernel, dim3(n_trees), dim3(64), 0, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace dvc

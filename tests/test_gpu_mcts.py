@@ -1,0 +1,117 @@
+"""GPU parity of the tree search (through the C ABI).
+
+Bar: bit-exact.  The chosen action, and every root child's action, visit
+count and win sum (single-precision, same rounding order) must equal the CPU
+oracle's for the same roots, seeds and parameters: the plain single-tree
+search (one fresh two-player deal, 2000 iterations x 16 playouts), and a
+batch of mixed 2/3/4-player mid-game roots (trees 0-63 of the batched
+workload, 1024 iterations x 32 playouts), plus depth thresholds, tiny
+iteration counts, forced wins and argument errors.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dvc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2403_10720_amd as D
+    D.lib()
+    return D
+
+
+def dev_states(a):
+    return torch.from_numpy(np.ascontiguousarray(a).view(np.int32)).cuda()
+
+
+def run_both(orc, dvc, roots, iters, ppl, dmax, seed, tree_base=0):
+    mo = orc.mcts_params(iterations=iters, playouts_per_leaf=ppl, max_depth=dmax)
+    md = dvc.mcts_params(iterations=iters, playouts_per_leaf=ppl, max_depth=dmax)
+    best_ref, kids_ref = orc.mcts_search(roots, mo, seed, tree_base)
+    best, kids = dvc.mcts_search(dev_states(roots), md, seed, tree_base)
+    torch.cuda.synchronize()
+    assert dvc.dvc_check() == 0
+    act, n, w = dvc.children_view(kids)
+    return best_ref, kids_ref, best.cpu().numpy(), act.numpy(), n.numpy(), w.numpy()
+
+
+def assert_same(best_ref, kids_ref, best, act, n, w):
+    assert np.array_equal(best, best_ref), (best, best_ref)
+    assert np.array_equal(act, kids_ref["action"].astype(np.int64))
+    assert np.array_equal(n, kids_ref["n"].astype(np.int64))
+    assert np.array_equal(w.view(np.uint32), kids_ref["w"].view(np.uint32))
+
+
+def test_plain_single_tree_search(orc, dvc):
+    """One fresh two-player deal, 4 tiles each, root draw; 2000 x 16, c = sqrt 2, depth 4."""
+    dp = orc.deal_params(p_min=2, p_max=2, fresh=1, root_draw=1)
+    roots = orc.init_states(1, dp, seed=1)
+    assert_same(*run_both(orc, dvc, roots, 2000, 16, 4, seed=1))
+
+
+@pytest.mark.parametrize("dmax", [1, 2, 3, 6])
+def test_depth_thresholds(orc, dvc, dmax):
+    dp = orc.deal_params(p_min=2, p_max=4, pile_min=0, pile_max=12, revealed_max=4, root_draw=1)
+    roots = orc.init_states(8, dp, seed=10 + dmax)
+    assert_same(*run_both(orc, dvc, roots, 300, 8, dmax, seed=5))
+
+
+@pytest.mark.parametrize("iters,ppl", [(1, 1), (2, 3), (7, 64), (5, 65), (40, 130)])
+def test_small_and_ragged(orc, dvc, iters, ppl):
+    dp = orc.deal_params(p_min=2, p_max=4, pile_min=0, pile_max=16, revealed_max=8, root_draw=1)
+    roots = orc.init_states(5, dp, seed=iters * 1000 + ppl)
+    assert_same(*run_both(orc, dvc, roots, iters, ppl, 4, seed=3, tree_base=77))
+
+
+def test_batched_workload_trees_0_to_63(orc, dvc):
+    """Mixed 2/3/4-player roots (hands 4/4/3, pool 0-16 capped, 0-8 revealed, root draw),
+    1024 iterations x 32 playouts: the first 64 trees of the batch, all compared."""
+    dp = orc.deal_params(p_min=2, p_max=4, hand=(0, 0, 4, 4, 3), pile_min=0, pile_max=16,
+                         revealed_max=8, root_draw=1)
+    roots = orc.init_states(64, dp, seed=3)
+    assert_same(*run_both(orc, dvc, roots, 1024, 32, 4, seed=3))
+
+
+def test_batch_invariance(orc, dvc):
+    dp = orc.deal_params(p_min=2, p_max=4, pile_min=0, pile_max=16, revealed_max=8, root_draw=1)
+    roots = orc.init_states(32, dp, seed=4)
+    md = dvc.mcts_params(iterations=200, playouts_per_leaf=8, max_depth=4)
+    bb, kb = dvc.mcts_search(dev_states(roots), md, 9, 0)
+    for i in [0, 17, 31]:
+        bi, ki = dvc.mcts_search(dev_states(roots[i:i + 1]), md, 9, i)
+        assert torch.equal(bi[0], bb[i]) and torch.equal(ki[0], kb[i])
+
+
+def test_forced_win_root(orc, dvc):
+    import positions as POS
+    root = POS.pack(POS.two_player_last_tiles(1))[None, :]
+    assert_same(*run_both(orc, dvc, root, 50, 16, 4, seed=3))
+
+
+def test_mcts_argument_errors(dvc):
+    st = torch.zeros((2, 4), dtype=torch.int32, device="cuda")
+    with pytest.raises(dvc.DvcError):
+        dvc.mcts_search(st, dvc.mcts_params(iterations=0), 1)
+    with pytest.raises(dvc.DvcError):
+        dvc.mcts_search(st, dvc.mcts_params(max_depth=17), 1)
+    md = dvc.mcts_params(iterations=10, playouts_per_leaf=4)
+    need = dvc.dvc_mcts_workspace_bytes(2, md)
+    small = torch.empty(need - 4, dtype=torch.uint8, device="cuda")
+    with pytest.raises(dvc.DvcError):
+        dvc.mcts_search(st, md, 1, workspace=small)
+
+
+def test_malformed_root_sets_error(orc, dvc):
+    dp = orc.deal_params(p_min=2, p_max=2, fresh=1, root_draw=1)
+    roots = orc.init_states(2, dp, seed=1)
+    roots[1, 3] |= np.uint32(1 << 30)
+    best, kids = dvc.mcts_search(dev_states(roots), dvc.mcts_params(iterations=20, playouts_per_leaf=4), 1)
+    assert dvc.dvc_check() == dvc.DVC_ESTATE
+    assert best.cpu().numpy()[1] == -1
+    ref_best, _ = orc.mcts_search(roots[:1], orc.mcts_params(iterations=20, playouts_per_leaf=4), 1)
+    assert best.cpu().numpy()[0] == ref_best[0]

@@ -70,7 +70,7 @@ def _compare(dvc, states_np, ppl, seed, tree, base, ref, **kw):
     assert np.array_equal(sw.cpu().numpy().view(np.uint32), rs), "seat wins"
 
 
-@pytest.mark.parametrize("variant", [1, 2, 3])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4])
 @pytest.mark.parametrize("P", [2, 3, 4])
 def test_rollout_bit_exact_small(orc, dvc, variant, P):
     po = orc.deal_params(p_min=P, p_max=P, pile_min=0, pile_max=16, revealed_max=8, phase_mix=1)
@@ -92,7 +92,7 @@ def test_rollout_schedule_invariance(orc, dvc, variant, block, grid):
     _compare(dvc, S, ppl, 77, 3, 0, ref, variant=variant, block=block, grid=grid)
 
 
-@pytest.mark.parametrize("variant", [2, 3])
+@pytest.mark.parametrize("variant", [2, 3, 4])
 @pytest.mark.parametrize("ppl", [1, 2, 63, 64, 65, 129, 1000])
 def test_rollout_ppl_edges(orc, dvc, variant, ppl):
     po = orc.deal_params(p_min=2, p_max=3, pile_min=0, pile_max=16, revealed_max=8)
@@ -100,6 +100,14 @@ def test_rollout_ppl_edges(orc, dvc, variant, ppl):
     S = orc.init_states(n, po, seed=ppl)
     ref = _rollout_ref(orc, S, ppl, 4, 0, 17)
     _compare(dvc, S, ppl, 4, 0, 17, ref, variant=variant)
+
+
+@pytest.mark.parametrize("per_lane", [1, 2, 4])
+def test_rollout_playouts_per_lane_invariance(orc, dvc, per_lane):
+    po = orc.deal_params(p_min=2, p_max=4, pile_min=0, pile_max=16, revealed_max=8)
+    S = orc.init_states(150, po, seed=6)
+    ref = _rollout_ref(orc, S, 90, 8, 1, 5)
+    _compare(dvc, S, 90, 8, 1, 5, ref, variant=4, grid=per_lane)
 
 
 def test_rollout_batch_invariance(orc, dvc):
@@ -126,7 +134,7 @@ def test_rollout_optional_outputs(orc, dvc):
     assert np.array_equal(w.cpu().numpy(), ref[0])
 
 
-@pytest.mark.parametrize("variant", [1, 2, 3])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4])
 def test_rollout_decided_and_malformed_leaves(orc, dvc, variant):
     import positions as POS
     rng = np.random.default_rng(9)
@@ -175,7 +183,7 @@ def test_rollout_full_leaf_parallel_workload(orc, dvc):
     st = dvc.dvc_init_states(4096, pd, seed=2)
     assert np.array_equal(to_np(st), S)
     ref = _rollout_ref(orc, S, 256, 2, 0, 0)
-    for variant in [1, 2, 3]:
+    for variant in [1, 2, 3, 4]:
         w, ln, sw = dvc.dvc_rollout(st, 256, 2, 0, 0, variant=variant)
         torch.cuda.synchronize()
         assert np.array_equal(w.cpu().numpy(), ref[0])

@@ -177,7 +177,7 @@ def test_determinization_fallback_is_smallest_world(orc):
         for i in range(20):
             world, a = orc.determinize(root, 1, t, i)
             _consistent(orc, root, world)
-            if a == 16:
+            if a == 64:
                 used += 1
     print("fallback used", used, "of", 300 * 20)
 
