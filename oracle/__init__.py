@@ -86,6 +86,16 @@ def lib():
         L.oracle_ln_entry.argtypes = [C.c_uint32]
         L.oracle_mcts_search.argtypes = [C.c_void_p, C.c_int64, C.POINTER(MctsParams), C.c_uint64,
                                          C.c_uint32, C.c_void_p, C.c_void_p]
+        L.oracle_bf16.restype = C.c_float
+        L.oracle_bf16.argtypes = [C.c_float]
+        L.oracle_vn_encode.argtypes = [C.c_void_p, C.c_int32, C.c_void_p]
+        L.oracle_vn_forward.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int,
+                                        C.c_void_p]
+        L.oracle_vn_loss_grad.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                          C.c_int, C.POINTER(C.c_double), C.c_void_p]
+        L.oracle_vn_adam.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                     C.c_int64, C.c_double, C.c_double, C.c_double, C.c_double]
+        L.oracle_vn_init.argtypes = [C.c_void_p, C.c_uint64]
         _lib = L
     return _lib
 
@@ -248,3 +258,62 @@ def mcts_search(roots, params: MctsParams, seed: int, tree_id_base: int = 0):
     if rc:
         raise ValueError(f"oracle_mcts_search failed ({rc})")
     return best, kids
+
+
+# ---------------------------------------------------------------------------
+# value network
+# ---------------------------------------------------------------------------
+VN_NPARAM = 107265
+VN_OFF = {"W1": (0, (256, 160)), "b1": (40960, (256,)), "W2": (41216, (256, 256)),
+          "b2": (106752, (256,)), "w3": (107008, (256,)), "b3": (107264, (1,))}
+
+
+def bf16(x: float) -> float:
+    return float(lib().oracle_bf16(x))
+
+
+def vn_encode(state, q: int) -> np.ndarray:
+    s = _states(state)
+    out = np.zeros(160, np.float32)
+    rc = lib().oracle_vn_encode(_ptr(s), q, _ptr(out))
+    if rc:
+        raise ValueError(f"encode failed ({rc})")
+    return out
+
+
+def vn_init(seed: int) -> np.ndarray:
+    p = np.zeros(VN_NPARAM, np.float32)
+    lib().oracle_vn_init(_ptr(p), seed)
+    return p
+
+
+def vn_forward(params, states, persp, bf16_mirror: bool = False) -> np.ndarray:
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    s = _states(states)
+    q = np.ascontiguousarray(persp, dtype=np.int32)
+    v = np.zeros(s.shape[0], np.float64)
+    rc = lib().oracle_vn_forward(_ptr(p), _ptr(s), _ptr(q), s.shape[0], int(bf16_mirror), _ptr(v))
+    if rc:
+        raise ValueError(f"forward failed ({rc})")
+    return v
+
+
+def vn_loss_grad(params, states, persp, labels, bf16_mirror: bool = False):
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    s = _states(states)
+    q = np.ascontiguousarray(persp, dtype=np.int32)
+    y = np.ascontiguousarray(labels, dtype=np.float32)
+    g = np.zeros(VN_NPARAM, np.float64)
+    loss = C.c_double(0.0)
+    rc = lib().oracle_vn_loss_grad(_ptr(p), _ptr(s), _ptr(q), _ptr(y), s.shape[0],
+                                   int(bf16_mirror), C.byref(loss), _ptr(g))
+    if rc:
+        raise ValueError(f"loss_grad failed ({rc})")
+    return loss.value, g
+
+
+def vn_adam(w, m, v, g, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """In-place Adam step on float64 arrays."""
+    for a in (w, m, v, g):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    lib().oracle_vn_adam(_ptr(w), _ptr(m), _ptr(v), _ptr(g), w.size, t, lr, b1, b2, eps)

@@ -117,57 +117,10 @@ __device__ __forceinline__ uint32_t kth_bit_tab(uint32_t m, uint32_t k, const ui
     return sh + tab[(byte << 3) | ((k - base) & 7u)];
 }
 
-// k-th set bit without memory: bit counts pick the byte, then the nibble;
-// the position inside the nibble comes from a 128-bit constant holding, for
-// every nibble value n and rank i < 4, the 2-bit position of its i-th set bit.
-constexpr uint64_t nibble_table_half(int hi)
-{
-    uint64_t t = 0;
-    for (int idx = 0; idx < 32; ++idx) {
-        const int e = idx + 32 * hi, n = e >> 2, k = e & 3;
-        int pos = 0, cnt = 0;
-        for (int b = 0; b < 4; ++b)
-            if ((n >> b) & 1) {
-                if (cnt == k) pos = b;
-                ++cnt;
-            }
-        t |= (uint64_t)pos << (2 * idx);
-    }
-    return t;
-}
-constexpr uint64_t kNibLo = nibble_table_half(0);
-constexpr uint64_t kNibHi = nibble_table_half(1);
-
-__device__ __forceinline__ uint32_t kth_bit_alu(uint32_t m, uint32_t k)
-{
-    const uint32_t c0 = (uint32_t)__popc(m & 0xFFu);
-    const uint32_t c01 = (uint32_t)__popc(m & 0xFFFFu);
-    const bool b2 = k >= c01, b1 = k >= c0;
-    const uint32_t sh = b2 ? 16u : (b1 ? 8u : 0u);
-    const uint32_t kk = k - (b2 ? c01 : (b1 ? c0 : 0u));
-    const uint32_t byte = (m >> sh) & 0xFFu;
-    const uint32_t cn = (uint32_t)__popc(byte & 0xFu);
-    const bool hn = kk >= cn;
-    const uint32_t sh2 = hn ? 4u : 0u;
-    const uint32_t k2 = (kk - (hn ? cn : 0u)) & 3u;
-    const uint32_t idx = (((byte >> sh2) & 0xFu) << 2) | k2;
-    const uint64_t tbl = idx < 32u ? kNibLo : kNibHi;
-    const uint32_t pos = (uint32_t)(tbl >> ((idx & 31u) * 2u)) & 3u;
-    return sh + sh2 + pos;
-}
-
-// The guess step selects k-th bits through one of the two routes above.
-#ifdef DVC_KTH_ALU
-__device__ __forceinline__ uint32_t pick_bit_tab(uint32_t m, uint32_t w, const uint8_t *)
-{
-    return kth_bit_alu(m, pick(w, (uint32_t)__popc(m)));
-}
-#else
 __device__ __forceinline__ uint32_t pick_bit_tab(uint32_t m, uint32_t w, const uint8_t *tab)
 {
     return kth_bit_tab(m, pick(w, (uint32_t)__popc(m)), tab);
 }
-#endif
 
 // Game state in registers: one tile mask per seat (seats >= P are empty).
 struct State {

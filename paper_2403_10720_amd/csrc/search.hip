@@ -133,11 +133,15 @@ __device__ bool det_attempt(const State &R, uint32_t attempt, uint32_t iter, uin
 // Deterministic fallback: the lexicographically smallest consistent world
 // (slots ordered by opponent from the mover's left, then left to right),
 // by depth-first search trying the lowest tile first.  Gives up (false)
-// after kDfsMaxCalls search calls.
-__device__ bool det_fallback(const State &R, State &out)
+// after kDfsMaxCalls search calls.  Runs in one lane; its per-slot arrays
+// live in LDS (`sl`), so the kernel needs no scratch memory.
+struct DfsSlots {
+    uint8_t o[24], col[24], hi[24], seg[24];
+    int8_t lo[24], assign[24], tried[24];
+};
+
+__device__ bool det_fallback(const State &R, State &out, DfsSlots &sl)
 {
-    uint8_t so[24], scol[24], shi[24], sseg[24];
-    int8_t slo[24], assign[24], tried[24];
     uint32_t ns = 0;
     for (uint32_t k = 1; k < 4u; ++k) {
         if (k >= R.P) break;
@@ -153,11 +157,11 @@ __device__ bool det_fallback(const State &R, State &out)
             const uint32_t below = revrow & ((1u << t0) - 1u);
             const uint32_t above = revrow & ~((2u << t0) - 1u);
             const int32_t lo = below ? 31 - __builtin_clz(below) : -1;
-            so[ns] = (uint8_t)o;
-            scol[ns] = (uint8_t)(t0 & 1u);
-            slo[ns] = (int8_t)lo;
-            shi[ns] = (uint8_t)(above ? (uint32_t)__builtin_ctz(above) : 24u);
-            sseg[ns] = (uint8_t)(first || lo != last_lo);
+            sl.o[ns] = (uint8_t)o;
+            sl.col[ns] = (uint8_t)(t0 & 1u);
+            sl.lo[ns] = (int8_t)lo;
+            sl.hi[ns] = (uint8_t)(above ? (uint32_t)__builtin_ctz(above) : 24u);
+            sl.seg[ns] = (uint8_t)(first || lo != last_lo);
             first = false;
             last_lo = lo;
             ++ns;
@@ -166,35 +170,34 @@ __device__ bool det_fallback(const State &R, State &out)
     uint32_t avail = ~(hand_of(R, R.m) | R.rev) & kAll;
     int32_t k = 0;
     uint32_t calls = 1;
-    if (ns > 0) tried[0] = -1;
+    if (ns > 0) sl.tried[0] = -1;
     while (k < (int32_t)ns) {
-        const int32_t prev = sseg[k] ? slo[k] : assign[k - 1];
-        const int32_t from = tried[k] < 0 ? prev + 1 : tried[k] + 1;
-        const uint32_t cand = avail & (scol[k] ? kWhite : kBlack) & below_bits(shi[k]) &
+        const int32_t prev = sl.seg[k] ? sl.lo[k] : sl.assign[k - 1];
+        const int32_t from = sl.tried[k] < 0 ? prev + 1 : sl.tried[k] + 1;
+        const uint32_t cand = avail & (sl.col[k] ? kWhite : kBlack) & below_bits(sl.hi[k]) &
                               ~((1u << (uint32_t)from) - 1u);
         if (cand) {
             const uint32_t x = (uint32_t)__builtin_ctz(cand);
-            tried[k] = (int8_t)x;
-            assign[k] = (int8_t)x;
+            sl.tried[k] = (int8_t)x;
+            sl.assign[k] = (int8_t)x;
             avail &= ~(1u << x);
             ++k;
             if (++calls > kDfsMaxCalls) return false;
-            if (k < (int32_t)ns) tried[k] = -1;
+            if (k < (int32_t)ns) sl.tried[k] = -1;
         } else {
-            tried[k] = -1;
+            sl.tried[k] = -1;
             --k;
             if (k < 0) return false;
-            avail |= 1u << (uint32_t)assign[k];
+            avail |= 1u << (uint32_t)sl.assign[k];
         }
     }
     out = R;
-    uint32_t rows[4] = {R.h0 & R.rev, R.h1 & R.rev, R.h2 & R.rev, R.h3 & R.rev};
-    for (uint32_t j = 0; j < ns; ++j) rows[so[j]] |= 1u << (uint32_t)assign[j];
-    for (uint32_t k2 = 1; k2 < 4u; ++k2) {
-        if (k2 >= R.P) break;
-        const uint32_t o = R.m + k2 >= R.P ? R.m + k2 - R.P : R.m + k2;
-        set_hand(out, o, rows[o]);
-    }
+    out.h0 &= R.rev;
+    out.h1 &= R.rev;
+    out.h2 &= R.rev;
+    out.h3 &= R.rev;
+    add_to_hand(out, R.m, hand_of(R, R.m));
+    for (uint32_t j = 0; j < ns; ++j) add_to_hand(out, sl.o[j], 1u << (uint32_t)sl.assign[j]);
     return true;
 }
 
@@ -323,6 +326,7 @@ __global__ void __launch_bounds__(64) mcts_tree_kernel(MctsArgs a)
     __shared__ uint8_t tab[kKthTableBytes];
     __shared__ uint32_t legal_s[72];
     __shared__ uint32_t path_e[kMaxDepthLimit + 1];
+    __shared__ DfsSlots dfs_slots;
     fill_kth_table(tab);
     __syncthreads();
     const uint32_t t = blockIdx.x;
@@ -347,7 +351,8 @@ __global__ void __launch_bounds__(64) mcts_tree_kernel(MctsArgs a)
     }
     if (lane < kNodeWords) nodes[lane] = lane < 2u ? kNoBlock : 0u;
     uint32_t n_nodes = 1u, n_blocks = 0u, n_root = 0u;
-    bool failed = false;
+    bool failed = false, have_fallback = false;
+    State fallback = R;
     __syncthreads();
 
     for (uint32_t it = 0; it < a.iters && !failed; ++it) {
@@ -358,16 +363,21 @@ __global__ void __launch_bounds__(64) mcts_tree_kernel(MctsArgs a)
         if (okm) {
             S = readlane_state(S, (uint32_t)__builtin_ctzll(okm));
         } else {
-            State F = R;
-            bool fok = false;
-            if (lane == 0) fok = det_fallback(R, F);
-            fok = __builtin_amdgcn_readfirstlane((uint32_t)fok) != 0u;
-            if (!fok) {
-                if (lane == 0) atomicOr(&g_error_word, kErrLimit);
-                failed = true;
-                break;
+            // the fallback world depends on the root only: search it once
+            if (!have_fallback) {
+                State F = R;
+                bool fok = false;
+                if (lane == 0) fok = det_fallback(R, F, dfs_slots);
+                fok = __builtin_amdgcn_readfirstlane((uint32_t)fok) != 0u;
+                if (!fok) {
+                    if (lane == 0) atomicOr(&g_error_word, kErrLimit);
+                    failed = true;
+                    break;
+                }
+                fallback = readlane_state(F, 0u);
+                have_fallback = true;
             }
-            S = readlane_state(F, 0u);
+            S = fallback;
         }
 
         // ---- 2. descend ----------------------------------------------------
