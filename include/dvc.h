@@ -195,6 +195,63 @@ int mcts_search(const dvc_state_t *roots, int64_t n_trees, const dvc_mcts_params
                 int32_t *best_action, dvc_child_stat *root_children, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Learned leaf evaluator (value network).  The paper weights tree nodes by the
+ * results of random playouts (Sec. II-B); this network learns the playout win
+ * rate of a perspective seat from (state, win rate) pairs the playout kernel
+ * generates, so that most leaves need no playouts.
+ * Features (160, zero padded from 148): per tile t (24), the owner relative to
+ * the perspective q as a one-hot of 4 ((owner - q) mod P, nothing for pool
+ * tiles), revealed, in pool; then (mover - q) mod P as a one-hot of 4.
+ * h1 = bf16(relu(W1 x + b1)) (256), h2 = bf16(relu(W2 h1 + b2)) (256),
+ * v = sigmoid(w3 . h2 + b3).  Products in bfloat16 on the matrix cores with
+ * float32 accumulation; float32 master weights; Adam (beta 0.9 / 0.999,
+ * eps 1e-8, bias-corrected) on the mean squared error.
+ * Flat parameter order (107265 floats): W1[256][160] (row = output), b1[256],
+ * W2[256][256], b2[256], w3[256], b3.
+ * ------------------------------------------------------------------------- */
+#define DVC_VALUENET_PARAMS 107265
+
+/* bytes of a network blob: weights, Adam moments and bf16 copies (device) */
+size_t dvc_valuenet_bytes(void);
+
+/* Initialize a blob: weight k of the flat order takes word k of the Philox
+ * stream (k>>2, 0xFFFFFFFE, 0, 0), u = (w >> 8) * 2^-24, U(-b, b) with
+ * b = sqrt(6/148) (W1), sqrt(6/256) (W2), 1/16 (w3); biases and moments 0. */
+int dvc_valuenet_init(void *net, uint64_t seed, void *stream);
+
+/* Load float32 parameters (device, flat order), reset the Adam moments. */
+int dvc_valuenet_set_params(void *net, const float *params, void *stream);
+
+/* Copy the float32 parameters out (device, flat order). */
+int dvc_valuenet_get_params(const void *net, float *params, void *stream);
+
+/* v_out[i] = value of states[i] for perspective seat persp[i] (< players).
+ * A malformed state or perspective sets DVC_ESTATE in the error word.     */
+int dvc_valuenet_infer(const void *net, const dvc_state_t *states, const uint8_t *persp,
+                       int64_t n, float *v_out, void *stream);
+
+size_t dvc_valuenet_train_workspace_bytes(int64_t batch);
+
+/* One Adam step (number `step` >= 1, learning rate lr) on the mean squared
+ * error over `batch` rows; row i is data[(perm_a*(row_base+i) + perm_b) %
+ * n_data] of (states, persp, labels).  batch: multiple of 32, <= 65536.
+ * loss_out (device float, may be NULL) receives the batch loss before the
+ * step; grad_out (device, 107265 floats, may be NULL) the gradient.       */
+int dvc_valuenet_train_step(void *net, const dvc_state_t *states, const uint8_t *persp,
+                            const float *labels, int64_t n_data, uint32_t perm_a, uint32_t perm_b,
+                            uint32_t row_base, int32_t batch, int64_t step, float lr, void *ws,
+                            size_t ws_bytes, float *loss_out, float *grad_out, void *stream);
+
+/* Training pairs: for state i (index index_base + i) a perspective seat q =
+ * floor(w * P / 2^32) with w word 0 of block (0, 0xFFFFFFFC, 0, index_base+i),
+ * and label = (playouts of the state won by q) / playouts, from `playouts`
+ * random playouts (tree id tree_id, leaf id index_base + i).  seat_wins_ws:
+ * device scratch of n*4 uint32.                                           */
+int dvc_valuenet_labels(const dvc_state_t *states, int64_t n, int32_t playouts, uint64_t seed,
+                        uint32_t tree_id, uint32_t index_base, uint8_t *persp_out,
+                        float *labels_out, uint32_t *seat_wins_ws, void *stream);
+
+/* ---------------------------------------------------------------------------
  * Status
  * ------------------------------------------------------------------------- */
 const char *dvc_status_str(int status);

@@ -82,6 +82,16 @@ def lib():
         L.dvc_init_states.argtypes = [vp, i64, C.POINTER(DealParams), u64, u32, vp]
         L.dvc_rollout.argtypes = [vp, i64, i32, u64, u32, u32, vp, vp, vp, vp]
         L.dvc_rollout_ex.argtypes = [vp, i64, i32, u64, u32, u32, vp, vp, vp, i32, i32, i32, vp]
+        L.dvc_valuenet_bytes.restype = C.c_size_t
+        L.dvc_valuenet_init.argtypes = [vp, u64, vp]
+        L.dvc_valuenet_set_params.argtypes = [vp, vp, vp]
+        L.dvc_valuenet_get_params.argtypes = [vp, vp, vp]
+        L.dvc_valuenet_infer.argtypes = [vp, vp, vp, i64, vp, vp]
+        L.dvc_valuenet_train_workspace_bytes.restype = C.c_size_t
+        L.dvc_valuenet_train_workspace_bytes.argtypes = [i64]
+        L.dvc_valuenet_train_step.argtypes = [vp, vp, vp, vp, i64, u32, u32, u32, i32, i64,
+                                              C.c_float, vp, C.c_size_t, vp, vp, vp]
+        L.dvc_valuenet_labels.argtypes = [vp, i64, i32, u64, u32, u32, vp, vp, vp, vp]
         if hasattr(L, "mcts_search"):
             L.dvc_mcts_workspace_bytes.restype = C.c_size_t
             L.dvc_mcts_workspace_bytes.argtypes = [i64, C.POINTER(MctsParams)]
@@ -207,3 +217,76 @@ def c_uct_default() -> float:
 
 
 assert abs(c_uct_default() - math.sqrt(2)) < 1e-6
+
+
+# ---------------------------------------------------------------------------
+# value network
+# ---------------------------------------------------------------------------
+VALUENET_PARAMS = 107265
+
+
+def dvc_valuenet_bytes() -> int:
+    return int(lib().dvc_valuenet_bytes())
+
+
+def dvc_valuenet_init(seed: int, net=None, device="cuda", stream=None) -> torch.Tensor:
+    if net is None:
+        net = torch.empty(dvc_valuenet_bytes(), dtype=torch.uint8, device=device)
+    _raise(lib().dvc_valuenet_init(_ptr(net), seed & (2**64 - 1), _stream(stream)), "dvc_valuenet_init")
+    return net
+
+
+def dvc_valuenet_set_params(net, params: torch.Tensor, stream=None):
+    _check_dev(params, torch.float32, (VALUENET_PARAMS,), "params")
+    _raise(lib().dvc_valuenet_set_params(_ptr(net), _ptr(params), _stream(stream)),
+           "dvc_valuenet_set_params")
+
+
+def dvc_valuenet_get_params(net, stream=None) -> torch.Tensor:
+    out = torch.empty(VALUENET_PARAMS, dtype=torch.float32, device=net.device)
+    _raise(lib().dvc_valuenet_get_params(_ptr(net), _ptr(out), _stream(stream)),
+           "dvc_valuenet_get_params")
+    return out
+
+
+def dvc_valuenet_infer(net, states: torch.Tensor, persp: torch.Tensor, out=None, stream=None):
+    _check_dev(states, torch.int32, None, "states")
+    _check_dev(persp, torch.uint8, (states.shape[0],), "persp")
+    n = states.shape[0]
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device=states.device)
+    _raise(lib().dvc_valuenet_infer(_ptr(net), _ptr(states), _ptr(persp), n, _ptr(out),
+                                    _stream(stream)), "dvc_valuenet_infer")
+    return out
+
+
+def dvc_valuenet_train_workspace_bytes(batch: int) -> int:
+    return int(lib().dvc_valuenet_train_workspace_bytes(batch))
+
+
+def dvc_valuenet_train_step(net, states, persp, labels, step: int, lr: float = 1e-3,
+                            batch: int = 8192, perm_a: int = 1, perm_b: int = 0, row_base: int = 0,
+                            ws=None, loss_out=None, grad_out=None, stream=None):
+    n_data = states.shape[0]
+    if ws is None:
+        ws = torch.empty(dvc_valuenet_train_workspace_bytes(batch), dtype=torch.uint8,
+                         device=states.device)
+    rc = lib().dvc_valuenet_train_step(_ptr(net), _ptr(states), _ptr(persp), _ptr(labels), n_data,
+                                       perm_a & 0xFFFFFFFF, perm_b & 0xFFFFFFFF,
+                                       row_base & 0xFFFFFFFF, batch, step, lr, _ptr(ws),
+                                       ws.numel(), _ptr(loss_out), _ptr(grad_out), _stream(stream))
+    _raise(rc, "dvc_valuenet_train_step")
+    return ws
+
+
+def dvc_valuenet_labels(states, playouts: int, seed: int, tree_id: int = 1, index_base: int = 0,
+                        stream=None):
+    n = states.shape[0]
+    dev = states.device
+    persp = torch.empty(n, dtype=torch.uint8, device=dev)
+    labels = torch.empty(n, dtype=torch.float32, device=dev)
+    ws = torch.empty((n, 4), dtype=torch.int32, device=dev)
+    rc = lib().dvc_valuenet_labels(_ptr(states), n, playouts, seed & (2**64 - 1), tree_id,
+                                   index_base, _ptr(persp), _ptr(labels), _ptr(ws), _stream(stream))
+    _raise(rc, "dvc_valuenet_labels")
+    return persp, labels

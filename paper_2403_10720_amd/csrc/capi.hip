@@ -231,4 +231,75 @@ int mcts_search(const dvc_state_t *roots, int64_t n_trees, const dvc_mcts_params
                                  (hipStream_t)stream));
 }
 
+size_t dvc_valuenet_bytes(void) { return vn_bytes(); }
+
+int dvc_valuenet_init(void *net, uint64_t seed, void *stream)
+{
+    if (net == nullptr) return DVC_EINVAL;
+    return status_of(launch_vn_init(net, (uint32_t)seed, (uint32_t)(seed >> 32), (hipStream_t)stream));
+}
+
+int dvc_valuenet_set_params(void *net, const float *params, void *stream)
+{
+    if (net == nullptr || params == nullptr) return DVC_EINVAL;
+    return status_of(launch_vn_set_params(net, params, (hipStream_t)stream));
+}
+
+int dvc_valuenet_get_params(const void *net, float *params, void *stream)
+{
+    if (net == nullptr || params == nullptr) return DVC_EINVAL;
+    return status_of(launch_vn_get_params(net, params, (hipStream_t)stream));
+}
+
+int dvc_valuenet_infer(const void *net, const dvc_state_t *states, const uint8_t *persp, int64_t n,
+                       float *v_out, void *stream)
+{
+    if (n < 0 || n >= (1ll << 31)) return DVC_EINVAL;
+    if (n == 0) return DVC_OK;
+    if (net == nullptr || states == nullptr || persp == nullptr || v_out == nullptr) return DVC_EINVAL;
+    return status_of(launch_vn_infer(net, reinterpret_cast<const uint4 *>(states), persp,
+                                     (uint32_t)n, v_out, (hipStream_t)stream));
+}
+
+size_t dvc_valuenet_train_workspace_bytes(int64_t batch)
+{
+    if (batch < 32 || batch > 65536 || batch % 32 != 0) return 0;
+    return vn_train_ws_bytes((uint32_t)batch);
+}
+
+int dvc_valuenet_train_step(void *net, const dvc_state_t *states, const uint8_t *persp,
+                            const float *labels, int64_t n_data, uint32_t perm_a, uint32_t perm_b,
+                            uint32_t row_base, int32_t batch, int64_t step, float lr, void *ws,
+                            size_t ws_bytes, float *loss_out, float *grad_out, void *stream)
+{
+    if (net == nullptr || states == nullptr || persp == nullptr || labels == nullptr || ws == nullptr)
+        return DVC_EINVAL;
+    if (batch < 32 || batch > 65536 || batch % 32 != 0 || n_data < 1 || n_data >= (1ll << 32) ||
+        step < 1 || !(lr > 0.0f))
+        return DVC_EINVAL;
+    if (ws_bytes < vn_train_ws_bytes((uint32_t)batch)) return DVC_ENOMEM;
+    const double c1 = 1.0 - std::pow(0.9, (double)step), c2 = 1.0 - std::pow(0.999, (double)step);
+    return status_of(launch_vn_train_step(net, reinterpret_cast<const uint4 *>(states), persp, labels,
+                                          (uint32_t)n_data, perm_a, perm_b, row_base,
+                                          (uint32_t)batch, lr, (float)c1, (float)c2, ws, loss_out,
+                                          grad_out, (hipStream_t)stream));
+}
+
+int dvc_valuenet_labels(const dvc_state_t *states, int64_t n, int32_t playouts, uint64_t seed,
+                        uint32_t tree_id, uint32_t index_base, uint8_t *persp_out,
+                        float *labels_out, uint32_t *seat_wins_ws, void *stream)
+{
+    if (n < 0 || playouts < 1) return DVC_EINVAL;
+    if (n == 0) return DVC_OK;
+    if (states == nullptr || persp_out == nullptr || labels_out == nullptr || seat_wins_ws == nullptr)
+        return DVC_EINVAL;
+    int rc = dvc_rollout(states, n, playouts, seed, tree_id, index_base, nullptr, nullptr,
+                         seat_wins_ws, stream);
+    if (rc != DVC_OK) return rc;
+    return status_of(launch_vn_labels(reinterpret_cast<const uint4 *>(states), (uint32_t)n,
+                                      (uint32_t)playouts, (uint32_t)seed, (uint32_t)(seed >> 32),
+                                      index_base, seat_wins_ws, persp_out, labels_out,
+                                      (hipStream_t)stream));
+}
+
 }  // extern "C"

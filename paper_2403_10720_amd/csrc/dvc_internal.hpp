@@ -53,6 +53,22 @@ hipError_t launch_mcts(const uint4 *roots, uint32_t n_trees, uint32_t iters, uin
                        uint32_t dmax, float c_uct, uint32_t k0, uint32_t k1, uint32_t tree_base,
                        const float *ln, uint32_t *ws, int32_t *best, uint32_t *kids,
                        hipStream_t st);
+size_t vn_bytes();
+size_t vn_train_ws_bytes(uint32_t batch);
+hipError_t launch_vn_init(void *net, uint32_t k0, uint32_t k1, hipStream_t st);
+hipError_t launch_vn_shadow(void *net, hipStream_t st);
+hipError_t launch_vn_infer(const void *net, const uint4 *states, const uint8_t *persp, uint32_t n,
+                           float *v_out, hipStream_t st);
+hipError_t launch_vn_train_step(void *net, const uint4 *states, const uint8_t *persp,
+                                const float *labels, uint32_t n_data, uint32_t perm_a,
+                                uint32_t perm_b, uint32_t row_base, uint32_t batch, float lr,
+                                float c1, float c2, void *ws, float *loss_out, float *grad_out,
+                                hipStream_t st);
+hipError_t launch_vn_set_params(void *net, const float *params, hipStream_t st);
+hipError_t launch_vn_get_params(const void *net, float *params, hipStream_t st);
+hipError_t launch_vn_labels(const uint4 *states, uint32_t n, uint32_t playouts, uint32_t k0,
+                            uint32_t k1, uint32_t index_base, const uint32_t *seat_wins,
+                            uint8_t *persp, float *labels, hipStream_t st);
 hipError_t launch_init_states(uint4 *out, uint32_t n, const DealArgs &d, uint32_t k0, uint32_t k1,
                               uint32_t index_base, hipStream_t st);
 

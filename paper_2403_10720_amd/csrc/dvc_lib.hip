@@ -4,4 +4,5 @@
 #include "rollout.hip"
 #include "gen.hip"
 #include "search.hip"
+#include "valuenet.hip"
 #include "capi.hip"

@@ -1,0 +1,604 @@
+// valuenet.hip -- the learned leaf evaluator on gfx950 matrix cores.
+//
+// A small value network estimates, from a full game state and a perspective
+// seat q, the probability that q wins a random playout (the quantity the
+// paper's playouts estimate, Sec. II-B).  Features (160, zero padded from
+// 148): per tile the owner seat relative to q (one-hot of 4, nothing for pool
+// tiles), revealed, in pool; then (mover - q) mod P one-hot of 4.
+//   h1 = bf16(relu(W1 x + b1)), h2 = bf16(relu(W2 h1 + b2)), z = w3.h2 + b3,
+//   v = sigmoid(z), loss = mean (v - y)^2, Adam on float32 master weights.
+// Products use v_mfma_f32_16x16x32_bf16 with bfloat16 operands and float32
+// accumulation.  A wavefront owns 16 rows: it encodes its features straight
+// into the A operand, runs both layers, and (training) back-propagates the
+// data gradient through layer 2; the weight gradients are a second kernel
+// that contracts the stored activations over the batch; Adam a third.
+//
+// Net blob (device, caller-owned, dvc_valuenet_bytes()):
+//   u32 header[64]; float master[NPAD], m[NPAD], v[NPAD];
+//   bf16 W1b[256][160], W2b[256][256], W2Tb[256][256] (W2 transposed),
+//   W1Tb[160][256] (W1 transposed), w3b[256].
+#include "dvc_core.hpp"
+#include "dvc_internal.hpp"
+
+namespace dvc {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr uint32_t kVnIn = 160, kVnH = 256;
+constexpr uint32_t kOffW1 = 0, kOffB1 = 40960, kOffW2 = 41216, kOffB2 = 106752, kOffW3 = 107008,
+                   kOffB3 = 107264, kVnParams = 107265;
+constexpr uint32_t kVnPad = 107328;                       // params rounded up to 64
+constexpr uint32_t kVnHeaderWords = 64;
+constexpr uint64_t kVnMasterOff = kVnHeaderWords * 4u;     // byte offsets
+constexpr uint64_t kVnMOff = kVnMasterOff + (uint64_t)kVnPad * 4u;
+constexpr uint64_t kVnVOff = kVnMOff + (uint64_t)kVnPad * 4u;
+constexpr uint64_t kVnW1bOff = kVnVOff + (uint64_t)kVnPad * 4u;
+constexpr uint64_t kVnW2bOff = kVnW1bOff + 40960u * 2u;
+constexpr uint64_t kVnW2TbOff = kVnW2bOff + 65536u * 2u;
+constexpr uint64_t kVnW1TbOff = kVnW2TbOff + 65536u * 2u;
+constexpr uint64_t kVnW3bOff = kVnW1TbOff + 40960u * 2u;
+constexpr uint64_t kVnBytes = kVnW3bOff + 256u * 2u;
+
+struct VnPtrs {
+    uint32_t *header;
+    float *master, *m, *v;
+    uint16_t *w1b, *w2b, *w2tb, *w1tb, *w3b;
+};
+
+__host__ __device__ inline VnPtrs vn_ptrs(void *net)
+{
+    uint8_t *b = (uint8_t *)net;
+    VnPtrs p;
+    p.header = (uint32_t *)b;
+    p.master = (float *)(b + kVnMasterOff);
+    p.m = (float *)(b + kVnMOff);
+    p.v = (float *)(b + kVnVOff);
+    p.w1b = (uint16_t *)(b + kVnW1bOff);
+    p.w2b = (uint16_t *)(b + kVnW2bOff);
+    p.w2tb = (uint16_t *)(b + kVnW2TbOff);
+    p.w1tb = (uint16_t *)(b + kVnW1TbOff);
+    p.w3b = (uint16_t *)(b + kVnW3bOff);
+    return p;
+}
+
+// float -> bfloat16 bits, round to nearest even
+__device__ __forceinline__ uint16_t bf16_bits(float x)
+{
+    uint32_t u = __float_as_uint(x);
+    if ((u & 0x7F800000u) == 0x7F800000u) return (uint16_t)(u >> 16);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+__device__ __forceinline__ float bf16_round(float x) { return bf16_to_f(bf16_bits(x)); }
+
+// ---------------------------------------------------------------------------
+// initialization and shadows
+// ---------------------------------------------------------------------------
+__global__ void vn_init_kernel(void *net, uint32_t k0, uint32_t k1, float bw1, float bw2, float bw3)
+{
+    VnPtrs p = vn_ptrs(net);
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k == 0) {
+        for (uint32_t i = 0; i < kVnHeaderWords; ++i) p.header[i] = 0u;
+    }
+    if (k >= kVnPad) return;
+    float w = 0.0f;
+    if (k < kVnParams) {
+        const Words b = philox(k >> 2, 0xFFFFFFFEu, 0u, 0u, k0, k1);
+        const uint32_t word = (k & 3u) == 0u ? b.w0 : (k & 3u) == 1u ? b.w1 : (k & 3u) == 2u ? b.w2 : b.w3;
+        const float u = (float)(word >> 8) * (1.0f / 16777216.0f);
+        const float bound = k < kOffB1 ? bw1 : (k >= kOffW2 && k < kOffB2) ? bw2
+                          : (k >= kOffW3 && k < kOffB3) ? bw3 : 0.0f;
+        w = (2.0f * u - 1.0f) * bound;
+    }
+    p.master[k] = w;
+    p.m[k] = 0.0f;
+    p.v[k] = 0.0f;
+}
+
+// bf16 copies of the weights in the layouts the products read
+__global__ void vn_shadow_kernel(void *net)
+{
+    VnPtrs p = vn_ptrs(net);
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < 40960u) {
+        const uint32_t n = k / kVnIn, f = k % kVnIn;
+        const uint16_t b = bf16_bits(p.master[kOffW1 + k]);
+        p.w1b[k] = b;
+        p.w1tb[f * kVnH + n] = b;
+    }
+    if (k < 65536u) {
+        const uint32_t n = k / kVnH, i = k % kVnH;
+        const uint16_t b = bf16_bits(p.master[kOffW2 + k]);
+        p.w2b[k] = b;
+        p.w2tb[i * kVnH + n] = b;
+    }
+    if (k < 256u) p.w3b[k] = bf16_bits(p.master[kOffW3 + k]);
+}
+
+// ---------------------------------------------------------------------------
+// features of one row as bfloat16 bits, 8 consecutive features per call
+// ---------------------------------------------------------------------------
+struct RowFeat {
+    uint32_t rel[4];   // tiles owned by the seat (q + k) mod P
+    uint32_t rev, pool, tomove;  // tomove = (mover - q) mod P
+    bool ok;
+};
+
+__device__ __forceinline__ RowFeat row_features(uint4 st, uint32_t q)
+{
+    State s;
+    RowFeat r;
+    r.ok = decode(st.x, st.y, st.z, st.w, s) && q < s.P;
+    const uint32_t qq = q < s.P ? q : 0u;
+#pragma unroll
+    for (uint32_t k = 0; k < 4u; ++k) {
+        const uint32_t seat = qq + k >= s.P ? qq + k - s.P : qq + k;
+        r.rel[k] = k < s.P ? hand_of(s, seat) : 0u;
+    }
+    r.rev = s.rev;
+    r.pool = ~(s.h0 | s.h1 | s.h2 | s.h3) & kAll;
+    r.tomove = s.m >= qq ? s.m - qq : s.m + s.P - qq;
+    return r;
+}
+
+__device__ __forceinline__ uint32_t feature_bit(const RowFeat &r, uint32_t f)
+{
+    if (f < 144u) {
+        const uint32_t t = f / 6u, kind = f - t * 6u;
+        const uint32_t mask = kind == 0u ? r.rel[0] : kind == 1u ? r.rel[1] : kind == 2u ? r.rel[2]
+                            : kind == 3u ? r.rel[3] : kind == 4u ? r.rev : r.pool;
+        return (mask >> t) & 1u;
+    }
+    if (f < 148u) return (f - 144u) == r.tomove ? 1u : 0u;
+    return 0u;
+}
+
+__device__ __forceinline__ bf16x8 feature8(const RowFeat &r, uint32_t f0)
+{
+    bf16x8 x;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) x[i] = feature_bit(r, f0 + (uint32_t)i) ? (__bf16)1.0f : (__bf16)0.0f;
+    return x;
+}
+
+__device__ __forceinline__ bf16x8 load8(const uint16_t *p)
+{
+    const uint4 u = *reinterpret_cast<const uint4 *>(p);
+    bf16x8 x;
+    __builtin_memcpy(&x, &u, 16);
+    return x;
+}
+
+__device__ __forceinline__ floatx4 mfma16(bf16x8 a, bf16x8 b, floatx4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------------------
+// forward (and, when training, data backward) for 16 rows per wavefront.
+// Operand layouts of the 16x16x32 product (lane l, r = l%16, g = l/16):
+//   A[r][8g..8g+7], B[8g..8g+7][r] (8 consecutive k of one column), and
+//   D[4g+i][r] for i < 4.
+// ---------------------------------------------------------------------------
+struct VnRowsArgs {
+    const void *net;
+    const uint4 *states;
+    const uint8_t *persp;
+    const float *labels;
+    uint32_t n_rows;          // rows in this launch
+    uint32_t n_data, perm_a, perm_b, row_base;   // training: row i is data[(a*(base+i)+b) % n_data]
+    float *v_out;             // inference output (or null)
+    // training outputs (feature-major, rows contiguous), bf16
+    uint16_t *xt, *h1t, *dh1t, *dh2t;
+    float *part;              // per wave: [loss, db3, dw3[256], db2[256], db1[256]]
+    float inv_batch;
+};
+
+constexpr uint32_t kPartWords = 2u + 3u * 256u;   // loss, db3, dw3[256], db2[256], db1[256]
+
+template <bool TRAIN>
+__global__ void __launch_bounds__(64) vn_rows_kernel(VnRowsArgs a)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t hs[16][kVnH + 8];   // h1, then dh2 tile (bf16)
+    const VnPtrs P = vn_ptrs(const_cast<void *>(a.net));
+    const uint32_t lane = threadIdx.x, r = lane & 15u, g = lane >> 4;
+    const uint32_t row0 = blockIdx.x * 16u;
+    const uint32_t myrow = row0 + r;
+    const bool has = myrow < a.n_rows;
+    uint32_t src = myrow;
+    if (TRAIN && has) src = (uint32_t)(((uint64_t)a.perm_a * (a.row_base + myrow) + a.perm_b) % a.n_data);
+    RowFeat rf;
+    if (has) {
+        rf = row_features(a.states[src], a.persp[src]);
+    } else {
+        rf.ok = false;
+    }
+    if (has && !rf.ok) atomicOr(&g_error_word, kErrState);
+    if (!rf.ok) {
+        rf.rel[0] = rf.rel[1] = rf.rel[2] = rf.rel[3] = 0u;
+        rf.rev = rf.pool = 0u;
+        rf.tomove = 7u;
+    }
+
+    // ---- layer 1: h1 = bf16(relu(W1 x + b1)) -------------------------------
+    bf16x8 xa[5];
+#pragma unroll
+    for (uint32_t s = 0; s < 5u; ++s) xa[s] = feature8(rf, 32u * s + 8u * g);
+    if (TRAIN) {
+        // X^T for the weight gradient: feature-major, rows contiguous
+#pragma unroll
+        for (uint32_t s = 0; s < 5u; ++s)
+#pragma unroll
+            for (uint32_t i = 0; i < 8u; ++i)
+                if (has) a.xt[(size_t)(32u * s + 8u * g + i) * a.n_rows + myrow] =
+                    __builtin_bit_cast(uint16_t, xa[s][i]);
+    }
+    uint64_t h1pos = 0ull;   // bit 4j+i: h1 of row 4g+i, column 16j+r is positive
+#pragma unroll 4
+    for (uint32_t j = 0; j < 16u; ++j) {
+        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        const uint16_t *wrow = P.w1b + (size_t)(16u * j + r) * kVnIn + 8u * g;
+#pragma unroll
+        for (uint32_t s = 0; s < 5u; ++s) acc = mfma16(xa[s], load8(wrow + 32u * s), acc);
+        const float b = P.master[kOffB1 + 16u * j + r];
+        uint16_t hq[4];
+#pragma unroll
+        for (uint32_t i = 0; i < 4u; ++i) {
+            const float h = acc[i] + b;
+            hq[i] = bf16_bits(h > 0.0f ? h : 0.0f);
+            hs[4u * g + i][16u * j + r] = hq[i];
+            h1pos |= (uint64_t)(h > 0.0f) << (4u * j + i);
+        }
+        if (TRAIN) {
+            const uint32_t rr = row0 + 4u * g;
+            if (rr + 3u < a.n_rows) {
+                const uint2 packed = make_uint2((uint32_t)hq[0] | ((uint32_t)hq[1] << 16),
+                                                (uint32_t)hq[2] | ((uint32_t)hq[3] << 16));
+                *reinterpret_cast<uint2 *>(a.h1t + (size_t)(16u * j + r) * a.n_rows + rr) = packed;
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- layer 2: h2 = bf16(relu(W2 h1 + b2)) ------------------------------
+    bf16x8 ha[8];
+#pragma unroll
+    for (uint32_t s = 0; s < 8u; ++s) ha[s] = load8(&hs[r][32u * s + 8u * g]);
+    floatx4 h2[16];
+    float zpart[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (uint32_t j = 0; j < 16u; ++j) {
+        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        const uint16_t *wrow = P.w2b + (size_t)(16u * j + r) * kVnH + 8u * g;
+#pragma unroll
+        for (uint32_t s = 0; s < 8u; ++s) acc = mfma16(ha[s], load8(wrow + 32u * s), acc);
+        const float b = P.master[kOffB2 + 16u * j + r];
+        const float w3 = bf16_to_f(P.w3b[16u * j + r]);
+#pragma unroll
+        for (uint32_t i = 0; i < 4u; ++i) {
+            const float h = acc[i] + b;
+            h2[j][i] = bf16_round(h > 0.0f ? h : 0.0f);
+            zpart[i] += h2[j][i] * w3;
+        }
+    }
+    // sum the 16 columns held by the lanes of one row group
+#pragma unroll
+    for (uint32_t i = 0; i < 4u; ++i)
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) zpart[i] += __shfl_xor(zpart[i], off, 64);
+    const float b3 = P.master[kOffB3];
+    float v4[4];
+#pragma unroll
+    for (uint32_t i = 0; i < 4u; ++i) v4[i] = 1.0f / (1.0f + expf(-(zpart[i] + b3)));
+    if (!TRAIN) {
+        if (r == 0u && a.v_out) {
+#pragma unroll
+            for (uint32_t i = 0; i < 4u; ++i) {
+                const uint32_t row = row0 + 4u * g + i;
+                if (row < a.n_rows) a.v_out[row] = v4[i];
+            }
+        }
+        return;
+    }
+
+    // ---- training: loss, dz, dh2, layer-2 data backward -----------------------
+    // labels of rows 4g+i (each lane of a group computes the same values)
+    float dz[4], err2 = 0.0f;
+#pragma unroll
+    for (uint32_t i = 0; i < 4u; ++i) {
+        const uint32_t row = row0 + 4u * g + i;
+        float y = 0.0f, d = 0.0f;
+        if (row < a.n_rows) {
+            const uint32_t sr = (uint32_t)(((uint64_t)a.perm_a * (a.row_base + row) + a.perm_b) % a.n_data);
+            y = a.labels[sr];
+            const float e = v4[i] - y;
+            err2 += e * e;
+            d = 2.0f * e * a.inv_batch * v4[i] * (1.0f - v4[i]);
+        }
+        dz[i] = d;
+    }
+    float *part = a.part + (size_t)blockIdx.x * kPartWords;
+    // loss and db3: one lane per row group, then across the four groups
+    float l4 = r == 0u ? err2 : 0.0f, d3 = r == 0u ? dz[0] + dz[1] + dz[2] + dz[3] : 0.0f;
+    for (int off = 1; off < 64; off <<= 1) {
+        l4 += __shfl_xor(l4, off, 64);
+        d3 += __shfl_xor(d3, off, 64);
+    }
+    if (lane == 0) {
+        part[0] = l4;
+        part[1] = d3;
+    }
+    __syncthreads();   // all lanes are done reading h1 from hs
+#pragma unroll
+    for (uint32_t j = 0; j < 16u; ++j) {
+        const uint32_t col = 16u * j + r;
+        const float w3 = bf16_to_f(P.w3b[col]);
+        float dw3 = 0.0f, db2 = 0.0f;
+        uint16_t dq[4];
+#pragma unroll
+        for (uint32_t i = 0; i < 4u; ++i) {
+            dw3 += dz[i] * h2[j][i];
+            const float d = h2[j][i] > 0.0f ? dz[i] * w3 : 0.0f;
+            dq[i] = bf16_bits(d);
+            db2 += bf16_to_f(dq[i]);
+            hs[4u * g + i][col] = dq[i];
+        }
+        // dh2^T rows contiguous: four rows of one column per lane
+        const uint32_t rr = row0 + 4u * g;
+        if (rr + 3u < a.n_rows) {
+            const uint2 packed = make_uint2((uint32_t)dq[0] | ((uint32_t)dq[1] << 16),
+                                            (uint32_t)dq[2] | ((uint32_t)dq[3] << 16));
+            *reinterpret_cast<uint2 *>(a.dh2t + (size_t)col * a.n_rows + rr) = packed;
+        }
+        dw3 += __shfl_xor(dw3, 16, 64);
+        dw3 += __shfl_xor(dw3, 32, 64);
+        db2 += __shfl_xor(db2, 16, 64);
+        db2 += __shfl_xor(db2, 32, 64);
+        if (g == 0u) {
+            part[2u + col] = dw3;
+            part[2u + 256u + col] = db2;
+        }
+    }
+    __syncthreads();
+    // dh1 = (dh2 W2) * (h1 > 0): A = dh2 rows from LDS, B from W2 transposed
+    bf16x8 da[8];
+#pragma unroll
+    for (uint32_t s = 0; s < 8u; ++s) da[s] = load8(&hs[r][32u * s + 8u * g]);
+#pragma unroll 4
+    for (uint32_t j = 0; j < 16u; ++j) {
+        const uint32_t col = 16u * j + r;
+        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        const uint16_t *wrow = P.w2tb + (size_t)col * kVnH + 8u * g;
+#pragma unroll
+        for (uint32_t s = 0; s < 8u; ++s) acc = mfma16(da[s], load8(wrow + 32u * s), acc);
+        float db1 = 0.0f;
+        uint16_t dq[4];
+#pragma unroll
+        for (uint32_t i = 0; i < 4u; ++i) {
+            const float d = ((h1pos >> (4u * j + i)) & 1ull) ? acc[i] : 0.0f;
+            dq[i] = bf16_bits(d);
+            db1 += bf16_to_f(dq[i]);
+        }
+        const uint32_t rr = row0 + 4u * g;
+        if (rr + 3u < a.n_rows) {
+            const uint2 packed = make_uint2((uint32_t)dq[0] | ((uint32_t)dq[1] << 16),
+                                            (uint32_t)dq[2] | ((uint32_t)dq[3] << 16));
+            *reinterpret_cast<uint2 *>(a.dh1t + (size_t)col * a.n_rows + rr) = packed;
+        }
+        db1 += __shfl_xor(db1, 16, 64);
+        db1 += __shfl_xor(db1, 32, 64);
+        if (g == 0u) part[2u + 512u + col] = db1;
+    }
+}
+
+// Weight gradient C[m][n] = sum_k AT[m][k] BT[n][k] over the batch (k), one
+// 16x16 output tile per wavefront; AT, BT feature-major with rows contiguous.
+__global__ void __launch_bounds__(64) vn_wgrad_kernel(const uint16_t *at, const uint16_t *bt,
+                                                       uint32_t K, float *out, uint32_t ldo,
+                                                       uint32_t ntiles)
+{
+    const uint32_t lane = threadIdx.x, r = lane & 15u, g = lane >> 4;
+    const uint32_t mt = blockIdx.x / ntiles, nt = blockIdx.x % ntiles;
+    const uint16_t *ap = at + (size_t)(16u * mt + r) * K + 8u * g;
+    const uint16_t *bp = bt + (size_t)(16u * nt + r) * K + 8u * g;
+    floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 4
+    for (uint32_t k0 = 0; k0 < K; k0 += 32u) acc = mfma16(load8(ap + k0), load8(bp + k0), acc);
+#pragma unroll
+    for (uint32_t i = 0; i < 4u; ++i) out[(size_t)(16u * mt + 4u * g + i) * ldo + 16u * nt + r] = acc[i];
+}
+
+// Adam (Kingma and Ba, 2015) on the float32 master weights; bias gradients
+// are summed here over the per-wavefront partials in wavefront order; the
+// bf16 shadows of the updated weights are refreshed in the same pass.
+__global__ void vn_adam_kernel(void *net, const float *grad, const float *part, uint32_t n_parts,
+                               float lr, float beta1, float beta2, float eps, float c1, float c2,
+                               float inv_batch, float *grad_out, float *loss_out)
+{
+    VnPtrs P = vn_ptrs(net);
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k == 0u && loss_out) {
+        float l = 0.0f;
+        for (uint32_t w = 0; w < n_parts; ++w) l += part[(size_t)w * kPartWords];
+        *loss_out = l * inv_batch;
+    }
+    if (k >= kVnParams) return;
+    float gk;
+    if (k < kOffB1 || (k >= kOffW2 && k < kOffB2)) {
+        gk = grad[k];
+    } else {
+        const uint32_t idx = k == kOffB3 ? 1u
+                           : k >= kOffW3 ? 2u + (k - kOffW3)
+                           : k >= kOffB2 ? 2u + 256u + (k - kOffB2)
+                                         : 2u + 512u + (k - kOffB1);
+        gk = 0.0f;
+        for (uint32_t w = 0; w < n_parts; ++w) gk += part[(size_t)w * kPartWords + idx];
+    }
+    if (grad_out) grad_out[k] = gk;
+    const float m = beta1 * P.m[k] + (1.0f - beta1) * gk;
+    const float v = beta2 * P.v[k] + (1.0f - beta2) * gk * gk;
+    P.m[k] = m;
+    P.v[k] = v;
+    const float w = P.master[k] - lr * (m / c1) / (sqrtf(v / c2) + eps);
+    P.master[k] = w;
+    const uint16_t b = bf16_bits(w);
+    if (k < kOffB1) {
+        const uint32_t n = k / kVnIn, f = k % kVnIn;
+        P.w1b[k] = b;
+        P.w1tb[f * kVnH + n] = b;
+    } else if (k >= kOffW2 && k < kOffB2) {
+        const uint32_t kk = k - kOffW2, n = kk / kVnH, i = kk % kVnH;
+        P.w2b[kk] = b;
+        P.w2tb[i * kVnH + n] = b;
+    } else if (k >= kOffW3 && k < kOffB3) {
+        P.w3b[k - kOffW3] = b;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+size_t vn_bytes() { return (size_t)kVnBytes; }
+
+size_t vn_train_ws_bytes(uint32_t batch)
+{
+    // xt[160][B], h1t, dh1t, dh2t [256][B] bf16; grad[NPAD] fp32; partials
+    return (size_t)batch * (160u + 3u * 256u) * 2u + (size_t)kVnPad * 4u +
+           (size_t)((batch + 15u) / 16u) * kPartWords * 4u + 256u;
+}
+
+hipError_t launch_vn_init(void *net, uint32_t k0, uint32_t k1, hipStream_t st)
+{
+    const float bw1 = sqrtf(6.0f / 148.0f), bw2 = sqrtf(6.0f / 256.0f), bw3 = 1.0f / 16.0f;
+    hipLaunchKernelGGL(vn_init_kernel, dim3((kVnPad + 255u) / 256u), dim3(256), 0, st, net, k0, k1,
+                       bw1, bw2, bw3);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(vn_shadow_kernel, dim3(65536u / 256u), dim3(256), 0, st, net);
+    return hipGetLastError();
+}
+
+hipError_t launch_vn_shadow(void *net, hipStream_t st)
+{
+    hipLaunchKernelGGL(vn_shadow_kernel, dim3(65536u / 256u), dim3(256), 0, st, net);
+    return hipGetLastError();
+}
+
+hipError_t launch_vn_infer(const void *net, const uint4 *states, const uint8_t *persp, uint32_t n,
+                           float *v_out, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    VnRowsArgs a = {};
+    a.net = net;
+    a.states = states;
+    a.persp = persp;
+    a.n_rows = n;
+    a.v_out = v_out;
+    hipLaunchKernelGGL(vn_rows_kernel<false>, dim3((n + 15u) / 16u), dim3(64), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_vn_train_step(void *net, const uint4 *states, const uint8_t *persp,
+                                const float *labels, uint32_t n_data, uint32_t perm_a,
+                                uint32_t perm_b, uint32_t row_base, uint32_t batch, float lr,
+                                float c1, float c2, void *ws, float *loss_out, float *grad_out,
+                                hipStream_t st)
+{
+    uint8_t *w = (uint8_t *)ws;
+    VnRowsArgs a = {};
+    a.net = net;
+    a.states = states;
+    a.persp = persp;
+    a.labels = labels;
+    a.n_rows = batch;
+    a.n_data = n_data;
+    a.perm_a = perm_a;
+    a.perm_b = perm_b;
+    a.row_base = row_base;
+    a.xt = (uint16_t *)w;
+    a.h1t = a.xt + (size_t)160u * batch;
+    a.dh1t = a.h1t + (size_t)256u * batch;
+    a.dh2t = a.dh1t + (size_t)256u * batch;
+    float *grad = (float *)(a.dh2t + (size_t)256u * batch);
+    a.part = grad + kVnPad;
+    a.inv_batch = 1.0f / (float)batch;
+    const uint32_t waves = batch / 16u;
+    hipLaunchKernelGGL(vn_rows_kernel<true>, dim3(waves), dim3(64), 0, st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // dW2 = dh2^T h1 (256 x 256), dW1 = dh1^T x (256 x 160)
+    hipLaunchKernelGGL(vn_wgrad_kernel, dim3(16u * 16u), dim3(64), 0, st, a.dh2t, a.h1t, batch,
+                       grad + kOffW2, 256u, 16u);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(vn_wgrad_kernel, dim3(16u * 10u), dim3(64), 0, st, a.dh1t, a.xt, batch,
+                       grad + kOffW1, 160u, 10u);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(vn_adam_kernel, dim3((kVnParams + 255u) / 256u), dim3(256), 0, st, net, grad,
+                       a.part, waves, lr, 0.9f, 0.999f, 1e-8f, c1, c2, a.inv_batch, grad_out,
+                       loss_out);
+    return hipGetLastError();
+}
+
+__global__ void vn_set_params_kernel(void *net, const float *params)
+{
+    VnPtrs P = vn_ptrs(net);
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= kVnPad) return;
+    P.master[k] = k < kVnParams ? params[k] : 0.0f;
+    P.m[k] = 0.0f;
+    P.v[k] = 0.0f;
+}
+
+__global__ void vn_get_params_kernel(const void *net, float *params)
+{
+    const VnPtrs P = vn_ptrs(const_cast<void *>(net));
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < kVnParams) params[k] = P.master[k];
+}
+
+// perspective of a training pair and its playout win-rate label
+__global__ void vn_labels_kernel(const uint4 *states, uint32_t n, uint32_t playouts, uint32_t k0,
+                                 uint32_t k1, uint32_t base, const uint32_t *seat_wins,
+                                 uint8_t *persp, float *labels)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t P = ((states[i].x >> 26) & 3u) + 1u;
+    const Words w = philox(0u, 0xFFFFFFFCu, 0u, base + i, k0, k1);
+    const uint32_t q = pick(w.w0, P);
+    persp[i] = (uint8_t)q;
+    labels[i] = (float)seat_wins[(size_t)i * 4u + q] / (float)playouts;
+}
+
+hipError_t launch_vn_set_params(void *net, const float *params, hipStream_t st)
+{
+    hipLaunchKernelGGL(vn_set_params_kernel, dim3((kVnPad + 255u) / 256u), dim3(256), 0, st, net,
+                       params);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_vn_shadow(net, st);
+}
+
+hipError_t launch_vn_get_params(const void *net, float *params, hipStream_t st)
+{
+    hipLaunchKernelGGL(vn_get_params_kernel, dim3((kVnParams + 255u) / 256u), dim3(256), 0, st, net,
+                       params);
+    return hipGetLastError();
+}
+
+hipError_t launch_vn_labels(const uint4 *states, uint32_t n, uint32_t playouts, uint32_t k0,
+                            uint32_t k1, uint32_t index_base, const uint32_t *seat_wins,
+                            uint8_t *persp, float *labels, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(vn_labels_kernel, dim3((n + 255u) / 256u), dim3(256), 0, st, states, n,
+                       playouts, k0, k1, index_base, seat_wins, persp, labels);
+    return hipGetLastError();
+}
+
+}  // namespace dvc

@@ -1,0 +1,140 @@
+"""GPU value network vs the oracle (through the C ABI).
+
+Bar: tolerance (the products run in bfloat16 on the matrix cores with
+float32 accumulation in a hardware order the oracle does not reproduce).
+* initialization: bit-exact float32 parameters (same Philox words);
+* inference vs the oracle's bf16-mirroring forward: |dv| <= 2^-7 |v| + 1e-3;
+* the gradient of one training step vs the oracle's bf16-mirroring gradient:
+  cosine >= 0.999 overall and per block, magnitudes within 5%;
+* Adam: the GPU step equals the oracle's Adam applied to the GPU's own
+  gradient (float32 vs double, 1e-5 relative);
+* training pairs: perspectives and labels bit-exact vs oracle playouts;
+* a few hundred steps on one batch drive its loss down (overfit check).
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dvc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2403_10720_amd as D
+    D.lib()
+    return D
+
+
+def _data(orc, n, seed):
+    dp = orc.deal_params(p_min=2, p_max=4, pile_min=0, pile_max=16, revealed_max=8, phase_mix=1)
+    S = orc.init_states(n, dp, seed=seed)
+    rng = np.random.default_rng(seed)
+    q = np.array([rng.integers(0, orc.unpack(s)["P"]) for s in S], np.uint8)
+    y = rng.random(n).astype(np.float32)
+    return S, q, y
+
+
+def _dev(S, q, y):
+    return (torch.from_numpy(S.view(np.int32)).cuda(), torch.from_numpy(q).cuda(),
+            torch.from_numpy(y).cuda())
+
+
+def test_init_bit_exact(orc, dvc):
+    net = dvc.dvc_valuenet_init(44)
+    got = dvc.dvc_valuenet_get_params(net).cpu().numpy()
+    ref = orc.vn_init(44)
+    assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
+
+
+@pytest.mark.parametrize("n", [1, 15, 16, 100, 1000])
+def test_infer_vs_oracle(orc, dvc, n):
+    S, q, y = _data(orc, n, 7 + n)
+    params = orc.vn_init(3)
+    net = dvc.dvc_valuenet_init(0)
+    dvc.dvc_valuenet_set_params(net, torch.from_numpy(params).cuda())
+    st, qd, _ = _dev(S, q, y)
+    v = dvc.dvc_valuenet_infer(net, st, qd).cpu().numpy()
+    ref = orc.vn_forward(params, S, q.astype(np.int32), bf16_mirror=True)
+    assert np.all(np.abs(v - ref) <= 2.0 ** -7 * np.abs(ref) + 1e-3), np.abs(v - ref).max()
+    assert dvc.dvc_check() == 0
+
+
+def test_gradient_vs_oracle(orc, dvc):
+    B = 256
+    S, q, y = _data(orc, B, 11)
+    params = orc.vn_init(5)
+    net = dvc.dvc_valuenet_init(0)
+    dvc.dvc_valuenet_set_params(net, torch.from_numpy(params).cuda())
+    st, qd, yd = _dev(S, q, y)
+    grad = torch.zeros(dvc.VALUENET_PARAMS, dtype=torch.float32, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    dvc.dvc_valuenet_train_step(net, st, qd, yd, step=1, lr=1e-3, batch=B, grad_out=grad,
+                                loss_out=loss)
+    g = grad.cpu().numpy().astype(np.float64)
+    ref_loss, ref = orc.vn_loss_grad(params, S, q.astype(np.int32), y, bf16_mirror=True)
+    assert abs(float(loss.item()) - ref_loss) <= 1e-3 * ref_loss + 1e-6
+    cos = g @ ref / (np.linalg.norm(g) * np.linalg.norm(ref))
+    assert cos >= 0.999, cos
+    blocks = {"W1": (0, 40960), "b1": (40960, 41216), "W2": (41216, 106752),
+              "b2": (106752, 107008), "w3": (107008, 107264)}
+    for name, (lo, hi) in blocks.items():
+        a, b = g[lo:hi], ref[lo:hi]
+        c = a @ b / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-30)
+        assert c >= 0.999, (name, c)
+        assert abs(np.linalg.norm(a) / np.linalg.norm(b) - 1) < 0.05, name
+    assert abs(g[107264] - ref[107264]) <= 1e-3 * abs(ref[107264]) + 1e-7
+    # Adam step: compare the updated parameters with the oracle's Adam on g
+    got = dvc.dvc_valuenet_get_params(net).cpu().numpy().astype(np.float64)
+    w = params.astype(np.float64).copy()
+    m = np.zeros_like(w)
+    v = np.zeros_like(w)
+    orc.vn_adam(w, m, v, g.copy(), 1, lr=1e-3)
+    assert np.allclose(got, w, rtol=1e-5, atol=1e-7)
+
+
+def test_labels_bit_exact(orc, dvc):
+    n, ppl, seed = 300, 64, 9
+    dp = orc.deal_params(p_min=2, p_max=4, pile_min=0, pile_max=16, revealed_max=8, phase_mix=1)
+    S = orc.init_states(n, dp, seed=seed, index_base=1000)
+    st = torch.from_numpy(S.view(np.int32)).cuda()
+    persp, labels = dvc.dvc_valuenet_labels(st, ppl, seed, tree_id=1, index_base=1000)
+    _, _, wins = orc.rollout(S, ppl, seed, tree_id=1, leaf_id_base=1000)
+    for i in range(n):
+        P = orc.unpack(S[i])["P"]
+        w = orc.philox([0, 0xFFFFFFFC, 0, 1000 + i], [seed, 0])[0]
+        q = orc.mulshift(int(w), P)
+        assert persp[i].item() == q
+        assert labels[i].item() == np.float32(wins[i, q]) / np.float32(ppl)
+
+
+def test_overfit_one_batch(orc, dvc):
+    B = 512
+    S, q, y = _data(orc, B, 13)
+    st, qd, yd = _dev(S, q, y)
+    net = dvc.dvc_valuenet_init(44)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    ws = None
+    hist = []
+    for step in range(1, 401):
+        ws = dvc.dvc_valuenet_train_step(net, st, qd, yd, step=step, lr=3e-3, batch=B, ws=ws,
+                                         loss_out=loss)
+        if step in (1, 400):
+            hist.append(float(loss.item()))
+    assert hist[1] < 0.25 * hist[0], hist
+    assert dvc.dvc_check() == 0
+
+
+def test_argument_errors(dvc):
+    net = dvc.dvc_valuenet_init(1)
+    st = torch.zeros((40, 4), dtype=torch.int32, device="cuda")
+    q = torch.zeros(40, dtype=torch.uint8, device="cuda")
+    y = torch.zeros(40, dtype=torch.float32, device="cuda")
+    with pytest.raises(dvc.DvcError):
+        dvc.dvc_valuenet_train_step(net, st, q, y, step=1, batch=40)   # not a multiple of 32
+    with pytest.raises(dvc.DvcError):
+        dvc.dvc_valuenet_train_step(net, st, q, y, step=0, batch=32)
