@@ -28,10 +28,12 @@ DEAL = dict(p_min=2, p_max=2, pile_min=0, pile_max=16, revealed_max=8)
 
 # Peak integer VALU issue rate of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 INT_VALU_PEAK = 256 * 4 * 16 * 2.4e9          # lane-ops/s
-# One guess step of the rollout kernel as compiled for gfx950:
-# 315 VALU instructions, 20 of them quarter-rate 32x32->64 multiplies, which
-# occupy four issue slots each.
-OPS_PER_GUESS = 315 + 3 * 20
+# Algorithmic integer operations of one guess step: one Philox4x32-10 block
+# (20 32x32->64 multiplies, 40 xors, 18 key adds = 78), four uniform picks
+# (4 high multiplies), four bit counts, three k-th-set-bit selections
+# (about 30 operations each as a bit-count search) and about 24 mask
+# operations on the 24-bit rows: ~200 lane-operations per guess.
+OPS_PER_GUESS = 200
 
 
 def parse():
@@ -43,7 +45,52 @@ def parse():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-search", action="store_true", help="skip the tree-search figures")
     return ap.parse_args()
+
+
+SEARCH_DEAL = dict(p_min=2, p_max=4, hand=(0, 0, 4, 4, 3), pile_min=0, pile_max=16,
+                   revealed_max=8, root_draw=1)
+
+
+def batched_search(D, torch, reps=3):
+    """Batched search: 2048 mixed 2/3/4-player roots, 1024 iterations x 32 playouts,
+    depth 4, one launch; decisions/s from HIP events."""
+    n, iters, ppl = 2048, 1024, 32
+    roots = D.dvc_init_states(n, D.deal_params(**SEARCH_DEAL), 3)
+    mp = D.mcts_params(iterations=iters, playouts_per_leaf=ppl, max_depth=4)
+    ws = torch.empty(D.dvc_mcts_workspace_bytes(n, mp), dtype=torch.uint8, device=roots.device)
+    D.mcts_search(roots, mp, 3, workspace=ws, want_children=False)
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        D.mcts_search(roots, mp, 3, workspace=ws, want_children=False)
+        e1.record()
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    best = min(ms)
+    return {"workload": "2048 trees (2-4 players, mid-game, root draw) x 1024 iterations x 32 "
+                        "playouts, depth 4", "ms_per_launch": best,
+            "decisions_per_s": n / (best / 1e3), "playouts_per_s": n * iters * ppl / (best / 1e3)}
+
+
+def single_tree_search(D, torch):
+    """Plain search: one fresh two-player deal, 2000 iterations x 16 playouts."""
+    roots = D.dvc_init_states(1, D.deal_params(p_min=2, p_max=2, fresh=1, root_draw=1), 1)
+    mp = D.mcts_params(iterations=2000, playouts_per_leaf=16, max_depth=4)
+    ws = torch.empty(D.dvc_mcts_workspace_bytes(1, mp), dtype=torch.uint8, device=roots.device)
+    D.mcts_search(roots, mp, 1, workspace=ws, want_children=False)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    D.mcts_search(roots, mp, 1, workspace=ws, want_children=False)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    return {"workload": "1 tree, fresh 2-player deal, 2000 iterations x 16 playouts",
+            "ms_per_decision": ms, "decisions_per_s": 1e3 / ms}
 
 
 def cpu_baseline(states_np, threads):
@@ -141,6 +188,9 @@ def main():
         "mean_game_length": float(lens.mean().item()),
         "wall_s": wall,
     }
+    if not args.no_search:
+        out["batched_search"] = batched_search(D, torch)
+        out["single_tree_search"] = single_tree_search(D, torch)
     if not args.no_cpu:
         threads = max(1, min(16, os.cpu_count() or 1))
         out["cpu_baseline"] = cpu_baseline(states.cpu().numpy().view(np.uint32), threads)

@@ -162,6 +162,11 @@ int dvc_rollout_ex(const dvc_state_t *leaves, int64_t n_leaves, int32_t playouts
  *      leaf counts all of them as won by its winner);
  *   4. every node on the path: N += playouts; every non-root node:
  *      W += wins of the seat that chose its action.
+ * Value mode (leaf_eval = 1): step 3 evaluates the leaf with the value
+ * network for every seat's perspective; if the root player's value v_M has
+ * |v_M - 1/2| < fallback_band the leaf is played out with fallback_playouts
+ * playouts instead.  Every leaf then weighs w = fallback_playouts: N += w and
+ * W += wins of the chooser (playouts) or w * v_chooser (network).
  * Decision: the root child with the most visits, earliest created on ties.
  * ------------------------------------------------------------------------- */
 typedef struct {

@@ -124,12 +124,18 @@ def deal_params(p_min=2, p_max=2, hand=(0, 0, 4, 4, 3), pile_min=0, pile_max=16,
 
 
 def mcts_params(iterations=2000, playouts_per_leaf=16, max_depth=4, c_uct=None, leaf_eval=0,
-                fallback_band=0.05, fallback_playouts=64) -> MctsParams:
+                fallback_band=0.05, fallback_playouts=64, valuenet=None) -> MctsParams:
+    """valuenet: float32 numpy array of the network parameters (value mode);
+    the caller keeps it alive while the search runs."""
     m = MctsParams()
     m.iterations, m.playouts_per_leaf, m.max_depth = iterations, playouts_per_leaf, max_depth
     m.c_uct = float(np.float32(np.sqrt(2.0))) if c_uct is None else c_uct
     m.leaf_eval, m.fallback_band, m.fallback_playouts = leaf_eval, fallback_band, fallback_playouts
-    m.valuenet = None
+    if valuenet is not None:
+        assert valuenet.dtype == np.float32 and valuenet.flags.c_contiguous
+        m.valuenet = valuenet.ctypes.data
+    else:
+        m.valuenet = None
     return m
 
 

@@ -429,13 +429,39 @@ static void tree_free(otree *t)
 int rollout_rows_wins(const orc_rows *leaf, int32_t ppl, uint64_t seed, uint32_t leaf_id,
                       uint32_t tree_id, uint32_t wins[4]);
 
+/* Leaf evaluation in value mode: the network's win probability of every
+ * seat (bf16-mirroring forward); when the root player's value lies within
+ * `band` of 1/2 the leaf is played out instead.  Either way the leaf weighs
+ * `fallback_playouts`: W gains playout wins, or fallback_playouts * v.    */
+static void value_leaf(const orc_rows *S, int root_mover, const orc_mcts_params *mp, uint64_t seed,
+                       uint32_t leaf_id, uint32_t tr, float vals[4])
+{
+    orc_packed ps;
+    oracle_pack(S, &ps);
+    double v[4] = {0, 0, 0, 0};
+    for (int q = 0; q < S->P; ++q) {
+        int32_t qq = q;
+        oracle_vn_forward((const float *)mp->valuenet, &ps, &qq, 1, 1, &v[q]);
+    }
+    float vm = (float)v[root_mover];
+    float d = vm - 0.5f;
+    if (d < 0.0f) d = -d;
+    if (d < mp->fallback_band) {
+        uint32_t wins[4];
+        rollout_rows_wins(S, mp->fallback_playouts, seed, leaf_id, tr, wins);
+        for (int k = 0; k < 4; ++k) vals[k] = (float)wins[k];
+    } else {
+        for (int k = 0; k < 4; ++k) vals[k] = (float)mp->fallback_playouts * (float)v[k];
+    }
+}
+
 static int search_one(const orc_rows *root, const orc_mcts_params *mp, uint64_t seed,
                       uint32_t tr, const float *LN, int32_t *best_action,
                       orc_child_stat *children_out)
 {
     otree T = {0};
     tree_new_node(&T, -1, -1);
-    int ppl = mp->playouts_per_leaf;
+    int ppl = mp->leaf_eval ? mp->fallback_playouts : mp->playouts_per_leaf;
     int path[64];
     uint8_t legal[ORC_MAX_CHILD];
     for (int i = 0; i < mp->iterations; ++i) {
@@ -482,16 +508,20 @@ static int search_one(const orc_rows *root, const orc_mcts_params *mp, uint64_t 
             path[np++] = best;
             ++depth;
         }
-        uint32_t wins[4] = {0, 0, 0, 0};
+        float vals[4] = {0.0f, 0.0f, 0.0f, 0.0f};
         if (terminal) {
-            wins[winner] = (uint32_t)ppl;
+            vals[winner] = (float)ppl;
+        } else if (mp->leaf_eval) {
+            value_leaf(&S, root->mover, mp, seed, (uint32_t)i, tr, vals);
         } else {
+            uint32_t wins[4] = {0, 0, 0, 0};
             rollout_rows_wins(&S, ppl, seed, (uint32_t)i, tr, wins);
+            for (int k = 0; k < 4; ++k) vals[k] = (float)wins[k];
         }
         for (int k = 0; k < np; ++k) {
             onode *x = &T.v[path[k]];
             x->N += (uint32_t)ppl;
-            if (k > 0) x->W += (float)wins[x->chooser];
+            if (k > 0) x->W += vals[x->chooser];
         }
     }
     onode *R = &T.v[0];
@@ -525,8 +555,9 @@ int oracle_mcts_search(const orc_packed *roots, int64_t n_trees, const orc_mcts_
                        orc_child_stat *root_children)
 {
     if (n_trees < 0 || mp->iterations < 1 || mp->playouts_per_leaf < 1 || mp->max_depth < 1 ||
-        mp->max_depth > 32 || mp->leaf_eval != 0)
+        mp->max_depth > 32 || mp->leaf_eval < 0 || mp->leaf_eval > 1)
         return -1;
+    if (mp->leaf_eval && (mp->valuenet == NULL || mp->fallback_playouts < 1)) return -1;
     for (int64_t t = 0; t < n_trees; ++t) {
         if (oracle_validate(&roots[t])) return -2;
         orc_rows r;
@@ -534,7 +565,8 @@ int oracle_mcts_search(const orc_packed *roots, int64_t n_trees, const orc_mcts_
         if (alive_count(&r) < 2) return -2;
         if (r.phase == 0 && r.pile_n > 0) return -2;
     }
-    uint64_t nln = (uint64_t)mp->iterations * (uint64_t)mp->playouts_per_leaf + 1;
+    uint64_t w_leaf = (uint64_t)(mp->leaf_eval ? mp->fallback_playouts : mp->playouts_per_leaf);
+    uint64_t nln = (uint64_t)mp->iterations * w_leaf + 1;
     float *LN = (float *)malloc(nln * sizeof(float));
     LN[0] = 0.0f;
     for (uint64_t k = 1; k < nln; ++k) LN[k] = oracle_ln_entry((uint32_t)k);

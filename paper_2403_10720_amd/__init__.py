@@ -203,6 +203,15 @@ def mcts_search(roots: torch.Tensor, params: MctsParams, seed: int, tree_id_base
     return best, kids
 
 
+def mcts_tree_stats(workspace: torch.Tensor, n_trees: int, params: MctsParams) -> dict:
+    """Per-tree counters the search leaves at the start of each tree's workspace."""
+    per_tree = dvc_mcts_workspace_bytes(1, params)
+    w = workspace[:n_trees * per_tree].view(n_trees, per_tree)[:, :32].contiguous().view(torch.int32)
+    w = w.cpu()
+    return {"nodes": w[:, 0], "blocks": w[:, 1], "root_visits": w[:, 2], "net_leaves": w[:, 3],
+            "played_leaves": w[:, 4], "sampler_fallbacks": w[:, 5]}
+
+
 def children_view(kids: torch.Tensor):
     """Split the raw child-statistics tensor into (action, n, w) tensors on the host."""
     k = kids.cpu()

@@ -87,9 +87,13 @@ static bool mcts_params_ok(const dvc_mcts_params *p)
     if (p->iterations < 1 || p->playouts_per_leaf < 1 || p->max_depth < 1 || p->max_depth > 16)
         return false;
     if (!(p->c_uct >= 0.0f) || std::isinf(p->c_uct)) return false;
+    if (p->leaf_eval != 0 && p->leaf_eval != 1) return false;
+    if (p->leaf_eval == 1 && (p->valuenet == nullptr || p->fallback_playouts < 1 ||
+                              !(p->fallback_band >= 0.0f)))
+        return false;
     // visit counts stay exact in float
-    if ((uint64_t)p->iterations * (uint64_t)p->playouts_per_leaf >= (1ull << 24)) return false;
-    if (p->leaf_eval != 0) return false;
+    const uint64_t w_leaf = (uint64_t)(p->leaf_eval ? p->fallback_playouts : p->playouts_per_leaf);
+    if ((uint64_t)p->iterations * w_leaf >= (1ull << 24)) return false;
     return true;
 }
 
@@ -219,7 +223,9 @@ int mcts_search(const dvc_state_t *roots, int64_t n_trees, const dvc_mcts_params
     if (roots == nullptr || best_action == nullptr || workspace == nullptr) return DVC_EINVAL;
     if (workspace_bytes < dvc_mcts_workspace_bytes(n_trees, params)) return DVC_ENOMEM;
     int status = DVC_OK;
-    const uint64_t need = (uint64_t)params->iterations * (uint64_t)params->playouts_per_leaf + 1u;
+    const uint64_t w_leaf =
+        (uint64_t)(params->leaf_eval ? params->fallback_playouts : params->playouts_per_leaf);
+    const uint64_t need = (uint64_t)params->iterations * w_leaf + 1u;
     const float *ln = ln_table(need, &status);
     if (ln == nullptr) return status;
     return status_of(launch_mcts(reinterpret_cast<const uint4 *>(roots), (uint32_t)n_trees,
@@ -228,6 +234,8 @@ int mcts_search(const dvc_state_t *roots, int64_t n_trees, const dvc_mcts_params
                                  (uint32_t)(seed >> 32), tree_id_base, ln,
                                  reinterpret_cast<uint32_t *>(workspace), best_action,
                                  reinterpret_cast<uint32_t *>(root_children),
+                                 (uint32_t)params->leaf_eval, params->fallback_band,
+                                 (uint32_t)params->fallback_playouts, params->valuenet,
                                  (hipStream_t)stream));
 }
 

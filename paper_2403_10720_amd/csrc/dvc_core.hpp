@@ -29,8 +29,9 @@ __device__ __forceinline__ void philox_round(uint32_t &x0, uint32_t &x1, uint32_
 {
     const uint64_t p0 = (uint64_t)x0 * kPhiloxM0;
     const uint64_t p1 = (uint64_t)x2 * kPhiloxM1;
-    const uint32_t y0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
-    const uint32_t y2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+    // three-input xor in one instruction (truth table 0x96)
+    const uint32_t y0 = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), x1, k0, 0x96);
+    const uint32_t y2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), x3, k1, 0x96);
     x1 = (uint32_t)p1;
     x3 = (uint32_t)p0;
     x0 = y0;

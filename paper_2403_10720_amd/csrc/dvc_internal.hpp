@@ -52,6 +52,7 @@ size_t mcts_tree_words(uint32_t iters);
 hipError_t launch_mcts(const uint4 *roots, uint32_t n_trees, uint32_t iters, uint32_t ppl,
                        uint32_t dmax, float c_uct, uint32_t k0, uint32_t k1, uint32_t tree_base,
                        const float *ln, uint32_t *ws, int32_t *best, uint32_t *kids,
+                       uint32_t leaf_eval, float band, uint32_t fb_ppl, const void *net,
                        hipStream_t st);
 size_t vn_bytes();
 size_t vn_train_ws_bytes(uint32_t batch);

@@ -3,6 +3,6 @@
 // by every kernel without relocatable device code.
 #include "rollout.hip"
 #include "gen.hip"
-#include "search.hip"
 #include "valuenet.hip"
+#include "search.hip"
 #include "capi.hip"

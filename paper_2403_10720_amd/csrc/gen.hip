@@ -24,11 +24,17 @@ struct WordStream {
     }
 };
 
-__global__ void __launch_bounds__(256) init_states_kernel(uint4 *out, uint32_t n, DealArgs d,
-                                                          uint32_t k0, uint32_t k1, uint32_t base)
+// One wavefront per workgroup: the per-state work is a serial chain of word
+// draws, so small workgroups spread a batch over as many compute units as
+// possible.
+constexpr uint32_t kGenBlock = 64;
+
+__global__ void __launch_bounds__(kGenBlock) init_states_kernel(uint4 *out, uint32_t n, DealArgs d,
+                                                                uint32_t k0, uint32_t k1,
+                                                                uint32_t base)
 {
-    __shared__ uint8_t scratch_rows[256][24];
-    const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+    __shared__ uint8_t scratch_rows[kGenBlock][24];
+    const uint32_t i = blockIdx.x * kGenBlock + threadIdx.x;
     if (i >= n) return;
     uint8_t *perm = scratch_rows[threadIdx.x];
     WordStream ws{k0, k1, base + i, 0u, Words{0u, 0u, 0u, 0u}};
@@ -105,8 +111,8 @@ hipError_t launch_init_states(uint4 *out, uint32_t n, const DealArgs &d, uint32_
                               uint32_t index_base, hipStream_t st)
 {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(init_states_kernel, dim3((n + 255u) / 256u), dim3(256), 0, st, out, n, d,
-                       k0, k1, index_base);
+    hipLaunchKernelGGL(init_states_kernel, dim3((n + kGenBlock - 1u) / kGenBlock), dim3(kGenBlock), 0,
+                       st, out, n, d, k0, k1, index_base);
     return hipGetLastError();
 }
 

@@ -39,10 +39,12 @@ __device__ __forceinline__ bool guess_step(State &s, const Words &w, uint32_t &w
     const uint32_t v = pick_bit_tab(cand, w.w2, tab);
     const bool right = v == t;
 
-    const uint32_t own_hidden = hm & ~s.rev;
-    const uint32_t r = pick_bit_tab(own_hidden, w.w3, tab);
-    const uint32_t wrong_bit = 1u << (s.drawn >= 0 ? (uint32_t)s.drawn : r);
-    s.rev |= right ? tb : wrong_bit;
+    // a wrong guess reveals the drawn tile; only with nothing drawn (empty
+    // pool) is a random own hidden tile needed, so that search is skipped
+    // by the whole wave in the common case
+    uint32_t wrong_tile = (uint32_t)s.drawn;
+    if (s.drawn < 0) wrong_tile = pick_bit_tab(hm & ~s.rev, w.w3, tab);
+    s.rev |= right ? tb : (1u << (wrong_tile & 31u));
 
     const uint32_t alive = alive_mask(s);
     const bool over = __popc(alive) == 1;

@@ -17,6 +17,9 @@
 //     with a wavefront arg-max (ties to the earliest child);
 //   * the leaf's playouts run one per lane, seat wins are summed by ballots;
 //   * back-propagation updates the path nodes from their own lanes.
+// Per-tree statistics are left in the first words of the tree's workspace:
+// nodes, child blocks, root visits, leaves scored by the network, leaves
+// played out in value mode, iterations that used the sampler's fallback.
 // Tree storage lives in the caller's workspace: a node table (child list
 // head/tail, child count, a bitmap of the actions that already have a child)
 // and blocks of 64 child entries {action | chooser << 16, N, W, node id}, so a
@@ -308,6 +311,11 @@ struct MctsArgs {
     uint32_t nodes_cap, blocks_cap;
     int32_t *best;
     uint32_t *kids;   // [n_trees][864][3] or null
+    // value mode: leaves are scored by the network; a leaf whose value for
+    // the root player is within `band` of 1/2 is played out instead
+    uint32_t leaf_eval, fb_ppl;
+    float band;
+    const void *net;
 };
 
 __device__ __forceinline__ void write_no_children(const MctsArgs &a, uint32_t t, uint32_t lane)
@@ -327,6 +335,7 @@ __global__ void __launch_bounds__(64) mcts_tree_kernel(MctsArgs a)
     __shared__ uint32_t legal_s[72];
     __shared__ uint32_t path_e[kMaxDepthLimit + 1];
     __shared__ DfsSlots dfs_slots;
+    __shared__ __attribute__((aligned(16))) uint16_t vn_tile[16][kVnH + 8];
     fill_kth_table(tab);
     __syncthreads();
     const uint32_t t = blockIdx.x;
@@ -351,6 +360,7 @@ __global__ void __launch_bounds__(64) mcts_tree_kernel(MctsArgs a)
     }
     if (lane < kNodeWords) nodes[lane] = lane < 2u ? kNoBlock : 0u;
     uint32_t n_nodes = 1u, n_blocks = 0u, n_root = 0u;
+    uint32_t n_net = 0u, n_played = 0u, n_sampler_fallback = 0u;   // statistics
     bool failed = false, have_fallback = false;
     State fallback = R;
     __syncthreads();
@@ -378,6 +388,7 @@ __global__ void __launch_bounds__(64) mcts_tree_kernel(MctsArgs a)
                 have_fallback = true;
             }
             S = fallback;
+            ++n_sampler_fallback;
         }
 
         // ---- 2. descend ----------------------------------------------------
@@ -478,19 +489,45 @@ __global__ void __launch_bounds__(64) mcts_tree_kernel(MctsArgs a)
             __syncthreads();
         }
 
-        // ---- 3. playouts from the leaf -------------------------------------
+        // ---- 3. evaluate the leaf: playouts, or the value network ---------
         uint32_t wins0 = 0u, wins1 = 0u, wins2 = 0u, wins3 = 0u;
+        float vals[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        bool use_vals = false;
+        uint32_t nplay = a.ppl;
+        if (!term && a.leaf_eval) {
+            // one row per seat perspective q = lane % 16 < P
+            uint4 ps;
+            encode(S, ps.x, ps.y, ps.z, ps.w);
+            const uint32_t q = lane & 15u;
+            RowFeat rf = q < S.P ? row_features(ps, q) : no_row();
+            float v4[4];
+            vn_eval16(vn_ptrs(const_cast<void *>(a.net)), rf, vn_tile, v4);
+            float v[4];
+#pragma unroll
+            for (uint32_t k = 0; k < 4u; ++k) v[k] = __shfl(v4[k], 0, 64);
+            const float vm = R.m == 0u ? v[0] : R.m == 1u ? v[1] : R.m == 2u ? v[2] : v[3];
+            const float dv = vm - 0.5f;
+            nplay = a.fb_ppl;
+            if (!((dv < 0.0f ? -dv : dv) < a.band)) {
+                use_vals = true;
+                ++n_net;
+#pragma unroll
+                for (uint32_t k = 0; k < 4u; ++k) vals[k] = (float)a.fb_ppl * v[k];
+            }
+        } else if (a.leaf_eval) {
+            nplay = a.fb_ppl;
+        }
         if (term) {
-            wins0 = winner == 0u ? a.ppl : 0u;
-            wins1 = winner == 1u ? a.ppl : 0u;
-            wins2 = winner == 2u ? a.ppl : 0u;
-            wins3 = winner == 3u ? a.ppl : 0u;
-        } else {
+            wins0 = winner == 0u ? nplay : 0u;
+            wins1 = winner == 1u ? nplay : 0u;
+            wins2 = winner == 2u ? nplay : 0u;
+            wins3 = winner == 3u ? nplay : 0u;
+        } else if (!use_vals) {
             const uint64_t pl = (uint64_t)it * kPhiloxM1;
             const uint32_t trk1 = tr ^ a.k1;
-            for (uint32_t pb = 0; pb < a.ppl; pb += 64u) {
+            for (uint32_t pb = 0; pb < nplay; pb += 64u) {
                 const uint32_t p = pb + lane;
-                const bool act = p < a.ppl;
+                const bool act = p < nplay;
                 uint32_t w = 4u;
                 if (act) {
                     State s = S;
@@ -519,14 +556,22 @@ __global__ void __launch_bounds__(64) mcts_tree_kernel(MctsArgs a)
             }
         }
 
+        if (!term && !use_vals && a.leaf_eval) ++n_played;
+        if (!use_vals) {
+            vals[0] = (float)wins0;
+            vals[1] = (float)wins1;
+            vals[2] = (float)wins2;
+            vals[3] = (float)wins3;
+        }
+
         // ---- 4. back-propagation --------------------------------------------
-        n_root += a.ppl;
+        n_root += nplay;
         if (lane < np) {
             const uint32_t e = path_e[lane];
             const uint32_t chooser = blocks[e] >> 16;
-            const uint32_t wc = chooser == 0u ? wins0 : chooser == 1u ? wins1 : chooser == 2u ? wins2 : wins3;
-            blocks[e + 1u] += a.ppl;
-            blocks[e + 2u] = __float_as_uint(__uint_as_float(blocks[e + 2u]) + (float)wc);
+            const float wc = chooser == 0u ? vals[0] : chooser == 1u ? vals[1] : chooser == 2u ? vals[2] : vals[3];
+            blocks[e + 1u] += nplay;
+            blocks[e + 2u] = __float_as_uint(__uint_as_float(blocks[e + 2u]) + wc);
         }
         __syncthreads();
     }
@@ -536,6 +581,9 @@ __global__ void __launch_bounds__(64) mcts_tree_kernel(MctsArgs a)
         W[0] = n_nodes;
         W[1] = n_blocks;
         W[2] = n_root;
+        W[3] = n_net;
+        W[4] = n_played;
+        W[5] = n_sampler_fallback;
     }
     if (failed) {
         if (lane == 0) a.best[t] = -1;
@@ -583,6 +631,7 @@ size_t mcts_tree_words(uint32_t iters)
 hipError_t launch_mcts(const uint4 *roots, uint32_t n_trees, uint32_t iters, uint32_t ppl,
                        uint32_t dmax, float c_uct, uint32_t k0, uint32_t k1, uint32_t tree_base,
                        const float *ln, uint32_t *ws, int32_t *best, uint32_t *kids,
+                       uint32_t leaf_eval, float band, uint32_t fb_ppl, const void *net,
                        hipStream_t st)
 {
     if (n_trees == 0) return hipSuccess;
@@ -603,6 +652,10 @@ hipError_t launch_mcts(const uint4 *roots, uint32_t n_trees, uint32_t iters, uin
     a.blocks_cap = (iters + 1u) + (iters + 1u) / kBlockEntries + 2u;
     a.best = best;
     a.kids = kids;
+    a.leaf_eval = leaf_eval;
+    a.band = band;
+    a.fb_ppl = fb_ppl;
+    a.net = net;
     hipLaunchKernelGGL(mcts_tree_kernel, dim3(n_trees), dim3(64), 0, st, a);
     return hipGetLastError();
 }

@@ -197,6 +197,95 @@ struct VnRowsArgs {
     float inv_batch;
 };
 
+// Value of 16 rows (lane l holds the features of row l%16): forward pass on
+// the matrix cores.  `hs` is a 16 x 264 bf16 LDS tile; v4[i] receives the
+// value of row 4*(l/16)+i.  Shared by batched inference and the tree search.
+__device__ __forceinline__ void vn_eval16(const VnPtrs &P, const RowFeat &rf,
+                                          uint16_t (*hs)[kVnH + 8], float v4[4])
+{
+    const uint32_t lane = threadIdx.x & 63u, r = lane & 15u, g = lane >> 4;
+    bf16x8 xa[5];
+#pragma unroll
+    for (uint32_t s = 0; s < 5u; ++s) xa[s] = feature8(rf, 32u * s + 8u * g);
+#pragma unroll 4
+    for (uint32_t j = 0; j < 16u; ++j) {
+        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        const uint16_t *wrow = P.w1b + (size_t)(16u * j + r) * kVnIn + 8u * g;
+#pragma unroll
+        for (uint32_t s = 0; s < 5u; ++s) acc = mfma16(xa[s], load8(wrow + 32u * s), acc);
+        const float b = P.master[kOffB1 + 16u * j + r];
+#pragma unroll
+        for (uint32_t i = 0; i < 4u; ++i) {
+            const float h = acc[i] + b;
+            hs[4u * g + i][16u * j + r] = bf16_bits(h > 0.0f ? h : 0.0f);
+        }
+    }
+    __syncthreads();
+    bf16x8 ha[8];
+#pragma unroll
+    for (uint32_t s = 0; s < 8u; ++s) ha[s] = load8(&hs[r][32u * s + 8u * g]);
+    float zpart[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 4
+    for (uint32_t j = 0; j < 16u; ++j) {
+        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        const uint16_t *wrow = P.w2b + (size_t)(16u * j + r) * kVnH + 8u * g;
+#pragma unroll
+        for (uint32_t s = 0; s < 8u; ++s) acc = mfma16(ha[s], load8(wrow + 32u * s), acc);
+        const float b = P.master[kOffB2 + 16u * j + r];
+        const float w3 = bf16_to_f(P.w3b[16u * j + r]);
+#pragma unroll
+        for (uint32_t i = 0; i < 4u; ++i) {
+            const float h = acc[i] + b;
+            zpart[i] += bf16_round(h > 0.0f ? h : 0.0f) * w3;
+        }
+    }
+#pragma unroll
+    for (uint32_t i = 0; i < 4u; ++i)
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) zpart[i] += __shfl_xor(zpart[i], off, 64);
+    const float b3 = P.master[kOffB3];
+#pragma unroll
+    for (uint32_t i = 0; i < 4u; ++i) v4[i] = 1.0f / (1.0f + expf(-(zpart[i] + b3)));
+    __syncthreads();   // hs may be reused by the caller
+}
+
+__device__ __forceinline__ RowFeat no_row()
+{
+    RowFeat rf;
+    rf.rel[0] = rf.rel[1] = rf.rel[2] = rf.rel[3] = 0u;
+    rf.rev = rf.pool = 0u;
+    rf.tomove = 7u;
+    rf.ok = false;
+    return rf;
+}
+
+__global__ void __launch_bounds__(64) vn_infer_kernel(const void *net, const uint4 *states,
+                                                       const uint8_t *persp, uint32_t n,
+                                                       float *v_out)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t hs[16][kVnH + 8];
+    const VnPtrs P = vn_ptrs(const_cast<void *>(net));
+    const uint32_t lane = threadIdx.x, r = lane & 15u, g = lane >> 4;
+    const uint32_t row0 = blockIdx.x * 16u, myrow = row0 + r;
+    RowFeat rf = no_row();
+    if (myrow < n) {
+        rf = row_features(states[myrow], persp[myrow]);
+        if (!rf.ok) {
+            atomicOr(&g_error_word, kErrState);
+            rf = no_row();
+        }
+    }
+    float v4[4];
+    vn_eval16(P, rf, hs, v4);
+    if (r == 0u) {
+#pragma unroll
+        for (uint32_t i = 0; i < 4u; ++i) {
+            const uint32_t row = row0 + 4u * g + i;
+            if (row < n) v_out[row] = v4[i];
+        }
+    }
+}
+
 constexpr uint32_t kPartWords = 2u + 3u * 256u;   // loss, db3, dw3[256], db2[256], db1[256]
 
 template <bool TRAIN>
@@ -497,7 +586,8 @@ hipError_t launch_vn_infer(const void *net, const uint4 *states, const uint8_t *
     a.persp = persp;
     a.n_rows = n;
     a.v_out = v_out;
-    hipLaunchKernelGGL(vn_rows_kernel<false>, dim3((n + 15u) / 16u), dim3(64), 0, st, a);
+    hipLaunchKernelGGL(vn_infer_kernel, dim3((n + 15u) / 16u), dim3(64), 0, st, net, states, persp, n,
+                       v_out);
     return hipGetLastError();
 }
 

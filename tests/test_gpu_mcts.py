@@ -115,3 +115,68 @@ def test_malformed_root_sets_error(orc, dvc):
     assert best.cpu().numpy()[1] == -1
     ref_best, _ = orc.mcts_search(roots[:1], orc.mcts_params(iterations=20, playouts_per_leaf=4), 1)
     assert best.cpu().numpy()[0] == ref_best[0]
+
+
+# ---------------------------------------------------------------------------
+# value mode
+# ---------------------------------------------------------------------------
+def _net(orc, dvc, seed=44):
+    params = orc.vn_init(seed)
+    net = dvc.dvc_valuenet_init(0)
+    dvc.dvc_valuenet_set_params(net, torch.from_numpy(params).cuda())
+    return params, net
+
+
+def test_value_mode_always_fallback_equals_rollouts(orc, dvc):
+    """band 1: every leaf is played out, so the search equals the playout search
+    with fallback_playouts playouts per leaf -- bit-exact."""
+    params, net = _net(orc, dvc)
+    dp = orc.deal_params(p_min=2, p_max=4, pile_min=0, pile_max=16, revealed_max=8, root_draw=1)
+    roots = orc.init_states(12, dp, seed=21)
+    mo = orc.mcts_params(iterations=150, playouts_per_leaf=64, max_depth=4)
+    best_ref, kids_ref = orc.mcts_search(roots, mo, 7)
+    md = dvc.mcts_params(iterations=150, playouts_per_leaf=5, max_depth=4, leaf_eval=1,
+                         fallback_band=1.0, fallback_playouts=64, valuenet=net)
+    best, kids = dvc.mcts_search(dev_states(roots), md, 7)
+    torch.cuda.synchronize()
+    act, n, w = dvc.children_view(kids)
+    assert_same(best_ref, kids_ref, best.cpu().numpy(), act.numpy(), n.numpy(), w.numpy())
+
+
+def test_value_mode_root_values_vs_oracle(orc, dvc):
+    """band 0: every leaf takes the network's value.  With as many iterations
+    as the root has legal guesses, each root child is expanded once, so every
+    child's W is 64 * v(chooser) of its leaf: compare with the oracle's
+    bf16-mirroring network within the inference tolerance."""
+    params, net = _net(orc, dvc)
+    dp = orc.deal_params(p_min=2, p_max=4, pile_min=0, pile_max=12, revealed_max=6, root_draw=1)
+    roots = orc.init_states(6, dp, seed=23)
+    for t in range(6):
+        k = int(orc.legal_actions(roots[t]).sum())
+        mo = orc.mcts_params(iterations=k, playouts_per_leaf=1, max_depth=4, leaf_eval=1,
+                             fallback_band=0.0, fallback_playouts=64, valuenet=params)
+        best_ref, kids_ref = orc.mcts_search(roots[t:t + 1], mo, 7, t)
+        md = dvc.mcts_params(iterations=k, playouts_per_leaf=1, max_depth=4, leaf_eval=1,
+                             fallback_band=0.0, fallback_playouts=64, valuenet=net)
+        best, kids = dvc.mcts_search(dev_states(roots[t:t + 1]), md, 7, t)
+        torch.cuda.synchronize()
+        act, n, w = dvc.children_view(kids)
+        kr = kids_ref[0]
+        assert np.array_equal(act.numpy()[0], kr["action"].astype(np.int64))
+        assert np.array_equal(n.numpy()[0], kr["n"].astype(np.int64))
+        tol = 64 * (2.0 ** -7 * np.abs(kr["w"] / 64) + 1e-3)
+        assert np.all(np.abs(w.numpy()[0] - kr["w"]) <= tol + 1e-6)
+
+
+def test_value_mode_decisions_mostly_agree_with_oracle(orc, dvc):
+    params, net = _net(orc, dvc)
+    dp = orc.deal_params(p_min=2, p_max=4, pile_min=0, pile_max=16, revealed_max=8, root_draw=1)
+    roots = orc.init_states(24, dp, seed=25)
+    mo = orc.mcts_params(iterations=200, playouts_per_leaf=1, max_depth=4, leaf_eval=1,
+                         fallback_band=0.05, fallback_playouts=64, valuenet=params)
+    best_ref, _ = orc.mcts_search(roots, mo, 9)
+    md = dvc.mcts_params(iterations=200, playouts_per_leaf=1, max_depth=4, leaf_eval=1,
+                         fallback_band=0.05, fallback_playouts=64, valuenet=net)
+    best, _ = dvc.mcts_search(dev_states(roots), md, 9)
+    agree = float(np.mean(best.cpu().numpy() == best_ref))
+    assert agree >= 0.75, agree
