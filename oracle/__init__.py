@@ -86,6 +86,9 @@ def lib():
         L.oracle_ln_entry.argtypes = [C.c_uint32]
         L.oracle_mcts_search.argtypes = [C.c_void_p, C.c_int64, C.POINTER(MctsParams), C.c_uint64,
                                          C.c_uint32, C.c_void_p, C.c_void_p]
+        L.oracle_mcts_search_merged.argtypes = [C.c_void_p, C.c_int64, C.c_int32,
+                                                C.POINTER(MctsParams), C.c_uint64, C.c_uint32,
+                                                C.c_void_p, C.c_void_p]
         L.oracle_bf16.restype = C.c_float
         L.oracle_bf16.argtypes = [C.c_float]
         L.oracle_vn_encode.argtypes = [C.c_void_p, C.c_int32, C.c_void_p]
@@ -263,6 +266,20 @@ def mcts_search(roots, params: MctsParams, seed: int, tree_id_base: int = 0):
                                   _ptr(kids))
     if rc:
         raise ValueError(f"oracle_mcts_search failed ({rc})")
+    return best, kids
+
+
+def mcts_search_merged(roots, trees_per_root: int, params: MctsParams, seed: int,
+                       tree_id_base: int = 0):
+    """Root-parallel search: (best [n], merged children [n, 864] indexed by action id)."""
+    s = _states(roots)
+    n = s.shape[0]
+    best = np.zeros(n, np.int32)
+    kids = np.zeros((n, MAX_CHILD), CHILD_DTYPE)
+    rc = lib().oracle_mcts_search_merged(_ptr(s), n, trees_per_root, C.byref(params), seed,
+                                         tree_id_base, _ptr(best), _ptr(kids))
+    if rc:
+        raise ValueError(f"oracle_mcts_search_merged failed ({rc})")
     return best, kids
 
 

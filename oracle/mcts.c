@@ -580,3 +580,54 @@ int oracle_mcts_search(const orc_packed *roots, int64_t n_trees, const orc_mcts_
     free(LN);
     return rc;
 }
+
+/* Root-parallel search (Sec. III-B): each root is searched by K independent
+ * trees, tree id tree_id_base + r*K + k, and the trees are amalgamated into
+ * one root: a root action's merged visit count and win sum are the sums of
+ * that action's (N, W) over the K trees, added in k order.  The decision is
+ * the action with the largest merged N, the lowest action id on ties.
+ * merged[r][a] is indexed by action id; actions no tree created have action
+ * 0xFFFF and zero statistics. */
+int oracle_mcts_search_merged(const orc_packed *roots, int64_t n_roots, int32_t trees_per_root,
+                              const orc_mcts_params *mp, uint64_t seed, uint32_t tree_id_base,
+                              int32_t *best_action, orc_child_stat *merged)
+{
+    if (n_roots < 0 || trees_per_root < 1) return -1;
+    orc_packed *copies = (orc_packed *)malloc(sizeof(orc_packed) * (size_t)(trees_per_root > 0 ? trees_per_root : 1));
+    int32_t *best_k = (int32_t *)malloc(sizeof(int32_t) * (size_t)trees_per_root);
+    orc_child_stat *kids = (orc_child_stat *)malloc(sizeof(orc_child_stat) * ORC_MAX_CHILD * (size_t)trees_per_root);
+    int rc = 0;
+    for (int64_t r = 0; r < n_roots && rc == 0; ++r) {
+        for (int32_t k = 0; k < trees_per_root; ++k) copies[k] = roots[r];
+        rc = oracle_mcts_search(copies, trees_per_root, mp, seed,
+                                tree_id_base + (uint32_t)(r * trees_per_root), best_k, kids);
+        if (rc) break;
+        uint32_t n[ORC_MAX_CHILD];
+        float w[ORC_MAX_CHILD];
+        for (int a = 0; a < ORC_MAX_CHILD; ++a) { n[a] = 0; w[a] = 0.0f; }
+        for (int32_t k = 0; k < trees_per_root; ++k)
+            for (int c = 0; c < ORC_MAX_CHILD; ++c) {
+                const orc_child_stat *s = &kids[(size_t)k * ORC_MAX_CHILD + c];
+                if (s->action == 0xFFFF) break;
+                n[s->action] += s->n;
+                w[s->action] += s->w;
+            }
+        int best = -1;
+        for (int a = 0; a < ORC_MAX_CHILD; ++a)
+            if (n[a] > 0 && (best < 0 || n[a] > n[best])) best = a;
+        best_action[r] = best;
+        if (merged) {
+            for (int a = 0; a < ORC_MAX_CHILD; ++a) {
+                orc_child_stat *m = &merged[(size_t)r * ORC_MAX_CHILD + a];
+                m->action = n[a] > 0 ? (uint16_t)a : 0xFFFF;
+                m->pad = 0;
+                m->n = n[a];
+                m->w = w[a];
+            }
+        }
+    }
+    free(copies);
+    free(best_k);
+    free(kids);
+    return rc;
+}

@@ -127,6 +127,11 @@ int oracle_mcts_search(const orc_packed *roots, int64_t n_trees, const orc_mcts_
                        uint64_t seed, uint32_t tree_id_base, int32_t *best_action,
                        orc_child_stat *root_children);
 
+/* root-parallel search: K trees per root, root statistics summed by action id */
+int oracle_mcts_search_merged(const orc_packed *roots, int64_t n_roots, int32_t trees_per_root,
+                              const orc_mcts_params *mp, uint64_t seed, uint32_t tree_id_base,
+                              int32_t *best_action, orc_child_stat *merged);
+
 /* ---- value network (valuenet.c) ---------------------------------------- */
 int oracle_vn_nparams(void);
 float oracle_bf16(float x);

@@ -185,3 +185,51 @@ def test_determinization_fallback_is_smallest_world(orc):
 def test_ln_table_matches_libm(orc):
     for k in [1, 2, 3, 10, 1000, 32000, 262143, 262144]:
         assert orc.ln_entry(k) == np.float32(math.log(k))
+
+
+# ---------------------------------------------------------------------------
+# root-parallel search: K trees per root amalgamated into one root (Sec. III-B)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("K", [1, 3])
+def test_merged_search_sums_independent_trees(orc, K):
+    """The amalgamated root is the per-action sum of K independent trees whose
+    tree ids are base + r*K + k; the decision is its most visited action,
+    lowest action id on ties; every merged visit count adds up to K*iters*ppl."""
+    roots = _roots(orc, 3, seed=41, p_min=2, p_max=4, fresh=0, hand=(0, 0, 4, 4, 3),
+                   pile_min=0, pile_max=12, revealed_max=4)
+    iters, ppl, base = 60, 4, 10
+    mp = orc.mcts_params(iterations=iters, playouts_per_leaf=ppl, max_depth=3)
+    best, merged = orc.mcts_search_merged(roots, K, mp, seed=8, tree_id_base=base)
+    for r in range(3):
+        n = np.zeros(864, np.int64)
+        w = np.zeros(864, np.float64)
+        for k in range(K):
+            _, kids = orc.mcts_search(roots[r:r + 1], mp, 8, base + r * K + k)
+            for c in kids[0]:
+                if c["action"] == 0xFFFF:
+                    break
+                n[c["action"]] += int(c["n"])
+                w[c["action"]] += float(c["w"])
+        m = merged[r]
+        assert np.array_equal(m["n"].astype(np.int64), n)
+        # rollout-mode win sums are integers, so float sums are exact
+        assert np.array_equal(m["w"].astype(np.float64), w)
+        created = n > 0
+        assert np.array_equal(m["action"] != 0xFFFF, created)
+        assert np.array_equal(np.flatnonzero(created), m["action"][created].astype(np.int64))
+        assert n.sum() == K * iters * ppl
+        assert best[r] == int(np.flatnonzero(n == n.max())[0])
+
+
+def test_merged_search_one_tree_matches_single_search(orc):
+    roots = _roots(orc, 4, seed=43)
+    mp = orc.mcts_params(iterations=200, playouts_per_leaf=8, max_depth=4)
+    best_m, merged = orc.mcts_search_merged(roots, 1, mp, seed=2, tree_id_base=5)
+    best_s, kids = orc.mcts_search(roots, mp, 2, 5)
+    for r in range(4):
+        live = kids[r][kids[r]["action"] != 0xFFFF]
+        m = merged[r][live["action"].astype(np.int64)]
+        assert np.array_equal(m["n"], live["n"]) and np.array_equal(m["w"], live["w"])
+        top = live["n"].max()
+        if np.sum(live["n"] == top) == 1:
+            assert best_m[r] == best_s[r]
