@@ -9,9 +9,15 @@ game length (int16) and per-leaf seat wins (dvc_rollout).  Inputs are
 synthetic and resident in HBM before timing starts.
 
 Prints one JSON line.  `value` is playouts/s of the whole step; `roofline`
-prices the dominant kernel (the persistent rollout kernel) against the
-integer-VALU issue peak of the chip; `cpu_baseline` is the CPU oracle timed
-on this host's cores on a bounded sample of the same workload.
+prices the dominant kernel (the rollout kernel, one playout per lane at this
+size) against the integer-VALU issue peak of the chip; `cpu_baseline` is the
+CPU oracle timed on this host's cores on a bounded sample of the same
+workload.  Side figures: batched search, root-parallel search and a single
+tree, timed with HIP events.
+
+--copy-mib N additionally copies an N MiB device buffer three times after the
+timed steps: a kernel of known traffic, used to scale the HBM byte counters
+of a profiler run.
 """
 import argparse
 import json
@@ -46,6 +52,7 @@ def parse():
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-search", action="store_true", help="skip the tree-search figures")
+    ap.add_argument("--copy-mib", type=int, default=0, help="copy a buffer of this size (MiB)")
     return ap.parse_args()
 
 
@@ -74,6 +81,30 @@ def batched_search(D, torch, reps=3):
     return {"workload": "2048 trees (2-4 players, mid-game, root draw) x 1024 iterations x 32 "
                         "playouts, depth 4", "ms_per_launch": best,
             "decisions_per_s": n / (best / 1e3), "playouts_per_s": n * iters * ppl / (best / 1e3)}
+
+
+def root_parallel_search(D, torch, reps=3):
+    """The paper's decomposition: 64 fresh 2-4 player deals, 32 independent
+    trees each (1024 iterations x 32 playouts, depth 4), amalgamated at the root."""
+    n, K, iters, ppl = 64, 32, 1024, 32
+    roots = D.dvc_init_states(n, D.deal_params(p_min=2, p_max=4, hand=(0, 0, 4, 4, 3), fresh=1,
+                                               root_draw=1), 6)
+    mp = D.mcts_params(iterations=iters, playouts_per_leaf=ppl, max_depth=4)
+    ws = torch.empty(D.dvc_mcts_workspace_bytes(n * K, mp), dtype=torch.uint8, device=roots.device)
+    D.mcts_search_root_parallel(roots, K, mp, 6, workspace=ws, want_children=False)
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        D.mcts_search_root_parallel(roots, K, mp, 6, workspace=ws, want_children=False)
+        e1.record()
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    best = min(ms)
+    return {"workload": "64 fresh 2-4 player deals x 32 trees x 1024 iterations x 32 playouts, "
+                        "depth 4, merged at the root", "ms_per_launch": best,
+            "decisions_per_s": n / (best / 1e3), "playouts_per_s": n * K * iters * ppl / (best / 1e3)}
 
 
 def single_tree_search(D, torch):
@@ -144,6 +175,9 @@ def main():
     rc = D.dvc_check()
     if rc != 0:
         raise RuntimeError(f"device error {rc}")
+    if args.copy_mib > 0:
+        src = torch.empty(args.copy_mib << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
     guesses = int(length.to(torch.int64).sum().item())
     lens = length.float()
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -157,6 +191,10 @@ def main():
     stop.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    if args.copy_mib > 0:
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
     ms_total = start.elapsed_time(stop)
     kern_ms = [a.elapsed_time(b) for a, b in evs]
     ms_step = ms_total / args.steps
@@ -179,7 +217,7 @@ def main():
         "config": {"workload": "leaf-parallel rollout: 4096 two-player mid-game leaves x 256 "
                                "playouts (pool 0-16, 0-8 revealed per row)",
                    "leaves": N_LEAVES, "playouts_per_leaf": PPL, "seed": SEED,
-                   "variant": args.variant or 2, "block": args.block, "grid": args.grid},
+                   "variant": args.variant or 4, "block": args.block, "grid": args.grid},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": INT_VALU_PEAK,
                      "unit": "int lane-ops/s", "frac": achieved / INT_VALU_PEAK,
                      "traffic": None},
@@ -190,6 +228,7 @@ def main():
     }
     if not args.no_search:
         out["batched_search"] = batched_search(D, torch)
+        out["root_parallel_search"] = root_parallel_search(D, torch)
         out["single_tree_search"] = single_tree_search(D, torch)
     if not args.no_cpu:
         threads = max(1, min(16, os.cpu_count() or 1))

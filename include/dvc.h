@@ -192,12 +192,30 @@ size_t dvc_mcts_workspace_bytes(int64_t n_trees, const dvc_mcts_params *params /
  * tree_id_base + t).  Roots must be valid and undecided, in phase 1 (or
  * phase 0 with an empty pool).  best_action[t] receives the chosen action id;
  * root_children (may be NULL) receives [n_trees][864] child statistics.
- * workspace: device memory of at least dvc_mcts_workspace_bytes().
- * Returns DVC_EINVAL on bad sizes/params, DVC_ENOMEM if the workspace is too
- * small; malformed roots set DVC_ESTATE in the error word.                  */
+ * workspace: device memory of at least dvc_mcts_workspace_bytes(), 16-byte
+ * aligned; it holds the trees after the call (and their per-tree counters).
+ * Returns DVC_EINVAL on bad sizes/params or a misaligned workspace,
+ * DVC_ENOMEM if the workspace is too small; malformed roots set DVC_ESTATE in
+ * the error word and get best_action -1 and no children.                    */
 int mcts_search(const dvc_state_t *roots, int64_t n_trees, const dvc_mcts_params *params /* host */,
                 uint64_t seed, uint32_t tree_id_base, void *workspace, size_t workspace_bytes,
                 int32_t *best_action, dvc_child_stat *root_children, void *stream);
+
+/* mcts_search_root_parallel -- the paper's decomposition (Sec. III-B): each
+ * root is searched by trees_per_root (K, 1..65536) independent trees, tree
+ * id tree_id_base + r*K + k, each exactly as in mcts_search, and the K trees
+ * are amalgamated into one root: a root action's merged N and W are the sums
+ * of that action's N and W over the K trees, added in k order (W in float).
+ * best_action[r] = the action with the largest merged N, the lowest action id
+ * on ties.  merged_children (may be NULL) receives [n_roots][864] statistics
+ * indexed by action id (entry a describes action a; action 0xFFFF and zeros
+ * where no tree created it).  workspace: dvc_mcts_workspace_bytes(n_roots*K).
+ * A root with a malformed state, or any of whose trees gives up, gets
+ * best_action -1 and no merged children.  Errors as for mcts_search.       */
+int mcts_search_root_parallel(const dvc_state_t *roots, int64_t n_roots, int32_t trees_per_root,
+                              const dvc_mcts_params *params /* host */, uint64_t seed,
+                              uint32_t tree_id_base, void *workspace, size_t workspace_bytes,
+                              int32_t *best_action, dvc_child_stat *merged_children, void *stream);
 
 /* ---------------------------------------------------------------------------
  * Learned leaf evaluator (value network).  The paper weights tree nodes by the

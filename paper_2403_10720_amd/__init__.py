@@ -97,6 +97,8 @@ def lib():
             L.dvc_mcts_workspace_bytes.argtypes = [i64, C.POINTER(MctsParams)]
             L.mcts_search.argtypes = [vp, i64, C.POINTER(MctsParams), u64, u32, vp, C.c_size_t,
                                       vp, vp, vp]
+            L.mcts_search_root_parallel.argtypes = [vp, i64, i32, C.POINTER(MctsParams), u64, u32,
+                                                    vp, C.c_size_t, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -203,13 +205,36 @@ def mcts_search(roots: torch.Tensor, params: MctsParams, seed: int, tree_id_base
     return best, kids
 
 
+def mcts_search_root_parallel(roots: torch.Tensor, trees_per_root: int, params: MctsParams,
+                              seed: int, tree_id_base: int = 0, workspace=None,
+                              want_children: bool = True, stream=None):
+    """K independent trees per root amalgamated into one root (tree id
+    tree_id_base + r*K + k).  Returns (best_action int32 [n], merged children
+    int32 [n, 864, 3] indexed by action id | None), same encoding as
+    mcts_search's children."""
+    _check_dev(roots, torch.int32, None, "roots")
+    n = roots.shape[0]
+    dev = roots.device
+    need = dvc_mcts_workspace_bytes(n * max(trees_per_root, 1), params)
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    best = torch.empty(n, dtype=torch.int32, device=dev)
+    kids = torch.empty((n, MAX_ACTIONS, 3), dtype=torch.int32, device=dev) if want_children else None
+    rc = lib().mcts_search_root_parallel(_ptr(roots), n, trees_per_root, C.byref(params),
+                                         seed & (2**64 - 1), tree_id_base, _ptr(workspace),
+                                         workspace.numel(), _ptr(best), _ptr(kids),
+                                         _stream(stream))
+    _raise(rc, "mcts_search_root_parallel")
+    return best, kids
+
+
 def mcts_tree_stats(workspace: torch.Tensor, n_trees: int, params: MctsParams) -> dict:
     """Per-tree counters the search leaves at the start of each tree's workspace."""
     per_tree = dvc_mcts_workspace_bytes(1, params)
     w = workspace[:n_trees * per_tree].view(n_trees, per_tree)[:, :32].contiguous().view(torch.int32)
     w = w.cpu()
-    return {"nodes": w[:, 0], "blocks": w[:, 1], "root_visits": w[:, 2], "net_leaves": w[:, 3],
-            "played_leaves": w[:, 4], "sampler_fallbacks": w[:, 5]}
+    return {"nodes": w[:, 0], "overflow_blocks": w[:, 1], "root_visits": w[:, 2], "net_leaves": w[:, 3],
+            "played_leaves": w[:, 4], "sampler_fallbacks": w[:, 5], "failed": w[:, 6]}
 
 
 def children_view(kids: torch.Tensor):

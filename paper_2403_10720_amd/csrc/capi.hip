@@ -196,7 +196,9 @@ int dvc_rollout_ex(const dvc_state_t *leaves, int64_t n_leaves, int32_t ppl, uin
         hipError_t e = launch_fill_u32(seat_wins, (uint64_t)n_leaves * 4u, 0u, st);
         if (e != hipSuccess) return DVC_EHIP;
     }
-    const int v = variant == 0 ? 3 : variant;
+    // automatic: one playout per lane (variant 4 with one playout per lane
+    // was the fastest at the leaf-parallel size, variant 1 within 8% above it)
+    const int v = variant == 0 ? 4 : variant;
     return status_of(launch_rollout(a, v, block, grid, st));
 }
 
@@ -214,13 +216,20 @@ size_t dvc_mcts_workspace_bytes(int64_t n_trees, const dvc_mcts_params *params)
     return (size_t)n_trees * mcts_tree_words((uint32_t)params->iterations) * sizeof(uint32_t);
 }
 
-int mcts_search(const dvc_state_t *roots, int64_t n_trees, const dvc_mcts_params *params,
-                uint64_t seed, uint32_t tree_id_base, void *workspace, size_t workspace_bytes,
-                int32_t *best_action, dvc_child_stat *root_children, void *stream)
+// merge = false: one tree per root, statistics in creation order;
+// merge = true: trees_per_root trees per root amalgamated by action id
+static int run_search(const dvc_state_t *roots, int64_t n_roots, int64_t trees_per_root, bool merge,
+                      const dvc_mcts_params *params, uint64_t seed, uint32_t tree_id_base,
+                      void *workspace, size_t workspace_bytes, int32_t *best_action,
+                      dvc_child_stat *children, void *stream)
 {
-    if (n_trees < 0 || n_trees >= (1ll << 31) || !mcts_params_ok(params)) return DVC_EINVAL;
-    if (n_trees == 0) return DVC_OK;
+    if (n_roots < 0 || trees_per_root < 1 || trees_per_root > 65536 || !mcts_params_ok(params))
+        return DVC_EINVAL;
+    const int64_t n_trees = n_roots * trees_per_root;
+    if (n_trees >= (1ll << 31)) return DVC_EINVAL;
+    if (n_roots == 0) return DVC_OK;
     if (roots == nullptr || best_action == nullptr || workspace == nullptr) return DVC_EINVAL;
+    if (reinterpret_cast<uintptr_t>(workspace) % 16u != 0u) return DVC_EINVAL;
     if (workspace_bytes < dvc_mcts_workspace_bytes(n_trees, params)) return DVC_ENOMEM;
     int status = DVC_OK;
     const uint64_t w_leaf =
@@ -228,15 +237,39 @@ int mcts_search(const dvc_state_t *roots, int64_t n_trees, const dvc_mcts_params
     const uint64_t need = (uint64_t)params->iterations * w_leaf + 1u;
     const float *ln = ln_table(need, &status);
     if (ln == nullptr) return status;
-    return status_of(launch_mcts(reinterpret_cast<const uint4 *>(roots), (uint32_t)n_trees,
-                                 (uint32_t)params->iterations, (uint32_t)params->playouts_per_leaf,
-                                 (uint32_t)params->max_depth, params->c_uct, (uint32_t)seed,
-                                 (uint32_t)(seed >> 32), tree_id_base, ln,
-                                 reinterpret_cast<uint32_t *>(workspace), best_action,
-                                 reinterpret_cast<uint32_t *>(root_children),
-                                 (uint32_t)params->leaf_eval, params->fallback_band,
-                                 (uint32_t)params->fallback_playouts, params->valuenet,
-                                 (hipStream_t)stream));
+    hipError_t e = launch_mcts(reinterpret_cast<const uint4 *>(roots), (uint32_t)n_trees,
+                               (uint32_t)trees_per_root, (uint32_t)params->iterations,
+                               (uint32_t)params->playouts_per_leaf, (uint32_t)params->max_depth,
+                               params->c_uct, (uint32_t)seed, (uint32_t)(seed >> 32), tree_id_base,
+                               ln, reinterpret_cast<uint32_t *>(workspace),
+                               merge ? nullptr : best_action,
+                               merge ? nullptr : reinterpret_cast<uint32_t *>(children),
+                               (uint32_t)params->leaf_eval, params->fallback_band,
+                               (uint32_t)params->fallback_playouts, params->valuenet,
+                               (hipStream_t)stream);
+    if (e != hipSuccess || !merge) return status_of(e);
+    return status_of(launch_mcts_merge(reinterpret_cast<const uint32_t *>(workspace),
+                                       (uint32_t)n_roots, (uint32_t)trees_per_root,
+                                       (uint32_t)params->iterations, best_action,
+                                       reinterpret_cast<uint32_t *>(children),
+                                       (hipStream_t)stream));
+}
+
+int mcts_search(const dvc_state_t *roots, int64_t n_trees, const dvc_mcts_params *params,
+                uint64_t seed, uint32_t tree_id_base, void *workspace, size_t workspace_bytes,
+                int32_t *best_action, dvc_child_stat *root_children, void *stream)
+{
+    return run_search(roots, n_trees, 1, false, params, seed, tree_id_base, workspace, workspace_bytes,
+                      best_action, root_children, stream);
+}
+
+int mcts_search_root_parallel(const dvc_state_t *roots, int64_t n_roots, int32_t trees_per_root,
+                              const dvc_mcts_params *params, uint64_t seed, uint32_t tree_id_base,
+                              void *workspace, size_t workspace_bytes, int32_t *best_action,
+                              dvc_child_stat *merged_children, void *stream)
+{
+    return run_search(roots, n_roots, trees_per_root, true, params, seed, tree_id_base, workspace,
+                      workspace_bytes, best_action, merged_children, stream);
 }
 
 size_t dvc_valuenet_bytes(void) { return vn_bytes(); }

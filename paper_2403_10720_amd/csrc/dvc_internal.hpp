@@ -49,11 +49,13 @@ int default_rollout_grid(int waves_per_block);
 hipError_t launch_rollout(const RolloutArgs &a, int variant, int block, int grid, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st);
 size_t mcts_tree_words(uint32_t iters);
-hipError_t launch_mcts(const uint4 *roots, uint32_t n_trees, uint32_t iters, uint32_t ppl,
-                       uint32_t dmax, float c_uct, uint32_t k0, uint32_t k1, uint32_t tree_base,
+hipError_t launch_mcts(const uint4 *roots, uint32_t n_trees, uint32_t trees_per_root,
+                       uint32_t iters, uint32_t ppl, uint32_t dmax, float c_uct, uint32_t k0, uint32_t k1, uint32_t tree_base,
                        const float *ln, uint32_t *ws, int32_t *best, uint32_t *kids,
                        uint32_t leaf_eval, float band, uint32_t fb_ppl, const void *net,
                        hipStream_t st);
+hipError_t launch_mcts_merge(const uint32_t *ws, uint32_t n_roots, uint32_t trees_per_root,
+                             uint32_t iters, int32_t *best, uint32_t *merged, hipStream_t st);
 size_t vn_bytes();
 size_t vn_train_ws_bytes(uint32_t batch);
 hipError_t launch_vn_init(void *net, uint32_t k0, uint32_t k1, hipStream_t st);

@@ -590,9 +590,10 @@ hipError_t launch_rollout(const RolloutArgs &a, int variant, int block, int grid
         return hipGetLastError();
     }
     if (variant == 4) {
-        // playouts per lane: enough lanes for eight waves per SIMD, at most 4
-        const uint64_t lanes8 = (uint64_t)default_rollout_grid(1) * 4u * 64u;
-        int kk = grid > 0 ? grid : (int)((a.total + lanes8 - 1) / lanes8);
+        // playouts per lane (1, 2 or 4); automatic = 1: more playouts per
+        // lane only lengthened the launch at every size measured (1M to 67M
+        // playouts), the hardware refilling finished waves being cheaper
+        int kk = grid > 0 ? grid : 1;
         kk = kk < 1 ? 1 : (kk > 4 ? 4 : kk);
         if (kk == 3) kk = 4;
         const uint32_t per_block = 256u * (uint32_t)kk;

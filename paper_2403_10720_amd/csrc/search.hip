@@ -20,19 +20,27 @@
 // Per-tree statistics are left in the first words of the tree's workspace:
 // nodes, child blocks, root visits, leaves scored by the network, leaves
 // played out in value mode, iterations that used the sampler's fallback.
-// Tree storage lives in the caller's workspace: a node table (child list
-// head/tail, child count, a bitmap of the actions that already have a child)
-// and blocks of 64 child entries {action | chooser << 16, N, W, node id}, so a
-// node's children are scored 64 at a time with coalesced loads.
+// Tree storage lives in the caller's workspace: per node a record (last
+// child block, child count, a bitmap of the actions that already have a
+// child) followed by its first block of 64 child entries {action | chooser
+// << 16, N, W, node id}; nodes with more than 64 children chain overflow
+// blocks.  A node's record and first 64 children arrive in one round of
+// loads, and its children are scored 64 at a time.
 #include "dvc_core.hpp"
 #include "dvc_internal.hpp"
 
 namespace dvc {
 
-constexpr uint32_t kNodeWords = 40;      // first block, last block, nchild, pad, 36 bitmap words
+constexpr uint32_t kNodeWords = 40;      // pad, last block, nchild, pad, 36 bitmap words
 constexpr uint32_t kBlockEntries = 64;
 constexpr uint32_t kEntryWords = 4;
 constexpr uint32_t kBlockWords = kBlockEntries * kEntryWords;
+// a node's record is followed by its first child block, so one round of
+// loads fetches both
+constexpr uint32_t kNodeStride = kNodeWords + kBlockWords;
+// tree header: nodes, overflow blocks, root visits, network leaves, played
+// leaves, sampler fallbacks, failed flag
+constexpr uint32_t kHdrFailed = 6;
 constexpr uint32_t kTreeHeaderWords = 16;
 constexpr uint32_t kNoBlock = 0xFFFFFFFFu;
 constexpr uint32_t kDetAttempts = 64;
@@ -302,14 +310,14 @@ __device__ __forceinline__ void wave_argmax_u(uint32_t &n, uint32_t &idx)
 
 struct MctsArgs {
     const uint4 *roots;
-    uint32_t n_trees, iters, ppl, dmax;
+    uint32_t n_trees, trees_per_root, iters, ppl, dmax;   // tree t searches root t / trees_per_root
     float c_uct;
     uint32_t k0, k1, tree_base;
     const float *ln;
     uint32_t *ws;
     uint64_t tree_words;
-    uint32_t nodes_cap, blocks_cap;
-    int32_t *best;
+    uint32_t nodes_cap, ovf_cap;
+    int32_t *best;    // [n_trees] or null
     uint32_t *kids;   // [n_trees][864][3] or null
     // value mode: leaves are scored by the network; a leaf whose value for
     // the root player is within `band` of 1/2 is played out instead
@@ -342,24 +350,32 @@ __global__ void __launch_bounds__(64) mcts_tree_kernel(MctsArgs a)
     const uint32_t lane = threadIdx.x;
     const uint32_t tr = a.tree_base + t;
     uint32_t *W = a.ws + (uint64_t)t * a.tree_words;
-    uint32_t *nodes = W + kTreeHeaderWords;
-    uint32_t *blocks = nodes + (uint64_t)a.nodes_cap * kNodeWords;
-    uint32_t *bnext = blocks + (uint64_t)a.blocks_cap * kBlockWords;
+    const uint32_t ovf_base = kTreeHeaderWords + a.nodes_cap * kNodeStride;
+    uint32_t *bnext = W + ovf_base + a.ovf_cap * kBlockWords;
+    // word offset (from W) of child block b: blocks below nodes_cap are the
+    // nodes' inline blocks, the rest overflow blocks
+    auto block_off = [&](uint32_t b) -> uint32_t {
+        return b < a.nodes_cap ? kTreeHeaderWords + b * kNodeStride + kNodeWords
+                               : ovf_base + (b - a.nodes_cap) * kBlockWords;
+    };
+    auto rec_off = [&](uint32_t nd) -> uint32_t { return kTreeHeaderWords + nd * kNodeStride; };
 
-    const uint4 rs = a.roots[t];
+    const uint4 rs = a.roots[t / a.trees_per_root];
     State R;
     const bool ok = decode(rs.x, rs.y, rs.z, rs.w, R);
     const uint32_t pool0 = ~(R.h0 | R.h1 | R.h2 | R.h3) & kAll;
     if (!ok || __popc(alive_mask(R)) < 2 || (R.phase == 0u && pool0 != 0u)) {
         if (lane == 0) {
             atomicOr(&g_error_word, kErrState);
-            a.best[t] = -1;
+            if (a.best) a.best[t] = -1;
         }
+        if (lane < kTreeHeaderWords) W[lane] = lane == kHdrFailed ? 1u : 0u;
         write_no_children(a, t, lane);
         return;
     }
-    if (lane < kNodeWords) nodes[lane] = lane < 2u ? kNoBlock : 0u;
-    uint32_t n_nodes = 1u, n_blocks = 0u, n_root = 0u;
+    if (lane < kNodeWords) W[rec_off(0u) + lane] = 0u;
+    if (lane == 0) bnext[0] = kNoBlock;
+    uint32_t n_nodes = 1u, n_ovf = 0u, n_root = 0u;
     uint32_t n_net = 0u, n_played = 0u, n_sampler_fallback = 0u;   // statistics
     bool failed = false, have_fallback = false;
     State fallback = R;
@@ -396,13 +412,19 @@ __global__ void __launch_bounds__(64) mcts_tree_kernel(MctsArgs a)
         bool term = false;
         for (;;) {
             if (term || depth >= a.dmax) break;
+            // one round of loads: bitmap, child count, first 64 children, LN
+            const uint32_t rec = rec_off(node);
+            const uint32_t cbw0 = W[rec + 4u + (lane >> 1)];
+            const uint32_t cbw1 = lane < 8u ? W[rec + 36u + (lane >> 1)] : 0u;
+            const uint32_t nchild = W[rec + 2u];
+            const uint4 ent0 = *reinterpret_cast<const uint4 *>(W + rec + kNodeWords + lane * kEntryWords);
+            const float lp = a.ln[node_n];
             const uint32_t l0 = legal_values(S, lane, tab);
             const uint32_t l1 = lane < 8u ? legal_values(S, 64u + lane, tab) : 0u;
             legal_s[lane] = l0;
             if (lane < 8u) legal_s[64u + lane] = l1;
-            const uint32_t *nd = nodes + (uint64_t)node * kNodeWords;
-            const uint32_t cb0 = (nd[4u + (lane >> 1)] >> ((lane & 1u) * 16u)) & 0xFFFu;
-            const uint32_t cb1 = lane < 8u ? (nd[4u + ((64u + lane) >> 1)] >> ((lane & 1u) * 16u)) & 0xFFFu : 0u;
+            const uint32_t cb0 = (cbw0 >> ((lane & 1u) * 16u)) & 0xFFFu;
+            const uint32_t cb1 = (cbw1 >> ((lane & 1u) * 16u)) & 0xFFFu;
             const uint32_t u0 = l0 & ~cb0, u1 = l1 & ~cb1;
             const uint64_t b0 = __ballot(u0 != 0u), b1 = __ballot(u1 != 0u);
             __syncthreads();
@@ -419,53 +441,52 @@ __global__ void __launch_bounds__(64) mcts_tree_kernel(MctsArgs a)
                 }
                 const uint32_t action = pair * 12u + (uint32_t)__builtin_ctz(vbits);
                 const uint32_t c = n_nodes++;
-                const uint32_t slot = nd[2];
-                uint32_t blk;
-                if ((slot & (kBlockEntries - 1u)) == 0u) {
-                    blk = n_blocks++;
-                    if (lane == 0) {
-                        bnext[blk] = kNoBlock;
-                        uint32_t *ndw = nodes + (uint64_t)node * kNodeWords;
-                        if (slot == 0u) ndw[0] = blk;
-                        else bnext[nd[1]] = blk;
-                        ndw[1] = blk;
+                const uint32_t slot = nchild;
+                uint32_t blk = node;
+                if (slot >= kBlockEntries) {
+                    blk = W[rec + 1u];
+                    if ((slot & (kBlockEntries - 1u)) == 0u) {
+                        const uint32_t ob = a.nodes_cap + n_ovf++;
+                        if (lane == 0) {
+                            bnext[ob] = kNoBlock;
+                            bnext[blk] = ob;
+                            W[rec + 1u] = ob;
+                        }
+                        blk = ob;
                     }
-                } else {
-                    blk = nd[1];
                 }
-                const uint32_t e = blk * kBlockWords + (slot & (kBlockEntries - 1u)) * kEntryWords;
+                const uint32_t e = block_off(blk) + (slot & (kBlockEntries - 1u)) * kEntryWords;
                 if (lane == 0) {
-                    uint32_t *ndw = nodes + (uint64_t)node * kNodeWords;
-                    blocks[e + 0u] = action | (S.m << 16);
-                    blocks[e + 1u] = 0u;
-                    blocks[e + 2u] = 0u;
-                    blocks[e + 3u] = c;
-                    ndw[2] = slot + 1u;
-                    ndw[4u + (pair >> 1)] |= 1u << ((action % 12u) + (pair & 1u) * 16u);
+                    W[e + 0u] = action | (S.m << 16);
+                    W[e + 1u] = 0u;
+                    W[e + 2u] = 0u;
+                    W[e + 3u] = c;
+                    W[rec + 2u] = slot + 1u;
+                    W[rec + 4u + (pair >> 1)] |= 1u << ((action % 12u) + (pair & 1u) * 16u);
+                    bnext[c] = kNoBlock;
                 }
-                if (lane < kNodeWords) nodes[(uint64_t)c * kNodeWords + lane] = lane < 2u ? kNoBlock : 0u;
+                if (lane < kNodeWords) W[rec_off(c) + lane] = lane == 1u ? c : 0u;
                 path_e[np++] = e;
                 term = apply_action(S, action, depth, it, tr, a.k0, a.k1, winner, tab);
                 __syncthreads();
                 break;
             }
             // selection: UCT over the legal children, 64 per pass
-            const uint32_t nchild = nd[2];
-            const float lp = a.ln[node_n];
             float best_s = -__builtin_inff();
-            uint32_t best_i = 0xFFFFFFFFu, best_e = 0u;
-            uint32_t blk = nd[0];
+            uint32_t best_i = 0xFFFFFFFFu, best_e = 0u, best_act = 0u, best_node = 0u, best_n = 0u;
+            uint32_t blk = node;
+            uint4 ent = ent0;
             for (uint32_t base = 0; base < nchild; base += kBlockEntries) {
+                if (base > 0u) ent = *reinterpret_cast<const uint4 *>(W + block_off(blk) + lane * kEntryWords);
                 const uint32_t ci = base + lane;
-                const uint32_t e = blk * kBlockWords + lane * kEntryWords;
                 float sc = -__builtin_inff();
                 uint32_t idx = 0xFFFFFFFFu;
                 if (ci < nchild) {
-                    const uint32_t act = blocks[e] & 0xFFFFu;
+                    const uint32_t act = ent.x & 0xFFFFu;
                     const uint32_t pr = act / 12u;
                     if ((legal_s[pr] >> (act - pr * 12u)) & 1u) {
-                        const float n = (float)blocks[e + 1u];
-                        const float q = __uint_as_float(blocks[e + 2u]) / n;
+                        const float n = (float)ent.y;
+                        const float q = __uint_as_float(ent.z) / n;
                         const float ex = lp / n;
                         const float u = a.c_uct * sqrtf(ex);
                         sc = q + u;
@@ -474,17 +495,20 @@ __global__ void __launch_bounds__(64) mcts_tree_kernel(MctsArgs a)
                 }
                 wave_argmax(sc, idx);
                 if (idx != 0xFFFFFFFFu && (best_i == 0xFFFFFFFFu || sc > best_s)) {
+                    const uint32_t wl = idx - base;
                     best_s = sc;
                     best_i = idx;
-                    best_e = blk * kBlockWords + (idx - base) * kEntryWords;
+                    best_e = block_off(blk) + wl * kEntryWords;
+                    best_act = __builtin_amdgcn_readlane(ent.x, wl) & 0xFFFFu;
+                    best_n = __builtin_amdgcn_readlane(ent.y, wl);
+                    best_node = __builtin_amdgcn_readlane(ent.w, wl);
                 }
                 if (base + kBlockEntries < nchild) blk = bnext[blk];
             }
-            const uint32_t action = blocks[best_e] & 0xFFFFu;
-            node = blocks[best_e + 3u];
-            node_n = blocks[best_e + 1u];
+            node = best_node;
+            node_n = best_n;
             path_e[np++] = best_e;
-            term = apply_action(S, action, depth, it, tr, a.k0, a.k1, winner, tab);
+            term = apply_action(S, best_act, depth, it, tr, a.k0, a.k1, winner, tab);
             ++depth;
             __syncthreads();
         }
@@ -568,10 +592,10 @@ __global__ void __launch_bounds__(64) mcts_tree_kernel(MctsArgs a)
         n_root += nplay;
         if (lane < np) {
             const uint32_t e = path_e[lane];
-            const uint32_t chooser = blocks[e] >> 16;
+            const uint32_t chooser = W[e] >> 16;
             const float wc = chooser == 0u ? vals[0] : chooser == 1u ? vals[1] : chooser == 2u ? vals[2] : vals[3];
-            blocks[e + 1u] += nplay;
-            blocks[e + 2u] = __float_as_uint(__uint_as_float(blocks[e + 2u]) + wc);
+            W[e + 1u] += nplay;
+            W[e + 2u] = __float_as_uint(__uint_as_float(W[e + 2u]) + wc);
         }
         __syncthreads();
     }
@@ -579,29 +603,30 @@ __global__ void __launch_bounds__(64) mcts_tree_kernel(MctsArgs a)
     // ---- decision and root statistics ----------------------------------------
     if (lane == 0) {
         W[0] = n_nodes;
-        W[1] = n_blocks;
+        W[1] = n_ovf;
         W[2] = n_root;
         W[3] = n_net;
         W[4] = n_played;
         W[5] = n_sampler_fallback;
+        W[kHdrFailed] = failed ? 1u : 0u;
     }
     if (failed) {
-        if (lane == 0) a.best[t] = -1;
+        if (lane == 0 && a.best) a.best[t] = -1;
         write_no_children(a, t, lane);
         return;
     }
-    const uint32_t nchild = nodes[2];
-    uint32_t blk = nodes[0];
+    const uint32_t nchild = W[rec_off(0u) + 2u];
+    uint32_t blk = 0u;
     uint32_t best_n = 0u, best_i = 0xFFFFFFFFu, best_act = 0xFFFFu;
     uint32_t *kid = a.kids ? a.kids + (size_t)t * kMaxActions * 3u : nullptr;
     for (uint32_t base = 0; base < kMaxActions; base += kBlockEntries) {
         const uint32_t ci = base + lane;
         uint32_t act = 0xFFFFu, n = 0u, wbits = 0u;
         if (base < nchild && ci < nchild) {
-            const uint32_t e = blk * kBlockWords + lane * kEntryWords;
-            act = blocks[e] & 0xFFFFu;
-            n = blocks[e + 1u];
-            wbits = blocks[e + 2u];
+            const uint32_t e = block_off(blk) + lane * kEntryWords;
+            act = W[e] & 0xFFFFu;
+            n = W[e + 1u];
+            wbits = W[e + 2u];
         }
         if (kid && ci < kMaxActions) {
             kid[ci * 3u + 0u] = act;
@@ -618,17 +643,92 @@ __global__ void __launch_bounds__(64) mcts_tree_kernel(MctsArgs a)
         }
         if (base + kBlockEntries < nchild) blk = bnext[blk];
     }
-    if (lane == 0) a.best[t] = best_i == 0xFFFFFFFFu ? -1 : (int32_t)best_act;
+    if (lane == 0 && a.best) a.best[t] = best_i == 0xFFFFFFFFu ? -1 : (int32_t)best_act;
+}
+
+// Root-parallel search (Sec. III-B): the K trees of one root are amalgamated
+// into one root by summing each action's (N, W) over the trees in tree order;
+// the decision is the most visited action, the lowest action id on ties.  One
+// 256-thread workgroup per root; a root with a failed tree gets no decision.
+constexpr uint32_t kMergeThreads = 256;
+
+__global__ void __launch_bounds__(kMergeThreads)
+mcts_merge_kernel(const uint32_t *ws, uint64_t tree_words, uint32_t nodes_cap, uint32_t ovf_cap,
+                  uint32_t K, int32_t *best, uint32_t *merged)
+{
+    __shared__ uint32_t sn[kMaxActions];
+    __shared__ float sw[kMaxActions];
+    __shared__ uint32_t s_failed;
+    __shared__ uint64_t s_best[kMergeThreads / 64u];
+    const uint32_t r = blockIdx.x, tid = threadIdx.x;
+    for (uint32_t c = tid; c < kMaxActions; c += kMergeThreads) {
+        sn[c] = 0u;
+        sw[c] = 0.0f;
+    }
+    if (tid == 0) s_failed = 0u;
+    __syncthreads();
+    const uint32_t ovf_base = kTreeHeaderWords + nodes_cap * kNodeStride;
+    for (uint32_t k = 0; k < K; ++k) {
+        const uint32_t *W = ws + ((uint64_t)r * K + k) * tree_words;
+        const uint32_t *bnext = W + ovf_base + ovf_cap * kBlockWords;
+        if (W[kHdrFailed] != 0u) {
+            if (tid == 0) s_failed = 1u;
+            continue;   // uniform across the workgroup
+        }
+        const uint32_t nchild = W[kTreeHeaderWords + 2u];
+        for (uint32_t ci = tid; ci < nchild; ci += kMergeThreads) {
+            uint32_t blk = 0u;
+            for (uint32_t j = 0; j < (ci >> 6); ++j) blk = bnext[blk];
+            const uint32_t off = blk < nodes_cap ? kTreeHeaderWords + blk * kNodeStride + kNodeWords
+                                                 : ovf_base + (blk - nodes_cap) * kBlockWords;
+            const uint32_t *e = W + off + (ci & (kBlockEntries - 1u)) * kEntryWords;
+            const uint32_t act = e[0] & 0xFFFFu;
+            // one tree has at most one child per action: no two threads collide
+            sn[act] += e[1];
+            sw[act] += __uint_as_float(e[2]);
+        }
+        __syncthreads();
+    }
+    // most visited action, lowest id on ties: key = N << 32 | (864 - 1 - action)
+    uint64_t key = 0ull;
+    for (uint32_t c = tid; c < kMaxActions; c += kMergeThreads) {
+        const uint64_t kc = sn[c] ? ((uint64_t)sn[c] << 32) | (kMaxActions - 1u - c) : 0ull;
+        key = kc > key ? kc : key;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint64_t o = __shfl_xor(key, off, 64);
+        key = o > key ? o : key;
+    }
+    if ((tid & 63u) == 0u) s_best[tid >> 6] = key;
+    __syncthreads();
+    const bool failed = s_failed != 0u;
+    if (tid == 0) {
+        uint64_t b = 0ull;
+        for (uint32_t i = 0; i < kMergeThreads / 64u; ++i) b = s_best[i] > b ? s_best[i] : b;
+        best[r] = failed || b == 0ull ? -1 : (int32_t)(kMaxActions - 1u - (uint32_t)(b & 0xFFFFFFFFull));
+    }
+    if (merged) {
+        uint32_t *m = merged + (size_t)r * kMaxActions * 3u;
+        for (uint32_t c = tid; c < kMaxActions; c += kMergeThreads) {
+            const bool live = !failed && sn[c] != 0u;
+            m[c * 3u + 0u] = live ? c : 0xFFFFu;
+            m[c * 3u + 1u] = live ? sn[c] : 0u;
+            m[c * 3u + 2u] = live ? __float_as_uint(sw[c]) : 0u;
+        }
+    }
 }
 
 size_t mcts_tree_words(uint32_t iters)
 {
     const uint64_t nodes_cap = (uint64_t)iters + 1u;
-    const uint64_t blocks_cap = nodes_cap + nodes_cap / kBlockEntries + 2u;
-    return kTreeHeaderWords + nodes_cap * kNodeWords + blocks_cap * kBlockWords + blocks_cap;
+    const uint64_t ovf_cap = nodes_cap / kBlockEntries + 2u;
+    const uint64_t words = kTreeHeaderWords + nodes_cap * kNodeStride + ovf_cap * kBlockWords +
+                           nodes_cap + ovf_cap;
+    return (size_t)((words + 3u) & ~(uint64_t)3u);   // keep every tree 16-byte aligned
 }
 
-hipError_t launch_mcts(const uint4 *roots, uint32_t n_trees, uint32_t iters, uint32_t ppl,
+hipError_t launch_mcts(const uint4 *roots, uint32_t n_trees, uint32_t trees_per_root,
+                       uint32_t iters, uint32_t ppl,
                        uint32_t dmax, float c_uct, uint32_t k0, uint32_t k1, uint32_t tree_base,
                        const float *ln, uint32_t *ws, int32_t *best, uint32_t *kids,
                        uint32_t leaf_eval, float band, uint32_t fb_ppl, const void *net,
@@ -638,6 +738,7 @@ hipError_t launch_mcts(const uint4 *roots, uint32_t n_trees, uint32_t iters, uin
     MctsArgs a;
     a.roots = roots;
     a.n_trees = n_trees;
+    a.trees_per_root = trees_per_root;
     a.iters = iters;
     a.ppl = ppl;
     a.dmax = dmax;
@@ -649,7 +750,7 @@ hipError_t launch_mcts(const uint4 *roots, uint32_t n_trees, uint32_t iters, uin
     a.ws = ws;
     a.tree_words = mcts_tree_words(iters);
     a.nodes_cap = iters + 1u;
-    a.blocks_cap = (iters + 1u) + (iters + 1u) / kBlockEntries + 2u;
+    a.ovf_cap = (iters + 1u) / kBlockEntries + 2u;
     a.best = best;
     a.kids = kids;
     a.leaf_eval = leaf_eval;
@@ -657,6 +758,16 @@ hipError_t launch_mcts(const uint4 *roots, uint32_t n_trees, uint32_t iters, uin
     a.fb_ppl = fb_ppl;
     a.net = net;
     hipLaunchKernelGGL(mcts_tree_kernel, dim3(n_trees), dim3(64), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_mcts_merge(const uint32_t *ws, uint32_t n_roots, uint32_t trees_per_root,
+                             uint32_t iters, int32_t *best, uint32_t *merged, hipStream_t st)
+{
+    if (n_roots == 0) return hipSuccess;
+    hipLaunchKernelGGL(mcts_merge_kernel, dim3(n_roots), dim3(kMergeThreads), 0, st, ws,
+                       (uint64_t)mcts_tree_words(iters), iters + 1u, (iters + 1u) / kBlockEntries + 2u,
+                       trees_per_root, best, merged);
     return hipGetLastError();
 }
 

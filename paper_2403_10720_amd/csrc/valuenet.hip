@@ -316,14 +316,17 @@ __global__ void __launch_bounds__(64) vn_rows_kernel(VnRowsArgs a)
     bf16x8 xa[5];
 #pragma unroll
     for (uint32_t s = 0; s < 5u; ++s) xa[s] = feature8(rf, 32u * s + 8u * g);
-    if (TRAIN) {
-        // X^T for the weight gradient: feature-major, rows contiguous
+    if (TRAIN && has) {
+        // X^T for the weight gradient: feature-major, rows contiguous.  The
+        // bits are recomputed rather than extracted from the bf16 operand
+        // vectors (gfx950 builds stored element 0 for every element).
 #pragma unroll
         for (uint32_t s = 0; s < 5u; ++s)
 #pragma unroll
-            for (uint32_t i = 0; i < 8u; ++i)
-                if (has) a.xt[(size_t)(32u * s + 8u * g + i) * a.n_rows + myrow] =
-                    __builtin_bit_cast(uint16_t, xa[s][i]);
+            for (uint32_t i = 0; i < 8u; ++i) {
+                const uint32_t f = 32u * s + 8u * g + i;
+                a.xt[(size_t)f * a.n_rows + myrow] = feature_bit(rf, f) ? (uint16_t)0x3F80u : (uint16_t)0u;
+            }
     }
     uint64_t h1pos = 0ull;   // bit 4j+i: h1 of row 4g+i, column 16j+r is positive
 #pragma unroll 4

@@ -60,8 +60,9 @@ def epoch_permutation(seed: int, epoch: int, n: int):
     return a % n if n > 1 else 1, b % max(n, 1)
 
 
-def train(cfg: TrainConfig, data=None, net=None, log_every: int = 0):
-    """Train a fresh (or given) network; returns (net, history of (step, loss), seconds)."""
+def train(cfg: TrainConfig, data=None, net=None, log_every: int = 0, log=None):
+    """Train a fresh (or given) network; returns (net, history of (step, loss), seconds).
+    Every `log_every` steps the batch loss is recorded (and passed to `log`)."""
     if data is None:
         data = make_data(cfg.n_data, cfg.playouts, cfg.data_seed)
     states, persp, labels = data
@@ -87,5 +88,7 @@ def train(cfg: TrainConfig, data=None, net=None, log_every: int = 0):
                                     ws=ws, loss_out=loss if want else None)
             if want:
                 hist.append((step, float(loss.item())))
+                if log is not None:
+                    log(f"step {step} loss {hist[-1][1]:.5f}")
     torch.cuda.synchronize()
     return net, hist, time.perf_counter() - t0

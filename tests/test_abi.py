@@ -60,3 +60,21 @@ def test_argument_errors_without_device(lib):
                               None) == -1
     lib.dvc_init_states.argtypes = [vp, C.c_int64, vp, C.c_uint64, C.c_uint32, vp]
     assert lib.dvc_init_states(None, -1, None, 0, 0, None) == -1
+
+
+def test_root_parallel_argument_errors_without_device(lib):
+    import paper_2403_10720_amd as D
+    vp = C.c_void_p
+    mp = D.mcts_params(iterations=10, playouts_per_leaf=4)
+    lib.mcts_search_root_parallel.argtypes = [vp, C.c_int64, C.c_int32, C.POINTER(D.MctsParams),
+                                              C.c_uint64, C.c_uint32, vp, C.c_size_t, vp, vp, vp]
+    # no trees per root, negative roots, null buffers
+    assert lib.mcts_search_root_parallel(vp(16), 2, 0, C.byref(mp), 1, 0, vp(16), 1 << 20, vp(16),
+                                         None, None) == -1
+    assert lib.mcts_search_root_parallel(vp(16), -1, 2, C.byref(mp), 1, 0, vp(16), 1 << 20,
+                                         vp(16), None, None) == -1
+    assert lib.mcts_search_root_parallel(None, 2, 2, C.byref(mp), 1, 0, vp(16), 1 << 20, vp(16),
+                                         None, None) == -1
+    # misaligned workspace
+    assert lib.mcts_search_root_parallel(vp(16), 1, 1, C.byref(mp), 1, 0, vp(20), 1 << 30, vp(16),
+                                         None, None) == -1

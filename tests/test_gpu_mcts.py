@@ -180,3 +180,77 @@ def test_value_mode_decisions_mostly_agree_with_oracle(orc, dvc):
     best, _ = dvc.mcts_search(dev_states(roots), md, 9)
     agree = float(np.mean(best.cpu().numpy() == best_ref))
     assert agree >= 0.75, agree
+
+
+# ---------------------------------------------------------------------------
+# root-parallel search: K trees per root amalgamated by action id
+# ---------------------------------------------------------------------------
+def merged_view(dvc, kids):
+    act, n, w = dvc.children_view(kids)
+    return act.numpy(), n.numpy(), w.numpy()
+
+
+def assert_same_merged(best_ref, m_ref, best, kids, dvc):
+    act, n, w = merged_view(dvc, kids)
+    assert np.array_equal(best.cpu().numpy(), best_ref), (best.cpu().numpy(), best_ref)
+    assert np.array_equal(act, m_ref["action"].astype(np.int64))
+    assert np.array_equal(n, m_ref["n"].astype(np.int64))
+    assert np.array_equal(w.view(np.uint32), m_ref["w"].view(np.uint32))
+
+
+@pytest.mark.parametrize("K,iters,ppl", [(1, 100, 8), (4, 256, 8), (7, 65, 3)])
+def test_root_parallel_matches_oracle(orc, dvc, K, iters, ppl):
+    dp = orc.deal_params(p_min=2, p_max=4, hand=(0, 0, 4, 4, 3), pile_min=0, pile_max=16,
+                         revealed_max=8, root_draw=1)
+    roots = orc.init_states(6, dp, seed=31 + K)
+    mo = orc.mcts_params(iterations=iters, playouts_per_leaf=ppl, max_depth=4)
+    md = dvc.mcts_params(iterations=iters, playouts_per_leaf=ppl, max_depth=4)
+    best_ref, m_ref = orc.mcts_search_merged(roots, K, mo, 6, 100)
+    best, kids = dvc.mcts_search_root_parallel(dev_states(roots), K, md, 6, 100)
+    torch.cuda.synchronize()
+    assert dvc.dvc_check() == 0
+    assert_same_merged(best_ref, m_ref, best, kids, dvc)
+
+
+def test_root_parallel_fresh_deals_32_trees(orc, dvc):
+    """Fresh 2-4 player deals, 32 trees x 1024 iterations x 32 playouts per root:
+    roots 0-2 of the root-parallel workload, compared in full."""
+    dp = orc.deal_params(p_min=2, p_max=4, hand=(0, 0, 4, 4, 3), fresh=1, root_draw=1)
+    roots = orc.init_states(3, dp, seed=6)
+    mo = orc.mcts_params(iterations=1024, playouts_per_leaf=32, max_depth=4)
+    md = dvc.mcts_params(iterations=1024, playouts_per_leaf=32, max_depth=4)
+    best_ref, m_ref = orc.mcts_search_merged(roots, 32, mo, 6, 0)
+    best, kids = dvc.mcts_search_root_parallel(dev_states(roots), 32, md, 6, 0)
+    torch.cuda.synchronize()
+    assert dvc.dvc_check() == 0
+    assert_same_merged(best_ref, m_ref, best, kids, dvc)
+
+
+def test_root_parallel_malformed_root(orc, dvc):
+    dp = orc.deal_params(p_min=2, p_max=2, fresh=1, root_draw=1)
+    roots = orc.init_states(3, dp, seed=2)
+    bad = roots.copy()
+    bad[1, 3] |= np.uint32(1 << 30)
+    md = dvc.mcts_params(iterations=30, playouts_per_leaf=4)
+    best, kids = dvc.mcts_search_root_parallel(dev_states(bad), 3, md, 1, 0)
+    torch.cuda.synchronize()
+    assert dvc.dvc_check() == dvc.DVC_ESTATE
+    act, n, w = merged_view(dvc, kids)
+    assert best.cpu().numpy()[1] == -1 and np.all(act[1] == 0xFFFF) and np.all(n[1] == 0)
+    # the trees of roots 0 and 2 have ids 0..2 and 6..8
+    b0, m0 = orc.mcts_search_merged(roots[0:1], 3, orc.mcts_params(iterations=30, playouts_per_leaf=4), 1, 0)
+    b2, m2 = orc.mcts_search_merged(roots[2:3], 3, orc.mcts_params(iterations=30, playouts_per_leaf=4), 1, 6)
+    assert best.cpu().numpy()[0] == b0[0] and best.cpu().numpy()[2] == b2[0]
+    assert np.array_equal(n[0], m0[0]["n"].astype(np.int64))
+    assert np.array_equal(n[2], m2[0]["n"].astype(np.int64))
+
+
+def test_root_parallel_argument_errors(dvc):
+    st = torch.zeros((2, 4), dtype=torch.int32, device="cuda")
+    md = dvc.mcts_params(iterations=10, playouts_per_leaf=4)
+    with pytest.raises(dvc.DvcError):
+        dvc.mcts_search_root_parallel(st, 0, md, 1)
+    need = dvc.dvc_mcts_workspace_bytes(2 * 3, md)
+    small = torch.empty(need - 16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(dvc.DvcError):
+        dvc.mcts_search_root_parallel(st, 3, md, 1, workspace=small)
