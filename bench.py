@@ -41,6 +41,34 @@ INT_VALU_PEAK = 256 * 4 * 16 * 2.4e9          # lane-ops/s
 # operations on the 24-bit rows: ~200 lane-operations per guess.
 OPS_PER_GUESS = 200
 
+# HBM traffic of one launch of the rollout kernel at this workload, from two
+# profiler counter passes (FETCH_SIZE, WRITE_SIZE in KiB per dispatch), each
+# scaled by what the same counter reads for a plain 256 MiB device copy
+# (FETCH_SIZE reads half the bytes moved, WRITE_SIZE all of them).  Valid
+# only for the kernel sources it was taken on: reported as null otherwise.
+PROFILED_TRAFFIC = {"fetch_kib": 314.75, "fetch_scale": 2.0, "write_kib": 3584.0,
+                    "write_scale": 1.0,
+                    "sources_sha256": "1caca99b37856bd24efbdbfcd4fd51454f418b44dd36d21f15b74ba73ce80937"}
+KERNEL_SOURCES = ["paper_2403_10720_amd/csrc/dvc_core.hpp",
+                  "paper_2403_10720_amd/csrc/dvc_internal.hpp",
+                  "paper_2403_10720_amd/csrc/rollout.hip"]
+
+
+def sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def profiled_traffic_bytes():
+    t = PROFILED_TRAFFIC
+    if sources_sha256() != t["sources_sha256"]:
+        return None
+    return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -53,6 +81,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-search", action="store_true", help="skip the tree-search figures")
     ap.add_argument("--copy-mib", type=int, default=0, help="copy a buffer of this size (MiB)")
+    ap.add_argument("--valu-probe", action="store_true",
+                    help="also measure the issue rate of the integer operations of a guess step")
+    ap.add_argument("--cpu-sweep", action="store_true",
+                    help="also time the CPU oracle at 1, 2, 4, ... threads (the paper's CPU sweep)")
     return ap.parse_args()
 
 
@@ -139,6 +171,41 @@ def cpu_baseline(states_np, threads):
                       f"{threads} threads, {dt:.2f} s"}
 
 
+def valu_probe(D, torch, iters=4096):
+    """Issue rate (T lane-ops/s) of each integer operation of a guess step,
+    eight waves per SIMD, eight independent chains per lane."""
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    blocks = cus * 8
+    sink = torch.empty(blocks * 256, dtype=torch.int32, device="cuda")
+    out = {}
+    for op, name in enumerate(D.VALU_PROBE_OPS):
+        D.dvc_probe_valu(op, blocks, 16, sink)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        D.dvc_probe_valu(op, blocks, iters, sink)
+        e1.record()
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) / 1e3
+        out[name] = blocks * 256 * iters * 64 / t / 1e12
+    return out
+
+
+def cpu_thread_sweep(states_np, max_threads):
+    """Oracle playouts/s against host threads on 512 leaves x 256 playouts."""
+    import oracle
+    sample = states_np[:512]
+    out = []
+    t = 1
+    while t <= max_threads:
+        t0 = time.perf_counter()
+        oracle.rollout(sample, PPL, SEED, threads=t, want_winner=False, want_length=False)
+        dt = time.perf_counter() - t0
+        out.append({"threads": t, "playouts_per_s": sample.shape[0] * PPL / dt})
+        t *= 2
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -162,10 +229,13 @@ def main():
 
     def step(ev=None):
         D.dvc_init_states(N_LEAVES, params, SEED, out=states)
+        wins.zero_()
+        # the events bracket the rollout kernel alone (the seat-win table is
+        # zeroed above, so the call adds to it and launches nothing else)
         if ev is not None:
             ev[0].record(stream)
         D.dvc_rollout(states, PPL, SEED, 0, 0, winner=winner, length=length, seat_wins=wins,
-                      variant=args.variant, block=args.block, grid=args.grid)
+                      variant=args.variant, block=args.block, grid=args.grid, accumulate=True)
         if ev is not None:
             ev[1].record(stream)
 
@@ -218,21 +288,27 @@ def main():
                                "playouts (pool 0-16, 0-8 revealed per row)",
                    "leaves": N_LEAVES, "playouts_per_leaf": PPL, "seed": SEED,
                    "variant": args.variant or 4, "block": args.block, "grid": args.grid},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": INT_VALU_PEAK,
-                     "unit": "int lane-ops/s", "frac": achieved / INT_VALU_PEAK,
-                     "traffic": None},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": INT_VALU_PEAK / 1e12,
+                     "unit": "TOP/s", "frac": achieved / INT_VALU_PEAK,
+                     "traffic": profiled_traffic_bytes()},
         "rollout_kernel_ms": kern_avg_s * 1e3,
         "guess_steps_per_launch": guesses,
         "mean_game_length": float(lens.mean().item()),
         "wall_s": wall,
     }
+    if args.valu_probe:
+        out["roofline"]["probe_TOPs"] = valu_probe(D, torch)
     if not args.no_search:
         out["batched_search"] = batched_search(D, torch)
         out["root_parallel_search"] = root_parallel_search(D, torch)
         out["single_tree_search"] = single_tree_search(D, torch)
     if not args.no_cpu:
         threads = max(1, min(16, os.cpu_count() or 1))
-        out["cpu_baseline"] = cpu_baseline(states.cpu().numpy().view(np.uint32), threads)
+        host_states = states.cpu().numpy().view(np.uint32)
+        out["cpu_baseline"] = cpu_baseline(host_states, threads)
+        if args.cpu_sweep:
+            out["cpu_baseline"]["thread_sweep"] = cpu_thread_sweep(
+                host_states, 2 * (os.cpu_count() or 1))
     print(json.dumps(out), flush=True)
 
 

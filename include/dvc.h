@@ -124,16 +124,42 @@ int dvc_rollout(const dvc_state_t *leaves, int64_t n_leaves, int32_t playouts_pe
                 uint64_t seed, uint32_t tree_id, uint32_t leaf_id_base,
                 int8_t *winner, int16_t *length, uint32_t *seat_wins, void *stream);
 
-/* Rollout kernel variants, for measurement: 0 = automatic (the fastest),
- * 1 = one lane per playout, 2 = lane refill + work stealing over LDS-staged
- * leaf chunks, 3 = lane refill + work stealing over single-leaf items,
- * 4 = several playouts per lane back to back (`grid` then gives the playouts
- * per lane, 1/2/4).  block/grid 0 = automatic.  Same outputs for every variant
- * and shape.                                                                */
+/* dvc_rollout with a choice of kernel, for measurement.  variant: 0 =
+ * automatic (the shape dvc_rollout_autotune chose for this size class, else
+ * below 4M playouts variant 4 with one playout per lane; above, variant 5 if
+ * playouts_per_leaf >= 256, else variant 1), 1 = one lane per playout,
+ * 2 = lane refill + work stealing over LDS-staged leaf chunks, 3 = lane
+ * refill + work stealing over single-leaf items, 4 = several playouts per
+ * lane back to back (`grid` then gives the playouts per lane, 1/2/4),
+ * 5 = one wavefront per item of up to 64*K playouts of one leaf, lanes
+ * refilled from the item as their games end (`grid` gives K, 1/2/4/8,
+ * default 4).  block/grid 0 = automatic.  Same outputs for every variant and shape.
+ * flags: DVC_ROLLOUT_ACCUMULATE adds the wins to seat_wins instead of
+ * overwriting it (the caller zeroes it once; several calls then tally into
+ * one table).  Errors as dvc_rollout, plus DVC_EINVAL for an unknown
+ * variant, block size or flag.                                             */
+#define DVC_ROLLOUT_ACCUMULATE 1
 int dvc_rollout_ex(const dvc_state_t *leaves, int64_t n_leaves, int32_t playouts_per_leaf,
                    uint64_t seed, uint32_t tree_id, uint32_t leaf_id_base,
                    int8_t *winner, int16_t *length, uint32_t *seat_wins,
-                   int32_t variant, int32_t block, int32_t grid, void *stream);
+                   int32_t variant, int32_t block, int32_t grid, int32_t flags, void *stream);
+
+/* dvc_rollout_autotune -- runs this batch with every rollout kernel shape in
+ * a fixed candidate list (variant 4 with 1 or 2 playouts per lane, variant 1,
+ * variant 5 with 128/256/512-playout items), each launched twice with the
+ * second launch timed by HIP events on `stream`, and remembers the fastest
+ * for batches of the same size class (device, floor(log2(n_leaves *
+ * playouts_per_leaf)), playouts_per_leaf >= 256 / >= 64 / smaller): later
+ * calls with variant 0 in that class use it (a library-owned table, guarded
+ * by a lock, kept until the process ends).  The outputs are this batch's
+ * playouts, exactly as dvc_rollout writes them (every shape computes the same
+ * outputs).  chosen (host, may be NULL) receives {variant, block, grid}.
+ * Synchronizes the stream.  Errors as dvc_rollout; DVC_EINVAL for an empty
+ * batch; DVC_EHIP if an event call fails.                                  */
+int dvc_rollout_autotune(const dvc_state_t *leaves, int64_t n_leaves, int32_t playouts_per_leaf,
+                         uint64_t seed, uint32_t tree_id, uint32_t leaf_id_base,
+                         int8_t *winner, int16_t *length, uint32_t *seat_wins,
+                         int32_t *chosen /* host [3] */, void *stream);
 
 /* ---------------------------------------------------------------------------
  * Tree search (Sec. II-B, Sec. III-A).
@@ -273,6 +299,16 @@ int dvc_valuenet_train_step(void *net, const dvc_state_t *states, const uint8_t 
 int dvc_valuenet_labels(const dvc_state_t *states, int64_t n, int32_t playouts, uint64_t seed,
                         uint32_t tree_id, uint32_t index_base, uint8_t *persp_out,
                         float *labels_out, uint32_t *seat_wins_ws, void *stream);
+
+/* dvc_probe_valu -- measurement aid for the integer roofline: launches
+ * `blocks` workgroups of 256 lanes; every lane issues iters * 64 operations
+ * of one kind in eight independent chains (op 0 v_xor_b32, 1 v_add_u32,
+ * 2 v_mul_hi_u32, 3 v_mad_u64_u32, 4 v_bitop3_b32 (three-input xor), 5
+ * v_bcnt_u32_b32) and writes one folded word to sink[lane] (device, blocks *
+ * 256 words).  Time it with events on `stream` to get the device's issue rate
+ * of that operation.  DVC_EINVAL for an unknown op, blocks outside 1..65536,
+ * iters < 1 or a NULL sink.                                                  */
+int dvc_probe_valu(int32_t op, int64_t blocks, int32_t iters, uint32_t *sink, void *stream);
 
 /* ---------------------------------------------------------------------------
  * Status

@@ -81,7 +81,10 @@ def lib():
         L.dvc_check.argtypes = [vp]
         L.dvc_init_states.argtypes = [vp, i64, C.POINTER(DealParams), u64, u32, vp]
         L.dvc_rollout.argtypes = [vp, i64, i32, u64, u32, u32, vp, vp, vp, vp]
-        L.dvc_rollout_ex.argtypes = [vp, i64, i32, u64, u32, u32, vp, vp, vp, i32, i32, i32, vp]
+        L.dvc_rollout_ex.argtypes = [vp, i64, i32, u64, u32, u32, vp, vp, vp, i32, i32, i32, i32,
+                                     vp]
+        L.dvc_rollout_autotune.argtypes = [vp, i64, i32, u64, u32, u32, vp, vp, vp, vp, vp]
+        L.dvc_probe_valu.argtypes = [i32, i64, i32, vp, vp]
         L.dvc_valuenet_bytes.restype = C.c_size_t
         L.dvc_valuenet_init.argtypes = [vp, u64, vp]
         L.dvc_valuenet_set_params.argtypes = [vp, vp, vp]
@@ -152,10 +155,11 @@ def dvc_init_states(n: int, params: DealParams, seed: int, index_base: int = 0, 
 
 def dvc_rollout(leaves: torch.Tensor, playouts_per_leaf: int, seed: int, tree_id: int = 0,
                 leaf_id_base: int = 0, winner=True, length=True, seat_wins=True, variant: int = 0,
-                block: int = 0, grid: int = 0, stream=None):
+                block: int = 0, grid: int = 0, accumulate: bool = False, stream=None):
     """Random playouts from every leaf.  Returns (winner int8 [n*ppl] | None,
     length int16 [n*ppl] | None, seat_wins int32 [n, 4] | None); pass
-    preallocated tensors instead of True to reuse memory."""
+    preallocated tensors instead of True to reuse memory.  accumulate=True
+    adds to the given seat_wins instead of overwriting it."""
     _check_dev(leaves, torch.int32, None, "leaves")
     if leaves.dim() != 2 or leaves.shape[1] != 4:
         raise ValueError("leaves must have shape (n, 4)")
@@ -176,9 +180,50 @@ def dvc_rollout(leaves: torch.Tensor, playouts_per_leaf: int, seed: int, tree_id
     sw = prep(seat_wins, torch.int32, (n, 4))
     rc = lib().dvc_rollout_ex(_ptr(leaves), n, playouts_per_leaf, seed & (2**64 - 1), tree_id,
                               leaf_id_base, _ptr(w), _ptr(ln), _ptr(sw), variant, block, grid,
-                              _stream(stream))
+                              1 if accumulate else 0, _stream(stream))
     _raise(rc, "dvc_rollout")
     return w, ln, sw
+
+
+def dvc_rollout_autotune(leaves: torch.Tensor, playouts_per_leaf: int, seed: int, tree_id: int = 0,
+                         leaf_id_base: int = 0, winner=True, length=True, seat_wins=True,
+                         stream=None):
+    """Time every rollout kernel shape on this batch and remember the fastest
+    for its size class (used by later calls with variant 0).  Returns
+    ((variant, block, grid), (winner, length, seat_wins)) -- the outputs are
+    the batch's playouts, as dvc_rollout writes them."""
+    _check_dev(leaves, torch.int32, None, "leaves")
+    n = leaves.shape[0]
+    dev = leaves.device
+    total = n * playouts_per_leaf
+
+    def prep(x, dtype, shape):
+        if x is True:
+            return torch.empty(shape, dtype=dtype, device=dev)
+        if x is False or x is None:
+            return None
+        _check_dev(x, dtype, shape, "output")
+        return x
+
+    w = prep(winner, torch.int8, (total,))
+    ln = prep(length, torch.int16, (total,))
+    sw = prep(seat_wins, torch.int32, (n, 4))
+    chosen = (C.c_int32 * 3)()
+    rc = lib().dvc_rollout_autotune(_ptr(leaves), n, playouts_per_leaf, seed & (2**64 - 1),
+                                    tree_id, leaf_id_base, _ptr(w), _ptr(ln), _ptr(sw),
+                                    C.cast(chosen, C.c_void_p), _stream(stream))
+    _raise(rc, "dvc_rollout_autotune")
+    return (chosen[0], chosen[1], chosen[2]), (w, ln, sw)
+
+
+VALU_PROBE_OPS = ["v_xor_b32", "v_add_u32", "v_mul_hi_u32", "v_mad_u64_u32", "v_bitop3_b32",
+                  "v_bcnt_u32_b32"]
+
+
+def dvc_probe_valu(op: int, blocks: int, iters: int, sink: torch.Tensor, stream=None):
+    """Launch the integer issue-rate probe (see dvc.h); sink: int32 [blocks * 256]."""
+    _check_dev(sink, torch.int32, (blocks * 256,), "sink")
+    _raise(lib().dvc_probe_valu(op, blocks, iters, _ptr(sink), _stream(stream)), "dvc_probe_valu")
 
 
 def dvc_mcts_workspace_bytes(n_trees: int, params: MctsParams) -> int:
@@ -229,12 +274,16 @@ def mcts_search_root_parallel(roots: torch.Tensor, trees_per_root: int, params: 
 
 
 def mcts_tree_stats(workspace: torch.Tensor, n_trees: int, params: MctsParams) -> dict:
-    """Per-tree counters the search leaves at the start of each tree's workspace."""
+    """Per-tree counters the search leaves at the start of each tree's workspace,
+    including shader clock cycles spent in each phase of the iterations."""
     per_tree = dvc_mcts_workspace_bytes(1, params)
-    w = workspace[:n_trees * per_tree].view(n_trees, per_tree)[:, :32].contiguous().view(torch.int32)
-    w = w.cpu()
+    h = workspace[:n_trees * per_tree].view(n_trees, per_tree)[:, :64].contiguous().cpu()
+    w = h.view(torch.int32)
+    cyc = h.view(torch.int64)[:, 4:8]
     return {"nodes": w[:, 0], "overflow_blocks": w[:, 1], "root_visits": w[:, 2], "net_leaves": w[:, 3],
-            "played_leaves": w[:, 4], "sampler_fallbacks": w[:, 5], "failed": w[:, 6]}
+            "played_leaves": w[:, 4], "sampler_fallbacks": w[:, 5], "failed": w[:, 6],
+            "cycles_sample": cyc[:, 0], "cycles_descend": cyc[:, 1], "cycles_evaluate": cyc[:, 2],
+            "cycles_backprop": cyc[:, 3]}
 
 
 def children_view(kids: torch.Tensor):

@@ -3,7 +3,9 @@
 // stream.  Nothing here allocates per call.
 #include <atomic>
 #include <cmath>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "dvc.h"
@@ -157,16 +159,46 @@ int dvc_init_states(dvc_state_t *out, int64_t n, const dvc_deal_params *p, uint6
                                         (hipStream_t)stream));
 }
 
-int dvc_rollout_ex(const dvc_state_t *leaves, int64_t n_leaves, int32_t ppl, uint64_t seed,
-                   uint32_t tree_id, uint32_t leaf_id_base, int8_t *winner, int16_t *length,
-                   uint32_t *seat_wins, int32_t variant, int32_t block, int32_t grid, void *stream)
+// ---------------------------------------------------------------------------
+// rollout launch shapes: an explicit variant, else the autotuner's choice for
+// the batch's size class on this device, else a rule from measurements
+// ---------------------------------------------------------------------------
+struct Shape {
+    int variant, block, grid;
+};
+
+static std::mutex g_tune_mutex;
+static std::map<std::tuple<int, int, int>, Shape> g_tuned;   // (device, log2 total, ppl class)
+
+static std::tuple<int, int, int> tune_key(uint64_t total, int32_t ppl)
 {
-    if (n_leaves < 0 || ppl < 1 || (n_leaves > 0 && leaves == nullptr)) return DVC_EINVAL;
-    if ((uint64_t)n_leaves * (uint64_t)ppl >= (1ull << 32)) return DVC_EINVAL;
-    if (variant < 0 || variant > 4) return DVC_EINVAL;
-    if (block != 0 && block != 64 && block != 128 && block != 256 && block != 512) return DVC_EINVAL;
-    if (grid < 0) return DVC_EINVAL;
-    hipStream_t st = (hipStream_t)stream;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = -1;
+    int lg = 0;
+    while ((2ull << lg) <= total) ++lg;
+    return std::make_tuple(dev, lg, ppl >= 256 ? 2 : ppl >= 64 ? 1 : 0);
+}
+
+static Shape automatic_shape(uint64_t total, int32_t ppl)
+{
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mutex);
+        auto it = g_tuned.find(tune_key(total, ppl));
+        if (it != g_tuned.end()) return it->second;
+    }
+    // measured on gfx950: up to ~4M playouts many short wavefronts win
+    // (variant 4, one playout per lane); beyond that in-wave refill over
+    // 256-playout items when leaves have at least 256 playouts (variant 5),
+    // else one lane per playout (variant 1)
+    if (total < (4ull << 20)) return Shape{4, 0, 1};
+    return ppl >= 256 ? Shape{5, 0, 4} : Shape{1, 0, 0};
+}
+
+static int rollout_impl(const dvc_state_t *leaves, int64_t n_leaves, int32_t ppl, uint64_t seed,
+                        uint32_t tree_id, uint32_t leaf_id_base, int8_t *winner, int16_t *length,
+                        uint32_t *seat_wins, Shape sh, int32_t flags, hipStream_t st)
+{
+    const int v = sh.variant, block = sh.block, grid = sh.grid;
     RolloutArgs a;
     a.leaves = reinterpret_cast<const uint4 *>(leaves);
     a.n_leaves = (uint32_t)n_leaves;
@@ -176,11 +208,15 @@ int dvc_rollout_ex(const dvc_state_t *leaves, int64_t n_leaves, int32_t ppl, uin
     a.k1 = (uint32_t)(seed >> 32);
     a.tree = tree_id;
     a.leaf_base = leaf_id_base;
-    // a chunk never spans more than kStageLeaves leaves
+    // variant 2: a chunk never spans more than kStageLeaves leaves
     const uint64_t max_chunk = (uint64_t)(kStageLeaves - 1u) * (uint64_t)ppl;
     a.chunk = (uint32_t)(max_chunk < 256u ? max_chunk : 256u);
-    // single-leaf items of at most one playout per lane
-    a.item_chunk = (uint32_t)(ppl < 64 ? ppl : 64);
+    // single-leaf items: variant 3 one playout per lane, variant 5 up to
+    // 64*K playouts (K = grid, default 4)
+    const int k5 = grid > 0 ? grid : 4;
+    if (v == 5 && k5 != 1 && k5 != 2 && k5 != 4 && k5 != 8) return DVC_EINVAL;
+    const uint32_t per_item = v == 5 ? 64u * (uint32_t)k5 : 64u;
+    a.item_chunk = (uint32_t)ppl < per_item ? (uint32_t)ppl : per_item;
     a.parts = ((uint32_t)ppl + a.item_chunk - 1u) / a.item_chunk;
     const uint64_t n_items = (uint64_t)n_leaves * a.parts;
     if (n_items >= (1ull << 32)) return DVC_EINVAL;
@@ -192,14 +228,91 @@ int dvc_rollout_ex(const dvc_state_t *leaves, int64_t n_leaves, int32_t ppl, uin
     a.seat_wins = seat_wins;
     a.stats = nullptr;
     if (a.total == 0) return DVC_OK;
-    if (seat_wins) {
+    if (seat_wins && !(flags & DVC_ROLLOUT_ACCUMULATE)) {
         hipError_t e = launch_fill_u32(seat_wins, (uint64_t)n_leaves * 4u, 0u, st);
         if (e != hipSuccess) return DVC_EHIP;
     }
-    // automatic: one playout per lane (variant 4 with one playout per lane
-    // was the fastest at the leaf-parallel size, variant 1 within 8% above it)
-    const int v = variant == 0 ? 4 : variant;
     return status_of(launch_rollout(a, v, block, grid, st));
+}
+
+static int rollout_args_ok(const dvc_state_t *leaves, int64_t n_leaves, int32_t ppl)
+{
+    if (n_leaves < 0 || ppl < 1 || (n_leaves > 0 && leaves == nullptr)) return DVC_EINVAL;
+    if ((uint64_t)n_leaves * (uint64_t)ppl >= (1ull << 32)) return DVC_EINVAL;
+    return DVC_OK;
+}
+
+int dvc_rollout_ex(const dvc_state_t *leaves, int64_t n_leaves, int32_t ppl, uint64_t seed,
+                   uint32_t tree_id, uint32_t leaf_id_base, int8_t *winner, int16_t *length,
+                   uint32_t *seat_wins, int32_t variant, int32_t block, int32_t grid, int32_t flags,
+                   void *stream)
+{
+    if ((flags & ~DVC_ROLLOUT_ACCUMULATE) != 0) return DVC_EINVAL;
+    const int ok = rollout_args_ok(leaves, n_leaves, ppl);
+    if (ok != DVC_OK) return ok;
+    if (variant < 0 || variant > 5) return DVC_EINVAL;
+    if (block != 0 && block != 64 && block != 128 && block != 256 && block != 512) return DVC_EINVAL;
+    if (grid < 0) return DVC_EINVAL;
+    const Shape sh = variant != 0 ? Shape{variant, block, grid}
+                                  : automatic_shape((uint64_t)n_leaves * (uint64_t)ppl, ppl);
+    return rollout_impl(leaves, n_leaves, ppl, seed, tree_id, leaf_id_base, winner, length,
+                        seat_wins, sh, flags, (hipStream_t)stream);
+}
+
+int dvc_rollout_autotune(const dvc_state_t *leaves, int64_t n_leaves, int32_t ppl, uint64_t seed,
+                         uint32_t tree_id, uint32_t leaf_id_base, int8_t *winner, int16_t *length,
+                         uint32_t *seat_wins, int32_t *chosen, void *stream)
+{
+    const int ok = rollout_args_ok(leaves, n_leaves, ppl);
+    if (ok != DVC_OK) return ok;
+    const uint64_t total = (uint64_t)n_leaves * (uint64_t)ppl;
+    if (total == 0) return DVC_EINVAL;
+    static const Shape kCandidates[] = {{4, 0, 1}, {1, 0, 0}, {4, 0, 2}, {5, 0, 2}, {5, 0, 4},
+                                        {5, 0, 8}};
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) hipEventDestroy(e0);
+        return DVC_EHIP;
+    }
+    int status = DVC_OK;
+    Shape best = kCandidates[0];
+    float best_ms = 0.0f;
+    bool have = false;
+    for (const Shape &c : kCandidates) {
+        // the first launch warms up, the second is timed
+        for (int rep = 0; rep < 2 && status == DVC_OK; ++rep) {
+            if (rep == 1 && hipEventRecord(e0, st) != hipSuccess) status = DVC_EHIP;
+            if (status == DVC_OK)
+                status = rollout_impl(leaves, n_leaves, ppl, seed, tree_id, leaf_id_base, winner,
+                                      length, seat_wins, c, 0, st);
+            if (status == DVC_OK && rep == 1 && hipEventRecord(e1, st) != hipSuccess)
+                status = DVC_EHIP;
+        }
+        float ms = 0.0f;
+        if (status == DVC_OK &&
+            (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            status = DVC_EHIP;
+        if (status != DVC_OK) break;
+        if (!have || ms < best_ms) {
+            best = c;
+            best_ms = ms;
+            have = true;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (status != DVC_OK) return status;
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mutex);
+        g_tuned[tune_key(total, ppl)] = best;
+    }
+    if (chosen) {
+        chosen[0] = best.variant;
+        chosen[1] = best.block;
+        chosen[2] = best.grid;
+    }
+    return DVC_OK;
 }
 
 int dvc_rollout(const dvc_state_t *leaves, int64_t n_leaves, int32_t ppl, uint64_t seed,
@@ -207,7 +320,7 @@ int dvc_rollout(const dvc_state_t *leaves, int64_t n_leaves, int32_t ppl, uint64
                 uint32_t *seat_wins, void *stream)
 {
     return dvc_rollout_ex(leaves, n_leaves, ppl, seed, tree_id, leaf_id_base, winner, length,
-                          seat_wins, 0, 0, 0, stream);
+                          seat_wins, 0, 0, 0, 0, stream);
 }
 
 size_t dvc_mcts_workspace_bytes(int64_t n_trees, const dvc_mcts_params *params)
@@ -270,6 +383,14 @@ int mcts_search_root_parallel(const dvc_state_t *roots, int64_t n_roots, int32_t
 {
     return run_search(roots, n_roots, trees_per_root, true, params, seed, tree_id_base, workspace,
                       workspace_bytes, best_action, merged_children, stream);
+}
+
+int dvc_probe_valu(int32_t op, int64_t blocks, int32_t iters, uint32_t *sink, void *stream)
+{
+    if (op < 0 || op > 5 || blocks < 1 || blocks > 65536 || iters < 1 || sink == nullptr)
+        return DVC_EINVAL;
+    return status_of(launch_valu_probe(op, (uint32_t)blocks, (uint32_t)iters, sink,
+                                       (hipStream_t)stream));
 }
 
 size_t dvc_valuenet_bytes(void) { return vn_bytes(); }

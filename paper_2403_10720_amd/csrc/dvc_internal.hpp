@@ -56,6 +56,8 @@ hipError_t launch_mcts(const uint4 *roots, uint32_t n_trees, uint32_t trees_per_
                        hipStream_t st);
 hipError_t launch_mcts_merge(const uint32_t *ws, uint32_t n_roots, uint32_t trees_per_root,
                              uint32_t iters, int32_t *best, uint32_t *merged, hipStream_t st);
+hipError_t launch_valu_probe(int op, uint32_t blocks, uint32_t iters, uint32_t *sink,
+                             hipStream_t st);
 size_t vn_bytes();
 size_t vn_train_ws_bytes(uint32_t batch);
 hipError_t launch_vn_init(void *net, uint32_t k0, uint32_t k1, hipStream_t st);

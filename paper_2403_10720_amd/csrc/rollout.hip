@@ -563,6 +563,109 @@ __global__ void __launch_bounds__(256) rollout_static(RolloutArgs a)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Variant 5: one wavefront per single-leaf item of up to 64*K playouts.  A
+// lane whose game ended takes the item's next playout at once (ballot +
+// mbcnt prefix over the lanes that finished); the leaf's start state stays
+// in registers, so a restart is a handful of register moves and no memory
+// access.  Lanes idle only while the item's last games finish.  Seat wins
+// are counted per lane in two registers of 16-bit fields and summed across
+// the wave once at the end.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) rollout_refill(RolloutArgs a)
+{
+    __shared__ uint8_t tab[kKthTableBytes];
+    fill_kth_table(tab);
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t item = blockIdx.x * 4u + (threadIdx.x >> 6);
+    if (item >= a.n_items) return;                       // whole wavefront
+    const uint32_t leaf = item / a.parts;
+    const uint32_t p0 = (item - leaf * a.parts) * a.item_chunk;
+    const uint32_t p1 = min(p0 + a.item_chunk, a.ppl);
+    uint32_t w0, w1, w2, w3;
+    load_uniform_state(a.leaves, leaf, w0, w1, w2, w3);
+    State s0;
+    const bool ok = decode(w0, w1, w2, w3, s0);
+    const uint32_t alive0 = alive_mask(s0);
+    if (!ok || __popc(alive0) == 1) {
+        // a decided or malformed leaf finishes the whole item at once
+        const int8_t wv = ok ? (int8_t)__builtin_ctz(alive0) : (int8_t)-1;
+        const int16_t lv = ok ? (int16_t)0 : (int16_t)-1;
+        for (uint32_t p = p0 + lane; p < p1; p += 64u) {
+            const uint32_t j = leaf * a.ppl + p;
+            if (a.winner) a.winner[j] = wv;
+            if (a.length) a.length[j] = lv;
+        }
+        if (lane == 0) {
+            if (!ok)
+                atomicOr(&g_error_word, kErrState);
+            else if (a.seat_wins)
+                atomicAdd(&a.seat_wins[(size_t)leaf * 4u + (uint32_t)wv], p1 - p0);
+        }
+        return;
+    }
+    const uint32_t trk1 = a.tree ^ a.k1;
+    const uint64_t pl = (uint64_t)(a.leaf_base + leaf) * kPhiloxM1;
+    const uint32_t ka = (uint32_t)(pl >> 32) ^ a.k0, kb = (uint32_t)pl;
+    uint32_t p = p0 + lane;
+    bool active = p < p1;
+    uint32_t next = p0 + 64u;                             // wave-uniform
+    State s = s0;
+    PlayoutKey pk = {ka ^ p, kb, 0u, 0u};
+    uint32_t len = 0u, winner = 0u;
+    uint32_t wins01 = 0u, wins23 = 0u;                    // 16-bit counters
+    while (__ballot(active) != 0ull) {
+        bool over = false;
+        if (active) {
+            const Words w = step_words(pk, trk1, a.k0, a.k1);
+            over = guess_step(s, w, winner, tab);
+            next_step(pk);
+            ++len;
+            if (!over && len >= kMaxGuesses) {
+                atomicOr(&g_error_word, kErrLimit);
+                over = true;
+                winner = 4u;
+            }
+        }
+        const uint64_t fin = __ballot(over);
+        if (fin != 0ull) {
+            if (over) {
+                const uint32_t j = leaf * a.ppl + p;
+                if (a.winner) a.winner[j] = winner < 4u ? (int8_t)winner : (int8_t)-1;
+                if (a.length) a.length[j] = (int16_t)len;
+                const uint32_t inc = winner < 4u ? 1u << ((winner & 1u) * 16u) : 0u;
+                if (winner < 2u) wins01 += inc; else wins23 += inc;
+            }
+            const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
+                (uint32_t)(fin >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)fin, 0u));
+            const uint32_t np = next + rank;
+            next += (uint32_t)__popcll(fin);
+            if (over) {
+                p = np;
+                active = np < p1;
+                s = s0;
+                pk.a = ka ^ np;
+                pk.b = kb;
+                pk.gm_lo = 0u;
+                pk.gm_hi = 0u;
+                len = 0u;
+            }
+        }
+    }
+    if (a.seat_wins) {
+        for (int off = 32; off > 0; off >>= 1) {
+            wins01 += __shfl_xor(wins01, off, 64);
+            wins23 += __shfl_xor(wins23, off, 64);
+        }
+        if (lane < 4u) {
+            const uint32_t c = lane == 0u ? wins01 & 0xFFFFu : lane == 1u ? wins01 >> 16
+                             : lane == 2u ? wins23 & 0xFFFFu : wins23 >> 16;
+            if (c) atomicAdd(&a.seat_wins[(size_t)leaf * 4u + lane], c);
+        }
+    }
+}
+
 __global__ void fill_u32(uint32_t *p, uint64_t n, uint32_t v)
 {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -603,6 +706,12 @@ hipError_t launch_rollout(const RolloutArgs &a, int variant, int block, int grid
         case 2: hipLaunchKernelGGL(rollout_static<2>, dim3(blocks), dim3(256), 0, st, a); break;
         default: hipLaunchKernelGGL(rollout_static<4>, dim3(blocks), dim3(256), 0, st, a); break;
         }
+        return hipGetLastError();
+    }
+    if (variant == 5) {
+        // one wavefront per item, four per workgroup
+        const uint32_t blocks = (a.n_items + 3u) / 4u;
+        hipLaunchKernelGGL(rollout_refill, dim3(blocks), dim3(256), 0, st, a);
         return hipGetLastError();
     }
     int waves = block > 0 ? block / 64 : 4;

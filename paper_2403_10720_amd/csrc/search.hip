@@ -39,8 +39,11 @@ constexpr uint32_t kBlockWords = kBlockEntries * kEntryWords;
 // loads fetches both
 constexpr uint32_t kNodeStride = kNodeWords + kBlockWords;
 // tree header: nodes, overflow blocks, root visits, network leaves, played
-// leaves, sampler fallbacks, failed flag
+// leaves, sampler fallbacks, failed flag; from word 8, four 64-bit sums of
+// shader clock cycles spent sampling worlds, descending, evaluating leaves
+// and back-propagating
 constexpr uint32_t kHdrFailed = 6;
+constexpr uint32_t kHdrCycles = 8;
 constexpr uint32_t kTreeHeaderWords = 16;
 constexpr uint32_t kNoBlock = 0xFFFFFFFFu;
 constexpr uint32_t kDetAttempts = 64;
@@ -379,9 +382,11 @@ __global__ void __launch_bounds__(64) mcts_tree_kernel(MctsArgs a)
     uint32_t n_net = 0u, n_played = 0u, n_sampler_fallback = 0u;   // statistics
     bool failed = false, have_fallback = false;
     State fallback = R;
+    uint64_t cyc[4] = {0u, 0u, 0u, 0u};   // shader clock per phase (statistics)
     __syncthreads();
 
     for (uint32_t it = 0; it < a.iters && !failed; ++it) {
+        const uint64_t t0 = clock64();
         // ---- 1. sample a world: attempt `lane`, lowest success wins ------
         State S;
         const bool got = det_attempt(R, lane, it, tr, a.k0, a.k1, S, tab);
@@ -407,6 +412,8 @@ __global__ void __launch_bounds__(64) mcts_tree_kernel(MctsArgs a)
             ++n_sampler_fallback;
         }
 
+        const uint64_t t1 = clock64();
+        cyc[0] += t1 - t0;
         // ---- 2. descend ----------------------------------------------------
         uint32_t node = 0u, node_n = n_root, depth = 0u, np = 0u, winner = 0u;
         bool term = false;
@@ -513,6 +520,8 @@ __global__ void __launch_bounds__(64) mcts_tree_kernel(MctsArgs a)
             __syncthreads();
         }
 
+        const uint64_t t2 = clock64();
+        cyc[1] += t2 - t1;
         // ---- 3. evaluate the leaf: playouts, or the value network ---------
         uint32_t wins0 = 0u, wins1 = 0u, wins2 = 0u, wins3 = 0u;
         float vals[4] = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -562,10 +571,16 @@ __global__ void __launch_bounds__(64) mcts_tree_kernel(MctsArgs a)
                     pk.gm_hi = 0u;
                     bool over = false;
                     uint32_t len = 0u;
+                    // the words of step g+1 do not depend on the game, so
+                    // they are computed while step g runs (one wavefront per
+                    // tree has no other wavefront to hide latencies behind)
+                    Words wd = step_words(pk, trk1, a.k0, a.k1);
+                    next_step(pk);
                     while (!over) {
-                        const Words wd = step_words(pk, trk1, a.k0, a.k1);
-                        over = guess_step(s, wd, w, tab);
+                        const Words wn = step_words(pk, trk1, a.k0, a.k1);
                         next_step(pk);
+                        over = guess_step(s, wd, w, tab);
+                        wd = wn;
                         if (++len >= kMaxGuesses && !over) {
                             atomicOr(&g_error_word, kErrLimit);
                             over = true;
@@ -588,6 +603,8 @@ __global__ void __launch_bounds__(64) mcts_tree_kernel(MctsArgs a)
             vals[3] = (float)wins3;
         }
 
+        const uint64_t t3 = clock64();
+        cyc[2] += t3 - t2;
         // ---- 4. back-propagation --------------------------------------------
         n_root += nplay;
         if (lane < np) {
@@ -598,6 +615,7 @@ __global__ void __launch_bounds__(64) mcts_tree_kernel(MctsArgs a)
             W[e + 2u] = __float_as_uint(__uint_as_float(W[e + 2u]) + wc);
         }
         __syncthreads();
+        cyc[3] += clock64() - t3;
     }
 
     // ---- decision and root statistics ----------------------------------------
@@ -609,6 +627,10 @@ __global__ void __launch_bounds__(64) mcts_tree_kernel(MctsArgs a)
         W[4] = n_played;
         W[5] = n_sampler_fallback;
         W[kHdrFailed] = failed ? 1u : 0u;
+        for (uint32_t q = 0; q < 4u; ++q) {
+            W[kHdrCycles + 2u * q] = (uint32_t)cyc[q];
+            W[kHdrCycles + 2u * q + 1u] = (uint32_t)(cyc[q] >> 32);
+        }
     }
     if (failed) {
         if (lane == 0 && a.best) a.best[t] = -1;

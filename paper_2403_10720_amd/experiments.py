@@ -17,6 +17,15 @@ positions next to the noise floor of those estimates.
 root_parallel_vs_single(): K independent trees per root amalgamated at the
 root (the paper's decomposition) against one tree with K times the
 iterations.
+
+search_phases(): where the iterations of the three search workloads spend
+their cycles (sampling a world, descending, evaluating, back-propagating).
+
+gpu_scaling(): playouts/s against the number of wavefronts (the paper's
+GPU thread sweep).
+
+ppl_autotune(): playouts per leaf of the batched search picked by
+measurement, with its root-move agreement.
 """
 from __future__ import annotations
 
@@ -145,11 +154,108 @@ def root_parallel_vs_single(n_roots=256, trees_per_root=32, iterations=1024, ppl
     }
 
 
+SEARCH_WORKLOADS = {
+    "single tree, fresh 2-player deal, 2000 x 16": (1, dict(p_min=2, p_max=2, fresh=1, root_draw=1), 2000, 16, 1),
+    "batched, 2048 mid-game roots, 1024 x 32": (2048, dict(p_min=2, p_max=4, hand=(0, 0, 4, 4, 3), pile_min=0,
+                                                       pile_max=16, revealed_max=8, root_draw=1), 1024, 32, 3),
+    "1024 fresh 2-4 player deals, 4096 x 64": (1024, ROOT_DEAL, 4096, 64, 5),
+}
+
+
+def search_phases(net=None):
+    """Share of each search phase in the shader clock cycles of the iterations
+    (per-tree counters kept by the kernel), for the three search workloads and,
+    with a network, the value-mode search of the last one (band 0: every leaf
+    scored by the network)."""
+    out = {}
+    work = dict(SEARCH_WORKLOADS)
+    if net is not None:
+        work["1024 fresh deals, 4096 iterations, value mode, band 0"] = \
+            SEARCH_WORKLOADS["1024 fresh 2-4 player deals, 4096 x 64"]
+    for name, (n, deal, iters, ppl, seed) in work.items():
+        roots = dvc_init_states(n, deal_params(**deal), seed)
+        if "value mode" in name:
+            mp = mcts_params(iterations=iters, playouts_per_leaf=1, max_depth=4, leaf_eval=1,
+                             fallback_band=0.0, fallback_playouts=ppl, valuenet=net)
+        else:
+            mp = mcts_params(iterations=iters, playouts_per_leaf=ppl, max_depth=4)
+        ws = torch.empty(dvc_mcts_workspace_bytes(n, mp), dtype=torch.uint8, device=roots.device)
+        mcts_search(roots, mp, seed, workspace=ws, want_children=False)
+        torch.cuda.synchronize()
+        st = mcts_tree_stats(ws, n, mp)
+        cyc = torch.stack([st["cycles_sample"], st["cycles_descend"], st["cycles_evaluate"],
+                           st["cycles_backprop"]], 1).double()
+        tot = cyc.sum(1)
+        frac = (cyc / tot[:, None]).mean(0).tolist()
+        out[name] = {"cycles_per_iteration": float((tot / iters).mean()),
+                     "sample": frac[0], "descend": frac[1], "evaluate": frac[2], "backprop": frac[3]}
+    return out
+
+
+def gpu_scaling(waves=(1, 4, 16, 64, 256, 1024, 2048, 4096, 8192), games_per_lane=16, reps=3):
+    """Playouts/s against the number of wavefronts running playouts (the
+    paper's simulations/s against GPU threads, Sec. IV): the persistent
+    refill kernel (variant 3) with W one-wavefront workgroups, each lane
+    playing about `games_per_lane` games from two-player mid-game leaves
+    (256 playouts per leaf)."""
+    from . import dvc_rollout
+    out = []
+    deal = deal_params(p_min=2, p_max=2, pile_min=0, pile_max=16, revealed_max=8)
+    for w in waves:
+        n_leaves = max(1, w * 64 * games_per_lane // 256)
+        st = dvc_init_states(n_leaves, deal, 2)
+        wins = torch.empty((n_leaves, 4), dtype=torch.int32, device=st.device)
+        run = lambda: dvc_rollout(st, 256, 2, winner=False, length=False, seat_wins=wins,
+                                  variant=3, block=64, grid=w)
+        run()
+        ts = []
+        for _ in range(reps):
+            _, t = _timed(run)
+            ts.append(t)
+        t = sorted(ts)[len(ts) // 2]
+        out.append({"wavefronts": w, "lanes": 64 * w, "playouts": n_leaves * 256,
+                    "playouts_per_s": n_leaves * 256 / t})
+    return out
+
+
+def ppl_autotune(n_trees=2048, iterations=1024, ppls=(4, 8, 16, 32, 64, 128), seed=3,
+                 tolerance=0.02):
+    """Playouts per leaf for the batched search, chosen by measurement: every
+    candidate is timed on the batched workload and its decisions compared with
+    the 32-playout search; the pick is the fastest candidate whose agreement
+    with it is within `tolerance` of what the 32-playout search reaches with
+    itself under another seed.  Parity and the headline stay at 32."""
+    roots = dvc_init_states(n_trees, deal_params(**SEARCH_WORKLOADS[
+        "batched, 2048 mid-game roots, 1024 x 32"][1]), seed)
+    ws = torch.empty(max(dvc_mcts_workspace_bytes(n_trees, mcts_params(iterations=iterations,
+                                                                       playouts_per_leaf=p))
+                         for p in ppls), dtype=torch.uint8, device=roots.device)
+
+    def search(ppl, sd):
+        mp = mcts_params(iterations=iterations, playouts_per_leaf=ppl, max_depth=4)
+        return _timed(lambda: mcts_search(roots, mp, sd, workspace=ws, want_children=False))
+
+    (ref, _), _ = search(32, seed)
+    (ref2, _), _ = search(32, seed + 1000)
+    ceiling = float((ref == ref2).float().mean().item())
+    rows = []
+    for ppl in ppls:
+        search(ppl, seed + 1)                       # warm
+        (best, _), t = search(ppl, seed + 1)
+        rows.append({"playouts_per_leaf": ppl, "decisions_per_s": n_trees / t,
+                     "agreement_with_32": float((best == ref).float().mean().item())})
+    ok = [r for r in rows if r["agreement_with_32"] >= ceiling - tolerance]
+    pick = max(ok, key=lambda r: r["decisions_per_s"]) if ok else None
+    return {"trees": n_trees, "iterations": iterations, "self_agreement_32": ceiling,
+            "candidates": rows, "chosen": pick}
+
+
 def main(argv=None):
     import argparse
     import json
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
-    ap.add_argument("--what", choices=["value", "root-parallel", "all"], default="all")
+    ap.add_argument("--what", choices=["value", "root-parallel", "phases", "scaling", "ppl", "all"],
+                    default="all")
     ap.add_argument("--trees", type=int, default=1024)
     ap.add_argument("--iterations", type=int, default=4096)
     ap.add_argument("--epochs", type=int, default=20)
@@ -163,6 +269,13 @@ def main(argv=None):
         print(json.dumps({"value_vs_rollout": out}), flush=True)
     if args.what in ("root-parallel", "all"):
         print(json.dumps({"root_parallel_vs_single": root_parallel_vs_single()}), flush=True)
+    if args.what in ("ppl", "all"):
+        print(json.dumps({"ppl_autotune": ppl_autotune()}), flush=True)
+    if args.what in ("scaling", "all"):
+        print(json.dumps({"gpu_scaling": gpu_scaling()}), flush=True)
+    if args.what in ("phases", "all"):
+        from . import dvc_valuenet_init
+        print(json.dumps({"search_phases": search_phases(dvc_valuenet_init(44))}), flush=True)
 
 
 if __name__ == "__main__":

@@ -51,12 +51,14 @@ def test_status_strings(lib):
 def test_argument_errors_without_device(lib):
     vp = C.c_void_p
     lib.dvc_rollout_ex.argtypes = [vp, C.c_int64, C.c_int32, C.c_uint64, C.c_uint32, C.c_uint32,
-                                   vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, vp]
-    assert lib.dvc_rollout_ex(None, -1, 8, 0, 0, 0, None, None, None, 0, 0, 0, None) == -1
-    assert lib.dvc_rollout_ex(None, 4, 8, 0, 0, 0, None, None, None, 0, 0, 0, None) == -1
-    assert lib.dvc_rollout_ex(None, 0, 0, 0, 0, 0, None, None, None, 0, 0, 0, None) == -1
+                                   vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, vp]
+    assert lib.dvc_rollout_ex(None, -1, 8, 0, 0, 0, None, None, None, 0, 0, 0, 0, None) == -1
+    assert lib.dvc_rollout_ex(None, 4, 8, 0, 0, 0, None, None, None, 0, 0, 0, 0, None) == -1
+    assert lib.dvc_rollout_ex(None, 0, 0, 0, 0, 0, None, None, None, 0, 0, 0, 0, None) == -1
+    # unknown flag
+    assert lib.dvc_rollout_ex(vp(16), 1, 8, 0, 0, 0, None, None, None, 0, 0, 0, 2, None) == -1
     # n * ppl must stay below 2^32
-    assert lib.dvc_rollout_ex(vp(16), 1 << 20, 1 << 12, 0, 0, 0, None, None, None, 0, 0, 0,
+    assert lib.dvc_rollout_ex(vp(16), 1 << 20, 1 << 12, 0, 0, 0, None, None, None, 0, 0, 0, 0,
                               None) == -1
     lib.dvc_init_states.argtypes = [vp, C.c_int64, vp, C.c_uint64, C.c_uint32, vp]
     assert lib.dvc_init_states(None, -1, None, 0, 0, None) == -1
@@ -78,3 +80,12 @@ def test_root_parallel_argument_errors_without_device(lib):
     # misaligned workspace
     assert lib.mcts_search_root_parallel(vp(16), 1, 1, C.byref(mp), 1, 0, vp(20), 1 << 30, vp(16),
                                          None, None) == -1
+
+
+def test_autotune_argument_errors_without_device(lib):
+    vp = C.c_void_p
+    lib.dvc_rollout_autotune.argtypes = [vp, C.c_int64, C.c_int32, C.c_uint64, C.c_uint32,
+                                         C.c_uint32, vp, vp, vp, vp, vp]
+    assert lib.dvc_rollout_autotune(vp(16), 0, 8, 0, 0, 0, None, None, None, None, None) == -1
+    assert lib.dvc_rollout_autotune(None, 4, 8, 0, 0, 0, None, None, None, None, None) == -1
+    assert lib.dvc_rollout_autotune(vp(16), 4, 0, 0, 0, 0, None, None, None, None, None) == -1

@@ -70,7 +70,7 @@ def _compare(dvc, states_np, ppl, seed, tree, base, ref, **kw):
     assert np.array_equal(sw.cpu().numpy().view(np.uint32), rs), "seat wins"
 
 
-@pytest.mark.parametrize("variant", [1, 2, 3, 4])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5])
 @pytest.mark.parametrize("P", [2, 3, 4])
 def test_rollout_bit_exact_small(orc, dvc, variant, P):
     po = orc.deal_params(p_min=P, p_max=P, pile_min=0, pile_max=16, revealed_max=8, phase_mix=1)
@@ -92,7 +92,7 @@ def test_rollout_schedule_invariance(orc, dvc, variant, block, grid):
     _compare(dvc, S, ppl, 77, 3, 0, ref, variant=variant, block=block, grid=grid)
 
 
-@pytest.mark.parametrize("variant", [2, 3, 4])
+@pytest.mark.parametrize("variant", [2, 3, 4, 5])
 @pytest.mark.parametrize("ppl", [1, 2, 63, 64, 65, 129, 1000])
 def test_rollout_ppl_edges(orc, dvc, variant, ppl):
     po = orc.deal_params(p_min=2, p_max=3, pile_min=0, pile_max=16, revealed_max=8)
@@ -108,6 +108,16 @@ def test_rollout_playouts_per_lane_invariance(orc, dvc, per_lane):
     S = orc.init_states(150, po, seed=6)
     ref = _rollout_ref(orc, S, 90, 8, 1, 5)
     _compare(dvc, S, 90, 8, 1, 5, ref, variant=4, grid=per_lane)
+
+
+@pytest.mark.parametrize("K", [1, 2, 4, 8])
+def test_rollout_refill_item_size_invariance(orc, dvc, K):
+    """Variant 5 with items of 64, 128, 256 and 512 playouts, 300 playouts per leaf
+    (items split ragged across the leaf)."""
+    po = orc.deal_params(p_min=2, p_max=4, pile_min=0, pile_max=16, revealed_max=8)
+    S = orc.init_states(37, po, seed=16)
+    ref = _rollout_ref(orc, S, 300, 8, 2, 9)
+    _compare(dvc, S, 300, 8, 2, 9, ref, variant=5, grid=K)
 
 
 def test_rollout_batch_invariance(orc, dvc):
@@ -134,7 +144,38 @@ def test_rollout_optional_outputs(orc, dvc):
     assert np.array_equal(w.cpu().numpy(), ref[0])
 
 
-@pytest.mark.parametrize("variant", [1, 2, 3, 4])
+def test_rollout_autotune(orc, dvc):
+    """The autotuner picks one of its candidate shapes, its outputs are the
+    batch's playouts, and later automatic calls of that size class use a shape
+    that gives the same outputs."""
+    po = orc.deal_params(p_min=2, p_max=4, pile_min=0, pile_max=16, revealed_max=8)
+    S = orc.init_states(97, po, seed=12)
+    ref = _rollout_ref(orc, S, 300, 6, 1, 3)
+    st = dev_states(S)
+    shape, (w, ln, sw) = dvc.dvc_rollout_autotune(st, 300, 6, 1, 3)
+    torch.cuda.synchronize()
+    assert shape in [(4, 0, 1), (1, 0, 0), (4, 0, 2), (5, 0, 2), (5, 0, 4), (5, 0, 8)]
+    assert np.array_equal(w.cpu().numpy(), ref[0])
+    assert np.array_equal(ln.cpu().numpy(), ref[1])
+    assert np.array_equal(sw.cpu().numpy().view(np.uint32), ref[2])
+    _compare(dvc, S, 300, 6, 1, 3, ref)
+    assert dvc.dvc_check() == 0
+
+
+def test_rollout_accumulate(orc, dvc):
+    """Two calls with different seeds tally into one seat-win table."""
+    po = orc.deal_params(p_min=2, p_max=4, pile_min=0, pile_max=16, revealed_max=8)
+    S = orc.init_states(40, po, seed=8)
+    _, _, r1 = orc.rollout(S, 24, 1)
+    _, _, r2 = orc.rollout(S, 24, 2)
+    st = dev_states(S)
+    sw = torch.zeros((40, 4), dtype=torch.int32, device="cuda")
+    dvc.dvc_rollout(st, 24, 1, winner=False, length=False, seat_wins=sw, accumulate=True)
+    dvc.dvc_rollout(st, 24, 2, winner=False, length=False, seat_wins=sw, accumulate=True)
+    assert np.array_equal(sw.cpu().numpy().view(np.uint32), r1 + r2)
+
+
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5])
 def test_rollout_decided_and_malformed_leaves(orc, dvc, variant):
     import positions as POS
     rng = np.random.default_rng(9)
@@ -170,6 +211,8 @@ def test_rollout_argument_errors(dvc):
         dvc.dvc_rollout(st, 8, 1, variant=3, block=96)
     with pytest.raises(dvc.DvcError):
         dvc.dvc_rollout(st, 8, 1, variant=2, block=96)
+    with pytest.raises(dvc.DvcError):
+        dvc.dvc_rollout(st, 8, 1, variant=5, grid=3)
     # empty batch is fine and writes nothing
     e = torch.zeros((0, 4), dtype=torch.int32, device="cuda")
     w, ln, sw = dvc.dvc_rollout(e, 8, 1)
@@ -183,9 +226,24 @@ def test_rollout_full_leaf_parallel_workload(orc, dvc):
     st = dvc.dvc_init_states(4096, pd, seed=2)
     assert np.array_equal(to_np(st), S)
     ref = _rollout_ref(orc, S, 256, 2, 0, 0)
-    for variant in [1, 2, 3, 4]:
+    for variant in [1, 2, 3, 4, 5]:
         w, ln, sw = dvc.dvc_rollout(st, 256, 2, 0, 0, variant=variant)
         torch.cuda.synchronize()
         assert np.array_equal(w.cpu().numpy(), ref[0])
         assert np.array_equal(ln.cpu().numpy(), ref[1])
         assert np.array_equal(sw.cpu().numpy().view(np.uint32), ref[2])
+
+
+def test_valu_probe(dvc):
+    """The integer issue-rate probe runs every operation; for v_xor_b32 each chain
+    is xored with the same word an even number of times, so every lane folds its
+    eight start values."""
+    sink = torch.empty(2 * 256, dtype=torch.int32, device="cuda")
+    for op in range(len(dvc.VALU_PROBE_OPS)):
+        dvc.dvc_probe_valu(op, 2, 3, sink)
+    dvc.dvc_probe_valu(0, 2, 3, sink)
+    t = np.arange(512, dtype=np.uint32)
+    want = t ^ (t + 1) ^ (t + 2) ^ (t + 3) ^ (t + 4) ^ (t + 5) ^ (t + 6) ^ (t + 7)
+    assert np.array_equal(sink.cpu().numpy().view(np.uint32), want)
+    with pytest.raises(dvc.DvcError):
+        dvc.dvc_probe_valu(6, 2, 3, sink)

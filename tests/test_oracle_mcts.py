@@ -233,3 +233,87 @@ def test_merged_search_one_tree_matches_single_search(orc):
         top = live["n"].max()
         if np.sum(live["n"] == top) == 1:
             assert best_m[r] == best_s[r]
+
+
+def _sampler_law(pos):
+    """Exact law of the world sampler for one opponent, enumerated from its
+    stated procedure: per run of hidden opponent slots between revealed tiles
+    (lo, hi), in row order, the bounds right to left (largest available tile
+    of the slot's colour below the next bound), then values left to right,
+    uniform over the available tiles of the slot's colour in (previous value,
+    bound]; available = neither in the mover's row nor revealed nor taken."""
+    from fractions import Fraction
+    m = pos["mover"]
+    opp = 1 - m
+    rev = set(pos["revealed"])
+    avail0 = {t for t in range(24) if pos["owner"][t] != m and t not in rev}
+    row = sorted(t for t in range(24) if pos["owner"][t] == opp)
+    segs, cur, lo = [], [], -1
+    for t in row:
+        if t in rev:
+            if cur:
+                segs.append((lo, t, cur))
+            cur, lo = [], t
+        else:
+            cur.append(t)
+    if cur:
+        segs.append((lo, 24, cur))
+    law = {}
+
+    def rec(si, avail, chosen, p):
+        if si == len(segs):
+            law[tuple(sorted(chosen))] = law.get(tuple(sorted(chosen)), 0) + p
+            return
+        lo, hi, slots = segs[si]
+        bounds, b = [], hi
+        for t in reversed(slots):
+            c = [u for u in avail if u % 2 == t % 2 and u < b]
+            b = max(c)
+            bounds.append(b)
+        bounds.reverse()
+        assert bounds[0] > lo
+
+        def fill(j, avail, prev, chosen, p):
+            if j == len(slots):
+                rec(si + 1, avail, chosen, p)
+                return
+            c = sorted(u for u in avail if u % 2 == slots[j] % 2 and prev < u <= bounds[j])
+            for u in c:
+                fill(j + 1, avail - {u}, u, chosen + [u], p / len(c))
+
+        fill(0, avail, lo, chosen, p)
+
+    rec(0, avail0, [], Fraction(1))
+    return law
+
+
+def test_determinization_matches_its_exact_law(orc):
+    """Two runs of hidden opponent slots (one and two slots) in a two-player
+    position: the frequencies of the sampled worlds over 30,000 iterations match
+    the sampler's exact law, enumerated from its procedure (chi-square)."""
+    from scipy import stats
+    owner = [-1] * 24
+    opp_row = [2, 7, 10, 15, 20]
+    mover_row = [0, 5, 12, 13, 19, 22]
+    for t in opp_row:
+        owner[t] = 1
+    for t in mover_row:
+        owner[t] = 0
+    pos = {"P": 2, "owner": owner, "revealed": {7, 20, 5}, "mover": 0, "phase": 1,
+           "drawn": 22}
+    root = POS.pack(pos)
+    law = _sampler_law(pos)
+    assert abs(sum(law.values()) - 1) == 0 and len(law) > 10
+    counts = {}
+    n = 30000
+    for i in range(n):
+        world, a = orc.determinize(root, 9, 3, i)
+        assert a == 0
+        w = POS.unpack(world)
+        hidden = tuple(sorted(t for t in range(24) if w["owner"][t] == 1 and t not in w["revealed"]))
+        counts[hidden] = counts.get(hidden, 0) + 1
+    assert set(counts) <= set(law)
+    keys = sorted(law)
+    f_obs = [counts.get(k, 0) for k in keys]
+    f_exp = [float(law[k]) * n for k in keys]
+    assert stats.chisquare(f_obs, f_exp).pvalue > 1e-4
