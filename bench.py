@@ -32,14 +32,21 @@ if ROOT not in sys.path:
 N_LEAVES, PPL, SEED = 4096, 256, 2
 DEAL = dict(p_min=2, p_max=2, pile_min=0, pile_max=16, revealed_max=8)
 
-# Peak integer VALU issue rate of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
-INT_VALU_PEAK = 256 * 4 * 16 * 2.4e9          # lane-ops/s
-# Algorithmic integer operations of one guess step: one Philox4x32-10 block
-# (20 32x32->64 multiplies, 40 xors, 18 key adds = 78), four uniform picks
-# (4 high multiplies), four bit counts, three k-th-set-bit selections
-# (about 30 operations each as a bit-count search) and about 24 mask
-# operations on the 24-bit rows: ~200 lane-operations per guess.
-OPS_PER_GUESS = 200
+# Integer VALU peak of MI355X, from its unit counts and clock: 256 CUs x 4
+# SIMDs x 32 lanes per clock x 2.4 GHz = 78.6 T lane-ops/s (the published
+# 157.3 TFLOP/s vector FP32 rate counts the same 32 lanes, an FMA as two).
+# The chip's own issue-rate probe (dvc_probe_valu: v_xor_b32 at 58 T/s) rules
+# out the 16-lanes-per-clock figure (39.3 T).
+INT_VALU_PEAK = 256 * 4 * 32 * 2.4e9          # lane-ops/s
+# Algorithmic integer operations of one guess step, each weighted by its
+# issue cost relative to a 32-bit xor as measured by that probe (xor 58.1,
+# add 54.5, 32x32->64 multiply-add 32.7, high multiply 34.7, bit count 36.7
+# T/s): one Philox4x32-10 block = 20 multiplies (x1.78) + 40 xors + 18 adds
+# (x1.07) = 94.7; four uniform picks (high multiplies, x1.67) = 6.7; four bit
+# counts (x1.58) = 6.3; three k-th-set-bit selections (about 30 operations
+# each as a bit-count search) = 90; about 24 mask operations on the 24-bit
+# rows.  Total ~222 xor-equivalent lane-operations per guess step.
+OPS_PER_GUESS = 222
 
 # HBM traffic of one launch of the rollout kernel at this workload, from two
 # profiler counter passes (FETCH_SIZE, WRITE_SIZE in KiB per dispatch), each

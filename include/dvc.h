@@ -133,7 +133,8 @@ int dvc_rollout(const dvc_state_t *leaves, int64_t n_leaves, int32_t playouts_pe
  * lane back to back (`grid` then gives the playouts per lane, 1/2/4),
  * 5 = one wavefront per item of up to 64*K playouts of one leaf, lanes
  * refilled from the item as their games end (`grid` gives K, 1/2/4/8,
- * default 4).  block/grid 0 = automatic.  Same outputs for every variant and shape.
+ * default 4), 6 = variant 4 with one playout per lane and each step's
+ * random words computed during the step before.  block/grid 0 = automatic.  Same outputs for every variant and shape.
  * flags: DVC_ROLLOUT_ACCUMULATE adds the wins to seat_wins instead of
  * overwriting it (the caller zeroes it once; several calls then tally into
  * one table).  Errors as dvc_rollout, plus DVC_EINVAL for an unknown

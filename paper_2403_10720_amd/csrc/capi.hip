@@ -250,7 +250,7 @@ int dvc_rollout_ex(const dvc_state_t *leaves, int64_t n_leaves, int32_t ppl, uin
     if ((flags & ~DVC_ROLLOUT_ACCUMULATE) != 0) return DVC_EINVAL;
     const int ok = rollout_args_ok(leaves, n_leaves, ppl);
     if (ok != DVC_OK) return ok;
-    if (variant < 0 || variant > 5) return DVC_EINVAL;
+    if (variant < 0 || variant > 6) return DVC_EINVAL;
     if (block != 0 && block != 64 && block != 128 && block != 256 && block != 512) return DVC_EINVAL;
     if (grid < 0) return DVC_EINVAL;
     const Shape sh = variant != 0 ? Shape{variant, block, grid}

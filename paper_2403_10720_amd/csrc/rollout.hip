@@ -469,7 +469,7 @@ __global__ void __launch_bounds__(WAVES * 64) rollout_items(RolloutArgs a)
 // ---------------------------------------------------------------------------
 constexpr uint32_t kOutError = 0x7Fu;     // packed outcome of a malformed leaf
 
-template <int K>
+template <int K, bool PIPE>
 __global__ void __launch_bounds__(256) rollout_static(RolloutArgs a)
 {
     __shared__ uint8_t tab[kKthTableBytes];
@@ -486,6 +486,7 @@ __global__ void __launch_bounds__(256) rollout_static(RolloutArgs a)
     s.h0 = s.h1 = s.h2 = s.h3 = s.rev = 0u;
     s.m = 0u; s.P = 2u; s.phase = 1u; s.drawn = -1;
     PlayoutKey pk = {0u, 0u, 0u, 0u};
+    Words wcur = {0u, 0u, 0u, 0u};
     uint4 next_st = make_uint4(0u, 0u, 0u, 0u);
     if (j < a.total) next_st = a.leaves[j / a.ppl];
     bool need_start = j < a.total;
@@ -497,6 +498,10 @@ __global__ void __launch_bounds__(256) rollout_static(RolloutArgs a)
             const uint32_t p = j - leaf * a.ppl;
             valid = decode(next_st.x, next_st.y, next_st.z, next_st.w, s);
             pk = playout_key(p, a.leaf_base + leaf, a.k0);
+            if (PIPE) {
+                wcur = step_words(pk, trk1, a.k0, a.k1);
+                next_step(pk);
+            }
             len = 0u;
             const uint32_t alive = alive_mask(s);
             winner = (uint32_t)__builtin_ctz(alive | 16u);
@@ -509,9 +514,18 @@ __global__ void __launch_bounds__(256) rollout_static(RolloutArgs a)
         const bool live = k < (uint32_t)K && j < a.total;
         if (__ballot(live) == 0ull) break;
         if (live && !over) {
-            const Words w = step_words(pk, trk1, a.k0, a.k1);
-            over = guess_step(s, w, winner, tab);
-            next_step(pk);
+            if (PIPE) {
+                // the next step's words do not depend on the game: computing
+                // them now overlaps their latency with this step's
+                const Words wn = step_words(pk, trk1, a.k0, a.k1);
+                next_step(pk);
+                over = guess_step(s, wcur, winner, tab);
+                wcur = wn;
+            } else {
+                const Words w = step_words(pk, trk1, a.k0, a.k1);
+                over = guess_step(s, w, winner, tab);
+                next_step(pk);
+            }
             ++len;
             if (!over && len >= kMaxGuesses) {
                 atomicOr(&g_error_word, kErrLimit);
@@ -692,6 +706,13 @@ hipError_t launch_rollout(const RolloutArgs &a, int variant, int block, int grid
         hipLaunchKernelGGL(rollout_lane_per_playout, dim3(blocks), dim3(256), 0, st, a);
         return hipGetLastError();
     }
+    if (variant == 6) {
+        // variant 4 with one playout per lane and the next step's random
+        // words computed during the current step
+        const uint32_t blocks = (a.total + 255u) / 256u;
+        hipLaunchKernelGGL((rollout_static<1, true>), dim3(blocks), dim3(256), 0, st, a);
+        return hipGetLastError();
+    }
     if (variant == 4) {
         // playouts per lane (1, 2 or 4); automatic = 1: more playouts per
         // lane only lengthened the launch at every size measured (1M to 67M
@@ -702,9 +723,9 @@ hipError_t launch_rollout(const RolloutArgs &a, int variant, int block, int grid
         const uint32_t per_block = 256u * (uint32_t)kk;
         const uint32_t blocks = (uint32_t)((a.total + per_block - 1u) / per_block);
         switch (kk) {
-        case 1: hipLaunchKernelGGL(rollout_static<1>, dim3(blocks), dim3(256), 0, st, a); break;
-        case 2: hipLaunchKernelGGL(rollout_static<2>, dim3(blocks), dim3(256), 0, st, a); break;
-        default: hipLaunchKernelGGL(rollout_static<4>, dim3(blocks), dim3(256), 0, st, a); break;
+        case 1: hipLaunchKernelGGL((rollout_static<1, false>), dim3(blocks), dim3(256), 0, st, a); break;
+        case 2: hipLaunchKernelGGL((rollout_static<2, false>), dim3(blocks), dim3(256), 0, st, a); break;
+        default: hipLaunchKernelGGL((rollout_static<4, false>), dim3(blocks), dim3(256), 0, st, a); break;
         }
         return hipGetLastError();
     }

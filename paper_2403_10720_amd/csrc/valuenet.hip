@@ -487,47 +487,64 @@ __global__ void __launch_bounds__(64) vn_rows_kernel(VnRowsArgs a)
 }
 
 // Weight gradient C[m][n] = sum_k AT[m][k] BT[n][k] over the batch (k), one
-// 16x16 output tile per wavefront; AT, BT feature-major with rows contiguous.
+// 16x16 output tile and one slice of the batch per wavefront (split K, so
+// that many wavefronts stream the activations at once); slice s writes its
+// partial tile to out + s * slice_stride.  AT, BT feature-major, rows
+// contiguous, row length K; the slice length is a multiple of 32.
 __global__ void __launch_bounds__(64) vn_wgrad_kernel(const uint16_t *at, const uint16_t *bt,
-                                                       uint32_t K, float *out, uint32_t ldo,
-                                                       uint32_t ntiles)
+                                                       uint32_t K, uint32_t k_slice, float *out,
+                                                       uint32_t ldo, uint32_t ntiles,
+                                                       uint32_t tiles, uint32_t slice_stride)
 {
     const uint32_t lane = threadIdx.x, r = lane & 15u, g = lane >> 4;
-    const uint32_t mt = blockIdx.x / ntiles, nt = blockIdx.x % ntiles;
-    const uint16_t *ap = at + (size_t)(16u * mt + r) * K + 8u * g;
-    const uint16_t *bp = bt + (size_t)(16u * nt + r) * K + 8u * g;
+    const uint32_t tile = blockIdx.x % tiles, slice = blockIdx.x / tiles;
+    const uint32_t mt = tile / ntiles, nt = tile % ntiles;
+    const uint32_t kb = slice * k_slice;
+    const uint16_t *ap = at + (size_t)(16u * mt + r) * K + kb + 8u * g;
+    const uint16_t *bp = bt + (size_t)(16u * nt + r) * K + kb + 8u * g;
     floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll 4
-    for (uint32_t k0 = 0; k0 < K; k0 += 32u) acc = mfma16(load8(ap + k0), load8(bp + k0), acc);
+    for (uint32_t k0 = 0; k0 < k_slice; k0 += 32u) acc = mfma16(load8(ap + k0), load8(bp + k0), acc);
+    float *o = out + (size_t)slice * slice_stride;
 #pragma unroll
-    for (uint32_t i = 0; i < 4u; ++i) out[(size_t)(16u * mt + 4u * g + i) * ldo + 16u * nt + r] = acc[i];
+    for (uint32_t i = 0; i < 4u; ++i) o[(size_t)(16u * mt + 4u * g + i) * ldo + 16u * nt + r] = acc[i];
 }
 
-// Adam (Kingma and Ba, 2015) on the float32 master weights; bias gradients
-// are summed here over the per-wavefront partials in wavefront order; the
-// bf16 shadows of the updated weights are refreshed in the same pass.
-__global__ void vn_adam_kernel(void *net, const float *grad, const float *part, uint32_t n_parts,
+// Sum of the per-wavefront partials (loss, bias gradients, w3 gradient): one
+// wavefront per column, lane l adding partials l, l+64, ... in order, then a
+// fixed butterfly across the lanes, so a step is deterministic.
+__global__ void __launch_bounds__(256) vn_partsum_kernel(const float *part, uint32_t n_parts,
+                                                          float *red)
+{
+    const uint32_t col = blockIdx.x * 4u + (threadIdx.x >> 6), lane = threadIdx.x & 63u;
+    if (col >= kPartWords) return;
+    float acc = 0.0f;
+    for (uint32_t w = lane; w < n_parts; w += 64u) acc += part[(size_t)w * kPartWords + col];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0u) red[col] = acc;
+}
+
+// Adam (Kingma and Ba, 2015) on the float32 master weights, with the bf16
+// shadows of the updated weights refreshed in the same pass.  `red` holds the
+// summed partials (loss, db3, dw3, db2, db1).
+__global__ void vn_adam_kernel(void *net, const float *grad, uint32_t slices, const float *red,
                                float lr, float beta1, float beta2, float eps, float c1, float c2,
                                float inv_batch, float *grad_out, float *loss_out)
 {
     VnPtrs P = vn_ptrs(net);
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k == 0u && loss_out) {
-        float l = 0.0f;
-        for (uint32_t w = 0; w < n_parts; ++w) l += part[(size_t)w * kPartWords];
-        *loss_out = l * inv_batch;
-    }
+    if (k == 0u && loss_out) *loss_out = red[0] * inv_batch;
     if (k >= kVnParams) return;
     float gk;
     if (k < kOffB1 || (k >= kOffW2 && k < kOffB2)) {
+        // weight gradients: the batch slices' partial sums, in slice order
         gk = grad[k];
+        for (uint32_t sl = 1; sl < slices; ++sl) gk += grad[(size_t)sl * kVnPad + k];
     } else {
         const uint32_t idx = k == kOffB3 ? 1u
                            : k >= kOffW3 ? 2u + (k - kOffW3)
                            : k >= kOffB2 ? 2u + 256u + (k - kOffB2)
                                          : 2u + 512u + (k - kOffB1);
-        gk = 0.0f;
-        for (uint32_t w = 0; w < n_parts; ++w) gk += part[(size_t)w * kPartWords + idx];
+        gk = red[idx];
     }
     if (grad_out) grad_out[k] = gk;
     const float m = beta1 * P.m[k] + (1.0f - beta1) * gk;
@@ -555,11 +572,20 @@ __global__ void vn_adam_kernel(void *net, const float *grad, const float *part, 
 // ---------------------------------------------------------------------------
 size_t vn_bytes() { return (size_t)kVnBytes; }
 
+// batch slices of the weight-gradient products: up to 8, each a multiple of
+// 32 rows
+static uint32_t vn_wgrad_slices(uint32_t batch)
+{
+    uint32_t s = 8u;
+    while (s > 1u && (batch / 32u) % s != 0u) s >>= 1;
+    return s;
+}
+
 size_t vn_train_ws_bytes(uint32_t batch)
 {
     // xt[160][B], h1t, dh1t, dh2t [256][B] bf16; grad[NPAD] fp32; partials
-    return (size_t)batch * (160u + 3u * 256u) * 2u + (size_t)kVnPad * 4u +
-           (size_t)((batch + 15u) / 16u) * kPartWords * 4u + 256u;
+    return (size_t)batch * (160u + 3u * 256u) * 2u + (size_t)vn_wgrad_slices(batch) * kVnPad * 4u +
+           (size_t)((batch + 15u) / 16u + 1u) * kPartWords * 4u + 256u;
 }
 
 hipError_t launch_vn_init(void *net, uint32_t k0, uint32_t k1, hipStream_t st)
@@ -616,23 +642,30 @@ hipError_t launch_vn_train_step(void *net, const uint4 *states, const uint8_t *p
     a.dh1t = a.h1t + (size_t)256u * batch;
     a.dh2t = a.dh1t + (size_t)256u * batch;
     float *grad = (float *)(a.dh2t + (size_t)256u * batch);
-    a.part = grad + kVnPad;
+    const uint32_t slices = vn_wgrad_slices(batch);
+    a.part = grad + (size_t)slices * kVnPad;
     a.inv_batch = 1.0f / (float)batch;
     const uint32_t waves = batch / 16u;
     hipLaunchKernelGGL(vn_rows_kernel<true>, dim3(waves), dim3(64), 0, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // dW2 = dh2^T h1 (256 x 256), dW1 = dh1^T x (256 x 160)
-    hipLaunchKernelGGL(vn_wgrad_kernel, dim3(16u * 16u), dim3(64), 0, st, a.dh2t, a.h1t, batch,
-                       grad + kOffW2, 256u, 16u);
+    const uint32_t ks = batch / slices;
+    hipLaunchKernelGGL(vn_wgrad_kernel, dim3(16u * 16u * slices), dim3(64), 0, st, a.dh2t, a.h1t,
+                       batch, ks, grad + kOffW2, 256u, 16u, 16u * 16u, kVnPad);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(vn_wgrad_kernel, dim3(16u * 10u), dim3(64), 0, st, a.dh1t, a.xt, batch,
-                       grad + kOffW1, 160u, 10u);
+    hipLaunchKernelGGL(vn_wgrad_kernel, dim3(16u * 10u * slices), dim3(64), 0, st, a.dh1t, a.xt,
+                       batch, ks, grad + kOffW1, 160u, 10u, 16u * 10u, kVnPad);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    float *red = a.part + (size_t)waves * kPartWords;
+    hipLaunchKernelGGL(vn_partsum_kernel, dim3((kPartWords + 3u) / 4u), dim3(256), 0, st, a.part,
+                       waves, red);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(vn_adam_kernel, dim3((kVnParams + 255u) / 256u), dim3(256), 0, st, net, grad,
-                       a.part, waves, lr, 0.9f, 0.999f, 1e-8f, c1, c2, a.inv_batch, grad_out,
+                       slices, red, lr, 0.9f, 0.999f, 1e-8f, c1, c2, a.inv_batch, grad_out,
                        loss_out);
     return hipGetLastError();
 }

@@ -92,3 +92,30 @@ def train(cfg: TrainConfig, data=None, net=None, log_every: int = 0, log=None):
                     log(f"step {step} loss {hist[-1][1]:.5f}")
     torch.cuda.synchronize()
     return net, hist, time.perf_counter() - t0
+
+
+def main(argv=None):
+    """Train on freshly generated pairs and print the time per step (for profiling)."""
+    import argparse
+    import json
+    ap = argparse.ArgumentParser(description="value-network training on generated pairs")
+    ap.add_argument("--pairs-log2", type=int, default=23)
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--batch", type=int, default=8192)
+    args = ap.parse_args(argv)
+    torch.cuda.set_device(0)
+    cfg = TrainConfig(n_data=1 << args.pairs_log2, epochs=args.epochs, batch=args.batch)
+    t0 = time.perf_counter()
+    data = make_data(cfg.n_data, cfg.playouts, cfg.data_seed)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    _, hist, t_train = train(cfg, data=data, log_every=1024,
+                             log=lambda m: print(m, flush=True))
+    steps = cfg.epochs * (cfg.n_data // cfg.batch)
+    print(json.dumps({"pairs": cfg.n_data, "data_s": t_data, "steps": steps,
+                      "step_ms": t_train / steps * 1e3,
+                      "loss_last": hist[-1][1] if hist else None}), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -70,7 +70,7 @@ def _compare(dvc, states_np, ppl, seed, tree, base, ref, **kw):
     assert np.array_equal(sw.cpu().numpy().view(np.uint32), rs), "seat wins"
 
 
-@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6])
 @pytest.mark.parametrize("P", [2, 3, 4])
 def test_rollout_bit_exact_small(orc, dvc, variant, P):
     po = orc.deal_params(p_min=P, p_max=P, pile_min=0, pile_max=16, revealed_max=8, phase_mix=1)
@@ -92,7 +92,7 @@ def test_rollout_schedule_invariance(orc, dvc, variant, block, grid):
     _compare(dvc, S, ppl, 77, 3, 0, ref, variant=variant, block=block, grid=grid)
 
 
-@pytest.mark.parametrize("variant", [2, 3, 4, 5])
+@pytest.mark.parametrize("variant", [2, 3, 4, 5, 6])
 @pytest.mark.parametrize("ppl", [1, 2, 63, 64, 65, 129, 1000])
 def test_rollout_ppl_edges(orc, dvc, variant, ppl):
     po = orc.deal_params(p_min=2, p_max=3, pile_min=0, pile_max=16, revealed_max=8)
@@ -175,7 +175,7 @@ def test_rollout_accumulate(orc, dvc):
     assert np.array_equal(sw.cpu().numpy().view(np.uint32), r1 + r2)
 
 
-@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6])
 def test_rollout_decided_and_malformed_leaves(orc, dvc, variant):
     import positions as POS
     rng = np.random.default_rng(9)
@@ -206,7 +206,7 @@ def test_rollout_argument_errors(dvc):
     with pytest.raises(dvc.DvcError):
         dvc.dvc_rollout(st, 0, 1)
     with pytest.raises(dvc.DvcError):
-        dvc.dvc_rollout(st, 8, 1, variant=7)
+        dvc.dvc_rollout(st, 8, 1, variant=9)
     with pytest.raises(dvc.DvcError):
         dvc.dvc_rollout(st, 8, 1, variant=3, block=96)
     with pytest.raises(dvc.DvcError):
@@ -226,7 +226,7 @@ def test_rollout_full_leaf_parallel_workload(orc, dvc):
     st = dvc.dvc_init_states(4096, pd, seed=2)
     assert np.array_equal(to_np(st), S)
     ref = _rollout_ref(orc, S, 256, 2, 0, 0)
-    for variant in [1, 2, 3, 4, 5]:
+    for variant in [1, 2, 3, 4, 5, 6]:
         w, ln, sw = dvc.dvc_rollout(st, 256, 2, 0, 0, variant=variant)
         torch.cuda.synchronize()
         assert np.array_equal(w.cpu().numpy(), ref[0])
