@@ -53,9 +53,9 @@ OPS_PER_GUESS = 222
 # scaled by what the same counter reads for a plain 256 MiB device copy
 # (FETCH_SIZE reads half the bytes moved, WRITE_SIZE all of them).  Valid
 # only for the kernel sources it was taken on: reported as null otherwise.
-PROFILED_TRAFFIC = {"fetch_kib": 314.75, "fetch_scale": 2.0, "write_kib": 3584.0,
+PROFILED_TRAFFIC = {"fetch_kib": 320.25, "fetch_scale": 2.0, "write_kib": 3584.0,
                     "write_scale": 1.0,
-                    "sources_sha256": "1caca99b37856bd24efbdbfcd4fd51454f418b44dd36d21f15b74ba73ce80937"}
+                    "sources_sha256": "ddcd7efc27ad5528776f5d00dac6d5a2018987ecf2827abdad9fe4fe14ad6949"}
 KERNEL_SOURCES = ["paper_2403_10720_amd/csrc/dvc_core.hpp",
                   "paper_2403_10720_amd/csrc/dvc_internal.hpp",
                   "paper_2403_10720_amd/csrc/rollout.hip"]

@@ -24,15 +24,19 @@ __device__ __forceinline__ bool guess_step(State &s, const Words &w, uint32_t &w
     const uint32_t pool = ~owned & kAll;
     const bool turn_start = s.phase == 0u;
     const bool draw = turn_start && pool != 0u;
+    // The target is a hidden tile of another player, so it never is the tile
+    // the mover draws: its pick does not wait for the draw's (two of the
+    // step's three table lookups run side by side).
+    const uint32_t hm0 = hand_of(s, s.m);
+    const uint32_t targets = owned & ~hm0 & ~s.rev;
+    const uint32_t t = pick_bit_tab(targets, w.w1, tab);
     const uint32_t d = pick_bit_tab(pool, w.w0, tab);
     const uint32_t dbit = draw ? (1u << d) : 0u;
     add_to_hand(s, s.m, dbit);
     s.drawn = turn_start ? (draw ? (int32_t)d : -1) : s.drawn;
     s.phase = 1u;
 
-    const uint32_t hm = hand_of(s, s.m);
-    const uint32_t targets = (owned | dbit) & ~hm & ~s.rev;
-    const uint32_t t = pick_bit_tab(targets, w.w1, tab);
+    const uint32_t hm = hm0 | dbit;
     const uint32_t tb = 1u << t;
     const uint32_t o = (s.h0 & tb) ? 0u : (s.h1 & tb) ? 1u : (s.h2 & tb) ? 2u : 3u;
     const uint32_t cand = candidates(t, hand_of(s, o), hm, s.rev);
