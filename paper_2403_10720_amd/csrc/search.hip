@@ -340,7 +340,12 @@ __device__ __forceinline__ void write_no_children(const MctsArgs &a, uint32_t t,
     }
 }
 
-__global__ void __launch_bounds__(64) mcts_tree_kernel(MctsArgs a)
+// VALUE: value mode (network leaves) -- one wavefront per SIMD, so that the
+// evaluation can keep many weight loads in flight; otherwise playout leaves
+// only, two wavefronts per SIMD.
+template <bool VALUE>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, VALUE ? 1 : 8)))
+mcts_tree_kernel(MctsArgs a)
 {
     __shared__ uint8_t tab[kKthTableBytes];
     __shared__ uint32_t legal_s[72];
@@ -527,14 +532,14 @@ __global__ void __launch_bounds__(64) mcts_tree_kernel(MctsArgs a)
         float vals[4] = {0.0f, 0.0f, 0.0f, 0.0f};
         bool use_vals = false;
         uint32_t nplay = a.ppl;
-        if (!term && a.leaf_eval) {
+        if (VALUE && !term) {
             // one row per seat perspective q = lane % 16 < P
             uint4 ps;
             encode(S, ps.x, ps.y, ps.z, ps.w);
             const uint32_t q = lane & 15u;
             RowFeat rf = q < S.P ? row_features(ps, q) : no_row();
             float v4[4];
-            vn_eval16(vn_ptrs(const_cast<void *>(a.net)), rf, vn_tile, v4);
+            vn_eval16_deep(vn_ptrs(const_cast<void *>(a.net)), rf, vn_tile, v4);
             float v[4];
 #pragma unroll
             for (uint32_t k = 0; k < 4u; ++k) v[k] = __shfl(v4[k], 0, 64);
@@ -547,7 +552,7 @@ __global__ void __launch_bounds__(64) mcts_tree_kernel(MctsArgs a)
 #pragma unroll
                 for (uint32_t k = 0; k < 4u; ++k) vals[k] = (float)a.fb_ppl * v[k];
             }
-        } else if (a.leaf_eval) {
+        } else if (VALUE) {
             nplay = a.fb_ppl;
         }
         if (term) {
@@ -779,7 +784,10 @@ hipError_t launch_mcts(const uint4 *roots, uint32_t n_trees, uint32_t trees_per_
     a.band = band;
     a.fb_ppl = fb_ppl;
     a.net = net;
-    hipLaunchKernelGGL(mcts_tree_kernel, dim3(n_trees), dim3(64), 0, st, a);
+    if (leaf_eval)
+        hipLaunchKernelGGL(mcts_tree_kernel<true>, dim3(n_trees), dim3(64), 0, st, a);
+    else
+        hipLaunchKernelGGL(mcts_tree_kernel<false>, dim3(n_trees), dim3(64), 0, st, a);
     return hipGetLastError();
 }
 

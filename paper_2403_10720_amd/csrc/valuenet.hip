@@ -249,6 +249,90 @@ __device__ __forceinline__ void vn_eval16(const VnPtrs &P, const RowFeat &rf,
     __syncthreads();   // hs may be reused by the caller
 }
 
+// vn_eval16 with the weight fragments streamed through a ring of kVnRing
+// registers: the fragment for product q + kVnRing is requested while product
+// q runs, so a wavefront keeps that many loads in flight instead of one or
+// two (one wavefront per tree has nothing else to hide the L2 latency
+// behind).  Same products in the same order as vn_eval16.  Needs the register
+// budget of one wavefront per SIMD.
+constexpr int kVnRing = 16;
+
+// out(j, acc): epilogue of output column tile j (16 columns, D layout)
+template <int KS, int LD, typename Epi>
+__device__ __forceinline__ void vn_layer_deep(const bf16x8 (&a)[KS], const uint16_t *w, uint32_t r,
+                                              uint32_t g, Epi out)
+{
+    constexpr int N = 16 * KS;
+    bf16x8 ring[kVnRing];
+#pragma unroll
+    for (int q = 0; q < kVnRing; ++q)
+        ring[q] = load8(w + (size_t)(16u * (uint32_t)(q / KS) + r) * LD + 8u * g + 32u * (uint32_t)(q % KS));
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            const int q = j * KS + s;
+            const bf16x8 b = ring[q % kVnRing];
+            if (q + kVnRing < N) {
+                const int qn = q + kVnRing;
+                ring[q % kVnRing] = load8(w + (size_t)(16u * (uint32_t)(qn / KS) + r) * LD + 8u * g +
+                                          32u * (uint32_t)(qn % KS));
+            }
+            acc = mfma16(a[s], b, acc);
+        }
+        out((uint32_t)j, acc);
+    }
+}
+
+__device__ __forceinline__ void vn_eval16_deep(const VnPtrs &P, const RowFeat &rf,
+                                               uint16_t (*hs)[kVnH + 8], float v4[4])
+{
+    const uint32_t lane = threadIdx.x & 63u, r = lane & 15u, g = lane >> 4;
+    // the lane's biases and output weights first: a load issued inside the
+    // product loop would make every wait cover all older weight loads
+    float b1v[16], b2v[16], w3v[16];
+    const float b3 = P.master[kOffB3];
+#pragma unroll
+    for (uint32_t j = 0; j < 16u; ++j) {
+        b1v[j] = P.master[kOffB1 + 16u * j + r];
+        b2v[j] = P.master[kOffB2 + 16u * j + r];
+        w3v[j] = bf16_to_f(P.w3b[16u * j + r]);
+    }
+    bf16x8 xa[5];
+#pragma unroll
+    for (uint32_t s = 0; s < 5u; ++s) xa[s] = feature8(rf, 32u * s + 8u * g);
+    vn_layer_deep<5, kVnIn>(xa, P.w1b, r, g, [&](uint32_t j, const floatx4 &acc) {
+        const float b = b1v[j];
+#pragma unroll
+        for (uint32_t i = 0; i < 4u; ++i) {
+            const float h = acc[i] + b;
+            hs[4u * g + i][16u * j + r] = bf16_bits(h > 0.0f ? h : 0.0f);
+        }
+    });
+    __syncthreads();
+    bf16x8 ha[8];
+#pragma unroll
+    for (uint32_t s = 0; s < 8u; ++s) ha[s] = load8(&hs[r][32u * s + 8u * g]);
+    float zpart[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    vn_layer_deep<8, kVnH>(ha, P.w2b, r, g, [&](uint32_t j, const floatx4 &acc) {
+        const float b = b2v[j];
+        const float w3 = w3v[j];
+#pragma unroll
+        for (uint32_t i = 0; i < 4u; ++i) {
+            const float h = acc[i] + b;
+            zpart[i] += bf16_round(h > 0.0f ? h : 0.0f) * w3;
+        }
+    });
+#pragma unroll
+    for (uint32_t i = 0; i < 4u; ++i)
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) zpart[i] += __shfl_xor(zpart[i], off, 64);
+#pragma unroll
+    for (uint32_t i = 0; i < 4u; ++i) v4[i] = 1.0f / (1.0f + expf(-(zpart[i] + b3)));
+    __syncthreads();   // hs may be reused by the caller
+}
+
 __device__ __forceinline__ RowFeat no_row()
 {
     RowFeat rf;
@@ -486,6 +570,194 @@ __global__ void __launch_bounds__(64) vn_rows_kernel(VnRowsArgs a)
     }
 }
 
+// Training rows, four wavefronts per 16-row tile: wavefront w computes output
+// columns 64w..64w+63 of every layer (a quarter of each weight matrix), the
+// tiles of activations and gradients being shared through LDS.  Same
+// arithmetic as vn_rows_kernel<true> except that z sums the four quarters'
+// partial dot products in wavefront order.
+__global__ void __launch_bounds__(256) vn_rows4_kernel(VnRowsArgs a)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t hs[16][kVnH + 8];   // h1, then dh2 tile (bf16)
+    __shared__ float zred[4][16];
+    const VnPtrs P = vn_ptrs(const_cast<void *>(a.net));
+    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6, r = lane & 15u, g = lane >> 4;
+    const uint32_t row0 = blockIdx.x * 16u;
+    const uint32_t myrow = row0 + r;
+    const bool has = myrow < a.n_rows;
+    uint32_t src = myrow;
+    if (has) src = (uint32_t)(((uint64_t)a.perm_a * (a.row_base + myrow) + a.perm_b) % a.n_data);
+    RowFeat rf;
+    if (has) {
+        rf = row_features(a.states[src], a.persp[src]);
+    } else {
+        rf.ok = false;
+    }
+    if (has && !rf.ok && wv == 0u) atomicOr(&g_error_word, kErrState);
+    if (!rf.ok) rf = no_row();
+
+    // ---- layer 1: h1 = bf16(relu(W1 x + b1)), columns of this wavefront ----
+    bf16x8 xa[5];
+#pragma unroll
+    for (uint32_t s = 0; s < 5u; ++s) xa[s] = feature8(rf, 32u * s + 8u * g);
+    if (has) {
+        // X^T for the weight gradient (feature blocks split over the wavefronts)
+        for (uint32_t s = wv; s < 5u; s += 4u)
+#pragma unroll
+            for (uint32_t i = 0; i < 8u; ++i) {
+                const uint32_t f = 32u * s + 8u * g + i;
+                a.xt[(size_t)f * a.n_rows + myrow] = feature_bit(rf, f) ? (uint16_t)0x3F80u : (uint16_t)0u;
+            }
+    }
+    uint32_t h1pos = 0u;   // bit 4jj+i: h1 of row 4g+i, column 16(4wv+jj)+r is positive
+#pragma unroll
+    for (uint32_t jj = 0; jj < 4u; ++jj) {
+        const uint32_t j = 4u * wv + jj;
+        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        const uint16_t *wrow = P.w1b + (size_t)(16u * j + r) * kVnIn + 8u * g;
+#pragma unroll
+        for (uint32_t s = 0; s < 5u; ++s) acc = mfma16(xa[s], load8(wrow + 32u * s), acc);
+        const float b = P.master[kOffB1 + 16u * j + r];
+        uint16_t hq[4];
+#pragma unroll
+        for (uint32_t i = 0; i < 4u; ++i) {
+            const float h = acc[i] + b;
+            hq[i] = bf16_bits(h > 0.0f ? h : 0.0f);
+            hs[4u * g + i][16u * j + r] = hq[i];
+            h1pos |= (uint32_t)(h > 0.0f) << (4u * jj + i);
+        }
+        const uint32_t rr = row0 + 4u * g;
+        if (rr + 3u < a.n_rows) {
+            const uint2 packed = make_uint2((uint32_t)hq[0] | ((uint32_t)hq[1] << 16),
+                                            (uint32_t)hq[2] | ((uint32_t)hq[3] << 16));
+            *reinterpret_cast<uint2 *>(a.h1t + (size_t)(16u * j + r) * a.n_rows + rr) = packed;
+        }
+    }
+    __syncthreads();
+
+    // ---- layer 2: h2 = bf16(relu(W2 h1 + b2)), z = w3 . h2 + b3 ------------
+    bf16x8 ha[8];
+#pragma unroll
+    for (uint32_t s = 0; s < 8u; ++s) ha[s] = load8(&hs[r][32u * s + 8u * g]);
+    floatx4 h2[4];
+    float zpart[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (uint32_t jj = 0; jj < 4u; ++jj) {
+        const uint32_t j = 4u * wv + jj;
+        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        const uint16_t *wrow = P.w2b + (size_t)(16u * j + r) * kVnH + 8u * g;
+#pragma unroll
+        for (uint32_t s = 0; s < 8u; ++s) acc = mfma16(ha[s], load8(wrow + 32u * s), acc);
+        const float b = P.master[kOffB2 + 16u * j + r];
+        const float w3 = bf16_to_f(P.w3b[16u * j + r]);
+#pragma unroll
+        for (uint32_t i = 0; i < 4u; ++i) {
+            const float h = acc[i] + b;
+            h2[jj][i] = bf16_round(h > 0.0f ? h : 0.0f);
+            zpart[i] += h2[jj][i] * w3;
+        }
+    }
+#pragma unroll
+    for (uint32_t i = 0; i < 4u; ++i)
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) zpart[i] += __shfl_xor(zpart[i], off, 64);
+    if (r == 0u) {
+#pragma unroll
+        for (uint32_t i = 0; i < 4u; ++i) zred[wv][4u * g + i] = zpart[i];
+    }
+    __syncthreads();   // zred complete; every wavefront has read h1 from hs
+    const float b3 = P.master[kOffB3];
+    float v4[4], dz[4], err2 = 0.0f;
+#pragma unroll
+    for (uint32_t i = 0; i < 4u; ++i) {
+        const uint32_t lr = 4u * g + i;
+        const float z = ((zred[0][lr] + zred[1][lr]) + zred[2][lr]) + zred[3][lr];
+        v4[i] = 1.0f / (1.0f + expf(-(z + b3)));
+        const uint32_t row = row0 + lr;
+        float d = 0.0f;
+        if (row < a.n_rows) {
+            const uint32_t sr = (uint32_t)(((uint64_t)a.perm_a * (a.row_base + row) + a.perm_b) % a.n_data);
+            const float e = v4[i] - a.labels[sr];
+            err2 += e * e;
+            d = 2.0f * e * a.inv_batch * v4[i] * (1.0f - v4[i]);
+        }
+        dz[i] = d;
+    }
+    float *part = a.part + (size_t)blockIdx.x * kPartWords;
+    if (wv == 0u) {
+        float l4 = r == 0u ? err2 : 0.0f, d3 = r == 0u ? dz[0] + dz[1] + dz[2] + dz[3] : 0.0f;
+        for (int off = 1; off < 64; off <<= 1) {
+            l4 += __shfl_xor(l4, off, 64);
+            d3 += __shfl_xor(d3, off, 64);
+        }
+        if (lane == 0) {
+            part[0] = l4;
+            part[1] = d3;
+        }
+    }
+
+    // ---- dh2 = dz w3 (h2 > 0); w3 and b2 gradients ---------------------------
+#pragma unroll
+    for (uint32_t jj = 0; jj < 4u; ++jj) {
+        const uint32_t col = 16u * (4u * wv + jj) + r;
+        const float w3 = bf16_to_f(P.w3b[col]);
+        float dw3 = 0.0f, db2 = 0.0f;
+        uint16_t dq[4];
+#pragma unroll
+        for (uint32_t i = 0; i < 4u; ++i) {
+            dw3 += dz[i] * h2[jj][i];
+            const float d = h2[jj][i] > 0.0f ? dz[i] * w3 : 0.0f;
+            dq[i] = bf16_bits(d);
+            db2 += bf16_to_f(dq[i]);
+            hs[4u * g + i][col] = dq[i];
+        }
+        const uint32_t rr = row0 + 4u * g;
+        if (rr + 3u < a.n_rows) {
+            const uint2 packed = make_uint2((uint32_t)dq[0] | ((uint32_t)dq[1] << 16),
+                                            (uint32_t)dq[2] | ((uint32_t)dq[3] << 16));
+            *reinterpret_cast<uint2 *>(a.dh2t + (size_t)col * a.n_rows + rr) = packed;
+        }
+        dw3 += __shfl_xor(dw3, 16, 64);
+        dw3 += __shfl_xor(dw3, 32, 64);
+        db2 += __shfl_xor(db2, 16, 64);
+        db2 += __shfl_xor(db2, 32, 64);
+        if (g == 0u) {
+            part[2u + col] = dw3;
+            part[2u + 256u + col] = db2;
+        }
+    }
+    __syncthreads();   // dh2 tile complete
+
+    // ---- dh1 = (dh2 W2) * (h1 > 0), columns of this wavefront ----------------
+    bf16x8 da[8];
+#pragma unroll
+    for (uint32_t s = 0; s < 8u; ++s) da[s] = load8(&hs[r][32u * s + 8u * g]);
+#pragma unroll
+    for (uint32_t jj = 0; jj < 4u; ++jj) {
+        const uint32_t col = 16u * (4u * wv + jj) + r;
+        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        const uint16_t *wrow = P.w2tb + (size_t)col * kVnH + 8u * g;
+#pragma unroll
+        for (uint32_t s = 0; s < 8u; ++s) acc = mfma16(da[s], load8(wrow + 32u * s), acc);
+        float db1 = 0.0f;
+        uint16_t dq[4];
+#pragma unroll
+        for (uint32_t i = 0; i < 4u; ++i) {
+            const float d = ((h1pos >> (4u * jj + i)) & 1u) ? acc[i] : 0.0f;
+            dq[i] = bf16_bits(d);
+            db1 += bf16_to_f(dq[i]);
+        }
+        const uint32_t rr = row0 + 4u * g;
+        if (rr + 3u < a.n_rows) {
+            const uint2 packed = make_uint2((uint32_t)dq[0] | ((uint32_t)dq[1] << 16),
+                                            (uint32_t)dq[2] | ((uint32_t)dq[3] << 16));
+            *reinterpret_cast<uint2 *>(a.dh1t + (size_t)col * a.n_rows + rr) = packed;
+        }
+        db1 += __shfl_xor(db1, 16, 64);
+        db1 += __shfl_xor(db1, 32, 64);
+        if (g == 0u) part[2u + 512u + col] = db1;
+    }
+}
+
 // Weight gradient C[m][n] = sum_k AT[m][k] BT[n][k] over the batch (k), one
 // 16x16 output tile and one slice of the batch per wavefront (split K, so
 // that many wavefronts stream the activations at once); slice s writes its
@@ -646,7 +918,7 @@ hipError_t launch_vn_train_step(void *net, const uint4 *states, const uint8_t *p
     a.part = grad + (size_t)slices * kVnPad;
     a.inv_batch = 1.0f / (float)batch;
     const uint32_t waves = batch / 16u;
-    hipLaunchKernelGGL(vn_rows_kernel<true>, dim3(waves), dim3(64), 0, st, a);
+    hipLaunchKernelGGL(vn_rows4_kernel, dim3(waves), dim3(256), 0, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // dW2 = dh2^T h1 (256 x 256), dW1 = dh1^T x (256 x 160)
