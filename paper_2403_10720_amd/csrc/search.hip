@@ -340,22 +340,62 @@ __device__ __forceinline__ void write_no_children(const MctsArgs &a, uint32_t t,
     }
 }
 
+// Orders one tree's memory accesses between its lanes.  A tree is one
+// wavefront; in the value-mode kernel four trees share a workgroup (and its
+// LDS copy of the second-layer weights) but never wait for each other, so
+// their orderings are fences plus a wavefront barrier, not workgroup barriers.
+template <bool SHARED_GROUP>
+__device__ __forceinline__ void tree_sync()
+{
+    if (SHARED_GROUP) {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+    } else {
+        __syncthreads();
+    }
+}
+
+// Trees per workgroup: value mode stages the 256 x 256 second-layer weights
+// in LDS once per workgroup for its four trees; playout mode runs one tree per
+// workgroup.
+template <bool VALUE> struct TreeGroup { static constexpr uint32_t kTrees = VALUE ? 4u : 1u; };
+
 // VALUE: value mode (network leaves) -- one wavefront per SIMD, so that the
 // evaluation can keep many weight loads in flight; otherwise playout leaves
-// only, two wavefronts per SIMD.
+// only.
 template <bool VALUE>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, VALUE ? 1 : 8)))
+__global__ void __launch_bounds__(64 * TreeGroup<VALUE>::kTrees)
+__attribute__((amdgpu_waves_per_eu(1, VALUE ? 1 : 8)))
 mcts_tree_kernel(MctsArgs a)
 {
+    constexpr uint32_t TG = TreeGroup<VALUE>::kTrees;
     __shared__ uint8_t tab[kKthTableBytes];
-    __shared__ uint32_t legal_s[72];
-    __shared__ uint32_t path_e[kMaxDepthLimit + 1];
-    __shared__ DfsSlots dfs_slots;
-    __shared__ __attribute__((aligned(16))) uint16_t vn_tile[16][kVnH + 8];
+    __shared__ uint32_t legal_all[TG][72];
+    __shared__ uint32_t path_all[TG][kMaxDepthLimit + 1];
+    __shared__ DfsSlots dfs_all[TG];
+    __shared__ __attribute__((aligned(16))) uint16_t tile_all[TG][4][kVnH + 8];
+    __shared__ __attribute__((aligned(16))) uint16_t w2_lds[VALUE ? kVnH : 1][kVnH + 8];
+    __shared__ VnSmall vn_small[1];
     fill_kth_table(tab);
-    __syncthreads();
-    const uint32_t t = blockIdx.x;
-    const uint32_t lane = threadIdx.x;
+    if (VALUE) {
+        vn_stage_small(vn_ptrs(const_cast<void *>(a.net)), vn_small[0]);
+        // second-layer weights (bf16, rows padded to 264 to spread LDS banks)
+        const uint16_t *w2 = vn_ptrs(const_cast<void *>(a.net)).w2b;
+        for (uint32_t c = threadIdx.x; c < kVnH * kVnH / 8u; c += blockDim.x) {
+            const uint32_t row = c >> 5, col = (c & 31u) * 8u;
+            *reinterpret_cast<uint4 *>(&w2_lds[row][col]) =
+                *reinterpret_cast<const uint4 *>(w2 + row * kVnH + col);
+        }
+    }
+    __syncthreads();   // the only workgroup barrier
+    const uint32_t wv = TG == 1u ? 0u : __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t t = blockIdx.x * TG + wv;
+    if (t >= a.n_trees) return;
+    const uint32_t lane = threadIdx.x & 63u;
+    uint32_t *legal_s = legal_all[wv];
+    uint32_t *path_e = path_all[wv];
+    DfsSlots &dfs_slots = dfs_all[wv];
+    uint16_t (*vn_tile)[kVnH + 8] = tile_all[wv];
     const uint32_t tr = a.tree_base + t;
     uint32_t *W = a.ws + (uint64_t)t * a.tree_words;
     const uint32_t ovf_base = kTreeHeaderWords + a.nodes_cap * kNodeStride;
@@ -388,7 +428,7 @@ mcts_tree_kernel(MctsArgs a)
     bool failed = false, have_fallback = false;
     State fallback = R;
     uint64_t cyc[4] = {0u, 0u, 0u, 0u};   // shader clock per phase (statistics)
-    __syncthreads();
+    tree_sync<VALUE>();
 
     for (uint32_t it = 0; it < a.iters && !failed; ++it) {
         const uint64_t t0 = clock64();
@@ -439,7 +479,7 @@ mcts_tree_kernel(MctsArgs a)
             const uint32_t cb1 = (cbw1 >> ((lane & 1u) * 16u)) & 0xFFFu;
             const uint32_t u0 = l0 & ~cb0, u1 = l1 & ~cb1;
             const uint64_t b0 = __ballot(u0 != 0u), b1 = __ballot(u1 != 0u);
-            __syncthreads();
+            tree_sync<VALUE>();
             if (b0 | b1) {
                 // expansion: the lowest legal action that has no child yet
                 uint32_t pair, vbits;
@@ -480,7 +520,7 @@ mcts_tree_kernel(MctsArgs a)
                 if (lane < kNodeWords) W[rec_off(c) + lane] = lane == 1u ? c : 0u;
                 path_e[np++] = e;
                 term = apply_action(S, action, depth, it, tr, a.k0, a.k1, winner, tab);
-                __syncthreads();
+                tree_sync<VALUE>();
                 break;
             }
             // selection: UCT over the legal children, 64 per pass
@@ -522,7 +562,7 @@ mcts_tree_kernel(MctsArgs a)
             path_e[np++] = best_e;
             term = apply_action(S, best_act, depth, it, tr, a.k0, a.k1, winner, tab);
             ++depth;
-            __syncthreads();
+            tree_sync<VALUE>();
         }
 
         const uint64_t t2 = clock64();
@@ -539,7 +579,7 @@ mcts_tree_kernel(MctsArgs a)
             const uint32_t q = lane & 15u;
             RowFeat rf = q < S.P ? row_features(ps, q) : no_row();
             float v4[4];
-            vn_eval16_deep(vn_ptrs(const_cast<void *>(a.net)), rf, vn_tile, v4);
+            vn_eval_tree(vn_ptrs(const_cast<void *>(a.net)), rf, vn_tile, w2_lds, vn_small[0], v4);
             float v[4];
 #pragma unroll
             for (uint32_t k = 0; k < 4u; ++k) v[k] = __shfl(v4[k], 0, 64);
@@ -619,7 +659,7 @@ mcts_tree_kernel(MctsArgs a)
             W[e + 1u] += nplay;
             W[e + 2u] = __float_as_uint(__uint_as_float(W[e + 2u]) + wc);
         }
-        __syncthreads();
+        tree_sync<VALUE>();
         cyc[3] += clock64() - t3;
     }
 
@@ -785,7 +825,7 @@ hipError_t launch_mcts(const uint4 *roots, uint32_t n_trees, uint32_t trees_per_
     a.fb_ppl = fb_ppl;
     a.net = net;
     if (leaf_eval)
-        hipLaunchKernelGGL(mcts_tree_kernel<true>, dim3(n_trees), dim3(64), 0, st, a);
+        hipLaunchKernelGGL(mcts_tree_kernel<true>, dim3((n_trees + 3u) / 4u), dim3(256), 0, st, a);
     else
         hipLaunchKernelGGL(mcts_tree_kernel<false>, dim3(n_trees), dim3(64), 0, st, a);
     return hipGetLastError();

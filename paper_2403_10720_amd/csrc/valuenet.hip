@@ -258,11 +258,12 @@ __device__ __forceinline__ void vn_eval16(const VnPtrs &P, const RowFeat &rf,
 constexpr int kVnRing = 16;
 
 // out(j, acc): epilogue of output column tile j (16 columns, D layout)
-template <int KS, int LD, typename Epi>
+template <int KS, int LD, int RING = kVnRing, typename Epi>
 __device__ __forceinline__ void vn_layer_deep(const bf16x8 (&a)[KS], const uint16_t *w, uint32_t r,
                                               uint32_t g, Epi out)
 {
     constexpr int N = 16 * KS;
+    constexpr int kVnRing = RING;
     bf16x8 ring[kVnRing];
 #pragma unroll
     for (int q = 0; q < kVnRing; ++q)
@@ -331,6 +332,84 @@ __device__ __forceinline__ void vn_eval16_deep(const VnPtrs &P, const RowFeat &r
 #pragma unroll
     for (uint32_t i = 0; i < 4u; ++i) v4[i] = 1.0f / (1.0f + expf(-(zpart[i] + b3)));
     __syncthreads();   // hs may be reused by the caller
+}
+
+// The evaluation inside a tree search: at most four rows (one per seat
+// perspective) in a 4 x 264 LDS tile, first-layer weights streamed from L2
+// through the load ring, second-layer weights read from the LDS copy the
+// workgroup staged at its start (`w2l`, rows padded to 264).  Rows 4..15 of
+// the products repeat rows 0..3 and are ignored.  Only this wavefront's lanes
+// touch `tile`, so it is ordered with wavefront barriers.  Same products, in
+// the same order, as vn_eval16.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Small per-workgroup LDS copy of the biases and output weights (float):
+// b1[256], b2[256], w3[256], b3.
+struct VnSmall {
+    float b1[kVnH], b2[kVnH], w3[kVnH], b3;
+};
+
+__device__ __forceinline__ void vn_stage_small(const VnPtrs &P, VnSmall &sm)
+{
+    for (uint32_t k = threadIdx.x; k < kVnH; k += blockDim.x) {
+        sm.b1[k] = P.master[kOffB1 + k];
+        sm.b2[k] = P.master[kOffB2 + k];
+        sm.w3[k] = bf16_to_f(P.w3b[k]);
+    }
+    if (threadIdx.x == 0) sm.b3 = P.master[kOffB3];
+}
+
+__device__ __forceinline__ void vn_eval_tree(const VnPtrs &P, const RowFeat &rf,
+                                             uint16_t (*tile)[kVnH + 8],
+                                             const uint16_t (*w2l)[kVnH + 8], const VnSmall &sm,
+                                             float v4[4])
+{
+    const uint32_t lane = threadIdx.x & 63u, r = lane & 15u, g = lane >> 4;
+    bf16x8 xa[5];
+#pragma unroll
+    for (uint32_t s = 0; s < 5u; ++s) xa[s] = feature8(rf, 32u * s + 8u * g);
+    vn_layer_deep<5, kVnIn, 32>(xa, P.w1b, r, g, [&](uint32_t j, const floatx4 &acc) {
+        if (g == 0u) {
+            const float b1 = sm.b1[16u * j + r];
+#pragma unroll
+            for (uint32_t i = 0; i < 4u; ++i) {
+                const float h = acc[i] + b1;
+                tile[i][16u * j + r] = bf16_bits(h > 0.0f ? h : 0.0f);
+            }
+        }
+    });
+    wave_lds_sync();
+    bf16x8 ha[8];
+#pragma unroll
+    for (uint32_t s = 0; s < 8u; ++s) ha[s] = load8(&tile[r & 3u][32u * s + 8u * g]);
+    float zpart[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (uint32_t j = 0; j < 16u; ++j) {
+        bf16x8 wb[8];
+#pragma unroll
+        for (uint32_t s = 0; s < 8u; ++s) wb[s] = load8(&w2l[16u * j + r][32u * s + 8u * g]);
+        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (uint32_t s = 0; s < 8u; ++s) acc = mfma16(ha[s], wb[s], acc);
+        const float b2 = sm.b2[16u * j + r], w3 = sm.w3[16u * j + r];
+#pragma unroll
+        for (uint32_t i = 0; i < 4u; ++i) {
+            const float h = acc[i] + b2;
+            zpart[i] += bf16_round(h > 0.0f ? h : 0.0f) * w3;
+        }
+    }
+#pragma unroll
+    for (uint32_t i = 0; i < 4u; ++i)
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) zpart[i] += __shfl_xor(zpart[i], off, 64);
+    const float b3 = sm.b3;
+#pragma unroll
+    for (uint32_t i = 0; i < 4u; ++i) v4[i] = 1.0f / (1.0f + expf(-(zpart[i] + b3)));
+    wave_lds_sync();   // the tile may be reused
 }
 
 __device__ __forceinline__ RowFeat no_row()
