@@ -62,6 +62,20 @@ __host__ __device__ inline VnPtrs vn_ptrs(void *net)
     return p;
 }
 
+// Inside the kernels the features are kept kind-major: internal feature p =
+// 24 * kind + t for tile t and kind 0..3 (owner seat relative to q), 4
+// (revealed), 5 (pool); 144 + m for (mover - q) mod P = m; zero above.  The
+// canonical (tile-major) index f = 6 t + kind of the master weights maps to p
+// = vn_perm(f); the bf16 shadows of W1 and the weight gradient of W1 use p.
+// This order makes a block of 32 features one word of the concatenated
+// masks, so a lane's 8 features are one byte.
+__device__ __forceinline__ uint32_t vn_perm(uint32_t f)
+{
+    if (f >= 144u) return f;
+    const uint32_t t = f / 6u;
+    return 24u * (f - 6u * t) + t;
+}
+
 // float -> bfloat16 bits, round to nearest even
 __device__ __forceinline__ uint16_t bf16_bits(float x)
 {
@@ -104,9 +118,9 @@ __global__ void vn_shadow_kernel(void *net)
     VnPtrs p = vn_ptrs(net);
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k < 40960u) {
-        const uint32_t n = k / kVnIn, f = k % kVnIn;
+        const uint32_t n = k / kVnIn, f = vn_perm(k % kVnIn);
         const uint16_t b = bf16_bits(p.master[kOffW1 + k]);
-        p.w1b[k] = b;
+        p.w1b[n * kVnIn + f] = b;
         p.w1tb[f * kVnH + n] = b;
     }
     if (k < 65536u) {
@@ -144,23 +158,28 @@ __device__ __forceinline__ RowFeat row_features(uint4 st, uint32_t q)
     return r;
 }
 
-__device__ __forceinline__ uint32_t feature_bit(const RowFeat &r, uint32_t f)
+// word s (bits 32s .. 32s+31) of the internal 160-bit feature vector
+__device__ __forceinline__ uint32_t feature_word(const RowFeat &r, uint32_t s)
 {
-    if (f < 144u) {
-        const uint32_t t = f / 6u, kind = f - t * 6u;
-        const uint32_t mask = kind == 0u ? r.rel[0] : kind == 1u ? r.rel[1] : kind == 2u ? r.rel[2]
-                            : kind == 3u ? r.rel[3] : kind == 4u ? r.rev : r.pool;
-        return (mask >> t) & 1u;
-    }
-    if (f < 148u) return (f - 144u) == r.tomove ? 1u : 0u;
-    return 0u;
+    const uint32_t mv = r.tomove < 4u ? 1u << r.tomove : 0u;
+    return s == 0u ? r.rel[0] | (r.rel[1] << 24)
+         : s == 1u ? (r.rel[1] >> 8) | (r.rel[2] << 16)
+         : s == 2u ? (r.rel[2] >> 16) | (r.rel[3] << 8)
+         : s == 3u ? r.rev | (r.pool << 24)
+                   : (r.pool >> 8) | (mv << 16);
 }
 
-__device__ __forceinline__ bf16x8 feature8(const RowFeat &r, uint32_t f0)
+// the eight features 32s + 8g .. 32s + 8g + 7 as bfloat16 1.0 / 0.0
+__device__ __forceinline__ bf16x8 feature8(const RowFeat &r, uint32_t s, uint32_t g)
 {
+    const uint32_t b = feature_word(r, s) >> (8u * g);
+    uint4 u;
+    u.x = ((b & 1u) ? 0x3F80u : 0u) | ((b & 2u) ? 0x3F800000u : 0u);
+    u.y = ((b & 4u) ? 0x3F80u : 0u) | ((b & 8u) ? 0x3F800000u : 0u);
+    u.z = ((b & 16u) ? 0x3F80u : 0u) | ((b & 32u) ? 0x3F800000u : 0u);
+    u.w = ((b & 64u) ? 0x3F80u : 0u) | ((b & 128u) ? 0x3F800000u : 0u);
     bf16x8 x;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) x[i] = feature_bit(r, f0 + (uint32_t)i) ? (__bf16)1.0f : (__bf16)0.0f;
+    __builtin_memcpy(&x, &u, 16);
     return x;
 }
 
@@ -206,7 +225,7 @@ __device__ __forceinline__ void vn_eval16(const VnPtrs &P, const RowFeat &rf,
     const uint32_t lane = threadIdx.x & 63u, r = lane & 15u, g = lane >> 4;
     bf16x8 xa[5];
 #pragma unroll
-    for (uint32_t s = 0; s < 5u; ++s) xa[s] = feature8(rf, 32u * s + 8u * g);
+    for (uint32_t s = 0; s < 5u; ++s) xa[s] = feature8(rf, s, g);
 #pragma unroll 4
     for (uint32_t j = 0; j < 16u; ++j) {
         floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -286,54 +305,6 @@ __device__ __forceinline__ void vn_layer_deep(const bf16x8 (&a)[KS], const uint1
     }
 }
 
-__device__ __forceinline__ void vn_eval16_deep(const VnPtrs &P, const RowFeat &rf,
-                                               uint16_t (*hs)[kVnH + 8], float v4[4])
-{
-    const uint32_t lane = threadIdx.x & 63u, r = lane & 15u, g = lane >> 4;
-    // the lane's biases and output weights first: a load issued inside the
-    // product loop would make every wait cover all older weight loads
-    float b1v[16], b2v[16], w3v[16];
-    const float b3 = P.master[kOffB3];
-#pragma unroll
-    for (uint32_t j = 0; j < 16u; ++j) {
-        b1v[j] = P.master[kOffB1 + 16u * j + r];
-        b2v[j] = P.master[kOffB2 + 16u * j + r];
-        w3v[j] = bf16_to_f(P.w3b[16u * j + r]);
-    }
-    bf16x8 xa[5];
-#pragma unroll
-    for (uint32_t s = 0; s < 5u; ++s) xa[s] = feature8(rf, 32u * s + 8u * g);
-    vn_layer_deep<5, kVnIn>(xa, P.w1b, r, g, [&](uint32_t j, const floatx4 &acc) {
-        const float b = b1v[j];
-#pragma unroll
-        for (uint32_t i = 0; i < 4u; ++i) {
-            const float h = acc[i] + b;
-            hs[4u * g + i][16u * j + r] = bf16_bits(h > 0.0f ? h : 0.0f);
-        }
-    });
-    __syncthreads();
-    bf16x8 ha[8];
-#pragma unroll
-    for (uint32_t s = 0; s < 8u; ++s) ha[s] = load8(&hs[r][32u * s + 8u * g]);
-    float zpart[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-    vn_layer_deep<8, kVnH>(ha, P.w2b, r, g, [&](uint32_t j, const floatx4 &acc) {
-        const float b = b2v[j];
-        const float w3 = w3v[j];
-#pragma unroll
-        for (uint32_t i = 0; i < 4u; ++i) {
-            const float h = acc[i] + b;
-            zpart[i] += bf16_round(h > 0.0f ? h : 0.0f) * w3;
-        }
-    });
-#pragma unroll
-    for (uint32_t i = 0; i < 4u; ++i)
-#pragma unroll
-        for (int off = 1; off < 16; off <<= 1) zpart[i] += __shfl_xor(zpart[i], off, 64);
-#pragma unroll
-    for (uint32_t i = 0; i < 4u; ++i) v4[i] = 1.0f / (1.0f + expf(-(zpart[i] + b3)));
-    __syncthreads();   // hs may be reused by the caller
-}
-
 // The evaluation inside a tree search: at most four rows (one per seat
 // perspective) in a 4 x 264 LDS tile, first-layer weights streamed from L2
 // through the load ring, second-layer weights read from the LDS copy the
@@ -371,7 +342,7 @@ __device__ __forceinline__ void vn_eval_tree(const VnPtrs &P, const RowFeat &rf,
     const uint32_t lane = threadIdx.x & 63u, r = lane & 15u, g = lane >> 4;
     bf16x8 xa[5];
 #pragma unroll
-    for (uint32_t s = 0; s < 5u; ++s) xa[s] = feature8(rf, 32u * s + 8u * g);
+    for (uint32_t s = 0; s < 5u; ++s) xa[s] = feature8(rf, s, g);
     vn_layer_deep<5, kVnIn, 32>(xa, P.w1b, r, g, [&](uint32_t j, const floatx4 &acc) {
         if (g == 0u) {
             const float b1 = sm.b1[16u * j + r];
@@ -451,209 +422,10 @@ __global__ void __launch_bounds__(64) vn_infer_kernel(const void *net, const uin
 
 constexpr uint32_t kPartWords = 2u + 3u * 256u;   // loss, db3, dw3[256], db2[256], db1[256]
 
-template <bool TRAIN>
-__global__ void __launch_bounds__(64) vn_rows_kernel(VnRowsArgs a)
-{
-    __shared__ __attribute__((aligned(16))) uint16_t hs[16][kVnH + 8];   // h1, then dh2 tile (bf16)
-    const VnPtrs P = vn_ptrs(const_cast<void *>(a.net));
-    const uint32_t lane = threadIdx.x, r = lane & 15u, g = lane >> 4;
-    const uint32_t row0 = blockIdx.x * 16u;
-    const uint32_t myrow = row0 + r;
-    const bool has = myrow < a.n_rows;
-    uint32_t src = myrow;
-    if (TRAIN && has) src = (uint32_t)(((uint64_t)a.perm_a * (a.row_base + myrow) + a.perm_b) % a.n_data);
-    RowFeat rf;
-    if (has) {
-        rf = row_features(a.states[src], a.persp[src]);
-    } else {
-        rf.ok = false;
-    }
-    if (has && !rf.ok) atomicOr(&g_error_word, kErrState);
-    if (!rf.ok) {
-        rf.rel[0] = rf.rel[1] = rf.rel[2] = rf.rel[3] = 0u;
-        rf.rev = rf.pool = 0u;
-        rf.tomove = 7u;
-    }
-
-    // ---- layer 1: h1 = bf16(relu(W1 x + b1)) -------------------------------
-    bf16x8 xa[5];
-#pragma unroll
-    for (uint32_t s = 0; s < 5u; ++s) xa[s] = feature8(rf, 32u * s + 8u * g);
-    if (TRAIN && has) {
-        // X^T for the weight gradient: feature-major, rows contiguous.  The
-        // bits are recomputed rather than extracted from the bf16 operand
-        // vectors (gfx950 builds stored element 0 for every element).
-#pragma unroll
-        for (uint32_t s = 0; s < 5u; ++s)
-#pragma unroll
-            for (uint32_t i = 0; i < 8u; ++i) {
-                const uint32_t f = 32u * s + 8u * g + i;
-                a.xt[(size_t)f * a.n_rows + myrow] = feature_bit(rf, f) ? (uint16_t)0x3F80u : (uint16_t)0u;
-            }
-    }
-    uint64_t h1pos = 0ull;   // bit 4j+i: h1 of row 4g+i, column 16j+r is positive
-#pragma unroll 4
-    for (uint32_t j = 0; j < 16u; ++j) {
-        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-        const uint16_t *wrow = P.w1b + (size_t)(16u * j + r) * kVnIn + 8u * g;
-#pragma unroll
-        for (uint32_t s = 0; s < 5u; ++s) acc = mfma16(xa[s], load8(wrow + 32u * s), acc);
-        const float b = P.master[kOffB1 + 16u * j + r];
-        uint16_t hq[4];
-#pragma unroll
-        for (uint32_t i = 0; i < 4u; ++i) {
-            const float h = acc[i] + b;
-            hq[i] = bf16_bits(h > 0.0f ? h : 0.0f);
-            hs[4u * g + i][16u * j + r] = hq[i];
-            h1pos |= (uint64_t)(h > 0.0f) << (4u * j + i);
-        }
-        if (TRAIN) {
-            const uint32_t rr = row0 + 4u * g;
-            if (rr + 3u < a.n_rows) {
-                const uint2 packed = make_uint2((uint32_t)hq[0] | ((uint32_t)hq[1] << 16),
-                                                (uint32_t)hq[2] | ((uint32_t)hq[3] << 16));
-                *reinterpret_cast<uint2 *>(a.h1t + (size_t)(16u * j + r) * a.n_rows + rr) = packed;
-            }
-        }
-    }
-    __syncthreads();
-
-    // ---- layer 2: h2 = bf16(relu(W2 h1 + b2)) ------------------------------
-    bf16x8 ha[8];
-#pragma unroll
-    for (uint32_t s = 0; s < 8u; ++s) ha[s] = load8(&hs[r][32u * s + 8u * g]);
-    floatx4 h2[16];
-    float zpart[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-    for (uint32_t j = 0; j < 16u; ++j) {
-        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-        const uint16_t *wrow = P.w2b + (size_t)(16u * j + r) * kVnH + 8u * g;
-#pragma unroll
-        for (uint32_t s = 0; s < 8u; ++s) acc = mfma16(ha[s], load8(wrow + 32u * s), acc);
-        const float b = P.master[kOffB2 + 16u * j + r];
-        const float w3 = bf16_to_f(P.w3b[16u * j + r]);
-#pragma unroll
-        for (uint32_t i = 0; i < 4u; ++i) {
-            const float h = acc[i] + b;
-            h2[j][i] = bf16_round(h > 0.0f ? h : 0.0f);
-            zpart[i] += h2[j][i] * w3;
-        }
-    }
-    // sum the 16 columns held by the lanes of one row group
-#pragma unroll
-    for (uint32_t i = 0; i < 4u; ++i)
-#pragma unroll
-        for (int off = 1; off < 16; off <<= 1) zpart[i] += __shfl_xor(zpart[i], off, 64);
-    const float b3 = P.master[kOffB3];
-    float v4[4];
-#pragma unroll
-    for (uint32_t i = 0; i < 4u; ++i) v4[i] = 1.0f / (1.0f + expf(-(zpart[i] + b3)));
-    if (!TRAIN) {
-        if (r == 0u && a.v_out) {
-#pragma unroll
-            for (uint32_t i = 0; i < 4u; ++i) {
-                const uint32_t row = row0 + 4u * g + i;
-                if (row < a.n_rows) a.v_out[row] = v4[i];
-            }
-        }
-        return;
-    }
-
-    // ---- training: loss, dz, dh2, layer-2 data backward -----------------------
-    // labels of rows 4g+i (each lane of a group computes the same values)
-    float dz[4], err2 = 0.0f;
-#pragma unroll
-    for (uint32_t i = 0; i < 4u; ++i) {
-        const uint32_t row = row0 + 4u * g + i;
-        float y = 0.0f, d = 0.0f;
-        if (row < a.n_rows) {
-            const uint32_t sr = (uint32_t)(((uint64_t)a.perm_a * (a.row_base + row) + a.perm_b) % a.n_data);
-            y = a.labels[sr];
-            const float e = v4[i] - y;
-            err2 += e * e;
-            d = 2.0f * e * a.inv_batch * v4[i] * (1.0f - v4[i]);
-        }
-        dz[i] = d;
-    }
-    float *part = a.part + (size_t)blockIdx.x * kPartWords;
-    // loss and db3: one lane per row group, then across the four groups
-    float l4 = r == 0u ? err2 : 0.0f, d3 = r == 0u ? dz[0] + dz[1] + dz[2] + dz[3] : 0.0f;
-    for (int off = 1; off < 64; off <<= 1) {
-        l4 += __shfl_xor(l4, off, 64);
-        d3 += __shfl_xor(d3, off, 64);
-    }
-    if (lane == 0) {
-        part[0] = l4;
-        part[1] = d3;
-    }
-    __syncthreads();   // all lanes are done reading h1 from hs
-#pragma unroll
-    for (uint32_t j = 0; j < 16u; ++j) {
-        const uint32_t col = 16u * j + r;
-        const float w3 = bf16_to_f(P.w3b[col]);
-        float dw3 = 0.0f, db2 = 0.0f;
-        uint16_t dq[4];
-#pragma unroll
-        for (uint32_t i = 0; i < 4u; ++i) {
-            dw3 += dz[i] * h2[j][i];
-            const float d = h2[j][i] > 0.0f ? dz[i] * w3 : 0.0f;
-            dq[i] = bf16_bits(d);
-            db2 += bf16_to_f(dq[i]);
-            hs[4u * g + i][col] = dq[i];
-        }
-        // dh2^T rows contiguous: four rows of one column per lane
-        const uint32_t rr = row0 + 4u * g;
-        if (rr + 3u < a.n_rows) {
-            const uint2 packed = make_uint2((uint32_t)dq[0] | ((uint32_t)dq[1] << 16),
-                                            (uint32_t)dq[2] | ((uint32_t)dq[3] << 16));
-            *reinterpret_cast<uint2 *>(a.dh2t + (size_t)col * a.n_rows + rr) = packed;
-        }
-        dw3 += __shfl_xor(dw3, 16, 64);
-        dw3 += __shfl_xor(dw3, 32, 64);
-        db2 += __shfl_xor(db2, 16, 64);
-        db2 += __shfl_xor(db2, 32, 64);
-        if (g == 0u) {
-            part[2u + col] = dw3;
-            part[2u + 256u + col] = db2;
-        }
-    }
-    __syncthreads();
-    // dh1 = (dh2 W2) * (h1 > 0): A = dh2 rows from LDS, B from W2 transposed
-    bf16x8 da[8];
-#pragma unroll
-    for (uint32_t s = 0; s < 8u; ++s) da[s] = load8(&hs[r][32u * s + 8u * g]);
-#pragma unroll 4
-    for (uint32_t j = 0; j < 16u; ++j) {
-        const uint32_t col = 16u * j + r;
-        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-        const uint16_t *wrow = P.w2tb + (size_t)col * kVnH + 8u * g;
-#pragma unroll
-        for (uint32_t s = 0; s < 8u; ++s) acc = mfma16(da[s], load8(wrow + 32u * s), acc);
-        float db1 = 0.0f;
-        uint16_t dq[4];
-#pragma unroll
-        for (uint32_t i = 0; i < 4u; ++i) {
-            const float d = ((h1pos >> (4u * j + i)) & 1ull) ? acc[i] : 0.0f;
-            dq[i] = bf16_bits(d);
-            db1 += bf16_to_f(dq[i]);
-        }
-        const uint32_t rr = row0 + 4u * g;
-        if (rr + 3u < a.n_rows) {
-            const uint2 packed = make_uint2((uint32_t)dq[0] | ((uint32_t)dq[1] << 16),
-                                            (uint32_t)dq[2] | ((uint32_t)dq[3] << 16));
-            *reinterpret_cast<uint2 *>(a.dh1t + (size_t)col * a.n_rows + rr) = packed;
-        }
-        db1 += __shfl_xor(db1, 16, 64);
-        db1 += __shfl_xor(db1, 32, 64);
-        if (g == 0u) part[2u + 512u + col] = db1;
-    }
-}
-
 // Training rows, four wavefronts per 16-row tile: wavefront w computes output
 // columns 64w..64w+63 of every layer (a quarter of each weight matrix), the
-// tiles of activations and gradients being shared through LDS.  Same
-// arithmetic as vn_rows_kernel<true> except that z sums the four quarters'
-// partial dot products in wavefront order.
+// tiles of activations and gradients being shared through LDS; z sums the
+// four quarters' partial dot products in wavefront order.
 __global__ void __launch_bounds__(256) vn_rows4_kernel(VnRowsArgs a)
 {
     __shared__ __attribute__((aligned(16))) uint16_t hs[16][kVnH + 8];   // h1, then dh2 tile (bf16)
@@ -677,15 +449,17 @@ __global__ void __launch_bounds__(256) vn_rows4_kernel(VnRowsArgs a)
     // ---- layer 1: h1 = bf16(relu(W1 x + b1)), columns of this wavefront ----
     bf16x8 xa[5];
 #pragma unroll
-    for (uint32_t s = 0; s < 5u; ++s) xa[s] = feature8(rf, 32u * s + 8u * g);
+    for (uint32_t s = 0; s < 5u; ++s) xa[s] = feature8(rf, s, g);
     if (has) {
-        // X^T for the weight gradient (feature blocks split over the wavefronts)
-        for (uint32_t s = wv; s < 5u; s += 4u)
+        // X^T (internal feature order) for the weight gradient, feature
+        // blocks split over the wavefronts
+        for (uint32_t s = wv; s < 5u; s += 4u) {
+            const uint32_t b = feature_word(rf, s) >> (8u * g);
 #pragma unroll
-            for (uint32_t i = 0; i < 8u; ++i) {
-                const uint32_t f = 32u * s + 8u * g + i;
-                a.xt[(size_t)f * a.n_rows + myrow] = feature_bit(rf, f) ? (uint16_t)0x3F80u : (uint16_t)0u;
-            }
+            for (uint32_t i = 0; i < 8u; ++i)
+                a.xt[(size_t)(32u * s + 8u * g + i) * a.n_rows + myrow] =
+                    ((b >> i) & 1u) ? (uint16_t)0x3F80u : (uint16_t)0u;
+        }
     }
     uint32_t h1pos = 0u;   // bit 4jj+i: h1 of row 4g+i, column 16(4wv+jj)+r is positive
 #pragma unroll
@@ -888,8 +662,10 @@ __global__ void vn_adam_kernel(void *net, const float *grad, uint32_t slices, co
     float gk;
     if (k < kOffB1 || (k >= kOffW2 && k < kOffB2)) {
         // weight gradients: the batch slices' partial sums, in slice order
-        gk = grad[k];
-        for (uint32_t sl = 1; sl < slices; ++sl) gk += grad[(size_t)sl * kVnPad + k];
+        // (the W1 gradient is laid out in the internal feature order)
+        const uint32_t kg = k < kOffB1 ? (k / kVnIn) * kVnIn + vn_perm(k % kVnIn) : k;
+        gk = grad[kg];
+        for (uint32_t sl = 1; sl < slices; ++sl) gk += grad[(size_t)sl * kVnPad + kg];
     } else {
         const uint32_t idx = k == kOffB3 ? 1u
                            : k >= kOffW3 ? 2u + (k - kOffW3)
@@ -906,8 +682,8 @@ __global__ void vn_adam_kernel(void *net, const float *grad, uint32_t slices, co
     P.master[k] = w;
     const uint16_t b = bf16_bits(w);
     if (k < kOffB1) {
-        const uint32_t n = k / kVnIn, f = k % kVnIn;
-        P.w1b[k] = b;
+        const uint32_t n = k / kVnIn, f = vn_perm(k % kVnIn);
+        P.w1b[n * kVnIn + f] = b;
         P.w1tb[f * kVnH + n] = b;
     } else if (k >= kOffW2 && k < kOffB2) {
         const uint32_t kk = k - kOffW2, n = kk / kVnH, i = kk % kVnH;
