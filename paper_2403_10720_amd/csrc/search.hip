@@ -374,18 +374,15 @@ mcts_tree_kernel(MctsArgs a)
     __shared__ uint32_t path_all[TG][kMaxDepthLimit + 1];
     __shared__ DfsSlots dfs_all[TG];
     __shared__ __attribute__((aligned(16))) uint16_t tile_all[TG][4][kVnH + 8];
-    __shared__ __attribute__((aligned(16))) uint16_t w2_lds[VALUE ? kVnH : 1][kVnH + 8];
+    __shared__ __attribute__((aligned(16))) uint16_t w2_lds[VALUE ? kVnH * kVnH : 8];
     __shared__ VnSmall vn_small[1];
     fill_kth_table(tab);
     if (VALUE) {
         vn_stage_small(vn_ptrs(const_cast<void *>(a.net)), vn_small[0]);
-        // second-layer weights (bf16, rows padded to 264 to spread LDS banks)
-        const uint16_t *w2 = vn_ptrs(const_cast<void *>(a.net)).w2b;
-        for (uint32_t c = threadIdx.x; c < kVnH * kVnH / 8u; c += blockDim.x) {
-            const uint32_t row = c >> 5, col = (c & 31u) * 8u;
-            *reinterpret_cast<uint4 *>(&w2_lds[row][col]) =
-                *reinterpret_cast<const uint4 *>(w2 + row * kVnH + col);
-        }
+        // second-layer weights (bf16, in the packed fragment order)
+        const uint4 *w2 = reinterpret_cast<const uint4 *>(vn_ptrs(const_cast<void *>(a.net)).w2b);
+        for (uint32_t c = threadIdx.x; c < kVnH * kVnH / 8u; c += blockDim.x)
+            reinterpret_cast<uint4 *>(w2_lds)[c] = w2[c];
     }
     __syncthreads();   // the only workgroup barrier
     const uint32_t wv = TG == 1u ? 0u : __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);

@@ -36,14 +36,24 @@ constexpr uint64_t kVnVOff = kVnMOff + (uint64_t)kVnPad * 4u;
 constexpr uint64_t kVnW1bOff = kVnVOff + (uint64_t)kVnPad * 4u;
 constexpr uint64_t kVnW2bOff = kVnW1bOff + 40960u * 2u;
 constexpr uint64_t kVnW2TbOff = kVnW2bOff + 65536u * 2u;
-constexpr uint64_t kVnW1TbOff = kVnW2TbOff + 65536u * 2u;
-constexpr uint64_t kVnW3bOff = kVnW1TbOff + 40960u * 2u;
+constexpr uint64_t kVnW3bOff = kVnW2TbOff + 65536u * 2u;
 constexpr uint64_t kVnBytes = kVnW3bOff + 256u * 2u;
+
+// The bf16 shadows of W1, W2 and W2 transposed are stored as ready-made B
+// operands of the 16x16x32 product: fragment q = j * KS + s (output column
+// tile j, k block s, KS = 5 for W1 and 8 for W2) holds, for lane l = 16 g +
+// r, the 8 values W[16 j + r][32 s + 8 g .. + 7] at (q * 64 + l) * 8, so a
+// wavefront reads a fragment as one contiguous kilobyte.
+__host__ __device__ constexpr uint32_t vn_frag(uint32_t row, uint32_t col, uint32_t ks)
+{
+    return ((((row >> 4) * ks + (col >> 5)) * 64u + ((col >> 3) & 3u) * 16u + (row & 15u)) << 3) +
+           (col & 7u);
+}
 
 struct VnPtrs {
     uint32_t *header;
     float *master, *m, *v;
-    uint16_t *w1b, *w2b, *w2tb, *w1tb, *w3b;
+    uint16_t *w1b, *w2b, *w2tb, *w3b;
 };
 
 __host__ __device__ inline VnPtrs vn_ptrs(void *net)
@@ -57,7 +67,6 @@ __host__ __device__ inline VnPtrs vn_ptrs(void *net)
     p.w1b = (uint16_t *)(b + kVnW1bOff);
     p.w2b = (uint16_t *)(b + kVnW2bOff);
     p.w2tb = (uint16_t *)(b + kVnW2TbOff);
-    p.w1tb = (uint16_t *)(b + kVnW1TbOff);
     p.w3b = (uint16_t *)(b + kVnW3bOff);
     return p;
 }
@@ -119,15 +128,13 @@ __global__ void vn_shadow_kernel(void *net)
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k < 40960u) {
         const uint32_t n = k / kVnIn, f = vn_perm(k % kVnIn);
-        const uint16_t b = bf16_bits(p.master[kOffW1 + k]);
-        p.w1b[n * kVnIn + f] = b;
-        p.w1tb[f * kVnH + n] = b;
+        p.w1b[vn_frag(n, f, 5u)] = bf16_bits(p.master[kOffW1 + k]);
     }
     if (k < 65536u) {
         const uint32_t n = k / kVnH, i = k % kVnH;
         const uint16_t b = bf16_bits(p.master[kOffW2 + k]);
-        p.w2b[k] = b;
-        p.w2tb[i * kVnH + n] = b;
+        p.w2b[vn_frag(n, i, 8u)] = b;
+        p.w2tb[vn_frag(i, n, 8u)] = b;
     }
     if (k < 256u) p.w3b[k] = bf16_bits(p.master[kOffW3 + k]);
 }
@@ -229,9 +236,9 @@ __device__ __forceinline__ void vn_eval16(const VnPtrs &P, const RowFeat &rf,
 #pragma unroll 4
     for (uint32_t j = 0; j < 16u; ++j) {
         floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-        const uint16_t *wrow = P.w1b + (size_t)(16u * j + r) * kVnIn + 8u * g;
 #pragma unroll
-        for (uint32_t s = 0; s < 5u; ++s) acc = mfma16(xa[s], load8(wrow + 32u * s), acc);
+        for (uint32_t s = 0; s < 5u; ++s)
+            acc = mfma16(xa[s], load8(P.w1b + ((j * 5u + s) * 64u + lane) * 8u), acc);
         const float b = P.master[kOffB1 + 16u * j + r];
 #pragma unroll
         for (uint32_t i = 0; i < 4u; ++i) {
@@ -247,9 +254,9 @@ __device__ __forceinline__ void vn_eval16(const VnPtrs &P, const RowFeat &rf,
 #pragma unroll 4
     for (uint32_t j = 0; j < 16u; ++j) {
         floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-        const uint16_t *wrow = P.w2b + (size_t)(16u * j + r) * kVnH + 8u * g;
 #pragma unroll
-        for (uint32_t s = 0; s < 8u; ++s) acc = mfma16(ha[s], load8(wrow + 32u * s), acc);
+        for (uint32_t s = 0; s < 8u; ++s)
+            acc = mfma16(ha[s], load8(P.w2b + ((j * 8u + s) * 64u + lane) * 8u), acc);
         const float b = P.master[kOffB2 + 16u * j + r];
         const float w3 = bf16_to_f(P.w3b[16u * j + r]);
 #pragma unroll
@@ -284,9 +291,9 @@ __device__ __forceinline__ void vn_layer_deep(const bf16x8 (&a)[KS], const uint1
     constexpr int N = 16 * KS;
     constexpr int kVnRing = RING;
     bf16x8 ring[kVnRing];
+    const uint32_t lane = 16u * g + r;
 #pragma unroll
-    for (int q = 0; q < kVnRing; ++q)
-        ring[q] = load8(w + (size_t)(16u * (uint32_t)(q / KS) + r) * LD + 8u * g + 32u * (uint32_t)(q % KS));
+    for (int q = 0; q < kVnRing; ++q) ring[q] = load8(w + ((uint32_t)q * 64u + lane) * 8u);
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
         floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -295,9 +302,7 @@ __device__ __forceinline__ void vn_layer_deep(const bf16x8 (&a)[KS], const uint1
             const int q = j * KS + s;
             const bf16x8 b = ring[q % kVnRing];
             if (q + kVnRing < N) {
-                const int qn = q + kVnRing;
-                ring[q % kVnRing] = load8(w + (size_t)(16u * (uint32_t)(qn / KS) + r) * LD + 8u * g +
-                                          32u * (uint32_t)(qn % KS));
+                ring[q % kVnRing] = load8(w + ((uint32_t)(q + kVnRing) * 64u + lane) * 8u);
             }
             acc = mfma16(a[s], b, acc);
         }
@@ -336,7 +341,7 @@ __device__ __forceinline__ void vn_stage_small(const VnPtrs &P, VnSmall &sm)
 
 __device__ __forceinline__ void vn_eval_tree(const VnPtrs &P, const RowFeat &rf,
                                              uint16_t (*tile)[kVnH + 8],
-                                             const uint16_t (*w2l)[kVnH + 8], const VnSmall &sm,
+                                             const uint16_t *w2l, const VnSmall &sm,
                                              float v4[4])
 {
     const uint32_t lane = threadIdx.x & 63u, r = lane & 15u, g = lane >> 4;
@@ -362,7 +367,7 @@ __device__ __forceinline__ void vn_eval_tree(const VnPtrs &P, const RowFeat &rf,
     for (uint32_t j = 0; j < 16u; ++j) {
         bf16x8 wb[8];
 #pragma unroll
-        for (uint32_t s = 0; s < 8u; ++s) wb[s] = load8(&w2l[16u * j + r][32u * s + 8u * g]);
+        for (uint32_t s = 0; s < 8u; ++s) wb[s] = load8(w2l + ((j * 8u + s) * 64u + lane) * 8u);
         floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (uint32_t s = 0; s < 8u; ++s) acc = mfma16(ha[s], wb[s], acc);
@@ -466,9 +471,9 @@ __global__ void __launch_bounds__(256) vn_rows4_kernel(VnRowsArgs a)
     for (uint32_t jj = 0; jj < 4u; ++jj) {
         const uint32_t j = 4u * wv + jj;
         floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-        const uint16_t *wrow = P.w1b + (size_t)(16u * j + r) * kVnIn + 8u * g;
 #pragma unroll
-        for (uint32_t s = 0; s < 5u; ++s) acc = mfma16(xa[s], load8(wrow + 32u * s), acc);
+        for (uint32_t s = 0; s < 5u; ++s)
+            acc = mfma16(xa[s], load8(P.w1b + ((j * 5u + s) * 64u + lane) * 8u), acc);
         const float b = P.master[kOffB1 + 16u * j + r];
         uint16_t hq[4];
 #pragma unroll
@@ -497,9 +502,9 @@ __global__ void __launch_bounds__(256) vn_rows4_kernel(VnRowsArgs a)
     for (uint32_t jj = 0; jj < 4u; ++jj) {
         const uint32_t j = 4u * wv + jj;
         floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-        const uint16_t *wrow = P.w2b + (size_t)(16u * j + r) * kVnH + 8u * g;
 #pragma unroll
-        for (uint32_t s = 0; s < 8u; ++s) acc = mfma16(ha[s], load8(wrow + 32u * s), acc);
+        for (uint32_t s = 0; s < 8u; ++s)
+            acc = mfma16(ha[s], load8(P.w2b + ((j * 8u + s) * 64u + lane) * 8u), acc);
         const float b = P.master[kOffB2 + 16u * j + r];
         const float w3 = bf16_to_f(P.w3b[16u * j + r]);
 #pragma unroll
@@ -588,9 +593,10 @@ __global__ void __launch_bounds__(256) vn_rows4_kernel(VnRowsArgs a)
     for (uint32_t jj = 0; jj < 4u; ++jj) {
         const uint32_t col = 16u * (4u * wv + jj) + r;
         floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-        const uint16_t *wrow = P.w2tb + (size_t)col * kVnH + 8u * g;
+        const uint32_t j = 4u * wv + jj;
 #pragma unroll
-        for (uint32_t s = 0; s < 8u; ++s) acc = mfma16(da[s], load8(wrow + 32u * s), acc);
+        for (uint32_t s = 0; s < 8u; ++s)
+            acc = mfma16(da[s], load8(P.w2tb + ((j * 8u + s) * 64u + lane) * 8u), acc);
         float db1 = 0.0f;
         uint16_t dq[4];
 #pragma unroll
@@ -683,12 +689,11 @@ __global__ void vn_adam_kernel(void *net, const float *grad, uint32_t slices, co
     const uint16_t b = bf16_bits(w);
     if (k < kOffB1) {
         const uint32_t n = k / kVnIn, f = vn_perm(k % kVnIn);
-        P.w1b[n * kVnIn + f] = b;
-        P.w1tb[f * kVnH + n] = b;
+        P.w1b[vn_frag(n, f, 5u)] = b;
     } else if (k >= kOffW2 && k < kOffB2) {
         const uint32_t kk = k - kOffW2, n = kk / kVnH, i = kk % kVnH;
-        P.w2b[kk] = b;
-        P.w2tb[i * kVnH + n] = b;
+        P.w2b[vn_frag(n, i, 8u)] = b;
+        P.w2tb[vn_frag(i, n, 8u)] = b;
     } else if (k >= kOffW3 && k < kOffB3) {
         P.w3b[k - kOffW3] = b;
     }
