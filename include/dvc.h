@@ -204,7 +204,7 @@ typedef struct {
     int32_t leaf_eval;          /* 0: playouts; 1: value network with fallback      */
     float fallback_band;        /* value mode: playouts when |v - 0.5| < band       */
     int32_t fallback_playouts;  /* value mode: playouts of a fallback leaf          */
-    const void *valuenet;       /* value mode: dvc_valuenet weights (device)        */
+    const void *valuenet;       /* value mode: dvc_valuenet blob (device, 16-aligned) */
 } dvc_mcts_params;
 
 /* one root child, in creation order; action 0xFFFF marks unused entries */
@@ -261,7 +261,9 @@ int mcts_search_root_parallel(const dvc_state_t *roots, int64_t n_roots, int32_t
  * ------------------------------------------------------------------------- */
 #define DVC_VALUENET_PARAMS 107265
 
-/* bytes of a network blob: weights, Adam moments and bf16 copies (device) */
+/* bytes of a network blob: weights, Adam moments and bf16 copies (device).
+ * Every call taking a blob (and dvc_valuenet_train_step's workspace) needs
+ * it 16-byte aligned and returns DVC_EINVAL otherwise.                      */
 size_t dvc_valuenet_bytes(void);
 
 /* Initialize a blob: weight k of the flat order takes word k of the Philox

@@ -15,6 +15,9 @@ namespace dvc {
 
 static std::atomic<uint32_t> g_next_slot{0};
 
+// the network blob and the workspaces are read as 16-byte fragments
+static bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0u; }
+
 uint32_t next_queue_slot()
 {
     return g_next_slot.fetch_add(1u, std::memory_order_relaxed) % (uint32_t)kQueueSlots;
@@ -90,8 +93,8 @@ static bool mcts_params_ok(const dvc_mcts_params *p)
         return false;
     if (!(p->c_uct >= 0.0f) || std::isinf(p->c_uct)) return false;
     if (p->leaf_eval != 0 && p->leaf_eval != 1) return false;
-    if (p->leaf_eval == 1 && (p->valuenet == nullptr || p->fallback_playouts < 1 ||
-                              !(p->fallback_band >= 0.0f)))
+    if (p->leaf_eval == 1 && (p->valuenet == nullptr || !aligned16(p->valuenet) ||
+                              p->fallback_playouts < 1 || !(p->fallback_band >= 0.0f)))
         return false;
     // visit counts stay exact in float
     const uint64_t w_leaf = (uint64_t)(p->leaf_eval ? p->fallback_playouts : p->playouts_per_leaf);
@@ -397,19 +400,19 @@ size_t dvc_valuenet_bytes(void) { return vn_bytes(); }
 
 int dvc_valuenet_init(void *net, uint64_t seed, void *stream)
 {
-    if (net == nullptr) return DVC_EINVAL;
+    if (net == nullptr || !aligned16(net)) return DVC_EINVAL;
     return status_of(launch_vn_init(net, (uint32_t)seed, (uint32_t)(seed >> 32), (hipStream_t)stream));
 }
 
 int dvc_valuenet_set_params(void *net, const float *params, void *stream)
 {
-    if (net == nullptr || params == nullptr) return DVC_EINVAL;
+    if (net == nullptr || params == nullptr || !aligned16(net)) return DVC_EINVAL;
     return status_of(launch_vn_set_params(net, params, (hipStream_t)stream));
 }
 
 int dvc_valuenet_get_params(const void *net, float *params, void *stream)
 {
-    if (net == nullptr || params == nullptr) return DVC_EINVAL;
+    if (net == nullptr || params == nullptr || !aligned16(net)) return DVC_EINVAL;
     return status_of(launch_vn_get_params(net, params, (hipStream_t)stream));
 }
 
@@ -418,7 +421,9 @@ int dvc_valuenet_infer(const void *net, const dvc_state_t *states, const uint8_t
 {
     if (n < 0 || n >= (1ll << 31)) return DVC_EINVAL;
     if (n == 0) return DVC_OK;
-    if (net == nullptr || states == nullptr || persp == nullptr || v_out == nullptr) return DVC_EINVAL;
+    if (net == nullptr || states == nullptr || persp == nullptr || v_out == nullptr ||
+        !aligned16(net))
+        return DVC_EINVAL;
     return status_of(launch_vn_infer(net, reinterpret_cast<const uint4 *>(states), persp,
                                      (uint32_t)n, v_out, (hipStream_t)stream));
 }
@@ -434,7 +439,8 @@ int dvc_valuenet_train_step(void *net, const dvc_state_t *states, const uint8_t 
                             uint32_t row_base, int32_t batch, int64_t step, float lr, void *ws,
                             size_t ws_bytes, float *loss_out, float *grad_out, void *stream)
 {
-    if (net == nullptr || states == nullptr || persp == nullptr || labels == nullptr || ws == nullptr)
+    if (net == nullptr || states == nullptr || persp == nullptr || labels == nullptr || ws == nullptr ||
+        !aligned16(net) || !aligned16(ws))
         return DVC_EINVAL;
     if (batch < 32 || batch > 65536 || batch % 32 != 0 || n_data < 1 || n_data >= (1ll << 32) ||
         step < 1 || !(lr > 0.0f))

@@ -89,3 +89,12 @@ def test_autotune_argument_errors_without_device(lib):
     assert lib.dvc_rollout_autotune(vp(16), 0, 8, 0, 0, 0, None, None, None, None, None) == -1
     assert lib.dvc_rollout_autotune(None, 4, 8, 0, 0, 0, None, None, None, None, None) == -1
     assert lib.dvc_rollout_autotune(vp(16), 4, 0, 0, 0, 0, None, None, None, None, None) == -1
+
+
+def test_valuenet_alignment_errors_without_device(lib):
+    vp = C.c_void_p
+    lib.dvc_valuenet_init.argtypes = [vp, C.c_uint64, vp]
+    lib.dvc_valuenet_infer.argtypes = [vp, vp, vp, C.c_int64, vp, vp]
+    # misaligned blobs are rejected before any device work
+    assert lib.dvc_valuenet_init(vp(8), 1, None) == -1
+    assert lib.dvc_valuenet_infer(vp(24), vp(16), vp(16), 4, vp(16), None) == -1
