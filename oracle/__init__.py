@@ -19,6 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 
 MAX_CHILD = 864
+STOP_KEY = 864          # tree key of the stop choice; a guess after a right guess is 865 + a
 
 
 class DealParams(C.Structure):
@@ -32,7 +33,7 @@ class MctsParams(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("playouts_per_leaf", C.c_int32),
                 ("max_depth", C.c_int32), ("c_uct", C.c_float), ("leaf_eval", C.c_int32),
                 ("fallback_band", C.c_float), ("fallback_playouts", C.c_int32),
-                ("valuenet", C.c_void_p)]
+                ("valuenet", C.c_void_p), ("continue_choice", C.c_int32), ("vanilla", C.c_int32)]
 
 
 class Rows(C.Structure):
@@ -89,6 +90,8 @@ def lib():
         L.oracle_mcts_search_merged.argtypes = [C.c_void_p, C.c_int64, C.c_int32,
                                                 C.POINTER(MctsParams), C.c_uint64, C.c_uint32,
                                                 C.c_void_p, C.c_void_p]
+        L.oracle_mcts_tree_dump.argtypes = [C.c_void_p, C.POINTER(MctsParams), C.c_uint64,
+                                            C.c_uint32, C.c_void_p, C.c_void_p, C.c_int64]
         L.oracle_bf16.restype = C.c_float
         L.oracle_bf16.argtypes = [C.c_float]
         L.oracle_vn_encode.argtypes = [C.c_void_p, C.c_int32, C.c_void_p]
@@ -127,10 +130,15 @@ def deal_params(p_min=2, p_max=2, hand=(0, 0, 4, 4, 3), pile_min=0, pile_max=16,
 
 
 def mcts_params(iterations=2000, playouts_per_leaf=16, max_depth=4, c_uct=None, leaf_eval=0,
-                fallback_band=0.05, fallback_playouts=64, valuenet=None) -> MctsParams:
+                fallback_band=0.05, fallback_playouts=64, valuenet=None, continue_choice=0,
+                vanilla=0) -> MctsParams:
     """valuenet: float32 numpy array of the network parameters (value mode);
-    the caller keeps it alive while the search runs."""
+    the caller keeps it alive while the search runs.  max_depth 0: no depth
+    threshold; continue_choice 1: a right guess is followed by the same
+    player's stop-or-guess choice; vanilla 1: the root's children are the
+    sampled worlds (children then come back indexed by action id)."""
     m = MctsParams()
+    m.continue_choice, m.vanilla = continue_choice, vanilla
     m.iterations, m.playouts_per_leaf, m.max_depth = iterations, playouts_per_leaf, max_depth
     m.c_uct = float(np.float32(np.sqrt(2.0))) if c_uct is None else c_uct
     m.leaf_eval, m.fallback_band, m.fallback_playouts = leaf_eval, fallback_band, fallback_playouts
@@ -281,6 +289,25 @@ def mcts_search_merged(roots, trees_per_root: int, params: MctsParams, seed: int
     if rc:
         raise ValueError(f"oracle_mcts_search_merged failed ({rc})")
     return best, kids
+
+
+TREE_NODE_DTYPE = np.dtype([("parent", np.int32), ("key", np.int32), ("chooser", np.int32),
+                            ("depth", np.int32), ("n", np.uint32), ("w", np.float32),
+                            ("world", np.uint64)])
+
+
+def mcts_tree(root, params: MctsParams, seed: int, tree_id: int = 0):
+    """(best action, every node of the searched tree in creation order as a
+    TREE_NODE_DTYPE array: parent, key, chooser, depth, N, W, world key)."""
+    s = _states(root)[:1]
+    w_nodes = 2 * params.iterations + 1
+    out = np.zeros(w_nodes, TREE_NODE_DTYPE)
+    best = C.c_int32(0)
+    n = lib().oracle_mcts_tree_dump(_ptr(s), C.byref(params), seed, tree_id, C.byref(best),
+                                    _ptr(out), w_nodes)
+    if n < 0:
+        raise ValueError(f"oracle_mcts_tree_dump failed ({n})")
+    return best.value, out[:n]
 
 
 # ---------------------------------------------------------------------------

@@ -5,12 +5,18 @@
  * TEST INFRASTRUCTURE ONLY (see oracle.h).
  *
  * The four MCTS steps (selection, expansion, simulation, backpropagation)
- * with the paper's three simplifications:
+ * with the paper's three simplifications (Sec. III-A), each of which can be
+ * switched off:
  *   1. a node is only (tile position, guessed number); the sampled set of
- *      plausible opponent numbers is not part of the node;
- *   2. guessing stops after a right guess inside the tree;
+ *      plausible opponent numbers is not part of the node.  Off (`vanilla`):
+ *      the root's children are the sampled worlds, one node per distinct set
+ *      of opponent numbers, and the guesses hang below them;
+ *   2. guessing stops after a right guess inside the tree.  Off
+ *      (`continue_choice`): after a right guess the same player chooses
+ *      between stopping (key 864) and another guess (key 865 + action), so
+ *      a player's further guesses are nodes of their own;
  *   3. nodes at a fixed depth threshold are not expanded further: they only
- *      simulate and back up.
+ *      simulate and back up.  Off: max_depth 0.
  * The opponent tiles are a black box to the searching player, so every
  * iteration first samples a plausible set of numbers for them (Sec. III-A);
  * the tree is open loop over those samples.
@@ -306,30 +312,56 @@ int oracle_legal_actions(const orc_packed *ps, uint8_t legal[ORC_MAX_CHILD])
     return 0;
 }
 
-/* Apply a guess inside the tree (simplification 2: the turn ends after it).
+/* The turn passes: the next seat with hidden tiles draws (word w1). */
+static void end_turn(orc_rows *s, int m, uint32_t w1)
+{
+    int nm = next_alive_after(s, m);
+    s->mover = nm;
+    s->phase = 1;
+    s->drawn = -1;
+    if (s->pile_n > 0) {
+        int k = (int)oracle_mulshift(w1, (uint32_t)s->pile_n);
+        int d = s->pile[k];
+        for (int j = k; j + 1 < s->pile_n; ++j) s->pile[j] = s->pile[j + 1];
+        s->pile_n--;
+        row_insert(s, nm, d);
+        s->drawn = d;
+    }
+}
+
+/* Play tree key `key` (a guess, the stop 864, or a further guess 865 + a).
  * Chance comes from block (depth, 0xC0000000, iter, tree): word 0 picks the
  * mover's own tile to reveal after a wrong guess when nothing was drawn,
- * word 1 is the next player's draw.  Returns 1 if the game ended.          */
-static int apply_rows(orc_rows *s, int action, uint64_t seed, uint32_t tree, uint32_t iter,
-                      uint32_t depth, int *winner)
+ * word 1 is the next player's draw.  A right guess ends the turn unless
+ * cont_mode is set; then *cont = 1 and the mover, still in phase 1 with the
+ * drawn tile hidden, decides again.  Returns 1 if the game ended.          */
+static int apply_rows(orc_rows *s, int key, int cont_mode, uint64_t seed, uint32_t tree,
+                      uint32_t iter, uint32_t depth, int *winner, int *cont)
 {
     uint32_t w[4];
     philox_block(seed, depth, 0xC0000000u, iter, tree, w);
     int m = s->mover;
+    *winner = -1;
+    *cont = 0;
+    if (key == ORC_STOP_KEY) {
+        end_turn(s, m, w[1]);
+        return 0;
+    }
+    int action = key > ORC_STOP_KEY ? key - ORC_STOP_KEY - 1 : key;
     int r = action / 288 + 1, slot = (action / 12) % 24, v = action % 12;
     int q = (m + r) % s->P;
     int t = s->tile[q][slot];
     int guess = 2 * v + (t & 1);
-    if (guess == t) {
+    int right = guess == t;
+    if (right) {
         s->rev[q][slot] = 1;
     } else if (s->drawn >= 0) {
         int j = 0, o = owner_of(s, s->drawn, &j);
         s->rev[o][j] = 1;
     } else {
-        int H[24], nH = 0, Hj[24];
+        int nH = 0, Hj[24];
         for (int j = 0; j < s->n[m]; ++j)
-            if (!s->rev[m][j]) { Hj[nH] = j; H[nH++] = s->tile[m][j]; }
-        (void)H;
+            if (!s->rev[m][j]) Hj[nH++] = j;
         s->rev[m][Hj[oracle_mulshift(w[0], (uint32_t)nH)]] = 1;
     }
     if (alive_count(s) == 1) {
@@ -338,20 +370,24 @@ static int apply_rows(orc_rows *s, int action, uint64_t seed, uint32_t tree, uin
         s->drawn = -1;
         return 1;
     }
-    int nm = next_alive_after(s, m);
-    s->mover = nm;
-    s->phase = 1;
-    s->drawn = -1;
-    if (s->pile_n > 0) {
-        int k = (int)oracle_mulshift(w[1], (uint32_t)s->pile_n);
-        int d = s->pile[k];
-        for (int j = k; j + 1 < s->pile_n; ++j) s->pile[j] = s->pile[j + 1];
-        s->pile_n--;
-        row_insert(s, nm, d);
-        s->drawn = d;
+    if (right && cont_mode) {
+        *cont = 1;
+        return 0;
     }
-    *winner = -1;
+    end_turn(s, m, w[1]);
     return 0;
+}
+
+/* A leaf reached right after a right guess (continue choice on): the random
+ * policy's continue coin, word 3 of the chance block of that guess, decides
+ * once for all the leaf's playouts -- below 2^31 the mover goes on guessing
+ * in the playouts, otherwise the turn passes (word 1 draws).               */
+static void leaf_continue_coin(orc_rows *s, uint64_t seed, uint32_t tree, uint32_t iter,
+                               uint32_t depth)
+{
+    uint32_t w[4];
+    philox_block(seed, depth, 0xC0000000u, iter, tree, w);
+    if (w[3] >= 0x80000000u) end_turn(s, s->mover, w[1]);
 }
 
 int oracle_apply_action(const orc_packed *ps, int action, uint64_t seed, uint32_t tree,
@@ -365,7 +401,8 @@ int oracle_apply_action(const orc_packed *ps, int action, uint64_t seed, uint32_
     uint8_t legal[ORC_MAX_CHILD];
     legal_rows(&s, legal);
     if (!legal[action]) return -1;
-    *terminal = apply_rows(&s, action, seed, tree, iter, depth, winner);
+    int cont = 0;
+    *terminal = apply_rows(&s, action, 0, seed, tree, iter, depth, winner, &cont);
     oracle_pack(&s, out);
     return 0;
 }
@@ -379,12 +416,13 @@ float oracle_ln_entry(uint32_t k)
 /* search                                                                     */
 /* ------------------------------------------------------------------------ */
 typedef struct {
-    int action, chooser;
+    int action, chooser; /* a world node has action -1 and chooser -1 */
+    uint64_t world;      /* world node: its key (world_key)            */
     uint32_t N;
     float W;
     int nchild, cap;
     int *child;
-    uint8_t *has; /* per action id: 1 if a child with that action exists */
+    uint8_t *has; /* per tree key: 1 if a child with that key exists */
 } onode;
 
 typedef struct {
@@ -408,13 +446,13 @@ static int tree_new_node(otree *t, int action, int chooser)
 static void node_add_child(otree *t, int parent, int child)
 {
     onode *p = &t->v[parent];
-    if (!p->has) p->has = (uint8_t *)calloc(ORC_MAX_CHILD, 1);
+    if (!p->has) p->has = (uint8_t *)calloc(ORC_KEYS, 1);
     if (p->nchild == p->cap) {
         p->cap = p->cap ? 2 * p->cap : 8;
         p->child = (int *)realloc(p->child, (size_t)p->cap * sizeof(int));
     }
     p->child[p->nchild++] = child;
-    p->has[t->v[child].action] = 1;
+    if (t->v[child].action >= 0) p->has[t->v[child].action] = 1;
 }
 
 static void tree_free(otree *t)
@@ -424,6 +462,30 @@ static void tree_free(otree *t)
         free(t->v[i].has);
     }
     free(t->v);
+}
+
+/* The sampled set of opponent numbers as a 48-bit key: 2 bits per tile, the
+ * holder's seat relative to the root mover (1..3) when an opponent holds the
+ * tile hidden, else 0.  Two worlds of one root are equal iff their keys are. */
+static uint64_t world_key(const orc_rows *w, int M)
+{
+    uint64_t key = 0;
+    for (int q = 0; q < w->P; ++q) {
+        if (q == M) continue;
+        uint64_t r = (uint64_t)((q - M + w->P) % w->P);
+        for (int j = 0; j < w->n[q]; ++j)
+            if (!w->rev[q][j]) key |= r << (2 * w->tile[q][j]);
+    }
+    return key;
+}
+
+/* A tree key is playable at a state: guesses only when the mover has not
+ * just guessed right, the stop and further guesses only when it has. */
+static int key_legal(int key, int cont, const uint8_t *legal)
+{
+    if (key == ORC_STOP_KEY) return cont;
+    if (key > ORC_STOP_KEY) return cont && legal[key - ORC_STOP_KEY - 1];
+    return !cont && legal[key];
 }
 
 int rollout_rows_wins(const orc_rows *leaf, int32_t ppl, uint64_t seed, uint32_t leaf_id,
@@ -455,14 +517,16 @@ static void value_leaf(const orc_rows *S, int root_mover, const orc_mcts_params 
     }
 }
 
+/* One tree's search.  If keep is not NULL the tree is handed to the caller
+ * (who frees it) instead of being freed. */
 static int search_one(const orc_rows *root, const orc_mcts_params *mp, uint64_t seed,
                       uint32_t tr, const float *LN, int32_t *best_action,
-                      orc_child_stat *children_out)
+                      orc_child_stat *children_out, otree *keep)
 {
     otree T = {0};
     tree_new_node(&T, -1, -1);
     int ppl = mp->leaf_eval ? mp->fallback_playouts : mp->playouts_per_leaf;
-    int path[64];
+    int path[128];
     uint8_t legal[ORC_MAX_CHILD];
     for (int i = 0; i < mp->iterations; ++i) {
         orc_rows S;
@@ -470,20 +534,38 @@ static int search_one(const orc_rows *root, const orc_mcts_params *mp, uint64_t 
             tree_free(&T);
             return -3;
         }
-        int node = 0, depth = 0, np = 0, terminal = 0, winner = -1;
+        int node = 0, depth = 0, np = 0, terminal = 0, winner = -1, cont = 0, last_block = -1;
         path[np++] = 0;
+        if (mp->vanilla) {
+            /* the world node of this sample: found among the root's children
+               by its key, or appended */
+            uint64_t key = world_key(&S, root->mover);
+            int found = -1;
+            for (int k = 0; k < T.v[0].nchild; ++k)
+                if (T.v[T.v[0].child[k]].world == key) { found = T.v[0].child[k]; break; }
+            if (found < 0) {
+                found = tree_new_node(&T, -1, -1);
+                T.v[found].world = key;
+                node_add_child(&T, 0, found);
+            }
+            node = found;
+            path[np++] = node;
+        }
         for (;;) {
             if (terminal) break;
-            if (depth >= mp->max_depth) break;
+            if (mp->max_depth > 0 && depth >= mp->max_depth) break;
             legal_rows(&S, legal);
             onode *X = &T.v[node];
+            /* expansion: the lowest playable key without a child */
             int expand = -1;
-            for (int a = 0; a < ORC_MAX_CHILD; ++a)
-                if (legal[a] && !(X->has && X->has[a])) { expand = a; break; }
+            for (int k = 0; k < ORC_KEYS; ++k)
+                if (key_legal(k, cont, legal) && !(X->has && X->has[k])) { expand = k; break; }
             if (expand >= 0) {
                 int c = tree_new_node(&T, expand, S.mover);
                 node_add_child(&T, node, c);
-                terminal = apply_rows(&S, expand, seed, tr, (uint32_t)i, (uint32_t)depth, &winner);
+                terminal = apply_rows(&S, expand, mp->continue_choice, seed, tr, (uint32_t)i,
+                                      (uint32_t)depth, &winner, &cont);
+                last_block = depth;
                 path[np++] = c;
                 break;
             }
@@ -495,7 +577,7 @@ static int search_one(const orc_rows *root, const orc_mcts_params *mp, uint64_t 
             float best_s = 0.0f;
             for (int k = 0; k < X->nchild; ++k) {
                 onode *c = &T.v[X->child[k]];
-                if (!legal[c->action]) continue;
+                if (!key_legal(c->action, cont, legal)) continue;
                 float n = (float)c->N;
                 float q = c->W / n;
                 float e = Lp / n;
@@ -503,11 +585,15 @@ static int search_one(const orc_rows *root, const orc_mcts_params *mp, uint64_t 
                 float s = q + u;
                 if (best < 0 || s > best_s) { best = X->child[k]; best_s = s; }
             }
-            terminal = apply_rows(&S, T.v[best].action, seed, tr, (uint32_t)i, (uint32_t)depth, &winner);
+            terminal = apply_rows(&S, T.v[best].action, mp->continue_choice, seed, tr, (uint32_t)i,
+                                  (uint32_t)depth, &winner, &cont);
+            last_block = depth;
             node = best;
             path[np++] = best;
             ++depth;
         }
+        if (!terminal && cont)
+            leaf_continue_coin(&S, seed, tr, (uint32_t)i, (uint32_t)last_block);
         float vals[4] = {0.0f, 0.0f, 0.0f, 0.0f};
         if (terminal) {
             vals[winner] = (float)ppl;
@@ -521,10 +607,39 @@ static int search_one(const orc_rows *root, const orc_mcts_params *mp, uint64_t 
         for (int k = 0; k < np; ++k) {
             onode *x = &T.v[path[k]];
             x->N += (uint32_t)ppl;
-            if (k > 0) x->W += vals[x->chooser];
+            if (k > 0 && x->chooser >= 0) x->W += vals[x->chooser];
         }
     }
     onode *R = &T.v[0];
+    if (mp->vanilla) {
+        /* a guess is judged over all worlds: its statistics are summed over
+           the world nodes in creation order; most visits wins, the lowest
+           action id on ties; children_out is indexed by action id */
+        uint32_t n[ORC_MAX_CHILD];
+        float w[ORC_MAX_CHILD];
+        for (int a = 0; a < ORC_MAX_CHILD; ++a) { n[a] = 0; w[a] = 0.0f; }
+        for (int k = 0; k < R->nchild; ++k) {
+            onode *x = &T.v[R->child[k]];
+            for (int j = 0; j < x->nchild; ++j) {
+                onode *c = &T.v[x->child[j]];
+                n[c->action] += c->N;
+                w[c->action] += c->W;
+            }
+        }
+        int best = -1;
+        for (int a = 0; a < ORC_MAX_CHILD; ++a)
+            if (n[a] > 0 && (best < 0 || n[a] > n[best])) best = a;
+        *best_action = best;
+        if (children_out)
+            for (int a = 0; a < ORC_MAX_CHILD; ++a) {
+                children_out[a].action = n[a] > 0 ? (uint16_t)a : 0xFFFF;
+                children_out[a].pad = 0;
+                children_out[a].n = n[a];
+                children_out[a].w = w[a];
+            }
+        if (keep) *keep = T; else tree_free(&T);
+        return 0;
+    }
     int best = -1;
     uint32_t bestN = 0;
     for (int k = 0; k < R->nchild; ++k) {
@@ -546,16 +661,28 @@ static int search_one(const orc_rows *root, const orc_mcts_params *mp, uint64_t 
             children_out[k].w = c->W;
         }
     }
-    tree_free(&T);
+    if (keep) *keep = T; else tree_free(&T);
     return 0;
+}
+
+static float *ln_table(const orc_mcts_params *mp)
+{
+    uint64_t w_leaf = (uint64_t)(mp->leaf_eval ? mp->fallback_playouts : mp->playouts_per_leaf);
+    uint64_t nln = (uint64_t)mp->iterations * w_leaf + 1;
+    float *LN = (float *)malloc(nln * sizeof(float));
+    LN[0] = 0.0f;
+    for (uint64_t k = 1; k < nln; ++k) LN[k] = oracle_ln_entry((uint32_t)k);
+    return LN;
 }
 
 int oracle_mcts_search(const orc_packed *roots, int64_t n_trees, const orc_mcts_params *mp,
                        uint64_t seed, uint32_t tree_id_base, int32_t *best_action,
                        orc_child_stat *root_children)
 {
-    if (n_trees < 0 || mp->iterations < 1 || mp->playouts_per_leaf < 1 || mp->max_depth < 1 ||
-        mp->max_depth > 32 || mp->leaf_eval < 0 || mp->leaf_eval > 1)
+    if (n_trees < 0 || mp->iterations < 1 || mp->playouts_per_leaf < 1 || mp->max_depth < 0 ||
+        mp->max_depth > 64 || mp->leaf_eval < 0 || mp->leaf_eval > 1 ||
+        (mp->continue_choice != 0 && mp->continue_choice != 1) ||
+        (mp->vanilla != 0 && mp->vanilla != 1))
         return -1;
     if (mp->leaf_eval && (mp->valuenet == NULL || mp->fallback_playouts < 1)) return -1;
     for (int64_t t = 0; t < n_trees; ++t) {
@@ -565,20 +692,63 @@ int oracle_mcts_search(const orc_packed *roots, int64_t n_trees, const orc_mcts_
         if (alive_count(&r) < 2) return -2;
         if (r.phase == 0 && r.pile_n > 0) return -2;
     }
-    uint64_t w_leaf = (uint64_t)(mp->leaf_eval ? mp->fallback_playouts : mp->playouts_per_leaf);
-    uint64_t nln = (uint64_t)mp->iterations * w_leaf + 1;
-    float *LN = (float *)malloc(nln * sizeof(float));
-    LN[0] = 0.0f;
-    for (uint64_t k = 1; k < nln; ++k) LN[k] = oracle_ln_entry((uint32_t)k);
+    float *LN = ln_table(mp);
     int rc = 0;
     for (int64_t t = 0; t < n_trees && rc == 0; ++t) {
         orc_rows r;
         oracle_unpack(&roots[t], &r);
         rc = search_one(&r, mp, seed, tree_id_base + (uint32_t)t, LN, &best_action[t],
-                        root_children ? root_children + t * ORC_MAX_CHILD : NULL);
+                        root_children ? root_children + t * ORC_MAX_CHILD : NULL, NULL);
     }
     free(LN);
     return rc;
+}
+
+/* The whole tree of one search (tree id tree_id), nodes in creation order:
+ * parent (-1 for the root), key (-1 for the root and world nodes), chooser,
+ * depth in guesses and stops (world nodes share the root's 0), N, W, world
+ * key.  Writes at most cap nodes; returns the node count, or a negative
+ * error as oracle_mcts_search. */
+int oracle_mcts_tree_dump(const orc_packed *root, const orc_mcts_params *mp, uint64_t seed,
+                          uint32_t tree_id, int32_t *best_action, orc_tree_node *out, int64_t cap)
+{
+    int32_t b;
+    int rc = oracle_mcts_search(root, 0, mp, seed, tree_id, &b, NULL);   /* parameter checks */
+    if (rc) return rc;
+    if (oracle_validate(root)) return -2;
+    orc_rows r;
+    oracle_unpack(root, &r);
+    if (alive_count(&r) < 2 || (r.phase == 0 && r.pile_n > 0)) return -2;
+    float *LN = ln_table(mp);
+    otree T = {0};
+    rc = search_one(&r, mp, seed, tree_id, LN, best_action, NULL, &T);
+    free(LN);
+    if (rc) return rc;
+    int32_t *parent = (int32_t *)malloc(sizeof(int32_t) * (size_t)T.n);
+    int32_t *depth = (int32_t *)malloc(sizeof(int32_t) * (size_t)T.n);
+    parent[0] = -1;
+    depth[0] = 0;
+    /* children are always created after their parent */
+    for (int x = 0; x < T.n; ++x)
+        for (int k = 0; k < T.v[x].nchild; ++k) {
+            int c = T.v[x].child[k];
+            parent[c] = x;
+            depth[c] = depth[x] + (T.v[c].action >= 0);
+        }
+    for (int x = 0; x < T.n && x < cap; ++x) {
+        out[x].parent = parent[x];
+        out[x].key = T.v[x].action;
+        out[x].chooser = T.v[x].chooser;
+        out[x].depth = depth[x];
+        out[x].n = T.v[x].N;
+        out[x].w = T.v[x].W;
+        out[x].world = T.v[x].world;
+    }
+    int n = T.n;
+    free(parent);
+    free(depth);
+    tree_free(&T);
+    return n;
 }
 
 /* Root-parallel search (Sec. III-B): each root is searched by K independent
@@ -592,7 +762,7 @@ int oracle_mcts_search_merged(const orc_packed *roots, int64_t n_roots, int32_t 
                               const orc_mcts_params *mp, uint64_t seed, uint32_t tree_id_base,
                               int32_t *best_action, orc_child_stat *merged)
 {
-    if (n_roots < 0 || trees_per_root < 1) return -1;
+    if (n_roots < 0 || trees_per_root < 1 || mp->vanilla) return -1;
     orc_packed *copies = (orc_packed *)malloc(sizeof(orc_packed) * (size_t)(trees_per_root > 0 ? trees_per_root : 1));
     int32_t *best_k = (int32_t *)malloc(sizeof(int32_t) * (size_t)trees_per_root);
     orc_child_stat *kids = (orc_child_stat *)malloc(sizeof(orc_child_stat) * ORC_MAX_CHILD * (size_t)trees_per_root);

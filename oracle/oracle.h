@@ -59,6 +59,8 @@ typedef struct {
     float fallback_band;
     int32_t fallback_playouts;
     const void *valuenet;
+    int32_t continue_choice; /* 1: after a right guess the mover may stop or guess again */
+    int32_t vanilla;         /* 1: the root's children are the sampled worlds            */
 } orc_mcts_params;
 
 typedef struct { uint16_t action; uint16_t pad; uint32_t n; float w; } orc_child_stat;
@@ -75,6 +77,9 @@ typedef struct {
 } orc_rows;
 
 #define ORC_MAX_CHILD 864
+/* tree keys: guesses 0..863, stop 864, a guess after a right guess 865 + a */
+#define ORC_STOP_KEY 864
+#define ORC_KEYS (2 * ORC_MAX_CHILD + 1)
 
 /* Philox4x32-10 block (Salmon, Moraes, Dror, Shaw, SC'11). */
 void oracle_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
@@ -126,6 +131,17 @@ float oracle_ln_entry(uint32_t k);
 int oracle_mcts_search(const orc_packed *roots, int64_t n_trees, const orc_mcts_params *mp,
                        uint64_t seed, uint32_t tree_id_base, int32_t *best_action,
                        orc_child_stat *root_children);
+
+/* one node of a searched tree (oracle_mcts_tree_dump) */
+typedef struct {
+    int32_t parent, key, chooser, depth;
+    uint32_t n;
+    float w;
+    uint64_t world;
+} orc_tree_node;
+
+int oracle_mcts_tree_dump(const orc_packed *root, const orc_mcts_params *mp, uint64_t seed,
+                          uint32_t tree_id, int32_t *best_action, orc_tree_node *out, int64_t cap);
 
 /* root-parallel search: K trees per root, root statistics summed by action id */
 int oracle_mcts_search_merged(const orc_packed *roots, int64_t n_roots, int32_t trees_per_root,
