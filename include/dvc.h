@@ -195,19 +195,42 @@ int dvc_rollout_autotune(const dvc_state_t *leaves, int64_t n_leaves, int32_t pl
  * playouts instead.  Every leaf then weighs w = fallback_playouts: N += w and
  * W += wins of the chooser (playouts) or w * v_chooser (network).
  * Decision: the root child with the most visits, earliest created on ties.
+ *
+ * The paper's three simplifications (Sec. III-A) can each be switched off:
+ *   max_depth 0 -- no depth threshold: nodes expand until the game ends;
+ *   continue_choice 1 -- a right guess no longer ends the turn: the same
+ *      player then chooses between stopping (tree key 864: the turn passes
+ *      and the next player draws, word 1) and another guess (key 865 +
+ *      action id), so a player's further guesses are nodes of their own.
+ *      Expansion takes the lowest key, so the stop comes first.  A leaf
+ *      reached right after a right guess draws the random policy's continue
+ *      coin once for all its playouts: word 3 of that guess's chance block,
+ *      below 2^31 the mover keeps guessing, else the turn passes (word 1);
+ *   vanilla 1 -- each sampled world is a node of its own (Sec. III-A): the
+ *      root's children are world nodes, one per distinct set of hidden
+ *      opponent tiles in the order first sampled, and every iteration
+ *      descends below the node of its world (UCT there uses that node's
+ *      visit count).  A guess's root statistics are its (N, W) summed over
+ *      the world nodes in creation order; the decision is the most visited
+ *      guess, the lowest action id on ties, and root_children is indexed by
+ *      action id (action 0xFFFF where no world has the guess).  Not
+ *      available to mcts_search_root_parallel.
  * ------------------------------------------------------------------------- */
 typedef struct {
     int32_t iterations;         /* per tree, >= 1                                   */
     int32_t playouts_per_leaf;  /* >= 1                                             */
-    int32_t max_depth;          /* expansion depth threshold, 1..16                 */
+    int32_t max_depth;          /* expansion depth threshold, 1..64; 0: none        */
     float c_uct;                /* exploration constant (sqrt 2 rounded to float)   */
     int32_t leaf_eval;          /* 0: playouts; 1: value network with fallback      */
     float fallback_band;        /* value mode: playouts when |v - 0.5| < band       */
     int32_t fallback_playouts;  /* value mode: playouts of a fallback leaf          */
     const void *valuenet;       /* value mode: dvc_valuenet blob (device, 16-aligned) */
+    int32_t continue_choice;    /* 1: stop-or-guess choice after a right guess      */
+    int32_t vanilla;            /* 1: sampled worlds are the root's children        */
 } dvc_mcts_params;
 
-/* one root child, in creation order; action 0xFFFF marks unused entries */
+/* one root child, in creation order (vanilla: indexed by action id); action
+ * 0xFFFF marks unused entries */
 typedef struct { uint16_t action; uint16_t pad; uint32_t n; float w; } dvc_child_stat;
 
 #define DVC_MAX_ACTIONS 864

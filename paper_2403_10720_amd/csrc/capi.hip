@@ -89,7 +89,9 @@ static const float *ln_table(uint64_t need, int *status)
 static bool mcts_params_ok(const dvc_mcts_params *p)
 {
     if (p == nullptr) return false;
-    if (p->iterations < 1 || p->playouts_per_leaf < 1 || p->max_depth < 1 || p->max_depth > 16)
+    if (p->iterations < 1 || p->playouts_per_leaf < 1 || p->max_depth < 0 || p->max_depth > 64)
+        return false;
+    if ((p->continue_choice != 0 && p->continue_choice != 1) || (p->vanilla != 0 && p->vanilla != 1))
         return false;
     if (!(p->c_uct >= 0.0f) || std::isinf(p->c_uct)) return false;
     if (p->leaf_eval != 0 && p->leaf_eval != 1) return false;
@@ -329,7 +331,9 @@ int dvc_rollout(const dvc_state_t *leaves, int64_t n_leaves, int32_t ppl, uint64
 size_t dvc_mcts_workspace_bytes(int64_t n_trees, const dvc_mcts_params *params)
 {
     if (n_trees < 0 || !mcts_params_ok(params)) return 0;
-    return (size_t)n_trees * mcts_tree_words((uint32_t)params->iterations) * sizeof(uint32_t);
+    const MctsShape sh = mcts_shape((uint32_t)params->iterations, (uint32_t)params->continue_choice,
+                                    (uint32_t)params->vanilla);
+    return (size_t)n_trees * sh.tree_words * sizeof(uint32_t);
 }
 
 // merge = false: one tree per root, statistics in creation order;
@@ -341,6 +345,7 @@ static int run_search(const dvc_state_t *roots, int64_t n_roots, int64_t trees_p
 {
     if (n_roots < 0 || trees_per_root < 1 || trees_per_root > 65536 || !mcts_params_ok(params))
         return DVC_EINVAL;
+    if (merge && params->vanilla) return DVC_EINVAL;   // world nodes are not merged
     const int64_t n_trees = n_roots * trees_per_root;
     if (n_trees >= (1ll << 31)) return DVC_EINVAL;
     if (n_roots == 0) return DVC_OK;
@@ -362,11 +367,13 @@ static int run_search(const dvc_state_t *roots, int64_t n_roots, int64_t trees_p
                                merge ? nullptr : reinterpret_cast<uint32_t *>(children),
                                (uint32_t)params->leaf_eval, params->fallback_band,
                                (uint32_t)params->fallback_playouts, params->valuenet,
+                               (uint32_t)params->continue_choice, (uint32_t)params->vanilla,
                                (hipStream_t)stream);
     if (e != hipSuccess || !merge) return status_of(e);
     return status_of(launch_mcts_merge(reinterpret_cast<const uint32_t *>(workspace),
                                        (uint32_t)n_roots, (uint32_t)trees_per_root,
-                                       (uint32_t)params->iterations, best_action,
+                                       (uint32_t)params->iterations,
+                                       (uint32_t)params->continue_choice, best_action,
                                        reinterpret_cast<uint32_t *>(children),
                                        (hipStream_t)stream));
 }

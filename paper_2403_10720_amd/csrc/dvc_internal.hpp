@@ -48,14 +48,21 @@ struct DealArgs {
 int default_rollout_grid(int waves_per_block);
 hipError_t launch_rollout(const RolloutArgs &a, int variant, int block, int grid, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st);
-size_t mcts_tree_words(uint32_t iters);
+// one tree's workspace: node records with their first child blocks,
+// overflow blocks, the block chain, and (vanilla) per-action sums
+struct MctsShape {
+    uint32_t node_words, node_stride, nodes_cap, ovf_cap;
+    uint64_t agg_off, tree_words;
+};
+MctsShape mcts_shape(uint32_t iters, uint32_t cont, uint32_t vanilla);
 hipError_t launch_mcts(const uint4 *roots, uint32_t n_trees, uint32_t trees_per_root,
                        uint32_t iters, uint32_t ppl, uint32_t dmax, float c_uct, uint32_t k0, uint32_t k1, uint32_t tree_base,
                        const float *ln, uint32_t *ws, int32_t *best, uint32_t *kids,
                        uint32_t leaf_eval, float band, uint32_t fb_ppl, const void *net,
-                       hipStream_t st);
+                       uint32_t cont, uint32_t vanilla, hipStream_t st);
 hipError_t launch_mcts_merge(const uint32_t *ws, uint32_t n_roots, uint32_t trees_per_root,
-                             uint32_t iters, int32_t *best, uint32_t *merged, hipStream_t st);
+                             uint32_t iters, uint32_t cont, int32_t *best, uint32_t *merged,
+                             hipStream_t st);
 hipError_t launch_valu_probe(int op, uint32_t blocks, uint32_t iters, uint32_t *sink,
                              hipStream_t st);
 size_t vn_bytes();

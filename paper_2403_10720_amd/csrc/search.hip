@@ -21,23 +21,34 @@
 // nodes, child blocks, root visits, leaves scored by the network, leaves
 // played out in value mode, iterations that used the sampler's fallback.
 // Tree storage lives in the caller's workspace: per node a record (last
-// child block, child count, a bitmap of the actions that already have a
-// child) followed by its first block of 64 child entries {action | chooser
-// << 16, N, W, node id}; nodes with more than 64 children chain overflow
-// blocks.  A node's record and first 64 children arrive in one round of
-// loads, and its children are scored 64 at a time.
+// child block, child count, bitmaps of the keys that already have a child)
+// followed by its first block of 64 child entries {key | chooser << 16, N,
+// W, node id}; nodes with more than 64 children chain overflow blocks.  A
+// node's record and first 64 children arrive in one round of loads, and its
+// children are scored 64 at a time.
+//
+// Each of the paper's three simplifications can be switched off:
+//   * continue choice: after a right guess the same player chooses between
+//     stopping (key 864) and another guess (key 865 + action), so records
+//     carry a second bitmap and a stop flag;
+//   * no depth threshold (max_depth 0);
+//   * vanilla: the root's children are world nodes, one per distinct sampled
+//     set of opponent numbers; their entries hold the 48-bit world key in
+//     the key and W words, and the guesses hang below them.
 #include "dvc_core.hpp"
 #include "dvc_internal.hpp"
 
 namespace dvc {
 
-constexpr uint32_t kNodeWords = 40;      // pad, last block, nchild, pad, 36 bitmap words
+// record: pad, last block, child count, stop flag, 36 bitmap words of plain
+// guesses (72 (target, slot) pairs x 16 bits), with the continue choice 36
+// more for the guesses after a right guess, padded to 16 bytes
+constexpr uint32_t kNodeWordsPlain = 40;
+constexpr uint32_t kNodeWordsCont = 80;
 constexpr uint32_t kBlockEntries = 64;
 constexpr uint32_t kEntryWords = 4;
 constexpr uint32_t kBlockWords = kBlockEntries * kEntryWords;
-// a node's record is followed by its first child block, so one round of
-// loads fetches both
-constexpr uint32_t kNodeStride = kNodeWords + kBlockWords;
+constexpr uint32_t kStopKey = kMaxActions;   // 864; a guess after a right guess is 865 + action
 // tree header: nodes, overflow blocks, root visits, network leaves, played
 // leaves, sampler fallbacks, failed flag; from word 8, four 64-bit sums of
 // shader clock cycles spent sampling worlds, descending, evaluating leaves
@@ -48,7 +59,27 @@ constexpr uint32_t kTreeHeaderWords = 16;
 constexpr uint32_t kNoBlock = 0xFFFFFFFFu;
 constexpr uint32_t kDetAttempts = 64;
 constexpr uint32_t kDfsMaxCalls = 1u << 22;
-constexpr uint32_t kMaxDepthLimit = 16;
+// path entries of one iteration: a game has at most 23 guesses (each reveals
+// a tile and the winner keeps one), stops only follow right guesses, and a
+// world node adds one: at most 47
+constexpr uint32_t kMaxPath = 64;
+
+MctsShape mcts_shape(uint32_t iters, uint32_t cont, uint32_t vanilla)
+{
+    MctsShape sh;
+    sh.node_words = cont ? kNodeWordsCont : kNodeWordsPlain;
+    sh.node_stride = sh.node_words + kBlockWords;
+    // one node per iteration, two with world nodes
+    sh.nodes_cap = (vanilla ? 2u * iters : iters) + 1u;
+    sh.ovf_cap = sh.nodes_cap / kBlockEntries + 2u;
+    uint64_t words = kTreeHeaderWords + (uint64_t)sh.nodes_cap * sh.node_stride +
+                     (uint64_t)sh.ovf_cap * kBlockWords + sh.nodes_cap + sh.ovf_cap;
+    words = (words + 3u) & ~(uint64_t)3u;
+    sh.agg_off = words;                     // vanilla: per-action (N, W) over the worlds
+    if (vanilla) words += 2u * kMaxActions;
+    sh.tree_words = (words + 3u) & ~(uint64_t)3u;   // keep every tree 16-byte aligned
+    return sh;
+}
 
 __device__ __forceinline__ void set_hand(State &s, uint32_t q, uint32_t v)
 {
@@ -236,39 +267,95 @@ __device__ __forceinline__ uint32_t legal_values(const State &S, uint32_t k, con
     return x & 0xFFFu;
 }
 
-// Play a guess inside the tree (the turn ends after it); chance words come
-// from block (depth, 0xC0000000, iter, tree).  Returns true if the game ended.
-__device__ __forceinline__ bool apply_action(State &S, uint32_t action, uint32_t depth,
+// The turn passes: the next seat with hidden tiles becomes the mover and
+// draws with word w1 (if the pool is not empty).
+__device__ __forceinline__ void end_turn(State &S, uint32_t alive, uint32_t w1, const uint8_t *tab)
+{
+    S.m = next_alive(alive, S.m, S.P);
+    S.phase = 1u;
+    S.drawn = -1;
+    const uint32_t pool = ~(S.h0 | S.h1 | S.h2 | S.h3) & kAll;
+    if (pool) {
+        const uint32_t d = pick_bit_tab(pool, w1, tab);
+        add_to_hand(S, S.m, 1u << d);
+        S.drawn = (int32_t)d;
+    }
+}
+
+// Play tree key `key` -- a guess, the stop (kStopKey), or a guess after a
+// right guess (kStopKey + 1 + action) -- with chance words from block (depth,
+// 0xC0000000, iter, tree): w0 picks the mover's own tile to reveal after a
+// wrong guess with nothing drawn, w1 the next player's draw.  A right guess
+// ends the turn unless cont_mode is set; then `cont` is set and the mover,
+// still holding the drawn tile hidden, decides again.  Returns true if the
+// game ended.
+__device__ __forceinline__ bool apply_action(State &S, uint32_t key, bool cont_mode, uint32_t depth,
                                              uint32_t iter, uint32_t tr, uint32_t k0, uint32_t k1,
-                                             uint32_t &winner, const uint8_t *tab)
+                                             uint32_t &winner, bool &cont, const uint8_t *tab)
 {
     const Words w = philox(depth, 0xC0000000u, iter, tr, k0, k1);
+    cont = false;
+    if (key == kStopKey) {
+        end_turn(S, alive_mask(S), w.w1, tab);
+        return false;
+    }
+    const uint32_t action = key > kStopKey ? key - kStopKey - 1u : key;
     const uint32_t r = action / 288u + 1u;
     const uint32_t slot = (action / 12u) % 24u;
     const uint32_t v = action % 12u;
     const uint32_t q = S.m + r >= S.P ? S.m + r - S.P : S.m + r;
     const uint32_t row = hand_of(S, q);
     const uint32_t t = kth_bit_tab(row, slot, tab);
-    const uint32_t guess = 2u * v + (t & 1u);
+    const bool right = 2u * v + (t & 1u) == t;
     const uint32_t hm = hand_of(S, S.m);
     const uint32_t own = pick_bit_tab(hm & ~S.rev, w.w0, tab);
     const uint32_t wrong_bit = 1u << (S.drawn >= 0 ? (uint32_t)S.drawn : own);
-    S.rev |= guess == t ? (1u << t) : wrong_bit;
+    S.rev |= right ? (1u << t) : wrong_bit;
     const uint32_t alive = alive_mask(S);
-    S.phase = 1u;
-    S.drawn = -1;
     if (__popc(alive) == 1) {
+        S.phase = 1u;
+        S.drawn = -1;
         winner = (uint32_t)__builtin_ctz(alive);
         return true;
     }
-    S.m = next_alive(alive, S.m, S.P);
-    const uint32_t pool = ~(S.h0 | S.h1 | S.h2 | S.h3) & kAll;
-    if (pool) {
-        const uint32_t d = pick_bit_tab(pool, w.w1, tab);
-        add_to_hand(S, S.m, 1u << d);
-        S.drawn = (int32_t)d;
+    if (right && cont_mode) {
+        cont = true;
+        return false;
     }
+    end_turn(S, alive, w.w1, tab);
     return false;
+}
+
+// A leaf reached right after a right guess (continue choice): the random
+// policy's continue coin, w3 of that guess's chance block, decides once for
+// all the leaf's playouts -- below 2^31 the mover goes on guessing, else the
+// turn passes (w1 draws).
+__device__ __forceinline__ void leaf_continue_coin(State &S, uint32_t depth, uint32_t iter,
+                                                   uint32_t tr, uint32_t k0, uint32_t k1,
+                                                   const uint8_t *tab)
+{
+    const Words w = philox(depth, 0xC0000000u, iter, tr, k0, k1);
+    if (w.w3 >= 0x80000000u) end_turn(S, alive_mask(S), w.w1, tab);
+}
+
+// The sampled world as a 48-bit key (lo: tiles 0-15, hi: tiles 16-23), 2 bits
+// per tile: the seat relative to the root mover m of the opponent holding the
+// tile hidden, else 0.
+__device__ __forceinline__ void world_key(const State &S, uint32_t m, uint32_t &lo, uint32_t &hi)
+{
+    uint64_t key = 0u;
+    for (uint32_t k = 1; k < 4u; ++k) {
+        if (k >= S.P) break;
+        const uint32_t o = m + k >= S.P ? m + k - S.P : m + k;
+        uint32_t x = hand_of(S, o) & ~S.rev;
+        while (x) {
+            const uint32_t t = (uint32_t)__builtin_ctz(x);
+            x &= x - 1u;
+            key |= (uint64_t)k << (2u * t);
+        }
+    }
+    lo = (uint32_t)key;
+    hi = (uint32_t)(key >> 32);
 }
 
 __device__ __forceinline__ State readlane_state(const State &s, uint32_t lane)
@@ -318,8 +405,8 @@ struct MctsArgs {
     uint32_t k0, k1, tree_base;
     const float *ln;
     uint32_t *ws;
-    uint64_t tree_words;
-    uint32_t nodes_cap, ovf_cap;
+    MctsShape sh;
+    uint32_t cont_mode, vanilla;   // simplifications 2 and 1 switched off
     int32_t *best;    // [n_trees] or null
     uint32_t *kids;   // [n_trees][864][3] or null
     // value mode: leaves are scored by the network; a leaf whose value for
@@ -370,8 +457,8 @@ mcts_tree_kernel(MctsArgs a)
 {
     constexpr uint32_t TG = TreeGroup<VALUE>::kTrees;
     __shared__ uint8_t tab[kKthTableBytes];
-    __shared__ uint32_t legal_all[TG][72];
-    __shared__ uint32_t path_all[TG][kMaxDepthLimit + 1];
+    __shared__ uint32_t legal_all[TG][73];
+    __shared__ uint32_t path_all[TG][kMaxPath];
     __shared__ DfsSlots dfs_all[TG];
     __shared__ __attribute__((aligned(16))) uint16_t tile_all[TG][4][kVnH + 8];
     __shared__ __attribute__((aligned(16))) uint16_t w2_lds[VALUE ? kVnH * kVnH : 8];
@@ -394,16 +481,18 @@ mcts_tree_kernel(MctsArgs a)
     DfsSlots &dfs_slots = dfs_all[wv];
     uint16_t (*vn_tile)[kVnH + 8] = tile_all[wv];
     const uint32_t tr = a.tree_base + t;
-    uint32_t *W = a.ws + (uint64_t)t * a.tree_words;
-    const uint32_t ovf_base = kTreeHeaderWords + a.nodes_cap * kNodeStride;
-    uint32_t *bnext = W + ovf_base + a.ovf_cap * kBlockWords;
+    uint32_t *W = a.ws + (uint64_t)t * a.sh.tree_words;
+    const uint32_t nodes_cap = a.sh.nodes_cap, node_words = a.sh.node_words;
+    const uint32_t node_stride = a.sh.node_stride;
+    const uint32_t ovf_base = kTreeHeaderWords + nodes_cap * node_stride;
+    uint32_t *bnext = W + ovf_base + a.sh.ovf_cap * kBlockWords;
     // word offset (from W) of child block b: blocks below nodes_cap are the
     // nodes' inline blocks, the rest overflow blocks
     auto block_off = [&](uint32_t b) -> uint32_t {
-        return b < a.nodes_cap ? kTreeHeaderWords + b * kNodeStride + kNodeWords
-                               : ovf_base + (b - a.nodes_cap) * kBlockWords;
+        return b < nodes_cap ? kTreeHeaderWords + b * node_stride + node_words
+                             : ovf_base + (b - nodes_cap) * kBlockWords;
     };
-    auto rec_off = [&](uint32_t nd) -> uint32_t { return kTreeHeaderWords + nd * kNodeStride; };
+    auto rec_off = [&](uint32_t nd) -> uint32_t { return kTreeHeaderWords + nd * node_stride; };
 
     const uint4 rs = a.roots[t / a.trees_per_root];
     State R;
@@ -418,7 +507,7 @@ mcts_tree_kernel(MctsArgs a)
         write_no_children(a, t, lane);
         return;
     }
-    if (lane < kNodeWords) W[rec_off(0u) + lane] = 0u;
+    for (uint32_t k = lane; k < node_words; k += 64u) W[rec_off(0u) + k] = 0u;
     if (lane == 0) bnext[0] = kNoBlock;
     uint32_t n_nodes = 1u, n_ovf = 0u, n_root = 0u;
     uint32_t n_net = 0u, n_played = 0u, n_sampler_fallback = 0u;   // statistics
@@ -457,70 +546,123 @@ mcts_tree_kernel(MctsArgs a)
         const uint64_t t1 = clock64();
         cyc[0] += t1 - t0;
         // ---- 2. descend ----------------------------------------------------
-        uint32_t node = 0u, node_n = n_root, depth = 0u, np = 0u, winner = 0u;
-        bool term = false;
+        // Append a child {ex | ..., 0, ez, id} to `parent` (child count nc);
+        // returns its id and its entry's word offset.
+        auto append_child = [&](uint32_t parent, uint32_t nc, uint32_t ex, uint32_t ez,
+                                uint32_t &e_out) -> uint32_t {
+            const uint32_t rec = rec_off(parent);
+            const uint32_t c = n_nodes++;
+            uint32_t blk = parent;
+            if (nc >= kBlockEntries) {
+                blk = W[rec + 1u];
+                if ((nc & (kBlockEntries - 1u)) == 0u) {
+                    const uint32_t ob = nodes_cap + n_ovf++;
+                    if (lane == 0) {
+                        bnext[ob] = kNoBlock;
+                        bnext[blk] = ob;
+                        W[rec + 1u] = ob;
+                    }
+                    blk = ob;
+                }
+            }
+            const uint32_t e = block_off(blk) + (nc & (kBlockEntries - 1u)) * kEntryWords;
+            if (lane == 0) {
+                W[e + 0u] = ex;
+                W[e + 1u] = 0u;
+                W[e + 2u] = ez;
+                W[e + 3u] = c;
+                W[rec + 2u] = nc + 1u;
+                bnext[c] = kNoBlock;
+            }
+            for (uint32_t k = lane; k < node_words; k += 64u) W[rec_off(c) + k] = k == 1u ? c : 0u;
+            e_out = e;
+            return c;
+        };
+        uint32_t node = 0u, node_n = n_root, depth = 0u, np = 0u, winner = 0u, last_block = 0u;
+        bool term = false, cont = false;
+        if (a.vanilla) {
+            // the world node of this sample among the root's children, by key
+            uint32_t klo, khi;
+            world_key(S, R.m, klo, khi);
+            const uint32_t nr = W[rec_off(0u) + 2u];
+            uint32_t blk = 0u, found_e = 0u;
+            bool found = false;
+            for (uint32_t base = 0; base < nr; base += kBlockEntries) {
+                const uint32_t eo = block_off(blk) + lane * kEntryWords;
+                const uint4 ent = *reinterpret_cast<const uint4 *>(W + eo);
+                const uint64_t hit = __ballot(base + lane < nr && ent.x == klo && ent.z == khi);
+                if (hit) {
+                    const uint32_t l = (uint32_t)__builtin_ctzll(hit);
+                    node = __builtin_amdgcn_readlane(ent.w, l);
+                    node_n = __builtin_amdgcn_readlane(ent.y, l);
+                    found_e = block_off(blk) + l * kEntryWords;
+                    found = true;
+                    break;
+                }
+                if (base + kBlockEntries < nr) blk = bnext[blk];
+            }
+            if (!found) {
+                node = append_child(0u, nr, klo, khi, found_e);
+                node_n = 0u;
+            }
+            path_e[np++] = found_e;
+            tree_sync<VALUE>();
+        }
         for (;;) {
-            if (term || depth >= a.dmax) break;
-            // one round of loads: bitmap, child count, first 64 children, LN
+            if (term || depth >= a.dmax || np >= kMaxPath - 1u) break;
+            // one round of loads: bitmaps, child count, first 64 children, LN
             const uint32_t rec = rec_off(node);
-            const uint32_t cbw0 = W[rec + 4u + (lane >> 1)];
-            const uint32_t cbw1 = lane < 8u ? W[rec + 36u + (lane >> 1)] : 0u;
+            const uint32_t half = cont ? 36u : 0u;
+            const uint32_t cbw0 = W[rec + 4u + half + (lane >> 1)];
+            const uint32_t cbw1 = lane < 8u ? W[rec + 36u + half + (lane >> 1)]
+                                            : lane == 8u ? W[rec + 3u] : 0u;
             const uint32_t nchild = W[rec + 2u];
-            const uint4 ent0 = *reinterpret_cast<const uint4 *>(W + rec + kNodeWords + lane * kEntryWords);
+            const uint4 ent0 = *reinterpret_cast<const uint4 *>(W + rec + node_words + lane * kEntryWords);
             const float lp = a.ln[node_n];
             const uint32_t l0 = legal_values(S, lane, tab);
-            const uint32_t l1 = lane < 8u ? legal_values(S, 64u + lane, tab) : 0u;
+            const uint32_t l1 = lane < 8u ? legal_values(S, 64u + lane, tab)
+                                          : (lane == 8u && cont) ? 1u : 0u;
             legal_s[lane] = l0;
-            if (lane < 8u) legal_s[64u + lane] = l1;
+            if (lane < 9u) legal_s[64u + lane] = l1;
             const uint32_t cb0 = (cbw0 >> ((lane & 1u) * 16u)) & 0xFFFu;
-            const uint32_t cb1 = (cbw1 >> ((lane & 1u) * 16u)) & 0xFFFu;
+            const uint32_t cb1 = lane == 8u ? (cbw1 & 1u) : (cbw1 >> ((lane & 1u) * 16u)) & 0xFFFu;
             const uint32_t u0 = l0 & ~cb0, u1 = l1 & ~cb1;
             const uint64_t b0 = __ballot(u0 != 0u), b1 = __ballot(u1 != 0u);
             tree_sync<VALUE>();
             if (b0 | b1) {
-                // expansion: the lowest legal action that has no child yet
-                uint32_t pair, vbits;
-                if (b0) {
-                    pair = (uint32_t)__builtin_ctzll(b0);
-                    vbits = __builtin_amdgcn_readlane(u0, pair);
+                // expansion: the lowest playable key that has no child yet --
+                // the stop before the guesses after a right guess
+                uint32_t key, word, bit;
+                if ((b1 >> 8) & 1u) {
+                    key = kStopKey;
+                    word = 3u;
+                    bit = 1u;
                 } else {
-                    const uint32_t l = (uint32_t)__builtin_ctzll(b1);
-                    vbits = __builtin_amdgcn_readlane(u1, l);
-                    pair = 64u + l;
-                }
-                const uint32_t action = pair * 12u + (uint32_t)__builtin_ctz(vbits);
-                const uint32_t c = n_nodes++;
-                const uint32_t slot = nchild;
-                uint32_t blk = node;
-                if (slot >= kBlockEntries) {
-                    blk = W[rec + 1u];
-                    if ((slot & (kBlockEntries - 1u)) == 0u) {
-                        const uint32_t ob = a.nodes_cap + n_ovf++;
-                        if (lane == 0) {
-                            bnext[ob] = kNoBlock;
-                            bnext[blk] = ob;
-                            W[rec + 1u] = ob;
-                        }
-                        blk = ob;
+                    uint32_t pair, vbits;
+                    if (b0) {
+                        pair = (uint32_t)__builtin_ctzll(b0);
+                        vbits = __builtin_amdgcn_readlane(u0, pair);
+                    } else {
+                        const uint32_t l = (uint32_t)__builtin_ctzll(b1);
+                        vbits = __builtin_amdgcn_readlane(u1, l);
+                        pair = 64u + l;
                     }
+                    const uint32_t v = (uint32_t)__builtin_ctz(vbits);
+                    key = pair * 12u + v + (cont ? kStopKey + 1u : 0u);
+                    word = 4u + half + (pair >> 1);
+                    bit = 1u << (v + (pair & 1u) * 16u);
                 }
-                const uint32_t e = block_off(blk) + (slot & (kBlockEntries - 1u)) * kEntryWords;
-                if (lane == 0) {
-                    W[e + 0u] = action | (S.m << 16);
-                    W[e + 1u] = 0u;
-                    W[e + 2u] = 0u;
-                    W[e + 3u] = c;
-                    W[rec + 2u] = slot + 1u;
-                    W[rec + 4u + (pair >> 1)] |= 1u << ((action % 12u) + (pair & 1u) * 16u);
-                    bnext[c] = kNoBlock;
-                }
-                if (lane < kNodeWords) W[rec_off(c) + lane] = lane == 1u ? c : 0u;
+                uint32_t e;
+                append_child(node, nchild, key | (S.m << 16), 0u, e);
+                if (lane == 0) W[rec + word] |= bit;
                 path_e[np++] = e;
-                term = apply_action(S, action, depth, it, tr, a.k0, a.k1, winner, tab);
+                last_block = depth;
+                term = apply_action(S, key, a.cont_mode != 0u, depth, it, tr, a.k0, a.k1, winner,
+                                    cont, tab);
                 tree_sync<VALUE>();
                 break;
             }
-            // selection: UCT over the legal children, 64 per pass
+            // selection: UCT over the playable children, 64 per pass
             float best_s = -__builtin_inff();
             uint32_t best_i = 0xFFFFFFFFu, best_e = 0u, best_act = 0u, best_node = 0u, best_n = 0u;
             uint32_t blk = node;
@@ -531,9 +673,14 @@ mcts_tree_kernel(MctsArgs a)
                 float sc = -__builtin_inff();
                 uint32_t idx = 0xFFFFFFFFu;
                 if (ci < nchild) {
-                    const uint32_t act = ent.x & 0xFFFFu;
+                    const uint32_t key = ent.x & 0xFFFFu;
+                    const bool after_right = key > kStopKey;
+                    const uint32_t act = after_right ? key - kStopKey - 1u : key;
                     const uint32_t pr = act / 12u;
-                    if ((legal_s[pr] >> (act - pr * 12u)) & 1u) {
+                    const bool playable =
+                        key == kStopKey ? cont
+                                        : after_right == cont && ((legal_s[pr] >> (act - pr * 12u)) & 1u);
+                    if (playable) {
                         const float n = (float)ent.y;
                         const float q = __uint_as_float(ent.z) / n;
                         const float ex = lp / n;
@@ -557,10 +704,13 @@ mcts_tree_kernel(MctsArgs a)
             node = best_node;
             node_n = best_n;
             path_e[np++] = best_e;
-            term = apply_action(S, best_act, depth, it, tr, a.k0, a.k1, winner, tab);
+            last_block = depth;
+            term = apply_action(S, best_act, a.cont_mode != 0u, depth, it, tr, a.k0, a.k1, winner,
+                                cont, tab);
             ++depth;
             tree_sync<VALUE>();
         }
+        if (!term && cont) leaf_continue_coin(S, last_block, it, tr, a.k0, a.k1, tab);
 
         const uint64_t t2 = clock64();
         cyc[1] += t2 - t1;
@@ -651,10 +801,12 @@ mcts_tree_kernel(MctsArgs a)
         n_root += nplay;
         if (lane < np) {
             const uint32_t e = path_e[lane];
-            const uint32_t chooser = W[e] >> 16;
-            const float wc = chooser == 0u ? vals[0] : chooser == 1u ? vals[1] : chooser == 2u ? vals[2] : vals[3];
             W[e + 1u] += nplay;
-            W[e + 2u] = __float_as_uint(__uint_as_float(W[e + 2u]) + wc);
+            if (!(a.vanilla && lane == 0u)) {   // a world node's W word holds its key
+                const uint32_t chooser = W[e] >> 16;
+                const float wc = chooser == 0u ? vals[0] : chooser == 1u ? vals[1] : chooser == 2u ? vals[2] : vals[3];
+                W[e + 2u] = __float_as_uint(__uint_as_float(W[e + 2u]) + wc);
+            }
         }
         tree_sync<VALUE>();
         cyc[3] += clock64() - t3;
@@ -679,10 +831,56 @@ mcts_tree_kernel(MctsArgs a)
         write_no_children(a, t, lane);
         return;
     }
+    uint32_t *kid = a.kids ? a.kids + (size_t)t * kMaxActions * 3u : nullptr;
+    if (a.vanilla) {
+        // a guess is judged over all worlds: its (N, W) summed over the world
+        // nodes in creation order; most visits wins, the lowest action id on
+        // ties; the statistics come back indexed by action id
+        uint32_t *agg = W + a.sh.agg_off;
+        for (uint32_t c = lane; c < 2u * kMaxActions; c += 64u) agg[c] = 0u;
+        tree_sync<VALUE>();
+        const uint32_t nw = W[rec_off(0u) + 2u];
+        uint32_t wblk = 0u;
+        for (uint32_t wi = 0; wi < nw; ++wi) {
+            if (wi > 0u && (wi & (kBlockEntries - 1u)) == 0u) wblk = bnext[wblk];
+            const uint32_t wnode = W[block_off(wblk) + (wi & (kBlockEntries - 1u)) * kEntryWords + 3u];
+            const uint32_t nc = W[rec_off(wnode) + 2u];
+            uint32_t blk = wnode;
+            for (uint32_t base = 0; base < nc; base += kBlockEntries) {
+                if (base + lane < nc) {
+                    // one child per action below a world node: no two lanes collide
+                    const uint4 ent = *reinterpret_cast<const uint4 *>(W + block_off(blk) + lane * kEntryWords);
+                    const uint32_t act = ent.x & 0xFFFFu;
+                    agg[2u * act] += ent.y;
+                    agg[2u * act + 1u] = __float_as_uint(__uint_as_float(agg[2u * act + 1u]) +
+                                                         __uint_as_float(ent.z));
+                }
+                if (base + kBlockEntries < nc) blk = bnext[blk];
+            }
+            tree_sync<VALUE>();
+        }
+        uint64_t key = 0ull;   // N << 32 | (863 - action): most visits, lowest id on ties
+        for (uint32_t c = lane; c < kMaxActions; c += 64u) {
+            const uint32_t n = agg[2u * c];
+            const uint64_t kc = n ? ((uint64_t)n << 32) | (kMaxActions - 1u - c) : 0ull;
+            key = kc > key ? kc : key;
+            if (kid) {
+                kid[c * 3u + 0u] = n ? c : 0xFFFFu;
+                kid[c * 3u + 1u] = n;
+                kid[c * 3u + 2u] = agg[2u * c + 1u];
+            }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            const uint64_t o = __shfl_xor(key, off, 64);
+            key = o > key ? o : key;
+        }
+        if (lane == 0 && a.best)
+            a.best[t] = key == 0ull ? -1 : (int32_t)(kMaxActions - 1u - (uint32_t)(key & 0xFFFFFFFFull));
+        return;
+    }
     const uint32_t nchild = W[rec_off(0u) + 2u];
     uint32_t blk = 0u;
     uint32_t best_n = 0u, best_i = 0xFFFFFFFFu, best_act = 0xFFFFu;
-    uint32_t *kid = a.kids ? a.kids + (size_t)t * kMaxActions * 3u : nullptr;
     for (uint32_t base = 0; base < kMaxActions; base += kBlockEntries) {
         const uint32_t ci = base + lane;
         uint32_t act = 0xFFFFu, n = 0u, wbits = 0u;
@@ -717,9 +915,10 @@ mcts_tree_kernel(MctsArgs a)
 constexpr uint32_t kMergeThreads = 256;
 
 __global__ void __launch_bounds__(kMergeThreads)
-mcts_merge_kernel(const uint32_t *ws, uint64_t tree_words, uint32_t nodes_cap, uint32_t ovf_cap,
-                  uint32_t K, int32_t *best, uint32_t *merged)
+mcts_merge_kernel(const uint32_t *ws, MctsShape sh, uint32_t K, int32_t *best, uint32_t *merged)
 {
+    const uint64_t tree_words = sh.tree_words;
+    const uint32_t nodes_cap = sh.nodes_cap, ovf_cap = sh.ovf_cap, node_stride = sh.node_stride;
     __shared__ uint32_t sn[kMaxActions];
     __shared__ float sw[kMaxActions];
     __shared__ uint32_t s_failed;
@@ -731,7 +930,7 @@ mcts_merge_kernel(const uint32_t *ws, uint64_t tree_words, uint32_t nodes_cap, u
     }
     if (tid == 0) s_failed = 0u;
     __syncthreads();
-    const uint32_t ovf_base = kTreeHeaderWords + nodes_cap * kNodeStride;
+    const uint32_t ovf_base = kTreeHeaderWords + nodes_cap * node_stride;
     for (uint32_t k = 0; k < K; ++k) {
         const uint32_t *W = ws + ((uint64_t)r * K + k) * tree_words;
         const uint32_t *bnext = W + ovf_base + ovf_cap * kBlockWords;
@@ -743,7 +942,7 @@ mcts_merge_kernel(const uint32_t *ws, uint64_t tree_words, uint32_t nodes_cap, u
         for (uint32_t ci = tid; ci < nchild; ci += kMergeThreads) {
             uint32_t blk = 0u;
             for (uint32_t j = 0; j < (ci >> 6); ++j) blk = bnext[blk];
-            const uint32_t off = blk < nodes_cap ? kTreeHeaderWords + blk * kNodeStride + kNodeWords
+            const uint32_t off = blk < nodes_cap ? kTreeHeaderWords + blk * node_stride + sh.node_words
                                                  : ovf_base + (blk - nodes_cap) * kBlockWords;
             const uint32_t *e = W + off + (ci & (kBlockEntries - 1u)) * kEntryWords;
             const uint32_t act = e[0] & 0xFFFFu;
@@ -782,21 +981,12 @@ mcts_merge_kernel(const uint32_t *ws, uint64_t tree_words, uint32_t nodes_cap, u
     }
 }
 
-size_t mcts_tree_words(uint32_t iters)
-{
-    const uint64_t nodes_cap = (uint64_t)iters + 1u;
-    const uint64_t ovf_cap = nodes_cap / kBlockEntries + 2u;
-    const uint64_t words = kTreeHeaderWords + nodes_cap * kNodeStride + ovf_cap * kBlockWords +
-                           nodes_cap + ovf_cap;
-    return (size_t)((words + 3u) & ~(uint64_t)3u);   // keep every tree 16-byte aligned
-}
-
 hipError_t launch_mcts(const uint4 *roots, uint32_t n_trees, uint32_t trees_per_root,
                        uint32_t iters, uint32_t ppl,
                        uint32_t dmax, float c_uct, uint32_t k0, uint32_t k1, uint32_t tree_base,
                        const float *ln, uint32_t *ws, int32_t *best, uint32_t *kids,
                        uint32_t leaf_eval, float band, uint32_t fb_ppl, const void *net,
-                       hipStream_t st)
+                       uint32_t cont, uint32_t vanilla, hipStream_t st)
 {
     if (n_trees == 0) return hipSuccess;
     MctsArgs a;
@@ -805,16 +995,16 @@ hipError_t launch_mcts(const uint4 *roots, uint32_t n_trees, uint32_t trees_per_
     a.trees_per_root = trees_per_root;
     a.iters = iters;
     a.ppl = ppl;
-    a.dmax = dmax;
+    a.dmax = dmax == 0u ? 0xFFFFFFFFu : dmax;   // 0: no depth threshold
     a.c_uct = c_uct;
     a.k0 = k0;
     a.k1 = k1;
     a.tree_base = tree_base;
     a.ln = ln;
     a.ws = ws;
-    a.tree_words = mcts_tree_words(iters);
-    a.nodes_cap = iters + 1u;
-    a.ovf_cap = (iters + 1u) / kBlockEntries + 2u;
+    a.sh = mcts_shape(iters, cont, vanilla);
+    a.cont_mode = cont;
+    a.vanilla = vanilla;
     a.best = best;
     a.kids = kids;
     a.leaf_eval = leaf_eval;
@@ -829,12 +1019,12 @@ hipError_t launch_mcts(const uint4 *roots, uint32_t n_trees, uint32_t trees_per_
 }
 
 hipError_t launch_mcts_merge(const uint32_t *ws, uint32_t n_roots, uint32_t trees_per_root,
-                             uint32_t iters, int32_t *best, uint32_t *merged, hipStream_t st)
+                             uint32_t iters, uint32_t cont, int32_t *best, uint32_t *merged,
+                             hipStream_t st)
 {
     if (n_roots == 0) return hipSuccess;
     hipLaunchKernelGGL(mcts_merge_kernel, dim3(n_roots), dim3(kMergeThreads), 0, st, ws,
-                       (uint64_t)mcts_tree_words(iters), iters + 1u, (iters + 1u) / kBlockEntries + 2u,
-                       trees_per_root, best, merged);
+                       mcts_shape(iters, cont, 0u), trees_per_root, best, merged);
     return hipGetLastError();
 }
 

@@ -98,3 +98,24 @@ def test_valuenet_alignment_errors_without_device(lib):
     # misaligned blobs are rejected before any device work
     assert lib.dvc_valuenet_init(vp(8), 1, None) == -1
     assert lib.dvc_valuenet_infer(vp(24), vp(16), vp(16), 4, vp(16), None) == -1
+
+
+def test_tree_variant_parameters_without_device(lib):
+    """Workspace sizes of the un-simplified variants (host-only), parameter
+    ranges, and vanilla trees refused by the root-parallel search."""
+    import paper_2403_10720_amd as D
+    vp = C.c_void_p
+    lib.dvc_mcts_workspace_bytes.restype = C.c_size_t
+    lib.dvc_mcts_workspace_bytes.argtypes = [C.c_int64, C.POINTER(D.MctsParams)]
+    size = lambda **kw: lib.dvc_mcts_workspace_bytes(3, C.byref(D.mcts_params(iterations=100, **kw)))
+    base, cont, van = size(), size(continue_choice=1), size(vanilla=1)
+    assert base > 0 and cont > base and van > base
+    assert base % 16 == 0 and cont % 16 == 0 and van % 16 == 0
+    assert size(max_depth=0) == base and size(max_depth=64) == base
+    for bad in (dict(max_depth=65), dict(max_depth=-1), dict(continue_choice=2), dict(vanilla=3)):
+        assert size(**bad) == 0
+    mp = D.mcts_params(iterations=10, playouts_per_leaf=4, vanilla=1)
+    lib.mcts_search_root_parallel.argtypes = [vp, C.c_int64, C.c_int32, C.POINTER(D.MctsParams),
+                                              C.c_uint64, C.c_uint32, vp, C.c_size_t, vp, vp, vp]
+    assert lib.mcts_search_root_parallel(vp(16), 1, 2, C.byref(mp), 1, 0, vp(16), 1 << 30, vp(16),
+                                         None, None) == -1

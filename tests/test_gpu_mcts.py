@@ -97,8 +97,10 @@ def test_mcts_argument_errors(dvc):
     st = torch.zeros((2, 4), dtype=torch.int32, device="cuda")
     with pytest.raises(dvc.DvcError):
         dvc.mcts_search(st, dvc.mcts_params(iterations=0), 1)
-    with pytest.raises(dvc.DvcError):
-        dvc.mcts_search(st, dvc.mcts_params(max_depth=17), 1)
+    for bad in (dict(max_depth=65), dict(max_depth=-1), dict(continue_choice=2),
+                dict(vanilla=-1)):
+        with pytest.raises(dvc.DvcError):
+            dvc.mcts_search(st, dvc.mcts_params(**bad), 1)
     md = dvc.mcts_params(iterations=10, playouts_per_leaf=4)
     need = dvc.dvc_mcts_workspace_bytes(2, md)
     small = torch.empty(need - 4, dtype=torch.uint8, device="cuda")
