@@ -280,13 +280,15 @@ def mcts_search_root_parallel(roots: torch.Tensor, trees_per_root: int, params: 
 
 def mcts_tree_stats(workspace: torch.Tensor, n_trees: int, params: MctsParams) -> dict:
     """Per-tree counters the search leaves at the start of each tree's workspace,
-    including shader clock cycles spent in each phase of the iterations."""
+    including shader clock cycles spent in each phase of the iterations, the
+    deepest leaf and the root's child count (world nodes in vanilla trees)."""
     per_tree = dvc_mcts_workspace_bytes(1, params)
-    h = workspace[:n_trees * per_tree].view(n_trees, per_tree)[:, :64].contiguous().cpu()
+    h = workspace[:n_trees * per_tree].view(n_trees, per_tree)[:, :80].contiguous().cpu()
     w = h.view(torch.int32)
     cyc = h.view(torch.int64)[:, 4:8]
     return {"nodes": w[:, 0], "overflow_blocks": w[:, 1], "root_visits": w[:, 2], "net_leaves": w[:, 3],
             "played_leaves": w[:, 4], "sampler_fallbacks": w[:, 5], "failed": w[:, 6],
+            "deepest_leaf": w[:, 7], "root_children": w[:, 18],
             "cycles_sample": cyc[:, 0], "cycles_descend": cyc[:, 1], "cycles_evaluate": cyc[:, 2],
             "cycles_backprop": cyc[:, 3]}
 

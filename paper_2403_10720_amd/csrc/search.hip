@@ -50,7 +50,8 @@ constexpr uint32_t kEntryWords = 4;
 constexpr uint32_t kBlockWords = kBlockEntries * kEntryWords;
 constexpr uint32_t kStopKey = kMaxActions;   // 864; a guess after a right guess is 865 + action
 // tree header: nodes, overflow blocks, root visits, network leaves, played
-// leaves, sampler fallbacks, failed flag; from word 8, four 64-bit sums of
+// leaves, sampler fallbacks, failed flag, deepest leaf (tree levels below the
+// root, world nodes not counted); from word 8, four 64-bit sums of
 // shader clock cycles spent sampling worlds, descending, evaluating leaves
 // and back-propagating
 constexpr uint32_t kHdrFailed = 6;
@@ -510,7 +511,7 @@ mcts_tree_kernel(MctsArgs a)
     for (uint32_t k = lane; k < node_words; k += 64u) W[rec_off(0u) + k] = 0u;
     if (lane == 0) bnext[0] = kNoBlock;
     uint32_t n_nodes = 1u, n_ovf = 0u, n_root = 0u;
-    uint32_t n_net = 0u, n_played = 0u, n_sampler_fallback = 0u;   // statistics
+    uint32_t n_net = 0u, n_played = 0u, n_sampler_fallback = 0u, deepest = 0u;   // statistics
     bool failed = false, have_fallback = false;
     State fallback = R;
     uint64_t cyc[4] = {0u, 0u, 0u, 0u};   // shader clock per phase (statistics)
@@ -711,6 +712,7 @@ mcts_tree_kernel(MctsArgs a)
             tree_sync<VALUE>();
         }
         if (!term && cont) leaf_continue_coin(S, last_block, it, tr, a.k0, a.k1, tab);
+        deepest = np - a.vanilla > deepest ? np - a.vanilla : deepest;
 
         const uint64_t t2 = clock64();
         cyc[1] += t2 - t1;
@@ -821,6 +823,7 @@ mcts_tree_kernel(MctsArgs a)
         W[4] = n_played;
         W[5] = n_sampler_fallback;
         W[kHdrFailed] = failed ? 1u : 0u;
+        W[kHdrFailed + 1u] = deepest;
         for (uint32_t q = 0; q < 4u; ++q) {
             W[kHdrCycles + 2u * q] = (uint32_t)cyc[q];
             W[kHdrCycles + 2u * q + 1u] = (uint32_t)(cyc[q] >> 32);

@@ -26,6 +26,10 @@ GPU thread sweep).
 
 ppl_autotune(): playouts per leaf of the batched search picked by
 measurement, with its root-move agreement.
+
+tree_variants(): each of the paper's simplifications switched off (Sec.
+III-A) on the batched workload: time per decision, tree shape and decision
+stability.
 """
 from __future__ import annotations
 
@@ -154,6 +158,71 @@ def root_parallel_vs_single(n_roots=256, trees_per_root=32, iterations=1024, ppl
     }
 
 
+BATCH_DEAL = dict(p_min=2, p_max=4, hand=(0, 0, 4, 4, 3), pile_min=0, pile_max=16, revealed_max=8,
+                  root_draw=1)
+
+TREE_VARIANTS = {
+    "simplified (paper)": dict(max_depth=4),
+    "continue choice": dict(max_depth=4, continue_choice=1),
+    "no depth threshold": dict(max_depth=0),
+    "continue choice, no depth threshold": dict(max_depth=0, continue_choice=1),
+    "vanilla (worlds as nodes)": dict(max_depth=4, vanilla=1),
+    "vanilla, continue choice, no depth threshold": dict(max_depth=0, continue_choice=1, vanilla=1),
+}
+
+
+def tree_variants(n_roots=512, iterations=1024, ppl=32, seed=3, ref_trees=32):
+    """Roots of the batched workload (mid-game 2-4 player roots) searched with
+    each simplification of Sec. III-A switched off.  Reported per variant: GPU
+    time per decision (HIP events around one launch), mean nodes per tree,
+    mean and largest deepest leaf, mean root children (world nodes in vanilla
+    trees), how often two seeds decide alike, how often the decision is the
+    lowest legal guess (the first one expanded: a tree whose visits follow
+    its expansion order rather than its playouts picks it), and agreement
+    with two references of ref_trees times the iterations: the simplified
+    root-parallel search (ref_trees trees per root) and the same variant
+    (root-parallel, or for vanilla trees one tree with ref_trees times the
+    iterations)."""
+    roots = dvc_init_states(n_roots, deal_params(**BATCH_DEAL), seed)
+    mp_ref = mcts_params(iterations=iterations, playouts_per_leaf=ppl, max_depth=4)
+    ref, _ = mcts_search_root_parallel(roots, ref_trees, mp_ref, seed + 7000, want_children=False)
+    _, kids = mcts_search(roots, mp_ref, seed, want_children=True)
+    lowest = kids[:, 0, 0] & 0xFFFF          # first child created = lowest legal guess
+    torch.cuda.empty_cache()
+    out = {"roots": n_roots, "iterations": iterations, "playouts_per_leaf": ppl,
+           "reference": f"{ref_trees} x the iterations (root-parallel, or one vanilla tree)",
+           "variants": {}}
+    for name, kw in TREE_VARIANTS.items():
+        mp = mcts_params(iterations=iterations, playouts_per_leaf=ppl, **kw)
+        ws = torch.empty(dvc_mcts_workspace_bytes(n_roots, mp), dtype=torch.uint8,
+                         device=roots.device)
+        mcts_search(roots, mp, seed + 1, workspace=ws, want_children=False)   # warm-up
+        b2, _ = mcts_search(roots, mp, seed + 2, workspace=ws, want_children=False)
+        (b1, _), t = _timed(lambda: mcts_search(roots, mp, seed, workspace=ws, want_children=False))
+        st = mcts_tree_stats(ws, n_roots, mp)
+        del ws
+        if kw.get("vanilla"):
+            own, _ = mcts_search(roots, mcts_params(iterations=iterations * ref_trees,
+                                                    playouts_per_leaf=ppl, **kw),
+                                 seed + 7000, want_children=False)
+        else:
+            own, _ = mcts_search_root_parallel(roots, ref_trees, mp, seed + 7000,
+                                               want_children=False)
+        torch.cuda.empty_cache()
+        out["variants"][name] = {
+            "ms_per_launch": t * 1e3, "decisions_per_s": n_roots / t,
+            "nodes_per_tree": float(st["nodes"].float().mean()),
+            "deepest_leaf_mean": float(st["deepest_leaf"].float().mean()),
+            "deepest_leaf_max": int(st["deepest_leaf"].max()),
+            "root_children_mean": float(st["root_children"].float().mean()),
+            "agreement_two_seeds": float((b1 == b2).float().mean().item()),
+            "lowest_legal_guess_rate": float((b1 == lowest).float().mean().item()),
+            "agreement_with_simplified_reference": float((b1 == ref).float().mean().item()),
+            "agreement_with_own_reference": float((b1 == own).float().mean().item()),
+        }
+    return out
+
+
 SEARCH_WORKLOADS = {
     "single tree, fresh 2-player deal, 2000 x 16": (1, dict(p_min=2, p_max=2, fresh=1, root_draw=1), 2000, 16, 1),
     "batched, 2048 mid-game roots, 1024 x 32": (2048, dict(p_min=2, p_max=4, hand=(0, 0, 4, 4, 3), pile_min=0,
@@ -254,7 +323,8 @@ def main(argv=None):
     import argparse
     import json
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
-    ap.add_argument("--what", choices=["value", "root-parallel", "phases", "scaling", "ppl", "all"],
+    ap.add_argument("--what", choices=["value", "root-parallel", "phases", "scaling", "ppl",
+                                       "variants", "all"],
                     default="all")
     ap.add_argument("--trees", type=int, default=1024)
     ap.add_argument("--iterations", type=int, default=4096)
@@ -273,6 +343,8 @@ def main(argv=None):
         print(json.dumps({"ppl_autotune": ppl_autotune()}), flush=True)
     if args.what in ("scaling", "all"):
         print(json.dumps({"gpu_scaling": gpu_scaling()}), flush=True)
+    if args.what in ("variants", "all"):
+        print(json.dumps({"tree_variants": tree_variants()}), flush=True)
     if args.what in ("phases", "all"):
         from . import dvc_valuenet_init
         print(json.dumps({"search_phases": search_phases(dvc_valuenet_init(44))}), flush=True)
