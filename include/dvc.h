@@ -23,6 +23,11 @@
  *     they do not depend on the launch shape, on the batch a leaf or tree is
  *     part of, or on the stream.
  *   - The library prints nothing and never aborts.
+ *   - Device memory the library allocates itself: the natural-log table of
+ *     the tree search, once per device on the first search that needs it
+ *     (grown, never freed, when a later search needs more entries; the
+ *     growing call copies it synchronously, so make one search before
+ *     capturing a graph).  Everything else lives in caller buffers.
  *
  * Random numbers: Philox4x32-10 (Salmon et al., SC'11) with key
  * (seed & 0xFFFFFFFF, seed >> 32).  A pick among k options from a word w is
@@ -33,7 +38,9 @@
  *     a word whose choice does not arise is skipped, never shifted.
  *   determinization attempt a of iteration i, word n   (n>>2, 0x80000000+a, i, tr)
  *   in-tree guess at depth d of iteration i             (d, 0xC0000000, i, tr)
- *     word 0 own tile to reveal, word 1 next player's draw
+ *     word 0 own tile to reveal, word 1 next player's draw, word 3 the
+ *     continue coin of a leaf reached right after a right guess (continue
+ *     choice on, see dvc_mcts_params)
  *   synthetic state s, word n                           (n>>2, 0xFFFFFFFF, 0xFFFFFFFF, s)
  */
 #ifndef DVC_H
