@@ -21,6 +21,12 @@
  * iteration first samples a plausible set of numbers for them (Sec. III-A);
  * the tree is open loop over those samples.
  *
+ * Leaf batching (leaves_per_pass = B): the iterations run in passes of B.
+ * Each descent of a pass adds its visit counts along its path as soon as its
+ * leaf is found (so the next descent of the pass sees them, with no wins
+ * yet); then the pass's leaves are evaluated and each path gets its wins, in
+ * iteration order.  B = 1 is the plain sequential search.
+ *
  * Selection uses UCT (Kocsis & Szepesvari 2006) evaluated in single precision
  * with one IEEE rounding per operation, in this order:
  *     n = float(N_c); q = W_c / n; e = LN[N_parent] / n; u = c * sqrt(e);
@@ -526,88 +532,103 @@ static int search_one(const orc_rows *root, const orc_mcts_params *mp, uint64_t 
     otree T = {0};
     tree_new_node(&T, -1, -1);
     int ppl = mp->leaf_eval ? mp->fallback_playouts : mp->playouts_per_leaf;
-    int path[128];
+    int B = mp->leaves_per_pass;
+    int path[ORC_MAX_PASS][128], np[ORC_MAX_PASS], terminal[ORC_MAX_PASS], winner[ORC_MAX_PASS];
+    orc_rows leafS[ORC_MAX_PASS];
     uint8_t legal[ORC_MAX_CHILD];
-    for (int i = 0; i < mp->iterations; ++i) {
-        orc_rows S;
-        if (determinize_rows(root, seed, tr, (uint32_t)i, &S) < 0) {
-            tree_free(&T);
-            return -3;
-        }
-        int node = 0, depth = 0, np = 0, terminal = 0, winner = -1, cont = 0, last_block = -1;
-        path[np++] = 0;
-        if (mp->vanilla) {
-            /* the world node of this sample: found among the root's children
-               by its key, or appended */
-            uint64_t key = world_key(&S, root->mover);
-            int found = -1;
-            for (int k = 0; k < T.v[0].nchild; ++k)
-                if (T.v[T.v[0].child[k]].world == key) { found = T.v[0].child[k]; break; }
-            if (found < 0) {
-                found = tree_new_node(&T, -1, -1);
-                T.v[found].world = key;
-                node_add_child(&T, 0, found);
+    for (int i0 = 0; i0 < mp->iterations; i0 += B) {
+        int nb = mp->iterations - i0 < B ? mp->iterations - i0 : B;
+        for (int b = 0; b < nb; ++b) {
+            int i = i0 + b;
+            orc_rows S;
+            if (determinize_rows(root, seed, tr, (uint32_t)i, &S) < 0) {
+                tree_free(&T);
+                return -3;
             }
-            node = found;
-            path[np++] = node;
-        }
-        for (;;) {
-            if (terminal) break;
-            if (mp->max_depth > 0 && depth >= mp->max_depth) break;
-            legal_rows(&S, legal);
-            onode *X = &T.v[node];
-            /* expansion: the lowest playable key without a child */
-            int expand = -1;
-            for (int k = 0; k < ORC_KEYS; ++k)
-                if (key_legal(k, cont, legal) && !(X->has && X->has[k])) { expand = k; break; }
-            if (expand >= 0) {
-                int c = tree_new_node(&T, expand, S.mover);
-                node_add_child(&T, node, c);
-                terminal = apply_rows(&S, expand, mp->continue_choice, seed, tr, (uint32_t)i,
-                                      (uint32_t)depth, &winner, &cont);
+            int node = 0, depth = 0, cont = 0, last_block = -1;
+            int *pth = path[b];
+            np[b] = 0;
+            terminal[b] = 0;
+            winner[b] = -1;
+            pth[np[b]++] = 0;
+            if (mp->vanilla) {
+                /* the world node of this sample: found among the root's
+                   children by its key, or appended */
+                uint64_t key = world_key(&S, root->mover);
+                int found = -1;
+                for (int k = 0; k < T.v[0].nchild; ++k)
+                    if (T.v[T.v[0].child[k]].world == key) { found = T.v[0].child[k]; break; }
+                if (found < 0) {
+                    found = tree_new_node(&T, -1, -1);
+                    T.v[found].world = key;
+                    node_add_child(&T, 0, found);
+                }
+                node = found;
+                pth[np[b]++] = node;
+            }
+            for (;;) {
+                if (terminal[b]) break;
+                if (mp->max_depth > 0 && depth >= mp->max_depth) break;
+                legal_rows(&S, legal);
+                onode *X = &T.v[node];
+                /* expansion: the lowest playable key without a child */
+                int expand = -1;
+                for (int k = 0; k < ORC_KEYS; ++k)
+                    if (key_legal(k, cont, legal) && !(X->has && X->has[k])) { expand = k; break; }
+                if (expand >= 0) {
+                    int c = tree_new_node(&T, expand, S.mover);
+                    node_add_child(&T, node, c);
+                    terminal[b] = apply_rows(&S, expand, mp->continue_choice, seed, tr, (uint32_t)i,
+                                             (uint32_t)depth, &winner[b], &cont);
+                    last_block = depth;
+                    pth[np[b]++] = c;
+                    break;
+                }
+                /* selection: strictly greater score wins, so ties keep the
+                   earliest-created child */
+                X = &T.v[node];
+                float Lp = LN[X->N];
+                int best = -1;
+                float best_s = 0.0f;
+                for (int k = 0; k < X->nchild; ++k) {
+                    onode *c = &T.v[X->child[k]];
+                    if (!key_legal(c->action, cont, legal)) continue;
+                    float n = (float)c->N;
+                    float q = c->W / n;
+                    float e = Lp / n;
+                    float u = mp->c_uct * sqrtf(e);
+                    float s = q + u;
+                    if (best < 0 || s > best_s) { best = X->child[k]; best_s = s; }
+                }
+                terminal[b] = apply_rows(&S, T.v[best].action, mp->continue_choice, seed, tr,
+                                         (uint32_t)i, (uint32_t)depth, &winner[b], &cont);
                 last_block = depth;
-                path[np++] = c;
-                break;
+                node = best;
+                pth[np[b]++] = best;
+                ++depth;
             }
-            /* selection: strictly greater score wins, so ties keep the
-               earliest-created child */
-            X = &T.v[node];
-            float Lp = LN[X->N];
-            int best = -1;
-            float best_s = 0.0f;
-            for (int k = 0; k < X->nchild; ++k) {
-                onode *c = &T.v[X->child[k]];
-                if (!key_legal(c->action, cont, legal)) continue;
-                float n = (float)c->N;
-                float q = c->W / n;
-                float e = Lp / n;
-                float u = mp->c_uct * sqrtf(e);
-                float s = q + u;
-                if (best < 0 || s > best_s) { best = X->child[k]; best_s = s; }
+            if (!terminal[b] && cont)
+                leaf_continue_coin(&S, seed, tr, (uint32_t)i, (uint32_t)last_block);
+            leafS[b] = S;
+            /* the visit counts go in at once */
+            for (int k = 0; k < np[b]; ++k) T.v[pth[k]].N += (uint32_t)ppl;
+        }
+        for (int b = 0; b < nb; ++b) {
+            int i = i0 + b;
+            float vals[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+            if (terminal[b]) {
+                vals[winner[b]] = (float)ppl;
+            } else if (mp->leaf_eval) {
+                value_leaf(&leafS[b], root->mover, mp, seed, (uint32_t)i, tr, vals);
+            } else {
+                uint32_t wins[4] = {0, 0, 0, 0};
+                rollout_rows_wins(&leafS[b], ppl, seed, (uint32_t)i, tr, wins);
+                for (int k = 0; k < 4; ++k) vals[k] = (float)wins[k];
             }
-            terminal = apply_rows(&S, T.v[best].action, mp->continue_choice, seed, tr, (uint32_t)i,
-                                  (uint32_t)depth, &winner, &cont);
-            last_block = depth;
-            node = best;
-            path[np++] = best;
-            ++depth;
-        }
-        if (!terminal && cont)
-            leaf_continue_coin(&S, seed, tr, (uint32_t)i, (uint32_t)last_block);
-        float vals[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-        if (terminal) {
-            vals[winner] = (float)ppl;
-        } else if (mp->leaf_eval) {
-            value_leaf(&S, root->mover, mp, seed, (uint32_t)i, tr, vals);
-        } else {
-            uint32_t wins[4] = {0, 0, 0, 0};
-            rollout_rows_wins(&S, ppl, seed, (uint32_t)i, tr, wins);
-            for (int k = 0; k < 4; ++k) vals[k] = (float)wins[k];
-        }
-        for (int k = 0; k < np; ++k) {
-            onode *x = &T.v[path[k]];
-            x->N += (uint32_t)ppl;
-            if (k > 0 && x->chooser >= 0) x->W += vals[x->chooser];
+            for (int k = 1; k < np[b]; ++k) {
+                onode *x = &T.v[path[b][k]];
+                if (x->chooser >= 0) x->W += vals[x->chooser];
+            }
         }
     }
     onode *R = &T.v[0];
@@ -682,7 +703,8 @@ int oracle_mcts_search(const orc_packed *roots, int64_t n_trees, const orc_mcts_
     if (n_trees < 0 || mp->iterations < 1 || mp->playouts_per_leaf < 1 || mp->max_depth < 0 ||
         mp->max_depth > 64 || mp->leaf_eval < 0 || mp->leaf_eval > 1 ||
         (mp->continue_choice != 0 && mp->continue_choice != 1) ||
-        (mp->vanilla != 0 && mp->vanilla != 1))
+        (mp->vanilla != 0 && mp->vanilla != 1) || mp->leaves_per_pass < 1 ||
+        mp->leaves_per_pass > ORC_MAX_PASS)
         return -1;
     if (mp->leaf_eval && (mp->valuenet == NULL || mp->fallback_playouts < 1)) return -1;
     for (int64_t t = 0; t < n_trees; ++t) {

@@ -61,6 +61,7 @@ typedef struct {
     const void *valuenet;
     int32_t continue_choice; /* 1: after a right guess the mover may stop or guess again */
     int32_t vanilla;         /* 1: the root's children are the sampled worlds            */
+    int32_t leaves_per_pass; /* B >= 1 descents before their leaves are evaluated        */
 } orc_mcts_params;
 
 typedef struct { uint16_t action; uint16_t pad; uint32_t n; float w; } orc_child_stat;
@@ -80,6 +81,8 @@ typedef struct {
 /* tree keys: guesses 0..863, stop 864, a guess after a right guess 865 + a */
 #define ORC_STOP_KEY 864
 #define ORC_KEYS (2 * ORC_MAX_CHILD + 1)
+/* most leaves evaluated together (leaves_per_pass) */
+#define ORC_MAX_PASS 16
 
 /* Philox4x32-10 block (Salmon, Moraes, Dror, Shaw, SC'11). */
 void oracle_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);

@@ -330,3 +330,100 @@ def test_vanilla_plausible_sets_of_four_same_coloured_tiles(orc):
     as_sets = {tuple(x for x in range(24) if (k >> (2 * x)) & 3) for k in keys}
     assert as_sets <= set(law)
     assert len(worlds) > 150               # dilution: most iterations open a new world
+
+
+# ---------------------------------------------------------------------------
+# leaf batching: B descents per pass, visits at once, wins after the pass
+# ---------------------------------------------------------------------------
+def _ucb1_batched_reference(orc, root, iters, ppl, seed, tree, B):
+    """UCB1 over the root's guesses where arms are pulled in passes of B:
+    within a pass every pull counts its visits at once (the later pulls of the
+    pass see them, with no wins), the pass's leaves are then played out and
+    their wins added in pull order."""
+    legal = np.flatnonzero(orc.legal_actions(root))
+    mover = orc.unpack(root)["mover"]
+    arms, N, W = [], {}, {}
+    n_root = 0
+    for i0 in range(0, iters, B):
+        pulls = []
+        for i in range(i0, min(iters, i0 + B)):
+            untried = [a for a in legal if a not in N]
+            if untried:
+                a = int(untried[0])
+                arms.append(a)
+                N[a], W[a] = 0, np.float32(0)
+            else:
+                lp = np.float32(math.log(n_root))
+                best, best_s = None, None
+                for c in arms:
+                    n = np.float32(N[c])
+                    s = W[c] / n + C_UCT * np.sqrt(lp / n)
+                    if best is None or s > best_s:
+                        best, best_s = c, s
+                a = best
+            N[a] += ppl
+            n_root += ppl
+            pulls.append((i, a))
+        for i, a in pulls:
+            world, _ = orc.determinize(root, seed, tree, i)
+            leaf, term, win = orc.apply_action(world, a, seed, tree, i, 0)
+            if term:
+                wins = np.zeros(4, np.uint32)
+                wins[win] = ppl
+            else:
+                _, _, w4 = orc.rollout(leaf, ppl, seed, tree_id=tree, leaf_id_base=i,
+                                       want_winner=False, want_length=False)
+                wins = w4[0]
+            W[a] = np.float32(W[a] + np.float32(wins[mover]))
+    best = max(arms, key=lambda a: (N[a], -arms.index(a)))
+    return arms, N, W, best
+
+
+@pytest.mark.parametrize("B", [2, 3, 4])
+def test_leaf_batching_depth_one_is_batched_ucb1(orc, B):
+    roots = orc.init_states(2, orc.deal_params(p_min=2, p_max=3, fresh=0, pile_min=0,
+                                               pile_max=8, revealed_max=6, root_draw=1), 83)
+    for case, root in enumerate(roots):
+        iters, ppl, seed, tree = 203, 4, 92, case
+        mp = orc.mcts_params(iterations=iters, playouts_per_leaf=ppl, max_depth=1,
+                             leaves_per_pass=B)
+        best, kids = orc.mcts_search(root, mp, seed, tree_id_base=tree)
+        arms, N, W, ref_best = _ucb1_batched_reference(orc, root, iters, ppl, seed, tree, B)
+        k = kids[0][kids[0]["action"] != 0xFFFF]
+        assert [int(a) for a in k["action"]] == arms
+        assert [int(n) for n in k["n"]] == [N[a] for a in arms]
+        assert [float(w) for w in k["w"]] == [float(W[a]) for a in arms]
+        assert best[0] == ref_best
+    # batching changes the search once selection starts
+    kw = dict(iterations=600, playouts_per_leaf=4, max_depth=1)
+    _, k1 = orc.mcts_search(roots[1], orc.mcts_params(**kw), 92, tree_id_base=1)
+    _, kb = orc.mcts_search(roots[1], orc.mcts_params(leaves_per_pass=B, **kw), 92, tree_id_base=1)
+    assert not (np.array_equal(k1[0]["n"], kb[0]["n"]) and np.array_equal(k1[0]["w"], kb[0]["w"]))
+
+
+@pytest.mark.parametrize("cont,vanilla", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_leaf_batching_tree_identities(orc, cont, vanilla):
+    """Whole trees with B = 4 (and a ragged last pass): every visit is counted
+    once, the identities of a searched tree hold, and a pass's descents
+    spread over different children."""
+    for P in (2, 3):
+        root = _mid_roots(orc, 1, 95 + P, P)[0]
+        iters, ppl = 401, 4
+        mp = orc.mcts_params(iterations=iters, playouts_per_leaf=ppl, max_depth=0,
+                             continue_choice=cont, vanilla=vanilla, leaves_per_pass=4)
+        _, t = orc.mcts_tree(root, mp, 8)
+        _check_tree(t, iters, ppl, cont)
+
+
+def test_leaf_batching_first_pass_is_the_expansion_sweep(orc):
+    """While the root still has untried guesses every descent expands the
+    next one, whatever the batch: the first B iterations give the same root as
+    B sequential iterations."""
+    root = orc.init_states(1, orc.deal_params(p_min=3, p_max=3, fresh=1, root_draw=1), 99)[0]
+    n_legal = int(orc.legal_actions(root).sum())
+    B = 16
+    assert n_legal >= B
+    a = orc.mcts_search(root, orc.mcts_params(iterations=B, playouts_per_leaf=8,
+                                              leaves_per_pass=B), 3, 4)
+    b = orc.mcts_search(root, orc.mcts_params(iterations=B, playouts_per_leaf=8), 3, 4)
+    assert a[0][0] == b[0][0] and np.array_equal(a[1], b[1])
