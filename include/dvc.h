@@ -203,6 +203,15 @@ int dvc_rollout_autotune(const dvc_state_t *leaves, int64_t n_leaves, int32_t pl
  * W += wins of the chooser (playouts) or w * v_chooser (network).
  * Decision: the root child with the most visits, earliest created on ties.
  *
+ * Leaf batching (leaves_per_pass = B > 1): the iterations run in passes of
+ * B.  Each descent of a pass adds its visit counts along its path as soon as
+ * its leaf is found (the pass's later descents see them, with no wins yet);
+ * then the pass's leaves are evaluated together -- their playouts share the
+ * 64 lanes of the tree's wavefront, their network rows one matrix tile --
+ * and each path gets its leaf's wins, in iteration order.  Every leaf keeps
+ * its iteration index for its world, chance words and playouts.  B = 1 is
+ * the sequential search above.
+ *
  * The paper's three simplifications (Sec. III-A) can each be switched off:
  *   max_depth 0 -- no depth threshold: nodes expand until the game ends;
  *   continue_choice 1 -- a right guess no longer ends the turn: the same
@@ -234,6 +243,8 @@ typedef struct {
     const void *valuenet;       /* value mode: dvc_valuenet blob (device, 16-aligned) */
     int32_t continue_choice;    /* 1: stop-or-guess choice after a right guess      */
     int32_t vanilla;            /* 1: sampled worlds are the root's children        */
+    int32_t leaves_per_pass;    /* B: leaves evaluated together, 1..16 (value mode
+                                   1..2); 1 = the sequential search              */
 } dvc_mcts_params;
 
 /* one root child, in creation order (vanilla: indexed by action id); action

@@ -93,6 +93,9 @@ static bool mcts_params_ok(const dvc_mcts_params *p)
         return false;
     if ((p->continue_choice != 0 && p->continue_choice != 1) || (p->vanilla != 0 && p->vanilla != 1))
         return false;
+    // leaves evaluated together: value mode fits two leaves' perspectives in
+    // one matrix tile, playout mode packs up to 16 leaves' playouts
+    if (p->leaves_per_pass < 1 || p->leaves_per_pass > (p->leaf_eval ? 2 : 16)) return false;
     if (!(p->c_uct >= 0.0f) || std::isinf(p->c_uct)) return false;
     if (p->leaf_eval != 0 && p->leaf_eval != 1) return false;
     if (p->leaf_eval == 1 && (p->valuenet == nullptr || !aligned16(p->valuenet) ||
@@ -368,7 +371,7 @@ static int run_search(const dvc_state_t *roots, int64_t n_roots, int64_t trees_p
                                (uint32_t)params->leaf_eval, params->fallback_band,
                                (uint32_t)params->fallback_playouts, params->valuenet,
                                (uint32_t)params->continue_choice, (uint32_t)params->vanilla,
-                               (hipStream_t)stream);
+                               (uint32_t)params->leaves_per_pass, (hipStream_t)stream);
     if (e != hipSuccess || !merge) return status_of(e);
     return status_of(launch_mcts_merge(reinterpret_cast<const uint32_t *>(workspace),
                                        (uint32_t)n_roots, (uint32_t)trees_per_root,

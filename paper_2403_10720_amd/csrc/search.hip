@@ -408,6 +408,7 @@ struct MctsArgs {
     uint32_t *ws;
     MctsShape sh;
     uint32_t cont_mode, vanilla;   // simplifications 2 and 1 switched off
+    uint32_t lpp;                  // leaves per pass
     int32_t *best;    // [n_trees] or null
     uint32_t *kids;   // [n_trees][864][3] or null
     // value mode: leaves are scored by the network; a leaf whose value for
@@ -446,7 +447,13 @@ __device__ __forceinline__ void tree_sync()
 // Trees per workgroup: value mode stages the 256 x 256 second-layer weights
 // in LDS once per workgroup for its four trees; playout mode runs one tree per
 // workgroup.
-template <bool VALUE> struct TreeGroup { static constexpr uint32_t kTrees = VALUE ? 4u : 1u; };
+template <bool VALUE> struct TreeGroup {
+    static constexpr uint32_t kTrees = VALUE ? 4u : 1u;
+    // leaves evaluated together: value mode puts their perspectives into the
+    // 16 rows of one matrix tile, four per leaf, and its LDS (the shared
+    // second-layer weights) leaves room for the rows of two
+    static constexpr uint32_t kPass = VALUE ? 2u : 16u;
+};
 
 // VALUE: value mode (network leaves) -- one wavefront per SIMD, so that the
 // evaluation can keep many weight loads in flight; otherwise playout leaves
@@ -459,9 +466,15 @@ mcts_tree_kernel(MctsArgs a)
     constexpr uint32_t TG = TreeGroup<VALUE>::kTrees;
     __shared__ uint8_t tab[kKthTableBytes];
     __shared__ uint32_t legal_all[TG][73];
-    __shared__ uint32_t path_all[TG][kMaxPath];
+    constexpr uint32_t BM = TreeGroup<VALUE>::kPass;
+    constexpr uint32_t kVnTreeRows = 4u * (VALUE ? BM : 1u);
+    __shared__ uint32_t path_all[TG][BM][kMaxPath];
+    __shared__ uint4 leaf_all[TG][BM];
+    __shared__ uint32_t np_all[TG][BM];
+    __shared__ uint32_t wins_all[TG][4u * BM];
+    __shared__ float vals_all[TG][BM][4];
     __shared__ DfsSlots dfs_all[TG];
-    __shared__ __attribute__((aligned(16))) uint16_t tile_all[TG][4][kVnH + 8];
+    __shared__ __attribute__((aligned(16))) uint16_t tile_all[TG][kVnTreeRows][kVnH + 8];
     __shared__ __attribute__((aligned(16))) uint16_t w2_lds[VALUE ? kVnH * kVnH : 8];
     __shared__ VnSmall vn_small[1];
     fill_kth_table(tab);
@@ -478,9 +491,9 @@ mcts_tree_kernel(MctsArgs a)
     if (t >= a.n_trees) return;
     const uint32_t lane = threadIdx.x & 63u;
     uint32_t *legal_s = legal_all[wv];
-    uint32_t *path_e = path_all[wv];
     DfsSlots &dfs_slots = dfs_all[wv];
     uint16_t (*vn_tile)[kVnH + 8] = tile_all[wv];
+    float (*vals)[4] = vals_all[wv];
     const uint32_t tr = a.tree_base + t;
     uint32_t *W = a.ws + (uint64_t)t * a.sh.tree_words;
     const uint32_t nodes_cap = a.sh.nodes_cap, node_words = a.sh.node_words;
@@ -517,247 +530,282 @@ mcts_tree_kernel(MctsArgs a)
     uint64_t cyc[4] = {0u, 0u, 0u, 0u};   // shader clock per phase (statistics)
     tree_sync<VALUE>();
 
-    for (uint32_t it = 0; it < a.iters && !failed; ++it) {
-        const uint64_t t0 = clock64();
-        // ---- 1. sample a world: attempt `lane`, lowest success wins ------
-        State S;
-        const bool got = det_attempt(R, lane, it, tr, a.k0, a.k1, S, tab);
-        const uint64_t okm = __ballot(got);
-        if (okm) {
-            S = readlane_state(S, (uint32_t)__builtin_ctzll(okm));
-        } else {
-            // the fallback world depends on the root only: search it once
-            if (!have_fallback) {
-                State F = R;
-                bool fok = false;
-                if (lane == 0) fok = det_fallback(R, F, dfs_slots);
-                fok = __builtin_amdgcn_readfirstlane((uint32_t)fok) != 0u;
-                if (!fok) {
-                    if (lane == 0) atomicOr(&g_error_word, kErrLimit);
-                    failed = true;
-                    break;
+    // Iterations run in passes of B = leaves_per_pass: each descent of a pass
+    // adds its visit counts along its path at once (the next descent sees
+    // them, with no wins yet); then the pass's leaves are evaluated together
+    // -- their playouts packed into the same 64 lanes, or their perspectives
+    // into the rows of one matrix tile -- and each path gets its wins, in
+    // iteration order.  B = 1 is the plain sequential search.
+    const uint32_t nplay = VALUE ? a.fb_ppl : a.ppl;   // visits of every leaf
+    for (uint32_t i0 = 0; i0 < a.iters && !failed; i0 += a.lpp) {
+        const uint32_t nb = a.iters - i0 < a.lpp ? a.iters - i0 : a.lpp;
+        uint32_t term_mask = 0u, winners = 0u;   // per leaf of the pass: decided, winner (2 bits)
+        for (uint32_t b = 0; b < nb; ++b) {
+            const uint32_t it = i0 + b;
+            uint32_t *path_e = path_all[wv][b];
+            const uint64_t t0 = clock64();
+            // ---- 1. sample a world: attempt `lane`, lowest success wins ------
+            State S;
+            const bool got = det_attempt(R, lane, it, tr, a.k0, a.k1, S, tab);
+            const uint64_t okm = __ballot(got);
+            if (okm) {
+                S = readlane_state(S, (uint32_t)__builtin_ctzll(okm));
+            } else {
+                // the fallback world depends on the root only: search it once
+                if (!have_fallback) {
+                    State F = R;
+                    bool fok = false;
+                    if (lane == 0) fok = det_fallback(R, F, dfs_slots);
+                    fok = __builtin_amdgcn_readfirstlane((uint32_t)fok) != 0u;
+                    if (!fok) {
+                        if (lane == 0) atomicOr(&g_error_word, kErrLimit);
+                        failed = true;
+                        break;
+                    }
+                    fallback = readlane_state(F, 0u);
+                    have_fallback = true;
                 }
-                fallback = readlane_state(F, 0u);
-                have_fallback = true;
+                S = fallback;
+                ++n_sampler_fallback;
             }
-            S = fallback;
-            ++n_sampler_fallback;
-        }
 
-        const uint64_t t1 = clock64();
-        cyc[0] += t1 - t0;
-        // ---- 2. descend ----------------------------------------------------
-        // Append a child {ex | ..., 0, ez, id} to `parent` (child count nc);
-        // returns its id and its entry's word offset.
-        auto append_child = [&](uint32_t parent, uint32_t nc, uint32_t ex, uint32_t ez,
-                                uint32_t &e_out) -> uint32_t {
-            const uint32_t rec = rec_off(parent);
-            const uint32_t c = n_nodes++;
-            uint32_t blk = parent;
-            if (nc >= kBlockEntries) {
-                blk = W[rec + 1u];
-                if ((nc & (kBlockEntries - 1u)) == 0u) {
-                    const uint32_t ob = nodes_cap + n_ovf++;
-                    if (lane == 0) {
-                        bnext[ob] = kNoBlock;
-                        bnext[blk] = ob;
-                        W[rec + 1u] = ob;
+            const uint64_t t1 = clock64();
+            cyc[0] += t1 - t0;
+            // ---- 2. descend ----------------------------------------------------
+            // Append a child {ex | ..., 0, ez, id} to `parent` (child count nc);
+            // returns its id and its entry's word offset.
+            auto append_child = [&](uint32_t parent, uint32_t nc, uint32_t ex, uint32_t ez,
+                                    uint32_t &e_out) -> uint32_t {
+                const uint32_t rec = rec_off(parent);
+                const uint32_t c = n_nodes++;
+                uint32_t blk = parent;
+                if (nc >= kBlockEntries) {
+                    blk = W[rec + 1u];
+                    if ((nc & (kBlockEntries - 1u)) == 0u) {
+                        const uint32_t ob = nodes_cap + n_ovf++;
+                        if (lane == 0) {
+                            bnext[ob] = kNoBlock;
+                            bnext[blk] = ob;
+                            W[rec + 1u] = ob;
+                        }
+                        blk = ob;
                     }
-                    blk = ob;
                 }
+                const uint32_t e = block_off(blk) + (nc & (kBlockEntries - 1u)) * kEntryWords;
+                if (lane == 0) {
+                    W[e + 0u] = ex;
+                    W[e + 1u] = 0u;
+                    W[e + 2u] = ez;
+                    W[e + 3u] = c;
+                    W[rec + 2u] = nc + 1u;
+                    bnext[c] = kNoBlock;
+                }
+                for (uint32_t k = lane; k < node_words; k += 64u) W[rec_off(c) + k] = k == 1u ? c : 0u;
+                e_out = e;
+                return c;
+            };
+            uint32_t node = 0u, node_n = n_root, depth = 0u, np = 0u, winner = 0u, last_block = 0u;
+            bool term = false, cont = false;
+            if (a.vanilla) {
+                // the world node of this sample among the root's children, by key
+                uint32_t klo, khi;
+                world_key(S, R.m, klo, khi);
+                const uint32_t nr = W[rec_off(0u) + 2u];
+                uint32_t blk = 0u, found_e = 0u;
+                bool found = false;
+                for (uint32_t base = 0; base < nr; base += kBlockEntries) {
+                    const uint32_t eo = block_off(blk) + lane * kEntryWords;
+                    const uint4 ent = *reinterpret_cast<const uint4 *>(W + eo);
+                    const uint64_t hit = __ballot(base + lane < nr && ent.x == klo && ent.z == khi);
+                    if (hit) {
+                        const uint32_t l = (uint32_t)__builtin_ctzll(hit);
+                        node = __builtin_amdgcn_readlane(ent.w, l);
+                        node_n = __builtin_amdgcn_readlane(ent.y, l);
+                        found_e = block_off(blk) + l * kEntryWords;
+                        found = true;
+                        break;
+                    }
+                    if (base + kBlockEntries < nr) blk = bnext[blk];
+                }
+                if (!found) {
+                    node = append_child(0u, nr, klo, khi, found_e);
+                    node_n = 0u;
+                }
+                path_e[np++] = found_e;
+                tree_sync<VALUE>();
             }
-            const uint32_t e = block_off(blk) + (nc & (kBlockEntries - 1u)) * kEntryWords;
-            if (lane == 0) {
-                W[e + 0u] = ex;
-                W[e + 1u] = 0u;
-                W[e + 2u] = ez;
-                W[e + 3u] = c;
-                W[rec + 2u] = nc + 1u;
-                bnext[c] = kNoBlock;
-            }
-            for (uint32_t k = lane; k < node_words; k += 64u) W[rec_off(c) + k] = k == 1u ? c : 0u;
-            e_out = e;
-            return c;
-        };
-        uint32_t node = 0u, node_n = n_root, depth = 0u, np = 0u, winner = 0u, last_block = 0u;
-        bool term = false, cont = false;
-        if (a.vanilla) {
-            // the world node of this sample among the root's children, by key
-            uint32_t klo, khi;
-            world_key(S, R.m, klo, khi);
-            const uint32_t nr = W[rec_off(0u) + 2u];
-            uint32_t blk = 0u, found_e = 0u;
-            bool found = false;
-            for (uint32_t base = 0; base < nr; base += kBlockEntries) {
-                const uint32_t eo = block_off(blk) + lane * kEntryWords;
-                const uint4 ent = *reinterpret_cast<const uint4 *>(W + eo);
-                const uint64_t hit = __ballot(base + lane < nr && ent.x == klo && ent.z == khi);
-                if (hit) {
-                    const uint32_t l = (uint32_t)__builtin_ctzll(hit);
-                    node = __builtin_amdgcn_readlane(ent.w, l);
-                    node_n = __builtin_amdgcn_readlane(ent.y, l);
-                    found_e = block_off(blk) + l * kEntryWords;
-                    found = true;
+            for (;;) {
+                if (term || depth >= a.dmax || np >= kMaxPath - 1u) break;
+                // one round of loads: bitmaps, child count, first 64 children, LN
+                const uint32_t rec = rec_off(node);
+                const uint32_t half = cont ? 36u : 0u;
+                const uint32_t cbw0 = W[rec + 4u + half + (lane >> 1)];
+                const uint32_t cbw1 = lane < 8u ? W[rec + 36u + half + (lane >> 1)]
+                                                : lane == 8u ? W[rec + 3u] : 0u;
+                const uint32_t nchild = W[rec + 2u];
+                const uint4 ent0 = *reinterpret_cast<const uint4 *>(W + rec + node_words + lane * kEntryWords);
+                const float lp = a.ln[node_n];
+                const uint32_t l0 = legal_values(S, lane, tab);
+                const uint32_t l1 = lane < 8u ? legal_values(S, 64u + lane, tab)
+                                              : (lane == 8u && cont) ? 1u : 0u;
+                legal_s[lane] = l0;
+                if (lane < 9u) legal_s[64u + lane] = l1;
+                const uint32_t cb0 = (cbw0 >> ((lane & 1u) * 16u)) & 0xFFFu;
+                const uint32_t cb1 = lane == 8u ? (cbw1 & 1u) : (cbw1 >> ((lane & 1u) * 16u)) & 0xFFFu;
+                const uint32_t u0 = l0 & ~cb0, u1 = l1 & ~cb1;
+                const uint64_t b0 = __ballot(u0 != 0u), b1 = __ballot(u1 != 0u);
+                tree_sync<VALUE>();
+                if (b0 | b1) {
+                    // expansion: the lowest playable key that has no child yet --
+                    // the stop before the guesses after a right guess
+                    uint32_t key, word, bit;
+                    if ((b1 >> 8) & 1u) {
+                        key = kStopKey;
+                        word = 3u;
+                        bit = 1u;
+                    } else {
+                        uint32_t pair, vbits;
+                        if (b0) {
+                            pair = (uint32_t)__builtin_ctzll(b0);
+                            vbits = __builtin_amdgcn_readlane(u0, pair);
+                        } else {
+                            const uint32_t l = (uint32_t)__builtin_ctzll(b1);
+                            vbits = __builtin_amdgcn_readlane(u1, l);
+                            pair = 64u + l;
+                        }
+                        const uint32_t v = (uint32_t)__builtin_ctz(vbits);
+                        key = pair * 12u + v + (cont ? kStopKey + 1u : 0u);
+                        word = 4u + half + (pair >> 1);
+                        bit = 1u << (v + (pair & 1u) * 16u);
+                    }
+                    uint32_t e;
+                    append_child(node, nchild, key | (S.m << 16), 0u, e);
+                    if (lane == 0) W[rec + word] |= bit;
+                    path_e[np++] = e;
+                    last_block = depth;
+                    term = apply_action(S, key, a.cont_mode != 0u, depth, it, tr, a.k0, a.k1, winner,
+                                        cont, tab);
+                    tree_sync<VALUE>();
                     break;
                 }
-                if (base + kBlockEntries < nr) blk = bnext[blk];
-            }
-            if (!found) {
-                node = append_child(0u, nr, klo, khi, found_e);
-                node_n = 0u;
-            }
-            path_e[np++] = found_e;
-            tree_sync<VALUE>();
-        }
-        for (;;) {
-            if (term || depth >= a.dmax || np >= kMaxPath - 1u) break;
-            // one round of loads: bitmaps, child count, first 64 children, LN
-            const uint32_t rec = rec_off(node);
-            const uint32_t half = cont ? 36u : 0u;
-            const uint32_t cbw0 = W[rec + 4u + half + (lane >> 1)];
-            const uint32_t cbw1 = lane < 8u ? W[rec + 36u + half + (lane >> 1)]
-                                            : lane == 8u ? W[rec + 3u] : 0u;
-            const uint32_t nchild = W[rec + 2u];
-            const uint4 ent0 = *reinterpret_cast<const uint4 *>(W + rec + node_words + lane * kEntryWords);
-            const float lp = a.ln[node_n];
-            const uint32_t l0 = legal_values(S, lane, tab);
-            const uint32_t l1 = lane < 8u ? legal_values(S, 64u + lane, tab)
-                                          : (lane == 8u && cont) ? 1u : 0u;
-            legal_s[lane] = l0;
-            if (lane < 9u) legal_s[64u + lane] = l1;
-            const uint32_t cb0 = (cbw0 >> ((lane & 1u) * 16u)) & 0xFFFu;
-            const uint32_t cb1 = lane == 8u ? (cbw1 & 1u) : (cbw1 >> ((lane & 1u) * 16u)) & 0xFFFu;
-            const uint32_t u0 = l0 & ~cb0, u1 = l1 & ~cb1;
-            const uint64_t b0 = __ballot(u0 != 0u), b1 = __ballot(u1 != 0u);
-            tree_sync<VALUE>();
-            if (b0 | b1) {
-                // expansion: the lowest playable key that has no child yet --
-                // the stop before the guesses after a right guess
-                uint32_t key, word, bit;
-                if ((b1 >> 8) & 1u) {
-                    key = kStopKey;
-                    word = 3u;
-                    bit = 1u;
-                } else {
-                    uint32_t pair, vbits;
-                    if (b0) {
-                        pair = (uint32_t)__builtin_ctzll(b0);
-                        vbits = __builtin_amdgcn_readlane(u0, pair);
-                    } else {
-                        const uint32_t l = (uint32_t)__builtin_ctzll(b1);
-                        vbits = __builtin_amdgcn_readlane(u1, l);
-                        pair = 64u + l;
+                // selection: UCT over the playable children, 64 per pass
+                float best_s = -__builtin_inff();
+                uint32_t best_i = 0xFFFFFFFFu, best_e = 0u, best_act = 0u, best_node = 0u, best_n = 0u;
+                uint32_t blk = node;
+                uint4 ent = ent0;
+                for (uint32_t base = 0; base < nchild; base += kBlockEntries) {
+                    if (base > 0u) ent = *reinterpret_cast<const uint4 *>(W + block_off(blk) + lane * kEntryWords);
+                    const uint32_t ci = base + lane;
+                    float sc = -__builtin_inff();
+                    uint32_t idx = 0xFFFFFFFFu;
+                    if (ci < nchild) {
+                        const uint32_t key = ent.x & 0xFFFFu;
+                        const bool after_right = key > kStopKey;
+                        const uint32_t act = after_right ? key - kStopKey - 1u : key;
+                        const uint32_t pr = act / 12u;
+                        const bool playable =
+                            key == kStopKey ? cont
+                                            : after_right == cont && ((legal_s[pr] >> (act - pr * 12u)) & 1u);
+                        if (playable) {
+                            const float n = (float)ent.y;
+                            const float q = __uint_as_float(ent.z) / n;
+                            const float ex = lp / n;
+                            const float u = a.c_uct * sqrtf(ex);
+                            sc = q + u;
+                            idx = ci;
+                        }
                     }
-                    const uint32_t v = (uint32_t)__builtin_ctz(vbits);
-                    key = pair * 12u + v + (cont ? kStopKey + 1u : 0u);
-                    word = 4u + half + (pair >> 1);
-                    bit = 1u << (v + (pair & 1u) * 16u);
+                    wave_argmax(sc, idx);
+                    if (idx != 0xFFFFFFFFu && (best_i == 0xFFFFFFFFu || sc > best_s)) {
+                        const uint32_t wl = idx - base;
+                        best_s = sc;
+                        best_i = idx;
+                        best_e = block_off(blk) + wl * kEntryWords;
+                        best_act = __builtin_amdgcn_readlane(ent.x, wl) & 0xFFFFu;
+                        best_n = __builtin_amdgcn_readlane(ent.y, wl);
+                        best_node = __builtin_amdgcn_readlane(ent.w, wl);
+                    }
+                    if (base + kBlockEntries < nchild) blk = bnext[blk];
                 }
-                uint32_t e;
-                append_child(node, nchild, key | (S.m << 16), 0u, e);
-                if (lane == 0) W[rec + word] |= bit;
-                path_e[np++] = e;
+                node = best_node;
+                node_n = best_n;
+                path_e[np++] = best_e;
                 last_block = depth;
-                term = apply_action(S, key, a.cont_mode != 0u, depth, it, tr, a.k0, a.k1, winner,
+                term = apply_action(S, best_act, a.cont_mode != 0u, depth, it, tr, a.k0, a.k1, winner,
                                     cont, tab);
+                ++depth;
                 tree_sync<VALUE>();
-                break;
             }
-            // selection: UCT over the playable children, 64 per pass
-            float best_s = -__builtin_inff();
-            uint32_t best_i = 0xFFFFFFFFu, best_e = 0u, best_act = 0u, best_node = 0u, best_n = 0u;
-            uint32_t blk = node;
-            uint4 ent = ent0;
-            for (uint32_t base = 0; base < nchild; base += kBlockEntries) {
-                if (base > 0u) ent = *reinterpret_cast<const uint4 *>(W + block_off(blk) + lane * kEntryWords);
-                const uint32_t ci = base + lane;
-                float sc = -__builtin_inff();
-                uint32_t idx = 0xFFFFFFFFu;
-                if (ci < nchild) {
-                    const uint32_t key = ent.x & 0xFFFFu;
-                    const bool after_right = key > kStopKey;
-                    const uint32_t act = after_right ? key - kStopKey - 1u : key;
-                    const uint32_t pr = act / 12u;
-                    const bool playable =
-                        key == kStopKey ? cont
-                                        : after_right == cont && ((legal_s[pr] >> (act - pr * 12u)) & 1u);
-                    if (playable) {
-                        const float n = (float)ent.y;
-                        const float q = __uint_as_float(ent.z) / n;
-                        const float ex = lp / n;
-                        const float u = a.c_uct * sqrtf(ex);
-                        sc = q + u;
-                        idx = ci;
-                    }
-                }
-                wave_argmax(sc, idx);
-                if (idx != 0xFFFFFFFFu && (best_i == 0xFFFFFFFFu || sc > best_s)) {
-                    const uint32_t wl = idx - base;
-                    best_s = sc;
-                    best_i = idx;
-                    best_e = block_off(blk) + wl * kEntryWords;
-                    best_act = __builtin_amdgcn_readlane(ent.x, wl) & 0xFFFFu;
-                    best_n = __builtin_amdgcn_readlane(ent.y, wl);
-                    best_node = __builtin_amdgcn_readlane(ent.w, wl);
-                }
-                if (base + kBlockEntries < nchild) blk = bnext[blk];
+            if (!term && cont) leaf_continue_coin(S, last_block, it, tr, a.k0, a.k1, tab);
+            deepest = np - a.vanilla > deepest ? np - a.vanilla : deepest;
+            cyc[1] += clock64() - t1;
+            // the leaf and its path, for the evaluation and the wins
+            if (lane == 0) {
+                uint4 ps;
+                encode(S, ps.x, ps.y, ps.z, ps.w);
+                leaf_all[wv][b] = ps;
+                np_all[wv][b] = np;
             }
-            node = best_node;
-            node_n = best_n;
-            path_e[np++] = best_e;
-            last_block = depth;
-            term = apply_action(S, best_act, a.cont_mode != 0u, depth, it, tr, a.k0, a.k1, winner,
-                                cont, tab);
-            ++depth;
+            term_mask |= term ? 1u << b : 0u;
+            winners |= (term ? winner : 0u) << (2u * b);
+            // visit counts at once
+            n_root += nplay;
+            if (lane < np) W[path_e[lane] + 1u] += nplay;
             tree_sync<VALUE>();
         }
-        if (!term && cont) leaf_continue_coin(S, last_block, it, tr, a.k0, a.k1, tab);
-        deepest = np - a.vanilla > deepest ? np - a.vanilla : deepest;
+        if (failed) break;
 
         const uint64_t t2 = clock64();
-        cyc[1] += t2 - t1;
-        // ---- 3. evaluate the leaf: playouts, or the value network ---------
-        uint32_t wins0 = 0u, wins1 = 0u, wins2 = 0u, wins3 = 0u;
-        float vals[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-        bool use_vals = false;
-        uint32_t nplay = a.ppl;
-        if (VALUE && !term) {
-            // one row per seat perspective q = lane % 16 < P
-            uint4 ps;
-            encode(S, ps.x, ps.y, ps.z, ps.w);
-            const uint32_t q = lane & 15u;
-            RowFeat rf = q < S.P ? row_features(ps, q) : no_row();
-            float v4[4];
-            vn_eval_tree(vn_ptrs(const_cast<void *>(a.net)), rf, vn_tile, w2_lds, vn_small[0], v4);
-            float v[4];
-#pragma unroll
-            for (uint32_t k = 0; k < 4u; ++k) v[k] = __shfl(v4[k], 0, 64);
-            const float vm = R.m == 0u ? v[0] : R.m == 1u ? v[1] : R.m == 2u ? v[2] : v[3];
-            const float dv = vm - 0.5f;
-            nplay = a.fb_ppl;
-            if (!((dv < 0.0f ? -dv : dv) < a.band)) {
-                use_vals = true;
-                ++n_net;
-#pragma unroll
-                for (uint32_t k = 0; k < 4u; ++k) vals[k] = (float)a.fb_ppl * v[k];
+        // ---- 3. evaluate the pass's leaves: playouts, or the value network --
+        uint32_t play_mask = ((1u << nb) - 1u) & ~term_mask;   // leaves to play out
+        if (VALUE && play_mask) {
+            // rows 4b + q: leaf b, seat perspective q < P
+            const uint32_t r = lane & 15u, lb = r >> 2, q = r & 3u;
+            RowFeat rf = no_row();
+            if (lb < nb && ((play_mask >> lb) & 1u)) {
+                const uint4 ps = leaf_all[wv][lb];
+                if (q < ((ps.x >> 26) & 3u) + 1u) rf = row_features(ps, q);
             }
-        } else if (VALUE) {
-            nplay = a.fb_ppl;
+            float v4[4];
+            vn_eval_tree<kVnTreeRows>(vn_ptrs(const_cast<void *>(a.net)), rf, vn_tile, w2_lds,
+                                      vn_small[0], v4);
+#pragma unroll
+            for (uint32_t b = 0; b < kVnTreeRows / 4u; ++b) {
+                if (!((play_mask >> b) & 1u)) continue;
+                float v[4];
+#pragma unroll
+                for (uint32_t k = 0; k < 4u; ++k) v[k] = __shfl(v4[k], 16 * b, 64);
+                const float vm = R.m == 0u ? v[0] : R.m == 1u ? v[1] : R.m == 2u ? v[2] : v[3];
+                const float dv = vm - 0.5f;
+                if (!((dv < 0.0f ? -dv : dv) < a.band)) {
+                    play_mask &= ~(1u << b);
+                    ++n_net;
+                    if (lane == 0)
+#pragma unroll
+                        for (uint32_t k = 0; k < 4u; ++k) vals[b][k] = (float)a.fb_ppl * v[k];
+                }
+            }
         }
-        if (term) {
-            wins0 = winner == 0u ? nplay : 0u;
-            wins1 = winner == 1u ? nplay : 0u;
-            wins2 = winner == 2u ? nplay : 0u;
-            wins3 = winner == 3u ? nplay : 0u;
-        } else if (!use_vals) {
-            const uint64_t pl = (uint64_t)it * kPhiloxM1;
+        // playouts of the leaves in play_mask, packed: playout g of the pass
+        // is playout g % nplay of leaf g / nplay
+        if (play_mask) {
+            if (lane < 4u * BM) wins_all[wv][lane] = 0u;
+            tree_sync<VALUE>();
             const uint32_t trk1 = tr ^ a.k1;
-            for (uint32_t pb = 0; pb < nplay; pb += 64u) {
-                const uint32_t p = pb + lane;
-                const bool act = p < nplay;
+            for (uint32_t pb = 0; pb < nb * nplay; pb += 64u) {
+                const uint32_t gp = pb + lane;
+                const uint32_t lb = gp / nplay;
+                const bool act = lb < nb && ((play_mask >> lb) & 1u);
+                const uint32_t b_lo = pb / nplay;
+                const uint32_t b_hi = (pb + 63u) / nplay < nb - 1u ? (pb + 63u) / nplay : nb - 1u;
+                if (!((play_mask >> b_lo) & ((2u << (b_hi - b_lo)) - 1u))) continue;
                 uint32_t w = 4u;
                 if (act) {
-                    State s = S;
+                    const uint4 ps = leaf_all[wv][lb];
+                    State s;
+                    decode(ps.x, ps.y, ps.z, ps.w, s);
+                    const uint32_t p = gp - lb * nplay;
+                    const uint64_t pl = (uint64_t)(i0 + lb) * kPhiloxM1;
                     PlayoutKey pk;
                     pk.a = (uint32_t)(pl >> 32) ^ p ^ a.k0;
                     pk.b = (uint32_t)pl;
@@ -782,35 +830,55 @@ mcts_tree_kernel(MctsArgs a)
                         }
                     }
                 }
-                wins0 += (uint32_t)__popcll(__ballot(act && w == 0u));
-                wins1 += (uint32_t)__popcll(__ballot(act && w == 1u));
-                wins2 += (uint32_t)__popcll(__ballot(act && w == 2u));
-                wins3 += (uint32_t)__popcll(__ballot(act && w == 3u));
+                // seat wins of every leaf in this chunk
+                for (uint32_t b = b_lo; b <= b_hi; ++b) {
+                    const bool mine = act && lb == b;
+                    const uint32_t c0 = (uint32_t)__popcll(__ballot(mine && w == 0u));
+                    const uint32_t c1 = (uint32_t)__popcll(__ballot(mine && w == 1u));
+                    const uint32_t c2 = (uint32_t)__popcll(__ballot(mine && w == 2u));
+                    const uint32_t c3 = (uint32_t)__popcll(__ballot(mine && w == 3u));
+                    if (lane == 0) {
+                        wins_all[wv][4u * b + 0u] += c0;
+                        wins_all[wv][4u * b + 1u] += c1;
+                        wins_all[wv][4u * b + 2u] += c2;
+                        wins_all[wv][4u * b + 3u] += c3;
+                    }
+                }
+            }
+            tree_sync<VALUE>();
+            for (uint32_t b = 0; b < nb; ++b) {
+                if (!((play_mask >> b) & 1u)) continue;
+                if (a.leaf_eval) ++n_played;
+                if (lane == 0)
+#pragma unroll
+                    for (uint32_t k = 0; k < 4u; ++k) vals[b][k] = (float)wins_all[wv][4u * b + k];
             }
         }
-
-        if (!term && !use_vals && a.leaf_eval) ++n_played;
-        if (!use_vals) {
-            vals[0] = (float)wins0;
-            vals[1] = (float)wins1;
-            vals[2] = (float)wins2;
-            vals[3] = (float)wins3;
+        for (uint32_t b = 0; b < nb; ++b) {
+            if (!((term_mask >> b) & 1u)) continue;
+            const uint32_t wn = (winners >> (2u * b)) & 3u;
+            if (lane == 0)
+#pragma unroll
+                for (uint32_t k = 0; k < 4u; ++k) vals[b][k] = k == wn ? (float)nplay : 0.0f;
         }
+        tree_sync<VALUE>();
 
         const uint64_t t3 = clock64();
         cyc[2] += t3 - t2;
-        // ---- 4. back-propagation --------------------------------------------
-        n_root += nplay;
-        if (lane < np) {
-            const uint32_t e = path_e[lane];
-            W[e + 1u] += nplay;
-            if (!(a.vanilla && lane == 0u)) {   // a world node's W word holds its key
-                const uint32_t chooser = W[e] >> 16;
-                const float wc = chooser == 0u ? vals[0] : chooser == 1u ? vals[1] : chooser == 2u ? vals[2] : vals[3];
+        // ---- 4. back-propagation: each path gets its leaf's wins, in order --
+        for (uint32_t b = 0; b < nb; ++b) {
+            const uint32_t npb = np_all[wv][b];
+            if (lane < npb && !(a.vanilla && lane == 0u)) {   // a world node's W word holds its key
+                const uint32_t e = path_all[wv][b][lane];
+                // the chooser's value by a computed index: a chain of selects
+                // over the four LDS entries was compiled into branches that
+                // left seat 3's lanes reading seat 2's entry
+                const uint32_t chooser = (W[e] >> 16) & 3u;
+                const float wc = vals[b][chooser];
                 W[e + 2u] = __float_as_uint(__uint_as_float(W[e + 2u]) + wc);
             }
+            tree_sync<VALUE>();
         }
-        tree_sync<VALUE>();
         cyc[3] += clock64() - t3;
     }
 
@@ -989,7 +1057,7 @@ hipError_t launch_mcts(const uint4 *roots, uint32_t n_trees, uint32_t trees_per_
                        uint32_t dmax, float c_uct, uint32_t k0, uint32_t k1, uint32_t tree_base,
                        const float *ln, uint32_t *ws, int32_t *best, uint32_t *kids,
                        uint32_t leaf_eval, float band, uint32_t fb_ppl, const void *net,
-                       uint32_t cont, uint32_t vanilla, hipStream_t st)
+                       uint32_t cont, uint32_t vanilla, uint32_t lpp, hipStream_t st)
 {
     if (n_trees == 0) return hipSuccess;
     MctsArgs a;
@@ -1008,6 +1076,7 @@ hipError_t launch_mcts(const uint4 *roots, uint32_t n_trees, uint32_t trees_per_
     a.sh = mcts_shape(iters, cont, vanilla);
     a.cont_mode = cont;
     a.vanilla = vanilla;
+    a.lpp = lpp;
     a.best = best;
     a.kids = kids;
     a.leaf_eval = leaf_eval;

@@ -339,6 +339,12 @@ __device__ __forceinline__ void vn_stage_small(const VnPtrs &P, VnSmall &sm)
     if (threadIdx.x == 0) sm.b3 = P.master[kOffB3];
 }
 
+// One wavefront scores NR (4, 8 or 16) rows of tree leaves: the lane's rf is
+// row lane % 16 (rows past NR are empty), the first layer streams its
+// weights from L2, its output rows go through `tile` (NR rows) to the second
+// layer, whose weights `w2l` sit in LDS.  v4[i] of the lanes of group g =
+// lane / 16 is the value of row 4g + i.
+template <uint32_t NR>
 __device__ __forceinline__ void vn_eval_tree(const VnPtrs &P, const RowFeat &rf,
                                              uint16_t (*tile)[kVnH + 8],
                                              const uint16_t *w2l, const VnSmall &sm,
@@ -349,19 +355,19 @@ __device__ __forceinline__ void vn_eval_tree(const VnPtrs &P, const RowFeat &rf,
 #pragma unroll
     for (uint32_t s = 0; s < 5u; ++s) xa[s] = feature8(rf, s, g);
     vn_layer_deep<5, kVnIn, 32>(xa, P.w1b, r, g, [&](uint32_t j, const floatx4 &acc) {
-        if (g == 0u) {
+        if (g < NR / 4u) {
             const float b1 = sm.b1[16u * j + r];
 #pragma unroll
             for (uint32_t i = 0; i < 4u; ++i) {
                 const float h = acc[i] + b1;
-                tile[i][16u * j + r] = bf16_bits(h > 0.0f ? h : 0.0f);
+                tile[4u * g + i][16u * j + r] = bf16_bits(h > 0.0f ? h : 0.0f);
             }
         }
     });
     wave_lds_sync();
     bf16x8 ha[8];
 #pragma unroll
-    for (uint32_t s = 0; s < 8u; ++s) ha[s] = load8(&tile[r & 3u][32u * s + 8u * g]);
+    for (uint32_t s = 0; s < 8u; ++s) ha[s] = load8(&tile[r % NR][32u * s + 8u * g]);
     float zpart[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (uint32_t j = 0; j < 16u; ++j) {

@@ -112,8 +112,10 @@ def test_tree_variant_parameters_without_device(lib):
     assert base > 0 and cont > base and van > base
     assert base % 16 == 0 and cont % 16 == 0 and van % 16 == 0
     assert size(max_depth=0) == base and size(max_depth=64) == base
-    for bad in (dict(max_depth=65), dict(max_depth=-1), dict(continue_choice=2), dict(vanilla=3)):
+    for bad in (dict(max_depth=65), dict(max_depth=-1), dict(continue_choice=2), dict(vanilla=3),
+                dict(leaves_per_pass=0), dict(leaves_per_pass=17)):
         assert size(**bad) == 0
+    assert size(leaves_per_pass=16) == base
     mp = D.mcts_params(iterations=10, playouts_per_leaf=4, vanilla=1)
     lib.mcts_search_root_parallel.argtypes = [vp, C.c_int64, C.c_int32, C.POINTER(D.MctsParams),
                                               C.c_uint64, C.c_uint32, vp, C.c_size_t, vp, vp, vp]
