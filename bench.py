@@ -53,9 +53,9 @@ OPS_PER_GUESS = 222
 # scaled by what the same counter reads for a plain 256 MiB device copy
 # (FETCH_SIZE reads half the bytes moved, WRITE_SIZE all of them).  Valid
 # only for the kernel sources it was taken on: reported as null otherwise.
-PROFILED_TRAFFIC = {"fetch_kib": 320.25, "fetch_scale": 2.0, "write_kib": 3584.0,
+PROFILED_TRAFFIC = {"fetch_kib": 317.77, "fetch_scale": 2.0, "write_kib": 3584.0,
                     "write_scale": 1.0,
-                    "sources_sha256": "ddcd7efc27ad5528776f5d00dac6d5a2018987ecf2827abdad9fe4fe14ad6949"}
+                    "sources_sha256": "5af839aa03765d8bac2d385abb356f3564c72e15e138476269769b176456623c"}
 KERNEL_SOURCES = ["paper_2403_10720_amd/csrc/dvc_core.hpp",
                   "paper_2403_10720_amd/csrc/dvc_internal.hpp",
                   "paper_2403_10720_amd/csrc/rollout.hip"]
@@ -99,12 +99,14 @@ SEARCH_DEAL = dict(p_min=2, p_max=4, hand=(0, 0, 4, 4, 3), pile_min=0, pile_max=
                    revealed_max=8, root_draw=1)
 
 
-def batched_search(D, torch, reps=3):
+def batched_search(D, torch, reps=3, leaves_per_pass=1):
     """Batched search: 2048 mixed 2/3/4-player roots, 1024 iterations x 32 playouts,
-    depth 4, one launch; decisions/s from HIP events."""
+    depth 4, one launch; decisions/s from HIP events.  leaves_per_pass 2: two
+    leaves' playouts share each tree's 64 lanes."""
     n, iters, ppl = 2048, 1024, 32
     roots = D.dvc_init_states(n, D.deal_params(**SEARCH_DEAL), 3)
-    mp = D.mcts_params(iterations=iters, playouts_per_leaf=ppl, max_depth=4)
+    mp = D.mcts_params(iterations=iters, playouts_per_leaf=ppl, max_depth=4,
+                       leaves_per_pass=leaves_per_pass)
     ws = torch.empty(D.dvc_mcts_workspace_bytes(n, mp), dtype=torch.uint8, device=roots.device)
     D.mcts_search(roots, mp, 3, workspace=ws, want_children=False)
     torch.cuda.synchronize()
@@ -118,7 +120,9 @@ def batched_search(D, torch, reps=3):
         ms.append(e0.elapsed_time(e1))
     best = min(ms)
     return {"workload": "2048 trees (2-4 players, mid-game, root draw) x 1024 iterations x 32 "
-                        "playouts, depth 4", "ms_per_launch": best,
+                        "playouts, depth 4" + (f", {leaves_per_pass} leaves per pass"
+                                               if leaves_per_pass > 1 else ""),
+            "ms_per_launch": best,
             "decisions_per_s": n / (best / 1e3), "playouts_per_s": n * iters * ppl / (best / 1e3)}
 
 
@@ -307,6 +311,7 @@ def main():
         out["roofline"]["probe_TOPs"] = valu_probe(D, torch)
     if not args.no_search:
         out["batched_search"] = batched_search(D, torch)
+        out["batched_search_leaf_batched"] = batched_search(D, torch, leaves_per_pass=2)
         out["root_parallel_search"] = root_parallel_search(D, torch)
         out["single_tree_search"] = single_tree_search(D, torch)
     if not args.no_cpu:

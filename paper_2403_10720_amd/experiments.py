@@ -27,6 +27,9 @@ GPU thread sweep).
 ppl_autotune(): playouts per leaf of the batched search picked by
 measurement, with its root-move agreement.
 
+leaf_batching(): several leaves evaluated together per pass (playouts
+packed into one wavefront's lanes) on the batched and single-tree searches.
+
 tree_variants(): each of the paper's simplifications switched off (Sec.
 III-A) on the batched workload: time per decision, tree shape and decision
 stability.
@@ -104,6 +107,12 @@ def compare(n_trees=1024, iterations=4096, ppl=64, band=0.05, train_cfg: TrainCo
     stats = mcts_tree_stats(ws, n_trees, mp_val)
     net_leaves = int(stats["net_leaves"].sum())
     played = int(stats["played_leaves"].sum())
+    # the same value search with two leaves per pass: their eight network
+    # rows share one matrix tile
+    mp_val2 = mcts_params(iterations=iterations, playouts_per_leaf=1, max_depth=4, leaf_eval=1,
+                          fallback_band=band, fallback_playouts=ppl, valuenet=net,
+                          leaves_per_pass=2)
+    best_val2, t_val2 = timed_search(roots, mp_val2, seed, ws)
     out = {
         "trees": n_trees, "iterations": iterations, "playouts_per_leaf": ppl, "band": band,
         "root_move_agreement": float((best_val == best_roll).float().mean().item()),
@@ -112,6 +121,10 @@ def compare(n_trees=1024, iterations=4096, ppl=64, band=0.05, train_cfg: TrainCo
         "gpu_s_per_decision_value": t_val / n_trees,
         "speedup": t_roll / t_val,
         "fallback_rate": played / max(1, played + net_leaves),
+        "two_leaves_per_pass": {
+            "root_move_agreement": float((best_val2 == best_roll).float().mean().item()),
+            "agreement_with_one_leaf_per_pass": float((best_val2 == best_val).float().mean().item()),
+            "gpu_s_per_decision": t_val2 / n_trees, "speedup": t_roll / t_val2},
         "value_mse_vs_4096_playouts": mse, "mse_noise_floor": floor,
         "training": train_info,
     }
@@ -223,6 +236,42 @@ def tree_variants(n_roots=512, iterations=1024, ppl=32, seed=3, ref_trees=32):
     return out
 
 
+def leaf_batching(seed=3):
+    """Leaves evaluated together (leaves_per_pass B) on the batched and the
+    single-tree workloads: time per launch, and how often the decisions agree
+    with B = 1 next to how often two B = 1 searches with different seeds
+    agree."""
+    out = {}
+    for name, (n, deal, iters, ppl, sd) in SEARCH_WORKLOADS.items():
+        if "4096" in name:
+            continue
+        roots = dvc_init_states(n, deal_params(**deal), sd)
+        rows = {}
+        ref = ref2 = None
+        for B in (1, 2, 4, 8):
+            if B * ppl > 256:
+                continue
+            mp = mcts_params(iterations=iters, playouts_per_leaf=ppl, max_depth=4, leaves_per_pass=B)
+            ws = torch.empty(dvc_mcts_workspace_bytes(n, mp), dtype=torch.uint8, device=roots.device)
+            mcts_search(roots, mp, sd + 1, workspace=ws, want_children=False)   # warm-up
+            reps = 3 if n > 1 else 5
+            times, best = [], None
+            for _ in range(reps):
+                (best, _), t = _timed(lambda: mcts_search(roots, mp, sd, workspace=ws,
+                                                          want_children=False))
+                times.append(t)
+            times.sort()
+            if B == 1:
+                ref = best
+                ref2, _ = mcts_search(roots, mp, sd + 1000, workspace=ws, want_children=False)
+            rows[f"B{B}"] = {"ms_per_launch": times[len(times) // 2] * 1e3,
+                             "decisions_per_s": n / times[len(times) // 2],
+                             "agreement_with_B1": float((best == ref).float().mean().item())}
+        rows["B1_two_seeds_agree"] = float((ref2 == ref).float().mean().item())
+        out[name] = rows
+    return out
+
+
 SEARCH_WORKLOADS = {
     "single tree, fresh 2-player deal, 2000 x 16": (1, dict(p_min=2, p_max=2, fresh=1, root_draw=1), 2000, 16, 1),
     "batched, 2048 mid-game roots, 1024 x 32": (2048, dict(p_min=2, p_max=4, hand=(0, 0, 4, 4, 3), pile_min=0,
@@ -324,7 +373,7 @@ def main(argv=None):
     import json
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--what", choices=["value", "root-parallel", "phases", "scaling", "ppl",
-                                       "variants", "all"],
+                                       "variants", "batching", "all"],
                     default="all")
     ap.add_argument("--trees", type=int, default=1024)
     ap.add_argument("--iterations", type=int, default=4096)
@@ -343,6 +392,8 @@ def main(argv=None):
         print(json.dumps({"ppl_autotune": ppl_autotune()}), flush=True)
     if args.what in ("scaling", "all"):
         print(json.dumps({"gpu_scaling": gpu_scaling()}), flush=True)
+    if args.what in ("batching", "all"):
+        print(json.dumps({"leaf_batching": leaf_batching()}), flush=True)
     if args.what in ("variants", "all"):
         print(json.dumps({"tree_variants": tree_variants()}), flush=True)
     if args.what in ("phases", "all"):
