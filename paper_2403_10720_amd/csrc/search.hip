@@ -739,6 +739,104 @@ mcts_tree_kernel(MctsArgs a)
             if (!term && cont) leaf_continue_coin(S, last_block, it, tr, a.k0, a.k1, tab);
             deepest = np - a.vanilla > deepest ? np - a.vanilla : deepest;
             cyc[1] += clock64() - t1;
+            if (a.lpp == 1u) {
+                // the sequential search: the leaf is evaluated and backed up
+                // before the next descent
+                const uint64_t t2 = clock64();
+                // ---- 3. evaluate the leaf: playouts, or the value network ---------
+                uint32_t wins0 = 0u, wins1 = 0u, wins2 = 0u, wins3 = 0u;
+                float vals[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+                bool use_vals = false;
+                if (VALUE && !term) {
+                    // one row per seat perspective q = lane % 16 < P
+                    uint4 ps;
+                    encode(S, ps.x, ps.y, ps.z, ps.w);
+                    const uint32_t q = lane & 15u;
+                    RowFeat rf = q < S.P ? row_features(ps, q) : no_row();
+                    float v4[4];
+                    vn_eval_tree<kVnTreeRows>(vn_ptrs(const_cast<void *>(a.net)), rf, vn_tile, w2_lds, vn_small[0], v4);
+                    float v[4];
+        #pragma unroll
+                    for (uint32_t k = 0; k < 4u; ++k) v[k] = __shfl(v4[k], 0, 64);
+                    const float vm = R.m == 0u ? v[0] : R.m == 1u ? v[1] : R.m == 2u ? v[2] : v[3];
+                    const float dv = vm - 0.5f;
+                    if (!((dv < 0.0f ? -dv : dv) < a.band)) {
+                        use_vals = true;
+                        ++n_net;
+        #pragma unroll
+                        for (uint32_t k = 0; k < 4u; ++k) vals[k] = (float)a.fb_ppl * v[k];
+                    }
+                }
+                if (term) {
+                    wins0 = winner == 0u ? nplay : 0u;
+                    wins1 = winner == 1u ? nplay : 0u;
+                    wins2 = winner == 2u ? nplay : 0u;
+                    wins3 = winner == 3u ? nplay : 0u;
+                } else if (!use_vals) {
+                    const uint64_t pl = (uint64_t)it * kPhiloxM1;
+                    const uint32_t trk1 = tr ^ a.k1;
+                    for (uint32_t pb = 0; pb < nplay; pb += 64u) {
+                        const uint32_t p = pb + lane;
+                        const bool act = p < nplay;
+                        uint32_t w = 4u;
+                        if (act) {
+                            State s = S;
+                            PlayoutKey pk;
+                            pk.a = (uint32_t)(pl >> 32) ^ p ^ a.k0;
+                            pk.b = (uint32_t)pl;
+                            pk.gm_lo = 0u;
+                            pk.gm_hi = 0u;
+                            bool over = false;
+                            uint32_t len = 0u;
+                            // the words of step g+1 do not depend on the game, so
+                            // they are computed while step g runs (one wavefront per
+                            // tree has no other wavefront to hide latencies behind)
+                            Words wd = step_words(pk, trk1, a.k0, a.k1);
+                            next_step(pk);
+                            while (!over) {
+                                const Words wn = step_words(pk, trk1, a.k0, a.k1);
+                                next_step(pk);
+                                over = guess_step(s, wd, w, tab);
+                                wd = wn;
+                                if (++len >= kMaxGuesses && !over) {
+                                    atomicOr(&g_error_word, kErrLimit);
+                                    over = true;
+                                    w = 4u;
+                                }
+                            }
+                        }
+                        wins0 += (uint32_t)__popcll(__ballot(act && w == 0u));
+                        wins1 += (uint32_t)__popcll(__ballot(act && w == 1u));
+                        wins2 += (uint32_t)__popcll(__ballot(act && w == 2u));
+                        wins3 += (uint32_t)__popcll(__ballot(act && w == 3u));
+                    }
+                }
+
+                if (!term && !use_vals && a.leaf_eval) ++n_played;
+                if (!use_vals) {
+                    vals[0] = (float)wins0;
+                    vals[1] = (float)wins1;
+                    vals[2] = (float)wins2;
+                    vals[3] = (float)wins3;
+                }
+
+                const uint64_t t3 = clock64();
+                cyc[2] += t3 - t2;
+                // ---- 4. back-propagation --------------------------------------------
+                n_root += nplay;
+                if (lane < np) {
+                    const uint32_t e = path_e[lane];
+                    W[e + 1u] += nplay;
+                    if (!(a.vanilla && lane == 0u)) {   // a world node's W word holds its key
+                        const uint32_t chooser = W[e] >> 16;
+                        const float wc = chooser == 0u ? vals[0] : chooser == 1u ? vals[1] : chooser == 2u ? vals[2] : vals[3];
+                        W[e + 2u] = __float_as_uint(__uint_as_float(W[e + 2u]) + wc);
+                    }
+                }
+                tree_sync<VALUE>();
+                cyc[3] += clock64() - t3;
+                continue;
+            }
             // the leaf and its path, for the evaluation and the wins
             if (lane == 0) {
                 uint4 ps;
@@ -754,6 +852,7 @@ mcts_tree_kernel(MctsArgs a)
             tree_sync<VALUE>();
         }
         if (failed) break;
+        if (a.lpp == 1u) continue;
 
         const uint64_t t2 = clock64();
         // ---- 3. evaluate the pass's leaves: playouts, or the value network --
