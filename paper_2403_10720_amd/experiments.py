@@ -338,19 +338,22 @@ def gpu_scaling(waves=(1, 4, 16, 64, 256, 1024, 2048, 4096, 8192), games_per_lan
 
 def ppl_autotune(n_trees=2048, iterations=1024, ppls=(4, 8, 16, 32, 64, 128), seed=3,
                  tolerance=0.02):
-    """Playouts per leaf for the batched search, chosen by measurement: every
-    candidate is timed on the batched workload and its decisions compared with
-    the 32-playout search; the pick is the fastest candidate whose agreement
-    with it is within `tolerance` of what the 32-playout search reaches with
-    itself under another seed.  Parity and the headline stay at 32."""
+    """Playouts per leaf and leaves per pass for the batched search, chosen by
+    measurement: every candidate (ppl, B), with B leaves per pass up to 64
+    playouts per pass, is timed on the batched workload and its decisions
+    compared with the sequential 32-playout search; the pick is the fastest
+    candidate whose agreement with it is within `tolerance` of what the
+    32-playout search reaches with itself under another seed.  Parity and the
+    headline stay at 32 playouts, one leaf per pass."""
     roots = dvc_init_states(n_trees, deal_params(**SEARCH_WORKLOADS[
         "batched, 2048 mid-game roots, 1024 x 32"][1]), seed)
     ws = torch.empty(max(dvc_mcts_workspace_bytes(n_trees, mcts_params(iterations=iterations,
                                                                        playouts_per_leaf=p))
                          for p in ppls), dtype=torch.uint8, device=roots.device)
 
-    def search(ppl, sd):
-        mp = mcts_params(iterations=iterations, playouts_per_leaf=ppl, max_depth=4)
+    def search(ppl, sd, B=1):
+        mp = mcts_params(iterations=iterations, playouts_per_leaf=ppl, max_depth=4,
+                         leaves_per_pass=B)
         return _timed(lambda: mcts_search(roots, mp, sd, workspace=ws, want_children=False))
 
     (ref, _), _ = search(32, seed)
@@ -358,10 +361,14 @@ def ppl_autotune(n_trees=2048, iterations=1024, ppls=(4, 8, 16, 32, 64, 128), se
     ceiling = float((ref == ref2).float().mean().item())
     rows = []
     for ppl in ppls:
-        search(ppl, seed + 1)                       # warm
-        (best, _), t = search(ppl, seed + 1)
-        rows.append({"playouts_per_leaf": ppl, "decisions_per_s": n_trees / t,
-                     "agreement_with_32": float((best == ref).float().mean().item())})
+        for B in (1, 2, 4, 8, 16):
+            if B > 1 and B * ppl > 64:
+                continue
+            search(ppl, seed + 1, B)                    # warm
+            (best, _), t = search(ppl, seed + 1, B)
+            rows.append({"playouts_per_leaf": ppl, "leaves_per_pass": B,
+                         "decisions_per_s": n_trees / t,
+                         "agreement_with_32": float((best == ref).float().mean().item())})
     ok = [r for r in rows if r["agreement_with_32"] >= ceiling - tolerance]
     pick = max(ok, key=lambda r: r["decisions_per_s"]) if ok else None
     return {"trees": n_trees, "iterations": iterations, "self_agreement_32": ceiling,
