@@ -247,3 +247,20 @@ def test_valu_probe(dvc):
     assert np.array_equal(sink.cpu().numpy().view(np.uint32), want)
     with pytest.raises(dvc.DvcError):
         dvc.dvc_probe_valu(6, 2, 3, sink)
+
+
+@pytest.mark.parametrize("variant", [4, 6])
+@pytest.mark.parametrize("ppl", [1, 3, 64, 100, 256, 300])
+def test_rollout_seat_wins_overwrite_the_table(orc, dvc, variant, ppl):
+    """Without accumulate the seat-win table is overwritten (zeroed, then
+    added to): a table full of garbage beforehand must not show."""
+    po = orc.deal_params(p_min=2, p_max=4, pile_min=0, pile_max=16, revealed_max=8)
+    n = 777
+    S = orc.init_states(n, po, seed=12)
+    ref = _rollout_ref(orc, S, ppl, 4, 3, 11)
+    sw = torch.full((n, 4), 0x5A5A5A5A, dtype=torch.int32, device="cuda")
+    w, ln, sw2 = dvc.dvc_rollout(dev_states(S), ppl, 4, 3, 11, seat_wins=sw, variant=variant)
+    torch.cuda.synchronize()
+    assert dvc.dvc_check() == 0
+    assert np.array_equal(sw.cpu().numpy().view(np.uint32), ref[2])
+    assert np.array_equal(w.cpu().numpy(), ref[0]) and np.array_equal(ln.cpu().numpy(), ref[1])
