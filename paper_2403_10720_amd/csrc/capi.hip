@@ -280,7 +280,7 @@ int dvc_rollout_autotune(const dvc_state_t *leaves, int64_t n_leaves, int32_t pp
     hipStream_t st = (hipStream_t)stream;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
-        if (e0) hipEventDestroy(e0);
+        if (e0) (void)hipEventDestroy(e0);   // cleanup: the failure is already reported
         return DVC_EHIP;
     }
     int status = DVC_OK;
@@ -308,8 +308,8 @@ int dvc_rollout_autotune(const dvc_state_t *leaves, int64_t n_leaves, int32_t pp
             have = true;
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);   // the timing is done; a failure here changes nothing
+    (void)hipEventDestroy(e1);
     if (status != DVC_OK) return status;
     {
         std::lock_guard<std::mutex> lock(g_tune_mutex);
