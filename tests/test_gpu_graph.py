@@ -55,12 +55,18 @@ def test_graph_rollout_step(dvc):
     assert dvc.dvc_check() == 0
 
 
-def test_graph_batched_search(dvc):
+@pytest.mark.parametrize("kw", [dict(), dict(leaves_per_pass=2, playouts_per_leaf=32),
+                                dict(continue_choice=1, max_depth=0, vanilla=1)])
+def test_graph_batched_search(dvc, kw):
+    """A captured search (sequential, leaf-batched, un-simplified variants)
+    replays to the eager result every time."""
     n = 64
     roots = dvc.dvc_init_states(n, dvc.deal_params(p_min=2, p_max=4, hand=(0, 0, 4, 4, 3),
                                                    pile_min=0, pile_max=16, revealed_max=8,
                                                    root_draw=1), 3)
-    mp = dvc.mcts_params(iterations=256, playouts_per_leaf=16, max_depth=4)
+    args = dict(iterations=256, playouts_per_leaf=16, max_depth=4)
+    args.update(kw)
+    mp = dvc.mcts_params(**args)
     ws = torch.empty(dvc.dvc_mcts_workspace_bytes(n, mp), dtype=torch.uint8, device="cuda")
     best = torch.empty(n, dtype=torch.int32, device="cuda")
     kids = torch.empty((n, 864, 3), dtype=torch.int32, device="cuda")
