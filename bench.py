@@ -177,9 +177,18 @@ def cpu_baseline(states_np, threads):
                                 want_length=False)
     dt = time.perf_counter() - t0
     n = states_np.shape[0] * PPL
+    # the single-tree search (one fresh two-player deal, 2000 iterations x 16
+    # playouts), one thread, as the GPU figure next to it
+    root = oracle.init_states(1, oracle.deal_params(p_min=2, p_max=2, fresh=1, root_draw=1), 1)
+    t1 = time.perf_counter()
+    oracle.mcts_search(root, oracle.mcts_params(iterations=2000, playouts_per_leaf=16, max_depth=4),
+                       1, 0)
+    dt1 = time.perf_counter() - t1
     return {"value": n / dt, "unit": "playouts/s", "cores": threads, "kind": "oracle",
             "sample": f"{states_np.shape[0]} leaves x {PPL} playouts (the full batch), "
-                      f"{threads} threads, {dt:.2f} s"}
+                      f"{threads} threads, {dt:.2f} s",
+            "single_tree_ms_per_decision": dt1 * 1e3,
+            "single_tree_sample": "1 fresh 2-player deal, 2000 iterations x 16 playouts, 1 thread"}
 
 
 def valu_probe(D, torch, iters=4096):
