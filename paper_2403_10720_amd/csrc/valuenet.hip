@@ -10,8 +10,9 @@
 // Products use v_mfma_f32_16x16x32_bf16 with bfloat16 operands and float32
 // accumulation.  A wavefront owns 16 rows: it encodes its features straight
 // into the A operand, runs both layers, and (training) back-propagates the
-// data gradient through layer 2; the weight gradients are a second kernel
-// that contracts the stored activations over the batch; Adam a third.
+// data gradient through layer 2.  A second kernel contracts the stored
+// activations over the batch into the weight gradients (and sums the bias
+// gradients and the loss); a third takes the Adam step of the weights.
 //
 // Net blob (device, caller-owned, dvc_valuenet_bytes()):
 //   u32 header[64]; float master[NPAD], m[NPAD], v[NPAD];
@@ -209,6 +210,18 @@ __device__ __forceinline__ floatx4 mfma16(bf16x8 a, bf16x8 b, floatx4 c)
 //   A[r][8g..8g+7], B[8g..8g+7][r] (8 consecutive k of one column), and
 //   D[4g+i][r] for i < 4.
 // ---------------------------------------------------------------------------
+// Training activations X^T, H1^T, dH1^T and dH2^T (feature f, batch row b;
+// batch K a multiple of 32) are stored as ready-made operands of the weight
+// gradient products: the 16 x 32 block (features 16T.., rows 32s..) is one
+// contiguous kilobyte in lane order, lane 16g + r holding feature 16T + r,
+// rows 32s + 8g .. + 7.  An operand load is then one contiguous kilobyte
+// rather than 16 rows a batch apart.
+__device__ __forceinline__ size_t vn_act_idx(uint32_t f, uint32_t b, uint32_t K)
+{
+    return ((((size_t)(f >> 4) * (K >> 5) + (b >> 5)) * 64u + ((b >> 3) & 3u) * 16u + (f & 15u))
+            << 3) + (b & 7u);
+}
+
 struct VnRowsArgs {
     const void *net;
     const uint4 *states;
@@ -217,9 +230,10 @@ struct VnRowsArgs {
     uint32_t n_rows;          // rows in this launch
     uint32_t n_data, perm_a, perm_b, row_base;   // training: row i is data[(a*(base+i)+b) % n_data]
     float *v_out;             // inference output (or null)
-    // training outputs (feature-major, rows contiguous), bf16
+    // training outputs (bf16, in the fragment layout of vn_act_idx)
     uint16_t *xt, *h1t, *dh1t, *dh2t;
-    float *part;              // per wave: [loss, db3, dw3[256], db2[256], db1[256]]
+    float *part;              // per 16-row tile, column-major: part[c * tiles + tile] for the
+                              // columns c of [loss, db3, dw3[256], db2[256], db1[256]]
     float inv_batch;
 };
 
@@ -432,24 +446,65 @@ __global__ void __launch_bounds__(64) vn_infer_kernel(const void *net, const uin
 }
 
 constexpr uint32_t kPartWords = 2u + 3u * 256u;   // loss, db3, dw3[256], db2[256], db1[256]
+// weight-gradient output tiles of 32 x 32: dW2 (256 x 256) then dW1 (256 x 160)
+constexpr uint32_t kVnTilesW2 = 64u, kVnTilesW1 = 40u, kVnGradTiles = kVnTilesW2 + kVnTilesW1;
+constexpr uint32_t kVnMaxSlices = 8u;   // batch slices of the weight-gradient products
 
 // Training rows, four wavefronts per 16-row tile: wavefront w computes output
 // columns 64w..64w+63 of every layer (a quarter of each weight matrix), the
 // tiles of activations and gradients being shared through LDS; z sums the
-// four quarters' partial dot products in wavefront order.
+// four quarters' partial dot products in wavefront order.  Every weight
+// fragment, bias and label a wavefront needs is requested a stage ahead of
+// its use (the first layer's before the features are built, each later
+// layer's while the previous layer's products run), so the memory latency is
+// paid a few times per workgroup rather than once per column tile.
+// Workgroups are dealt to the XCDs in turn; with a multiple of 8 tiles,
+// workgroup b takes tile (b % 8) * tiles / 8 + b / 8, so that each XCD writes
+// one contiguous eighth of the batch: the slice of the batch the weight
+// gradient kernel later reads on that XCD.
+__device__ __forceinline__ uint32_t vn_train_row(const VnRowsArgs &a, uint32_t row)
+{
+    return (uint32_t)(((uint64_t)a.perm_a * (a.row_base + row) + a.perm_b) % a.n_data);
+}
+
 __global__ void __launch_bounds__(256) vn_rows4_kernel(VnRowsArgs a)
 {
     __shared__ __attribute__((aligned(16))) uint16_t hs[16][kVnH + 8];   // h1, then dh2 tile (bf16)
     __shared__ float zred[4][16];
     const VnPtrs P = vn_ptrs(const_cast<void *>(a.net));
     const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6, r = lane & 15u, g = lane >> 4;
-    const uint32_t row0 = blockIdx.x * 16u;
+    const uint32_t nb = gridDim.x, b = blockIdx.x;
+    const uint32_t tb = nb % 8u == 0u ? (b % 8u) * (nb / 8u) + b / 8u : b;
+    const uint32_t row0 = tb * 16u;
     const uint32_t myrow = row0 + r;
     const bool has = myrow < a.n_rows;
-    uint32_t src = myrow;
-    if (has) src = (uint32_t)(((uint64_t)a.perm_a * (a.row_base + myrow) + a.perm_b) % a.n_data);
+
+    // first-layer weights, biases, output weights and labels, requested first
+    bf16x8 w1f[4][5];
+#pragma unroll
+    for (uint32_t jj = 0; jj < 4u; ++jj)
+#pragma unroll
+        for (uint32_t s = 0; s < 5u; ++s)
+            w1f[jj][s] = load8(P.w1b + (((4u * wv + jj) * 5u + s) * 64u + lane) * 8u);
+    float b1v[4], b2v[4], w3v[4];
+#pragma unroll
+    for (uint32_t jj = 0; jj < 4u; ++jj) {
+        const uint32_t col = 16u * (4u * wv + jj) + r;
+        b1v[jj] = P.master[kOffB1 + col];
+        b2v[jj] = P.master[kOffB2 + col];
+        w3v[jj] = bf16_to_f(P.w3b[col]);
+    }
+    const float b3 = P.master[kOffB3];
+    float yv[4];
+#pragma unroll
+    for (uint32_t i = 0; i < 4u; ++i) {
+        const uint32_t row = row0 + 4u * g + i;
+        yv[i] = row < a.n_rows ? a.labels[vn_train_row(a, row)] : 0.0f;
+    }
+
     RowFeat rf;
     if (has) {
+        const uint32_t src = vn_train_row(a, myrow);
         rf = row_features(a.states[src], a.persp[src]);
     } else {
         rf.ok = false;
@@ -461,30 +516,40 @@ __global__ void __launch_bounds__(256) vn_rows4_kernel(VnRowsArgs a)
     bf16x8 xa[5];
 #pragma unroll
     for (uint32_t s = 0; s < 5u; ++s) xa[s] = feature8(rf, s, g);
+    floatx4 acc1[4];
+#pragma unroll
+    for (uint32_t jj = 0; jj < 4u; ++jj) {
+        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (uint32_t s = 0; s < 5u; ++s) acc = mfma16(xa[s], w1f[jj][s], acc);
+        acc1[jj] = acc;
+    }
+    // second-layer weights, requested while the first layer's products run
+    bf16x8 w2f[4][8];
+#pragma unroll
+    for (uint32_t jj = 0; jj < 4u; ++jj)
+#pragma unroll
+        for (uint32_t s = 0; s < 8u; ++s)
+            w2f[jj][s] = load8(P.w2b + (((4u * wv + jj) * 8u + s) * 64u + lane) * 8u);
     if (has) {
         // X^T (internal feature order) for the weight gradient, feature
         // blocks split over the wavefronts
         for (uint32_t s = wv; s < 5u; s += 4u) {
-            const uint32_t b = feature_word(rf, s) >> (8u * g);
+            const uint32_t fb = feature_word(rf, s) >> (8u * g);
 #pragma unroll
             for (uint32_t i = 0; i < 8u; ++i)
-                a.xt[(size_t)(32u * s + 8u * g + i) * a.n_rows + myrow] =
-                    ((b >> i) & 1u) ? (uint16_t)0x3F80u : (uint16_t)0u;
+                a.xt[vn_act_idx(32u * s + 8u * g + i, myrow, a.n_rows)] =
+                    ((fb >> i) & 1u) ? (uint16_t)0x3F80u : (uint16_t)0u;
         }
     }
     uint32_t h1pos = 0u;   // bit 4jj+i: h1 of row 4g+i, column 16(4wv+jj)+r is positive
 #pragma unroll
     for (uint32_t jj = 0; jj < 4u; ++jj) {
         const uint32_t j = 4u * wv + jj;
-        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (uint32_t s = 0; s < 5u; ++s)
-            acc = mfma16(xa[s], load8(P.w1b + ((j * 5u + s) * 64u + lane) * 8u), acc);
-        const float b = P.master[kOffB1 + 16u * j + r];
         uint16_t hq[4];
 #pragma unroll
         for (uint32_t i = 0; i < 4u; ++i) {
-            const float h = acc[i] + b;
+            const float h = acc1[jj][i] + b1v[jj];
             hq[i] = bf16_bits(h > 0.0f ? h : 0.0f);
             hs[4u * g + i][16u * j + r] = hq[i];
             h1pos |= (uint32_t)(h > 0.0f) << (4u * jj + i);
@@ -493,7 +558,7 @@ __global__ void __launch_bounds__(256) vn_rows4_kernel(VnRowsArgs a)
         if (rr + 3u < a.n_rows) {
             const uint2 packed = make_uint2((uint32_t)hq[0] | ((uint32_t)hq[1] << 16),
                                             (uint32_t)hq[2] | ((uint32_t)hq[3] << 16));
-            *reinterpret_cast<uint2 *>(a.h1t + (size_t)(16u * j + r) * a.n_rows + rr) = packed;
+            *reinterpret_cast<uint2 *>(a.h1t + vn_act_idx(16u * j + r, rr, a.n_rows)) = packed;
         }
     }
     __syncthreads();
@@ -502,22 +567,30 @@ __global__ void __launch_bounds__(256) vn_rows4_kernel(VnRowsArgs a)
     bf16x8 ha[8];
 #pragma unroll
     for (uint32_t s = 0; s < 8u; ++s) ha[s] = load8(&hs[r][32u * s + 8u * g]);
+    floatx4 acc2[4];
+#pragma unroll
+    for (uint32_t jj = 0; jj < 4u; ++jj) {
+        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (uint32_t s = 0; s < 8u; ++s) acc = mfma16(ha[s], w2f[jj][s], acc);
+        acc2[jj] = acc;
+    }
+    // transposed second-layer weights for the data gradient, requested now
+    bf16x8 w2tf[4][8];
+#pragma unroll
+    for (uint32_t jj = 0; jj < 4u; ++jj)
+#pragma unroll
+        for (uint32_t s = 0; s < 8u; ++s)
+            w2tf[jj][s] = load8(P.w2tb + (((4u * wv + jj) * 8u + s) * 64u + lane) * 8u);
     floatx4 h2[4];
     float zpart[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (uint32_t jj = 0; jj < 4u; ++jj) {
-        const uint32_t j = 4u * wv + jj;
-        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (uint32_t s = 0; s < 8u; ++s)
-            acc = mfma16(ha[s], load8(P.w2b + ((j * 8u + s) * 64u + lane) * 8u), acc);
-        const float b = P.master[kOffB2 + 16u * j + r];
-        const float w3 = bf16_to_f(P.w3b[16u * j + r]);
 #pragma unroll
         for (uint32_t i = 0; i < 4u; ++i) {
-            const float h = acc[i] + b;
+            const float h = acc2[jj][i] + b2v[jj];
             h2[jj][i] = bf16_round(h > 0.0f ? h : 0.0f);
-            zpart[i] += h2[jj][i] * w3;
+            zpart[i] += h2[jj][i] * w3v[jj];
         }
     }
 #pragma unroll
@@ -529,7 +602,6 @@ __global__ void __launch_bounds__(256) vn_rows4_kernel(VnRowsArgs a)
         for (uint32_t i = 0; i < 4u; ++i) zred[wv][4u * g + i] = zpart[i];
     }
     __syncthreads();   // zred complete; every wavefront has read h1 from hs
-    const float b3 = P.master[kOffB3];
     float v4[4], dz[4], err2 = 0.0f;
 #pragma unroll
     for (uint32_t i = 0; i < 4u; ++i) {
@@ -539,14 +611,15 @@ __global__ void __launch_bounds__(256) vn_rows4_kernel(VnRowsArgs a)
         const uint32_t row = row0 + lr;
         float d = 0.0f;
         if (row < a.n_rows) {
-            const uint32_t sr = (uint32_t)(((uint64_t)a.perm_a * (a.row_base + row) + a.perm_b) % a.n_data);
-            const float e = v4[i] - a.labels[sr];
+            const float e = v4[i] - yv[i];
             err2 += e * e;
             d = 2.0f * e * a.inv_batch * v4[i] * (1.0f - v4[i]);
         }
         dz[i] = d;
     }
-    float *part = a.part + (size_t)blockIdx.x * kPartWords;
+    // this tile's partials, one column of stride gridDim.x each
+    float *part = a.part + tb;
+    const size_t pst = nb;
     if (wv == 0u) {
         float l4 = r == 0u ? err2 : 0.0f, d3 = r == 0u ? dz[0] + dz[1] + dz[2] + dz[3] : 0.0f;
         for (int off = 1; off < 64; off <<= 1) {
@@ -555,7 +628,7 @@ __global__ void __launch_bounds__(256) vn_rows4_kernel(VnRowsArgs a)
         }
         if (lane == 0) {
             part[0] = l4;
-            part[1] = d3;
+            part[pst] = d3;
         }
     }
 
@@ -563,7 +636,7 @@ __global__ void __launch_bounds__(256) vn_rows4_kernel(VnRowsArgs a)
 #pragma unroll
     for (uint32_t jj = 0; jj < 4u; ++jj) {
         const uint32_t col = 16u * (4u * wv + jj) + r;
-        const float w3 = bf16_to_f(P.w3b[col]);
+        const float w3 = w3v[jj];
         float dw3 = 0.0f, db2 = 0.0f;
         uint16_t dq[4];
 #pragma unroll
@@ -578,15 +651,15 @@ __global__ void __launch_bounds__(256) vn_rows4_kernel(VnRowsArgs a)
         if (rr + 3u < a.n_rows) {
             const uint2 packed = make_uint2((uint32_t)dq[0] | ((uint32_t)dq[1] << 16),
                                             (uint32_t)dq[2] | ((uint32_t)dq[3] << 16));
-            *reinterpret_cast<uint2 *>(a.dh2t + (size_t)col * a.n_rows + rr) = packed;
+            *reinterpret_cast<uint2 *>(a.dh2t + vn_act_idx(col, rr, a.n_rows)) = packed;
         }
         dw3 += __shfl_xor(dw3, 16, 64);
         dw3 += __shfl_xor(dw3, 32, 64);
         db2 += __shfl_xor(db2, 16, 64);
         db2 += __shfl_xor(db2, 32, 64);
         if (g == 0u) {
-            part[2u + col] = dw3;
-            part[2u + 256u + col] = db2;
+            part[(2u + col) * pst] = dw3;
+            part[(2u + 256u + col) * pst] = db2;
         }
     }
     __syncthreads();   // dh2 tile complete
@@ -595,19 +668,22 @@ __global__ void __launch_bounds__(256) vn_rows4_kernel(VnRowsArgs a)
     bf16x8 da[8];
 #pragma unroll
     for (uint32_t s = 0; s < 8u; ++s) da[s] = load8(&hs[r][32u * s + 8u * g]);
+    floatx4 acc3[4];
+#pragma unroll
+    for (uint32_t jj = 0; jj < 4u; ++jj) {
+        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (uint32_t s = 0; s < 8u; ++s) acc = mfma16(da[s], w2tf[jj][s], acc);
+        acc3[jj] = acc;
+    }
 #pragma unroll
     for (uint32_t jj = 0; jj < 4u; ++jj) {
         const uint32_t col = 16u * (4u * wv + jj) + r;
-        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-        const uint32_t j = 4u * wv + jj;
-#pragma unroll
-        for (uint32_t s = 0; s < 8u; ++s)
-            acc = mfma16(da[s], load8(P.w2tb + ((j * 8u + s) * 64u + lane) * 8u), acc);
         float db1 = 0.0f;
         uint16_t dq[4];
 #pragma unroll
         for (uint32_t i = 0; i < 4u; ++i) {
-            const float d = ((h1pos >> (4u * jj + i)) & 1u) ? acc[i] : 0.0f;
+            const float d = ((h1pos >> (4u * jj + i)) & 1u) ? acc3[jj][i] : 0.0f;
             dq[i] = bf16_bits(d);
             db1 += bf16_to_f(dq[i]);
         }
@@ -615,87 +691,35 @@ __global__ void __launch_bounds__(256) vn_rows4_kernel(VnRowsArgs a)
         if (rr + 3u < a.n_rows) {
             const uint2 packed = make_uint2((uint32_t)dq[0] | ((uint32_t)dq[1] << 16),
                                             (uint32_t)dq[2] | ((uint32_t)dq[3] << 16));
-            *reinterpret_cast<uint2 *>(a.dh1t + (size_t)col * a.n_rows + rr) = packed;
+            *reinterpret_cast<uint2 *>(a.dh1t + vn_act_idx(col, rr, a.n_rows)) = packed;
         }
         db1 += __shfl_xor(db1, 16, 64);
         db1 += __shfl_xor(db1, 32, 64);
-        if (g == 0u) part[2u + 512u + col] = db1;
+        if (g == 0u) part[(2u + 512u + col) * pst] = db1;
     }
 }
 
-// Weight gradient C[m][n] = sum_k AT[m][k] BT[n][k] over the batch (k), one
-// 16x16 output tile and one slice of the batch per wavefront (split K, so
-// that many wavefronts stream the activations at once); slice s writes its
-// partial tile to out + s * slice_stride.  AT, BT feature-major, rows
-// contiguous, row length K; the slice length is a multiple of 32.
-__global__ void __launch_bounds__(64) vn_wgrad_kernel(const uint16_t *at, const uint16_t *bt,
-                                                       uint32_t K, uint32_t k_slice, float *out,
-                                                       uint32_t ldo, uint32_t ntiles,
-                                                       uint32_t tiles, uint32_t slice_stride)
-{
-    const uint32_t lane = threadIdx.x, r = lane & 15u, g = lane >> 4;
-    const uint32_t tile = blockIdx.x % tiles, slice = blockIdx.x / tiles;
-    const uint32_t mt = tile / ntiles, nt = tile % ntiles;
-    const uint32_t kb = slice * k_slice;
-    const uint16_t *ap = at + (size_t)(16u * mt + r) * K + kb + 8u * g;
-    const uint16_t *bp = bt + (size_t)(16u * nt + r) * K + kb + 8u * g;
-    floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-    for (uint32_t k0 = 0; k0 < k_slice; k0 += 32u) acc = mfma16(load8(ap + k0), load8(bp + k0), acc);
-    float *o = out + (size_t)slice * slice_stride;
-#pragma unroll
-    for (uint32_t i = 0; i < 4u; ++i) o[(size_t)(16u * mt + 4u * g + i) * ldo + 16u * nt + r] = acc[i];
-}
+// Adam (Kingma and Ba, 2015) for parameter k (canonical order) with gradient
+// gk, on the float32 master weight and moments; the bf16 shadow the products
+// read is refreshed from the updated weight.  `p` is the internal feature
+// index of a W1 weight (its column in the shadow), unused otherwise.
+struct VnAdam {
+    float lr, beta1, beta2, eps, c1, c2;
+};
 
-// Sum of the per-wavefront partials (loss, bias gradients, w3 gradient): one
-// wavefront per column, lane l adding partials l, l+64, ... in order, then a
-// fixed butterfly across the lanes, so a step is deterministic.
-__global__ void __launch_bounds__(256) vn_partsum_kernel(const float *part, uint32_t n_parts,
-                                                          float *red)
+__device__ __forceinline__ void vn_adam_one(const VnPtrs &P, const VnAdam &h, uint32_t k,
+                                            uint32_t p, float gk, float *grad_out)
 {
-    const uint32_t col = blockIdx.x * 4u + (threadIdx.x >> 6), lane = threadIdx.x & 63u;
-    if (col >= kPartWords) return;
-    float acc = 0.0f;
-    for (uint32_t w = lane; w < n_parts; w += 64u) acc += part[(size_t)w * kPartWords + col];
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-    if (lane == 0u) red[col] = acc;
-}
-
-// Adam (Kingma and Ba, 2015) on the float32 master weights, with the bf16
-// shadows of the updated weights refreshed in the same pass.  `red` holds the
-// summed partials (loss, db3, dw3, db2, db1).
-__global__ void vn_adam_kernel(void *net, const float *grad, uint32_t slices, const float *red,
-                               float lr, float beta1, float beta2, float eps, float c1, float c2,
-                               float inv_batch, float *grad_out, float *loss_out)
-{
-    VnPtrs P = vn_ptrs(net);
-    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k == 0u && loss_out) *loss_out = red[0] * inv_batch;
-    if (k >= kVnParams) return;
-    float gk;
-    if (k < kOffB1 || (k >= kOffW2 && k < kOffB2)) {
-        // weight gradients: the batch slices' partial sums, in slice order
-        // (the W1 gradient is laid out in the internal feature order)
-        const uint32_t kg = k < kOffB1 ? (k / kVnIn) * kVnIn + vn_perm(k % kVnIn) : k;
-        gk = grad[kg];
-        for (uint32_t sl = 1; sl < slices; ++sl) gk += grad[(size_t)sl * kVnPad + kg];
-    } else {
-        const uint32_t idx = k == kOffB3 ? 1u
-                           : k >= kOffW3 ? 2u + (k - kOffW3)
-                           : k >= kOffB2 ? 2u + 256u + (k - kOffB2)
-                                         : 2u + 512u + (k - kOffB1);
-        gk = red[idx];
-    }
     if (grad_out) grad_out[k] = gk;
-    const float m = beta1 * P.m[k] + (1.0f - beta1) * gk;
-    const float v = beta2 * P.v[k] + (1.0f - beta2) * gk * gk;
+    const float m = h.beta1 * P.m[k] + (1.0f - h.beta1) * gk;
+    const float v = h.beta2 * P.v[k] + (1.0f - h.beta2) * gk * gk;
     P.m[k] = m;
     P.v[k] = v;
-    const float w = P.master[k] - lr * (m / c1) / (sqrtf(v / c2) + eps);
+    const float w = P.master[k] - h.lr * (m / h.c1) / (sqrtf(v / h.c2) + h.eps);
     P.master[k] = w;
     const uint16_t b = bf16_bits(w);
     if (k < kOffB1) {
-        const uint32_t n = k / kVnIn, f = vn_perm(k % kVnIn);
-        P.w1b[vn_frag(n, f, 5u)] = b;
+        P.w1b[vn_frag(k / kVnIn, p, 5u)] = b;
     } else if (k >= kOffW2 && k < kOffB2) {
         const uint32_t kk = k - kOffW2, n = kk / kVnH, i = kk % kVnH;
         P.w2b[vn_frag(n, i, 8u)] = b;
@@ -703,6 +727,178 @@ __global__ void vn_adam_kernel(void *net, const float *grad, uint32_t slices, co
     } else if (k >= kOffW3 && k < kOffB3) {
         P.w3b[k - kOffW3] = b;
     }
+}
+
+struct VnGradArgs {
+    void *net;
+    const uint16_t *xt, *h1t, *dh1t, *dh2t;   // fragment layout (vn_act_idx), batch K
+    uint32_t K, slices, k_slice;             // slice length: a multiple of 32
+    float *grad;                             // slice s of the weight gradients at s * kVnPad
+    const float *part;                       // column-major partials of the 16-row tiles
+    uint32_t n_parts;
+    VnAdam h;
+    float inv_batch;
+    float *grad_out, *loss_out;
+};
+
+// The weight gradients, and the Adam step of the parameters outside W1 and
+// W2, in one launch of single-wavefront workgroups.  Workgroups [0, 104 S):
+// one 32 x 32 tile of dW2 = dh2^T h1 or dW1 = dh1^T x and one of S batch
+// slices each (split K, so that enough wavefronts stream the activations at
+// once); the partial tile goes to its slice's copy of the gradient.
+// Workgroup b takes slice b % S: with S = 8, consecutive workgroups going to
+// the 8 XCDs in turn, each XCD streams one slice of the activations (1/8 of
+// them, small enough to stay in its L2) instead of all of them.
+// Workgroups [104 S, 104 S + 770): one column of the rows kernel's partials
+// each (loss, b3, w3, b2, b1), summed by lane l over tiles l, l + 64, ... and
+// then across the lanes in a fixed order, followed by that parameter's Adam
+// step (those parameters are read by no other workgroup of the launch).
+constexpr uint32_t kVnChunk = 4u;        // k steps whose operands are loaded together
+
+__global__ void __launch_bounds__(64) vn_grad_kernel(VnGradArgs a)
+{
+    const VnPtrs P = vn_ptrs(a.net);
+    const uint32_t lane = threadIdx.x, r = lane & 15u, g = lane >> 4;
+    const uint32_t n_tile_groups = kVnGradTiles * a.slices;
+    if (blockIdx.x >= n_tile_groups) {
+        const uint32_t col = blockIdx.x - n_tile_groups;
+        if (col >= kPartWords) return;
+        const float *pc = a.part + (size_t)col * a.n_parts;
+        float acc = 0.0f;
+        for (uint32_t w0 = 0; w0 < a.n_parts; w0 += 512u) {
+            // eight loads in flight, then the additions in index order
+            float x[8];
+#pragma unroll
+            for (uint32_t u = 0; u < 8u; ++u) {
+                const uint32_t w = w0 + 64u * u + lane;
+                x[u] = w < a.n_parts ? pc[w] : 0.0f;
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < 8u; ++u)
+                if (w0 + 64u * u + lane < a.n_parts) acc += x[u];
+        }
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        if (lane != 0u) return;
+        if (col == 0u) {
+            if (a.loss_out) *a.loss_out = acc * a.inv_batch;
+            return;
+        }
+        const uint32_t k = col == 1u ? kOffB3
+                         : col < 258u ? kOffW3 + (col - 2u)
+                         : col < 514u ? kOffB2 + (col - 258u)
+                                      : kOffB1 + (col - 514u);
+        vn_adam_one(P, a.h, k, 0u, acc, a.grad_out);
+        return;
+    }
+
+    const uint32_t tile = blockIdx.x / a.slices, slice = blockIdx.x % a.slices;
+    const bool w2 = tile < kVnTilesW2;
+    const uint32_t t = w2 ? tile : tile - kVnTilesW2;
+    const uint32_t ntn = w2 ? 8u : 5u;                    // 32-wide column tiles
+    const uint32_t mt = t / ntn, nt = t % ntn;
+    const uint32_t ldo = w2 ? kVnH : kVnIn, off = w2 ? kOffW2 : kOffW1;
+    const uint16_t *at = w2 ? a.dh2t : a.dh1t;
+    const uint16_t *bt = w2 ? a.h1t : a.xt;
+    const uint32_t kb = slice * a.k_slice;
+    // operand fragments of the 16-feature tiles 2mt, 2mt + 1 (A) and 2nt,
+    // 2nt + 1 (B) at the slice's first k step; a k step is 512 elements on
+    const uint16_t *ap0 = at + vn_act_idx(32u * mt, kb, a.K) + 8u * lane;
+    const uint16_t *ap1 = at + vn_act_idx(32u * mt + 16u, kb, a.K) + 8u * lane;
+    const uint16_t *bp0 = bt + vn_act_idx(32u * nt, kb, a.K) + 8u * lane;
+    const uint16_t *bp1 = bt + vn_act_idx(32u * nt + 16u, kb, a.K) + 8u * lane;
+
+    floatx4 acc[2][2];
+#pragma unroll
+    for (uint32_t x = 0; x < 2u; ++x)
+#pragma unroll
+        for (uint32_t y = 0; y < 2u; ++y) acc[x][y] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+
+    // operands of kVnChunk k steps are requested one chunk ahead of the
+    // products that use them
+    const uint32_t nsteps = a.k_slice / 32u, nfull = nsteps / kVnChunk;
+    bf16x8 fa[kVnChunk][2], fb[kVnChunk][2];
+    auto load_chunk = [&](uint32_t c, bf16x8 (&A)[kVnChunk][2], bf16x8 (&B)[kVnChunk][2]) {
+#pragma unroll
+        for (uint32_t u = 0; u < kVnChunk; ++u) {
+            const uint32_t k0 = 512u * (c * kVnChunk + u);
+            A[u][0] = load8(ap0 + k0);
+            A[u][1] = load8(ap1 + k0);
+            B[u][0] = load8(bp0 + k0);
+            B[u][1] = load8(bp1 + k0);
+        }
+    };
+    auto run_chunk = [&](bf16x8 (&A)[kVnChunk][2], bf16x8 (&B)[kVnChunk][2]) {
+#pragma unroll
+        for (uint32_t u = 0; u < kVnChunk; ++u)
+#pragma unroll
+            for (uint32_t x = 0; x < 2u; ++x)
+#pragma unroll
+                for (uint32_t y = 0; y < 2u; ++y) acc[x][y] = mfma16(A[u][x], B[u][y], acc[x][y]);
+    };
+    // two operand buffers used in turn (no register copies between chunks,
+    // which would wait for the loads just issued)
+    if (nfull > 0u) {
+        bf16x8 ga_[kVnChunk][2], gb_[kVnChunk][2];
+        load_chunk(0u, fa, fb);
+        uint32_t c = 0;
+        for (; c + 2u < nfull; c += 2u) {
+            load_chunk(c + 1u, ga_, gb_);
+            run_chunk(fa, fb);
+            load_chunk(c + 2u, fa, fb);
+            run_chunk(ga_, gb_);
+        }
+        if (c + 1u < nfull) {
+            load_chunk(c + 1u, ga_, gb_);
+            run_chunk(fa, fb);
+            run_chunk(ga_, gb_);
+        } else {
+            run_chunk(fa, fb);
+        }
+    }
+    for (uint32_t s = nfull * kVnChunk; s < nsteps; ++s) {
+        const uint32_t k0 = 512u * s;
+        const bf16x8 a0 = load8(ap0 + k0), a1 = load8(ap1 + k0);
+        const bf16x8 b0 = load8(bp0 + k0), b1 = load8(bp1 + k0);
+        acc[0][0] = mfma16(a0, b0, acc[0][0]);
+        acc[0][1] = mfma16(a0, b1, acc[0][1]);
+        acc[1][0] = mfma16(a1, b0, acc[1][0]);
+        acc[1][1] = mfma16(a1, b1, acc[1][1]);
+    }
+
+    float *o = a.grad + (size_t)slice * kVnPad + off;
+#pragma unroll
+    for (uint32_t x = 0; x < 2u; ++x)
+#pragma unroll
+        for (uint32_t y = 0; y < 2u; ++y)
+#pragma unroll
+            for (uint32_t i = 0; i < 4u; ++i)
+                o[(size_t)(32u * mt + 16u * x + 4u * g + i) * ldo + 32u * nt + 16u * y + r] =
+                    acc[x][y][i];
+
+}
+
+// Adam for the weights of W1 and W2: the S slices' partial gradients summed
+// in slice order (the W1 gradient is laid out in the internal feature order).
+__global__ void vn_adam_w_kernel(void *net, const float *grad, uint32_t slices, VnAdam h,
+                                 float *grad_out)
+{
+    const VnPtrs P = vn_ptrs(net);
+    const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= kOffB1 + kVnH * kVnH) return;
+    const bool w1 = e < kOffB1;
+    const uint32_t k = w1 ? e : kOffW2 + (e - kOffB1);          // canonical index
+    const uint32_t p = w1 ? vn_perm(k % kVnIn) : 0u;
+    const uint32_t kg = w1 ? (k / kVnIn) * kVnIn + p : k;
+    // the (at most eight) slices' loads in flight together, then summed in order
+    float x[kVnMaxSlices];
+#pragma unroll
+    for (uint32_t sl = 0; sl < kVnMaxSlices; ++sl)
+        x[sl] = sl < slices ? grad[(size_t)sl * kVnPad + kg] : 0.0f;
+    float gk = x[0];
+#pragma unroll
+    for (uint32_t sl = 1; sl < kVnMaxSlices; ++sl)
+        if (sl < slices) gk += x[sl];
+    vn_adam_one(P, h, k, p, gk, grad_out);
 }
 
 // ---------------------------------------------------------------------------
@@ -714,14 +910,15 @@ size_t vn_bytes() { return (size_t)kVnBytes; }
 // 32 rows
 static uint32_t vn_wgrad_slices(uint32_t batch)
 {
-    uint32_t s = 8u;
+    uint32_t s = kVnMaxSlices;
     while (s > 1u && (batch / 32u) % s != 0u) s >>= 1;
     return s;
 }
 
 size_t vn_train_ws_bytes(uint32_t batch)
 {
-    // xt[160][B], h1t, dh1t, dh2t [256][B] bf16; grad[NPAD] fp32; partials
+    // xt (160 x B), h1t, dh1t, dh2t (256 x B) bf16; grad[NPAD] fp32 per slice; partials of
+    // the 16-row tiles (and one spare row)
     return (size_t)batch * (160u + 3u * 256u) * 2u + (size_t)vn_wgrad_slices(batch) * kVnPad * 4u +
            (size_t)((batch + 15u) / 16u + 1u) * kPartWords * 4u + 256u;
 }
@@ -787,24 +984,29 @@ hipError_t launch_vn_train_step(void *net, const uint4 *states, const uint8_t *p
     hipLaunchKernelGGL(vn_rows4_kernel, dim3(waves), dim3(256), 0, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    // dW2 = dh2^T h1 (256 x 256), dW1 = dh1^T x (256 x 160)
-    const uint32_t ks = batch / slices;
-    hipLaunchKernelGGL(vn_wgrad_kernel, dim3(16u * 16u * slices), dim3(64), 0, st, a.dh2t, a.h1t,
-                       batch, ks, grad + kOffW2, 256u, 16u, 16u * 16u, kVnPad);
+    VnGradArgs ga = {};
+    ga.net = net;
+    ga.xt = a.xt;
+    ga.h1t = a.h1t;
+    ga.dh1t = a.dh1t;
+    ga.dh2t = a.dh2t;
+    ga.K = batch;
+    ga.slices = slices;
+    ga.k_slice = batch / slices;
+    ga.grad = grad;
+    ga.part = a.part;
+    ga.n_parts = waves;
+    ga.h = VnAdam{lr, 0.9f, 0.999f, 1e-8f, c1, c2};
+    ga.inv_batch = a.inv_batch;
+    ga.grad_out = grad_out;
+    ga.loss_out = loss_out;
+    hipLaunchKernelGGL(vn_grad_kernel, dim3(kVnGradTiles * slices + kPartWords), dim3(64), 0, st,
+                       ga);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(vn_wgrad_kernel, dim3(16u * 10u * slices), dim3(64), 0, st, a.dh1t, a.xt,
-                       batch, ks, grad + kOffW1, 160u, 10u, 16u * 10u, kVnPad);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    float *red = a.part + (size_t)waves * kPartWords;
-    hipLaunchKernelGGL(vn_partsum_kernel, dim3((kPartWords + 3u) / 4u), dim3(256), 0, st, a.part,
-                       waves, red);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(vn_adam_kernel, dim3((kVnParams + 255u) / 256u), dim3(256), 0, st, net, grad,
-                       slices, red, lr, 0.9f, 0.999f, 1e-8f, c1, c2, a.inv_batch, grad_out,
-                       loss_out);
+    constexpr uint32_t n_w = kOffB1 + kVnH * kVnH;
+    hipLaunchKernelGGL(vn_adam_w_kernel, dim3((n_w + 255u) / 256u), dim3(256), 0, st, net, grad,
+                       slices, ga.h, grad_out);
     return hipGetLastError();
 }
 
