@@ -307,7 +307,10 @@ def main():
         "config": {"workload": "leaf-parallel rollout: 4096 two-player mid-game leaves x 256 "
                                "playouts (pool 0-16, 0-8 revealed per row)",
                    "leaves": N_LEAVES, "playouts_per_leaf": PPL, "seed": SEED,
-                   "variant": args.variant or 4, "block": args.block, "grid": args.grid},
+                   # 0/0/0 is the library's automatic shape at this size: variant 7
+                   # (compacted at steps 5, 8, 11, 14)
+                   "variant": args.variant or 7, "block": args.block,
+                   "grid": args.grid if args.variant else 2},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": INT_VALU_PEAK / 1e12,
                      "unit": "TOP/s", "frac": achieved / INT_VALU_PEAK,
                      "traffic": profiled_traffic_bytes()},

@@ -133,7 +133,7 @@ int dvc_rollout(const dvc_state_t *leaves, int64_t n_leaves, int32_t playouts_pe
 
 /* dvc_rollout with a choice of kernel, for measurement.  variant: 0 =
  * automatic (the shape dvc_rollout_autotune chose for this size class, else
- * below 4M playouts variant 4 with one playout per lane; above, variant 5 if
+ * below 4M playouts variant 7 with steps 5, 8, 11, 14; above, variant 5 if
  * playouts_per_leaf >= 256, else variant 1), 1 = one lane per playout,
  * 2 = lane refill + work stealing over LDS-staged leaf chunks, 3 = lane
  * refill + work stealing over single-leaf items, 4 = several playouts per
@@ -141,7 +141,11 @@ int dvc_rollout(const dvc_state_t *leaves, int64_t n_leaves, int32_t playouts_pe
  * 5 = one wavefront per item of up to 64*K playouts of one leaf, lanes
  * refilled from the item as their games end (`grid` gives K, 1/2/4/8,
  * default 4), 6 = variant 4 with one playout per lane and each step's
- * random words computed during the step before.  block/grid 0 = automatic.  Same outputs for every variant and shape.
+ * random words computed during the step before, 7 = one playout per lane
+ * with the workgroup's unfinished games packed into its first lanes at
+ * fixed step counts (Sec. IV-B's divergence: wavefronts left without a game
+ * stop issuing; `grid` 0/1 = steps 6, 9, 12, 2 = steps 5, 8, 11, 14).
+ * block/grid 0 = automatic.  Same outputs for every variant and shape.
  * flags: DVC_ROLLOUT_ACCUMULATE adds the wins to seat_wins instead of
  * overwriting it (the caller zeroes it once; several calls then tally into
  * one table).  Errors as dvc_rollout, plus DVC_EINVAL for an unknown
@@ -153,8 +157,9 @@ int dvc_rollout_ex(const dvc_state_t *leaves, int64_t n_leaves, int32_t playouts
                    int32_t variant, int32_t block, int32_t grid, int32_t flags, void *stream);
 
 /* dvc_rollout_autotune -- runs this batch with every rollout kernel shape in
- * a fixed candidate list (variant 4 with 1 or 2 playouts per lane, variant 1,
- * variant 5 with 128/256/512-playout items), each launched twice with the
+ * a fixed candidate list (variant 7 with steps 5, 8, 11, 14, variant 4 with 1
+ * or 2 playouts per lane, variant 1, variant 5 with 128/256/512-playout
+ * items), each launched twice with the
  * second launch timed by HIP events on `stream`, and remembers the fastest
  * for batches of the same size class (device, floor(log2(n_leaves *
  * playouts_per_leaf)), playouts_per_leaf >= 256 / >= 64 / smaller): later

@@ -473,6 +473,41 @@ __global__ void __launch_bounds__(WAVES * 64) rollout_items(RolloutArgs a)
 // ---------------------------------------------------------------------------
 constexpr uint32_t kOutError = 0x7Fu;     // packed outcome of a malformed leaf
 
+// Outputs of playout jj (packed outcome `code`: winner | length << 2, or
+// kOutError), and the wave's seat wins summed per leaf with ballots, one
+// atomic per (leaf, seat) present.  Every lane of the wavefront takes part.
+__device__ __forceinline__ void emit_outcome(const RolloutArgs &a, uint32_t jj, uint32_t code,
+                                             uint32_t lane)
+{
+    const bool has = jj < a.total;
+    const bool err = code == kOutError;
+    const uint32_t w = code & 3u;
+    if (has) {
+        if (a.winner) a.winner[jj] = err ? (int8_t)-1 : (int8_t)w;
+        if (a.length) a.length[jj] = err ? (int16_t)-1 : (int16_t)(code >> 2);
+    }
+    if (a.seat_wins) {
+        const uint32_t lf = has ? jj / a.ppl : 0u;
+        const bool fin = has && !err;
+        uint64_t fmask = __ballot(fin);
+        while (fmask != 0ull) {
+            const uint32_t first = (uint32_t)__builtin_ctzll(fmask);
+            const uint32_t L = __builtin_amdgcn_readlane(lf, first);
+            const bool mineL = fin && lf == L;
+            const uint64_t same = __ballot(mineL);
+            const uint32_t c0 = (uint32_t)__popcll(__ballot(mineL && w == 0u));
+            const uint32_t c1 = (uint32_t)__popcll(__ballot(mineL && w == 1u));
+            const uint32_t c2 = (uint32_t)__popcll(__ballot(mineL && w == 2u));
+            const uint32_t c3 = (uint32_t)__popcll(__ballot(mineL && w == 3u));
+            if (lane < 4u) {
+                const uint32_t c = lane == 0u ? c0 : lane == 1u ? c1 : lane == 2u ? c2 : c3;
+                if (c) atomicAdd(&a.seat_wins[(size_t)L * 4u + lane], c);
+            }
+            fmask &= ~same;
+        }
+    }
+}
+
 template <int K, bool PIPE>
 __global__ void __launch_bounds__(256) rollout_static(RolloutArgs a)
 {
@@ -548,37 +583,141 @@ __global__ void __launch_bounds__(256) rollout_static(RolloutArgs a)
 
     // outputs, and seat wins summed per leaf across the wave
 #pragma unroll
-    for (uint32_t kk = 0; kk < (uint32_t)K; ++kk) {
-        const uint32_t jj = g + kk * S;
-        const bool has = jj < a.total;
-        const uint32_t code = (packed >> (7u * kk)) & 0x7Fu;
-        const bool err = code == kOutError;
-        const uint32_t w = code & 3u;
-        if (has) {
-            if (a.winner) a.winner[jj] = err ? (int8_t)-1 : (int8_t)w;
-            if (a.length) a.length[jj] = err ? (int16_t)-1 : (int16_t)(code >> 2);
-        }
-        if (a.seat_wins) {
-            const uint32_t lf = has ? jj / a.ppl : 0u;
-            const bool fin = has && !err;
-            uint64_t fmask = __ballot(fin);
-            while (fmask != 0ull) {
-                const uint32_t first = (uint32_t)__builtin_ctzll(fmask);
-                const uint32_t L = __builtin_amdgcn_readlane(lf, first);
-                const bool mineL = fin && lf == L;
-                const uint64_t same = __ballot(mineL);
-                const uint32_t c0 = (uint32_t)__popcll(__ballot(mineL && w == 0u));
-                const uint32_t c1 = (uint32_t)__popcll(__ballot(mineL && w == 1u));
-                const uint32_t c2 = (uint32_t)__popcll(__ballot(mineL && w == 2u));
-                const uint32_t c3 = (uint32_t)__popcll(__ballot(mineL && w == 3u));
-                if (lane < 4u) {
-                    const uint32_t c = lane == 0u ? c0 : lane == 1u ? c1 : lane == 2u ? c2 : c3;
-                    if (c) atomicAdd(&a.seat_wins[(size_t)L * 4u + lane], c);
-                }
-                fmask &= ~same;
+    for (uint32_t kk = 0; kk < (uint32_t)K; ++kk)
+        emit_outcome(a, g + kk * S, (packed >> (7u * kk)) & 0x7Fu, lane);
+}
+
+// ---------------------------------------------------------------------------
+// Variant 7: one playout per lane, compacted at a few fixed step counts.
+//
+// Games end at different steps, and a wavefront runs until its longest game
+// has ended (the divergence the paper blames for the GPU's scaling, Sec.
+// IV-B).  At each checkpoint step the workgroup packs its unfinished games
+// into its first lanes, in lane order, through LDS: a wavefront left with no
+// game skips the rest of the loop, so later steps are issued for about as
+// many wavefronts as there are games.  Every unfinished game has played
+// exactly the checkpoint's number of steps, so the step counter (and the
+// Philox counter word it feeds) stays uniform.  A game's packed outcome is
+// recorded in LDS under its original slot; after the last step the outputs
+// and seat wins are written per original slot exactly as variant 4 writes
+// them, so every output equals the other variants'.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kCompactSched[2][4] = {{6u, 9u, 12u, 0u}, {5u, 8u, 11u, 14u}};
+constexpr int kCompactCount[2] = {3, 4};
+
+// the packed format of a state already checked by decode()
+__device__ __forceinline__ void unpack_valid(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3,
+                                             State &s)
+{
+    const uint32_t b0 = w0 & kAll, b1 = w1 & kAll, b2 = w2 & kAll;
+    s.h0 = b0 & ~b1 & ~b2;
+    s.h1 = ~b0 & b1 & ~b2 & kAll;
+    s.h2 = b0 & b1 & ~b2;
+    s.h3 = b2;
+    s.rev = w3 & kAll;
+    s.m = (w0 >> 24) & 3u;
+    s.P = ((w0 >> 26) & 3u) + 1u;
+    s.phase = (w0 >> 28) & 1u;
+    s.drawn = ((w0 >> 29) & 1u) ? (int32_t)((w1 >> 24) & 31u) : -1;
+}
+
+template <int SCHED>
+__global__ void __launch_bounds__(256) rollout_compact(RolloutArgs a)
+{
+    constexpr int NCP = kCompactCount[SCHED];
+    __shared__ uint8_t tab[kKthTableBytes];
+    __shared__ uint32_t mig[7][256];       // packed state, playout id, round-1 key words
+    __shared__ uint8_t outc[256];          // packed outcome per original slot
+    __shared__ uint32_t wcnt[4];
+    fill_kth_table(tab);
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
+    const uint32_t base = blockIdx.x * 256u;
+    const uint32_t trk1 = a.tree ^ a.k1;
+
+    uint32_t j = base + tid, winner = 0u;
+    bool live = false;
+    State s;
+    s.h0 = s.h1 = s.h2 = s.h3 = s.rev = 0u;
+    s.m = 0u; s.P = 2u; s.phase = 1u; s.drawn = -1;
+    PlayoutKey pk = {0u, 0u, 0u, 0u};
+    outc[tid] = (uint8_t)kOutError;
+    if (j < a.total) {
+        const uint32_t leaf = j / a.ppl;
+        const uint4 st = a.leaves[leaf];
+        if (!decode(st.x, st.y, st.z, st.w, s)) {
+            atomicOr(&g_error_word, kErrState);
+        } else {
+            const uint32_t alive = alive_mask(s);
+            winner = (uint32_t)__builtin_ctz(alive | 16u);
+            if (__popc(alive) == 1) {
+                outc[tid] = (uint8_t)winner;          // decided before any guess
+            } else {
+                live = true;
+                pk = playout_key(j - leaf * a.ppl, a.leaf_base + leaf, a.k0);
             }
         }
     }
+    __syncthreads();   // k-th-bit table ready
+
+#pragma unroll
+    for (int seg = 0; seg <= NCP; ++seg) {
+        const uint32_t first = seg == 0 ? 0u : kCompactSched[SCHED][seg - 1];
+        const uint32_t limit = seg < NCP ? kCompactSched[SCHED][seg] : kMaxGuesses;
+        for (uint32_t step = first; step < limit; ++step) {
+            if (__ballot(live) == 0ull) break;
+            if (live) {
+                const Words w = step_words(pk, trk1, a.k0, a.k1);
+                const bool over = guess_step(s, w, winner, tab);
+                next_step(pk);
+                if (over) {
+                    outc[j - base] = (uint8_t)(winner | ((step + 1u) << 2));
+                    live = false;
+                }
+            }
+        }
+        if (seg == NCP) {
+            // still undecided after the most guesses a valid game can take
+            if (live) atomicOr(&g_error_word, kErrLimit);
+            break;
+        }
+        // pack the unfinished games into the first lanes of the workgroup
+        const uint64_t lm = __ballot(live);
+        if (lane == 0u) wcnt[wv] = (uint32_t)__popcll(lm);
+        __syncthreads();
+        uint32_t before = 0u, n_live = 0u;
+#pragma unroll
+        for (uint32_t w = 0; w < 4u; ++w) {
+            const uint32_t c = wcnt[w];
+            before += w < wv ? c : 0u;
+            n_live += c;
+        }
+        if (live) {
+            const uint32_t dst = before + __builtin_amdgcn_mbcnt_hi(
+                (uint32_t)(lm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)lm, 0u));
+            uint32_t e0, e1, e2, e3;
+            encode(s, e0, e1, e2, e3);
+            mig[0][dst] = e0;
+            mig[1][dst] = e1;
+            mig[2][dst] = e2;
+            mig[3][dst] = e3;
+            mig[4][dst] = j;
+            mig[5][dst] = pk.a;
+            mig[6][dst] = pk.b;
+        }
+        __syncthreads();
+        live = tid < n_live;
+        if (live) {
+            unpack_valid(mig[0][tid], mig[1][tid], mig[2][tid], mig[3][tid], s);
+            j = mig[4][tid];
+            pk.a = mig[5][tid];
+            pk.b = mig[6][tid];
+            const uint64_t gm = (uint64_t)limit * kPhiloxM0;   // the step counter times M0
+            pk.gm_lo = (uint32_t)gm;
+            pk.gm_hi = (uint32_t)(gm >> 32);
+        }
+    }
+    __syncthreads();   // every game's outcome is in outc
+    emit_outcome(a, base + tid, outc[tid], lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -731,6 +870,16 @@ hipError_t launch_rollout(const RolloutArgs &a, int variant, int block, int grid
         case 2: hipLaunchKernelGGL((rollout_static<2, false>), dim3(blocks), dim3(256), 0, st, a); break;
         default: hipLaunchKernelGGL((rollout_static<4, false>), dim3(blocks), dim3(256), 0, st, a); break;
         }
+        return hipGetLastError();
+    }
+    if (variant == 7) {
+        // one playout per lane, compacted at steps 6, 9, 12 (grid 0 or 1) or
+        // 5, 8, 11, 14 (grid 2)
+        const uint32_t blocks = (a.total + 255u) / 256u;
+        if (grid == 2)
+            hipLaunchKernelGGL(rollout_compact<1>, dim3(blocks), dim3(256), 0, st, a);
+        else
+            hipLaunchKernelGGL(rollout_compact<0>, dim3(blocks), dim3(256), 0, st, a);
         return hipGetLastError();
     }
     if (variant == 5) {

@@ -70,7 +70,7 @@ def _compare(dvc, states_np, ppl, seed, tree, base, ref, **kw):
     assert np.array_equal(sw.cpu().numpy().view(np.uint32), rs), "seat wins"
 
 
-@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6, 7])
 @pytest.mark.parametrize("P", [2, 3, 4])
 def test_rollout_bit_exact_small(orc, dvc, variant, P):
     po = orc.deal_params(p_min=P, p_max=P, pile_min=0, pile_max=16, revealed_max=8, phase_mix=1)
@@ -92,7 +92,7 @@ def test_rollout_schedule_invariance(orc, dvc, variant, block, grid):
     _compare(dvc, S, ppl, 77, 3, 0, ref, variant=variant, block=block, grid=grid)
 
 
-@pytest.mark.parametrize("variant", [2, 3, 4, 5, 6])
+@pytest.mark.parametrize("variant", [2, 3, 4, 5, 6, 7])
 @pytest.mark.parametrize("ppl", [1, 2, 63, 64, 65, 129, 1000])
 def test_rollout_ppl_edges(orc, dvc, variant, ppl):
     po = orc.deal_params(p_min=2, p_max=3, pile_min=0, pile_max=16, revealed_max=8)
@@ -108,6 +108,20 @@ def test_rollout_playouts_per_lane_invariance(orc, dvc, per_lane):
     S = orc.init_states(150, po, seed=6)
     ref = _rollout_ref(orc, S, 90, 8, 1, 5)
     _compare(dvc, S, 90, 8, 1, 5, ref, variant=4, grid=per_lane)
+
+
+@pytest.mark.parametrize("sched", [0, 2])
+@pytest.mark.parametrize("ppl", [1, 37, 100, 256, 700])
+def test_rollout_compacted_long_games(orc, dvc, sched, ppl):
+    """Variant 7 packs unfinished games into the first lanes of the workgroup at
+    fixed step counts: fresh four-player deals give games of up to 23 guesses
+    (every checkpoint and the last segment are crossed), with leaves spanning
+    workgroups and several leaves in one workgroup."""
+    po, _ = deal_pair(orc, dvc, p_min=2, p_max=4, fresh=1, root_draw=1)
+    S = orc.init_states(37, po, seed=5)
+    ref = _rollout_ref(orc, S, ppl, 6, 2, 40)
+    assert ref[1].max() >= 15, "the batch should reach past the last checkpoint"
+    _compare(dvc, S, ppl, 6, 2, 40, ref, variant=7, grid=sched)
 
 
 @pytest.mark.parametrize("K", [1, 2, 4, 8])
@@ -175,7 +189,7 @@ def test_rollout_accumulate(orc, dvc):
     assert np.array_equal(sw.cpu().numpy().view(np.uint32), r1 + r2)
 
 
-@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6, 7])
 def test_rollout_decided_and_malformed_leaves(orc, dvc, variant):
     import positions as POS
     rng = np.random.default_rng(9)
@@ -226,8 +240,8 @@ def test_rollout_full_leaf_parallel_workload(orc, dvc):
     st = dvc.dvc_init_states(4096, pd, seed=2)
     assert np.array_equal(to_np(st), S)
     ref = _rollout_ref(orc, S, 256, 2, 0, 0)
-    for variant in [1, 2, 3, 4, 5, 6]:
-        w, ln, sw = dvc.dvc_rollout(st, 256, 2, 0, 0, variant=variant)
+    for variant, grid in [(1, 0), (2, 0), (3, 0), (4, 0), (5, 0), (6, 0), (7, 0), (7, 2)]:
+        w, ln, sw = dvc.dvc_rollout(st, 256, 2, 0, 0, variant=variant, grid=grid)
         torch.cuda.synchronize()
         assert np.array_equal(w.cpu().numpy(), ref[0])
         assert np.array_equal(ln.cpu().numpy(), ref[1])
@@ -249,7 +263,7 @@ def test_valu_probe(dvc):
         dvc.dvc_probe_valu(6, 2, 3, sink)
 
 
-@pytest.mark.parametrize("variant", [4, 6])
+@pytest.mark.parametrize("variant", [4, 6, 7])
 @pytest.mark.parametrize("ppl", [1, 3, 64, 100, 256, 300])
 def test_rollout_seat_wins_overwrite_the_table(orc, dvc, variant, ppl):
     """Without accumulate the seat-win table is overwritten (zeroed, then
