@@ -53,9 +53,9 @@ OPS_PER_GUESS = 222
 # scaled by what the same counter reads for a plain 256 MiB device copy
 # (FETCH_SIZE reads half the bytes moved, WRITE_SIZE all of them).  Valid
 # only for the kernel sources it was taken on: reported as null otherwise.
-PROFILED_TRAFFIC = {"fetch_kib": 317.77, "fetch_scale": 2.0, "write_kib": 3584.0,
+PROFILED_TRAFFIC = {"fetch_kib": 378.5, "fetch_scale": 2.0, "write_kib": 3584.0,
                     "write_scale": 1.0,
-                    "sources_sha256": "5af839aa03765d8bac2d385abb356f3564c72e15e138476269769b176456623c"}
+                    "sources_sha256": "ffa7f2f17d2e460a47dcc3067cc1a5d111c7b43e717227a774987ab6c94e5540"}
 KERNEL_SOURCES = ["paper_2403_10720_amd/csrc/dvc_core.hpp",
                   "paper_2403_10720_amd/csrc/dvc_internal.hpp",
                   "paper_2403_10720_amd/csrc/rollout.hip"]
