@@ -86,13 +86,14 @@ __device__ __forceinline__ uint32_t vn_perm(uint32_t f)
     return 24u * (f - 6u * t) + t;
 }
 
-// float -> bfloat16 bits, round to nearest even
+// float -> bfloat16 bits, round to nearest even (the gfx950 conversion
+// instruction; the values converted here are finite)
 __device__ __forceinline__ uint16_t bf16_bits(float x)
 {
-    uint32_t u = __float_as_uint(x);
-    if ((u & 0x7F800000u) == 0x7F800000u) return (uint16_t)(u >> 16);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+    const __bf16 b = (__bf16)x;
+    uint16_t u;
+    __builtin_memcpy(&u, &b, 2);
+    return u;
 }
 __device__ __forceinline__ float bf16_to_f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 __device__ __forceinline__ float bf16_round(float x) { return bf16_to_f(bf16_bits(x)); }
@@ -495,16 +496,19 @@ __global__ void __launch_bounds__(256) vn_rows4_kernel(VnRowsArgs a)
         w3v[jj] = bf16_to_f(P.w3b[col]);
     }
     const float b3 = P.master[kOffB3];
+    // the data row of batch row r, computed by the lanes r (< 16); the labels
+    // of rows 4g + i take it from lane 4g + i
+    const uint32_t src = has ? vn_train_row(a, myrow) : 0u;
     float yv[4];
 #pragma unroll
     for (uint32_t i = 0; i < 4u; ++i) {
         const uint32_t row = row0 + 4u * g + i;
-        yv[i] = row < a.n_rows ? a.labels[vn_train_row(a, row)] : 0.0f;
+        const uint32_t sr = (uint32_t)__shfl((int)src, (int)(4u * g + i), 64);
+        yv[i] = row < a.n_rows ? a.labels[sr] : 0.0f;
     }
 
     RowFeat rf;
     if (has) {
-        const uint32_t src = vn_train_row(a, myrow);
         rf = row_features(a.states[src], a.persp[src]);
     } else {
         rf.ok = false;
