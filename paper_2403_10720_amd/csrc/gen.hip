@@ -8,8 +8,10 @@
 // one after another from Philox blocks (n>>2, 0xFFFFFFFF, 0xFFFFFFFF, s).
 //
 // One wavefront per state.  Every word a state can use lies in its first 14
-// blocks, so lane b computes block b at once and a word is read from its
-// lane when its turn comes.  The shuffles are followed from the tiles' side:
+// blocks, so lane b computes block b at once, and four shuffles then put word
+// w in lane w: a word is one read from its lane when its turn comes.  The 23
+// swap targets of the tile shuffle are picked in parallel, one per lane.  The
+// shuffles are followed from the tiles' side:
 // lane t (t < 24) keeps the position of tile t through the swaps of the
 // Fisher-Yates shuffle, so a row, a set of revealed tiles or the pool is one
 // ballot -- no per-state array and no serial chain through memory.
@@ -33,11 +35,17 @@ __global__ void __launch_bounds__(kGenBlock) init_states_kernel(uint4 *out, uint
     // words: at most 2 (players, pool) + 23 (shuffle) + 4 + 22 (reveals: at
     // most 24 - P of them) + 2 (draw coin, draw) = 53, i.e. blocks 0..13
     const Words blk = philox(lane, 0xFFFFFFFFu, 0xFFFFFFFFu, base + i, k0, k1);
+    // lane w holds word w (component w % 4 of block w / 4)
+    const int src = (int)(lane >> 2);
+    const uint32_t c0 = (uint32_t)__shfl((int)blk.w0, src, 64);
+    const uint32_t c1 = (uint32_t)__shfl((int)blk.w1, src, 64);
+    const uint32_t c2 = (uint32_t)__shfl((int)blk.w2, src, 64);
+    const uint32_t c3 = (uint32_t)__shfl((int)blk.w3, src, 64);
+    const uint32_t cl = lane & 3u;
+    const uint32_t words = cl == 0u ? c0 : cl == 1u ? c1 : cl == 2u ? c2 : c3;
     uint32_t nw = 0u;
     auto word = [&]() -> uint32_t {
-        const uint32_t c = nw & 3u;
-        const uint32_t v = c == 0u ? blk.w0 : c == 1u ? blk.w1 : c == 2u ? blk.w2 : blk.w3;
-        const uint32_t w = __builtin_amdgcn_readlane(v, nw >> 2);
+        const uint32_t w = __builtin_amdgcn_readlane(words, nw);
         ++nw;
         return w;
     };
@@ -56,10 +64,16 @@ __global__ void __launch_bounds__(kGenBlock) init_states_kernel(uint4 *out, uint
         hi = max(hi, lo);
         pile = lo + pick(word(), hi - lo + 1u);
     }
-    // Fisher-Yates over positions 23..1: the tiles at positions k and j swap
+    // Fisher-Yates over positions 23..1: the tiles at positions k and j swap.
+    // Step t (k = 23 - t) uses word nw + t; lane t picks its j.
+    const uint32_t fw = (uint32_t)__shfl((int)words, (int)((nw + lane) & 63u), 64);
+    const uint32_t jv = lane < 23u ? pick(fw, 24u - lane) : 0u;
+    nw += 23u;
     uint32_t pos = lane;
-    for (uint32_t k = 23u; k >= 1u; --k) {
-        const uint32_t j = pick(word(), k + 1u);
+#pragma unroll
+    for (uint32_t t = 0; t < 23u; ++t) {
+        const uint32_t k = 23u - t;
+        const uint32_t j = __builtin_amdgcn_readlane(jv, t);
         pos = pos == k ? j : (pos == j ? k : pos);
     }
     // rows: seat q takes the next h_q positions of the shuffled array
