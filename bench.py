@@ -53,9 +53,9 @@ OPS_PER_GUESS = 222
 # scaled by what the same counter reads for a plain 256 MiB device copy
 # (FETCH_SIZE reads half the bytes moved, WRITE_SIZE all of them).  Valid
 # only for the kernel sources it was taken on: reported as null otherwise.
-PROFILED_TRAFFIC = {"fetch_kib": 378.5, "fetch_scale": 2.0, "write_kib": 3584.0,
+PROFILED_TRAFFIC = {"fetch_kib": 389.0, "fetch_scale": 2.0, "write_kib": 3200.0,
                     "write_scale": 1.0,
-                    "sources_sha256": "ffa7f2f17d2e460a47dcc3067cc1a5d111c7b43e717227a774987ab6c94e5540"}
+                    "sources_sha256": "ab762a0174c43cc1ef2b14952f8151b628146513bf447dddd050e235e023d2fb"}
 KERNEL_SOURCES = ["paper_2403_10720_amd/csrc/dvc_core.hpp",
                   "paper_2403_10720_amd/csrc/dvc_internal.hpp",
                   "paper_2403_10720_amd/csrc/rollout.hip"]
@@ -247,15 +247,21 @@ def main():
     length = torch.empty(total, dtype=torch.int16, device=dev)
     wins = torch.empty((N_LEAVES, 4), dtype=torch.int32, device=dev)
 
+    # The automatic shape (variant 7) stores each leaf's seat wins over the
+    # table, 256 playouts being one workgroup; other shapes add to a table
+    # zeroed here first.  Either way the events bracket the rollout kernel
+    # alone.
+    stores_wins = args.variant in (0, 7)
+
     def step(ev=None):
         D.dvc_init_states(N_LEAVES, params, SEED, out=states)
-        wins.zero_()
-        # the events bracket the rollout kernel alone (the seat-win table is
-        # zeroed above, so the call adds to it and launches nothing else)
+        if not stores_wins:
+            wins.zero_()
         if ev is not None:
             ev[0].record(stream)
         D.dvc_rollout(states, PPL, SEED, 0, 0, winner=winner, length=length, seat_wins=wins,
-                      variant=args.variant, block=args.block, grid=args.grid, accumulate=True)
+                      variant=args.variant, block=args.block, grid=args.grid,
+                      accumulate=not stores_wins)
         if ev is not None:
             ev[1].record(stream)
 

@@ -237,8 +237,12 @@ static int rollout_impl(const dvc_state_t *leaves, int64_t n_leaves, int32_t ppl
     a.length = length;
     a.seat_wins = seat_wins;
     a.stats = nullptr;
+    // variant 7 with whole leaves per 256-playout workgroup stores each
+    // leaf's sums itself: no zeroing launch
+    a.store_wins = (seat_wins && !(flags & DVC_ROLLOUT_ACCUMULATE) && v == 7 && ppl <= 256 &&
+                    256 % ppl == 0) ? 1u : 0u;
     if (a.total == 0) return DVC_OK;
-    if (seat_wins && !(flags & DVC_ROLLOUT_ACCUMULATE)) {
+    if (seat_wins && !(flags & DVC_ROLLOUT_ACCUMULATE) && !a.store_wins) {
         hipError_t e = launch_fill_u32(seat_wins, (uint64_t)n_leaves * 4u, 0u, st);
         if (e != hipSuccess) return DVC_EHIP;
     }

@@ -36,6 +36,8 @@ struct RolloutArgs {
     int8_t *winner;
     int16_t *length;
     uint32_t *seat_wins;
+    uint32_t store_wins;             // variant 7, ppl dividing 256: store each leaf's sums
+                                     // (the table is not zeroed beforehand)
     unsigned long long *stats;       // optional: [0] += wave steps
 };
 

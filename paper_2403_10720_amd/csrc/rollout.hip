@@ -475,9 +475,12 @@ constexpr uint32_t kOutError = 0x7Fu;     // packed outcome of a malformed leaf
 
 // Outputs of playout jj (packed outcome `code`: winner | length << 2, or
 // kOutError), and the wave's seat wins summed per leaf with ballots, one
-// atomic per (leaf, seat) present.  Every lane of the wavefront takes part.
+// atomic per (leaf, seat) present: to the table, or with `lsum` to the
+// workgroup's LDS sums of leaves leaf0, leaf0 + 1, ...  Every lane of the
+// wavefront takes part.
 __device__ __forceinline__ void emit_outcome(const RolloutArgs &a, uint32_t jj, uint32_t code,
-                                             uint32_t lane)
+                                             uint32_t lane, uint32_t *lsum = nullptr,
+                                             uint32_t leaf0 = 0u)
 {
     const bool has = jj < a.total;
     const bool err = code == kOutError;
@@ -501,7 +504,10 @@ __device__ __forceinline__ void emit_outcome(const RolloutArgs &a, uint32_t jj, 
             const uint32_t c3 = (uint32_t)__popcll(__ballot(mineL && w == 3u));
             if (lane < 4u) {
                 const uint32_t c = lane == 0u ? c0 : lane == 1u ? c1 : lane == 2u ? c2 : c3;
-                if (c) atomicAdd(&a.seat_wins[(size_t)L * 4u + lane], c);
+                if (c) {
+                    if (lsum) atomicAdd(&lsum[(L - leaf0) * 4u + lane], c);
+                    else atomicAdd(&a.seat_wins[(size_t)L * 4u + lane], c);
+                }
             }
             fmask &= ~same;
         }
@@ -629,6 +635,7 @@ __global__ void __launch_bounds__(256) rollout_compact(RolloutArgs a)
     __shared__ uint32_t mig[7][256];       // packed state, playout id, round-1 key words
     __shared__ uint8_t outc[256];          // packed outcome per original slot
     __shared__ uint32_t wcnt[4];
+    __shared__ uint32_t lsum[256 * 4];     // store_wins: seat wins of the workgroup's leaves
     fill_kth_table(tab);
     const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
     const uint32_t base = blockIdx.x * 256u;
@@ -641,6 +648,10 @@ __global__ void __launch_bounds__(256) rollout_compact(RolloutArgs a)
     s.m = 0u; s.P = 2u; s.phase = 1u; s.drawn = -1;
     PlayoutKey pk = {0u, 0u, 0u, 0u};
     outc[tid] = (uint8_t)kOutError;
+    if (a.store_wins) {
+#pragma unroll
+        for (uint32_t q = 0; q < 4u; ++q) lsum[4u * tid + q] = 0u;
+    }
     if (j < a.total) {
         const uint32_t leaf = j / a.ppl;
         const uint4 st = a.leaves[leaf];
@@ -717,7 +728,19 @@ __global__ void __launch_bounds__(256) rollout_compact(RolloutArgs a)
         }
     }
     __syncthreads();   // every game's outcome is in outc
-    emit_outcome(a, base + tid, outc[tid], lane);
+    if (!a.store_wins) {
+        emit_outcome(a, base + tid, outc[tid], lane);
+        return;
+    }
+    // the workgroup holds whole leaves (ppl divides 256): sum them in LDS and
+    // store each leaf's four counts once, over whatever the table held
+    const uint32_t leaf0 = base / a.ppl;
+    emit_outcome(a, base + tid, outc[tid], lane, lsum, leaf0);
+    __syncthreads();
+    const uint32_t last = (base + 255u < a.total ? base + 255u : a.total - 1u) / a.ppl;
+    const uint32_t nw4 = 4u * (last - leaf0 + 1u);
+    if (a.seat_wins)
+        for (uint32_t e = tid; e < nw4; e += 256u) a.seat_wins[(size_t)leaf0 * 4u + e] = lsum[e];
 }
 
 // ---------------------------------------------------------------------------

@@ -176,16 +176,21 @@ def test_rollout_autotune(orc, dvc):
     assert dvc.dvc_check() == 0
 
 
-def test_rollout_accumulate(orc, dvc):
-    """Two calls with different seeds tally into one seat-win table."""
+@pytest.mark.parametrize("variant,ppl", [(0, 24), (7, 64), (7, 256)])
+def test_rollout_accumulate(orc, dvc, variant, ppl):
+    """Two calls with different seeds tally into one seat-win table (variant 7
+    with whole leaves per workgroup, which stores its sums when overwriting,
+    adds them here)."""
     po = orc.deal_params(p_min=2, p_max=4, pile_min=0, pile_max=16, revealed_max=8)
     S = orc.init_states(40, po, seed=8)
-    _, _, r1 = orc.rollout(S, 24, 1)
-    _, _, r2 = orc.rollout(S, 24, 2)
+    _, _, r1 = orc.rollout(S, ppl, 1)
+    _, _, r2 = orc.rollout(S, ppl, 2)
     st = dev_states(S)
     sw = torch.zeros((40, 4), dtype=torch.int32, device="cuda")
-    dvc.dvc_rollout(st, 24, 1, winner=False, length=False, seat_wins=sw, accumulate=True)
-    dvc.dvc_rollout(st, 24, 2, winner=False, length=False, seat_wins=sw, accumulate=True)
+    dvc.dvc_rollout(st, ppl, 1, winner=False, length=False, seat_wins=sw, accumulate=True,
+                    variant=variant)
+    dvc.dvc_rollout(st, ppl, 2, winner=False, length=False, seat_wins=sw, accumulate=True,
+                    variant=variant)
     assert np.array_equal(sw.cpu().numpy().view(np.uint32), r1 + r2)
 
 
@@ -267,7 +272,9 @@ def test_valu_probe(dvc):
 @pytest.mark.parametrize("ppl", [1, 3, 64, 100, 256, 300])
 def test_rollout_seat_wins_overwrite_the_table(orc, dvc, variant, ppl):
     """Without accumulate the seat-win table is overwritten (zeroed, then
-    added to): a table full of garbage beforehand must not show."""
+    added to; variant 7 with playouts per leaf dividing 256 stores each leaf's
+    sums without the zeroing): a table full of garbage beforehand must not
+    show."""
     po = orc.deal_params(p_min=2, p_max=4, pile_min=0, pile_max=16, revealed_max=8)
     n = 777
     S = orc.init_states(n, po, seed=12)
