@@ -9,6 +9,7 @@ float32 accumulation in a hardware order the oracle does not reproduce).
 * Adam: the GPU step equals the oracle's Adam applied to the GPU's own
   gradient (float32 vs double, 1e-5 relative);
 * training pairs: perspectives and labels bit-exact vs oracle playouts;
+* a training step is deterministic (fixed-order reductions): repeated runs agree bit for bit;
 * a few hundred steps on one batch drive its loss down (overfit check).
 """
 import math
@@ -95,6 +96,36 @@ def test_gradient_vs_oracle(orc, dvc):
     v = np.zeros_like(w)
     orc.vn_adam(w, m, v, g.copy(), 1, lr=1e-3)
     assert np.allclose(got, w, rtol=1e-5, atol=1e-7)
+
+
+@pytest.mark.parametrize("B", [32, 96, 8192])
+def test_training_step_is_deterministic(orc, dvc, B):
+    """Every reduction of a training step (split-K weight gradients over batch
+    slices, bias gradients and loss over row tiles) runs in a fixed order, so
+    the same steps from the same weights give bit-identical gradients, losses
+    and weights, whatever the scheduling of the workgroups."""
+    n = max(B, 4096)
+    S, q, y = _data(orc, n, 23)
+    st, qd, yd = _dev(S, q, y)
+    runs = []
+    for _ in range(2):
+        net = dvc.dvc_valuenet_init(44)
+        grad = torch.zeros(dvc.VALUENET_PARAMS, dtype=torch.float32, device="cuda")
+        loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+        ws, out = None, []
+        for step in range(1, 4):
+            ws = dvc.dvc_valuenet_train_step(net, st, qd, yd, step=step, lr=1e-3, batch=B,
+                                             perm_a=2654435761 if n > B else 1, perm_b=3,
+                                             row_base=(step - 1) * B, ws=ws, loss_out=loss,
+                                             grad_out=grad)
+            out.append((grad.cpu().numpy().copy(), loss.cpu().numpy().copy()))
+        runs.append((out, dvc.dvc_valuenet_get_params(net).cpu().numpy()))
+    (o1, p1), (o2, p2) = runs
+    for (g1, l1), (g2, l2) in zip(o1, o2):
+        assert np.array_equal(g1.view(np.uint32), g2.view(np.uint32))
+        assert np.array_equal(l1.view(np.uint32), l2.view(np.uint32))
+    assert np.array_equal(p1.view(np.uint32), p2.view(np.uint32))
+    assert dvc.dvc_check() == 0
 
 
 def test_labels_bit_exact(orc, dvc):
