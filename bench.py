@@ -150,10 +150,13 @@ def root_parallel_search(D, torch, reps=3):
             "decisions_per_s": n / (best / 1e3), "playouts_per_s": n * K * iters * ppl / (best / 1e3)}
 
 
-def single_tree_search(D, torch):
-    """Plain search: one fresh two-player deal, 2000 iterations x 16 playouts."""
+def single_tree_search(D, torch, leaves_per_pass=1):
+    """Plain search: one fresh two-player deal, 2000 iterations x 16 playouts.
+    leaves_per_pass 4: four descents per pass, their 64 playouts filling the
+    wavefront (a different, batched schedule of the same iterations)."""
     roots = D.dvc_init_states(1, D.deal_params(p_min=2, p_max=2, fresh=1, root_draw=1), 1)
-    mp = D.mcts_params(iterations=2000, playouts_per_leaf=16, max_depth=4)
+    mp = D.mcts_params(iterations=2000, playouts_per_leaf=16, max_depth=4,
+                       leaves_per_pass=leaves_per_pass)
     ws = torch.empty(D.dvc_mcts_workspace_bytes(1, mp), dtype=torch.uint8, device=roots.device)
     D.mcts_search(roots, mp, 1, workspace=ws, want_children=False)
     torch.cuda.synchronize()
@@ -163,7 +166,8 @@ def single_tree_search(D, torch):
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
-    return {"workload": "1 tree, fresh 2-player deal, 2000 iterations x 16 playouts",
+    return {"workload": "1 tree, fresh 2-player deal, 2000 iterations x 16 playouts" +
+                        (f", {leaves_per_pass} leaves per pass" if leaves_per_pass > 1 else ""),
             "ms_per_decision": ms, "decisions_per_s": 1e3 / ms}
 
 
@@ -332,6 +336,7 @@ def main():
         out["batched_search_leaf_batched"] = batched_search(D, torch, leaves_per_pass=2)
         out["root_parallel_search"] = root_parallel_search(D, torch)
         out["single_tree_search"] = single_tree_search(D, torch)
+        out["single_tree_search_leaf_batched"] = single_tree_search(D, torch, leaves_per_pass=4)
     if not args.no_cpu:
         threads = max(1, min(16, os.cpu_count() or 1))
         host_states = states.cpu().numpy().view(np.uint32)
