@@ -133,7 +133,7 @@ int dvc_rollout(const dvc_state_t *leaves, int64_t n_leaves, int32_t playouts_pe
 
 /* dvc_rollout with a choice of kernel, for measurement.  variant: 0 =
  * automatic (the shape dvc_rollout_autotune chose for this size class, else
- * below 4M playouts variant 7 with steps 5, 8, 11, 14; above, variant 5 if
+ * up to 4M playouts variant 7 with steps 5, 8, 11, 14; above, variant 5 if
  * playouts_per_leaf >= 256, else variant 1), 1 = one lane per playout,
  * 2 = lane refill + work stealing over LDS-staged leaf chunks, 3 = lane
  * refill + work stealing over single-leaf items, 4 = several playouts per

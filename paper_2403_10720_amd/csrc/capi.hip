@@ -194,13 +194,14 @@ static Shape automatic_shape(uint64_t total, int32_t ppl)
         auto it = g_tuned.find(tune_key(total, ppl));
         if (it != g_tuned.end()) return it->second;
     }
-    // measured on gfx950: below 4M playouts one playout per lane with the
+    // measured on gfx950: up to 4M playouts one playout per lane with the
     // workgroup's unfinished games compacted at steps 5, 8, 11, 14 (variant
-    // 7; 0.108 ms vs 0.122 ms for variant 4 at 1M playouts); from 4M on
-    // in-wave refill over 256-playout items when leaves have at least 256
-    // playouts (variant 5; 4.38 ms vs 5.01 ms for variant 7 at 64M), else
+    // 7; 0.108 ms vs 0.122 ms for variant 4 at 1M playouts, 0.339-0.393 ms vs
+    // 0.343-0.424 ms for variant 5 at 4M); beyond that in-wave refill over
+    // 256-playout items when leaves have at least 256 playouts (variant 5;
+    // 1.15-1.36 ms vs 1.27-1.42 ms at 16M, 4.38 ms vs 5.01 ms at 64M), else
     // one lane per playout (variant 1)
-    if (total < (4ull << 20)) return Shape{7, 0, 2};
+    if (total <= (4ull << 20)) return Shape{7, 0, 2};
     return ppl >= 256 ? Shape{5, 0, 4} : Shape{1, 0, 0};
 }
 
