@@ -99,8 +99,12 @@ __global__ void __launch_bounds__(kGenBlock) init_states_kernel(uint4 *out, uint
         const uint32_t nrev = d.fresh ? 0u : pick(word(), rmax + 1u);
         const bool mine = tile_lane && ((hq >> (lane & 31u)) & 1u);
         uint32_t slot = tile_lane ? (uint32_t)__popc(hq & ((1u << lane) - 1u)) : 0u;
+        // step k uses word nw + k; lane k picks its swap target
+        const uint32_t rw = (uint32_t)__shfl((int)words, (int)((nw + lane) & 63u), 64);
+        const uint32_t jr = lane < h ? lane + pick(rw, h - lane) : 0u;
+        nw += nrev;
         for (uint32_t k = 0; k < nrev; ++k) {
-            const uint32_t j = k + pick(word(), h - k);
+            const uint32_t j = __builtin_amdgcn_readlane(jr, k);
             slot = slot == k ? j : (slot == j ? k : slot);
         }
         rev |= (uint32_t)__ballot(mine && slot < nrev);
