@@ -13,16 +13,17 @@ SOURCES = ["rules.c", "mcts.c", "valuenet.c"]
 LIB = os.path.join(HERE, "liboracle.so")
 
 
-def build(verbose: bool = False) -> str:
-    srcs = [os.path.join(HERE, s) for s in SOURCES if os.path.exists(os.path.join(HERE, s))]
+def build(verbose: bool = False, src_dir: str = HERE, out: str = LIB) -> str:
+    """Compile the sources of `src_dir` (default: this folder) into `out`."""
+    srcs = [os.path.join(src_dir, s) for s in SOURCES if os.path.exists(os.path.join(src_dir, s))]
     cmd = ["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-mfpmath=sse",
            "-msse2", "-fPIC", "-shared", "-Wall", "-Wextra", "-Wno-unused-parameter",
-           "-o", LIB + ".tmp"] + srcs + ["-lm", "-lpthread"]
+           "-o", out + ".tmp"] + srcs + ["-lm", "-lpthread"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(out + ".tmp", out)
+    return out
 
 
 if __name__ == "__main__":
