@@ -13,7 +13,10 @@ prices the dominant kernel (the rollout kernel, one playout per lane at this
 size) against the integer-VALU issue peak of the chip; `cpu_baseline` is the
 CPU oracle timed on this host's cores on a bounded sample of the same
 workload.  Side figures: batched search, root-parallel search and a single
-tree, timed with HIP events.
+tree, timed with HIP events; `value_vs_rollout`: value-network training on
+pairs the rollout kernel labels (step time, TFLOP/s) and the value-network
+search against the pure-playout search on 1024 fresh deals x 4096 iterations
+(decisions/s of both, GPU-seconds ratio, root-move agreement).
 
 --copy-mib N additionally copies an N MiB device buffer three times after the
 timed steps: a kernel of known traffic, used to scale the HBM byte counters
@@ -35,7 +38,7 @@ DEAL = dict(p_min=2, p_max=2, pile_min=0, pile_max=16, revealed_max=8)
 # Integer VALU peak of MI355X, from its unit counts and clock: 256 CUs x 4
 # SIMDs x 32 lanes per clock x 2.4 GHz = 78.6 T lane-ops/s (the published
 # 157.3 TFLOP/s vector FP32 rate counts the same 32 lanes, an FMA as two).
-# The chip's own issue-rate probe (dvc_probe_valu: v_xor_b32 at 58 T/s) rules
+# The chip's own issue-rate probe (measure.probe_valu: v_xor_b32 at 58 T/s) rules
 # out the 16-lanes-per-clock figure (39.3 T).
 INT_VALU_PEAK = 256 * 4 * 32 * 2.4e9          # lane-ops/s
 # Algorithmic integer operations of one guess step, each weighted by its
@@ -87,6 +90,8 @@ def parse():
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-search", action="store_true", help="skip the tree-search figures")
+    ap.add_argument("--no-value", action="store_true",
+                    help="skip value-network training and the value-vs-playout search")
     ap.add_argument("--copy-mib", type=int, default=0, help="copy a buffer of this size (MiB)")
     ap.add_argument("--valu-probe", action="store_true",
                     help="also measure the issue rate of the integer operations of a guess step")
@@ -171,43 +176,106 @@ def single_tree_search(D, torch, leaves_per_pass=1):
             "ms_per_decision": ms, "decisions_per_s": 1e3 / ms}
 
 
-def cpu_baseline(states_np, threads):
-    """The oracle, as it stands, on this host: all 4096 leaves x 256 playouts,
-    leaves split over `threads` POSIX threads."""
+def value_vs_rollout():
+    """The learned evaluator end to end: 2^23 training pairs (2-4 player
+    mid-game states, labels = 256-playout win rates) generated by the rollout
+    kernel, 20 epochs of batch 8192 on the library's training kernels (Adam,
+    lr 1e-3), the network's MSE against 4096-playout estimates on 4096
+    held-out states, then 1024 fresh 2-4 player deals searched for 4096
+    iterations with the network at the leaves (64 fallback playouts when the
+    root player's value is within 0.05 of 1/2) and with 64 playouts per leaf:
+    decisions/s of both, the GPU-seconds ratio, root-move agreement next to
+    the agreement of two playout searches with different seeds.  Every search
+    is timed with HIP events, median of three launches after a warm-up."""
+    from paper_2403_10720_amd.experiments import compare
+    out, _ = compare(log=lambda m: None)
+    return out
+
+
+def host_cpu():
+    """(CPU model, physical cores among the CPUs this process may run on)."""
+    model, cores, phys, core = "unknown", set(), None, None
+    allowed = os.sched_getaffinity(0) if hasattr(os, "sched_getaffinity") else None
+    cpu = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                k, _, v = line.partition(":")
+                k, v = k.strip(), v.strip()
+                if k == "processor":
+                    cpu = int(v)
+                elif k == "model name" and model == "unknown":
+                    model = v
+                elif k == "physical id":
+                    phys = v
+                elif k == "core id":
+                    core = v
+                if k == "core id" and (allowed is None or cpu in allowed):
+                    cores.add((phys, core))
+    except OSError:
+        pass
+    n = len(cores) or len(allowed or []) or (os.cpu_count() or 1)
+    return model, n
+
+
+def _median_rate(fn, n_items, reps):
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        ts.append(time.perf_counter() - t0)
+    ts.sort()
+    return n_items / ts[len(ts) // 2], ts
+
+
+def cpu_baseline(states_np, reps=10):
+    """The oracle, as it stands, on this host.  Playouts/s on the full batch
+    (4096 leaves x 256 playouts) with the leaves split over one thread per
+    physical core (at most 16, this GPU's share of the host), and on 512 of
+    the leaves with one thread; median of `reps` runs each.  Also the single
+    tree search (one fresh two-player deal, 2000 iterations x 16 playouts), one
+    thread, median of 5."""
     import oracle
+    model, phys = host_cpu()
+    threads = max(1, min(16, phys))
     oracle.rollout(states_np[:64], 16, SEED)          # load + warm
-    t0 = time.perf_counter()
-    _, _, wins = oracle.rollout(states_np, PPL, SEED, threads=threads, want_winner=False,
-                                want_length=False)
-    dt = time.perf_counter() - t0
     n = states_np.shape[0] * PPL
-    # the single-tree search (one fresh two-player deal, 2000 iterations x 16
-    # playouts), one thread, as the GPU figure next to it
+    rate, ts = _median_rate(lambda: oracle.rollout(states_np, PPL, SEED, threads=threads,
+                                                   want_winner=False, want_length=False),
+                            n, reps)
+    sample = states_np[:512]
+    rate1, ts1 = _median_rate(lambda: oracle.rollout(sample, PPL, SEED, threads=1,
+                                                     want_winner=False, want_length=False),
+                              sample.shape[0] * PPL, reps)
     root = oracle.init_states(1, oracle.deal_params(p_min=2, p_max=2, fresh=1, root_draw=1), 1)
-    t1 = time.perf_counter()
-    oracle.mcts_search(root, oracle.mcts_params(iterations=2000, playouts_per_leaf=16, max_depth=4),
-                       1, 0)
-    dt1 = time.perf_counter() - t1
-    return {"value": n / dt, "unit": "playouts/s", "cores": threads, "kind": "oracle",
+    mp = oracle.mcts_params(iterations=2000, playouts_per_leaf=16, max_depth=4)
+    rate_t, _ = _median_rate(lambda: oracle.mcts_search(root, mp, 1, 0), 1, 5)
+    return {"value": rate, "unit": "playouts/s", "cores": threads, "kind": "oracle",
             "sample": f"{states_np.shape[0]} leaves x {PPL} playouts (the full batch), "
-                      f"{threads} threads, {dt:.2f} s",
-            "single_tree_ms_per_decision": dt1 * 1e3,
-            "single_tree_sample": "1 fresh 2-player deal, 2000 iterations x 16 playouts, 1 thread"}
+                      f"{threads} threads, median of {reps} runs ({ts[len(ts) // 2]:.3f} s)",
+            "cpu_model": model, "physical_cores": phys,
+            "single_thread": {"value": rate1, "unit": "playouts/s",
+                              "sample": f"512 leaves x {PPL} playouts, 1 thread, median of "
+                                        f"{reps} runs ({ts1[len(ts1) // 2]:.3f} s)"},
+            "single_tree_ms_per_decision": 1e3 / rate_t,
+            "single_tree_sample": "1 fresh 2-player deal, 2000 iterations x 16 playouts, "
+                                  "1 thread, median of 5"}
 
 
-def valu_probe(D, torch, iters=4096):
+def valu_probe(torch, iters=4096):
     """Issue rate (T lane-ops/s) of each integer operation of a guess step,
     eight waves per SIMD, eight independent chains per lane."""
+    from paper_2403_10720_amd import measure
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     blocks = cus * 8
     sink = torch.empty(blocks * 256, dtype=torch.int32, device="cuda")
     out = {}
-    for op, name in enumerate(D.VALU_PROBE_OPS):
-        D.dvc_probe_valu(op, blocks, 16, sink)
+    for op, name in enumerate(measure.OPS):
+        measure.probe_valu(op, blocks, 16, sink)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        D.dvc_probe_valu(op, blocks, iters, sink)
+        measure.probe_valu(op, blocks, iters, sink)
         e1.record()
         torch.cuda.synchronize()
         t = e0.elapsed_time(e1) / 1e3
@@ -330,17 +398,18 @@ def main():
         "wall_s": wall,
     }
     if args.valu_probe:
-        out["roofline"]["probe_TOPs"] = valu_probe(D, torch)
+        out["roofline"]["probe_TOPs"] = valu_probe(torch)
     if not args.no_search:
         out["batched_search"] = batched_search(D, torch)
         out["batched_search_leaf_batched"] = batched_search(D, torch, leaves_per_pass=2)
         out["root_parallel_search"] = root_parallel_search(D, torch)
         out["single_tree_search"] = single_tree_search(D, torch)
         out["single_tree_search_leaf_batched"] = single_tree_search(D, torch, leaves_per_pass=4)
+    if not args.no_value:
+        out["value_vs_rollout"] = value_vs_rollout()
     if not args.no_cpu:
-        threads = max(1, min(16, os.cpu_count() or 1))
         host_states = states.cpu().numpy().view(np.uint32)
-        out["cpu_baseline"] = cpu_baseline(host_states, threads)
+        out["cpu_baseline"] = cpu_baseline(host_states)
         if args.cpu_sweep:
             out["cpu_baseline"]["thread_sweep"] = cpu_thread_sweep(
                 host_states, 2 * (os.cpu_count() or 1))

@@ -42,6 +42,8 @@
  *     continue coin of a leaf reached right after a right guess (continue
  *     choice on, see dvc_mcts_params)
  *   synthetic state s, word n                           (n>>2, 0xFFFFFFFF, 0xFFFFFFFF, s)
+ *   value network: initial weight k (k>>2, 0xFFFFFFFE, 0, 0), training pair
+ *   perspective (0, 0xFFFFFFFC, 0, i), batch order of an epoch (e, 0xFFFFFFFD, 0, 0)
  */
 #ifndef DVC_H
 #define DVC_H
@@ -251,6 +253,13 @@ typedef struct {
     int32_t leaves_per_pass;    /* B: leaves evaluated together, 1..16 (value mode
                                    1..2); 1 = the sequential search              */
 } dvc_mcts_params;
+/* Automatic shape: with playout leaves, playouts_per_leaf = 0 together with
+ * leaves_per_pass = 0 asks for the shape dvc_mcts_autotune chose for this
+ * size class (device, floor(log2 n_trees), floor(log2 iterations), max_depth,
+ * continue_choice, vanilla), else 32 playouts per leaf with two leaves per
+ * pass (the fastest shape within two points of the sequential 32-playout
+ * search's seed-to-seed agreement, measured on 2048 mixed mid-game roots x
+ * 1024 iterations).  Such searches need iterations * 128 < 2^24.          */
 
 /* one root child, in creation order (vanilla: indexed by action id); action
  * 0xFFFF marks unused entries */
@@ -273,6 +282,36 @@ size_t dvc_mcts_workspace_bytes(int64_t n_trees, const dvc_mcts_params *params /
 int mcts_search(const dvc_state_t *roots, int64_t n_trees, const dvc_mcts_params *params /* host */,
                 uint64_t seed, uint32_t tree_id_base, void *workspace, size_t workspace_bytes,
                 int32_t *best_action, dvc_child_stat *root_children, void *stream);
+
+/* dvc_mcts_autotune -- picks playouts per leaf and leaves per pass for
+ * searches like this one (Sec. IV-B: the paper sweeps threads and warps for
+ * the simulations; here the leaf's playouts and the leaves evaluated together
+ * share the tree's 64 lanes).  params: playout leaves, playouts_per_leaf =
+ * the reference P_ref >= 1, leaves_per_pass = 1.  Runs the reference (the
+ * sequential search with P_ref playouts per leaf) under `seed` and under a
+ * second seed (seed ^ 0x9E3779B97F4A7C15); their root-move agreement is the
+ * ceiling A0.  Then every candidate (4 playouts x 1/2/4/8/16 leaves per pass,
+ * 8 x 1/2/4/8, 16 x 1/2/4, 32 x 1/2, 64 x 1, 128 x 1) runs once under seed + 1,
+ * timed by HIP events on `stream`, and is admitted when its agreement with the
+ * reference is at least A0 - tolerance.  The fastest admitted candidate (the
+ * reference shape when none is) is remembered for the size class (see the
+ * automatic shape above; a library-owned table guarded by a lock, kept until
+ * the process ends) and described in *result (host, may be NULL).
+ * best_action (device, n_trees) receives the chosen candidate's decisions.
+ * workspace as for mcts_search with iterations and variants of params.
+ * Synchronizes the stream; 18 searches of this size.  DVC_EINVAL for value
+ * leaves, leaves_per_pass != 1, n_trees < 1, a negative tolerance, or
+ * iterations * 128 >= 2^24; other errors as mcts_search.                   */
+typedef struct {
+    int32_t playouts_per_leaf, leaves_per_pass;   /* the choice                  */
+    float decisions_per_s;                        /* its measured rate           */
+    float agreement;                              /* its agreement with the reference */
+    float self_agreement;                         /* A0                           */
+} dvc_mcts_tuning;
+int dvc_mcts_autotune(const dvc_state_t *roots, int64_t n_trees, const dvc_mcts_params *params /* host */,
+                      uint64_t seed, uint32_t tree_id_base, void *workspace, size_t workspace_bytes,
+                      float tolerance, int32_t *best_action, dvc_mcts_tuning *result /* host */,
+                      void *stream);
 
 /* mcts_search_root_parallel -- the paper's decomposition (Sec. III-B): each
  * root is searched by trees_per_root (K, 1..65536) independent trees, tree
@@ -323,6 +362,12 @@ int dvc_valuenet_set_params(void *net, const float *params, void *stream);
 /* Copy the float32 parameters out (device, flat order). */
 int dvc_valuenet_get_params(const void *net, float *params, void *stream);
 
+/* Copy the Adam moments out (device, flat order, 107265 floats each): m, the
+ * decayed mean of the gradients, and v, the decayed mean of their squares,
+ * after the last dvc_valuenet_train_step (Kingma and Ba, 2015; zero after
+ * dvc_valuenet_init or dvc_valuenet_set_params).                          */
+int dvc_valuenet_get_moments(const void *net, float *m, float *v, void *stream);
+
 /* v_out[i] = value of states[i] for perspective seat persp[i] (< players).
  * A malformed state or perspective sets DVC_ESTATE in the error word.     */
 int dvc_valuenet_infer(const void *net, const dvc_state_t *states, const uint8_t *persp,
@@ -340,6 +385,16 @@ int dvc_valuenet_train_step(void *net, const dvc_state_t *states, const uint8_t 
                             uint32_t row_base, int32_t batch, int64_t step, float lr, void *ws,
                             size_t ws_bytes, float *loss_out, float *grad_out, void *stream);
 
+/* Batch order of training epoch `epoch` over n_data pairs (a power of two,
+ * 1..2^32): with w0, w1 words 0 and 1 of the Philox block (epoch,
+ * 0xFFFFFFFD, 0, 0) under `seed`, perm_a = (w0 | 1) mod n_data (odd, so
+ * i -> (perm_a*i + perm_b) mod n_data is a bijection; 1 when n_data is 1)
+ * and perm_b = w1 mod n_data, the values dvc_valuenet_train_step takes.
+ * Host outputs; no device work.  DVC_EINVAL for an epoch outside
+ * 0..2^32-1, an n_data that is not a power of two, or NULL outputs.       */
+int dvc_valuenet_epoch_order(uint64_t seed, int64_t epoch, int64_t n_data,
+                             uint32_t *perm_a /* host */, uint32_t *perm_b /* host */);
+
 /* Training pairs: for state i (index index_base + i) a perspective seat q =
  * floor(w * P / 2^32) with w word 0 of block (0, 0xFFFFFFFC, 0, index_base+i),
  * and label = (playouts of the state won by q) / playouts, from `playouts`
@@ -348,16 +403,6 @@ int dvc_valuenet_train_step(void *net, const dvc_state_t *states, const uint8_t 
 int dvc_valuenet_labels(const dvc_state_t *states, int64_t n, int32_t playouts, uint64_t seed,
                         uint32_t tree_id, uint32_t index_base, uint8_t *persp_out,
                         float *labels_out, uint32_t *seat_wins_ws, void *stream);
-
-/* dvc_probe_valu -- measurement aid for the integer roofline: launches
- * `blocks` workgroups of 256 lanes; every lane issues iters * 64 operations
- * of one kind in eight independent chains (op 0 v_xor_b32, 1 v_add_u32,
- * 2 v_mul_hi_u32, 3 v_mad_u64_u32, 4 v_bitop3_b32 (three-input xor), 5
- * v_bcnt_u32_b32) and writes one folded word to sink[lane] (device, blocks *
- * 256 words).  Time it with events on `stream` to get the device's issue rate
- * of that operation.  DVC_EINVAL for an unknown op, blocks outside 1..65536,
- * iters < 1 or a NULL sink.                                                  */
-int dvc_probe_valu(int32_t op, int64_t blocks, int32_t iters, uint32_t *sink, void *stream);
 
 /* ---------------------------------------------------------------------------
  * Status

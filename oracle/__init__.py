@@ -99,7 +99,7 @@ def lib():
         L.oracle_vn_forward.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int,
                                         C.c_void_p]
         L.oracle_vn_loss_grad.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
-                                          C.c_int, C.POINTER(C.c_double), C.c_void_p]
+                                          C.c_int, C.POINTER(C.c_double), C.c_void_p, C.c_void_p]
         L.oracle_vn_adam.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                                      C.c_int64, C.c_double, C.c_double, C.c_double, C.c_double]
         L.oracle_vn_init.argtypes = [C.c_void_p, C.c_uint64]
@@ -351,18 +351,22 @@ def vn_forward(params, states, persp, bf16_mirror: bool = False) -> np.ndarray:
     return v
 
 
-def vn_loss_grad(params, states, persp, labels, bf16_mirror: bool = False):
+def vn_loss_grad(params, states, persp, labels, bf16_mirror: bool = False,
+                 want_abs: bool = False):
+    """(loss, gradient), plus with want_abs the per-parameter sum of the
+    absolute values of the gradient's per-row terms."""
     p = np.ascontiguousarray(params, dtype=np.float32)
     s = _states(states)
     q = np.ascontiguousarray(persp, dtype=np.int32)
     y = np.ascontiguousarray(labels, dtype=np.float32)
     g = np.zeros(VN_NPARAM, np.float64)
+    ga = np.zeros(VN_NPARAM, np.float64) if want_abs else None
     loss = C.c_double(0.0)
     rc = lib().oracle_vn_loss_grad(_ptr(p), _ptr(s), _ptr(q), _ptr(y), s.shape[0],
-                                   int(bf16_mirror), C.byref(loss), _ptr(g))
+                                   int(bf16_mirror), C.byref(loss), _ptr(g), _ptr(ga))
     if rc:
         raise ValueError(f"loss_grad failed ({rc})")
-    return loss.value, g
+    return (loss.value, g, ga) if want_abs else (loss.value, g)
 
 
 def vn_adam(w, m, v, g, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):

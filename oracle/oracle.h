@@ -158,7 +158,8 @@ int oracle_vn_encode(const orc_packed *s, int32_t q, float feat[160]);
 int oracle_vn_forward(const float *params, const orc_packed *states, const int32_t *persp,
                       int64_t n, int bf16, double *v_out);
 int oracle_vn_loss_grad(const float *params, const orc_packed *states, const int32_t *persp,
-                        const float *labels, int64_t n, int bf16, double *loss, double *grad);
+                        const float *labels, int64_t n, int bf16, double *loss, double *grad,
+                        double *grad_abs);
 void oracle_vn_adam(double *w, double *m, double *v, const double *g, int64_t n, int64_t t,
                     double lr, double b1, double b2, double eps);
 void oracle_vn_init(float *params, uint64_t seed);

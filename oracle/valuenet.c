@@ -90,24 +90,39 @@ typedef struct {
     double z, v;
 } vn_row;
 
-static void forward_row(const float *P, const float *x, int bf16, vn_row *o)
+/* The weights the products read: W1, W2 and w3 rounded to bfloat16 in the
+ * mirror mode (each weight is rounded the same way wherever it is read, so
+ * rounding them once per call gives the same values as rounding at every
+ * use), the float parameters otherwise.  Biases stay float.               */
+static double *product_weights(const float *P, int bf16)
+{
+    double *Q = (double *)malloc(VN_NPARAM * sizeof(double));
+    for (int k = 0; k < VN_NPARAM; ++k) {
+        const int is_bias = (k >= OFF_B1 && k < OFF_W2) || (k >= OFF_B2 && k < OFF_W3) || k == OFF_B3;
+        Q[k] = is_bias ? (double)P[k] : rnd(P[k], bf16);
+    }
+    return Q;
+}
+
+/* Q: product_weights() of the parameters */
+static void forward_row(const double *Q, const float *x, int bf16, vn_row *o)
 {
     for (int i = 0; i < VN_IN; ++i) o->x[i] = x[i];
     for (int k = 0; k < VN_H; ++k) {
         double acc = 0.0;
-        for (int i = 0; i < VN_IN; ++i) acc += rnd(P[OFF_W1 + k * VN_IN + i], bf16) * o->x[i];
-        o->a1[k] = acc + P[OFF_B1 + k];
+        for (int i = 0; i < VN_IN; ++i) acc += Q[OFF_W1 + k * VN_IN + i] * o->x[i];
+        o->a1[k] = acc + Q[OFF_B1 + k];
         o->h1[k] = rnd(o->a1[k] > 0.0 ? o->a1[k] : 0.0, bf16);
     }
     for (int k = 0; k < VN_H; ++k) {
         double acc = 0.0;
-        for (int i = 0; i < VN_H; ++i) acc += rnd(P[OFF_W2 + k * VN_H + i], bf16) * o->h1[i];
-        o->a2[k] = acc + P[OFF_B2 + k];
+        for (int i = 0; i < VN_H; ++i) acc += Q[OFF_W2 + k * VN_H + i] * o->h1[i];
+        o->a2[k] = acc + Q[OFF_B2 + k];
         o->h2[k] = rnd(o->a2[k] > 0.0 ? o->a2[k] : 0.0, bf16);
     }
     double acc = 0.0;
-    for (int i = 0; i < VN_H; ++i) acc += rnd(P[OFF_W3 + i], bf16) * o->h2[i];
-    o->z = acc + P[OFF_B3];
+    for (int i = 0; i < VN_H; ++i) acc += Q[OFF_W3 + i] * o->h2[i];
+    o->z = acc + Q[OFF_B3];
     o->v = 1.0 / (1.0 + exp(-o->z));
 }
 
@@ -116,40 +131,51 @@ int oracle_vn_forward(const float *params, const orc_packed *states, const int32
 {
     float x[VN_IN];
     vn_row *o = (vn_row *)malloc(sizeof(vn_row));
-    for (int64_t i = 0; i < n; ++i) {
+    double *Q = product_weights(params, bf16);
+    int rc = 0;
+    for (int64_t i = 0; i < n && rc == 0; ++i) {
         if (oracle_vn_encode(&states[i], persp[i], x)) {
-            free(o);
-            return -2;
+            rc = -2;
+            break;
         }
-        forward_row(params, x, bf16, o);
+        forward_row(Q, x, bf16, o);
         v_out[i] = o->v;
     }
+    free(Q);
     free(o);
-    return 0;
+    return rc;
 }
 
-/* loss = mean over rows of (v - y)^2 and its gradient w.r.t. every parameter */
+/* loss = mean over rows of (v - y)^2 and its gradient w.r.t. every parameter.
+ * grad_abs (may be NULL) receives, per parameter, the sum of the absolute
+ * values of the per-row terms that make up its gradient: the scale against
+ * which a gradient summed in another order, or with an operand rounded the
+ * other way, is judged.                                                    */
 int oracle_vn_loss_grad(const float *params, const orc_packed *states, const int32_t *persp,
-                        const float *labels, int64_t n, int bf16, double *loss, double *grad)
+                        const float *labels, int64_t n, int bf16, double *loss, double *grad,
+                        double *grad_abs)
 {
     float x[VN_IN];
     vn_row *o = (vn_row *)malloc(sizeof(vn_row));
+    double *Q = product_weights(params, bf16);
     double dh2[VN_H], dh1[VN_H];
     memset(grad, 0, VN_NPARAM * sizeof(double));
+    if (grad_abs) memset(grad_abs, 0, VN_NPARAM * sizeof(double));
     double L = 0.0;
+    int rc = 0;
     for (int64_t r = 0; r < n; ++r) {
         if (oracle_vn_encode(&states[r], persp[r], x)) {
-            free(o);
-            return -2;
+            rc = -2;
+            break;
         }
-        forward_row(params, x, bf16, o);
+        forward_row(Q, x, bf16, o);
         double e = o->v - (double)labels[r];
         L += e * e;
         double dz = 2.0 * e / (double)n * o->v * (1.0 - o->v);
         grad[OFF_B3] += dz;
         for (int i = 0; i < VN_H; ++i) {
             grad[OFF_W3 + i] += dz * o->h2[i];
-            double d = dz * rnd(params[OFF_W3 + i], bf16);
+            double d = dz * Q[OFF_W3 + i];
             dh2[i] = rnd(o->a2[i] > 0.0 ? d : 0.0, bf16);
         }
         for (int k = 0; k < VN_H; ++k) {
@@ -158,17 +184,30 @@ int oracle_vn_loss_grad(const float *params, const orc_packed *states, const int
         }
         for (int i = 0; i < VN_H; ++i) {
             double acc = 0.0;
-            for (int k = 0; k < VN_H; ++k) acc += dh2[k] * rnd(params[OFF_W2 + k * VN_H + i], bf16);
+            for (int k = 0; k < VN_H; ++k) acc += dh2[k] * Q[OFF_W2 + k * VN_H + i];
             dh1[i] = rnd(o->a1[i] > 0.0 ? acc : 0.0, bf16);
         }
         for (int k = 0; k < VN_H; ++k) {
             grad[OFF_B1 + k] += dh1[k];
             for (int i = 0; i < VN_IN; ++i) grad[OFF_W1 + k * VN_IN + i] += dh1[k] * o->x[i];
         }
+        if (grad_abs) {
+            grad_abs[OFF_B3] += fabs(dz);
+            for (int i = 0; i < VN_H; ++i) grad_abs[OFF_W3 + i] += fabs(dz * o->h2[i]);
+            for (int k = 0; k < VN_H; ++k) {
+                grad_abs[OFF_B2 + k] += fabs(dh2[k]);
+                for (int i = 0; i < VN_H; ++i)
+                    grad_abs[OFF_W2 + k * VN_H + i] += fabs(dh2[k] * o->h1[i]);
+                grad_abs[OFF_B1 + k] += fabs(dh1[k]);
+                for (int i = 0; i < VN_IN; ++i)
+                    grad_abs[OFF_W1 + k * VN_IN + i] += fabs(dh1[k] * o->x[i]);
+            }
+        }
     }
     *loss = L / (double)n;
+    free(Q);
     free(o);
-    return 0;
+    return rc;
 }
 
 /* one Adam step on double copies of the parameters and moments (t >= 1) */

@@ -43,6 +43,12 @@ class MctsParams(C.Structure):
                 ("leaves_per_pass", C.c_int32)]
 
 
+class MctsTuning(C.Structure):
+    _fields_ = [("playouts_per_leaf", C.c_int32), ("leaves_per_pass", C.c_int32),
+                ("decisions_per_s", C.c_float), ("agreement", C.c_float),
+                ("self_agreement", C.c_float)]
+
+
 def deal_params(p_min=2, p_max=2, hand=(0, 0, 4, 4, 3), pile_min=0, pile_max=16,
                 revealed_max=8, fresh=0, root_draw=0, phase_mix=0) -> DealParams:
     d = DealParams()
@@ -91,11 +97,12 @@ def lib():
         L.dvc_rollout_ex.argtypes = [vp, i64, i32, u64, u32, u32, vp, vp, vp, i32, i32, i32, i32,
                                      vp]
         L.dvc_rollout_autotune.argtypes = [vp, i64, i32, u64, u32, u32, vp, vp, vp, vp, vp]
-        L.dvc_probe_valu.argtypes = [i32, i64, i32, vp, vp]
         L.dvc_valuenet_bytes.restype = C.c_size_t
         L.dvc_valuenet_init.argtypes = [vp, u64, vp]
         L.dvc_valuenet_set_params.argtypes = [vp, vp, vp]
         L.dvc_valuenet_get_params.argtypes = [vp, vp, vp]
+        L.dvc_valuenet_get_moments.argtypes = [vp, vp, vp, vp]
+        L.dvc_valuenet_epoch_order.argtypes = [u64, i64, i64, C.POINTER(u32), C.POINTER(u32)]
         L.dvc_valuenet_infer.argtypes = [vp, vp, vp, i64, vp, vp]
         L.dvc_valuenet_train_workspace_bytes.restype = C.c_size_t
         L.dvc_valuenet_train_workspace_bytes.argtypes = [i64]
@@ -109,6 +116,8 @@ def lib():
                                       vp, vp, vp]
             L.mcts_search_root_parallel.argtypes = [vp, i64, i32, C.POINTER(MctsParams), u64, u32,
                                                     vp, C.c_size_t, vp, vp, vp]
+            L.dvc_mcts_autotune.argtypes = [vp, i64, C.POINTER(MctsParams), u64, u32, vp,
+                                            C.c_size_t, C.c_float, vp, C.POINTER(MctsTuning), vp]
         _lib = L
     return _lib
 
@@ -223,16 +232,6 @@ def dvc_rollout_autotune(leaves: torch.Tensor, playouts_per_leaf: int, seed: int
     return (chosen[0], chosen[1], chosen[2]), (w, ln, sw)
 
 
-VALU_PROBE_OPS = ["v_xor_b32", "v_add_u32", "v_mul_hi_u32", "v_mad_u64_u32", "v_bitop3_b32",
-                  "v_bcnt_u32_b32"]
-
-
-def dvc_probe_valu(op: int, blocks: int, iters: int, sink: torch.Tensor, stream=None):
-    """Launch the integer issue-rate probe (see dvc.h); sink: int32 [blocks * 256]."""
-    _check_dev(sink, torch.int32, (blocks * 256,), "sink")
-    _raise(lib().dvc_probe_valu(op, blocks, iters, _ptr(sink), _stream(stream)), "dvc_probe_valu")
-
-
 def dvc_mcts_workspace_bytes(n_trees: int, params: MctsParams) -> int:
     return int(lib().dvc_mcts_workspace_bytes(n_trees, C.byref(params)))
 
@@ -255,6 +254,26 @@ def mcts_search(roots: torch.Tensor, params: MctsParams, seed: int, tree_id_base
                            _stream(stream))
     _raise(rc, "mcts_search")
     return best, kids
+
+
+def dvc_mcts_autotune(roots: torch.Tensor, params: MctsParams, seed: int, tree_id_base: int = 0,
+                      tolerance: float = 0.02, workspace=None, stream=None):
+    """Pick playouts per leaf x leaves per pass for searches of this size class
+    (see include/dvc.h).  Returns (choice dict, decisions of the chosen shape)."""
+    _check_dev(roots, torch.int32, None, "roots")
+    n = roots.shape[0]
+    need = dvc_mcts_workspace_bytes(n, params)
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=roots.device)
+    best = torch.empty(n, dtype=torch.int32, device=roots.device)
+    res = MctsTuning()
+    rc = lib().dvc_mcts_autotune(_ptr(roots), n, C.byref(params), seed & (2**64 - 1), tree_id_base,
+                                 _ptr(workspace), workspace.numel(), tolerance, _ptr(best),
+                                 C.byref(res), _stream(stream))
+    _raise(rc, "dvc_mcts_autotune")
+    return ({"playouts_per_leaf": res.playouts_per_leaf, "leaves_per_pass": res.leaves_per_pass,
+             "decisions_per_s": res.decisions_per_s, "agreement": res.agreement,
+             "self_agreement": res.self_agreement}, best)
 
 
 def mcts_search_root_parallel(roots: torch.Tensor, trees_per_root: int, params: MctsParams,
@@ -341,6 +360,15 @@ def dvc_valuenet_get_params(net, stream=None) -> torch.Tensor:
     return out
 
 
+def dvc_valuenet_get_moments(net, stream=None):
+    """(m, v): the Adam moments in the flat parameter order."""
+    m = torch.empty(VALUENET_PARAMS, dtype=torch.float32, device=net.device)
+    v = torch.empty(VALUENET_PARAMS, dtype=torch.float32, device=net.device)
+    _raise(lib().dvc_valuenet_get_moments(_ptr(net), _ptr(m), _ptr(v), _stream(stream)),
+           "dvc_valuenet_get_moments")
+    return m, v
+
+
 def dvc_valuenet_infer(net, states: torch.Tensor, persp: torch.Tensor, out=None, stream=None):
     _check_dev(states, torch.int32, None, "states")
     _check_dev(persp, torch.uint8, (states.shape[0],), "persp")
@@ -350,6 +378,14 @@ def dvc_valuenet_infer(net, states: torch.Tensor, persp: torch.Tensor, out=None,
     _raise(lib().dvc_valuenet_infer(_ptr(net), _ptr(states), _ptr(persp), n, _ptr(out),
                                     _stream(stream)), "dvc_valuenet_infer")
     return out
+
+
+def dvc_valuenet_epoch_order(seed: int, epoch: int, n_data: int):
+    """(perm_a, perm_b) of an epoch's batch order (Philox, see include/dvc.h)."""
+    a, b = C.c_uint32(0), C.c_uint32(0)
+    _raise(lib().dvc_valuenet_epoch_order(seed & (2**64 - 1), epoch, n_data, C.byref(a),
+                                          C.byref(b)), "dvc_valuenet_epoch_order")
+    return a.value, b.value
 
 
 def dvc_valuenet_train_workspace_bytes(batch: int) -> int:

@@ -1,4 +1,5 @@
-"""Build the gfx950 HIP library libdvc.so in place (next to this file).
+"""Build the gfx950 HIP library libdvc.so in place (next to this file), and
+the measurement library measure/libvalu_probe.so.
 
 hipcc --offload-arch=gfx950, one translation unit (csrc/dvc_lib.hip),
 -ffp-contract=off so that single-precision UCT arithmetic rounds once per
@@ -14,6 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc", "dvc_lib.hip")
 LIB = os.path.join(HERE, "libdvc.so")
+PROBE_SRC = os.path.join(HERE, "measure", "valu_probe.hip")
+PROBE_LIB = os.path.join(HERE, "measure", "libvalu_probe.so")
 
 
 def hipcc() -> str:
@@ -30,12 +33,17 @@ def flags(arch: str = "gfx950"):
             "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include")]
 
 
-def build(verbose: bool = False, extra=()) -> str:
-    cmd = [hipcc()] + flags() + list(extra) + ["-o", LIB + ".tmp", SRC]
+def _compile(src: str, out: str, verbose: bool, extra=()):
+    cmd = [hipcc()] + flags() + list(extra) + ["-o", out + ".tmp", src]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
+    os.replace(out + ".tmp", out)
+
+
+def build(verbose: bool = False, extra=()) -> str:
+    _compile(SRC, LIB, verbose, extra)
+    _compile(PROBE_SRC, PROBE_LIB, verbose, extra)
     return LIB
 
 

@@ -78,6 +78,7 @@ static const float *ln_table(uint64_t need, int *status)
         return nullptr;
     }
     if (hipMemcpy(p, g_ln_host.data(), cap * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(p);   // never handed out; the copy failure is what gets reported
         *status = DVC_EHIP;
         return nullptr;
     }
@@ -86,25 +87,110 @@ static const float *ln_table(uint64_t need, int *status)
     return p;
 }
 
+// Philox4x32-10 on the host (Salmon et al., SC'11), for the few words the
+// host itself draws: ten rounds of two 32x32->64 multiplies, the key advanced
+// by the Weyl constants between rounds.
+static void philox_host(const uint32_t ctr[4], uint32_t k0, uint32_t k1, uint32_t out[4])
+{
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)x0 * 0xD2511F53u, p1 = (uint64_t)x2 * 0xCD9E8D57u;
+        const uint32_t y0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0, y2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+        x1 = (uint32_t)p1;
+        x3 = (uint32_t)p0;
+        x0 = y0;
+        x2 = y2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = x0;
+    out[1] = x1;
+    out[2] = x2;
+    out[3] = x3;
+}
+
+// playouts per leaf x leaves per pass candidates of the search autotuner:
+// every pass holds at most 64 playouts (the tree's wavefront), plus one leaf
+// per pass with 64 and 128 playouts
+struct SearchShape {
+    int32_t ppl, lpp;
+};
+static const SearchShape kSearchCandidates[] = {
+    {4, 1}, {4, 2}, {4, 4}, {4, 8}, {4, 16}, {8, 1}, {8, 2}, {8, 4}, {8, 8}, {16, 1},
+    {16, 2}, {16, 4}, {32, 1}, {32, 2}, {64, 1}, {128, 1}};
+constexpr int32_t kAutoMaxPpl = 128;
+
+static bool is_auto(const dvc_mcts_params *p)
+{
+    return p->leaf_eval == 0 && p->playouts_per_leaf == 0 && p->leaves_per_pass == 0;
+}
+
 static bool mcts_params_ok(const dvc_mcts_params *p)
 {
     if (p == nullptr) return false;
-    if (p->iterations < 1 || p->playouts_per_leaf < 1 || p->max_depth < 0 || p->max_depth > 64)
+    const bool aut = is_auto(p);
+    if (p->iterations < 1 || (p->playouts_per_leaf < 1 && !aut) || p->max_depth < 0 ||
+        p->max_depth > 64)
         return false;
     if ((p->continue_choice != 0 && p->continue_choice != 1) || (p->vanilla != 0 && p->vanilla != 1))
         return false;
     // leaves evaluated together: value mode fits two leaves' perspectives in
     // one matrix tile, playout mode packs up to 16 leaves' playouts
-    if (p->leaves_per_pass < 1 || p->leaves_per_pass > (p->leaf_eval ? 2 : 16)) return false;
+    if (!aut && (p->leaves_per_pass < 1 || p->leaves_per_pass > (p->leaf_eval ? 2 : 16)))
+        return false;
     if (!(p->c_uct >= 0.0f) || std::isinf(p->c_uct)) return false;
     if (p->leaf_eval != 0 && p->leaf_eval != 1) return false;
     if (p->leaf_eval == 1 && (p->valuenet == nullptr || !aligned16(p->valuenet) ||
                               p->fallback_playouts < 1 || !(p->fallback_band >= 0.0f)))
         return false;
-    // visit counts stay exact in float
-    const uint64_t w_leaf = (uint64_t)(p->leaf_eval ? p->fallback_playouts : p->playouts_per_leaf);
+    // visit counts stay exact in float (an automatic shape may take up to
+    // kAutoMaxPpl playouts per leaf)
+    const uint64_t w_leaf = (uint64_t)(p->leaf_eval ? p->fallback_playouts
+                                       : aut ? kAutoMaxPpl : p->playouts_per_leaf);
     if ((uint64_t)p->iterations * w_leaf >= (1ull << 24)) return false;
     return true;
+}
+
+// the autotuner's choices: (device, log2 trees, log2 iterations, max depth,
+// continue choice, vanilla) -> (playouts per leaf, leaves per pass)
+static std::mutex g_search_tune_mutex;
+static std::map<std::tuple<int, int, int, int, int, int>, SearchShape> g_search_tuned;
+
+static int floor_log2(uint64_t x)
+{
+    int lg = 0;
+    while ((2ull << lg) <= x) ++lg;
+    return lg;
+}
+
+static std::tuple<int, int, int, int, int, int> search_key(int64_t n_trees,
+                                                           const dvc_mcts_params *p)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = -1;
+    return std::make_tuple(dev, floor_log2((uint64_t)(n_trees > 0 ? n_trees : 1)),
+                           floor_log2((uint64_t)p->iterations), p->max_depth, p->continue_choice,
+                           p->vanilla);
+}
+
+// The parameters a search runs with: automatic playouts per leaf and leaves
+// per pass (both 0, playout leaves) become the autotuner's choice for this
+// size class, else 32 playouts with two leaves per pass (the fastest shape
+// within two points of the sequential 32-playout search's self-agreement on
+// 2048 mixed mid-game roots x 1024 iterations, measured on gfx950).
+static dvc_mcts_params resolved(const dvc_mcts_params *p, int64_t n_trees)
+{
+    dvc_mcts_params r = *p;
+    if (!is_auto(p)) return r;
+    SearchShape sh{32, 2};
+    {
+        std::lock_guard<std::mutex> lock(g_search_tune_mutex);
+        auto it = g_search_tuned.find(search_key(n_trees, p));
+        if (it != g_search_tuned.end()) sh = it->second;
+    }
+    r.playouts_per_leaf = sh.ppl;
+    r.leaves_per_pass = sh.lpp;
+    return r;
 }
 
 }  // namespace dvc
@@ -349,12 +435,15 @@ size_t dvc_mcts_workspace_bytes(int64_t n_trees, const dvc_mcts_params *params)
 // merge = false: one tree per root, statistics in creation order;
 // merge = true: trees_per_root trees per root amalgamated by action id
 static int run_search(const dvc_state_t *roots, int64_t n_roots, int64_t trees_per_root, bool merge,
-                      const dvc_mcts_params *params, uint64_t seed, uint32_t tree_id_base,
+                      const dvc_mcts_params *user_params, uint64_t seed, uint32_t tree_id_base,
                       void *workspace, size_t workspace_bytes, int32_t *best_action,
                       dvc_child_stat *children, void *stream)
 {
-    if (n_roots < 0 || trees_per_root < 1 || trees_per_root > 65536 || !mcts_params_ok(params))
+    if (n_roots < 0 || trees_per_root < 1 || trees_per_root > 65536 ||
+        !mcts_params_ok(user_params))
         return DVC_EINVAL;
+    const dvc_mcts_params rp = resolved(user_params, n_roots * trees_per_root);
+    const dvc_mcts_params *params = &rp;
     if (merge && params->vanilla) return DVC_EINVAL;   // world nodes are not merged
     const int64_t n_trees = n_roots * trees_per_root;
     if (n_trees >= (1ll << 31)) return DVC_EINVAL;
@@ -396,6 +485,96 @@ int mcts_search(const dvc_state_t *roots, int64_t n_trees, const dvc_mcts_params
                       best_action, root_children, stream);
 }
 
+int dvc_mcts_autotune(const dvc_state_t *roots, int64_t n_trees, const dvc_mcts_params *params,
+                      uint64_t seed, uint32_t tree_id_base, void *workspace, size_t workspace_bytes,
+                      float tolerance, int32_t *best_action, dvc_mcts_tuning *result,
+                      void *stream)
+{
+    if (params == nullptr || params->leaf_eval != 0 || params->playouts_per_leaf < 1 ||
+        params->leaves_per_pass != 1 || n_trees < 1 || !(tolerance >= 0.0f) ||
+        best_action == nullptr)
+        return DVC_EINVAL;
+    dvc_mcts_params cand = *params;
+    cand.playouts_per_leaf = kAutoMaxPpl;   // every candidate's visit counts stay exact
+    if (!mcts_params_ok(params) || !mcts_params_ok(&cand)) return DVC_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    const size_t n = (size_t)n_trees;
+    std::vector<int32_t> ref(n), ref2(n), got(n), chosen_dec(n);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);   // cleanup: the failure is already reported
+        return DVC_EHIP;
+    }
+    // one search with its decisions copied to `out` and its time in *ms
+    auto run = [&](const dvc_mcts_params &mp, uint64_t sd, std::vector<int32_t> &out,
+                   float *ms) -> int {
+        if (hipEventRecord(e0, st) != hipSuccess) return DVC_EHIP;
+        int rc = run_search(roots, n_trees, 1, false, &mp, sd, tree_id_base, workspace,
+                            workspace_bytes, best_action, nullptr, stream);
+        if (rc != DVC_OK) return rc;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+            return DVC_EHIP;
+        if (ms && hipEventElapsedTime(ms, e0, e1) != hipSuccess) return DVC_EHIP;
+        if (hipMemcpy(out.data(), best_action, n * sizeof(int32_t), hipMemcpyDeviceToHost) !=
+            hipSuccess)
+            return DVC_EHIP;
+        return DVC_OK;
+    };
+    auto agreement = [&](const std::vector<int32_t> &a, const std::vector<int32_t> &b) {
+        size_t k = 0;
+        for (size_t i = 0; i < n; ++i) k += a[i] == b[i];
+        return (float)k / (float)n;
+    };
+    // the reference: the sequential search with the caller's playouts per
+    // leaf, under the caller's seed and under a second seed
+    int status = run(*params, seed, ref, nullptr);
+    if (status == DVC_OK) status = run(*params, seed ^ 0x9E3779B97F4A7C15ull, ref2, nullptr);
+    const float ceiling = status == DVC_OK ? agreement(ref, ref2) : 0.0f;
+    SearchShape best{params->playouts_per_leaf, 1};
+    float best_ms = 0.0f, best_agree = 0.0f;
+    bool have = false;
+    for (const SearchShape &c : kSearchCandidates) {
+        if (status != DVC_OK) break;
+        cand.playouts_per_leaf = c.ppl;
+        cand.leaves_per_pass = c.lpp;
+        float ms = 0.0f;
+        // candidates run under a third seed, so that the caller's own shape is
+        // judged like the others (its agreement is then the seed-to-seed one)
+        status = run(cand, seed + 1u, got, &ms);
+        if (status != DVC_OK) break;
+        const float agree = agreement(got, ref);
+        if (agree + tolerance >= ceiling && (!have || ms < best_ms)) {
+            best = c;
+            best_ms = ms;
+            best_agree = agree;
+            chosen_dec = got;
+            have = true;
+        }
+    }
+    (void)hipEventDestroy(e0);   // the timing is done; a failure here changes nothing
+    (void)hipEventDestroy(e1);
+    if (status != DVC_OK) return status;
+    if (!have) {   // no candidate within the tolerance: the caller's own shape
+        chosen_dec = ref;
+        best_agree = 1.0f;
+    }
+    if (hipMemcpy(best_action, chosen_dec.data(), n * sizeof(int32_t), hipMemcpyHostToDevice) !=
+        hipSuccess)
+        return DVC_EHIP;
+    {
+        std::lock_guard<std::mutex> lock(g_search_tune_mutex);
+        g_search_tuned[search_key(n_trees, params)] = best;
+    }
+    if (result) {
+        result->playouts_per_leaf = best.ppl;
+        result->leaves_per_pass = best.lpp;
+        result->decisions_per_s = have ? (float)((double)n_trees / (best_ms * 1e-3)) : 0.0f;
+        result->agreement = best_agree;
+        result->self_agreement = ceiling;
+    }
+    return DVC_OK;
+}
+
 int mcts_search_root_parallel(const dvc_state_t *roots, int64_t n_roots, int32_t trees_per_root,
                               const dvc_mcts_params *params, uint64_t seed, uint32_t tree_id_base,
                               void *workspace, size_t workspace_bytes, int32_t *best_action,
@@ -403,14 +582,6 @@ int mcts_search_root_parallel(const dvc_state_t *roots, int64_t n_roots, int32_t
 {
     return run_search(roots, n_roots, trees_per_root, true, params, seed, tree_id_base, workspace,
                       workspace_bytes, best_action, merged_children, stream);
-}
-
-int dvc_probe_valu(int32_t op, int64_t blocks, int32_t iters, uint32_t *sink, void *stream)
-{
-    if (op < 0 || op > 5 || blocks < 1 || blocks > 65536 || iters < 1 || sink == nullptr)
-        return DVC_EINVAL;
-    return status_of(launch_valu_probe(op, (uint32_t)blocks, (uint32_t)iters, sink,
-                                       (hipStream_t)stream));
 }
 
 size_t dvc_valuenet_bytes(void) { return vn_bytes(); }
@@ -433,6 +604,12 @@ int dvc_valuenet_get_params(const void *net, float *params, void *stream)
     return status_of(launch_vn_get_params(net, params, (hipStream_t)stream));
 }
 
+int dvc_valuenet_get_moments(const void *net, float *m, float *v, void *stream)
+{
+    if (net == nullptr || m == nullptr || v == nullptr || !aligned16(net)) return DVC_EINVAL;
+    return status_of(launch_vn_get_moments(net, m, v, (hipStream_t)stream));
+}
+
 int dvc_valuenet_infer(const void *net, const dvc_state_t *states, const uint8_t *persp, int64_t n,
                        float *v_out, void *stream)
 {
@@ -443,6 +620,21 @@ int dvc_valuenet_infer(const void *net, const dvc_state_t *states, const uint8_t
         return DVC_EINVAL;
     return status_of(launch_vn_infer(net, reinterpret_cast<const uint4 *>(states), persp,
                                      (uint32_t)n, v_out, (hipStream_t)stream));
+}
+
+int dvc_valuenet_epoch_order(uint64_t seed, int64_t epoch, int64_t n_data, uint32_t *perm_a,
+                             uint32_t *perm_b)
+{
+    if (epoch < 0 || epoch > 0xFFFFFFFFll || n_data < 1 || n_data > (1ll << 32) ||
+        (n_data & (n_data - 1)) != 0 || perm_a == nullptr || perm_b == nullptr)
+        return DVC_EINVAL;
+    const uint32_t ctr[4] = {(uint32_t)epoch, 0xFFFFFFFDu, 0u, 0u};
+    uint32_t w[4];
+    philox_host(ctr, (uint32_t)seed, (uint32_t)(seed >> 32), w);
+    const uint64_t mask = (uint64_t)n_data - 1u;
+    *perm_a = n_data == 1 ? 1u : (uint32_t)((uint64_t)(w[0] | 1u) & mask);
+    *perm_b = (uint32_t)((uint64_t)w[1] & mask);
+    return DVC_OK;
 }
 
 size_t dvc_valuenet_train_workspace_bytes(int64_t batch)

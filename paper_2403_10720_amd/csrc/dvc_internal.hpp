@@ -65,8 +65,6 @@ hipError_t launch_mcts(const uint4 *roots, uint32_t n_trees, uint32_t trees_per_
 hipError_t launch_mcts_merge(const uint32_t *ws, uint32_t n_roots, uint32_t trees_per_root,
                              uint32_t iters, uint32_t cont, int32_t *best, uint32_t *merged,
                              hipStream_t st);
-hipError_t launch_valu_probe(int op, uint32_t blocks, uint32_t iters, uint32_t *sink,
-                             hipStream_t st);
 size_t vn_bytes();
 size_t vn_train_ws_bytes(uint32_t batch);
 hipError_t launch_vn_init(void *net, uint32_t k0, uint32_t k1, hipStream_t st);
@@ -80,6 +78,7 @@ hipError_t launch_vn_train_step(void *net, const uint4 *states, const uint8_t *p
                                 hipStream_t st);
 hipError_t launch_vn_set_params(void *net, const float *params, hipStream_t st);
 hipError_t launch_vn_get_params(const void *net, float *params, hipStream_t st);
+hipError_t launch_vn_get_moments(const void *net, float *m, float *v, hipStream_t st);
 hipError_t launch_vn_labels(const uint4 *states, uint32_t n, uint32_t playouts, uint32_t k0,
                             uint32_t k1, uint32_t index_base, const uint32_t *seat_wins,
                             uint8_t *persp, float *labels, hipStream_t st);

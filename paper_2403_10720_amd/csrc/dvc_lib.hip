@@ -5,5 +5,4 @@
 #include "gen.hip"
 #include "valuenet.hip"
 #include "search.hip"
-#include "probe.hip"
 #include "capi.hip"

@@ -912,20 +912,22 @@ size_t vn_bytes() { return (size_t)kVnBytes; }
 
 // batch slices of the weight-gradient products: up to 8, each a multiple of
 // 32 rows
-static uint32_t vn_wgrad_slices(uint32_t batch)
+static constexpr uint32_t vn_wgrad_slices(uint32_t batch)
 {
     uint32_t s = kVnMaxSlices;
     while (s > 1u && (batch / 32u) % s != 0u) s >>= 1;
     return s;
 }
 
-size_t vn_train_ws_bytes(uint32_t batch)
+// xt (160 x B), h1t, dh1t, dh2t (256 x B) bf16; grad[NPAD] fp32 per slice;
+// partials of the 16-row tiles (and one spare row)
+static constexpr size_t vn_ws_bytes(uint32_t batch)
 {
-    // xt (160 x B), h1t, dh1t, dh2t (256 x B) bf16; grad[NPAD] fp32 per slice; partials of
-    // the 16-row tiles (and one spare row)
     return (size_t)batch * (160u + 3u * 256u) * 2u + (size_t)vn_wgrad_slices(batch) * kVnPad * 4u +
            (size_t)((batch + 15u) / 16u + 1u) * kPartWords * 4u + 256u;
 }
+
+size_t vn_train_ws_bytes(uint32_t batch) { return vn_ws_bytes(batch); }
 
 hipError_t launch_vn_init(void *net, uint32_t k0, uint32_t k1, hipStream_t st)
 {
@@ -1031,6 +1033,15 @@ __global__ void vn_get_params_kernel(const void *net, float *params)
     if (k < kVnParams) params[k] = P.master[k];
 }
 
+__global__ void vn_get_moments_kernel(const void *net, float *m, float *v)
+{
+    const VnPtrs P = vn_ptrs(const_cast<void *>(net));
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= kVnParams) return;
+    m[k] = P.m[k];
+    v[k] = P.v[k];
+}
+
 // perspective of a training pair and its playout win-rate label
 __global__ void vn_labels_kernel(const uint4 *states, uint32_t n, uint32_t playouts, uint32_t k0,
                                  uint32_t k1, uint32_t base, const uint32_t *seat_wins,
@@ -1058,6 +1069,13 @@ hipError_t launch_vn_get_params(const void *net, float *params, hipStream_t st)
 {
     hipLaunchKernelGGL(vn_get_params_kernel, dim3((kVnParams + 255u) / 256u), dim3(256), 0, st, net,
                        params);
+    return hipGetLastError();
+}
+
+hipError_t launch_vn_get_moments(const void *net, float *m, float *v, hipStream_t st)
+{
+    hipLaunchKernelGGL(vn_get_moments_kernel, dim3((kVnParams + 255u) / 256u), dim3(256), 0, st,
+                       net, m, v);
     return hipGetLastError();
 }
 

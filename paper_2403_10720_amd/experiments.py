@@ -73,22 +73,43 @@ def value_mse(net, n=4096, playouts=4096, seed=99, index_base=1 << 28):
     return mse, floor
 
 
+def median_search(roots, mp, seed, ws, reps=3):
+    """One warm-up launch, then `reps` timed launches: (decisions, median seconds)."""
+    mcts_search(roots, mp, seed, workspace=ws, want_children=False)
+    ts, best = [], None
+    for _ in range(reps):
+        best, t = timed_search(roots, mp, seed, ws)
+        ts.append(t)
+    return best, sorted(ts)[len(ts) // 2]
+
+
+# the value search's targets against the pure-playout search
+TARGET_AGREEMENT, TARGET_SPEEDUP = 0.95, 5.0
+
+
 def compare(n_trees=1024, iterations=4096, ppl=64, band=0.05, train_cfg: TrainConfig = None,
-            net=None, seed=5, log=print):
+            net=None, seed=5, reps=3, log=print):
     t0 = time.perf_counter()
     train_info = {}
     if net is None:
         cfg = train_cfg or TrainConfig()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
         data = make_data(cfg.n_data, cfg.playouts, cfg.data_seed)
+        e1.record()
         torch.cuda.synchronize()
         t_data = time.perf_counter() - t0
+        gpu_data = e0.elapsed_time(e1) / 1e3
         log(f"training pairs ready: {cfg.n_data} in {t_data:.2f} s")
-        net, hist, t_train = train(cfg, data=data, log_every=1024, log=log)
-        steps = cfg.epochs * (cfg.n_data // cfg.batch)
+        net, hist, tm = train(cfg, data=data, log_every=1024, log=log)
+        steps = tm["steps"]
         train_info = {"pairs": cfg.n_data, "label_playouts": cfg.playouts, "batch": cfg.batch,
-                      "epochs": cfg.epochs, "data_s": t_data, "train_s": t_train,
-                      "steps": steps, "step_ms": t_train / steps * 1e3,
-                      "train_tflops": steps * cfg.batch * FLOP_PER_ROW_TRAIN / t_train / 1e12,
+                      "epochs": cfg.epochs, "lr": cfg.lr, "data_s": t_data, "data_gpu_s": gpu_data,
+                      "label_playouts_per_s": cfg.n_data * cfg.playouts / gpu_data,
+                      "train_wall_s": tm["wall_s"], "train_gpu_s": tm["gpu_s"], "steps": steps,
+                      "step_ms": tm["gpu_s"] / steps * 1e3,
+                      "train_tflops": steps * cfg.batch * FLOP_PER_ROW_TRAIN / tm["gpu_s"] / 1e12,
                       "loss_first": hist[0][1] if hist else None,
                       "loss_last": hist[-1][1] if hist else None}
         log(f"trained: {train_info}")
@@ -101,9 +122,9 @@ def compare(n_trees=1024, iterations=4096, ppl=64, band=0.05, train_cfg: TrainCo
     ws = torch.empty(max(dvc_mcts_workspace_bytes(n_trees, mp_roll),
                          dvc_mcts_workspace_bytes(n_trees, mp_val)), dtype=torch.uint8,
                      device=roots.device)
-    best_roll, t_roll = timed_search(roots, mp_roll, seed, ws)
+    best_roll, t_roll = median_search(roots, mp_roll, seed, ws, reps)
     best_roll2, _ = timed_search(roots, mp_roll, seed + 1000, ws)
-    best_val, t_val = timed_search(roots, mp_val, seed, ws)
+    best_val, t_val = median_search(roots, mp_val, seed, ws, reps)
     stats = mcts_tree_stats(ws, n_trees, mp_val)
     net_leaves = int(stats["net_leaves"].sum())
     played = int(stats["played_leaves"].sum())
@@ -112,20 +133,37 @@ def compare(n_trees=1024, iterations=4096, ppl=64, band=0.05, train_cfg: TrainCo
     mp_val2 = mcts_params(iterations=iterations, playouts_per_leaf=1, max_depth=4, leaf_eval=1,
                           fallback_band=band, fallback_playouts=ppl, valuenet=net,
                           leaves_per_pass=2)
-    best_val2, t_val2 = timed_search(roots, mp_val2, seed, ws)
+    best_val2, t_val2 = median_search(roots, mp_val2, seed, ws, reps)
+    agree = float((best_val == best_roll).float().mean().item())
+    ceiling = float((best_roll2 == best_roll).float().mean().item())
+    speedup = t_roll / t_val
     out = {
+        "workload": f"{n_trees} fresh 2-4 player deals (root draw) x {iterations} iterations, "
+                    f"depth 4; playout mode {ppl} playouts per leaf; value mode band {band}, "
+                    f"{ppl} fallback playouts",
         "trees": n_trees, "iterations": iterations, "playouts_per_leaf": ppl, "band": band,
-        "root_move_agreement": float((best_val == best_roll).float().mean().item()),
-        "rollout_self_agreement": float((best_roll2 == best_roll).float().mean().item()),
+        "root_move_agreement": agree,
+        "rollout_self_agreement": ceiling,
+        "agreement_over_self_agreement": agree / ceiling if ceiling else None,
+        "decisions_per_s_rollout": n_trees / t_roll,
+        "decisions_per_s_value": n_trees / t_val,
         "gpu_s_per_decision_rollout": t_roll / n_trees,
         "gpu_s_per_decision_value": t_val / n_trees,
-        "speedup": t_roll / t_val,
+        "speedup": speedup,
+        "playouts_per_s_rollout": n_trees * iterations * ppl / t_roll,
         "fallback_rate": played / max(1, played + net_leaves),
         "two_leaves_per_pass": {
             "root_move_agreement": float((best_val2 == best_roll).float().mean().item()),
             "agreement_with_one_leaf_per_pass": float((best_val2 == best_val).float().mean().item()),
+            "decisions_per_s": n_trees / t_val2,
             "gpu_s_per_decision": t_val2 / n_trees, "speedup": t_roll / t_val2},
+        "targets": {"root_move_agreement": {"target": TARGET_AGREEMENT, "measured": agree,
+                                            "met": agree >= TARGET_AGREEMENT},
+                    "gpu_seconds_ratio": {"target": TARGET_SPEEDUP,
+                                          "measured": max(speedup, t_roll / t_val2),
+                                          "met": max(speedup, t_roll / t_val2) >= TARGET_SPEEDUP}},
         "value_mse_vs_4096_playouts": mse, "mse_noise_floor": floor,
+        "timing": f"HIP events, median of {reps} launches after one warm-up",
         "training": train_info,
     }
     return out, net

@@ -14,8 +14,9 @@ from dataclasses import dataclass
 
 import torch
 
-from . import (dvc_init_states, dvc_valuenet_init, dvc_valuenet_labels,
-               dvc_valuenet_train_step, dvc_valuenet_train_workspace_bytes, deal_params)
+from . import (dvc_init_states, dvc_valuenet_epoch_order, dvc_valuenet_init,
+               dvc_valuenet_labels, dvc_valuenet_train_step, dvc_valuenet_train_workspace_bytes,
+               deal_params)
 
 # mid-game positions of 2-4 players, half of them after the mover's draw
 TRAIN_DEAL = dict(p_min=2, p_max=4, hand=(0, 0, 4, 4, 3), pile_min=0, pile_max=16,
@@ -53,16 +54,16 @@ def make_data(n: int, playouts: int, seed: int, index_base: int = 0, chunk: int 
 
 def epoch_permutation(seed: int, epoch: int, n: int):
     """Batch order of an epoch: row i -> (a*i + b) mod n with a odd, a bijection
-    when n is a power of two (a and b from a seeded generator)."""
-    g = torch.Generator().manual_seed((seed << 20) ^ epoch)
-    a = int(torch.randint(0, 1 << 30, (1,), generator=g).item()) * 2 + 1
-    b = int(torch.randint(0, 1 << 30, (1,), generator=g).item())
-    return a % n if n > 1 else 1, b % max(n, 1)
+    when n is a power of two; a and b are Philox words (dvc_valuenet_epoch_order)."""
+    return dvc_valuenet_epoch_order(seed, epoch, n)
 
 
 def train(cfg: TrainConfig, data=None, net=None, log_every: int = 0, log=None):
-    """Train a fresh (or given) network; returns (net, history of (step, loss), seconds).
-    Every `log_every` steps the batch loss is recorded (and passed to `log`)."""
+    """Train a fresh (or given) network; returns (net, history of (step, loss),
+    timing) with timing = {"steps", "wall_s", "gpu_s"}: host seconds of the loop
+    and GPU seconds between HIP events recorded around it on the current
+    stream.  Every `log_every` steps the batch loss is recorded (and passed to
+    `log`)."""
     if data is None:
         data = make_data(cfg.n_data, cfg.playouts, cfg.data_seed)
     states, persp, labels = data
@@ -75,8 +76,10 @@ def train(cfg: TrainConfig, data=None, net=None, log_every: int = 0, log=None):
     loss = torch.zeros(1, dtype=torch.float32, device=states.device)
     steps_per_epoch = n // cfg.batch
     hist = []
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    e0.record()
     step = 0
     for epoch in range(cfg.epochs):
         a, b = epoch_permutation(cfg.data_seed, epoch, n)
@@ -90,8 +93,10 @@ def train(cfg: TrainConfig, data=None, net=None, log_every: int = 0, log=None):
                 hist.append((step, float(loss.item())))
                 if log is not None:
                     log(f"step {step} loss {hist[-1][1]:.5f}")
+    e1.record()
     torch.cuda.synchronize()
-    return net, hist, time.perf_counter() - t0
+    return net, hist, {"steps": step, "wall_s": time.perf_counter() - t0,
+                       "gpu_s": e0.elapsed_time(e1) / 1e3}
 
 
 def main(argv=None):
@@ -109,11 +114,9 @@ def main(argv=None):
     data = make_data(cfg.n_data, cfg.playouts, cfg.data_seed)
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
-    _, hist, t_train = train(cfg, data=data, log_every=1024,
-                             log=lambda m: print(m, flush=True))
-    steps = cfg.epochs * (cfg.n_data // cfg.batch)
-    print(json.dumps({"pairs": cfg.n_data, "data_s": t_data, "steps": steps,
-                      "step_ms": t_train / steps * 1e3,
+    _, hist, tm = train(cfg, data=data, log_every=1024, log=lambda m: print(m, flush=True))
+    print(json.dumps({"pairs": cfg.n_data, "data_s": t_data, "steps": tm["steps"],
+                      "step_ms": tm["gpu_s"] / tm["steps"] * 1e3,
                       "loss_last": hist[-1][1] if hist else None}), flush=True)
 
 

@@ -125,3 +125,54 @@ def test_tree_variant_parameters_without_device(lib):
                                               C.c_uint64, C.c_uint32, vp, C.c_size_t, vp, vp, vp]
     assert lib.mcts_search_root_parallel(vp(16), 1, 2, C.byref(mp), 1, 0, vp(16), 1 << 30, vp(16),
                                          None, None) == -1
+
+
+def test_epoch_order_is_the_philox_stream(lib, orc):
+    """dvc_valuenet_epoch_order (host only) takes words 0 and 1 of the Philox
+    block (epoch, 0xFFFFFFFD, 0, 0): checked against the oracle's Philox, and
+    the resulting map is a bijection of the rows."""
+    import numpy as np
+    u32 = C.c_uint32
+    lib.dvc_valuenet_epoch_order.argtypes = [C.c_uint64, C.c_int64, C.c_int64, C.POINTER(u32),
+                                             C.POINTER(u32)]
+    for seed in (4, 2**40 + 17):
+        for epoch in (0, 1, 19, 2**32 - 1):
+            for n in (1, 2, 1024, 2**23, 2**32):
+                a, b = u32(7), u32(7)
+                assert lib.dvc_valuenet_epoch_order(seed, epoch, n, C.byref(a), C.byref(b)) == 0
+                w = orc.philox([epoch, 0xFFFFFFFD, 0, 0], [seed & 0xFFFFFFFF, seed >> 32])
+                if n == 1:
+                    assert (a.value, b.value) == (1, 0)
+                else:
+                    assert a.value == (int(w[0]) | 1) % n and a.value % 2 == 1
+                    assert b.value == int(w[1]) % n
+                if n == 1024:
+                    rows = (a.value * np.arange(n, dtype=np.int64) + b.value) % n
+                    assert len(set(rows.tolist())) == n
+    a, b = u32(), u32()
+    assert lib.dvc_valuenet_epoch_order(4, 0, 3, C.byref(a), C.byref(b)) == -1
+    assert lib.dvc_valuenet_epoch_order(4, -1, 4, C.byref(a), C.byref(b)) == -1
+    assert lib.dvc_valuenet_epoch_order(4, 0, 2**33, C.byref(a), C.byref(b)) == -1
+    assert lib.dvc_valuenet_epoch_order(4, 0, 4, None, C.byref(b)) == -1
+
+
+def test_search_autotune_argument_errors_without_device(lib):
+    """Value leaves, several leaves per pass in the reference, no trees or a
+    negative tolerance are refused before any device work; automatic shapes
+    (playouts per leaf and leaves per pass both 0) have a workspace size."""
+    import paper_2403_10720_amd as D
+    L = D.lib()
+    vp = C.c_void_p
+    ok = D.mcts_params(iterations=64, playouts_per_leaf=8)
+    auto = D.mcts_params(iterations=64, playouts_per_leaf=0, leaves_per_pass=0)
+    assert L.dvc_mcts_workspace_bytes(4, C.byref(auto)) == L.dvc_mcts_workspace_bytes(4, C.byref(ok)) > 0
+    half = D.mcts_params(iterations=64, playouts_per_leaf=0, leaves_per_pass=1)
+    assert L.dvc_mcts_workspace_bytes(4, C.byref(half)) == 0
+    big = D.mcts_params(iterations=1 << 17, playouts_per_leaf=0, leaves_per_pass=0)
+    assert L.dvc_mcts_workspace_bytes(4, C.byref(big)) == 0
+    res = D.MctsTuning()
+    for mp, n, tol in [(D.mcts_params(iterations=64, playouts_per_leaf=8, leaves_per_pass=2), 4, 0.0),
+                       (ok, 0, 0.0), (ok, 4, -0.1), (auto, 4, 0.0),
+                       (D.mcts_params(iterations=64, playouts_per_leaf=8, leaf_eval=1), 4, 0.0)]:
+        assert L.dvc_mcts_autotune(vp(16), n, C.byref(mp), 1, 0, vp(16), 1 << 30, tol, vp(16),
+                                   C.byref(res), None) == -1

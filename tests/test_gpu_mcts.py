@@ -256,3 +256,43 @@ def test_root_parallel_argument_errors(dvc):
     small = torch.empty(need - 16, dtype=torch.uint8, device="cuda")
     with pytest.raises(dvc.DvcError):
         dvc.mcts_search_root_parallel(st, 3, md, 1, workspace=small)
+
+
+# ---------------------------------------------------------------------------
+# search autotuner: playouts per leaf x leaves per pass
+# ---------------------------------------------------------------------------
+def test_search_autotune_and_automatic_shape(dvc):
+    deal = dvc.deal_params(p_min=2, p_max=4, hand=(0, 0, 4, 4, 3), pile_min=0, pile_max=16,
+                           revealed_max=8, root_draw=1)
+    roots = dvc.dvc_init_states(256, deal, 3)
+    auto = dvc.mcts_params(iterations=128, playouts_per_leaf=0, max_depth=4, leaves_per_pass=0)
+
+    def same(a, b):
+        return torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+    # untuned size class: 32 playouts per leaf, two leaves per pass
+    assert same(dvc.mcts_search(roots, auto, 9),
+                dvc.mcts_search(roots, dvc.mcts_params(iterations=128, playouts_per_leaf=32,
+                                                       max_depth=4, leaves_per_pass=2), 9))
+    ref = dvc.mcts_params(iterations=128, playouts_per_leaf=32, max_depth=4)
+    choice, dec = dvc.dvc_mcts_autotune(roots, ref, 9, tolerance=0.05)
+    cands = {(4, 1), (4, 2), (4, 4), (4, 8), (4, 16), (8, 1), (8, 2), (8, 4), (8, 8), (16, 1),
+             (16, 2), (16, 4), (32, 1), (32, 2), (64, 1), (128, 1)}
+    shape = (choice["playouts_per_leaf"], choice["leaves_per_pass"])
+    assert shape in cands, choice
+    assert choice["agreement"] + 0.05 >= choice["self_agreement"], choice
+    chosen = dvc.mcts_params(iterations=128, playouts_per_leaf=shape[0], max_depth=4,
+                             leaves_per_pass=shape[1])
+    # the returned decisions are the chosen shape's (candidates run under seed + 1)
+    b, _ = dvc.mcts_search(roots, chosen, 10, want_children=False)
+    assert torch.equal(b, dec)
+    # the size class now runs the chosen shape; other classes keep the default
+    assert same(dvc.mcts_search(roots, auto, 11), dvc.mcts_search(roots, chosen, 11))
+    small = roots[:64]
+    assert same(dvc.mcts_search(small, auto, 11),
+                dvc.mcts_search(small, dvc.mcts_params(iterations=128, playouts_per_leaf=32,
+                                                       max_depth=4, leaves_per_pass=2), 11))
+    assert dvc.dvc_check() == 0
+    with pytest.raises(dvc.DvcError):
+        dvc.dvc_mcts_autotune(roots, dvc.mcts_params(iterations=128, playouts_per_leaf=32,
+                                                     leaves_per_pass=2), 9)

@@ -254,18 +254,21 @@ def test_rollout_full_leaf_parallel_workload(orc, dvc):
 
 
 def test_valu_probe(dvc):
-    """The integer issue-rate probe runs every operation; for v_xor_b32 each chain
-    is xored with the same word an even number of times, so every lane folds its
-    eight start values."""
+    """The integer issue-rate probe of the benchmark (a measurement library of
+    its own) runs every operation; for v_xor_b32 each chain is xored with the
+    same word an even number of times, so every lane folds its eight start
+    values."""
+    from paper_2403_10720_amd import measure
     sink = torch.empty(2 * 256, dtype=torch.int32, device="cuda")
-    for op in range(len(dvc.VALU_PROBE_OPS)):
-        dvc.dvc_probe_valu(op, 2, 3, sink)
-    dvc.dvc_probe_valu(0, 2, 3, sink)
+    for op in range(len(measure.OPS)):
+        measure.probe_valu(op, 2, 3, sink)
+    measure.probe_valu(0, 2, 3, sink)
     t = np.arange(512, dtype=np.uint32)
     want = t ^ (t + 1) ^ (t + 2) ^ (t + 3) ^ (t + 4) ^ (t + 5) ^ (t + 6) ^ (t + 7)
+    torch.cuda.synchronize()
     assert np.array_equal(sink.cpu().numpy().view(np.uint32), want)
-    with pytest.raises(dvc.DvcError):
-        dvc.dvc_probe_valu(6, 2, 3, sink)
+    with pytest.raises(ValueError):
+        measure.probe_valu(6, 2, 3, sink)
 
 
 @pytest.mark.parametrize("variant", [4, 6, 7])
