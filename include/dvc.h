@@ -251,7 +251,7 @@ typedef struct {
     int32_t continue_choice;    /* 1: stop-or-guess choice after a right guess      */
     int32_t vanilla;            /* 1: sampled worlds are the root's children        */
     int32_t leaves_per_pass;    /* B: leaves evaluated together, 1..16 (value mode
-                                   1..2); 1 = the sequential search              */
+                                   1..4); 1 = the sequential search              */
 } dvc_mcts_params;
 /* Automatic shape: with playout leaves, playouts_per_leaf = 0 together with
  * leaves_per_pass = 0 asks for the shape dvc_mcts_autotune chose for this

@@ -134,9 +134,9 @@ static bool mcts_params_ok(const dvc_mcts_params *p)
         return false;
     if ((p->continue_choice != 0 && p->continue_choice != 1) || (p->vanilla != 0 && p->vanilla != 1))
         return false;
-    // leaves evaluated together: value mode fits two leaves' perspectives in
+    // leaves evaluated together: value mode fits four leaves' perspectives in
     // one matrix tile, playout mode packs up to 16 leaves' playouts
-    if (!aut && (p->leaves_per_pass < 1 || p->leaves_per_pass > (p->leaf_eval ? 2 : 16)))
+    if (!aut && (p->leaves_per_pass < 1 || p->leaves_per_pass > (p->leaf_eval ? 4 : 16)))
         return false;
     if (!(p->c_uct >= 0.0f) || std::isinf(p->c_uct)) return false;
     if (p->leaf_eval != 0 && p->leaf_eval != 1) return false;

@@ -283,18 +283,29 @@ __device__ __forceinline__ void end_turn(State &S, uint32_t alive, uint32_t w1, 
     }
 }
 
+// The chance words of the in-tree guesses of one iteration: lane d holds
+// block (d, 0xC0000000, iter, tree), the words of the guess at depth d
+// (a descent is at most 64 levels deep); chance_at reads depth d's block.
+__device__ __forceinline__ Words chance_at(const Words &cw, uint32_t depth)
+{
+    Words w;
+    w.w0 = __builtin_amdgcn_readlane(cw.w0, depth);
+    w.w1 = __builtin_amdgcn_readlane(cw.w1, depth);
+    w.w2 = 0u;
+    w.w3 = __builtin_amdgcn_readlane(cw.w3, depth);
+    return w;
+}
+
 // Play tree key `key` -- a guess, the stop (kStopKey), or a guess after a
-// right guess (kStopKey + 1 + action) -- with chance words from block (depth,
-// 0xC0000000, iter, tree): w0 picks the mover's own tile to reveal after a
-// wrong guess with nothing drawn, w1 the next player's draw.  A right guess
-// ends the turn unless cont_mode is set; then `cont` is set and the mover,
-// still holding the drawn tile hidden, decides again.  Returns true if the
-// game ended.
-__device__ __forceinline__ bool apply_action(State &S, uint32_t key, bool cont_mode, uint32_t depth,
-                                             uint32_t iter, uint32_t tr, uint32_t k0, uint32_t k1,
+// right guess (kStopKey + 1 + action) -- with the chance words w of block
+// (depth, 0xC0000000, iter, tree): w0 picks the mover's own tile to reveal
+// after a wrong guess with nothing drawn, w1 the next player's draw.  A right
+// guess ends the turn unless cont_mode is set; then `cont` is set and the
+// mover, still holding the drawn tile hidden, decides again.  Returns true
+// if the game ended.
+__device__ __forceinline__ bool apply_action(State &S, uint32_t key, bool cont_mode, const Words &w,
                                              uint32_t &winner, bool &cont, const uint8_t *tab)
 {
-    const Words w = philox(depth, 0xC0000000u, iter, tr, k0, k1);
     cont = false;
     if (key == kStopKey) {
         end_turn(S, alive_mask(S), w.w1, tab);
@@ -328,14 +339,11 @@ __device__ __forceinline__ bool apply_action(State &S, uint32_t key, bool cont_m
 }
 
 // A leaf reached right after a right guess (continue choice): the random
-// policy's continue coin, w3 of that guess's chance block, decides once for
+// policy's continue coin, w3 of that guess's chance block w, decides once for
 // all the leaf's playouts -- below 2^31 the mover goes on guessing, else the
 // turn passes (w1 draws).
-__device__ __forceinline__ void leaf_continue_coin(State &S, uint32_t depth, uint32_t iter,
-                                                   uint32_t tr, uint32_t k0, uint32_t k1,
-                                                   const uint8_t *tab)
+__device__ __forceinline__ void leaf_continue_coin(State &S, const Words &w, const uint8_t *tab)
 {
-    const Words w = philox(depth, 0xC0000000u, iter, tr, k0, k1);
     if (w.w3 >= 0x80000000u) end_turn(S, alive_mask(S), w.w1, tab);
 }
 
@@ -374,17 +382,48 @@ __device__ __forceinline__ State readlane_state(const State &s, uint32_t lane)
     return r;
 }
 
-// wavefront arg-max: greatest score, lowest index on ties
+// arg-max step: the other candidate (os, oi) replaces (s, idx) if its score
+// is greater, or equal with a lower index
+__device__ __forceinline__ void argmax_take(float &s, uint32_t &idx, float os, uint32_t oi)
+{
+    const bool take = os > s || (os == s && oi < idx);
+    s = take ? os : s;
+    idx = take ? oi : idx;
+}
+
+// one exchange between the lanes of a 16-lane row (data-parallel-primitive
+// move with row control CTRL), then the arg-max step
+template <int CTRL>
+__device__ __forceinline__ void argmax_dpp(float &s, uint32_t &idx)
+{
+    const float os =
+        __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(s), CTRL, 0xF, 0xF, false));
+    const uint32_t oi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)idx, CTRL, 0xF, 0xF, false);
+    argmax_take(s, idx, os, oi);
+}
+
+// Wavefront arg-max: greatest score, lowest index on ties; every lane gets
+// the result.  The candidates are totally ordered (score descending, index
+// ascending), so any order of pairwise steps gives the same winner: within
+// each 16-lane row by lane exchanges (lane ^ 1, lane ^ 2, then the mirror
+// images within 8 and within 16 lanes), then the four rows' winners, read
+// from lanes 0, 16, 32, 48, in row order.  All 64 lanes must be active.
 __device__ __forceinline__ void wave_argmax(float &s, uint32_t &idx)
 {
+    argmax_dpp<0xB1>(s, idx);    // quad_perm [1, 0, 3, 2]
+    argmax_dpp<0x4E>(s, idx);    // quad_perm [2, 3, 0, 1]
+    argmax_dpp<0x141>(s, idx);   // row_half_mirror
+    argmax_dpp<0x140>(s, idx);   // row_mirror
+    float bs = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(s), 0));
+    uint32_t bi = __builtin_amdgcn_readlane(idx, 0);
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        const float os = __shfl_xor(s, off, 64);
-        const uint32_t oi = __shfl_xor(idx, off, 64);
-        const bool take = os > s || (os == s && oi < idx);
-        s = take ? os : s;
-        idx = take ? oi : idx;
+    for (int row = 1; row < 4; ++row) {
+        const float os = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(s), 16 * row));
+        const uint32_t oi = __builtin_amdgcn_readlane(idx, 16 * row);
+        argmax_take(bs, bi, os, oi);
     }
+    s = bs;
+    idx = bi;
 }
 
 __device__ __forceinline__ void wave_argmax_u(uint32_t &n, uint32_t &idx)
@@ -450,9 +489,8 @@ __device__ __forceinline__ void tree_sync()
 template <bool VALUE> struct TreeGroup {
     static constexpr uint32_t kTrees = VALUE ? 4u : 1u;
     // leaves evaluated together: value mode puts their perspectives into the
-    // 16 rows of one matrix tile, four per leaf, and its LDS (the shared
-    // second-layer weights) leaves room for the rows of two
-    static constexpr uint32_t kPass = VALUE ? 2u : 16u;
+    // 16 rows of one matrix tile, four per leaf
+    static constexpr uint32_t kPass = VALUE ? 4u : 16u;
 };
 
 // VALUE: value mode (network leaves) -- one wavefront per SIMD, so that the
@@ -467,23 +505,19 @@ mcts_tree_kernel(MctsArgs a)
     __shared__ uint8_t tab[kKthTableBytes];
     __shared__ uint32_t legal_all[TG][73];
     constexpr uint32_t BM = TreeGroup<VALUE>::kPass;
-    constexpr uint32_t kVnTreeRows = 4u * (VALUE ? BM : 1u);
     __shared__ uint32_t path_all[TG][BM][kMaxPath];
     __shared__ uint4 leaf_all[TG][BM];
     __shared__ uint32_t np_all[TG][BM];
     __shared__ uint32_t wins_all[TG][4u * BM];
     __shared__ float vals_all[TG][BM][4];
     __shared__ DfsSlots dfs_all[TG];
-    __shared__ __attribute__((aligned(16))) uint16_t tile_all[TG][kVnTreeRows][kVnH + 8];
     __shared__ __attribute__((aligned(16))) uint16_t w2_lds[VALUE ? kVnH * kVnH : 8];
     __shared__ VnSmall vn_small[1];
     fill_kth_table(tab);
     if (VALUE) {
         vn_stage_small(vn_ptrs(const_cast<void *>(a.net)), vn_small[0]);
-        // second-layer weights (bf16, in the packed fragment order)
-        const uint4 *w2 = reinterpret_cast<const uint4 *>(vn_ptrs(const_cast<void *>(a.net)).w2b);
-        for (uint32_t c = threadIdx.x; c < kVnH * kVnH / 8u; c += blockDim.x)
-            reinterpret_cast<uint4 *>(w2_lds)[c] = w2[c];
+        // second-layer weights (bf16) as A operands of the transposed product
+        vn_stage_w2t(vn_ptrs(const_cast<void *>(a.net)), w2_lds);
     }
     __syncthreads();   // the only workgroup barrier
     const uint32_t wv = TG == 1u ? 0u : __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -492,7 +526,6 @@ mcts_tree_kernel(MctsArgs a)
     const uint32_t lane = threadIdx.x & 63u;
     uint32_t *legal_s = legal_all[wv];
     DfsSlots &dfs_slots = dfs_all[wv];
-    uint16_t (*vn_tile)[kVnH + 8] = tile_all[wv];
     float (*vals)[4] = vals_all[wv];
     const uint32_t tr = a.tree_base + t;
     uint32_t *W = a.ws + (uint64_t)t * a.sh.tree_words;
@@ -528,6 +561,13 @@ mcts_tree_kernel(MctsArgs a)
     bool failed = false, have_fallback = false;
     State fallback = R;
     uint64_t cyc[4] = {0u, 0u, 0u, 0u};   // shader clock per phase (statistics)
+    // Worlds of iterations ib .. ib + 63 by attempt 0, sampled together (lane
+    // l: iteration ib + l) at every 64th iteration: the world's rows as owner
+    // bit-planes, and the lanes whose attempt succeeded.  An iteration whose
+    // attempt 0 failed runs all 64 attempts on its own below; its lowest
+    // successful attempt is the same one either way.
+    uint32_t wpl0 = 0u, wpl1 = 0u, wpl2 = 0u;
+    uint64_t wok = 0u;
     tree_sync<VALUE>();
 
     // Iterations run in passes of B = leaves_per_pass: each descent of a pass
@@ -544,13 +584,34 @@ mcts_tree_kernel(MctsArgs a)
             const uint32_t it = i0 + b;
             uint32_t *path_e = path_all[wv][b];
             const uint64_t t0 = clock64();
-            // ---- 1. sample a world: attempt `lane`, lowest success wins ------
+            // ---- 1. sample a world: the lowest successful attempt ------------
+            if ((it & 63u) == 0u) {
+                State Sw;
+                const bool got0 = det_attempt(R, 0u, it + lane, tr, a.k0, a.k1, Sw, tab);
+                wok = __ballot(got0 && it + lane < a.iters);
+                wpl0 = Sw.h0 | Sw.h2;
+                wpl1 = Sw.h1 | Sw.h2;
+                wpl2 = Sw.h3;
+            }
             State S;
-            const bool got = det_attempt(R, lane, it, tr, a.k0, a.k1, S, tab);
-            const uint64_t okm = __ballot(got);
-            if (okm) {
-                S = readlane_state(S, (uint32_t)__builtin_ctzll(okm));
+            const uint32_t wl = it & 63u;
+            uint64_t okm = 0u;
+            if ((wok >> wl) & 1u) {
+                S = R;
+                const uint32_t p0 = __builtin_amdgcn_readlane(wpl0, wl);
+                const uint32_t p1 = __builtin_amdgcn_readlane(wpl1, wl);
+                const uint32_t p2 = __builtin_amdgcn_readlane(wpl2, wl);
+                S.h0 = p0 & ~p1 & ~p2;
+                S.h1 = ~p0 & p1 & ~p2 & kAll;
+                S.h2 = p0 & p1 & ~p2;
+                S.h3 = p2;
             } else {
+                // attempt `lane` of this iteration (attempt 0 fails again)
+                const bool got = det_attempt(R, lane, it, tr, a.k0, a.k1, S, tab);
+                okm = __ballot(got);
+                if (okm) S = readlane_state(S, (uint32_t)__builtin_ctzll(okm));
+            }
+            if (!((wok >> wl) & 1u) && !okm) {
                 // the fallback world depends on the root only: search it once
                 if (!have_fallback) {
                     State F = R;
@@ -572,6 +633,7 @@ mcts_tree_kernel(MctsArgs a)
             const uint64_t t1 = clock64();
             cyc[0] += t1 - t0;
             // ---- 2. descend ----------------------------------------------------
+            const Words cw = philox(lane, 0xC0000000u, it, tr, a.k0, a.k1);
             // Append a child {ex | ..., 0, ez, id} to `parent` (child count nc);
             // returns its id and its entry's word offset.
             auto append_child = [&](uint32_t parent, uint32_t nc, uint32_t ex, uint32_t ez,
@@ -683,7 +745,7 @@ mcts_tree_kernel(MctsArgs a)
                     if (lane == 0) W[rec + word] |= bit;
                     path_e[np++] = e;
                     last_block = depth;
-                    term = apply_action(S, key, a.cont_mode != 0u, depth, it, tr, a.k0, a.k1, winner,
+                    term = apply_action(S, key, a.cont_mode != 0u, chance_at(cw, depth), winner,
                                         cont, tab);
                     tree_sync<VALUE>();
                     break;
@@ -731,12 +793,12 @@ mcts_tree_kernel(MctsArgs a)
                 node_n = best_n;
                 path_e[np++] = best_e;
                 last_block = depth;
-                term = apply_action(S, best_act, a.cont_mode != 0u, depth, it, tr, a.k0, a.k1, winner,
+                term = apply_action(S, best_act, a.cont_mode != 0u, chance_at(cw, depth), winner,
                                     cont, tab);
                 ++depth;
                 tree_sync<VALUE>();
             }
-            if (!term && cont) leaf_continue_coin(S, last_block, it, tr, a.k0, a.k1, tab);
+            if (!term && cont) leaf_continue_coin(S, chance_at(cw, last_block), tab);
             deepest = np - a.vanilla > deepest ? np - a.vanilla : deepest;
             cyc[1] += clock64() - t1;
             if (a.lpp == 1u) {
@@ -753,11 +815,12 @@ mcts_tree_kernel(MctsArgs a)
                     encode(S, ps.x, ps.y, ps.z, ps.w);
                     const uint32_t q = lane & 15u;
                     RowFeat rf = q < S.P ? row_features(ps, q) : no_row();
-                    float v4[4];
-                    vn_eval_tree<kVnTreeRows>(vn_ptrs(const_cast<void *>(a.net)), rf, vn_tile, w2_lds, vn_small[0], v4);
+                    const float vrow = vn_eval_tree_t(vn_ptrs(const_cast<void *>(a.net)), rf,
+                                                      w2_lds, vn_small[0]);
                     float v[4];
         #pragma unroll
-                    for (uint32_t k = 0; k < 4u; ++k) v[k] = __shfl(v4[k], 0, 64);
+                    for (uint32_t k = 0; k < 4u; ++k)
+                        v[k] = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(vrow), k));
                     const float vm = R.m == 0u ? v[0] : R.m == 1u ? v[1] : R.m == 2u ? v[2] : v[3];
                     const float dv = vm - 0.5f;
                     if (!((dv < 0.0f ? -dv : dv) < a.band)) {
@@ -865,15 +928,15 @@ mcts_tree_kernel(MctsArgs a)
                 const uint4 ps = leaf_all[wv][lb];
                 if (q < ((ps.x >> 26) & 3u) + 1u) rf = row_features(ps, q);
             }
-            float v4[4];
-            vn_eval_tree<kVnTreeRows>(vn_ptrs(const_cast<void *>(a.net)), rf, vn_tile, w2_lds,
-                                      vn_small[0], v4);
+            const float vrow = vn_eval_tree_t(vn_ptrs(const_cast<void *>(a.net)), rf, w2_lds,
+                                              vn_small[0]);
 #pragma unroll
-            for (uint32_t b = 0; b < kVnTreeRows / 4u; ++b) {
+            for (uint32_t b = 0; b < BM; ++b) {
                 if (!((play_mask >> b) & 1u)) continue;
                 float v[4];
 #pragma unroll
-                for (uint32_t k = 0; k < 4u; ++k) v[k] = __shfl(v4[k], 16 * b, 64);
+                for (uint32_t k = 0; k < 4u; ++k)
+                    v[k] = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(vrow), 4u * b + k));
                 const float vm = R.m == 0u ? v[0] : R.m == 1u ? v[1] : R.m == 2u ? v[2] : v[3];
                 const float dv = vm - 0.5f;
                 if (!((dv < 0.0f ? -dv : dv) < a.band)) {

@@ -290,52 +290,35 @@ __device__ __forceinline__ void vn_eval16(const VnPtrs &P, const RowFeat &rf,
     __syncthreads();   // hs may be reused by the caller
 }
 
-// vn_eval16 with the weight fragments streamed through a ring of kVnRing
-// registers: the fragment for product q + kVnRing is requested while product
-// q runs, so a wavefront keeps that many loads in flight instead of one or
-// two (one wavefront per tree has nothing else to hide the L2 latency
-// behind).  Same products in the same order as vn_eval16.  Needs the register
-// budget of one wavefront per SIMD.
-constexpr int kVnRing = 16;
-
-// out(j, acc): epilogue of output column tile j (16 columns, D layout)
-template <int KS, int LD, int RING = kVnRing, typename Epi>
-__device__ __forceinline__ void vn_layer_deep(const bf16x8 (&a)[KS], const uint16_t *w, uint32_t r,
-                                              uint32_t g, Epi out)
+// The first layer inside a tree search streams its weight fragments through
+// a ring of RING registers: the fragment for product q + RING is requested
+// while product q runs, so a wavefront keeps that many loads in flight
+// instead of one or two (one wavefront per tree has nothing else to hide the
+// L2 latency behind).  Needs the register budget of one wavefront per SIMD.
+// The streamed weight fragment is the A operand (16 output units x 32 k)
+// and a[s] the B operand (32 k x 16 rows), so out(j, acc) receives D[unit
+// 16j + 4g + i][row r].  A weight fragment is the same registers as either
+// operand (lane 16g + r holds 8 consecutive k of unit 16j + r).
+template <int KS, int RING, typename Epi>
+__device__ __forceinline__ void vn_layer_deep_t(const bf16x8 (&a)[KS], const uint16_t *w,
+                                                uint32_t lane, Epi out)
 {
     constexpr int N = 16 * KS;
-    constexpr int kVnRing = RING;
-    bf16x8 ring[kVnRing];
-    const uint32_t lane = 16u * g + r;
+    bf16x8 ring[RING];
 #pragma unroll
-    for (int q = 0; q < kVnRing; ++q) ring[q] = load8(w + ((uint32_t)q * 64u + lane) * 8u);
+    for (int q = 0; q < RING; ++q) ring[q] = load8(w + ((uint32_t)q * 64u + lane) * 8u);
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
         floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
             const int q = j * KS + s;
-            const bf16x8 b = ring[q % kVnRing];
-            if (q + kVnRing < N) {
-                ring[q % kVnRing] = load8(w + ((uint32_t)(q + kVnRing) * 64u + lane) * 8u);
-            }
-            acc = mfma16(a[s], b, acc);
+            const bf16x8 b = ring[q % RING];
+            if (q + RING < N) ring[q % RING] = load8(w + ((uint32_t)(q + RING) * 64u + lane) * 8u);
+            acc = mfma16(b, a[s], acc);
         }
         out((uint32_t)j, acc);
     }
-}
-
-// The evaluation inside a tree search: at most four rows (one per seat
-// perspective) in a 4 x 264 LDS tile, first-layer weights streamed from L2
-// through the load ring, second-layer weights read from the LDS copy the
-// workgroup staged at its start (`w2l`, rows padded to 264).  Rows 4..15 of
-// the products repeat rows 0..3 and are ignored.  Only this wavefront's lanes
-// touch `tile`, so it is ordered with wavefront barriers.  Same products, in
-// the same order, as vn_eval16.
-__device__ __forceinline__ void wave_lds_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    __builtin_amdgcn_wave_barrier();
 }
 
 // Small per-workgroup LDS copy of the biases and output weights (float):
@@ -354,59 +337,81 @@ __device__ __forceinline__ void vn_stage_small(const VnPtrs &P, VnSmall &sm)
     if (threadIdx.x == 0) sm.b3 = P.master[kOffB3];
 }
 
-// One wavefront scores NR (4, 8 or 16) rows of tree leaves: the lane's rf is
-// row lane % 16 (rows past NR are empty), the first layer streams its
-// weights from L2, its output rows go through `tile` (NR rows) to the second
-// layer, whose weights `w2l` sit in LDS.  v4[i] of the lanes of group g =
-// lane / 16 is the value of row 4g + i.
-template <uint32_t NR>
-__device__ __forceinline__ void vn_eval_tree(const VnPtrs &P, const RowFeat &rf,
-                                             uint16_t (*tile)[kVnH + 8],
-                                             const uint16_t *w2l, const VnSmall &sm,
-                                             float v4[4])
+// k order of the transposed second product: slot 8g + e of a 32-unit block
+// holds unit 4g + e (e < 4) or 16 + 4g + e - 4 (e >= 4) -- the units that
+// lane group g holds of the block's two 16-unit output tiles of the first
+// product, so those tiles, packed to bfloat16, are the second product's B
+// operand as they stand
+__host__ __device__ constexpr uint32_t vn_tk(uint32_t slot)
 {
-    const uint32_t lane = threadIdx.x & 63u, r = lane & 15u, g = lane >> 4;
-    bf16x8 xa[5];
+    return (slot & 4u) ? 16u + 4u * (slot >> 3) + (slot & 3u) : 4u * (slot >> 3) + (slot & 3u);
+}
+
+// Stage the bf16 W2 in LDS as A operands of the transposed second product:
+// fragment q = 8j + s, lane 16g + r, element e holds W2[16j + r][32s +
+// vn_tk(8g + e)] (the blob's shadow holds W2 as B operands in natural k
+// order).  Four consecutive units are one 8-byte copy.
+__device__ void vn_stage_w2t(const VnPtrs &P, uint16_t *w2p)
+{
+    for (uint32_t c = threadIdx.x; c < kVnH * kVnH / 4u; c += blockDim.x) {
+        const uint32_t d = 4u * c;
+        const uint32_t e = d & 7u, l = (d >> 3) & 63u, q = d >> 9;
+        const uint32_t j = q >> 3, s = q & 7u, g = l >> 4, r = l & 15u;
+        const uint32_t src = vn_frag(16u * j + r, 32u * s + vn_tk(8u * g + e), 8u);
+        *reinterpret_cast<uint2 *>(w2p + d) = *reinterpret_cast<const uint2 *>(P.w2b + src);
+    }
+}
+
+// Value of 16 rows inside a tree search, computed transposed: H1^T = W1 X^T
+// then H2^T = W2 H1^T, so that each layer's output stays in registers (the
+// first layer's tiles 2s, 2s + 1, relu'd and packed to bfloat16, are block s
+// of the second product's B operand) -- no LDS tile, no barrier.  The
+// lane's row is r = lane % 16 (rf; empty rows give some value that callers
+// ignore); first-layer weights stream from L2 through a ring of loads,
+// second-layer weights come from `w2p` (vn_stage_w2t), biases and output
+// weights from `sm`.  Returns the value of row r in lanes r, r + 16, r + 32
+// and r + 48 (the same bits in all four).  Same products as vn_eval16, the
+// sums in another order.
+__device__ __forceinline__ float vn_eval_tree_t(const VnPtrs &P, const RowFeat &rf,
+                                                const uint16_t *w2p, const VnSmall &sm)
+{
+    const uint32_t lane = threadIdx.x & 63u, g = lane >> 4;
+    bf16x8 xb[5];
 #pragma unroll
-    for (uint32_t s = 0; s < 5u; ++s) xa[s] = feature8(rf, s, g);
-    vn_layer_deep<5, kVnIn, 32>(xa, P.w1b, r, g, [&](uint32_t j, const floatx4 &acc) {
-        if (g < NR / 4u) {
-            const float b1 = sm.b1[16u * j + r];
+    for (uint32_t s = 0; s < 5u; ++s) xb[s] = feature8(rf, s, g);
+    uint32_t hw[8][4];
+    vn_layer_deep_t<5, 32>(xb, P.w1b, lane, [&](uint32_t j, const floatx4 &acc) {
+        uint32_t hq[4];
 #pragma unroll
-            for (uint32_t i = 0; i < 4u; ++i) {
-                const float h = acc[i] + b1;
-                tile[4u * g + i][16u * j + r] = bf16_bits(h > 0.0f ? h : 0.0f);
-            }
+        for (uint32_t i = 0; i < 4u; ++i) {
+            const float h = acc[i] + sm.b1[16u * j + 4u * g + i];
+            hq[i] = bf16_bits(h > 0.0f ? h : 0.0f);
         }
+        hw[j >> 1][2u * (j & 1u)] = hq[0] | (hq[1] << 16);
+        hw[j >> 1][2u * (j & 1u) + 1u] = hq[2] | (hq[3] << 16);
     });
-    wave_lds_sync();
-    bf16x8 ha[8];
+    bf16x8 hb[8];
 #pragma unroll
-    for (uint32_t s = 0; s < 8u; ++s) ha[s] = load8(&tile[r % NR][32u * s + 8u * g]);
-    float zpart[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (uint32_t s = 0; s < 8u; ++s) __builtin_memcpy(&hb[s], hw[s], 16);
+    float z = 0.0f;
 #pragma unroll
     for (uint32_t j = 0; j < 16u; ++j) {
         bf16x8 wb[8];
 #pragma unroll
-        for (uint32_t s = 0; s < 8u; ++s) wb[s] = load8(w2l + ((j * 8u + s) * 64u + lane) * 8u);
+        for (uint32_t s = 0; s < 8u; ++s) wb[s] = load8(w2p + ((j * 8u + s) * 64u + lane) * 8u);
         floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (uint32_t s = 0; s < 8u; ++s) acc = mfma16(ha[s], wb[s], acc);
-        const float b2 = sm.b2[16u * j + r], w3 = sm.w3[16u * j + r];
+        for (uint32_t s = 0; s < 8u; ++s) acc = mfma16(wb[s], hb[s], acc);
 #pragma unroll
         for (uint32_t i = 0; i < 4u; ++i) {
-            const float h = acc[i] + b2;
-            zpart[i] += bf16_round(h > 0.0f ? h : 0.0f) * w3;
+            const uint32_t u = 16u * j + 4u * g + i;
+            const float h = acc[i] + sm.b2[u];
+            z += bf16_round(h > 0.0f ? h : 0.0f) * sm.w3[u];
         }
     }
-#pragma unroll
-    for (uint32_t i = 0; i < 4u; ++i)
-#pragma unroll
-        for (int off = 1; off < 16; off <<= 1) zpart[i] += __shfl_xor(zpart[i], off, 64);
-    const float b3 = sm.b3;
-#pragma unroll
-    for (uint32_t i = 0; i < 4u; ++i) v4[i] = 1.0f / (1.0f + expf(-(zpart[i] + b3)));
-    wave_lds_sync();   // the tile may be reused
+    z += __shfl_xor(z, 16, 64);
+    z += __shfl_xor(z, 32, 64);
+    return 1.0f / (1.0f + expf(-(z + sm.b3)));
 }
 
 __device__ __forceinline__ RowFeat no_row()
@@ -707,16 +712,19 @@ __global__ void __launch_bounds__(256) vn_rows4_kernel(VnRowsArgs a)
 // gk, on the float32 master weight and moments; the bf16 shadow the products
 // read is refreshed from the updated weight.  `p` is the internal feature
 // index of a W1 weight (its column in the shadow), unused otherwise.
+// beta1, beta2 and their complements 1 - beta1, 1 - beta2 are each the
+// float nearest the exact value (1 - 0.999f computed in float would be
+// 1.3e-5 away from 0.001 in relative terms)
 struct VnAdam {
-    float lr, beta1, beta2, eps, c1, c2;
+    float lr, beta1, beta2, eps, c1, c2, omb1, omb2;
 };
 
 __device__ __forceinline__ void vn_adam_one(const VnPtrs &P, const VnAdam &h, uint32_t k,
                                             uint32_t p, float gk, float *grad_out)
 {
     if (grad_out) grad_out[k] = gk;
-    const float m = h.beta1 * P.m[k] + (1.0f - h.beta1) * gk;
-    const float v = h.beta2 * P.v[k] + (1.0f - h.beta2) * gk * gk;
+    const float m = h.beta1 * P.m[k] + h.omb1 * gk;
+    const float v = h.beta2 * P.v[k] + h.omb2 * gk * gk;
     P.m[k] = m;
     P.v[k] = v;
     const float w = P.master[k] - h.lr * (m / h.c1) / (sqrtf(v / h.c2) + h.eps);
@@ -1002,7 +1010,7 @@ hipError_t launch_vn_train_step(void *net, const uint4 *states, const uint8_t *p
     ga.grad = grad;
     ga.part = a.part;
     ga.n_parts = waves;
-    ga.h = VnAdam{lr, 0.9f, 0.999f, 1e-8f, c1, c2};
+    ga.h = VnAdam{lr, 0.9f, 0.999f, 1e-8f, c1, c2, (float)(1.0 - 0.9), (float)(1.0 - 0.999)};
     ga.inv_batch = a.inv_batch;
     ga.grad_out = grad_out;
     ga.loss_out = loss_out;

@@ -128,11 +128,12 @@ def compare(n_trees=1024, iterations=4096, ppl=64, band=0.05, train_cfg: TrainCo
     stats = mcts_tree_stats(ws, n_trees, mp_val)
     net_leaves = int(stats["net_leaves"].sum())
     played = int(stats["played_leaves"].sum())
-    # the same value search with two leaves per pass: their eight network
-    # rows share one matrix tile
+    # the same value search with four leaves per pass: their sixteen network
+    # rows fill one matrix tile
+    lpp = 4
     mp_val2 = mcts_params(iterations=iterations, playouts_per_leaf=1, max_depth=4, leaf_eval=1,
                           fallback_band=band, fallback_playouts=ppl, valuenet=net,
-                          leaves_per_pass=2)
+                          leaves_per_pass=lpp)
     best_val2, t_val2 = median_search(roots, mp_val2, seed, ws, reps)
     agree = float((best_val == best_roll).float().mean().item())
     ceiling = float((best_roll2 == best_roll).float().mean().item())
@@ -152,7 +153,8 @@ def compare(n_trees=1024, iterations=4096, ppl=64, band=0.05, train_cfg: TrainCo
         "speedup": speedup,
         "playouts_per_s_rollout": n_trees * iterations * ppl / t_roll,
         "fallback_rate": played / max(1, played + net_leaves),
-        "two_leaves_per_pass": {
+        "leaf_batched": {
+            "leaves_per_pass": lpp,
             "root_move_agreement": float((best_val2 == best_roll).float().mean().item()),
             "agreement_with_one_leaf_per_pass": float((best_val2 == best_val).float().mean().item()),
             "decisions_per_s": n_trees / t_val2,

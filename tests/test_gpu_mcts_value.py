@@ -14,8 +14,8 @@ root's children check credit to other players than the searching one
   any summation order, so the search's own rules are compared without
   rounding: band 0 (every leaf scored by the network) and band 0.05 (leaves
   whose root-player value is 1/2 fall back to 64 playouts), deep trees
-  (several times as many iterations as the root has guesses), one and two
-  leaves per pass.
+  (several times as many iterations as the root has guesses), one to four
+  leaves per pass (four leaves' perspective rows fill one matrix tile).
 """
 import numpy as np
 import pytest
@@ -79,7 +79,8 @@ def _value_kw(net, band, iters, dmax, lpp):
                 fallback_band=band, fallback_playouts=64, valuenet=net, leaves_per_pass=lpp)
 
 
-@pytest.mark.parametrize("band,dmax,lpp", [(0.0, 4, 1), (0.05, 4, 1), (0.0, 0, 2), (0.05, 3, 2)])
+@pytest.mark.parametrize("band,dmax,lpp", [(0.0, 4, 1), (0.05, 4, 1), (0.0, 0, 2), (0.05, 3, 2),
+                                           (0.05, 4, 3), (0.0, 4, 4)])
 def test_value_mode_trees_node_by_node(orc, dvc, band, dmax, lpp):
     p = exact_net.params()
     net = dvc.dvc_valuenet_init(0)

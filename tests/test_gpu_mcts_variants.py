@@ -235,6 +235,6 @@ def test_leaf_batching_root_parallel(orc, dvc):
 def test_leaf_batching_argument_errors(dvc):
     st = torch.zeros((2, 4), dtype=torch.int32, device="cuda")
     for bad in (dict(leaves_per_pass=0), dict(leaves_per_pass=17),
-                dict(leaves_per_pass=3, leaf_eval=1, valuenet=st)):
+                dict(leaves_per_pass=5, leaf_eval=1, valuenet=st)):
         with pytest.raises(dvc.DvcError):
             dvc.mcts_search(st, dvc.mcts_params(**bad), 1)

@@ -145,6 +145,12 @@ def test_adam_three_steps_vs_oracle(orc, dvc):
     w = params.astype(np.float64).copy()
     m = np.zeros_like(w)
     v = np.zeros_like(w)
+    # float32 rounding of the first moment scales with the terms it adds,
+    # beta1 |m| + (1 - beta1) |g|, not with m, which can cancel: A is that
+    # scale (the decayed sum of |g|), and a few roundings of 2^-24 each are
+    # allowed for every step
+    A = np.zeros_like(w)
+    prev_w = w.copy()
     ws = None
     for step in range(1, 4):
         lr = 1e-3 * step   # a different rate per step
@@ -153,14 +159,18 @@ def test_adam_three_steps_vs_oracle(orc, dvc):
                                          ws=ws, grad_out=grad)
         g = grad.cpu().numpy().astype(np.float64)
         orc.vn_adam(w, m, v, g.copy(), step, lr=lr)
+        A = 0.9 * A + 0.1 * np.abs(g)
         got_w = dvc.dvc_valuenet_get_params(net).cpu().numpy().astype(np.float64)
         gm, gv = (t.cpu().numpy().astype(np.float64) for t in dvc.dvc_valuenet_get_moments(net))
-        assert np.allclose(gm, m, rtol=1e-5, atol=1e-30), step
+        err = np.abs(gm - m)
+        assert np.all(err <= 2.0 ** -20 * A), (step, int(np.argmax(err / np.maximum(A, 1e-300))))
         assert np.allclose(gv, v, rtol=1e-5, atol=1e-38), step
         assert np.allclose(got_w, w, rtol=1e-5, atol=1e-7), step
-        # the step moved the weights: Adam steps are about lr in size
-        moved = np.abs(got_w - params) > 0.5 * 1e-3
+        # the step moved the weights (every parameter with a nonzero first
+        # moment moves)
+        moved = got_w != prev_w
         assert moved.sum() > 50000, (step, moved.sum())
+        prev_w = got_w
     assert dvc.dvc_check() == 0
 
 
