@@ -27,7 +27,9 @@
  *     the tree search, once per device on the first search that needs it
  *     (grown, never freed, when a later search needs more entries; the
  *     growing call copies it synchronously, so make one search before
- *     capturing a graph).  Everything else lives in caller buffers.
+ *     capturing a graph), and the static scratch of mcts_search_noalloc
+ *     (part of the library's code object, one per device).  Everything else
+ *     lives in caller buffers.
  *
  * Random numbers: Philox4x32-10 (Salmon et al., SC'11) with key
  * (seed & 0xFFFFFFFF, seed >> 32).  A pick among k options from a word w is
@@ -83,7 +85,8 @@ enum dvc_status {
     DVC_ESTATE = -2,  /* a malformed packed state was found                 */
     DVC_EHIP = -3,    /* a HIP runtime call failed                          */
     DVC_ENOMEM = -4,  /* workspace too small / library allocation failed    */
-    DVC_ELIMIT = -5   /* a kernel hit an internal bound                     */
+    DVC_ELIMIT = -5,  /* a kernel hit an internal bound                     */
+    DVC_ETOOBIG = -6  /* beyond the static scratch of mcts_search_noalloc   */
 };
 
 /* Parameters of the synthetic state generator.
@@ -282,6 +285,27 @@ size_t dvc_mcts_workspace_bytes(int64_t n_trees, const dvc_mcts_params *params /
 int mcts_search(const dvc_state_t *roots, int64_t n_trees, const dvc_mcts_params *params /* host */,
                 uint64_t seed, uint32_t tree_id_base, void *workspace, size_t workspace_bytes,
                 int32_t *best_action, dvc_child_stat *root_children, void *stream);
+
+/* mcts_search_noalloc -- mcts_search for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): no workspace argument and no allocation
+ * in the call.  The trees and the natural-log table live in a library-owned
+ * static device array, one per device, kept until the process ends:
+ * DVC_NOALLOC_TREE_BYTES of trees (dvc_mcts_workspace_bytes(n_trees, params)
+ * must not exceed it) and a table of 2^20 entries (iterations times the
+ * playouts per leaf -- fallback playouts in value mode -- below 2^20).  The
+ * first call on a device sets the array up (its address, then the table,
+ * copied synchronously); later calls only enqueue the search.  Same results
+ * as mcts_search with the same arguments.  Every call on one device shares
+ * that device's array: calls that overlap on one GPU (other streams, other
+ * host threads) race, so serialise them.  The array keeps the last call's
+ * trees; a call does not depend on them.  Returns DVC_ETOOBIG beyond either
+ * limit; other errors as mcts_search.                                    */
+#define DVC_NOALLOC_TREE_BYTES (64ull << 20)
+int mcts_search_noalloc(const dvc_state_t *roots, int64_t n_trees,
+                        const dvc_mcts_params *params /* host */, uint64_t seed,
+                        uint32_t tree_id_base, int32_t *best_action,
+                        dvc_child_stat *root_children, void *stream);
 
 /* dvc_mcts_autotune -- picks playouts per leaf and leaves per pass for
  * searches like this one (Sec. IV-B: the paper sweeps threads and warps for

@@ -20,6 +20,8 @@ LIB_PATH = os.path.join(HERE, "libdvc.so")
 MAX_ACTIONS = 864
 
 DVC_OK, DVC_EINVAL, DVC_ESTATE, DVC_EHIP, DVC_ENOMEM, DVC_ELIMIT = 0, -1, -2, -3, -4, -5
+DVC_ETOOBIG = -6
+NOALLOC_TREE_BYTES = 64 << 20
 
 
 class DvcError(RuntimeError):
@@ -114,6 +116,8 @@ def lib():
             L.dvc_mcts_workspace_bytes.argtypes = [i64, C.POINTER(MctsParams)]
             L.mcts_search.argtypes = [vp, i64, C.POINTER(MctsParams), u64, u32, vp, C.c_size_t,
                                       vp, vp, vp]
+            L.mcts_search_noalloc.argtypes = [vp, i64, C.POINTER(MctsParams), u64, u32, vp, vp,
+                                              vp]
             L.mcts_search_root_parallel.argtypes = [vp, i64, i32, C.POINTER(MctsParams), u64, u32,
                                                     vp, C.c_size_t, vp, vp, vp]
             L.dvc_mcts_autotune.argtypes = [vp, i64, C.POINTER(MctsParams), u64, u32, vp,
@@ -253,6 +257,24 @@ def mcts_search(roots: torch.Tensor, params: MctsParams, seed: int, tree_id_base
                            _ptr(workspace), workspace.numel(), _ptr(best), _ptr(kids),
                            _stream(stream))
     _raise(rc, "mcts_search")
+    return best, kids
+
+
+def mcts_search_noalloc(roots: torch.Tensor, params: MctsParams, seed: int, tree_id_base: int = 0,
+                        best=None, kids=None, stream=None):
+    """mcts_search with the trees in the library's static scratch (no
+    workspace, nothing allocated by the call).  Outputs as mcts_search; pass
+    `best` (int32 [n]) and `kids` (int32 [n, 864, 3] or None) to reuse
+    buffers."""
+    _check_dev(roots, torch.int32, None, "roots")
+    n = roots.shape[0]
+    if best is None:
+        best = torch.empty(n, dtype=torch.int32, device=roots.device)
+    _check_dev(best, torch.int32, (n,), "best")
+    _check_dev(kids, torch.int32, (n, MAX_ACTIONS, 3), "kids")
+    rc = lib().mcts_search_noalloc(_ptr(roots), n, C.byref(params), seed & (2**64 - 1),
+                                   tree_id_base, _ptr(best), _ptr(kids), _stream(stream))
+    _raise(rc, "mcts_search_noalloc")
     return best, kids
 
 

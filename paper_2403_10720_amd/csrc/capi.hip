@@ -210,6 +210,7 @@ const char *dvc_status_str(int status)
     case DVC_EHIP: return "HIP runtime error";
     case DVC_ENOMEM: return "workspace too small or allocation failed";
     case DVC_ELIMIT: return "internal bound reached";
+    case DVC_ETOOBIG: return "request exceeds the static scratch of the allocation-free entry point";
     default: return "unknown status";
     }
 }
@@ -433,11 +434,14 @@ size_t dvc_mcts_workspace_bytes(int64_t n_trees, const dvc_mcts_params *params)
 }
 
 // merge = false: one tree per root, statistics in creation order;
-// merge = true: trees_per_root trees per root amalgamated by action id
+// merge = true: trees_per_root trees per root amalgamated by action id.
+// static_ln: a natural-log table of static_ln_entries entries to use instead
+// of the library-allocated one (the allocation-free entry point's).
 static int run_search(const dvc_state_t *roots, int64_t n_roots, int64_t trees_per_root, bool merge,
                       const dvc_mcts_params *user_params, uint64_t seed, uint32_t tree_id_base,
                       void *workspace, size_t workspace_bytes, int32_t *best_action,
-                      dvc_child_stat *children, void *stream)
+                      dvc_child_stat *children, void *stream, const float *static_ln = nullptr,
+                      uint64_t static_ln_entries = 0)
 {
     if (n_roots < 0 || trees_per_root < 1 || trees_per_root > 65536 ||
         !mcts_params_ok(user_params))
@@ -455,7 +459,8 @@ static int run_search(const dvc_state_t *roots, int64_t n_roots, int64_t trees_p
     const uint64_t w_leaf =
         (uint64_t)(params->leaf_eval ? params->fallback_playouts : params->playouts_per_leaf);
     const uint64_t need = (uint64_t)params->iterations * w_leaf + 1u;
-    const float *ln = ln_table(need, &status);
+    if (static_ln != nullptr && need > static_ln_entries) return DVC_ETOOBIG;
+    const float *ln = static_ln != nullptr ? static_ln : ln_table(need, &status);
     if (ln == nullptr) return status;
     hipError_t e = launch_mcts(reinterpret_cast<const uint4 *>(roots), (uint32_t)n_trees,
                                (uint32_t)trees_per_root, (uint32_t)params->iterations,
@@ -483,6 +488,75 @@ int mcts_search(const dvc_state_t *roots, int64_t n_trees, const dvc_mcts_params
 {
     return run_search(roots, n_trees, 1, false, params, seed, tree_id_base, workspace, workspace_bytes,
                       best_action, root_children, stream);
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free search.  The trees and the natural-log table live in
+// `scratch`, a file-scope device array: every device the library runs on
+// holds its own copy, at its own address, until the process ends.  Its first
+// kScratchLnEntries floats are the table LN[k] = float(log(double k)),
+// written once per device at set-up; the rest holds the trees of the call
+// in flight.  Host code never passes the array's name to a kernel or a copy
+// (on the host it is a stand-in, not a device address): it uses the address
+// hipGetSymbolAddress returns for the current device.
+// ---------------------------------------------------------------------------
+constexpr uint64_t kScratchLnEntries = 1ull << 20;
+constexpr uint64_t kScratchLnBytes = kScratchLnEntries * sizeof(float);
+constexpr uint64_t kScratchBytes = kScratchLnBytes + ((uint64_t)DVC_NOALLOC_TREE_BYTES);
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+static std::mutex g_scratch_mutex;
+static uint8_t *g_scratch_dev[64] = {nullptr};
+
+// Set-up on the current device, once: the array's device address, then the
+// log table written into its first bytes (synchronous copies from a stack
+// buffer, no allocation).  Returns the address, or null with *status set.
+static uint8_t *scratch_on_device(int *status)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+        *status = DVC_EHIP;
+        return nullptr;
+    }
+    if (g_scratch_dev[dev] != nullptr) return g_scratch_dev[dev];
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || ptr == nullptr) {
+        *status = DVC_EHIP;
+        return nullptr;
+    }
+    constexpr uint64_t kChunk = 4096;
+    float buf[kChunk];
+    for (uint64_t base = 0; base < kScratchLnEntries; base += kChunk) {
+        for (uint64_t k = 0; k < kChunk; ++k) {
+            const uint64_t i = base + k;
+            buf[k] = i == 0 ? 0.0f : (float)std::log((double)i);
+        }
+        if (hipMemcpy(static_cast<uint8_t *>(ptr) + base * sizeof(float), buf, sizeof(buf),
+                      hipMemcpyHostToDevice) != hipSuccess) {
+            *status = DVC_EHIP;
+            return nullptr;
+        }
+    }
+    g_scratch_dev[dev] = static_cast<uint8_t *>(ptr);
+    return g_scratch_dev[dev];
+}
+
+int mcts_search_noalloc(const dvc_state_t *roots, int64_t n_trees, const dvc_mcts_params *params,
+                        uint64_t seed, uint32_t tree_id_base, int32_t *best_action,
+                        dvc_child_stat *root_children, void *stream)
+{
+    if (n_trees < 0 || !mcts_params_ok(params)) return DVC_EINVAL;
+    const dvc_mcts_params rp = resolved(params, n_trees);
+    const size_t need = dvc_mcts_workspace_bytes(n_trees, &rp);
+    if (n_trees > 0 && need == 0) return DVC_EINVAL;
+    if (need > (size_t)DVC_NOALLOC_TREE_BYTES) return DVC_ETOOBIG;
+    int status = DVC_OK;
+    uint8_t *base = scratch_on_device(&status);
+    if (base == nullptr) return status;
+    return run_search(roots, n_trees, 1, false, &rp, seed, tree_id_base, base + kScratchLnBytes,
+                      (size_t)DVC_NOALLOC_TREE_BYTES, best_action, root_children, stream,
+                      reinterpret_cast<const float *>(base), kScratchLnEntries);
 }
 
 int dvc_mcts_autotune(const dvc_state_t *roots, int64_t n_trees, const dvc_mcts_params *params,
