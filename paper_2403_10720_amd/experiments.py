@@ -135,6 +135,10 @@ def compare(n_trees=1024, iterations=4096, ppl=64, band=0.05, train_cfg: TrainCo
                           fallback_band=band, fallback_playouts=ppl, valuenet=net,
                           leaves_per_pass=lpp)
     best_val2, t_val2 = median_search(roots, mp_val2, seed, ws, reps)
+    phases_val2 = tree_phases(ws, n_trees, mp_val2)
+    # the playout search's phases (its trees are overwritten above)
+    timed_search(roots, mp_roll, seed, ws)
+    phases_roll = tree_phases(ws, n_trees, mp_roll)
     agree = float((best_val == best_roll).float().mean().item())
     ceiling = float((best_roll2 == best_roll).float().mean().item())
     speedup = t_roll / t_val
@@ -158,7 +162,9 @@ def compare(n_trees=1024, iterations=4096, ppl=64, band=0.05, train_cfg: TrainCo
             "root_move_agreement": float((best_val2 == best_roll).float().mean().item()),
             "agreement_with_one_leaf_per_pass": float((best_val2 == best_val).float().mean().item()),
             "decisions_per_s": n_trees / t_val2,
-            "gpu_s_per_decision": t_val2 / n_trees, "speedup": t_roll / t_val2},
+            "gpu_s_per_decision": t_val2 / n_trees, "speedup": t_roll / t_val2,
+            "phases": phases_val2},
+        "rollout_phases": phases_roll,
         "targets": {"root_move_agreement": {"target": TARGET_AGREEMENT, "measured": agree,
                                             "met": agree >= TARGET_AGREEMENT},
                     "gpu_seconds_ratio": {"target": TARGET_SPEEDUP,
@@ -320,33 +326,45 @@ SEARCH_WORKLOADS = {
 }
 
 
+def tree_phases(ws, n, mp):
+    """Per-phase shares of the trees' shader clock cycles (the counters each
+    tree leaves in its workspace), mean cycles per iteration, and the slowest
+    tree's cycles per iteration (a batched launch lasts as long as it does)."""
+    st = mcts_tree_stats(ws, n, mp)
+    cyc = torch.stack([st["cycles_sample"], st["cycles_descend"], st["cycles_evaluate"],
+                       st["cycles_backprop"]], 1).double()
+    tot = cyc.sum(1)
+    frac = (cyc / tot[:, None]).mean(0).tolist()
+    per_it = tot / mp.iterations
+    return {"cycles_per_iteration": float(per_it.mean()),
+            "slowest_tree_cycles_per_iteration": float(per_it.max()),
+            "sample": frac[0], "descend": frac[1], "evaluate": frac[2], "backprop": frac[3]}
+
+
 def search_phases(net=None):
     """Share of each search phase in the shader clock cycles of the iterations
     (per-tree counters kept by the kernel), for the three search workloads and,
-    with a network, the value-mode search of the last one (band 0: every leaf
-    scored by the network)."""
+    with a network, the value-mode searches of the last one: band 0 (every leaf
+    scored by the network), one leaf per pass.  Also the cycles of the
+    slowest tree against the mean: a batched launch lasts as long as its
+    slowest tree."""
     out = {}
-    work = dict(SEARCH_WORKLOADS)
+    work = {k: v + (1, None) for k, v in SEARCH_WORKLOADS.items()}
     if net is not None:
-        work["1024 fresh deals, 4096 iterations, value mode, band 0"] = \
-            SEARCH_WORKLOADS["1024 fresh 2-4 player deals, 4096 x 64"]
-    for name, (n, deal, iters, ppl, seed) in work.items():
+        base = SEARCH_WORKLOADS["1024 fresh 2-4 player deals, 4096 x 64"]
+        work["1024 fresh deals, 4096 iterations, value mode, band 0"] = base + (1, 0.0)
+    for name, (n, deal, iters, ppl, seed, lpp, band) in work.items():
         roots = dvc_init_states(n, deal_params(**deal), seed)
-        if "value mode" in name:
+        if band is not None:
             mp = mcts_params(iterations=iters, playouts_per_leaf=1, max_depth=4, leaf_eval=1,
-                             fallback_band=0.0, fallback_playouts=ppl, valuenet=net)
+                             fallback_band=band, fallback_playouts=ppl, valuenet=net,
+                             leaves_per_pass=lpp)
         else:
             mp = mcts_params(iterations=iters, playouts_per_leaf=ppl, max_depth=4)
         ws = torch.empty(dvc_mcts_workspace_bytes(n, mp), dtype=torch.uint8, device=roots.device)
         mcts_search(roots, mp, seed, workspace=ws, want_children=False)
         torch.cuda.synchronize()
-        st = mcts_tree_stats(ws, n, mp)
-        cyc = torch.stack([st["cycles_sample"], st["cycles_descend"], st["cycles_evaluate"],
-                           st["cycles_backprop"]], 1).double()
-        tot = cyc.sum(1)
-        frac = (cyc / tot[:, None]).mean(0).tolist()
-        out[name] = {"cycles_per_iteration": float((tot / iters).mean()),
-                     "sample": frac[0], "descend": frac[1], "evaluate": frac[2], "backprop": frac[3]}
+        out[name] = tree_phases(ws, n, mp)
     return out
 
 
