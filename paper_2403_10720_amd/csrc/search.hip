@@ -250,22 +250,23 @@ __device__ bool det_fallback(const State &R, State &out, DfsSlots &sl)
 // Legal guessed values (12-bit mask over v) of pair k = (r-1)*24 + s for the
 // mover of S: target seat (m + r) mod P still in, slot s exists and is
 // hidden, value 2v + colour is a consistent candidate.
+// Straight-line code: every lane computes the candidate mask (the k-th-bit
+// lookup stays inside the table for any slot) and the conditions select it.
 __device__ __forceinline__ uint32_t legal_values(const State &S, uint32_t k, const uint8_t *tab)
 {
     const uint32_t r = k / 24u + 1u, slot = k - (k / 24u) * 24u;
-    if (r >= S.P) return 0u;
     const uint32_t q = S.m + r >= S.P ? S.m + r - S.P : S.m + r;
     const uint32_t row = hand_of(S, q);
-    if ((row & ~S.rev) == 0u || slot >= (uint32_t)__popc(row)) return 0u;
     const uint32_t t = kth_bit_tab(row, slot, tab);
-    if ((S.rev >> t) & 1u) return 0u;
+    const bool ok = (r < S.P) & ((row & ~S.rev) != 0u) & (slot < (uint32_t)__popc(row)) &
+                    !((S.rev >> t) & 1u);
     uint32_t x = candidates(t, row, hand_of(S, S.m), S.rev) >> (t & 1u);
     x &= 0x555555u;
     x = (x | (x >> 1)) & 0x333333u;
     x = (x | (x >> 2)) & 0x0F0F0Fu;
     x = (x | (x >> 4)) & 0x00FF00FFu;
     x = (x | (x >> 8)) & 0x0000FFFFu;
-    return x & 0xFFFu;
+    return ok ? x & 0xFFFu : 0u;
 }
 
 // The turn passes: the next seat with hidden tiles becomes the mover and
@@ -382,48 +383,36 @@ __device__ __forceinline__ State readlane_state(const State &s, uint32_t lane)
     return r;
 }
 
-// arg-max step: the other candidate (os, oi) replaces (s, idx) if its score
-// is greater, or equal with a lower index
-__device__ __forceinline__ void argmax_take(float &s, uint32_t &idx, float os, uint32_t oi)
-{
-    const bool take = os > s || (os == s && oi < idx);
-    s = take ? os : s;
-    idx = take ? oi : idx;
-}
+// greater of two scores (no NaN arises: every visited child has N >= 1)
+__device__ __forceinline__ float score_max(float a, float b) { return a > b ? a : b; }
 
-// one exchange between the lanes of a 16-lane row (data-parallel-primitive
-// move with row control CTRL), then the arg-max step
 template <int CTRL>
-__device__ __forceinline__ void argmax_dpp(float &s, uint32_t &idx)
+__device__ __forceinline__ float dpp_f(float s)
 {
-    const float os =
-        __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(s), CTRL, 0xF, 0xF, false));
-    const uint32_t oi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)idx, CTRL, 0xF, 0xF, false);
-    argmax_take(s, idx, os, oi);
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(s), CTRL, 0xF, 0xF, false));
 }
 
-// Wavefront arg-max: greatest score, lowest index on ties; every lane gets
-// the result.  The candidates are totally ordered (score descending, index
-// ascending), so any order of pairwise steps gives the same winner: within
-// each 16-lane row by lane exchanges (lane ^ 1, lane ^ 2, then the mirror
-// images within 8 and within 16 lanes), then the four rows' winners, read
-// from lanes 0, 16, 32, 48, in row order.  All 64 lanes must be active.
-__device__ __forceinline__ void wave_argmax(float &s, uint32_t &idx)
+// Wavefront arg-max of scores whose index is base + lane: the greatest score
+// (every lane gets it) and the lowest lane holding it, which is the lowest
+// index on ties; lane -1 when every score is -inf (nothing playable).  The
+// maximum is reduced within each 16-lane row by lane exchanges (lane ^ 1,
+// lane ^ 2, then the mirror images within 8 and within 16 lanes), then over
+// the four rows' maxima; the lane is the lowest set bit of the ballot of
+// lanes equal to it.  All 64 lanes must be active.
+__device__ __forceinline__ int wave_argmax_lane(float s, float &best)
 {
-    argmax_dpp<0xB1>(s, idx);    // quad_perm [1, 0, 3, 2]
-    argmax_dpp<0x4E>(s, idx);    // quad_perm [2, 3, 0, 1]
-    argmax_dpp<0x141>(s, idx);   // row_half_mirror
-    argmax_dpp<0x140>(s, idx);   // row_mirror
-    float bs = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(s), 0));
-    uint32_t bi = __builtin_amdgcn_readlane(idx, 0);
-#pragma unroll
-    for (int row = 1; row < 4; ++row) {
-        const float os = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(s), 16 * row));
-        const uint32_t oi = __builtin_amdgcn_readlane(idx, 16 * row);
-        argmax_take(bs, bi, os, oi);
-    }
-    s = bs;
-    idx = bi;
+    float m = s;
+    m = score_max(m, dpp_f<0xB1>(m));    // quad_perm [1, 0, 3, 2]
+    m = score_max(m, dpp_f<0x4E>(m));    // quad_perm [2, 3, 0, 1]
+    m = score_max(m, dpp_f<0x141>(m));   // row_half_mirror
+    m = score_max(m, dpp_f<0x140>(m));   // row_mirror
+    const float r0 = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(m), 0));
+    const float r1 = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(m), 16));
+    const float r2 = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(m), 32));
+    const float r3 = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(m), 48));
+    best = score_max(score_max(r0, r1), score_max(r2, r3));
+    const uint64_t hit = __ballot(s == best);
+    return best == -__builtin_inff() ? -1 : (int)__builtin_ctzll(hit);
 }
 
 __device__ __forceinline__ void wave_argmax_u(uint32_t &n, uint32_t &idx)
@@ -704,8 +693,9 @@ mcts_tree_kernel(MctsArgs a)
                 const uint32_t cbw0 = W[rec + 4u + half + (lane >> 1)];
                 const uint32_t cbw1 = lane < 8u ? W[rec + 36u + half + (lane >> 1)]
                                                 : lane == 8u ? W[rec + 3u] : 0u;
-                const uint32_t nchild = W[rec + 2u];
+                const uint32_t nchild_v = W[rec + 2u];
                 const uint4 ent0 = *reinterpret_cast<const uint4 *>(W + rec + node_words + lane * kEntryWords);
+                const uint32_t next0_v = bnext[node];   // the second child block, if any
                 const float lp = a.ln[node_n];
                 const uint32_t l0 = legal_values(S, lane, tab);
                 const uint32_t l1 = lane < 8u ? legal_values(S, 64u + lane, tab)
@@ -717,14 +707,22 @@ mcts_tree_kernel(MctsArgs a)
                 const uint32_t u0 = l0 & ~cb0, u1 = l1 & ~cb1;
                 const uint64_t b0 = __ballot(u0 != 0u), b1 = __ballot(u1 != 0u);
                 tree_sync<VALUE>();
+                // uniform values every lane loaded, read once after the loads
+                // have landed, so that the loops over blocks stay scalar
+                const uint32_t nchild = __builtin_amdgcn_readfirstlane(nchild_v);
+                const uint32_t next0 = __builtin_amdgcn_readfirstlane(next0_v);
                 if (b0 | b1) {
                     // expansion: the lowest playable key that has no child yet --
                     // the stop before the guesses after a right guess
-                    uint32_t key, word, bit;
+                    // the record word that gets the new key's bit, as this
+                    // level loaded it: word 3 is lane 8's cbw1, a guess bitmap
+                    // word that of the pair's lane (cbw0, or cbw1 past pair 63)
+                    uint32_t key, word, bit, old;
                     if ((b1 >> 8) & 1u) {
                         key = kStopKey;
                         word = 3u;
                         bit = 1u;
+                        old = __builtin_amdgcn_readlane(cbw1, 8);
                     } else {
                         uint32_t pair, vbits;
                         if (b0) {
@@ -739,10 +737,12 @@ mcts_tree_kernel(MctsArgs a)
                         key = pair * 12u + v + (cont ? kStopKey + 1u : 0u);
                         word = 4u + half + (pair >> 1);
                         bit = 1u << (v + (pair & 1u) * 16u);
+                        old = pair < 64u ? __builtin_amdgcn_readlane(cbw0, pair)
+                                         : __builtin_amdgcn_readlane(cbw1, pair - 64u);
                     }
                     uint32_t e;
                     append_child(node, nchild, key | (S.m << 16), 0u, e);
-                    if (lane == 0) W[rec + word] |= bit;
+                    if (lane == 0) W[rec + word] = old | bit;
                     path_e[np++] = e;
                     last_block = depth;
                     term = apply_action(S, key, a.cont_mode != 0u, chance_at(cw, depth), winner,
@@ -753,41 +753,52 @@ mcts_tree_kernel(MctsArgs a)
                 // selection: UCT over the playable children, 64 per pass
                 float best_s = -__builtin_inff();
                 uint32_t best_i = 0xFFFFFFFFu, best_e = 0u, best_act = 0u, best_node = 0u, best_n = 0u;
-                uint32_t blk = node;
+                // block blk's entries are scored while the next block's (and
+                // the block id after it) are being loaded
+                uint32_t blk = node, nxt = next0;
                 uint4 ent = ent0;
                 for (uint32_t base = 0; base < nchild; base += kBlockEntries) {
-                    if (base > 0u) ent = *reinterpret_cast<const uint4 *>(W + block_off(blk) + lane * kEntryWords);
-                    const uint32_t ci = base + lane;
-                    float sc = -__builtin_inff();
-                    uint32_t idx = 0xFFFFFFFFu;
-                    if (ci < nchild) {
-                        const uint32_t key = ent.x & 0xFFFFu;
-                        const bool after_right = key > kStopKey;
-                        const uint32_t act = after_right ? key - kStopKey - 1u : key;
-                        const uint32_t pr = act / 12u;
-                        const bool playable =
-                            key == kStopKey ? cont
-                                            : after_right == cont && ((legal_s[pr] >> (act - pr * 12u)) & 1u);
-                        if (playable) {
-                            const float n = (float)ent.y;
-                            const float q = __uint_as_float(ent.z) / n;
-                            const float ex = lp / n;
-                            const float u = a.c_uct * sqrtf(ex);
-                            sc = q + u;
-                            idx = ci;
-                        }
+                    const bool more = base + kBlockEntries < nchild;
+                    uint4 ent_n = ent;
+                    uint32_t nxt_n = kNoBlock;
+                    if (more) {
+                        ent_n = *reinterpret_cast<const uint4 *>(W + block_off(nxt) + lane * kEntryWords);
+                        if (base + 2u * kBlockEntries < nchild)
+                            nxt_n = __builtin_amdgcn_readfirstlane(bnext[nxt]);
                     }
-                    wave_argmax(sc, idx);
-                    if (idx != 0xFFFFFFFFu && (best_i == 0xFFFFFFFFu || sc > best_s)) {
-                        const uint32_t wl = idx - base;
-                        best_s = sc;
-                        best_i = idx;
+                    // straight-line scoring: every lane computes a score (a
+                    // lane past the children reads some entry: its pair index
+                    // is clamped into the legal table) and the playable ones
+                    // keep it
+                    const uint32_t ci = base + lane;
+                    const uint32_t key = ent.x & 0xFFFFu;
+                    const bool after_right = key > kStopKey;
+                    const uint32_t act = after_right ? key - kStopKey - 1u : key;
+                    const uint32_t pr = act / 12u < 72u ? act / 12u : 72u;
+                    const bool legal = (legal_s[pr] >> ((act - pr * 12u) & 31u)) & 1u;
+                    const bool playable =
+                        (ci < nchild) & (key == kStopKey ? cont : (after_right == cont) & legal);
+                    const float n = (float)ent.y;
+                    const float q = __uint_as_float(ent.z) / n;
+                    const float ex = lp / n;
+                    const float u = a.c_uct * sqrtf(ex);
+                    const float sc = playable ? q + u : -__builtin_inff();
+                    float bs;
+                    const int bl = wave_argmax_lane(sc, bs);
+                    if (bl >= 0 && (best_i == 0xFFFFFFFFu || bs > best_s)) {
+                        const uint32_t wl = (uint32_t)bl;
+                        best_s = bs;
+                        best_i = base + wl;
                         best_e = block_off(blk) + wl * kEntryWords;
                         best_act = __builtin_amdgcn_readlane(ent.x, wl) & 0xFFFFu;
                         best_n = __builtin_amdgcn_readlane(ent.y, wl);
                         best_node = __builtin_amdgcn_readlane(ent.w, wl);
                     }
-                    if (base + kBlockEntries < nchild) blk = bnext[blk];
+                    if (more) {
+                        blk = nxt;
+                        ent = ent_n;
+                        nxt = nxt_n;
+                    }
                 }
                 node = best_node;
                 node_n = best_n;
@@ -888,12 +899,14 @@ mcts_tree_kernel(MctsArgs a)
                 // ---- 4. back-propagation --------------------------------------------
                 n_root += nplay;
                 if (lane < np) {
+                    // the entry {key | chooser << 16, N, W, id} in one load
                     const uint32_t e = path_e[lane];
-                    W[e + 1u] += nplay;
+                    const uint4 en = *reinterpret_cast<const uint4 *>(W + e);
+                    W[e + 1u] = en.y + nplay;
                     if (!(a.vanilla && lane == 0u)) {   // a world node's W word holds its key
-                        const uint32_t chooser = W[e] >> 16;
+                        const uint32_t chooser = en.x >> 16;
                         const float wc = chooser == 0u ? vals[0] : chooser == 1u ? vals[1] : chooser == 2u ? vals[2] : vals[3];
-                        W[e + 2u] = __float_as_uint(__uint_as_float(W[e + 2u]) + wc);
+                        W[e + 2u] = __float_as_uint(__uint_as_float(en.z) + wc);
                     }
                 }
                 tree_sync<VALUE>();
@@ -1035,9 +1048,10 @@ mcts_tree_kernel(MctsArgs a)
                 // the chooser's value by a computed index: a chain of selects
                 // over the four LDS entries was compiled into branches that
                 // left seat 3's lanes reading seat 2's entry
-                const uint32_t chooser = (W[e] >> 16) & 3u;
+                const uint4 en = *reinterpret_cast<const uint4 *>(W + e);
+                const uint32_t chooser = (en.x >> 16) & 3u;
                 const float wc = vals[b][chooser];
-                W[e + 2u] = __float_as_uint(__uint_as_float(W[e + 2u]) + wc);
+                W[e + 2u] = __float_as_uint(__uint_as_float(en.z) + wc);
             }
             tree_sync<VALUE>();
         }
