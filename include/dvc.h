@@ -149,7 +149,9 @@ int dvc_rollout(const dvc_state_t *leaves, int64_t n_leaves, int32_t playouts_pe
  * random words computed during the step before, 7 = one playout per lane
  * with the workgroup's unfinished games packed into its first lanes at
  * fixed step counts (Sec. IV-B's divergence: wavefronts left without a game
- * stop issuing; `grid` 0/1 = steps 6, 9, 12, 2 = steps 5, 8, 11, 14).
+ * stop issuing; `grid` 0/1 = steps 6, 9, 12, 2 = steps 5, 8, 11, 14),
+ * 8 = variant 7 (steps 5, 8, 11, 14) with two games per lane advanced
+ * together, 512 playouts per workgroup.
  * block/grid 0 = automatic.  Same outputs for every variant and shape.
  * flags: DVC_ROLLOUT_ACCUMULATE adds the wins to seat_wins instead of
  * overwriting it (the caller zeroes it once; several calls then tally into
@@ -162,9 +164,9 @@ int dvc_rollout_ex(const dvc_state_t *leaves, int64_t n_leaves, int32_t playouts
                    int32_t variant, int32_t block, int32_t grid, int32_t flags, void *stream);
 
 /* dvc_rollout_autotune -- runs this batch with every rollout kernel shape in
- * a fixed candidate list (variant 7 with steps 5, 8, 11, 14, variant 4 with 1
- * or 2 playouts per lane, variant 1, variant 5 with 128/256/512-playout
- * items), each launched twice with the
+ * a fixed candidate list (variant 7 with steps 5, 8, 11, 14, variant 8,
+ * variant 4 with 1 or 2 playouts per lane, variant 1, variant 5 with
+ * 128/256/512-playout items), each launched twice with the
  * second launch timed by HIP events on `stream`, and remembers the fastest
  * for batches of the same size class (device, floor(log2(n_leaves *
  * playouts_per_leaf)), playouts_per_leaf >= 256 / >= 64 / smaller): later

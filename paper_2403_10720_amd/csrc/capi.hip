@@ -325,10 +325,11 @@ static int rollout_impl(const dvc_state_t *leaves, int64_t n_leaves, int32_t ppl
     a.length = length;
     a.seat_wins = seat_wins;
     a.stats = nullptr;
-    // variant 7 with whole leaves per 256-playout workgroup stores each
-    // leaf's sums itself: no zeroing launch
-    a.store_wins = (seat_wins && !(flags & DVC_ROLLOUT_ACCUMULATE) && v == 7 && ppl <= 256 &&
-                    256 % ppl == 0) ? 1u : 0u;
+    // variants 7 and 8 with whole leaves per workgroup (256 and 512
+    // playouts) store each leaf's sums themselves: no zeroing launch
+    const uint32_t per_group = v == 8 ? 512u : 256u;   // playouts per workgroup
+    a.store_wins = (seat_wins && !(flags & DVC_ROLLOUT_ACCUMULATE) && (v == 7 || v == 8) &&
+                    (uint32_t)ppl <= per_group && per_group % (uint32_t)ppl == 0u) ? 1u : 0u;
     if (a.total == 0) return DVC_OK;
     if (seat_wins && !(flags & DVC_ROLLOUT_ACCUMULATE) && !a.store_wins) {
         hipError_t e = launch_fill_u32(seat_wins, (uint64_t)n_leaves * 4u, 0u, st);
@@ -352,7 +353,7 @@ int dvc_rollout_ex(const dvc_state_t *leaves, int64_t n_leaves, int32_t ppl, uin
     if ((flags & ~DVC_ROLLOUT_ACCUMULATE) != 0) return DVC_EINVAL;
     const int ok = rollout_args_ok(leaves, n_leaves, ppl);
     if (ok != DVC_OK) return ok;
-    if (variant < 0 || variant > 7) return DVC_EINVAL;
+    if (variant < 0 || variant > 8) return DVC_EINVAL;
     if (block != 0 && block != 64 && block != 128 && block != 256 && block != 512) return DVC_EINVAL;
     if (grid < 0) return DVC_EINVAL;
     const Shape sh = variant != 0 ? Shape{variant, block, grid}
@@ -369,8 +370,8 @@ int dvc_rollout_autotune(const dvc_state_t *leaves, int64_t n_leaves, int32_t pp
     if (ok != DVC_OK) return ok;
     const uint64_t total = (uint64_t)n_leaves * (uint64_t)ppl;
     if (total == 0) return DVC_EINVAL;
-    static const Shape kCandidates[] = {{7, 0, 2}, {4, 0, 1}, {1, 0, 0}, {4, 0, 2}, {5, 0, 2},
-                                        {5, 0, 4}, {5, 0, 8}};
+    static const Shape kCandidates[] = {{7, 0, 2}, {8, 0, 0}, {4, 0, 1}, {1, 0, 0}, {4, 0, 2},
+                                        {5, 0, 2}, {5, 0, 4}, {5, 0, 8}};
     hipStream_t st = (hipStream_t)stream;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {

@@ -744,6 +744,163 @@ __global__ void __launch_bounds__(256) rollout_compact(RolloutArgs a)
 }
 
 // ---------------------------------------------------------------------------
+// Variant 8: variant 7 with two games per lane, advanced together.
+//
+// A guess step is one long chain of dependent operations (the Philox rounds,
+// then the table lookups of the guess); a lane that carries two games issues
+// two independent chains side by side, so a wavefront has work to issue while
+// either chain waits.  A workgroup of 256 lanes holds 512 games: game slot k
+// lives in lane k / 2 (k even: first game, odd: second).  Both games of a
+// lane run every step; a finished game's step is computed and discarded (its
+// outcome was recorded when it ended), so the step needs no branch.  At
+// steps 5, 8, 11, 14 the workgroup packs its unfinished games into its first
+// slots, in slot order, exactly as variant 7 does with one game per lane, so
+// a wavefront whose 128 slots are empty stops issuing.  Outputs per original
+// slot, identical to every other variant's.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) rollout_compact2(RolloutArgs a)
+{
+    constexpr int NCP = kCompactCount[1];
+    __shared__ uint8_t tab[kKthTableBytes];
+    __shared__ uint32_t mig[7][512];       // packed state, playout id, round-1 key words
+    __shared__ uint8_t outc[512];          // packed outcome per original slot
+    __shared__ uint32_t wcnt[4];
+    __shared__ uint32_t lsum[512 * 4];     // store_wins: seat wins of the workgroup's leaves
+    fill_kth_table(tab);
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
+    const uint32_t base = blockIdx.x * 512u;
+    const uint32_t trk1 = a.tree ^ a.k1;
+
+    // game g of the lane (g = 0, 1): slot 2 tid + g
+    uint32_t j[2], winner[2] = {0u, 0u};
+    bool live[2] = {false, false};
+    State s[2];
+    PlayoutKey pk[2];
+#pragma unroll
+    for (uint32_t g = 0; g < 2u; ++g) {
+        j[g] = base + 2u * tid + g;
+        s[g].h0 = s[g].h1 = s[g].h2 = s[g].h3 = s[g].rev = 0u;
+        s[g].m = 0u; s[g].P = 2u; s[g].phase = 1u; s[g].drawn = -1;
+        pk[g] = PlayoutKey{0u, 0u, 0u, 0u};
+        outc[2u * tid + g] = (uint8_t)kOutError;
+    }
+    if (a.store_wins) {
+#pragma unroll
+        for (uint32_t q = 0; q < 8u; ++q) lsum[8u * tid + q] = 0u;
+    }
+#pragma unroll
+    for (uint32_t g = 0; g < 2u; ++g) {
+        if (j[g] < a.total) {
+            const uint32_t leaf = j[g] / a.ppl;
+            const uint4 st = a.leaves[leaf];
+            if (!decode(st.x, st.y, st.z, st.w, s[g])) {
+                atomicOr(&g_error_word, kErrState);
+            } else {
+                const uint32_t alive = alive_mask(s[g]);
+                winner[g] = (uint32_t)__builtin_ctz(alive | 16u);
+                if (__popc(alive) == 1) {
+                    outc[j[g] - base] = (uint8_t)winner[g];   // decided before any guess
+                } else {
+                    live[g] = true;
+                    pk[g] = playout_key(j[g] - leaf * a.ppl, a.leaf_base + leaf, a.k0);
+                }
+            }
+        }
+    }
+    __syncthreads();   // k-th-bit table ready
+
+#pragma unroll
+    for (int seg = 0; seg <= NCP; ++seg) {
+        const uint32_t first = seg == 0 ? 0u : kCompactSched[1][seg - 1];
+        const uint32_t limit = seg < NCP ? kCompactSched[1][seg] : kMaxGuesses;
+        for (uint32_t step = first; step < limit; ++step) {
+            if (__ballot(live[0] | live[1]) == 0ull) break;
+            const Words w0 = step_words(pk[0], trk1, a.k0, a.k1);
+            const Words w1 = step_words(pk[1], trk1, a.k0, a.k1);
+            uint32_t wn0 = winner[0], wn1 = winner[1];
+            const bool over0 = guess_step(s[0], w0, wn0, tab);
+            const bool over1 = guess_step(s[1], w1, wn1, tab);
+            next_step(pk[0]);
+            next_step(pk[1]);
+            if (live[0] && over0) {
+                outc[j[0] - base] = (uint8_t)(wn0 | ((step + 1u) << 2));
+                live[0] = false;
+            }
+            if (live[1] && over1) {
+                outc[j[1] - base] = (uint8_t)(wn1 | ((step + 1u) << 2));
+                live[1] = false;
+            }
+        }
+        if (seg == NCP) {
+            // still undecided after the most guesses a valid game can take
+            if (live[0] | live[1]) atomicOr(&g_error_word, kErrLimit);
+            break;
+        }
+        // pack the unfinished games into the first slots of the workgroup,
+        // in slot order (lane order, first game before second)
+        const uint64_t l0 = __ballot(live[0]), l1 = __ballot(live[1]);
+        if (lane == 0u) wcnt[wv] = (uint32_t)(__popcll(l0) + __popcll(l1));
+        __syncthreads();
+        uint32_t before = 0u, n_live = 0u;
+#pragma unroll
+        for (uint32_t w = 0; w < 4u; ++w) {
+            const uint32_t c = wcnt[w];
+            before += w < wv ? c : 0u;
+            n_live += c;
+        }
+        const uint32_t below =
+            __builtin_amdgcn_mbcnt_hi((uint32_t)(l0 >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)l0, 0u)) +
+            __builtin_amdgcn_mbcnt_hi((uint32_t)(l1 >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)l1, 0u));
+#pragma unroll
+        for (uint32_t g = 0; g < 2u; ++g) {
+            if (live[g]) {
+                const uint32_t dst = before + below + (g == 1u && live[0] ? 1u : 0u);
+                uint32_t e0, e1, e2, e3;
+                encode(s[g], e0, e1, e2, e3);
+                mig[0][dst] = e0;
+                mig[1][dst] = e1;
+                mig[2][dst] = e2;
+                mig[3][dst] = e3;
+                mig[4][dst] = j[g];
+                mig[5][dst] = pk[g].a;
+                mig[6][dst] = pk[g].b;
+            }
+        }
+        __syncthreads();
+        const uint64_t gm = (uint64_t)limit * kPhiloxM0;   // the step counter times M0
+#pragma unroll
+        for (uint32_t g = 0; g < 2u; ++g) {
+            const uint32_t k = 2u * tid + g;
+            live[g] = k < n_live;
+            if (live[g]) {
+                unpack_valid(mig[0][k], mig[1][k], mig[2][k], mig[3][k], s[g]);
+                j[g] = mig[4][k];
+                pk[g].a = mig[5][k];
+                pk[g].b = mig[6][k];
+                pk[g].gm_lo = (uint32_t)gm;
+                pk[g].gm_hi = (uint32_t)(gm >> 32);
+            }
+        }
+    }
+    __syncthreads();   // every game's outcome is in outc
+    if (!a.store_wins) {
+        emit_outcome(a, base + tid, outc[tid], lane);
+        emit_outcome(a, base + 256u + tid, outc[256u + tid], lane);
+        return;
+    }
+    // the workgroup holds whole leaves (ppl divides 512): sum them in LDS and
+    // store each leaf's four counts once, over whatever the table held
+    const uint32_t leaf0 = base / a.ppl;
+    emit_outcome(a, base + tid, outc[tid], lane, lsum, leaf0);
+    emit_outcome(a, base + 256u + tid, outc[256u + tid], lane, lsum, leaf0);
+    __syncthreads();
+    const uint32_t last = (base + 511u < a.total ? base + 511u : a.total - 1u) / a.ppl;
+    const uint32_t nw4 = 4u * (last - leaf0 + 1u);
+    if (a.seat_wins)
+        for (uint32_t e = tid; e < nw4; e += 256u) a.seat_wins[(size_t)leaf0 * 4u + e] = lsum[e];
+}
+
+// ---------------------------------------------------------------------------
 // Variant 5: one wavefront per single-leaf item of up to 64*K playouts.  A
 // lane whose game ended takes the item's next playout at once (ballot +
 // mbcnt prefix over the lanes that finished); the leaf's start state stays
@@ -903,6 +1060,12 @@ hipError_t launch_rollout(const RolloutArgs &a, int variant, int block, int grid
             hipLaunchKernelGGL(rollout_compact<1>, dim3(blocks), dim3(256), 0, st, a);
         else
             hipLaunchKernelGGL(rollout_compact<0>, dim3(blocks), dim3(256), 0, st, a);
+        return hipGetLastError();
+    }
+    if (variant == 8) {
+        // two games per lane, compacted at steps 5, 8, 11, 14
+        const uint32_t blocks = (a.total + 511u) / 512u;
+        hipLaunchKernelGGL(rollout_compact2, dim3(blocks), dim3(256), 0, st, a);
         return hipGetLastError();
     }
     if (variant == 5) {

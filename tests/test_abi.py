@@ -57,8 +57,8 @@ def test_argument_errors_without_device(lib):
     assert lib.dvc_rollout_ex(None, 0, 0, 0, 0, 0, None, None, None, 0, 0, 0, 0, None) == -1
     # unknown flag
     assert lib.dvc_rollout_ex(vp(16), 1, 8, 0, 0, 0, None, None, None, 0, 0, 0, 2, None) == -1
-    # kernel variants 0-7 exist; 8 and negative ones do not
-    for bad in (8, -1):
+    # kernel variants 0-8 exist; 9 and negative ones do not
+    for bad in (9, -1):
         assert lib.dvc_rollout_ex(vp(16), 1, 8, 0, 0, 0, None, None, None, bad, 0, 0, 0,
                                   None) == -1
     # n * ppl must stay below 2^32

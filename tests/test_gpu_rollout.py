@@ -70,7 +70,7 @@ def _compare(dvc, states_np, ppl, seed, tree, base, ref, **kw):
     assert np.array_equal(sw.cpu().numpy().view(np.uint32), rs), "seat wins"
 
 
-@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6, 7, 8])
 @pytest.mark.parametrize("P", [2, 3, 4])
 def test_rollout_bit_exact_small(orc, dvc, variant, P):
     po = orc.deal_params(p_min=P, p_max=P, pile_min=0, pile_max=16, revealed_max=8, phase_mix=1)
@@ -92,7 +92,7 @@ def test_rollout_schedule_invariance(orc, dvc, variant, block, grid):
     _compare(dvc, S, ppl, 77, 3, 0, ref, variant=variant, block=block, grid=grid)
 
 
-@pytest.mark.parametrize("variant", [2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("variant", [2, 3, 4, 5, 6, 7, 8])
 @pytest.mark.parametrize("ppl", [1, 2, 63, 64, 65, 129, 1000])
 def test_rollout_ppl_edges(orc, dvc, variant, ppl):
     po = orc.deal_params(p_min=2, p_max=3, pile_min=0, pile_max=16, revealed_max=8)
@@ -176,7 +176,7 @@ def test_rollout_autotune(orc, dvc):
     assert dvc.dvc_check() == 0
 
 
-@pytest.mark.parametrize("variant,ppl", [(0, 24), (7, 64), (7, 256)])
+@pytest.mark.parametrize("variant,ppl", [(0, 24), (7, 64), (7, 256), (8, 64), (8, 512)])
 def test_rollout_accumulate(orc, dvc, variant, ppl):
     """Two calls with different seeds tally into one seat-win table (variant 7
     with whole leaves per workgroup, which stores its sums when overwriting,
@@ -194,7 +194,7 @@ def test_rollout_accumulate(orc, dvc, variant, ppl):
     assert np.array_equal(sw.cpu().numpy().view(np.uint32), r1 + r2)
 
 
-@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6, 7, 8])
 def test_rollout_decided_and_malformed_leaves(orc, dvc, variant):
     import positions as POS
     rng = np.random.default_rng(9)
@@ -245,7 +245,7 @@ def test_rollout_full_leaf_parallel_workload(orc, dvc):
     st = dvc.dvc_init_states(4096, pd, seed=2)
     assert np.array_equal(to_np(st), S)
     ref = _rollout_ref(orc, S, 256, 2, 0, 0)
-    for variant, grid in [(1, 0), (2, 0), (3, 0), (4, 0), (5, 0), (6, 0), (7, 0), (7, 2)]:
+    for variant, grid in [(1, 0), (2, 0), (3, 0), (4, 0), (5, 0), (6, 0), (7, 0), (7, 2), (8, 0)]:
         w, ln, sw = dvc.dvc_rollout(st, 256, 2, 0, 0, variant=variant, grid=grid)
         torch.cuda.synchronize()
         assert np.array_equal(w.cpu().numpy(), ref[0])
@@ -271,7 +271,7 @@ def test_valu_probe(dvc):
         measure.probe_valu(6, 2, 3, sink)
 
 
-@pytest.mark.parametrize("variant", [4, 6, 7])
+@pytest.mark.parametrize("variant", [4, 6, 7, 8])
 @pytest.mark.parametrize("ppl", [1, 3, 64, 100, 256, 300])
 def test_rollout_seat_wins_overwrite_the_table(orc, dvc, variant, ppl):
     """Without accumulate the seat-win table is overwritten (zeroed, then
