@@ -56,9 +56,9 @@ OPS_PER_GUESS = 222
 # scaled by what the same counter reads for a plain 256 MiB device copy
 # (FETCH_SIZE reads half the bytes moved, WRITE_SIZE all of them).  Valid
 # only for the kernel sources it was taken on: reported as null otherwise.
-PROFILED_TRAFFIC = {"fetch_kib": 389.0, "fetch_scale": 2.0, "write_kib": 3200.0,
+PROFILED_TRAFFIC = {"fetch_kib": 385.0, "fetch_scale": 2.0, "write_kib": 3200.0,
                     "write_scale": 1.0,
-                    "sources_sha256": "ab762a0174c43cc1ef2b14952f8151b628146513bf447dddd050e235e023d2fb"}
+                    "sources_sha256": "1ef06c6e657b94f29901b98acbfd9f4b322126ad2fb7d20a4b4189dad4abb21a"}
 KERNEL_SOURCES = ["paper_2403_10720_amd/csrc/dvc_core.hpp",
                   "paper_2403_10720_amd/csrc/dvc_internal.hpp",
                   "paper_2403_10720_amd/csrc/rollout.hip"]
