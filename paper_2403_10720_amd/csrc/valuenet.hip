@@ -230,6 +230,7 @@ struct VnRowsArgs {
     const float *labels;
     uint32_t n_rows;          // rows in this launch
     uint32_t n_data, perm_a, perm_b, row_base;   // training: row i is data[(a*(base+i)+b) % n_data]
+    uint32_t n_mask;                             // n_data - 1 when n_data is a power of two, else 0
     float *v_out;             // inference output (or null)
     // training outputs (bf16, in the fragment layout of vn_act_idx)
     uint16_t *xt, *h1t, *dh1t, *dh2t;
@@ -459,7 +460,8 @@ constexpr uint32_t kVnMaxSlices = 8u;   // batch slices of the weight-gradient p
 // data row of batch row `row` of a training step
 __device__ __forceinline__ uint32_t vn_train_row(const VnRowsArgs &a, uint32_t row)
 {
-    return (uint32_t)(((uint64_t)a.perm_a * (a.row_base + row) + a.perm_b) % a.n_data);
+    const uint64_t x = (uint64_t)a.perm_a * (a.row_base + row) + a.perm_b;
+    return a.n_mask ? (uint32_t)x & a.n_mask : (uint32_t)(x % a.n_data);
 }
 
 // Training rows (forward, loss, data gradients, bias-gradient partials), MT
@@ -478,6 +480,18 @@ __device__ __forceinline__ uint32_t vn_train_row(const VnRowsArgs &a, uint32_t r
 // each XCD writes one contiguous eighth of the batch: the slice of the batch
 // the weight-gradient kernel later reads on that XCD.  One column of
 // partials per workgroup.
+// Workgroup barrier that orders LDS accesses only: the global loads and
+// stores in flight are not waited for.  The rows kernel's wavefronts share
+// data only through LDS (the activations it stores are read by the next
+// launch), so its weight prefetches and activation stores run on across
+// its barriers.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 template <uint32_t MT>
 __global__ void __launch_bounds__(256 * MT) vn_rows_kernel(VnRowsArgs a)
 {
@@ -507,22 +521,34 @@ __global__ void __launch_bounds__(256 * MT) vn_rows_kernel(VnRowsArgs a)
     const float b3 = P.master[kOffB3];
     // lane r holds row 16m + r of tile m; the labels of rows 16m + 4g + i
     // come from lane 4g + i
+    // (every tile's state, perspective and labels are requested before any
+    // of them is waited for; data row 0 stands in for rows past the batch)
     bool has[MT];
     RowFeat rf[MT];
     float yv[MT][4];
+    uint32_t src[MT];
+    uint4 st[MT];
+    uint32_t pq[MT];
 #pragma unroll
     for (uint32_t m = 0; m < MT; ++m) {
         const uint32_t myrow = row0 + 16u * m + r;
         has[m] = myrow < a.n_rows;
-        const uint32_t src = has[m] ? vn_train_row(a, myrow) : 0u;
+        src[m] = has[m] ? vn_train_row(a, myrow) : 0u;
+        st[m] = a.states[src[m]];
+        pq[m] = a.persp[src[m]];
+    }
+#pragma unroll
+    for (uint32_t m = 0; m < MT; ++m)
 #pragma unroll
         for (uint32_t i = 0; i < 4u; ++i) {
             const uint32_t row = row0 + 16u * m + 4u * g + i;
-            const uint32_t sr = (uint32_t)__shfl((int)src, (int)(4u * g + i), 64);
+            const uint32_t sr = (uint32_t)__shfl((int)src[m], (int)(4u * g + i), 64);
             yv[m][i] = row < a.n_rows ? a.labels[sr] : 0.0f;
         }
+#pragma unroll
+    for (uint32_t m = 0; m < MT; ++m) {
         if (has[m]) {
-            rf[m] = row_features(a.states[src], a.persp[src]);
+            rf[m] = row_features(st[m], pq[m]);
         } else {
             rf[m].ok = false;
         }
@@ -596,7 +622,7 @@ __global__ void __launch_bounds__(256 * MT) vn_rows_kernel(VnRowsArgs a)
             }
         }
     }
-    __syncthreads();
+    lds_barrier();
 
     // ---- layer 2: h2 = bf16(relu(W2 h1 + b2)), z = w3 . h2 + b3 ------------
     floatx4 acc2[MT][JJ];
@@ -642,7 +668,7 @@ __global__ void __launch_bounds__(256 * MT) vn_rows_kernel(VnRowsArgs a)
             for (uint32_t i = 0; i < 4u; ++i) zred[wv][16u * m + 4u * g + i] = zpart[i];
         }
     }
-    __syncthreads();   // zred complete; every wavefront has read h1 from hs
+    lds_barrier();   // zred complete; every wavefront has read h1 from hs
     float dz[MT][4], err2 = 0.0f, dsum = 0.0f;
 #pragma unroll
     for (uint32_t m = 0; m < MT; ++m) {
@@ -712,7 +738,7 @@ __global__ void __launch_bounds__(256 * MT) vn_rows_kernel(VnRowsArgs a)
             part[(2u + 256u + col) * pst] = db2;
         }
     }
-    __syncthreads();   // dh2 tiles complete
+    lds_barrier();   // dh2 tiles complete
 
     // ---- dh1 = (dh2 W2) * (h1 > 0), columns of this wavefront ----------------
     float db1[JJ];
@@ -1030,6 +1056,7 @@ hipError_t launch_vn_train_step(void *net, const uint4 *states, const uint8_t *p
     a.labels = labels;
     a.n_rows = batch;
     a.n_data = n_data;
+    a.n_mask = (n_data & (n_data - 1u)) == 0u ? n_data - 1u : 0u;
     a.perm_a = perm_a;
     a.perm_b = perm_b;
     a.row_base = row_base;
