@@ -27,6 +27,13 @@
  * yet); then the pass's leaves are evaluated and each path gets its wins, in
  * iteration order.  B = 1 is the plain sequential search.
  *
+ * Pipelined passes (pipeline = 1): the wins of pass k are backed up only
+ * after the descents of pass k + 1 (in iteration order, before that pass's
+ * leaves are evaluated), and the last pass's after the loop; a descent of
+ * pass k thus sees the visits of every earlier descent but the wins of passes
+ * up to k - 2.  This is the order in which one worker can descend pass k + 1
+ * while another evaluates pass k.
+ *
  * Selection uses UCT (Kocsis & Szepesvari 2006) evaluated in single precision
  * with one IEEE rounding per operation, in this order:
  *     n = float(N_c); q = W_c / n; e = LN[N_parent] / n; u = c * sqrt(e);
@@ -536,6 +543,10 @@ static int search_one(const orc_rows *root, const orc_mcts_params *mp, uint64_t 
     int path[ORC_MAX_PASS][128], np[ORC_MAX_PASS], terminal[ORC_MAX_PASS], winner[ORC_MAX_PASS];
     orc_rows leafS[ORC_MAX_PASS];
     uint8_t legal[ORC_MAX_CHILD];
+    /* pipelined passes: the previous pass's paths and leaf values, not yet
+       backed up */
+    int pend_path[ORC_MAX_PASS][128], pend_np[ORC_MAX_PASS], pend_n = 0;
+    float pend_vals[ORC_MAX_PASS][4];
     for (int i0 = 0; i0 < mp->iterations; i0 += B) {
         int nb = mp->iterations - i0 < B ? mp->iterations - i0 : B;
         for (int b = 0; b < nb; ++b) {
@@ -613,6 +624,14 @@ static int search_one(const orc_rows *root, const orc_mcts_params *mp, uint64_t 
             /* the visit counts go in at once */
             for (int k = 0; k < np[b]; ++k) T.v[pth[k]].N += (uint32_t)ppl;
         }
+        /* pipelined: the previous pass's wins go in now, after this pass's
+           descents */
+        for (int b = 0; b < pend_n; ++b)
+            for (int k = 1; k < pend_np[b]; ++k) {
+                onode *x = &T.v[pend_path[b][k]];
+                if (x->chooser >= 0) x->W += pend_vals[b][x->chooser];
+            }
+        pend_n = 0;
         for (int b = 0; b < nb; ++b) {
             int i = i0 + b;
             float vals[4] = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -625,12 +644,24 @@ static int search_one(const orc_rows *root, const orc_mcts_params *mp, uint64_t 
                 rollout_rows_wins(&leafS[b], ppl, seed, (uint32_t)i, tr, wins);
                 for (int k = 0; k < 4; ++k) vals[k] = (float)wins[k];
             }
+            if (mp->pipeline) {
+                for (int k = 0; k < np[b]; ++k) pend_path[b][k] = path[b][k];
+                pend_np[b] = np[b];
+                for (int k = 0; k < 4; ++k) pend_vals[b][k] = vals[k];
+                pend_n = b + 1;
+                continue;
+            }
             for (int k = 1; k < np[b]; ++k) {
                 onode *x = &T.v[path[b][k]];
                 if (x->chooser >= 0) x->W += vals[x->chooser];
             }
         }
     }
+    for (int b = 0; b < pend_n; ++b)   /* the last pipelined pass */
+        for (int k = 1; k < pend_np[b]; ++k) {
+            onode *x = &T.v[pend_path[b][k]];
+            if (x->chooser >= 0) x->W += pend_vals[b][x->chooser];
+        }
     onode *R = &T.v[0];
     if (mp->vanilla) {
         /* a guess is judged over all worlds: its statistics are summed over
@@ -704,7 +735,8 @@ int oracle_mcts_search(const orc_packed *roots, int64_t n_trees, const orc_mcts_
         mp->max_depth > 64 || mp->leaf_eval < 0 || mp->leaf_eval > 1 ||
         (mp->continue_choice != 0 && mp->continue_choice != 1) ||
         (mp->vanilla != 0 && mp->vanilla != 1) || mp->leaves_per_pass < 1 ||
-        mp->leaves_per_pass > ORC_MAX_PASS)
+        mp->leaves_per_pass > ORC_MAX_PASS || (mp->pipeline != 0 && mp->pipeline != 1) ||
+        (mp->pipeline && mp->vanilla))
         return -1;
     if (mp->leaf_eval && (mp->valuenet == NULL || mp->fallback_playouts < 1)) return -1;
     for (int64_t t = 0; t < n_trees; ++t) {

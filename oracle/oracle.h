@@ -62,6 +62,7 @@ typedef struct {
     int32_t continue_choice; /* 1: after a right guess the mover may stop or guess again */
     int32_t vanilla;         /* 1: the root's children are the sampled worlds            */
     int32_t leaves_per_pass; /* B >= 1 descents before their leaves are evaluated        */
+    int32_t pipeline;        /* 1: a pass's wins are backed up after the next pass's descents */
 } orc_mcts_params;
 
 typedef struct { uint16_t action; uint16_t pad; uint32_t n; float w; } orc_child_stat;

@@ -19,6 +19,11 @@ fixes is the search itself (Sec. II-B, Sec. III-A):
 * every node on the path gains the leaf's weight in N; every node below the
   root gains in W the value of the seat that chose its guess -- the player to
   move at its parent, not the searching player.
+
+Passes (``leaves_per_pass`` B): B descents, each adding its N at once, then
+the B leaves' values in iteration order.  Pipelined passes (``pipeline``):
+a pass's values go in only after the next pass's descents, the last pass's
+at the end.
 """
 from __future__ import annotations
 
@@ -31,7 +36,7 @@ import rules_ref as R
 
 
 def search(orc, root, iters, ppl, max_depth, seed, tree, c_uct=None, value=None, band=0.05,
-           fallback_playouts=64):
+           fallback_playouts=64, leaves_per_pass=1, pipeline=0):
     """Returns the tree as a list of nodes {parent, key, chooser, n, w} in
     creation order (node 0 is the root) and the decision.  value: None for
     playout leaves, else a function (position dict, seat) -> value."""
@@ -40,6 +45,13 @@ def search(orc, root, iters, ppl, max_depth, seed, tree, c_uct=None, value=None,
     key = [seed & 0xFFFFFFFF, seed >> 32]
     nodes = [{"parent": -1, "key": -1, "chooser": -1, "n": 0, "w": np.float32(0), "kids": []}]
     M = POS.unpack(root)["mover"]
+
+    def credit(path, vals):
+        for k in path[1:]:
+            nodes[k]["w"] = np.float32(nodes[k]["w"] + vals[nodes[k]["chooser"]])
+
+    pending = []          # (path, values) of a pipelined pass not yet credited
+    passed = []           # this pass's (iteration, path, position, over, winner)
     for i in range(iters):
         world, _ = orc.determinize(root, seed, tree, i)
         pos = POS.unpack(world)
@@ -73,24 +85,37 @@ def search(orc, root, iters, ppl, max_depth, seed, tree, c_uct=None, value=None,
             depth += 1
         for k in path:
             nodes[k]["n"] += weight
-        vals = [np.float32(0)] * 4
-        if over:
-            vals[winner] = np.float32(weight)
-        else:
-            playout = value is None
-            if value is not None:
-                v = [np.float32(value(pos, q)) for q in range(pos["P"])]
-                if abs(v[M] - np.float32(0.5)) < np.float32(band):
-                    playout = True
-                else:
-                    vals = [np.float32(weight) * v[q] for q in range(pos["P"])] + \
-                           [np.float32(0)] * (4 - pos["P"])
-            if playout:
-                _, _, wins = orc.rollout(POS.pack(pos), weight, seed, tree_id=tree, leaf_id_base=i,
-                                         want_winner=False, want_length=False)
-                vals = [np.float32(w) for w in wins[0]]
-        for k in path[1:]:
-            nodes[k]["w"] = np.float32(nodes[k]["w"] + vals[nodes[k]["chooser"]])
+        passed.append((i, path, pos, over, winner))
+        if len(passed) < leaves_per_pass and i + 1 < iters:
+            continue
+        # the pass is complete: a pipelined search credits the previous pass now
+        for pth, vals in pending:
+            credit(pth, vals)
+        pending = []
+        for it, pth, lpos, lover, lwin in passed:
+            vals = [np.float32(0)] * 4
+            if lover:
+                vals[lwin] = np.float32(weight)
+            else:
+                playout = value is None
+                if value is not None:
+                    v = [np.float32(value(lpos, q)) for q in range(lpos["P"])]
+                    if abs(v[M] - np.float32(0.5)) < np.float32(band):
+                        playout = True
+                    else:
+                        vals = [np.float32(weight) * v[q] for q in range(lpos["P"])] + \
+                               [np.float32(0)] * (4 - lpos["P"])
+                if playout:
+                    _, _, wins = orc.rollout(POS.pack(lpos), weight, seed, tree_id=tree,
+                                             leaf_id_base=it, want_winner=False, want_length=False)
+                    vals = [np.float32(w) for w in wins[0]]
+            if pipeline:
+                pending.append((pth, vals))
+            else:
+                credit(pth, vals)
+        passed = []
+    for pth, vals in pending:
+        credit(pth, vals)
     root_kids = nodes[0]["kids"]
     best = max(root_kids, key=lambda k: (nodes[k]["n"], -root_kids.index(k)))
     return nodes, nodes[best]["key"]

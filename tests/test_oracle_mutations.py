@@ -39,6 +39,9 @@ MUTATIONS = {
                               "vals[k] = (float)mp->fallback_playouts * (float)v[k];",
                               "vals[k] = (float)mp->fallback_playouts * (float)v[root_mover];",
                               PINS.check_value_trees),
+    # a pipelined pass credited at once instead of after the next pass's descents
+    "pipeline_credited_at_once": ("mcts.c", "if (mp->pipeline) {", "if (0) {",
+                                  PINS.check_pass_trees),
     # the fallback decided on the leaf's player to move instead of the searching player
     "fallback_on_leaf_mover": ("mcts.c", "float vm = (float)v[root_mover];",
                                "float vm = (float)v[S->mover];",

@@ -140,6 +140,44 @@ def check_value_trees(orc):
         _compare_tree(orc, root, mp, seed, t, nodes, best)
 
 
+def check_pass_trees(orc):
+    """Passes of B leaves, pipelined (a pass's wins credited after the next
+    pass's descents), playout and value leaves, against the loop of
+    ``search_ref`` with the same pass rule; on these roots the pipelined trees
+    differ from the plain passes' trees, so crediting a pass at once fails."""
+    p = exact_net.params()
+    dp = orc.deal_params(p_min=2, p_max=3, hand=(0, 0, 4, 4, 3), pile_min=0, pile_max=6,
+                         revealed_max=5, root_draw=1)
+    roots = orc.init_states(6, dp, seed=311)
+    differ = 0
+    for t, root in enumerate(roots):
+        B = (1, 2, 4)[t % 3]
+        if t >= 3:   # value leaves with the integer network
+            band = 0.05 if t % 2 else 0.0
+            kw = dict(value=exact_net.closed_form, band=band, fallback_playouts=64)
+            mk = lambda pipe: orc.mcts_params(iterations=300, playouts_per_leaf=1, max_depth=3,
+                                              leaf_eval=1, fallback_band=band,
+                                              fallback_playouts=64, valuenet=p,
+                                              leaves_per_pass=B, pipeline=pipe)
+            iters, ppl = 300, 1
+        else:
+            kw = {}
+            mk = lambda pipe: orc.mcts_params(iterations=400, playouts_per_leaf=4, max_depth=3,
+                                              leaves_per_pass=B, pipeline=pipe)
+            iters, ppl = 400, 4
+        nodes, best = search_ref.search(orc, root, iters, ppl, 3, 29, t, leaves_per_pass=B,
+                                        pipeline=1, **kw)
+        _compare_tree(orc, root, mk(1), 29, t, nodes, best)
+        plain, _ = search_ref.search(orc, root, iters, ppl, 3, 29, t, leaves_per_pass=B, **kw)
+        differ += [(n["key"], n["n"], n["w"]) for n in plain] != \
+            [(n["key"], n["n"], n["w"]) for n in nodes]
+    assert differ >= 4, differ
+
+
+def test_pipelined_and_batched_passes(orc):
+    check_pass_trees(orc)
+
+
 def test_candidate_guesses(orc):
     check_candidates(orc)
 
