@@ -12,8 +12,10 @@ Prints one JSON line.  `value` is playouts/s of the whole step; `roofline`
 prices the dominant kernel (the rollout kernel, one playout per lane at this
 size) against the integer-VALU issue peak of the chip; `cpu_baseline` is the
 CPU oracle timed on this host's cores on a bounded sample of the same
-workload.  Side figures: batched search, root-parallel search and a single
-tree, timed with HIP events; `value_vs_rollout`: value-network training on
+workload.  Side figures: batched search (as configured, with two leaves per
+pass, and with the shape the library's search autotuner picks under its
+agreement guard), root-parallel search and a single tree, timed with HIP
+events; `value_vs_rollout`: value-network training on
 pairs the rollout kernel labels (step time, TFLOP/s) and the value-network
 search against the pure-playout search on 1024 fresh deals x 4096 iterations
 (decisions/s of both, GPU-seconds ratio, root-move agreement).
@@ -129,6 +131,38 @@ def batched_search(D, torch, reps=3, leaves_per_pass=1):
                                                if leaves_per_pass > 1 else ""),
             "ms_per_launch": best,
             "decisions_per_s": n / (best / 1e3), "playouts_per_s": n * iters * ppl / (best / 1e3)}
+
+
+def autotuned_search(D, torch, reps=3, tolerance=0.02):
+    """The batched search with the shape the library's search autotuner picks
+    for it: dvc_mcts_autotune times every (playouts per leaf, leaves per pass)
+    candidate on these roots and admits those whose decisions agree with the
+    sequential 32-playout search at least as often as a second seed of that
+    search does, less `tolerance`; the fastest admitted shape then runs as the
+    automatic shape (playouts per leaf and leaves per pass both 0)."""
+    n, iters, ppl = 2048, 1024, 32
+    roots = D.dvc_init_states(n, D.deal_params(**SEARCH_DEAL), 3)
+    ref = D.mcts_params(iterations=iters, playouts_per_leaf=ppl, max_depth=4)
+    auto = D.mcts_params(iterations=iters, playouts_per_leaf=0, max_depth=4, leaves_per_pass=0)
+    ws = torch.empty(max(D.dvc_mcts_workspace_bytes(n, ref), D.dvc_mcts_workspace_bytes(n, auto)),
+                     dtype=torch.uint8, device=roots.device)
+    choice, _ = D.dvc_mcts_autotune(roots, ref, 3, workspace=ws, tolerance=tolerance)
+    D.mcts_search(roots, auto, 3, workspace=ws, want_children=False)
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        D.mcts_search(roots, auto, 3, workspace=ws, want_children=False)
+        e1.record()
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    best = min(ms)
+    return {"workload": "2048 trees (2-4 players, mid-game, root draw) x 1024 iterations, depth 4, "
+                        "autotuned playouts per leaf x leaves per pass (agreement guard: within "
+                        f"{tolerance} of the 32-playout search's seed-to-seed agreement)",
+            "choice": choice, "ms_per_launch": best, "decisions_per_s": n / (best / 1e3),
+            "playouts_per_s": n * iters * choice["playouts_per_leaf"] / (best / 1e3)}
 
 
 def root_parallel_search(D, torch, reps=3):
@@ -402,6 +436,7 @@ def main():
     if not args.no_search:
         out["batched_search"] = batched_search(D, torch)
         out["batched_search_leaf_batched"] = batched_search(D, torch, leaves_per_pass=2)
+        out["batched_search_autotuned"] = autotuned_search(D, torch)
         out["root_parallel_search"] = root_parallel_search(D, torch)
         out["single_tree_search"] = single_tree_search(D, torch)
         out["single_tree_search_leaf_batched"] = single_tree_search(D, torch, leaves_per_pass=4)
