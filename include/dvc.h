@@ -224,6 +224,13 @@ int dvc_rollout_autotune(const dvc_state_t *leaves, int64_t n_leaves, int32_t pl
  * its iteration index for its world, chance words and playouts.  B = 1 is
  * the sequential search above.
  *
+ * Pipelined passes (pipeline = 1): the wins of pass k are credited after the
+ * descents of pass k + 1 (before its leaves are evaluated), the last pass's
+ * at the end, so a descent of pass k sees the wins of passes up to k - 2.
+ * Each tree then runs as two wavefronts, one descending pass k + 1 while the
+ * other evaluates pass k (Sec. III-B: simulations of several workers side by
+ * side).  With B = 1 too.  Not with vanilla.
+ *
  * The paper's three simplifications (Sec. III-A) can each be switched off:
  *   max_depth 0 -- no depth threshold: nodes expand until the game ends;
  *   continue_choice 1 -- a right guess no longer ends the turn: the same
@@ -257,6 +264,7 @@ typedef struct {
     int32_t vanilla;            /* 1: sampled worlds are the root's children        */
     int32_t leaves_per_pass;    /* B: leaves evaluated together, 1..16 (value mode
                                    1..4); 1 = the sequential search              */
+    int32_t pipeline;           /* 1: pipelined passes (see above); not with vanilla */
 } dvc_mcts_params;
 /* Automatic shape: with playout leaves, playouts_per_leaf = 0 together with
  * leaves_per_pass = 0 asks for the shape dvc_mcts_autotune chose for this

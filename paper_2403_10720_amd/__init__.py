@@ -42,7 +42,7 @@ class MctsParams(C.Structure):
                 ("max_depth", C.c_int32), ("c_uct", C.c_float), ("leaf_eval", C.c_int32),
                 ("fallback_band", C.c_float), ("fallback_playouts", C.c_int32),
                 ("valuenet", C.c_void_p), ("continue_choice", C.c_int32), ("vanilla", C.c_int32),
-                ("leaves_per_pass", C.c_int32)]
+                ("leaves_per_pass", C.c_int32), ("pipeline", C.c_int32)]
 
 
 class MctsTuning(C.Structure):
@@ -64,13 +64,16 @@ def deal_params(p_min=2, p_max=2, hand=(0, 0, 4, 4, 3), pile_min=0, pile_max=16,
 
 def mcts_params(iterations=2000, playouts_per_leaf=16, max_depth=4, c_uct=None, leaf_eval=0,
                 fallback_band=0.05, fallback_playouts=64, valuenet=None, continue_choice=0,
-                vanilla=0, leaves_per_pass=1) -> MctsParams:
+                vanilla=0, leaves_per_pass=1, pipeline=0) -> MctsParams:
     """max_depth 0: no depth threshold; continue_choice 1: a right guess is
     followed by the same player's stop-or-guess choice; vanilla 1: sampled
     worlds are the root's children (root children come back by action id);
-    leaves_per_pass B: B descents per pass, their leaves evaluated together."""
+    leaves_per_pass B: B descents per pass, their leaves evaluated together;
+    pipeline 1: a pass's wins are credited after the next pass's descents
+    (one wavefront descends while another evaluates)."""
     m = MctsParams()
     m.continue_choice, m.vanilla, m.leaves_per_pass = continue_choice, vanilla, leaves_per_pass
+    m.pipeline = pipeline
     m.iterations, m.playouts_per_leaf, m.max_depth = iterations, playouts_per_leaf, max_depth
     m.c_uct = float.fromhex("0x1.6a09e6p+0") if c_uct is None else c_uct  # sqrt(2) in float
     m.leaf_eval, m.fallback_band, m.fallback_playouts = leaf_eval, fallback_band, fallback_playouts

@@ -134,6 +134,8 @@ static bool mcts_params_ok(const dvc_mcts_params *p)
         return false;
     if ((p->continue_choice != 0 && p->continue_choice != 1) || (p->vanilla != 0 && p->vanilla != 1))
         return false;
+    // pipelined passes keep no world nodes
+    if ((p->pipeline != 0 && p->pipeline != 1) || (p->pipeline && p->vanilla)) return false;
     // leaves evaluated together: value mode fits four leaves' perspectives in
     // one matrix tile, playout mode packs up to 16 leaves' playouts
     if (!aut && (p->leaves_per_pass < 1 || p->leaves_per_pass > (p->leaf_eval ? 4 : 16)))
@@ -473,7 +475,8 @@ static int run_search(const dvc_state_t *roots, int64_t n_roots, int64_t trees_p
                                (uint32_t)params->leaf_eval, params->fallback_band,
                                (uint32_t)params->fallback_playouts, params->valuenet,
                                (uint32_t)params->continue_choice, (uint32_t)params->vanilla,
-                               (uint32_t)params->leaves_per_pass, (hipStream_t)stream);
+                               (uint32_t)params->leaves_per_pass, (uint32_t)params->pipeline,
+                               (hipStream_t)stream);
     if (e != hipSuccess || !merge) return status_of(e);
     return status_of(launch_mcts_merge(reinterpret_cast<const uint32_t *>(workspace),
                                        (uint32_t)n_roots, (uint32_t)trees_per_root,

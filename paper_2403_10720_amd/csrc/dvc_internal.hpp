@@ -61,7 +61,8 @@ hipError_t launch_mcts(const uint4 *roots, uint32_t n_trees, uint32_t trees_per_
                        uint32_t iters, uint32_t ppl, uint32_t dmax, float c_uct, uint32_t k0, uint32_t k1, uint32_t tree_base,
                        const float *ln, uint32_t *ws, int32_t *best, uint32_t *kids,
                        uint32_t leaf_eval, float band, uint32_t fb_ppl, const void *net,
-                       uint32_t cont, uint32_t vanilla, uint32_t lpp, hipStream_t st);
+                       uint32_t cont, uint32_t vanilla, uint32_t lpp, uint32_t pipe,
+                       hipStream_t st);
 hipError_t launch_mcts_merge(const uint32_t *ws, uint32_t n_roots, uint32_t trees_per_root,
                              uint32_t iters, uint32_t cont, int32_t *best, uint32_t *merged,
                              hipStream_t st);

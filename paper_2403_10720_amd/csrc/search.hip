@@ -437,6 +437,7 @@ struct MctsArgs {
     MctsShape sh;
     uint32_t cont_mode, vanilla;   // simplifications 2 and 1 switched off
     uint32_t lpp;                  // leaves per pass
+    uint32_t pipe;                 // pipelined passes: wins credited one pass late
     int32_t *best;    // [n_trees] or null
     uint32_t *kids;   // [n_trees][864][3] or null
     // value mode: leaves are scored by the network; a leaf whose value for
@@ -474,48 +475,65 @@ __device__ __forceinline__ void tree_sync()
 
 // Trees per workgroup: value mode stages the 256 x 256 second-layer weights
 // in LDS once per workgroup for its four trees; playout mode runs one tree per
-// workgroup.
-template <bool VALUE> struct TreeGroup {
-    static constexpr uint32_t kTrees = VALUE ? 4u : 1u;
+// workgroup.  Pipelined passes (PIPE): one tree per workgroup of two
+// wavefronts, one descending pass k + 1 while the other evaluates pass k,
+// with two pass buffers used in turn.
+template <bool VALUE, bool PIPE> struct TreeGroup {
+    static constexpr uint32_t kTrees = PIPE ? 1u : (VALUE ? 4u : 1u);
+    static constexpr uint32_t kWaves = PIPE ? 2u : kTrees;
     // leaves evaluated together: value mode puts their perspectives into the
     // 16 rows of one matrix tile, four per leaf
     static constexpr uint32_t kPass = VALUE ? 4u : 16u;
+    static constexpr uint32_t kBufs = PIPE ? 2u : 1u;
 };
 
 // VALUE: value mode (network leaves) -- one wavefront per SIMD, so that the
 // evaluation can keep many weight loads in flight; otherwise playout leaves
-// only.
-template <bool VALUE>
-__global__ void __launch_bounds__(64 * TreeGroup<VALUE>::kTrees)
-__attribute__((amdgpu_waves_per_eu(1, VALUE ? 1 : 8)))
+// only.  PIPE: pipelined passes, wavefront 0 of the workgroup samples,
+// descends and backs up, wavefront 1 evaluates.
+template <bool VALUE, bool PIPE>
+__global__ void __launch_bounds__((64 * TreeGroup<VALUE, PIPE>::kWaves))
+__attribute__((amdgpu_waves_per_eu(1, (VALUE && !PIPE) ? 1 : 8)))
 mcts_tree_kernel(MctsArgs a)
 {
-    constexpr uint32_t TG = TreeGroup<VALUE>::kTrees;
+    constexpr uint32_t TG = TreeGroup<VALUE, PIPE>::kTrees;
+    constexpr uint32_t NBUF = TreeGroup<VALUE, PIPE>::kBufs;
+    // a tree's wavefront orders its own memory accesses with wavefront
+    // barriers when it shares the workgroup with other wavefronts
+    constexpr bool WS = VALUE || PIPE;
     __shared__ uint8_t tab[kKthTableBytes];
     __shared__ uint32_t legal_all[TG][73];
-    constexpr uint32_t BM = TreeGroup<VALUE>::kPass;
-    __shared__ uint32_t path_all[TG][BM][kMaxPath];
-    __shared__ uint4 leaf_all[TG][BM];
-    __shared__ uint32_t np_all[TG][BM];
+    constexpr uint32_t BM = TreeGroup<VALUE, PIPE>::kPass;
+    __shared__ uint32_t path_all[TG][NBUF][BM][kMaxPath];
+    __shared__ uint4 leaf_all[TG][NBUF][BM];
+    __shared__ uint32_t np_all[TG][NBUF][BM];
+    __shared__ uint32_t meta_all[TG][NBUF][2];   // a pass's decided leaves, their winners
     __shared__ uint32_t wins_all[TG][4u * BM];
-    __shared__ float vals_all[TG][BM][4];
+    __shared__ float vals_all[TG][NBUF][BM][4];
     __shared__ DfsSlots dfs_all[TG];
-    __shared__ __attribute__((aligned(16))) uint16_t w2_lds[VALUE ? kVnH * kVnH : 8];
+    __shared__ __attribute__((aligned(16))) uint16_t w2_lds[(VALUE && !PIPE) ? kVnH * kVnH : 8];
+    __shared__ __attribute__((aligned(16))) uint16_t hs_pipe[(VALUE && PIPE) ? 16 : 1][kVnH + 8];
     __shared__ VnSmall vn_small[1];
+    // pipelined passes: [0] the step + 1 at which the descending wavefront
+    // gave up (0: it did not); [1..4] the evaluating wavefront's network /
+    // played-out leaves and evaluation cycles
+    __shared__ uint32_t pipe_x[8];
     fill_kth_table(tab);
     if (VALUE) {
         vn_stage_small(vn_ptrs(const_cast<void *>(a.net)), vn_small[0]);
         // second-layer weights (bf16) as A operands of the transposed product
-        vn_stage_w2t(vn_ptrs(const_cast<void *>(a.net)), w2_lds);
+        if (!PIPE) vn_stage_w2t(vn_ptrs(const_cast<void *>(a.net)), w2_lds);
     }
-    __syncthreads();   // the only workgroup barrier
+    if (threadIdx.x == 0) pipe_x[0] = 0u;
+    __syncthreads();   // the only workgroup barrier outside pipelined passes
     const uint32_t wv = TG == 1u ? 0u : __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // pipelined passes: 0 samples, descends and backs up, 1 evaluates
+    const uint32_t role = PIPE ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : 0u;
     const uint32_t t = blockIdx.x * TG + wv;
     if (t >= a.n_trees) return;
     const uint32_t lane = threadIdx.x & 63u;
     uint32_t *legal_s = legal_all[wv];
     DfsSlots &dfs_slots = dfs_all[wv];
-    float (*vals)[4] = vals_all[wv];
     const uint32_t tr = a.tree_base + t;
     uint32_t *W = a.ws + (uint64_t)t * a.sh.tree_words;
     const uint32_t nodes_cap = a.sh.nodes_cap, node_words = a.sh.node_words;
@@ -535,6 +553,7 @@ mcts_tree_kernel(MctsArgs a)
     const bool ok = decode(rs.x, rs.y, rs.z, rs.w, R);
     const uint32_t pool0 = ~(R.h0 | R.h1 | R.h2 | R.h3) & kAll;
     if (!ok || __popc(alive_mask(R)) < 2 || (R.phase == 0u && pool0 != 0u)) {
+        if (role != 0u) return;   // both wavefronts of a pipelined tree leave here
         if (lane == 0) {
             atomicOr(&g_error_word, kErrState);
             if (a.best) a.best[t] = -1;
@@ -543,8 +562,10 @@ mcts_tree_kernel(MctsArgs a)
         write_no_children(a, t, lane);
         return;
     }
-    for (uint32_t k = lane; k < node_words; k += 64u) W[rec_off(0u) + k] = 0u;
-    if (lane == 0) bnext[0] = kNoBlock;
+    if (role == 0u) {
+        for (uint32_t k = lane; k < node_words; k += 64u) W[rec_off(0u) + k] = 0u;
+        if (lane == 0) bnext[0] = kNoBlock;
+    }
     uint32_t n_nodes = 1u, n_ovf = 0u, n_root = 0u;
     uint32_t n_net = 0u, n_played = 0u, n_sampler_fallback = 0u, deepest = 0u;   // statistics
     bool failed = false, have_fallback = false;
@@ -557,7 +578,7 @@ mcts_tree_kernel(MctsArgs a)
     // successful attempt is the same one either way.
     uint32_t wpl0 = 0u, wpl1 = 0u, wpl2 = 0u;
     uint64_t wok = 0u;
-    tree_sync<VALUE>();
+    tree_sync<WS>();
 
     // Iterations run in passes of B = leaves_per_pass: each descent of a pass
     // adds its visit counts along its path at once (the next descent sees
@@ -566,12 +587,178 @@ mcts_tree_kernel(MctsArgs a)
     // into the rows of one matrix tile -- and each path gets its wins, in
     // iteration order.  B = 1 is the plain sequential search.
     const uint32_t nplay = VALUE ? a.fb_ppl : a.ppl;   // visits of every leaf
-    for (uint32_t i0 = 0; i0 < a.iters && !failed; i0 += a.lpp) {
-        const uint32_t nb = a.iters - i0 < a.lpp ? a.iters - i0 : a.lpp;
+    // ---- 3. evaluate a pass's leaves (pass buffer buf, iterations i0 ..
+    // i0 + nb - 1): playouts packed into the 64 lanes, or network rows; the
+    // decided leaves get their winner's share.  Results in vals_all[wv][buf].
+    auto eval_pass = [&](uint32_t buf, uint32_t i0, uint32_t nb, uint32_t term_mask,
+                     uint32_t winners) {
+        uint32_t play_mask = ((1u << nb) - 1u) & ~term_mask;   // leaves to play out
+        if (VALUE && play_mask) {
+            // rows 4b + q: leaf b, seat perspective q < P
+            const uint32_t r = lane & 15u, lb = r >> 2, q = r & 3u;
+            RowFeat rf = no_row();
+            if (lb < nb && ((play_mask >> lb) & 1u)) {
+                const uint4 ps = leaf_all[wv][buf][lb];
+                if (q < ((ps.x >> 26) & 3u) + 1u) rf = row_features(ps, q);
+            }
+            // the value of row 4b + k: lane 4b + k of vrow (transposed
+            // products), or v4[k] of lane group b (the wavefront's own tile)
+            float vrow = 0.0f, v4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+            if (PIPE)
+                vn_eval16_wave(vn_ptrs(const_cast<void *>(a.net)), rf, hs_pipe, vn_small[0], v4);
+            else
+                vrow = vn_eval_tree_t(vn_ptrs(const_cast<void *>(a.net)), rf, w2_lds, vn_small[0]);
+#pragma unroll
+            for (uint32_t b = 0; b < BM; ++b) {
+                if (!((play_mask >> b) & 1u)) continue;
+                float v[4];
+#pragma unroll
+                for (uint32_t k = 0; k < 4u; ++k)
+                    v[k] = __uint_as_float(__builtin_amdgcn_readlane(
+                        __float_as_uint(PIPE ? v4[k] : vrow), PIPE ? 16u * b : 4u * b + k));
+                const float vm = R.m == 0u ? v[0] : R.m == 1u ? v[1] : R.m == 2u ? v[2] : v[3];
+                const float dv = vm - 0.5f;
+                if (!((dv < 0.0f ? -dv : dv) < a.band)) {
+                    play_mask &= ~(1u << b);
+                    ++n_net;
+                    if (lane == 0)
+#pragma unroll
+                        for (uint32_t k = 0; k < 4u; ++k) vals_all[wv][buf][b][k] = (float)a.fb_ppl * v[k];
+                }
+            }
+        }
+        // playouts of the leaves in play_mask, packed: playout g of the pass
+        // is playout g % nplay of leaf g / nplay
+        if (play_mask) {
+            if (lane < 4u * BM) wins_all[wv][lane] = 0u;
+            tree_sync<WS>();
+            const uint32_t trk1 = tr ^ a.k1;
+            for (uint32_t pb = 0; pb < nb * nplay; pb += 64u) {
+                const uint32_t gp = pb + lane;
+                const uint32_t lb = gp / nplay;
+                const bool act = lb < nb && ((play_mask >> lb) & 1u);
+                const uint32_t b_lo = pb / nplay;
+                const uint32_t b_hi = (pb + 63u) / nplay < nb - 1u ? (pb + 63u) / nplay : nb - 1u;
+                if (!((play_mask >> b_lo) & ((2u << (b_hi - b_lo)) - 1u))) continue;
+                uint32_t w = 4u;
+                if (act) {
+                    const uint4 ps = leaf_all[wv][buf][lb];
+                    State s;
+                    decode(ps.x, ps.y, ps.z, ps.w, s);
+                    const uint32_t p = gp - lb * nplay;
+                    const uint64_t pl = (uint64_t)(i0 + lb) * kPhiloxM1;
+                    PlayoutKey pk;
+                    pk.a = (uint32_t)(pl >> 32) ^ p ^ a.k0;
+                    pk.b = (uint32_t)pl;
+                    pk.gm_lo = 0u;
+                    pk.gm_hi = 0u;
+                    bool over = false;
+                    uint32_t len = 0u;
+                    // the words of step g+1 do not depend on the game, so
+                    // they are computed while step g runs (one wavefront per
+                    // tree has no other wavefront to hide latencies behind)
+                    Words wd = step_words(pk, trk1, a.k0, a.k1);
+                    next_step(pk);
+                    while (!over) {
+                        const Words wn = step_words(pk, trk1, a.k0, a.k1);
+                        next_step(pk);
+                        over = guess_step(s, wd, w, tab);
+                        wd = wn;
+                        if (++len >= kMaxGuesses && !over) {
+                            atomicOr(&g_error_word, kErrLimit);
+                            over = true;
+                            w = 4u;
+                        }
+                    }
+                }
+                // seat wins of every leaf in this chunk
+                for (uint32_t b = b_lo; b <= b_hi; ++b) {
+                    const bool mine = act && lb == b;
+                    const uint32_t c0 = (uint32_t)__popcll(__ballot(mine && w == 0u));
+                    const uint32_t c1 = (uint32_t)__popcll(__ballot(mine && w == 1u));
+                    const uint32_t c2 = (uint32_t)__popcll(__ballot(mine && w == 2u));
+                    const uint32_t c3 = (uint32_t)__popcll(__ballot(mine && w == 3u));
+                    if (lane == 0) {
+                        wins_all[wv][4u * b + 0u] += c0;
+                        wins_all[wv][4u * b + 1u] += c1;
+                        wins_all[wv][4u * b + 2u] += c2;
+                        wins_all[wv][4u * b + 3u] += c3;
+                    }
+                }
+            }
+            tree_sync<WS>();
+            for (uint32_t b = 0; b < nb; ++b) {
+                if (!((play_mask >> b) & 1u)) continue;
+                if (a.leaf_eval) ++n_played;
+                if (lane == 0)
+#pragma unroll
+                    for (uint32_t k = 0; k < 4u; ++k) vals_all[wv][buf][b][k] = (float)wins_all[wv][4u * b + k];
+            }
+        }
+        for (uint32_t b = 0; b < nb; ++b) {
+            if (!((term_mask >> b) & 1u)) continue;
+            const uint32_t wn = (winners >> (2u * b)) & 3u;
+            if (lane == 0)
+#pragma unroll
+                for (uint32_t k = 0; k < 4u; ++k) vals_all[wv][buf][b][k] = k == wn ? (float)nplay : 0.0f;
+        }
+        tree_sync<WS>();
+
+    };
+    // ---- 4. back-propagation of a pass: each path gets its leaf's wins, in order
+    auto backprop_pass = [&](uint32_t buf, uint32_t nb) {
+        for (uint32_t b = 0; b < nb; ++b) {
+            const uint32_t npb = np_all[wv][buf][b];
+            if (lane < npb && !(a.vanilla && lane == 0u)) {   // a world node's W word holds its key
+                const uint32_t e = path_all[wv][buf][b][lane];
+                // the chooser's value by a computed index: a chain of selects
+                // over the four LDS entries was compiled into branches that
+                // left seat 3's lanes reading seat 2's entry
+                const uint4 en = *reinterpret_cast<const uint4 *>(W + e);
+                const uint32_t chooser = (en.x >> 16) & 3u;
+                const float wc = vals_all[wv][buf][b][chooser];
+                W[e + 2u] = __float_as_uint(__uint_as_float(en.z) + wc);
+            }
+            tree_sync<WS>();
+        }
+
+    };
+
+    // Pipelined passes, the evaluating wavefront: step k evaluates pass
+    // k - 1 while the other wavefront descends pass k; both then meet at the
+    // step's workgroup barrier.  The two run the same number of steps (or
+    // both stop at the step where the descending wavefront gave up).
+    const uint32_t n_pass = (a.iters + a.lpp - 1u) / a.lpp;
+    if (PIPE && role == 1u) {
+        for (uint32_t k = 0; k <= n_pass; ++k) {
+            if (k >= 1u) {
+                const uint32_t ip = (k - 1u) * a.lpp, buf = (k - 1u) & 1u;
+                const uint64_t t2 = clock64();
+                eval_pass(buf, ip, a.iters - ip < a.lpp ? a.iters - ip : a.lpp,
+                          meta_all[wv][buf][0], meta_all[wv][buf][1]);
+                cyc[2] += clock64() - t2;
+            }
+            __syncthreads();
+            if (pipe_x[0] == k + 1u) break;
+        }
+        if (lane == 0) {
+            pipe_x[1] = n_net;
+            pipe_x[2] = n_played;
+            pipe_x[3] = (uint32_t)cyc[2];
+            pipe_x[4] = (uint32_t)(cyc[2] >> 32);
+        }
+        __syncthreads();
+        return;
+    }
+    for (uint32_t k = 0; k < n_pass + (PIPE ? 1u : 0u); ++k) {
+        const uint32_t buf = PIPE ? (k & 1u) : 0u;
+        const uint32_t i0 = k * a.lpp;
+        // pipelined passes end with a step that only backs up the last pass
+        const uint32_t nb = k < n_pass ? (a.iters - i0 < a.lpp ? a.iters - i0 : a.lpp) : 0u;
         uint32_t term_mask = 0u, winners = 0u;   // per leaf of the pass: decided, winner (2 bits)
         for (uint32_t b = 0; b < nb; ++b) {
             const uint32_t it = i0 + b;
-            uint32_t *path_e = path_all[wv][b];
+            uint32_t *path_e = path_all[wv][buf][b];
             const uint64_t t0 = clock64();
             // ---- 1. sample a world: the lowest successful attempt ------------
             if ((it & 63u) == 0u) {
@@ -683,7 +870,7 @@ mcts_tree_kernel(MctsArgs a)
                     node_n = 0u;
                 }
                 path_e[np++] = found_e;
-                tree_sync<VALUE>();
+                tree_sync<WS>();
             }
             for (;;) {
                 if (term || depth >= a.dmax || np >= kMaxPath - 1u) break;
@@ -706,7 +893,7 @@ mcts_tree_kernel(MctsArgs a)
                 const uint32_t cb1 = lane == 8u ? (cbw1 & 1u) : (cbw1 >> ((lane & 1u) * 16u)) & 0xFFFu;
                 const uint32_t u0 = l0 & ~cb0, u1 = l1 & ~cb1;
                 const uint64_t b0 = __ballot(u0 != 0u), b1 = __ballot(u1 != 0u);
-                tree_sync<VALUE>();
+                tree_sync<WS>();
                 // uniform values every lane loaded, read once after the loads
                 // have landed, so that the loops over blocks stay scalar
                 const uint32_t nchild = __builtin_amdgcn_readfirstlane(nchild_v);
@@ -747,7 +934,7 @@ mcts_tree_kernel(MctsArgs a)
                     last_block = depth;
                     term = apply_action(S, key, a.cont_mode != 0u, chance_at(cw, depth), winner,
                                         cont, tab);
-                    tree_sync<VALUE>();
+                    tree_sync<WS>();
                     break;
                 }
                 // selection: UCT over the playable children, 64 per pass
@@ -807,12 +994,12 @@ mcts_tree_kernel(MctsArgs a)
                 term = apply_action(S, best_act, a.cont_mode != 0u, chance_at(cw, depth), winner,
                                     cont, tab);
                 ++depth;
-                tree_sync<VALUE>();
+                tree_sync<WS>();
             }
             if (!term && cont) leaf_continue_coin(S, chance_at(cw, last_block), tab);
             deepest = np - a.vanilla > deepest ? np - a.vanilla : deepest;
             cyc[1] += clock64() - t1;
-            if (a.lpp == 1u) {
+            if (!PIPE && a.lpp == 1u) {
                 // the sequential search: the leaf is evaluated and backed up
                 // before the next descent
                 const uint64_t t2 = clock64();
@@ -909,7 +1096,7 @@ mcts_tree_kernel(MctsArgs a)
                         W[e + 2u] = __float_as_uint(__uint_as_float(en.z) + wc);
                     }
                 }
-                tree_sync<VALUE>();
+                tree_sync<WS>();
                 cyc[3] += clock64() - t3;
                 continue;
             }
@@ -917,145 +1104,50 @@ mcts_tree_kernel(MctsArgs a)
             if (lane == 0) {
                 uint4 ps;
                 encode(S, ps.x, ps.y, ps.z, ps.w);
-                leaf_all[wv][b] = ps;
-                np_all[wv][b] = np;
+                leaf_all[wv][buf][b] = ps;
+                np_all[wv][buf][b] = np;
             }
             term_mask |= term ? 1u << b : 0u;
             winners |= (term ? winner : 0u) << (2u * b);
             // visit counts at once
             n_root += nplay;
             if (lane < np) W[path_e[lane] + 1u] += nplay;
-            tree_sync<VALUE>();
+            tree_sync<WS>();
+        }
+        if (PIPE) {
+            // pass k descended, pass k - 1 evaluated: back up pass k - 1.  A
+            // search that gave up still meets the step's barrier, and tells
+            // the other wavefront which step it stopped at (it may read the
+            // word only after this wavefront has gone on to the next step)
+            if (lane == 0) {
+                meta_all[wv][buf][0] = term_mask;
+                meta_all[wv][buf][1] = winners;
+                if (failed) pipe_x[0] = k + 1u;
+            }
+            __syncthreads();
+            if (failed) break;
+            if (k >= 1u) {
+                const uint32_t ip = (k - 1u) * a.lpp;
+                const uint64_t t3 = clock64();
+                backprop_pass(buf ^ 1u, a.iters - ip < a.lpp ? a.iters - ip : a.lpp);
+                cyc[3] += clock64() - t3;
+            }
+            continue;
         }
         if (failed) break;
         if (a.lpp == 1u) continue;
-
         const uint64_t t2 = clock64();
-        // ---- 3. evaluate the pass's leaves: playouts, or the value network --
-        uint32_t play_mask = ((1u << nb) - 1u) & ~term_mask;   // leaves to play out
-        if (VALUE && play_mask) {
-            // rows 4b + q: leaf b, seat perspective q < P
-            const uint32_t r = lane & 15u, lb = r >> 2, q = r & 3u;
-            RowFeat rf = no_row();
-            if (lb < nb && ((play_mask >> lb) & 1u)) {
-                const uint4 ps = leaf_all[wv][lb];
-                if (q < ((ps.x >> 26) & 3u) + 1u) rf = row_features(ps, q);
-            }
-            const float vrow = vn_eval_tree_t(vn_ptrs(const_cast<void *>(a.net)), rf, w2_lds,
-                                              vn_small[0]);
-#pragma unroll
-            for (uint32_t b = 0; b < BM; ++b) {
-                if (!((play_mask >> b) & 1u)) continue;
-                float v[4];
-#pragma unroll
-                for (uint32_t k = 0; k < 4u; ++k)
-                    v[k] = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(vrow), 4u * b + k));
-                const float vm = R.m == 0u ? v[0] : R.m == 1u ? v[1] : R.m == 2u ? v[2] : v[3];
-                const float dv = vm - 0.5f;
-                if (!((dv < 0.0f ? -dv : dv) < a.band)) {
-                    play_mask &= ~(1u << b);
-                    ++n_net;
-                    if (lane == 0)
-#pragma unroll
-                        for (uint32_t k = 0; k < 4u; ++k) vals[b][k] = (float)a.fb_ppl * v[k];
-                }
-            }
-        }
-        // playouts of the leaves in play_mask, packed: playout g of the pass
-        // is playout g % nplay of leaf g / nplay
-        if (play_mask) {
-            if (lane < 4u * BM) wins_all[wv][lane] = 0u;
-            tree_sync<VALUE>();
-            const uint32_t trk1 = tr ^ a.k1;
-            for (uint32_t pb = 0; pb < nb * nplay; pb += 64u) {
-                const uint32_t gp = pb + lane;
-                const uint32_t lb = gp / nplay;
-                const bool act = lb < nb && ((play_mask >> lb) & 1u);
-                const uint32_t b_lo = pb / nplay;
-                const uint32_t b_hi = (pb + 63u) / nplay < nb - 1u ? (pb + 63u) / nplay : nb - 1u;
-                if (!((play_mask >> b_lo) & ((2u << (b_hi - b_lo)) - 1u))) continue;
-                uint32_t w = 4u;
-                if (act) {
-                    const uint4 ps = leaf_all[wv][lb];
-                    State s;
-                    decode(ps.x, ps.y, ps.z, ps.w, s);
-                    const uint32_t p = gp - lb * nplay;
-                    const uint64_t pl = (uint64_t)(i0 + lb) * kPhiloxM1;
-                    PlayoutKey pk;
-                    pk.a = (uint32_t)(pl >> 32) ^ p ^ a.k0;
-                    pk.b = (uint32_t)pl;
-                    pk.gm_lo = 0u;
-                    pk.gm_hi = 0u;
-                    bool over = false;
-                    uint32_t len = 0u;
-                    // the words of step g+1 do not depend on the game, so
-                    // they are computed while step g runs (one wavefront per
-                    // tree has no other wavefront to hide latencies behind)
-                    Words wd = step_words(pk, trk1, a.k0, a.k1);
-                    next_step(pk);
-                    while (!over) {
-                        const Words wn = step_words(pk, trk1, a.k0, a.k1);
-                        next_step(pk);
-                        over = guess_step(s, wd, w, tab);
-                        wd = wn;
-                        if (++len >= kMaxGuesses && !over) {
-                            atomicOr(&g_error_word, kErrLimit);
-                            over = true;
-                            w = 4u;
-                        }
-                    }
-                }
-                // seat wins of every leaf in this chunk
-                for (uint32_t b = b_lo; b <= b_hi; ++b) {
-                    const bool mine = act && lb == b;
-                    const uint32_t c0 = (uint32_t)__popcll(__ballot(mine && w == 0u));
-                    const uint32_t c1 = (uint32_t)__popcll(__ballot(mine && w == 1u));
-                    const uint32_t c2 = (uint32_t)__popcll(__ballot(mine && w == 2u));
-                    const uint32_t c3 = (uint32_t)__popcll(__ballot(mine && w == 3u));
-                    if (lane == 0) {
-                        wins_all[wv][4u * b + 0u] += c0;
-                        wins_all[wv][4u * b + 1u] += c1;
-                        wins_all[wv][4u * b + 2u] += c2;
-                        wins_all[wv][4u * b + 3u] += c3;
-                    }
-                }
-            }
-            tree_sync<VALUE>();
-            for (uint32_t b = 0; b < nb; ++b) {
-                if (!((play_mask >> b) & 1u)) continue;
-                if (a.leaf_eval) ++n_played;
-                if (lane == 0)
-#pragma unroll
-                    for (uint32_t k = 0; k < 4u; ++k) vals[b][k] = (float)wins_all[wv][4u * b + k];
-            }
-        }
-        for (uint32_t b = 0; b < nb; ++b) {
-            if (!((term_mask >> b) & 1u)) continue;
-            const uint32_t wn = (winners >> (2u * b)) & 3u;
-            if (lane == 0)
-#pragma unroll
-                for (uint32_t k = 0; k < 4u; ++k) vals[b][k] = k == wn ? (float)nplay : 0.0f;
-        }
-        tree_sync<VALUE>();
-
+        eval_pass(0u, i0, nb, term_mask, winners);
         const uint64_t t3 = clock64();
         cyc[2] += t3 - t2;
-        // ---- 4. back-propagation: each path gets its leaf's wins, in order --
-        for (uint32_t b = 0; b < nb; ++b) {
-            const uint32_t npb = np_all[wv][b];
-            if (lane < npb && !(a.vanilla && lane == 0u)) {   // a world node's W word holds its key
-                const uint32_t e = path_all[wv][b][lane];
-                // the chooser's value by a computed index: a chain of selects
-                // over the four LDS entries was compiled into branches that
-                // left seat 3's lanes reading seat 2's entry
-                const uint4 en = *reinterpret_cast<const uint4 *>(W + e);
-                const uint32_t chooser = (en.x >> 16) & 3u;
-                const float wc = vals[b][chooser];
-                W[e + 2u] = __float_as_uint(__uint_as_float(en.z) + wc);
-            }
-            tree_sync<VALUE>();
-        }
+        backprop_pass(0u, nb);
         cyc[3] += clock64() - t3;
+    }
+    if (PIPE) {
+        __syncthreads();   // the evaluating wavefront's statistics
+        n_net = pipe_x[1];
+        n_played = pipe_x[2];
+        cyc[2] = (uint64_t)pipe_x[3] | ((uint64_t)pipe_x[4] << 32);
     }
 
     // ---- decision and root statistics ----------------------------------------
@@ -1085,7 +1177,7 @@ mcts_tree_kernel(MctsArgs a)
         // ties; the statistics come back indexed by action id
         uint32_t *agg = W + a.sh.agg_off;
         for (uint32_t c = lane; c < 2u * kMaxActions; c += 64u) agg[c] = 0u;
-        tree_sync<VALUE>();
+        tree_sync<WS>();
         const uint32_t nw = W[rec_off(0u) + 2u];
         uint32_t wblk = 0u;
         for (uint32_t wi = 0; wi < nw; ++wi) {
@@ -1104,7 +1196,7 @@ mcts_tree_kernel(MctsArgs a)
                 }
                 if (base + kBlockEntries < nc) blk = bnext[blk];
             }
-            tree_sync<VALUE>();
+            tree_sync<WS>();
         }
         uint64_t key = 0ull;   // N << 32 | (863 - action): most visits, lowest id on ties
         for (uint32_t c = lane; c < kMaxActions; c += 64u) {
@@ -1233,7 +1325,8 @@ hipError_t launch_mcts(const uint4 *roots, uint32_t n_trees, uint32_t trees_per_
                        uint32_t dmax, float c_uct, uint32_t k0, uint32_t k1, uint32_t tree_base,
                        const float *ln, uint32_t *ws, int32_t *best, uint32_t *kids,
                        uint32_t leaf_eval, float band, uint32_t fb_ppl, const void *net,
-                       uint32_t cont, uint32_t vanilla, uint32_t lpp, hipStream_t st)
+                       uint32_t cont, uint32_t vanilla, uint32_t lpp, uint32_t pipe,
+                       hipStream_t st)
 {
     if (n_trees == 0) return hipSuccess;
     MctsArgs a;
@@ -1253,16 +1346,25 @@ hipError_t launch_mcts(const uint4 *roots, uint32_t n_trees, uint32_t trees_per_
     a.cont_mode = cont;
     a.vanilla = vanilla;
     a.lpp = lpp;
+    a.pipe = pipe;
     a.best = best;
     a.kids = kids;
     a.leaf_eval = leaf_eval;
     a.band = band;
     a.fb_ppl = fb_ppl;
     a.net = net;
-    if (leaf_eval)
-        hipLaunchKernelGGL(mcts_tree_kernel<true>, dim3((n_trees + 3u) / 4u), dim3(256), 0, st, a);
-    else
-        hipLaunchKernelGGL(mcts_tree_kernel<false>, dim3(n_trees), dim3(64), 0, st, a);
+    if (pipe) {
+        // one tree per workgroup: a descending and an evaluating wavefront
+        if (leaf_eval)
+            hipLaunchKernelGGL((mcts_tree_kernel<true, true>), dim3(n_trees), dim3(128), 0, st, a);
+        else
+            hipLaunchKernelGGL((mcts_tree_kernel<false, true>), dim3(n_trees), dim3(128), 0, st, a);
+    } else if (leaf_eval) {
+        hipLaunchKernelGGL((mcts_tree_kernel<true, false>), dim3((n_trees + 3u) / 4u), dim3(256), 0,
+                           st, a);
+    } else {
+        hipLaunchKernelGGL((mcts_tree_kernel<false, false>), dim3(n_trees), dim3(64), 0, st, a);
+    }
     return hipGetLastError();
 }
 

@@ -338,6 +338,71 @@ __device__ __forceinline__ void vn_stage_small(const VnPtrs &P, VnSmall &sm)
     if (threadIdx.x == 0) sm.b3 = P.master[kOffB3];
 }
 
+// orders LDS accesses between the lanes of one wavefront
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Value of 16 rows (lane l holds the features of row l % 16) by one
+// wavefront that shares its workgroup with another wavefront doing other
+// work: the same products as vn_eval16, both layers' weight fragments read
+// from L2, biases and output weights from `sm`, the 16 x 264 bf16 tile `hs`
+// (this wavefront's own) ordered with wavefront barriers.  v4[i] receives
+// the value of row 4 (l / 16) + i.
+__device__ __forceinline__ void vn_eval16_wave(const VnPtrs &P, const RowFeat &rf,
+                                               uint16_t (*hs)[kVnH + 8], const VnSmall &sm,
+                                               float v4[4])
+{
+    const uint32_t lane = threadIdx.x & 63u, r = lane & 15u, g = lane >> 4;
+    bf16x8 xa[5];
+#pragma unroll
+    for (uint32_t s = 0; s < 5u; ++s) xa[s] = feature8(rf, s, g);
+#pragma unroll 4
+    for (uint32_t j = 0; j < 16u; ++j) {
+        bf16x8 wb[5];
+#pragma unroll
+        for (uint32_t s = 0; s < 5u; ++s) wb[s] = load8(P.w1b + ((j * 5u + s) * 64u + lane) * 8u);
+        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (uint32_t s = 0; s < 5u; ++s) acc = mfma16(xa[s], wb[s], acc);
+        const float b = sm.b1[16u * j + r];
+#pragma unroll
+        for (uint32_t i = 0; i < 4u; ++i) {
+            const float h = acc[i] + b;
+            hs[4u * g + i][16u * j + r] = bf16_bits(h > 0.0f ? h : 0.0f);
+        }
+    }
+    wave_lds_sync();
+    bf16x8 ha[8];
+#pragma unroll
+    for (uint32_t s = 0; s < 8u; ++s) ha[s] = load8(&hs[r][32u * s + 8u * g]);
+    float zpart[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 4
+    for (uint32_t j = 0; j < 16u; ++j) {
+        bf16x8 wb[8];
+#pragma unroll
+        for (uint32_t s = 0; s < 8u; ++s) wb[s] = load8(P.w2b + ((j * 8u + s) * 64u + lane) * 8u);
+        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (uint32_t s = 0; s < 8u; ++s) acc = mfma16(ha[s], wb[s], acc);
+        const float b = sm.b2[16u * j + r], w3 = sm.w3[16u * j + r];
+#pragma unroll
+        for (uint32_t i = 0; i < 4u; ++i) {
+            const float h = acc[i] + b;
+            zpart[i] += bf16_round(h > 0.0f ? h : 0.0f) * w3;
+        }
+    }
+#pragma unroll
+    for (uint32_t i = 0; i < 4u; ++i)
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) zpart[i] += __shfl_xor(zpart[i], off, 64);
+#pragma unroll
+    for (uint32_t i = 0; i < 4u; ++i) v4[i] = 1.0f / (1.0f + expf(-(zpart[i] + sm.b3)));
+    wave_lds_sync();   // the tile may be reused
+}
+
 // k order of the transposed second product: slot 8g + e of a 32-unit block
 // holds unit 4g + e (e < 4) or 16 + 4g + e - 4 (e >= 4) -- the units that
 // lane group g holds of the block's two 16-unit output tiles of the first

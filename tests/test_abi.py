@@ -106,7 +106,8 @@ def test_valuenet_alignment_errors_without_device(lib):
 
 def test_tree_variant_parameters_without_device(lib):
     """Workspace sizes of the un-simplified variants (host-only), parameter
-    ranges, and vanilla trees refused by the root-parallel search."""
+    ranges (pipelined passes keep no world nodes: not with vanilla), and
+    vanilla trees refused by the root-parallel search."""
     import paper_2403_10720_amd as D
     vp = C.c_void_p
     lib.dvc_mcts_workspace_bytes.restype = C.c_size_t
@@ -117,9 +118,11 @@ def test_tree_variant_parameters_without_device(lib):
     assert base % 16 == 0 and cont % 16 == 0 and van % 16 == 0
     assert size(max_depth=0) == base and size(max_depth=64) == base
     for bad in (dict(max_depth=65), dict(max_depth=-1), dict(continue_choice=2), dict(vanilla=3),
-                dict(leaves_per_pass=0), dict(leaves_per_pass=17)):
+                dict(leaves_per_pass=0), dict(leaves_per_pass=17), dict(pipeline=2),
+                dict(pipeline=-1), dict(pipeline=1, vanilla=1)):
         assert size(**bad) == 0
     assert size(leaves_per_pass=16) == base
+    assert size(pipeline=1) == base and size(pipeline=1, leaves_per_pass=16) == base
     mp = D.mcts_params(iterations=10, playouts_per_leaf=4, vanilla=1)
     lib.mcts_search_root_parallel.argtypes = [vp, C.c_int64, C.c_int32, C.POINTER(D.MctsParams),
                                               C.c_uint64, C.c_uint32, vp, C.c_size_t, vp, vp, vp]

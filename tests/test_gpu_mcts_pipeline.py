@@ -1,0 +1,153 @@
+"""GPU parity of pipelined passes, node by node (through the C ABI).
+
+Pipelined passes credit a pass's wins only after the next pass's descents,
+the last pass's at the end (Sec. III-B: several workers' simulations side by
+side; the oracle's reading of it is pinned in the oracle tests).  On the GPU
+a tree is then two wavefronts, one descending while the other evaluates.
+
+Bar: bit-exact.  Every searched tree is decoded from the workspace and
+compared with the oracle's tree dump: creation order, parent, guess key,
+chooser, N and W; the decision and the root children as well.
+
+* playout leaves: mixed 2/3/4-player roots, depth thresholds 3 and 4 and none,
+  with the continue choice, one to sixteen leaves per pass, iteration counts
+  that leave a ragged last pass;
+* value leaves with the integer network of ``exact_net`` (outputs exact in
+  any summation order): band 0 and 0.05, one to four leaves per pass;
+* a batch against its trees searched alone, a malformed root next to good
+  ones, and root-parallel search with merged children.
+"""
+import numpy as np
+import pytest
+
+import exact_net
+import gpu_tree
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dvc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2403_10720_amd as D
+    D.lib()
+    return D
+
+
+def dev_states(a):
+    return torch.from_numpy(np.ascontiguousarray(a).view(np.int32)).cuda()
+
+
+def _roots(orc, n, seed, **kw):
+    args = dict(p_min=2, p_max=4, hand=(0, 0, 4, 4, 3), pile_min=0, pile_max=12,
+                revealed_max=5, root_draw=1)
+    args.update(kw)
+    return orc.init_states(n, orc.deal_params(**args), seed=seed)
+
+
+def _search_and_compare(orc, dvc, roots, mo, md, seed, tree_base=0):
+    n = len(roots)
+    per_tree = dvc.dvc_mcts_workspace_bytes(1, md)
+    ws = torch.zeros(per_tree * n, dtype=torch.uint8, device="cuda")
+    best, _ = dvc.mcts_search(dev_states(roots), md, seed, tree_base, workspace=ws,
+                              want_children=False)
+    torch.cuda.synchronize()
+    assert dvc.dvc_check() == 0
+    got = gpu_tree.trees(ws, n, per_tree, md.iterations, md.continue_choice)
+    stats = dvc.mcts_tree_stats(ws, n, md)
+    deep = 0
+    for t in range(n):
+        ref_best, ref = orc.mcts_tree(roots[t], mo, seed, tree_base + t)
+        print(f"tree {t}: {len(ref)} nodes", flush=True)
+        gpu_tree.assert_same_tree(got[t], ref)
+        assert int(best[t].item()) == ref_best
+        deep += int(np.sum(ref["depth"] >= 2))
+    return stats, deep
+
+
+@pytest.mark.parametrize("dmax,cont,lpp,iters", [(3, 0, 1, 300), (0, 1, 2, 301), (4, 0, 4, 301),
+                                                 (0, 0, 16, 300), (4, 1, 7, 250)])
+def test_pipelined_playout_trees_node_by_node(orc, dvc, dmax, cont, lpp, iters):
+    roots = _roots(orc, 8, 501 + dmax + 10 * cont + lpp)
+    kw = dict(iterations=iters, playouts_per_leaf=8, max_depth=dmax, continue_choice=cont,
+              leaves_per_pass=lpp, pipeline=1)
+    _, deep = _search_and_compare(orc, dvc, roots, orc.mcts_params(**kw), dvc.mcts_params(**kw), 23)
+    assert deep > 200
+
+
+def _value_kw(net, band, iters, dmax, lpp):
+    return dict(iterations=iters, playouts_per_leaf=1, max_depth=dmax, leaf_eval=1,
+                fallback_band=band, fallback_playouts=64, valuenet=net, leaves_per_pass=lpp,
+                pipeline=1)
+
+
+@pytest.mark.parametrize("band,dmax,lpp", [(0.0, 4, 1), (0.05, 4, 2), (0.05, 3, 4), (0.0, 0, 3),
+                                           (0.05, 0, 1)])
+def test_pipelined_value_trees_node_by_node(orc, dvc, band, dmax, lpp):
+    p = exact_net.params()
+    net = dvc.dvc_valuenet_init(0)
+    dvc.dvc_valuenet_set_params(net, torch.from_numpy(p).cuda())
+    roots = _roots(orc, 8, 521 + int(band * 100) + dmax + lpp)
+    legal = max(int(orc.legal_actions(r).sum()) for r in roots)
+    iters = 4 * legal + 1
+    mo = orc.mcts_params(**_value_kw(p, band, iters, dmax, lpp))
+    md = dvc.mcts_params(**_value_kw(net, band, iters, dmax, lpp))
+    stats, deep = _search_and_compare(orc, dvc, roots, mo, md, 29)
+    assert deep > 100
+    played = int(stats["played_leaves"].sum())
+    scored = int(stats["net_leaves"].sum())
+    if band == 0.0:
+        assert played == 0 and scored > 0
+    else:
+        assert played > 0 and scored > 0, (played, scored)
+
+
+@pytest.mark.parametrize("value", [0, 1])
+def test_pipelined_batch_against_single_trees(orc, dvc, value):
+    """A tree's result does not depend on the other trees of the batch."""
+    roots = _roots(orc, 10, 541 + value, pile_max=16, revealed_max=8)
+    if value:
+        net = dvc.dvc_valuenet_init(0)
+        dvc.dvc_valuenet_set_params(net, torch.from_numpy(exact_net.params()).cuda())
+        md = dvc.mcts_params(**_value_kw(net, 0.05, 160, 4, 4))
+    else:
+        md = dvc.mcts_params(iterations=200, playouts_per_leaf=8, leaves_per_pass=4, pipeline=1)
+    st = dev_states(roots)
+    best, kids = dvc.mcts_search(st, md, 31, 60)
+    for t in (0, 4, 9):
+        b1, k1 = dvc.mcts_search(st[t:t + 1], md, 31, 60 + t)
+        assert int(b1[0].item()) == int(best[t].item())
+        assert torch.equal(k1[0], kids[t])
+    assert dvc.dvc_check() == 0
+
+
+def test_pipelined_malformed_root(orc, dvc):
+    """Both wavefronts of a malformed root's tree leave at once; the others search."""
+    roots = _roots(orc, 3, 551)
+    roots[1, 3] |= np.uint32(1 << 30)
+    kw = dict(iterations=64, playouts_per_leaf=4, leaves_per_pass=2, pipeline=1)
+    best, _ = dvc.mcts_search(dev_states(roots), dvc.mcts_params(**kw), 7)
+    torch.cuda.synchronize()
+    assert dvc.dvc_check() == dvc.DVC_ESTATE
+    got = best.cpu().numpy()
+    assert got[1] == -1
+    for t in (0, 2):
+        ref_best, _ = orc.mcts_search(roots[t:t + 1], orc.mcts_params(**kw), 7, t)
+        assert got[t] == ref_best[0]
+
+
+def test_pipelined_root_parallel(orc, dvc):
+    roots = _roots(orc, 4, 561, pile_max=16, revealed_max=8)
+    kw = dict(iterations=200, playouts_per_leaf=8, max_depth=4, leaves_per_pass=2, pipeline=1)
+    best_ref, m_ref = orc.mcts_search_merged(roots, 5, orc.mcts_params(**kw), 8, 40)
+    best, kids = dvc.mcts_search_root_parallel(dev_states(roots), 5, dvc.mcts_params(**kw), 8, 40)
+    torch.cuda.synchronize()
+    assert dvc.dvc_check() == 0
+    assert np.array_equal(best.cpu().numpy(), best_ref)
+    act, n, w = dvc.children_view(kids)
+    assert np.array_equal(act.numpy(), m_ref["action"].astype(np.int64))
+    assert np.array_equal(n.numpy(), m_ref["n"].astype(np.int64))
+    assert np.array_equal(w.numpy().view(np.uint32), m_ref["w"].view(np.uint32))
