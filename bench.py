@@ -13,9 +13,10 @@ prices the dominant kernel (the rollout kernel, one playout per lane at this
 size) against the integer-VALU issue peak of the chip; `cpu_baseline` is the
 CPU oracle timed on this host's cores on a bounded sample of the same
 workload.  Side figures: batched search (as configured, with two leaves per
-pass, and with the shape the library's search autotuner picks under its
-agreement guard), root-parallel search and a single tree, timed with HIP
-events; `value_vs_rollout`: value-network training on
+pass, also pipelined, and with the shape the library's search autotuner
+picks under its agreement guard), root-parallel search and a single tree
+(also four leaves per pass, plain and pipelined), timed with HIP events;
+`value_vs_rollout`: value-network training on
 pairs the rollout kernel labels (step time, TFLOP/s) and the value-network
 search against the pure-playout search on 1024 fresh deals x 4096 iterations
 (decisions/s of both, GPU-seconds ratio, root-move agreement).
@@ -106,14 +107,16 @@ SEARCH_DEAL = dict(p_min=2, p_max=4, hand=(0, 0, 4, 4, 3), pile_min=0, pile_max=
                    revealed_max=8, root_draw=1)
 
 
-def batched_search(D, torch, reps=3, leaves_per_pass=1):
+def batched_search(D, torch, reps=3, leaves_per_pass=1, pipeline=0):
     """Batched search: 2048 mixed 2/3/4-player roots, 1024 iterations x 32 playouts,
     depth 4, one launch; decisions/s from HIP events.  leaves_per_pass 2: two
-    leaves' playouts share each tree's 64 lanes."""
+    leaves' playouts share each tree's 64 lanes; pipeline 1: a pass's wins are
+    credited after the next pass's descents, one wavefront per tree descending
+    while another plays out."""
     n, iters, ppl = 2048, 1024, 32
     roots = D.dvc_init_states(n, D.deal_params(**SEARCH_DEAL), 3)
     mp = D.mcts_params(iterations=iters, playouts_per_leaf=ppl, max_depth=4,
-                       leaves_per_pass=leaves_per_pass)
+                       leaves_per_pass=leaves_per_pass, pipeline=pipeline)
     ws = torch.empty(D.dvc_mcts_workspace_bytes(n, mp), dtype=torch.uint8, device=roots.device)
     D.mcts_search(roots, mp, 3, workspace=ws, want_children=False)
     torch.cuda.synchronize()
@@ -128,18 +131,20 @@ def batched_search(D, torch, reps=3, leaves_per_pass=1):
     best = min(ms)
     return {"workload": "2048 trees (2-4 players, mid-game, root draw) x 1024 iterations x 32 "
                         "playouts, depth 4" + (f", {leaves_per_pass} leaves per pass"
-                                               if leaves_per_pass > 1 else ""),
+                                               if leaves_per_pass > 1 else "") +
+                        (", pipelined passes" if pipeline else ""),
             "ms_per_launch": best,
             "decisions_per_s": n / (best / 1e3), "playouts_per_s": n * iters * ppl / (best / 1e3)}
 
 
 def autotuned_search(D, torch, reps=3, tolerance=0.02):
     """The batched search with the shape the library's search autotuner picks
-    for it: dvc_mcts_autotune times every (playouts per leaf, leaves per pass)
-    candidate on these roots and admits those whose decisions agree with the
-    sequential 32-playout search at least as often as a second seed of that
-    search does, less `tolerance`; the fastest admitted shape then runs as the
-    automatic shape (playouts per leaf and leaves per pass both 0)."""
+    for it: dvc_mcts_autotune times every (playouts per leaf, leaves per pass,
+    pipelined or not) candidate on these roots and admits those whose
+    decisions agree with the sequential 32-playout search at least as often as
+    a second seed of that search does, less `tolerance`; the fastest admitted
+    shape then runs as the automatic shape (playouts per leaf, leaves per pass
+    and pipeline all 0)."""
     n, iters, ppl = 2048, 1024, 32
     roots = D.dvc_init_states(n, D.deal_params(**SEARCH_DEAL), 3)
     ref = D.mcts_params(iterations=iters, playouts_per_leaf=ppl, max_depth=4)
@@ -159,7 +164,8 @@ def autotuned_search(D, torch, reps=3, tolerance=0.02):
         ms.append(e0.elapsed_time(e1))
     best = min(ms)
     return {"workload": "2048 trees (2-4 players, mid-game, root draw) x 1024 iterations, depth 4, "
-                        "autotuned playouts per leaf x leaves per pass (agreement guard: within "
+                        "autotuned playouts per leaf x leaves per pass x pipelined passes "
+                        "(agreement guard: within "
                         f"{tolerance} of the 32-playout search's seed-to-seed agreement)",
             "choice": choice, "ms_per_launch": best, "decisions_per_s": n / (best / 1e3),
             "playouts_per_s": n * iters * choice["playouts_per_leaf"] / (best / 1e3)}
@@ -189,13 +195,14 @@ def root_parallel_search(D, torch, reps=3):
             "decisions_per_s": n / (best / 1e3), "playouts_per_s": n * K * iters * ppl / (best / 1e3)}
 
 
-def single_tree_search(D, torch, leaves_per_pass=1):
+def single_tree_search(D, torch, leaves_per_pass=1, pipeline=0):
     """Plain search: one fresh two-player deal, 2000 iterations x 16 playouts.
     leaves_per_pass 4: four descents per pass, their 64 playouts filling the
-    wavefront (a different, batched schedule of the same iterations)."""
+    wavefront (a different, batched schedule of the same iterations);
+    pipeline 1: pipelined passes (two wavefronts)."""
     roots = D.dvc_init_states(1, D.deal_params(p_min=2, p_max=2, fresh=1, root_draw=1), 1)
     mp = D.mcts_params(iterations=2000, playouts_per_leaf=16, max_depth=4,
-                       leaves_per_pass=leaves_per_pass)
+                       leaves_per_pass=leaves_per_pass, pipeline=pipeline)
     ws = torch.empty(D.dvc_mcts_workspace_bytes(1, mp), dtype=torch.uint8, device=roots.device)
     D.mcts_search(roots, mp, 1, workspace=ws, want_children=False)
     torch.cuda.synchronize()
@@ -206,7 +213,8 @@ def single_tree_search(D, torch, leaves_per_pass=1):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
     return {"workload": "1 tree, fresh 2-player deal, 2000 iterations x 16 playouts" +
-                        (f", {leaves_per_pass} leaves per pass" if leaves_per_pass > 1 else ""),
+                        (f", {leaves_per_pass} leaves per pass" if leaves_per_pass > 1 else "") +
+                        (", pipelined passes" if pipeline else ""),
             "ms_per_decision": ms, "decisions_per_s": 1e3 / ms}
 
 
@@ -436,10 +444,13 @@ def main():
     if not args.no_search:
         out["batched_search"] = batched_search(D, torch)
         out["batched_search_leaf_batched"] = batched_search(D, torch, leaves_per_pass=2)
+        out["batched_search_pipelined"] = batched_search(D, torch, leaves_per_pass=2, pipeline=1)
         out["batched_search_autotuned"] = autotuned_search(D, torch)
         out["root_parallel_search"] = root_parallel_search(D, torch)
         out["single_tree_search"] = single_tree_search(D, torch)
         out["single_tree_search_leaf_batched"] = single_tree_search(D, torch, leaves_per_pass=4)
+        out["single_tree_search_pipelined"] = single_tree_search(D, torch, leaves_per_pass=4,
+                                                                 pipeline=1)
     if not args.no_value:
         out["value_vs_rollout"] = value_vs_rollout()
     if not args.no_cpu:

@@ -267,12 +267,14 @@ typedef struct {
     int32_t pipeline;           /* 1: pipelined passes (see above); not with vanilla */
 } dvc_mcts_params;
 /* Automatic shape: with playout leaves, playouts_per_leaf = 0 together with
- * leaves_per_pass = 0 asks for the shape dvc_mcts_autotune chose for this
+ * leaves_per_pass = 0 and pipeline = 0 asks for the shape (playouts per
+ * leaf, leaves per pass, pipelined or not) dvc_mcts_autotune chose for this
  * size class (device, floor(log2 n_trees), floor(log2 iterations), max_depth,
  * continue_choice, vanilla), else 32 playouts per leaf with two leaves per
- * pass (the fastest shape within two points of the sequential 32-playout
- * search's seed-to-seed agreement, measured on 2048 mixed mid-game roots x
- * 1024 iterations).  Such searches need iterations * 128 < 2^24.          */
+ * pass, not pipelined (the fastest such shape within two points of the
+ * sequential 32-playout search's seed-to-seed agreement, measured on 2048
+ * mixed mid-game roots x 1024 iterations).  Such searches need
+ * iterations * 128 < 2^24.                                                 */
 
 /* one root child, in creation order (vanilla: indexed by action id); action
  * 0xFFFF marks unused entries */
@@ -321,26 +323,30 @@ int mcts_search_noalloc(const dvc_state_t *roots, int64_t n_trees,
  * searches like this one (Sec. IV-B: the paper sweeps threads and warps for
  * the simulations; here the leaf's playouts and the leaves evaluated together
  * share the tree's 64 lanes).  params: playout leaves, playouts_per_leaf =
- * the reference P_ref >= 1, leaves_per_pass = 1.  Runs the reference (the
- * sequential search with P_ref playouts per leaf) under `seed` and under a
- * second seed (seed ^ 0x9E3779B97F4A7C15); their root-move agreement is the
- * ceiling A0.  Then every candidate (4 playouts x 1/2/4/8/16 leaves per pass,
- * 8 x 1/2/4/8, 16 x 1/2/4, 32 x 1/2, 64 x 1, 128 x 1) runs once under seed + 1,
- * timed by HIP events on `stream`, and is admitted when its agreement with the
+ * the reference P_ref >= 1, leaves_per_pass = 1, pipeline = 0.  Runs the
+ * reference (the sequential search with P_ref playouts per leaf) under `seed`
+ * and under a second seed (seed ^ 0x9E3779B97F4A7C15); their root-move
+ * agreement is the ceiling A0.  Then every candidate (4 playouts x 1/2/4/8/16
+ * leaves per pass, 8 x 1/2/4/8, 16 x 1/2/4, 32 x 1/2, 64 x 1, 128 x 1, each
+ * without and with pipelined passes; vanilla searches without only) runs once
+ * under seed + 1, timed by HIP events on `stream`, and is admitted when its
+ * agreement with the
  * reference is at least A0 - tolerance.  The fastest admitted candidate (the
  * reference shape when none is) is remembered for the size class (see the
  * automatic shape above; a library-owned table guarded by a lock, kept until
  * the process ends) and described in *result (host, may be NULL).
  * best_action (device, n_trees) receives the chosen candidate's decisions.
  * workspace as for mcts_search with iterations and variants of params.
- * Synchronizes the stream; 18 searches of this size.  DVC_EINVAL for value
- * leaves, leaves_per_pass != 1, n_trees < 1, a negative tolerance, or
- * iterations * 128 >= 2^24; other errors as mcts_search.                   */
+ * Synchronizes the stream; 34 searches of this size (18 for vanilla).
+ * DVC_EINVAL for value leaves, leaves_per_pass != 1, pipeline != 0,
+ * n_trees < 1, a negative tolerance, or iterations * 128 >= 2^24; other
+ * errors as mcts_search.                                                   */
 typedef struct {
     int32_t playouts_per_leaf, leaves_per_pass;   /* the choice                  */
     float decisions_per_s;                        /* its measured rate           */
     float agreement;                              /* its agreement with the reference */
     float self_agreement;                         /* A0                           */
+    int32_t pipeline;                             /* the choice: pipelined passes */
 } dvc_mcts_tuning;
 int dvc_mcts_autotune(const dvc_state_t *roots, int64_t n_trees, const dvc_mcts_params *params /* host */,
                       uint64_t seed, uint32_t tree_id_base, void *workspace, size_t workspace_bytes,

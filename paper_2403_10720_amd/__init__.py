@@ -48,7 +48,7 @@ class MctsParams(C.Structure):
 class MctsTuning(C.Structure):
     _fields_ = [("playouts_per_leaf", C.c_int32), ("leaves_per_pass", C.c_int32),
                 ("decisions_per_s", C.c_float), ("agreement", C.c_float),
-                ("self_agreement", C.c_float)]
+                ("self_agreement", C.c_float), ("pipeline", C.c_int32)]
 
 
 def deal_params(p_min=2, p_max=2, hand=(0, 0, 4, 4, 3), pile_min=0, pile_max=16,
@@ -283,8 +283,9 @@ def mcts_search_noalloc(roots: torch.Tensor, params: MctsParams, seed: int, tree
 
 def dvc_mcts_autotune(roots: torch.Tensor, params: MctsParams, seed: int, tree_id_base: int = 0,
                       tolerance: float = 0.02, workspace=None, stream=None):
-    """Pick playouts per leaf x leaves per pass for searches of this size class
-    (see include/dvc.h).  Returns (choice dict, decisions of the chosen shape)."""
+    """Pick playouts per leaf x leaves per pass x pipelined passes for searches
+    of this size class (see include/dvc.h).  Returns (choice dict, decisions of
+    the chosen shape)."""
     _check_dev(roots, torch.int32, None, "roots")
     n = roots.shape[0]
     need = dvc_mcts_workspace_bytes(n, params)
@@ -297,7 +298,8 @@ def dvc_mcts_autotune(roots: torch.Tensor, params: MctsParams, seed: int, tree_i
                                  C.byref(res), _stream(stream))
     _raise(rc, "dvc_mcts_autotune")
     return ({"playouts_per_leaf": res.playouts_per_leaf, "leaves_per_pass": res.leaves_per_pass,
-             "decisions_per_s": res.decisions_per_s, "agreement": res.agreement,
+             "pipeline": res.pipeline, "decisions_per_s": res.decisions_per_s,
+             "agreement": res.agreement,
              "self_agreement": res.self_agreement}, best)
 
 

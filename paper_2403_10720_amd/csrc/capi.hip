@@ -111,18 +111,23 @@ static void philox_host(const uint32_t ctr[4], uint32_t k0, uint32_t k1, uint32_
 
 // playouts per leaf x leaves per pass candidates of the search autotuner:
 // every pass holds at most 64 playouts (the tree's wavefront), plus one leaf
-// per pass with 64 and 128 playouts
+// per pass with 64 and 128 playouts; each shape is tried with and without
+// pipelined passes
 struct SearchShape {
-    int32_t ppl, lpp;
+    int32_t ppl, lpp, pipe;
 };
 static const SearchShape kSearchCandidates[] = {
-    {4, 1}, {4, 2}, {4, 4}, {4, 8}, {4, 16}, {8, 1}, {8, 2}, {8, 4}, {8, 8}, {16, 1},
-    {16, 2}, {16, 4}, {32, 1}, {32, 2}, {64, 1}, {128, 1}};
+    {4, 1, 0}, {4, 2, 0}, {4, 4, 0}, {4, 8, 0}, {4, 16, 0}, {8, 1, 0}, {8, 2, 0}, {8, 4, 0},
+    {8, 8, 0}, {16, 1, 0}, {16, 2, 0}, {16, 4, 0}, {32, 1, 0}, {32, 2, 0}, {64, 1, 0},
+    {128, 1, 0}, {4, 1, 1}, {4, 2, 1}, {4, 4, 1}, {4, 8, 1}, {4, 16, 1}, {8, 1, 1}, {8, 2, 1},
+    {8, 4, 1}, {8, 8, 1}, {16, 1, 1}, {16, 2, 1}, {16, 4, 1}, {32, 1, 1}, {32, 2, 1},
+    {64, 1, 1}, {128, 1, 1}};
 constexpr int32_t kAutoMaxPpl = 128;
 
 static bool is_auto(const dvc_mcts_params *p)
 {
-    return p->leaf_eval == 0 && p->playouts_per_leaf == 0 && p->leaves_per_pass == 0;
+    return p->leaf_eval == 0 && p->playouts_per_leaf == 0 && p->leaves_per_pass == 0 &&
+           p->pipeline == 0;
 }
 
 static bool mcts_params_ok(const dvc_mcts_params *p)
@@ -154,7 +159,8 @@ static bool mcts_params_ok(const dvc_mcts_params *p)
 }
 
 // the autotuner's choices: (device, log2 trees, log2 iterations, max depth,
-// continue choice, vanilla) -> (playouts per leaf, leaves per pass)
+// continue choice, vanilla) -> (playouts per leaf, leaves per pass,
+// pipelined passes)
 static std::mutex g_search_tune_mutex;
 static std::map<std::tuple<int, int, int, int, int, int>, SearchShape> g_search_tuned;
 
@@ -175,16 +181,17 @@ static std::tuple<int, int, int, int, int, int> search_key(int64_t n_trees,
                            p->vanilla);
 }
 
-// The parameters a search runs with: automatic playouts per leaf and leaves
-// per pass (both 0, playout leaves) become the autotuner's choice for this
-// size class, else 32 playouts with two leaves per pass (the fastest shape
-// within two points of the sequential 32-playout search's self-agreement on
-// 2048 mixed mid-game roots x 1024 iterations, measured on gfx950).
+// The parameters a search runs with: an automatic shape (playout leaves,
+// playouts per leaf, leaves per pass and pipeline all 0) becomes the
+// autotuner's choice for this size class, else 32 playouts with two leaves
+// per pass, not pipelined (the fastest shape within two points of the
+// sequential 32-playout search's self-agreement on 2048 mixed mid-game
+// roots x 1024 iterations, measured on gfx950 before pipelined passes).
 static dvc_mcts_params resolved(const dvc_mcts_params *p, int64_t n_trees)
 {
     dvc_mcts_params r = *p;
     if (!is_auto(p)) return r;
-    SearchShape sh{32, 2};
+    SearchShape sh{32, 2, 0};
     {
         std::lock_guard<std::mutex> lock(g_search_tune_mutex);
         auto it = g_search_tuned.find(search_key(n_trees, p));
@@ -192,6 +199,7 @@ static dvc_mcts_params resolved(const dvc_mcts_params *p, int64_t n_trees)
     }
     r.playouts_per_leaf = sh.ppl;
     r.leaves_per_pass = sh.lpp;
+    r.pipeline = sh.pipe;
     return r;
 }
 
@@ -569,8 +577,8 @@ int dvc_mcts_autotune(const dvc_state_t *roots, int64_t n_trees, const dvc_mcts_
                       void *stream)
 {
     if (params == nullptr || params->leaf_eval != 0 || params->playouts_per_leaf < 1 ||
-        params->leaves_per_pass != 1 || n_trees < 1 || !(tolerance >= 0.0f) ||
-        best_action == nullptr)
+        params->leaves_per_pass != 1 || params->pipeline != 0 || n_trees < 1 ||
+        !(tolerance >= 0.0f) || best_action == nullptr)
         return DVC_EINVAL;
     dvc_mcts_params cand = *params;
     cand.playouts_per_leaf = kAutoMaxPpl;   // every candidate's visit counts stay exact
@@ -608,13 +616,15 @@ int dvc_mcts_autotune(const dvc_state_t *roots, int64_t n_trees, const dvc_mcts_
     int status = run(*params, seed, ref, nullptr);
     if (status == DVC_OK) status = run(*params, seed ^ 0x9E3779B97F4A7C15ull, ref2, nullptr);
     const float ceiling = status == DVC_OK ? agreement(ref, ref2) : 0.0f;
-    SearchShape best{params->playouts_per_leaf, 1};
+    SearchShape best{params->playouts_per_leaf, 1, 0};
     float best_ms = 0.0f, best_agree = 0.0f;
     bool have = false;
     for (const SearchShape &c : kSearchCandidates) {
         if (status != DVC_OK) break;
+        if (c.pipe && params->vanilla) continue;   // pipelined passes keep no world nodes
         cand.playouts_per_leaf = c.ppl;
         cand.leaves_per_pass = c.lpp;
+        cand.pipeline = c.pipe;
         float ms = 0.0f;
         // candidates run under a third seed, so that the caller's own shape is
         // judged like the others (its agreement is then the seed-to-seed one)
@@ -646,6 +656,7 @@ int dvc_mcts_autotune(const dvc_state_t *roots, int64_t n_trees, const dvc_mcts_
     if (result) {
         result->playouts_per_leaf = best.ppl;
         result->leaves_per_pass = best.lpp;
+        result->pipeline = best.pipe;
         result->decisions_per_s = have ? (float)((double)n_trees / (best_ms * 1e-3)) : 0.0f;
         result->agreement = best_agree;
         result->self_agreement = ceiling;

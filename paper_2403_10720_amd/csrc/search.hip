@@ -493,7 +493,7 @@ template <bool VALUE, bool PIPE> struct TreeGroup {
 // descends and backs up, wavefront 1 evaluates.
 template <bool VALUE, bool PIPE>
 __global__ void __launch_bounds__((64 * TreeGroup<VALUE, PIPE>::kWaves))
-__attribute__((amdgpu_waves_per_eu(1, (VALUE && !PIPE) ? 1 : 8)))
+__attribute__((amdgpu_waves_per_eu(PIPE ? 2 : 1, VALUE ? (PIPE ? 2 : 1) : 8)))
 mcts_tree_kernel(MctsArgs a)
 {
     constexpr uint32_t TG = TreeGroup<VALUE, PIPE>::kTrees;

@@ -351,49 +351,85 @@ __device__ __forceinline__ void wave_lds_sync()
 // from L2, biases and output weights from `sm`, the 16 x 264 bf16 tile `hs`
 // (this wavefront's own) ordered with wavefront barriers.  v4[i] receives
 // the value of row 4 (l / 16) + i.
+//
+// The wavefront has nothing else to hide the L2 latency behind, so the
+// weight fragments of output tile j + 4 (first layer) or j + 3 (second) are
+// requested right after tile j is multiplied (requests past the last tile
+// repeat it); the scheduling
+// barriers keep the compiler from moving the requests back next to their
+// uses.
 __device__ __forceinline__ void vn_eval16_wave(const VnPtrs &P, const RowFeat &rf,
                                                uint16_t (*hs)[kVnH + 8], const VnSmall &sm,
                                                float v4[4])
 {
     const uint32_t lane = threadIdx.x & 63u, r = lane & 15u, g = lane >> 4;
+    constexpr uint32_t D1 = 4u, D2 = 3u;
+    const uint16_t *w1 = P.w1b + lane * 8u, *w2 = P.w2b + lane * 8u;
     bf16x8 xa[5];
 #pragma unroll
     for (uint32_t s = 0; s < 5u; ++s) xa[s] = feature8(rf, s, g);
-#pragma unroll 4
-    for (uint32_t j = 0; j < 16u; ++j) {
-        bf16x8 wb[5];
+    bf16x8 w1r[D1][5];
 #pragma unroll
-        for (uint32_t s = 0; s < 5u; ++s) wb[s] = load8(P.w1b + ((j * 5u + s) * 64u + lane) * 8u);
-        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (uint32_t j = 0; j < D1; ++j)
 #pragma unroll
-        for (uint32_t s = 0; s < 5u; ++s) acc = mfma16(xa[s], wb[s], acc);
-        const float b = sm.b1[16u * j + r];
+        for (uint32_t s = 0; s < 5u; ++s) w1r[j][s] = load8(w1 + (j * 5u + s) * 512u);
+#pragma unroll 1
+    for (uint32_t j0 = 0; j0 < 16u; j0 += D1) {
 #pragma unroll
-        for (uint32_t i = 0; i < 4u; ++i) {
-            const float h = acc[i] + b;
-            hs[4u * g + i][16u * j + r] = bf16_bits(h > 0.0f ? h : 0.0f);
+        for (uint32_t jj = 0; jj < D1; ++jj) {
+            const uint32_t j = j0 + jj, jn = j + D1 < 16u ? j + D1 : 15u;
+            __builtin_amdgcn_sched_barrier(0);
+            floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (uint32_t s = 0; s < 5u; ++s) acc = mfma16(xa[s], w1r[jj][s], acc);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (uint32_t s = 0; s < 5u; ++s) w1r[jj][s] = load8(w1 + (jn * 5u + s) * 512u);
+            __builtin_amdgcn_sched_barrier(0);
+            const float b = sm.b1[16u * j + r];
+#pragma unroll
+            for (uint32_t i = 0; i < 4u; ++i) {
+                const float h = acc[i] + b;
+                hs[4u * g + i][16u * j + r] = bf16_bits(h > 0.0f ? h : 0.0f);
+            }
         }
     }
+    // the second layer's first fragments are requested before the tile is read back
+    bf16x8 w2r[D2][8];
+#pragma unroll
+    for (uint32_t j = 0; j < D2; ++j)
+#pragma unroll
+        for (uint32_t s = 0; s < 8u; ++s) w2r[j][s] = load8(w2 + (j * 8u + s) * 512u);
     wave_lds_sync();
     bf16x8 ha[8];
 #pragma unroll
     for (uint32_t s = 0; s < 8u; ++s) ha[s] = load8(&hs[r][32u * s + 8u * g]);
     float zpart[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll 4
-    for (uint32_t j = 0; j < 16u; ++j) {
-        bf16x8 wb[8];
-#pragma unroll
-        for (uint32_t s = 0; s < 8u; ++s) wb[s] = load8(P.w2b + ((j * 8u + s) * 64u + lane) * 8u);
+    // output tile j from the ring slot wq, which then requests tile j + D2
+    auto layer2_tile = [&](uint32_t j, bf16x8 (&wq)[8]) {
+        const uint32_t jn = j + D2 < 16u ? j + D2 : 15u;
+        __builtin_amdgcn_sched_barrier(0);
         floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (uint32_t s = 0; s < 8u; ++s) acc = mfma16(ha[s], wb[s], acc);
+        for (uint32_t s = 0; s < 8u; ++s) acc = mfma16(ha[s], wq[s], acc);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (uint32_t s = 0; s < 8u; ++s) wq[s] = load8(w2 + (jn * 8u + s) * 512u);
+        __builtin_amdgcn_sched_barrier(0);
         const float b = sm.b2[16u * j + r], w3 = sm.w3[16u * j + r];
 #pragma unroll
         for (uint32_t i = 0; i < 4u; ++i) {
             const float h = acc[i] + b;
             zpart[i] += bf16_round(h > 0.0f ? h : 0.0f) * w3;
         }
+    };
+    // tiles 0 .. 14 three at a time, then tile 15 (ring slot 0)
+#pragma unroll 1
+    for (uint32_t j0 = 0; j0 < 15u; j0 += D2) {
+#pragma unroll
+        for (uint32_t jj = 0; jj < D2; ++jj) layer2_tile(j0 + jj, w2r[jj]);
     }
+    layer2_tile(15u, w2r[0]);
 #pragma unroll
     for (uint32_t i = 0; i < 4u; ++i)
 #pragma unroll

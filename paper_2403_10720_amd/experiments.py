@@ -136,12 +136,24 @@ def compare(n_trees=1024, iterations=4096, ppl=64, band=0.05, train_cfg: TrainCo
                           leaves_per_pass=lpp)
     best_val2, t_val2 = median_search(roots, mp_val2, seed, ws, reps)
     phases_val2 = tree_phases(ws, n_trees, mp_val2)
+    # both searches with pipelined passes (a pass's values credited after the
+    # next pass's descents): one wavefront descends while another evaluates
+    mp_val3 = mcts_params(iterations=iterations, playouts_per_leaf=1, max_depth=4, leaf_eval=1,
+                          fallback_band=band, fallback_playouts=ppl, valuenet=net,
+                          leaves_per_pass=lpp, pipeline=1)
+    best_val3, t_val3 = median_search(roots, mp_val3, seed, ws, reps)
+    mp_roll3 = mcts_params(iterations=iterations, playouts_per_leaf=ppl, max_depth=4, pipeline=1)
+    best_roll3, t_roll3 = median_search(roots, mp_roll3, seed, ws, reps)
     # the playout search's phases (its trees are overwritten above)
     timed_search(roots, mp_roll, seed, ws)
     phases_roll = tree_phases(ws, n_trees, mp_roll)
     agree = float((best_val == best_roll).float().mean().item())
     ceiling = float((best_roll2 == best_roll).float().mean().item())
     speedup = t_roll / t_val
+    # the GPU-seconds ratio of the fastest value search against the fastest
+    # playout search (pipelined or not)
+    t_val_best, t_roll_best = min(t_val, t_val2, t_val3), min(t_roll, t_roll3)
+    ratio = t_roll_best / t_val_best
     out = {
         "workload": f"{n_trees} fresh 2-4 player deals (root draw) x {iterations} iterations, "
                     f"depth 4; playout mode {ppl} playouts per leaf; value mode band {band}, "
@@ -164,12 +176,23 @@ def compare(n_trees=1024, iterations=4096, ppl=64, band=0.05, train_cfg: TrainCo
             "decisions_per_s": n_trees / t_val2,
             "gpu_s_per_decision": t_val2 / n_trees, "speedup": t_roll / t_val2,
             "phases": phases_val2},
+        "pipelined": {
+            "leaves_per_pass": lpp,
+            "root_move_agreement": float((best_val3 == best_roll).float().mean().item()),
+            "decisions_per_s": n_trees / t_val3,
+            "gpu_s_per_decision": t_val3 / n_trees, "speedup": t_roll / t_val3,
+            "rollout_decisions_per_s": n_trees / t_roll3,
+            "rollout_gpu_s_per_decision": t_roll3 / n_trees,
+            "rollout_agreement_with_sequential": float((best_roll3 == best_roll).float()
+                                                       .mean().item())},
         "rollout_phases": phases_roll,
+        "gpu_seconds_ratio_fastest": ratio,
         "targets": {"root_move_agreement": {"target": TARGET_AGREEMENT, "measured": agree,
                                             "met": agree >= TARGET_AGREEMENT},
                     "gpu_seconds_ratio": {"target": TARGET_SPEEDUP,
-                                          "measured": max(speedup, t_roll / t_val2),
-                                          "met": max(speedup, t_roll / t_val2) >= TARGET_SPEEDUP}},
+                                          "measured": ratio, "met": ratio >= TARGET_SPEEDUP,
+                                          "against_sequential_playout_search":
+                                              t_roll / t_val_best}},
         "value_mse_vs_4096_playouts": mse, "mse_noise_floor": floor,
         "timing": f"HIP events, median of {reps} launches after one warm-up",
         "training": train_info,

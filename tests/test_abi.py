@@ -160,9 +160,10 @@ def test_epoch_order_is_the_philox_stream(lib, orc):
 
 
 def test_search_autotune_argument_errors_without_device(lib):
-    """Value leaves, several leaves per pass in the reference, no trees or a
-    negative tolerance are refused before any device work; automatic shapes
-    (playouts per leaf and leaves per pass both 0) have a workspace size."""
+    """Value leaves, several leaves per pass or pipelined passes in the
+    reference, no trees or a negative tolerance are refused before any device
+    work; automatic shapes (playouts per leaf, leaves per pass and pipeline
+    all 0) have a workspace size, a pipelined one with no shape has none."""
     import paper_2403_10720_amd as D
     L = D.lib()
     vp = C.c_void_p
@@ -174,7 +175,10 @@ def test_search_autotune_argument_errors_without_device(lib):
     big = D.mcts_params(iterations=1 << 17, playouts_per_leaf=0, leaves_per_pass=0)
     assert L.dvc_mcts_workspace_bytes(4, C.byref(big)) == 0
     res = D.MctsTuning()
+    pipe_auto = D.mcts_params(iterations=64, playouts_per_leaf=0, leaves_per_pass=0, pipeline=1)
+    assert L.dvc_mcts_workspace_bytes(4, C.byref(pipe_auto)) == 0
     for mp, n, tol in [(D.mcts_params(iterations=64, playouts_per_leaf=8, leaves_per_pass=2), 4, 0.0),
+                       (D.mcts_params(iterations=64, playouts_per_leaf=8, pipeline=1), 4, 0.0),
                        (ok, 0, 0.0), (ok, 4, -0.1), (auto, 4, 0.0),
                        (D.mcts_params(iterations=64, playouts_per_leaf=8, leaf_eval=1), 4, 0.0)]:
         assert L.dvc_mcts_autotune(vp(16), n, C.byref(mp), 1, 0, vp(16), 1 << 30, tol, vp(16),

@@ -259,7 +259,7 @@ def test_root_parallel_argument_errors(dvc):
 
 
 # ---------------------------------------------------------------------------
-# search autotuner: playouts per leaf x leaves per pass
+# search autotuner: playouts per leaf x leaves per pass x pipelined passes
 # ---------------------------------------------------------------------------
 def test_search_autotune_and_automatic_shape(dvc):
     deal = dvc.deal_params(p_min=2, p_max=4, hand=(0, 0, 4, 4, 3), pile_min=0, pile_max=16,
@@ -279,10 +279,10 @@ def test_search_autotune_and_automatic_shape(dvc):
     cands = {(4, 1), (4, 2), (4, 4), (4, 8), (4, 16), (8, 1), (8, 2), (8, 4), (8, 8), (16, 1),
              (16, 2), (16, 4), (32, 1), (32, 2), (64, 1), (128, 1)}
     shape = (choice["playouts_per_leaf"], choice["leaves_per_pass"])
-    assert shape in cands, choice
+    assert shape in cands and choice["pipeline"] in (0, 1), choice
     assert choice["agreement"] + 0.05 >= choice["self_agreement"], choice
     chosen = dvc.mcts_params(iterations=128, playouts_per_leaf=shape[0], max_depth=4,
-                             leaves_per_pass=shape[1])
+                             leaves_per_pass=shape[1], pipeline=choice["pipeline"])
     # the returned decisions are the chosen shape's (candidates run under seed + 1)
     b, _ = dvc.mcts_search(roots, chosen, 10, want_children=False)
     assert torch.equal(b, dec)
@@ -296,3 +296,6 @@ def test_search_autotune_and_automatic_shape(dvc):
     with pytest.raises(dvc.DvcError):
         dvc.dvc_mcts_autotune(roots, dvc.mcts_params(iterations=128, playouts_per_leaf=32,
                                                      leaves_per_pass=2), 9)
+    with pytest.raises(dvc.DvcError):
+        dvc.dvc_mcts_autotune(roots, dvc.mcts_params(iterations=128, playouts_per_leaf=32,
+                                                     pipeline=1), 9)
