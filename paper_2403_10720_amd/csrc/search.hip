@@ -269,16 +269,36 @@ __device__ __forceinline__ uint32_t legal_values(const State &S, uint32_t k, con
     return ok ? x & 0xFFFu : 0u;
 }
 
+// The k-th lowest set bit of a 24-bit mask m (k < popcount(m)), with m and
+// k the same in every lane of the wavefront and every lane active: lane j <
+// 24 holds bit j and counts the set bits below it, one ballot finds the
+// lane.  The descent's state is the same in every lane, so its moves use
+// this instead of the per-lane table.  0 when m has no k-th bit.
+__device__ __forceinline__ uint32_t kth_bit_wave(uint32_t m, uint32_t k)
+{
+    const uint32_t lane = threadIdx.x & 63u;
+    const bool hit = lane < 32u && ((m >> (lane & 31u)) & 1u) != 0u &&
+                     __builtin_amdgcn_mbcnt_lo(m, 0u) == k;
+    const uint64_t b = __ballot(hit);
+    return b ? (uint32_t)__builtin_ctzll(b) : 0u;
+}
+
+// a uniformly drawn set bit of m (word w), as kth_bit_wave
+__device__ __forceinline__ uint32_t pick_bit_wave(uint32_t m, uint32_t w)
+{
+    return kth_bit_wave(m, pick(w, (uint32_t)__popc(m)));
+}
+
 // The turn passes: the next seat with hidden tiles becomes the mover and
-// draws with word w1 (if the pool is not empty).
-__device__ __forceinline__ void end_turn(State &S, uint32_t alive, uint32_t w1, const uint8_t *tab)
+// draws with word w1 (if the pool is not empty).  Wave-uniform state.
+__device__ __forceinline__ void end_turn(State &S, uint32_t alive, uint32_t w1)
 {
     S.m = next_alive(alive, S.m, S.P);
     S.phase = 1u;
     S.drawn = -1;
     const uint32_t pool = ~(S.h0 | S.h1 | S.h2 | S.h3) & kAll;
     if (pool) {
-        const uint32_t d = pick_bit_tab(pool, w1, tab);
+        const uint32_t d = pick_bit_wave(pool, w1);
         add_to_hand(S, S.m, 1u << d);
         S.drawn = (int32_t)d;
     }
@@ -305,11 +325,11 @@ __device__ __forceinline__ Words chance_at(const Words &cw, uint32_t depth)
 // mover, still holding the drawn tile hidden, decides again.  Returns true
 // if the game ended.
 __device__ __forceinline__ bool apply_action(State &S, uint32_t key, bool cont_mode, const Words &w,
-                                             uint32_t &winner, bool &cont, const uint8_t *tab)
+                                             uint32_t &winner, bool &cont)
 {
     cont = false;
     if (key == kStopKey) {
-        end_turn(S, alive_mask(S), w.w1, tab);
+        end_turn(S, alive_mask(S), w.w1);
         return false;
     }
     const uint32_t action = key > kStopKey ? key - kStopKey - 1u : key;
@@ -318,10 +338,10 @@ __device__ __forceinline__ bool apply_action(State &S, uint32_t key, bool cont_m
     const uint32_t v = action % 12u;
     const uint32_t q = S.m + r >= S.P ? S.m + r - S.P : S.m + r;
     const uint32_t row = hand_of(S, q);
-    const uint32_t t = kth_bit_tab(row, slot, tab);
+    const uint32_t t = kth_bit_wave(row, slot);
     const bool right = 2u * v + (t & 1u) == t;
     const uint32_t hm = hand_of(S, S.m);
-    const uint32_t own = pick_bit_tab(hm & ~S.rev, w.w0, tab);
+    const uint32_t own = pick_bit_wave(hm & ~S.rev, w.w0);
     const uint32_t wrong_bit = 1u << (S.drawn >= 0 ? (uint32_t)S.drawn : own);
     S.rev |= right ? (1u << t) : wrong_bit;
     const uint32_t alive = alive_mask(S);
@@ -335,7 +355,7 @@ __device__ __forceinline__ bool apply_action(State &S, uint32_t key, bool cont_m
         cont = true;
         return false;
     }
-    end_turn(S, alive, w.w1, tab);
+    end_turn(S, alive, w.w1);
     return false;
 }
 
@@ -343,9 +363,9 @@ __device__ __forceinline__ bool apply_action(State &S, uint32_t key, bool cont_m
 // policy's continue coin, w3 of that guess's chance block w, decides once for
 // all the leaf's playouts -- below 2^31 the mover goes on guessing, else the
 // turn passes (w1 draws).
-__device__ __forceinline__ void leaf_continue_coin(State &S, const Words &w, const uint8_t *tab)
+__device__ __forceinline__ void leaf_continue_coin(State &S, const Words &w)
 {
-    if (w.w3 >= 0x80000000u) end_turn(S, alive_mask(S), w.w1, tab);
+    if (w.w3 >= 0x80000000u) end_turn(S, alive_mask(S), w.w1);
 }
 
 // The sampled world as a 48-bit key (lo: tiles 0-15, hi: tiles 16-23), 2 bits
@@ -493,7 +513,7 @@ template <bool VALUE, bool PIPE> struct TreeGroup {
 // descends and backs up, wavefront 1 evaluates.
 template <bool VALUE, bool PIPE>
 __global__ void __launch_bounds__((64 * TreeGroup<VALUE, PIPE>::kWaves))
-__attribute__((amdgpu_waves_per_eu(PIPE ? 2 : 1, VALUE ? (PIPE ? 2 : 1) : 8)))
+__attribute__((amdgpu_waves_per_eu(VALUE ? (PIPE ? 2 : 1) : 4, VALUE ? (PIPE ? 2 : 1) : 8)))
 mcts_tree_kernel(MctsArgs a)
 {
     constexpr uint32_t TG = TreeGroup<VALUE, PIPE>::kTrees;
@@ -511,6 +531,7 @@ mcts_tree_kernel(MctsArgs a)
     __shared__ uint32_t wins_all[TG][4u * BM];
     __shared__ float vals_all[TG][NBUF][BM][4];
     __shared__ DfsSlots dfs_all[TG];
+    __shared__ uint4 fb_rows[TG];   // rows of the sampler's fallback world
     __shared__ __attribute__((aligned(16))) uint16_t w2_lds[(VALUE && !PIPE) ? kVnH * kVnH : 8];
     __shared__ __attribute__((aligned(16))) uint16_t hs_pipe[(VALUE && PIPE) ? 16 : 1][kVnH + 8];
     __shared__ VnSmall vn_small[1];
@@ -569,7 +590,6 @@ mcts_tree_kernel(MctsArgs a)
     uint32_t n_nodes = 1u, n_ovf = 0u, n_root = 0u;
     uint32_t n_net = 0u, n_played = 0u, n_sampler_fallback = 0u, deepest = 0u;   // statistics
     bool failed = false, have_fallback = false;
-    State fallback = R;
     uint64_t cyc[4] = {0u, 0u, 0u, 0u};   // shader clock per phase (statistics)
     // Worlds of iterations ib .. ib + 63 by attempt 0, sampled together (lane
     // l: iteration ib + l) at every 64th iteration: the world's rows as owner
@@ -578,6 +598,34 @@ mcts_tree_kernel(MctsArgs a)
     // successful attempt is the same one either way.
     uint32_t wpl0 = 0u, wpl1 = 0u, wpl2 = 0u;
     uint64_t wok = 0u;
+    // The root's first two child blocks (lane l: children l and 64 + l), its
+    // guess bitmap words (laid out as the descent loads them), child count
+    // and next two block ids, kept in registers: the wavefront that owns the
+    // tree makes every change to them, to memory and here at the same points,
+    // so the root level of a descent issues no loads.  Not for vanilla trees,
+    // whose root children are worlds.
+    const bool rc_on = !a.vanilla;
+    uint4 rc_e0 = make_uint4(0u, 0u, 0u, 0u), rc_e1 = make_uint4(0u, 0u, 0u, 0u);
+    uint32_t rc_cb0 = 0u, rc_cb1 = 0u, rc_nc = 0u, rc_nx0 = kNoBlock, rc_nx1 = kNoBlock;
+    // root child slot (0 .. 127, else not cached) of the entry at word offset e
+    auto rc_slot = [&](uint32_t e) -> uint32_t {
+        const uint32_t b0 = block_off(0u);
+        if (e - b0 < kBlockWords) return (e - b0) / kEntryWords;
+        if (rc_nx0 != kNoBlock && e - block_off(rc_nx0) < kBlockWords)
+            return kBlockEntries + (e - block_off(rc_nx0)) / kEntryWords;
+        return 0xFFFFFFFFu;
+    };
+    // visits dn for cached slot `slot`; its W word set to wbits when set_w
+    auto rc_update = [&](uint32_t slot, uint32_t dn, bool set_w, uint32_t wbits) {
+        if (slot == lane) {
+            rc_e0.y += dn;
+            if (set_w) rc_e0.z = wbits;
+        }
+        if (slot == kBlockEntries + lane) {
+            rc_e1.y += dn;
+            if (set_w) rc_e1.z = wbits;
+        }
+    };
     tree_sync<WS>();
 
     // Iterations run in passes of B = leaves_per_pass: each descent of a pass
@@ -709,16 +757,21 @@ mcts_tree_kernel(MctsArgs a)
     auto backprop_pass = [&](uint32_t buf, uint32_t nb) {
         for (uint32_t b = 0; b < nb; ++b) {
             const uint32_t npb = np_all[wv][buf][b];
+            uint32_t e = 0u, nw = 0u;
             if (lane < npb && !(a.vanilla && lane == 0u)) {   // a world node's W word holds its key
-                const uint32_t e = path_all[wv][buf][b][lane];
+                e = path_all[wv][buf][b][lane];
                 // the chooser's value by a computed index: a chain of selects
                 // over the four LDS entries was compiled into branches that
                 // left seat 3's lanes reading seat 2's entry
                 const uint4 en = *reinterpret_cast<const uint4 *>(W + e);
                 const uint32_t chooser = (en.x >> 16) & 3u;
                 const float wc = vals_all[wv][buf][b][chooser];
-                W[e + 2u] = __float_as_uint(__uint_as_float(en.z) + wc);
+                nw = __float_as_uint(__uint_as_float(en.z) + wc);
+                W[e + 2u] = nw;
             }
+            if (rc_on && npb > 0u)   // lane 0 holds the root child's entry
+                rc_update(rc_slot(__builtin_amdgcn_readlane(e, 0)), 0u, true,
+                          __builtin_amdgcn_readlane(nw, 0));
             tree_sync<WS>();
         }
 
@@ -789,6 +842,7 @@ mcts_tree_kernel(MctsArgs a)
             }
             if (!((wok >> wl) & 1u) && !okm) {
                 // the fallback world depends on the root only: search it once
+                // (it differs from the root in its rows only; they are kept in LDS)
                 if (!have_fallback) {
                     State F = R;
                     bool fok = false;
@@ -799,10 +853,16 @@ mcts_tree_kernel(MctsArgs a)
                         failed = true;
                         break;
                     }
-                    fallback = readlane_state(F, 0u);
+                    if (lane == 0) fb_rows[wv] = make_uint4(F.h0, F.h1, F.h2, F.h3);
                     have_fallback = true;
+                    tree_sync<WS>();
                 }
-                S = fallback;
+                const uint4 fr = fb_rows[wv];
+                S = R;
+                S.h0 = fr.x;
+                S.h1 = fr.y;
+                S.h2 = fr.z;
+                S.h3 = fr.w;
                 ++n_sampler_fallback;
             }
 
@@ -877,16 +937,31 @@ mcts_tree_kernel(MctsArgs a)
                 // one round of loads: bitmaps, child count, first 64 children, LN
                 const uint32_t rec = rec_off(node);
                 const uint32_t half = cont ? 36u : 0u;
-                const uint32_t cbw0 = W[rec + 4u + half + (lane >> 1)];
-                const uint32_t cbw1 = lane < 8u ? W[rec + 36u + half + (lane >> 1)]
-                                                : lane == 8u ? W[rec + 3u] : 0u;
-                const uint32_t nchild_v = W[rec + 2u];
-                const uint4 ent0 = *reinterpret_cast<const uint4 *>(W + rec + node_words + lane * kEntryWords);
-                const uint32_t next0_v = bnext[node];   // the second child block, if any
+                // the root (a turn start: no continue choice there) from registers
+                const bool at_root = rc_on && node == 0u;
+                uint32_t cbw0, cbw1, nchild_v, next0_v;
+                uint4 ent0;
+                if (at_root) {
+                    cbw0 = rc_cb0;
+                    cbw1 = rc_cb1;
+                    nchild_v = rc_nc;
+                    ent0 = rc_e0;
+                    next0_v = rc_nx0;
+                } else {
+                    cbw0 = W[rec + 4u + half + (lane >> 1)];
+                    cbw1 = lane < 8u ? W[rec + 36u + half + (lane >> 1)] : lane == 8u ? W[rec + 3u] : 0u;
+                    nchild_v = W[rec + 2u];
+                    ent0 = *reinterpret_cast<const uint4 *>(W + rec + node_words + lane * kEntryWords);
+                    next0_v = bnext[node];   // the second child block, if any
+                }
                 const float lp = a.ln[node_n];
                 const uint32_t l0 = legal_values(S, lane, tab);
-                const uint32_t l1 = lane < 8u ? legal_values(S, 64u + lane, tab)
-                                              : (lane == 8u && cont) ? 1u : 0u;
+                // pairs 64-71 are slots 16-23 of the third opponent: only a
+                // four-player game with a row of 17 tiles or more has them
+                uint32_t l1 = (lane == 8u && cont) ? 1u : 0u;
+                const bool wide = S.P == 4u && __popc(hand_of(S, (S.m + 3u) & 3u)) > 16;
+                if (__builtin_amdgcn_readfirstlane((uint32_t)wide) != 0u && lane < 8u)
+                    l1 = legal_values(S, 64u + lane, tab);
                 legal_s[lane] = l0;
                 if (lane < 9u) legal_s[64u + lane] = l1;
                 const uint32_t cb0 = (cbw0 >> ((lane & 1u) * 16u)) & 0xFFFu;
@@ -928,12 +1003,23 @@ mcts_tree_kernel(MctsArgs a)
                                          : __builtin_amdgcn_readlane(cbw1, pair - 64u);
                     }
                     uint32_t e;
-                    append_child(node, nchild, key | (S.m << 16), 0u, e);
+                    const uint32_t c = append_child(node, nchild, key | (S.m << 16), 0u, e);
                     if (lane == 0) W[rec + word] = old | bit;
+                    if (at_root) {
+                        const uint4 ne = make_uint4(key | (S.m << 16), 0u, 0u, c);
+                        if (nchild == lane) rc_e0 = ne;
+                        if (nchild == kBlockEntries + lane) rc_e1 = ne;
+                        // a new overflow block starts at child 64 and at child 128
+                        if (nchild == kBlockEntries) rc_nx0 = nodes_cap + n_ovf - 1u;
+                        if (nchild == 2u * kBlockEntries) rc_nx1 = nodes_cap + n_ovf - 1u;
+                        rc_nc = nchild + 1u;
+                        if (4u + (lane >> 1) == word) rc_cb0 |= bit;
+                        if ((lane < 8u ? 36u + (lane >> 1) : lane == 8u ? 3u : 0u) == word) rc_cb1 |= bit;
+                    }
                     path_e[np++] = e;
                     last_block = depth;
                     term = apply_action(S, key, a.cont_mode != 0u, chance_at(cw, depth), winner,
-                                        cont, tab);
+                                        cont);
                     tree_sync<WS>();
                     break;
                 }
@@ -949,9 +1035,14 @@ mcts_tree_kernel(MctsArgs a)
                     uint4 ent_n = ent;
                     uint32_t nxt_n = kNoBlock;
                     if (more) {
-                        ent_n = *reinterpret_cast<const uint4 *>(W + block_off(nxt) + lane * kEntryWords);
-                        if (base + 2u * kBlockEntries < nchild)
-                            nxt_n = __builtin_amdgcn_readfirstlane(bnext[nxt]);
+                        if (at_root && base == 0u) {
+                            ent_n = rc_e1;
+                            nxt_n = rc_nx1;
+                        } else {
+                            ent_n = *reinterpret_cast<const uint4 *>(W + block_off(nxt) + lane * kEntryWords);
+                            if (base + 2u * kBlockEntries < nchild)
+                                nxt_n = __builtin_amdgcn_readfirstlane(bnext[nxt]);
+                        }
                     }
                     // straight-line scoring: every lane computes a score (a
                     // lane past the children reads some entry: its pair index
@@ -992,11 +1083,11 @@ mcts_tree_kernel(MctsArgs a)
                 path_e[np++] = best_e;
                 last_block = depth;
                 term = apply_action(S, best_act, a.cont_mode != 0u, chance_at(cw, depth), winner,
-                                    cont, tab);
+                                    cont);
                 ++depth;
                 tree_sync<WS>();
             }
-            if (!term && cont) leaf_continue_coin(S, chance_at(cw, last_block), tab);
+            if (!term && cont) leaf_continue_coin(S, chance_at(cw, last_block));
             deepest = np - a.vanilla > deepest ? np - a.vanilla : deepest;
             cyc[1] += clock64() - t1;
             if (!PIPE && a.lpp == 1u) {
@@ -1085,17 +1176,22 @@ mcts_tree_kernel(MctsArgs a)
                 cyc[2] += t3 - t2;
                 // ---- 4. back-propagation --------------------------------------------
                 n_root += nplay;
+                uint32_t e = 0u, nw = 0u;
                 if (lane < np) {
                     // the entry {key | chooser << 16, N, W, id} in one load
-                    const uint32_t e = path_e[lane];
+                    e = path_e[lane];
                     const uint4 en = *reinterpret_cast<const uint4 *>(W + e);
                     W[e + 1u] = en.y + nplay;
                     if (!(a.vanilla && lane == 0u)) {   // a world node's W word holds its key
                         const uint32_t chooser = en.x >> 16;
                         const float wc = chooser == 0u ? vals[0] : chooser == 1u ? vals[1] : chooser == 2u ? vals[2] : vals[3];
-                        W[e + 2u] = __float_as_uint(__uint_as_float(en.z) + wc);
+                        nw = __float_as_uint(__uint_as_float(en.z) + wc);
+                        W[e + 2u] = nw;
                     }
                 }
+                if (rc_on && np > 0u)   // lane 0 holds the root child's entry
+                    rc_update(rc_slot(__builtin_amdgcn_readlane(e, 0)), nplay, true,
+                              __builtin_amdgcn_readlane(nw, 0));
                 tree_sync<WS>();
                 cyc[3] += clock64() - t3;
                 continue;
@@ -1112,6 +1208,7 @@ mcts_tree_kernel(MctsArgs a)
             // visit counts at once
             n_root += nplay;
             if (lane < np) W[path_e[lane] + 1u] += nplay;
+            if (rc_on && np > 0u) rc_update(rc_slot(path_e[0]), nplay, false, 0u);
             tree_sync<WS>();
         }
         if (PIPE) {

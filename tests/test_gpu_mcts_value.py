@@ -8,7 +8,9 @@ root's children check credit to other players than the searching one
 (Sec. II-B: the results weight the nodes on the path).
 
 * playout leaves: mixed 2/3/4-player roots, depth thresholds 3 and 4 and none,
-  with the continue choice, one and four leaves per pass;
+  with the continue choice, one and four leaves per pass; roots with more
+  than 128 legal guesses (three blocks of root children); a four-player root
+  whose third opponent holds 17 tiles (guesses of pairs 64-71);
 * value leaves (the learned evaluator with its playout fallback) with the
   integer network of ``exact_net``, whose outputs 0, 1/2 and 1 are exact in
   any summation order, so the search's own rules are compared without
@@ -22,6 +24,7 @@ import pytest
 
 import exact_net
 import gpu_tree
+import positions as POS
 
 torch = pytest.importorskip("torch")
 
@@ -71,6 +74,40 @@ def test_playout_trees_node_by_node(orc, dvc, dmax, cont, lpp):
     kw = dict(iterations=300, playouts_per_leaf=8, max_depth=dmax, continue_choice=cont,
               leaves_per_pass=lpp)
     _, deep = _search_and_compare(orc, dvc, roots, orc.mcts_params(**kw), dvc.mcts_params(**kw), 13)
+    assert deep > 200
+
+
+# roots of the batched workload (2048 mixed mid-game roots, seed 3) with more
+# than 128 legal guesses: the root's children fill three child blocks
+WIDE_ROOTS = [392, 910, 1214, 1269, 1571, 1827, 1863, 1899]
+
+
+@pytest.mark.parametrize("lpp,pipe", [(1, 0), (2, 1)])
+def test_wide_roots_node_by_node(orc, dvc, lpp, pipe):
+    roots = _roots(orc, 2048, 3, pile_max=16, revealed_max=8)[WIDE_ROOTS]
+    assert min(int(orc.legal_actions(r).sum()) for r in roots) > 128
+    kw = dict(iterations=400, playouts_per_leaf=8, max_depth=4, leaves_per_pass=lpp, pipeline=pipe)
+    _, deep = _search_and_compare(orc, dvc, roots, orc.mcts_params(**kw), dvc.mcts_params(**kw), 3)
+    assert deep > 200
+
+
+def _long_row_root():
+    """Four players, the mover's third opponent holding 17 tiles (its slot 16
+    hidden: guesses of pairs 64-71), after the mover's draw, empty pool."""
+    owner = [3] * 17 + [0, 1, 2, 0, 1, 2, 0]
+    hidden = {3, 5, 8, 11, 14, 16, 17, 20, 21, 22}
+    return POS.pack({"P": 4, "owner": owner, "revealed": set(range(24)) - hidden, "mover": 0,
+                     "phase": 1, "drawn": 20})
+
+
+@pytest.mark.parametrize("lpp,pipe", [(1, 0), (2, 1)])
+def test_long_row_root_node_by_node(orc, dvc, lpp, pipe):
+    root = _long_row_root()
+    legal = np.nonzero(orc.legal_actions(root))[0]
+    assert any(a // 12 >= 64 for a in legal)
+    roots = np.stack([root, root])
+    kw = dict(iterations=300, playouts_per_leaf=8, max_depth=4, leaves_per_pass=lpp, pipeline=pipe)
+    _, deep = _search_and_compare(orc, dvc, roots, orc.mcts_params(**kw), dvc.mcts_params(**kw), 5)
     assert deep > 200
 
 
