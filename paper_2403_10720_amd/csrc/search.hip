@@ -521,6 +521,10 @@ mcts_tree_kernel(MctsArgs a)
     // a tree's wavefront orders its own memory accesses with wavefront
     // barriers when it shares the workgroup with other wavefronts
     constexpr bool WS = VALUE || PIPE;
+    // pipelined passes with network leaves: the evaluating wavefront, which
+    // has time to spare, also samples the worlds (with playout leaves it has
+    // none)
+    constexpr bool ESAMPLE = PIPE && VALUE;
     __shared__ uint8_t tab[kKthTableBytes];
     __shared__ uint32_t legal_all[TG][73];
     constexpr uint32_t BM = TreeGroup<VALUE, PIPE>::kPass;
@@ -532,12 +536,17 @@ mcts_tree_kernel(MctsArgs a)
     __shared__ float vals_all[TG][NBUF][BM][4];
     __shared__ DfsSlots dfs_all[TG];
     __shared__ uint4 fb_rows[TG];   // rows of the sampler's fallback world
+    // worlds of a pass sampled by the evaluating wavefront (rows; flag 1:
+    // the sampler gave up)
+    __shared__ uint4 wrows_all[ESAMPLE ? 2 : 1][ESAMPLE ? BM : 1];
+    __shared__ uint32_t wflag_all[ESAMPLE ? 2 : 1][ESAMPLE ? BM : 1];
     __shared__ __attribute__((aligned(16))) uint16_t w2_lds[(VALUE && !PIPE) ? kVnH * kVnH : 8];
     __shared__ __attribute__((aligned(16))) uint16_t hs_pipe[(VALUE && PIPE) ? 16 : 1][kVnH + 8];
     __shared__ VnSmall vn_small[1];
     // pipelined passes: [0] the step + 1 at which the descending wavefront
-    // gave up (0: it did not); [1..4] the evaluating wavefront's network /
-    // played-out leaves and evaluation cycles
+    // gave up (0: it did not); [1..7] the evaluating wavefront's statistics:
+    // network / played-out leaves, evaluation cycles, sampler fallbacks,
+    // sampling cycles
     __shared__ uint32_t pipe_x[8];
     fill_kth_table(tab);
     if (VALUE) {
@@ -605,6 +614,16 @@ mcts_tree_kernel(MctsArgs a)
     // so the root level of a descent issues no loads.  Not for vanilla trees,
     // whose root children are worlds.
     const bool rc_on = !a.vanilla;
+    // The root's legal guesses, the same in every sampled world: a guess
+    // names an opponent's row slot and a value; which slots are hidden, their
+    // colours, the revealed tiles around them and the mover's own tiles are
+    // what the searching player sees, and the sampler keeps them all.
+    const uint32_t rc_l0 = legal_values(R, lane, tab);
+    uint32_t rc_l1 = 0u;
+    if (__builtin_amdgcn_readfirstlane(
+            (uint32_t)(R.P == 4u && __popc(hand_of(R, (R.m + 3u) & 3u)) > 16)) != 0u &&
+        lane < 8u)
+        rc_l1 = legal_values(R, 64u + lane, tab);
     uint4 rc_e0 = make_uint4(0u, 0u, 0u, 0u), rc_e1 = make_uint4(0u, 0u, 0u, 0u);
     uint32_t rc_cb0 = 0u, rc_cb1 = 0u, rc_nc = 0u, rc_nx0 = kNoBlock, rc_nx1 = kNoBlock;
     // root child slot (0 .. 127, else not cached) of the entry at word offset e
@@ -635,6 +654,64 @@ mcts_tree_kernel(MctsArgs a)
     // into the rows of one matrix tile -- and each path gets its wins, in
     // iteration order.  B = 1 is the plain sequential search.
     const uint32_t nplay = VALUE ? a.fb_ppl : a.ppl;   // visits of every leaf
+    // ---- 1. sample the world of iteration `it`: its lowest successful
+    // attempt.  Worlds of iterations ib .. ib + 63 by attempt 0 are sampled
+    // together at every 64th iteration; an iteration whose attempt 0 failed
+    // runs all 64 attempts on its own (the lowest successful one is the same
+    // either way), and one with none left takes the fallback world.  Returns
+    // false when the fallback search gives up.
+    auto sample_world = [&](uint32_t it, State &S) -> bool {
+        if ((it & 63u) == 0u) {
+            State Sw;
+            const bool got0 = det_attempt(R, 0u, it + lane, tr, a.k0, a.k1, Sw, tab);
+            wok = __ballot(got0 && it + lane < a.iters);
+            wpl0 = Sw.h0 | Sw.h2;
+            wpl1 = Sw.h1 | Sw.h2;
+            wpl2 = Sw.h3;
+        }
+        const uint32_t wl = it & 63u;
+        if ((wok >> wl) & 1u) {
+            S = R;
+            const uint32_t p0 = __builtin_amdgcn_readlane(wpl0, wl);
+            const uint32_t p1 = __builtin_amdgcn_readlane(wpl1, wl);
+            const uint32_t p2 = __builtin_amdgcn_readlane(wpl2, wl);
+            S.h0 = p0 & ~p1 & ~p2;
+            S.h1 = ~p0 & p1 & ~p2 & kAll;
+            S.h2 = p0 & p1 & ~p2;
+            S.h3 = p2;
+            return true;
+        }
+        // attempt `lane` of this iteration (attempt 0 fails again)
+        const bool got = det_attempt(R, lane, it, tr, a.k0, a.k1, S, tab);
+        const uint64_t okm = __ballot(got);
+        if (okm) {
+            S = readlane_state(S, (uint32_t)__builtin_ctzll(okm));
+            return true;
+        }
+        // the fallback world depends on the root only: search it once (it
+        // differs from the root in its rows only; they are kept in LDS)
+        if (!have_fallback) {
+            State F = R;
+            bool fok = false;
+            if (lane == 0) fok = det_fallback(R, F, dfs_slots);
+            fok = __builtin_amdgcn_readfirstlane((uint32_t)fok) != 0u;
+            if (!fok) {
+                if (lane == 0) atomicOr(&g_error_word, kErrLimit);
+                return false;
+            }
+            if (lane == 0) fb_rows[wv] = make_uint4(F.h0, F.h1, F.h2, F.h3);
+            have_fallback = true;
+            tree_sync<WS>();
+        }
+        const uint4 fr = fb_rows[wv];
+        S = R;
+        S.h0 = fr.x;
+        S.h1 = fr.y;
+        S.h2 = fr.z;
+        S.h3 = fr.w;
+        ++n_sampler_fallback;
+        return true;
+    };
     // ---- 3. evaluate a pass's leaves (pass buffer buf, iterations i0 ..
     // i0 + nb - 1): playouts packed into the 64 lanes, or network rows; the
     // decided leaves get their winner's share.  Results in vals_all[wv][buf].
@@ -783,6 +860,29 @@ mcts_tree_kernel(MctsArgs a)
     // both stop at the step where the descending wavefront gave up).
     const uint32_t n_pass = (a.iters + a.lpp - 1u) / a.lpp;
     if (PIPE && role == 1u) {
+        // the worlds of pass kp into world buffer kp & 1 (in iteration
+        // order); after a world the sampler gave up on, none
+        bool gave_up = false;
+        auto sample_pass = [&](uint32_t kp) {
+            if (!ESAMPLE || kp >= n_pass || gave_up) return;
+            const uint32_t ip = kp * a.lpp, nbp = a.iters - ip < a.lpp ? a.iters - ip : a.lpp;
+            const uint64_t t0 = clock64();
+            for (uint32_t b = 0; b < nbp; ++b) {
+                State Sw;
+                const bool ok = sample_world(ip + b, Sw);
+                if (lane == 0) {
+                    wrows_all[kp & 1u][b] = make_uint4(Sw.h0, Sw.h1, Sw.h2, Sw.h3);
+                    wflag_all[kp & 1u][b] = ok ? 0u : 1u;
+                }
+                if (!ok) {
+                    gave_up = true;
+                    break;
+                }
+            }
+            cyc[0] += clock64() - t0;
+        };
+        sample_pass(0u);
+        __syncthreads();   // the first pass's worlds
         for (uint32_t k = 0; k <= n_pass; ++k) {
             if (k >= 1u) {
                 const uint32_t ip = (k - 1u) * a.lpp, buf = (k - 1u) & 1u;
@@ -791,6 +891,7 @@ mcts_tree_kernel(MctsArgs a)
                           meta_all[wv][buf][0], meta_all[wv][buf][1]);
                 cyc[2] += clock64() - t2;
             }
+            sample_pass(k + 1u);
             __syncthreads();
             if (pipe_x[0] == k + 1u) break;
         }
@@ -799,10 +900,14 @@ mcts_tree_kernel(MctsArgs a)
             pipe_x[2] = n_played;
             pipe_x[3] = (uint32_t)cyc[2];
             pipe_x[4] = (uint32_t)(cyc[2] >> 32);
+            pipe_x[5] = n_sampler_fallback;
+            pipe_x[6] = (uint32_t)cyc[0];
+            pipe_x[7] = (uint32_t)(cyc[0] >> 32);
         }
         __syncthreads();
         return;
     }
+    if (PIPE) __syncthreads();   // the first pass's worlds
     for (uint32_t k = 0; k < n_pass + (PIPE ? 1u : 0u); ++k) {
         const uint32_t buf = PIPE ? (k & 1u) : 0u;
         const uint32_t i0 = k * a.lpp;
@@ -813,59 +918,24 @@ mcts_tree_kernel(MctsArgs a)
             const uint32_t it = i0 + b;
             uint32_t *path_e = path_all[wv][buf][b];
             const uint64_t t0 = clock64();
-            // ---- 1. sample a world: the lowest successful attempt ------------
-            if ((it & 63u) == 0u) {
-                State Sw;
-                const bool got0 = det_attempt(R, 0u, it + lane, tr, a.k0, a.k1, Sw, tab);
-                wok = __ballot(got0 && it + lane < a.iters);
-                wpl0 = Sw.h0 | Sw.h2;
-                wpl1 = Sw.h1 | Sw.h2;
-                wpl2 = Sw.h3;
-            }
+            // ---- 1. the iteration's world: sampled here, or (pipelined
+            // passes with network leaves) by the other wavefront one step ahead
             State S;
-            const uint32_t wl = it & 63u;
-            uint64_t okm = 0u;
-            if ((wok >> wl) & 1u) {
-                S = R;
-                const uint32_t p0 = __builtin_amdgcn_readlane(wpl0, wl);
-                const uint32_t p1 = __builtin_amdgcn_readlane(wpl1, wl);
-                const uint32_t p2 = __builtin_amdgcn_readlane(wpl2, wl);
-                S.h0 = p0 & ~p1 & ~p2;
-                S.h1 = ~p0 & p1 & ~p2 & kAll;
-                S.h2 = p0 & p1 & ~p2;
-                S.h3 = p2;
-            } else {
-                // attempt `lane` of this iteration (attempt 0 fails again)
-                const bool got = det_attempt(R, lane, it, tr, a.k0, a.k1, S, tab);
-                okm = __ballot(got);
-                if (okm) S = readlane_state(S, (uint32_t)__builtin_ctzll(okm));
-            }
-            if (!((wok >> wl) & 1u) && !okm) {
-                // the fallback world depends on the root only: search it once
-                // (it differs from the root in its rows only; they are kept in LDS)
-                if (!have_fallback) {
-                    State F = R;
-                    bool fok = false;
-                    if (lane == 0) fok = det_fallback(R, F, dfs_slots);
-                    fok = __builtin_amdgcn_readfirstlane((uint32_t)fok) != 0u;
-                    if (!fok) {
-                        if (lane == 0) atomicOr(&g_error_word, kErrLimit);
-                        failed = true;
-                        break;
-                    }
-                    if (lane == 0) fb_rows[wv] = make_uint4(F.h0, F.h1, F.h2, F.h3);
-                    have_fallback = true;
-                    tree_sync<WS>();
+            if (ESAMPLE) {
+                const uint4 wr = wrows_all[buf][b];
+                if (wflag_all[buf][b] != 0u) {
+                    failed = true;
+                    break;
                 }
-                const uint4 fr = fb_rows[wv];
                 S = R;
-                S.h0 = fr.x;
-                S.h1 = fr.y;
-                S.h2 = fr.z;
-                S.h3 = fr.w;
-                ++n_sampler_fallback;
+                S.h0 = wr.x;
+                S.h1 = wr.y;
+                S.h2 = wr.z;
+                S.h3 = wr.w;
+            } else if (!sample_world(it, S)) {
+                failed = true;
+                break;
             }
-
             const uint64_t t1 = clock64();
             cyc[0] += t1 - t0;
             // ---- 2. descend ----------------------------------------------------
@@ -955,13 +1025,19 @@ mcts_tree_kernel(MctsArgs a)
                     next0_v = bnext[node];   // the second child block, if any
                 }
                 const float lp = a.ln[node_n];
-                const uint32_t l0 = legal_values(S, lane, tab);
-                // pairs 64-71 are slots 16-23 of the third opponent: only a
-                // four-player game with a row of 17 tiles or more has them
-                uint32_t l1 = (lane == 8u && cont) ? 1u : 0u;
-                const bool wide = S.P == 4u && __popc(hand_of(S, (S.m + 3u) & 3u)) > 16;
-                if (__builtin_amdgcn_readfirstlane((uint32_t)wide) != 0u && lane < 8u)
-                    l1 = legal_values(S, 64u + lane, tab);
+                uint32_t l0, l1;
+                if (at_root) {
+                    l0 = rc_l0;
+                    l1 = rc_l1;
+                } else {
+                    l0 = legal_values(S, lane, tab);
+                    // pairs 64-71 are slots 16-23 of the third opponent: only
+                    // a four-player game with a row of 17 tiles or more has them
+                    l1 = (lane == 8u && cont) ? 1u : 0u;
+                    const bool wide = S.P == 4u && __popc(hand_of(S, (S.m + 3u) & 3u)) > 16;
+                    if (__builtin_amdgcn_readfirstlane((uint32_t)wide) != 0u && lane < 8u)
+                        l1 = legal_values(S, 64u + lane, tab);
+                }
                 legal_s[lane] = l0;
                 if (lane < 9u) legal_s[64u + lane] = l1;
                 const uint32_t cb0 = (cbw0 >> ((lane & 1u) * 16u)) & 0xFFFu;
@@ -1245,6 +1321,8 @@ mcts_tree_kernel(MctsArgs a)
         n_net = pipe_x[1];
         n_played = pipe_x[2];
         cyc[2] = (uint64_t)pipe_x[3] | ((uint64_t)pipe_x[4] << 32);
+        n_sampler_fallback += pipe_x[5];   // counted by whichever wavefront samples
+        cyc[0] += (uint64_t)pipe_x[6] | ((uint64_t)pipe_x[7] << 32);
     }
 
     // ---- decision and root statistics ----------------------------------------

@@ -338,6 +338,26 @@ __device__ __forceinline__ void vn_stage_small(const VnPtrs &P, VnSmall &sm)
     if (threadIdx.x == 0) sm.b3 = P.master[kOffB3];
 }
 
+// 16 bytes at byte offset voff + soff of the buffer `rs` (voff per lane,
+// soff the same in every lane): one lane-offset register serves every weight
+// fragment request, and requests past the buffer's end read zeros
+__device__ __forceinline__ bf16x8 buf_load8(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff)
+{
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    const u32x4 u = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, 0);
+    bf16x8 x;
+    __builtin_memcpy(&x, &u, 16);
+    return x;
+}
+
+// raw buffer resource over `bytes` bytes at p (dword 3: 32-bit data format,
+// the gfx9 value)
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t weight_rsrc(const uint16_t *p, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t *>(p), (short)0, (int)bytes,
+                                             0x00020000);
+}
+
 // orders LDS accesses between the lanes of one wavefront
 __device__ __forceinline__ void wave_lds_sync()
 {
@@ -364,7 +384,9 @@ __device__ __forceinline__ void vn_eval16_wave(const VnPtrs &P, const RowFeat &r
 {
     const uint32_t lane = threadIdx.x & 63u, r = lane & 15u, g = lane >> 4;
     constexpr uint32_t D1 = 4u, D2 = 3u;
-    const uint16_t *w1 = P.w1b + lane * 8u, *w2 = P.w2b + lane * 8u;
+    const __amdgpu_buffer_rsrc_t w1 = weight_rsrc(P.w1b, kVnIn * kVnH * 2u);
+    const __amdgpu_buffer_rsrc_t w2 = weight_rsrc(P.w2b, kVnH * kVnH * 2u);
+    const uint32_t voff = lane * 16u;   // fragment j of a weight block: byte 1024 j + 16 lane
     bf16x8 xa[5];
 #pragma unroll
     for (uint32_t s = 0; s < 5u; ++s) xa[s] = feature8(rf, s, g);
@@ -372,7 +394,7 @@ __device__ __forceinline__ void vn_eval16_wave(const VnPtrs &P, const RowFeat &r
 #pragma unroll
     for (uint32_t j = 0; j < D1; ++j)
 #pragma unroll
-        for (uint32_t s = 0; s < 5u; ++s) w1r[j][s] = load8(w1 + (j * 5u + s) * 512u);
+        for (uint32_t s = 0; s < 5u; ++s) w1r[j][s] = buf_load8(w1, voff, (j * 5u + s) * 1024u);
 #pragma unroll 1
     for (uint32_t j0 = 0; j0 < 16u; j0 += D1) {
 #pragma unroll
@@ -384,7 +406,7 @@ __device__ __forceinline__ void vn_eval16_wave(const VnPtrs &P, const RowFeat &r
             for (uint32_t s = 0; s < 5u; ++s) acc = mfma16(xa[s], w1r[jj][s], acc);
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (uint32_t s = 0; s < 5u; ++s) w1r[jj][s] = load8(w1 + (jn * 5u + s) * 512u);
+            for (uint32_t s = 0; s < 5u; ++s) w1r[jj][s] = buf_load8(w1, voff, (jn * 5u + s) * 1024u);
             __builtin_amdgcn_sched_barrier(0);
             const float b = sm.b1[16u * j + r];
 #pragma unroll
@@ -399,7 +421,7 @@ __device__ __forceinline__ void vn_eval16_wave(const VnPtrs &P, const RowFeat &r
 #pragma unroll
     for (uint32_t j = 0; j < D2; ++j)
 #pragma unroll
-        for (uint32_t s = 0; s < 8u; ++s) w2r[j][s] = load8(w2 + (j * 8u + s) * 512u);
+        for (uint32_t s = 0; s < 8u; ++s) w2r[j][s] = buf_load8(w2, voff, (j * 8u + s) * 1024u);
     wave_lds_sync();
     bf16x8 ha[8];
 #pragma unroll
@@ -414,7 +436,7 @@ __device__ __forceinline__ void vn_eval16_wave(const VnPtrs &P, const RowFeat &r
         for (uint32_t s = 0; s < 8u; ++s) acc = mfma16(ha[s], wq[s], acc);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (uint32_t s = 0; s < 8u; ++s) wq[s] = load8(w2 + (jn * 8u + s) * 512u);
+        for (uint32_t s = 0; s < 8u; ++s) wq[s] = buf_load8(w2, voff, (jn * 8u + s) * 1024u);
         __builtin_amdgcn_sched_barrier(0);
         const float b = sm.b2[16u * j + r], w3 = sm.w3[16u * j + r];
 #pragma unroll

@@ -366,24 +366,31 @@ def tree_phases(ws, n, mp):
 
 def search_phases(net=None):
     """Share of each search phase in the shader clock cycles of the iterations
-    (per-tree counters kept by the kernel), for the three search workloads and,
-    with a network, the value-mode searches of the last one: band 0 (every leaf
-    scored by the network), one leaf per pass.  Also the cycles of the
-    slowest tree against the mean: a batched launch lasts as long as its
-    slowest tree."""
+    (per-tree counters kept by the kernel), for the three search workloads, the
+    batched one also with two leaves per pass pipelined (the autotuner's shape)
+    and, with a network, the value-mode searches of the last one: band 0
+    (every leaf scored by the network), one leaf per pass, and four leaves per
+    pass pipelined.  Also the cycles of the slowest tree against the mean: a
+    batched launch lasts as long as its slowest tree.  Pipelined searches count
+    the evaluating wavefront's cycles beside the descending one's."""
     out = {}
-    work = {k: v + (1, None) for k, v in SEARCH_WORKLOADS.items()}
+    work = {k: v + (1, None, 0) for k, v in SEARCH_WORKLOADS.items()}
+    work["batched, 2048 mid-game roots, 1024 x 32, two leaves per pass, pipelined"] = \
+        SEARCH_WORKLOADS["batched, 2048 mid-game roots, 1024 x 32"] + (2, None, 1)
     if net is not None:
         base = SEARCH_WORKLOADS["1024 fresh 2-4 player deals, 4096 x 64"]
-        work["1024 fresh deals, 4096 iterations, value mode, band 0"] = base + (1, 0.0)
-    for name, (n, deal, iters, ppl, seed, lpp, band) in work.items():
+        work["1024 fresh deals, 4096 iterations, value mode, band 0"] = base + (1, 0.0, 0)
+        work["1024 fresh deals, 4096 iterations, value mode, band 0, four leaves per pass, "
+             "pipelined"] = base + (4, 0.0, 1)
+    for name, (n, deal, iters, ppl, seed, lpp, band, pipe) in work.items():
         roots = dvc_init_states(n, deal_params(**deal), seed)
         if band is not None:
             mp = mcts_params(iterations=iters, playouts_per_leaf=1, max_depth=4, leaf_eval=1,
                              fallback_band=band, fallback_playouts=ppl, valuenet=net,
-                             leaves_per_pass=lpp)
+                             leaves_per_pass=lpp, pipeline=pipe)
         else:
-            mp = mcts_params(iterations=iters, playouts_per_leaf=ppl, max_depth=4)
+            mp = mcts_params(iterations=iters, playouts_per_leaf=ppl, max_depth=4,
+                             leaves_per_pass=lpp, pipeline=pipe)
         ws = torch.empty(dvc_mcts_workspace_bytes(n, mp), dtype=torch.uint8, device=roots.device)
         mcts_search(roots, mp, seed, workspace=ws, want_children=False)
         torch.cuda.synchronize()

@@ -14,6 +14,8 @@ chooser, N and W; the decision and the root children as well.
   that leave a ragged last pass;
 * value leaves with the integer network of ``exact_net`` (outputs exact in
   any summation order): band 0 and 0.05, one to four leaves per pass;
+* roots on which the sampler often takes its fallback world (sampled by the
+  evaluating wavefront in pipelined value searches), with the fallback counts;
 * a batch against its trees searched alone, a malformed root next to good
   ones, and root-parallel search with merged children.
 """
@@ -122,6 +124,41 @@ def test_pipelined_batch_against_single_trees(orc, dvc, value):
         assert int(b1[0].item()) == int(best[t].item())
         assert torch.equal(k1[0], kids[t])
     assert dvc.dvc_check() == 0
+
+
+def _fallback_roots(orc):
+    """Roots on which the sampler often gives up after 64 attempts and takes
+    the fallback world (found with the oracle's sampler: 3-62 of the first 64
+    iterations of seed 9)."""
+    a = _roots(orc, 300, 3, pile_max=16, revealed_max=8)[[24, 163, 165, 297]]
+    b = _roots(orc, 300, 401)[[100, 177, 270]]
+    return np.concatenate([a, b])
+
+
+@pytest.mark.parametrize("value,lpp,pipe", [(0, 1, 0), (0, 2, 1), (1, 4, 1), (1, 1, 0)])
+def test_sampler_fallback_worlds(orc, dvc, value, lpp, pipe):
+    """Fallback worlds (sampled by the evaluating wavefront in pipelined
+    value searches): trees node by node, and each tree's fallback count
+    against the oracle's sampler."""
+    roots = _fallback_roots(orc)
+    iters = 160
+    if value:
+        p = exact_net.params()
+        net = dvc.dvc_valuenet_init(0)
+        dvc.dvc_valuenet_set_params(net, torch.from_numpy(p).cuda())
+        kw = lambda n: dict(iterations=iters, playouts_per_leaf=1, max_depth=4, leaf_eval=1,
+                            fallback_band=0.05, fallback_playouts=16, valuenet=n,
+                            leaves_per_pass=lpp, pipeline=pipe)
+        mo, md = orc.mcts_params(**kw(p)), dvc.mcts_params(**kw(net))
+    else:
+        kw = dict(iterations=iters, playouts_per_leaf=8, max_depth=4, leaves_per_pass=lpp,
+                  pipeline=pipe)
+        mo, md = orc.mcts_params(**kw), dvc.mcts_params(**kw)
+    stats, _ = _search_and_compare(orc, dvc, roots, mo, md, 9)
+    want = [sum(1 for i in range(iters) if orc.determinize(roots[t], 9, t, i)[1] == 64)
+            for t in range(len(roots))]
+    assert sum(want) > 100
+    assert stats["sampler_fallbacks"].tolist() == want
 
 
 def test_pipelined_malformed_root(orc, dvc):
