@@ -276,11 +276,12 @@ __device__ __forceinline__ uint32_t legal_values(const State &S, uint32_t k, con
 // this instead of the per-lane table.  0 when m has no k-th bit.
 __device__ __forceinline__ uint32_t kth_bit_wave(uint32_t m, uint32_t k)
 {
-    const uint32_t lane = threadIdx.x & 63u;
-    const bool hit = lane < 32u && ((m >> (lane & 31u)) & 1u) != 0u &&
-                     __builtin_amdgcn_mbcnt_lo(m, 0u) == k;
-    const uint64_t b = __ballot(hit);
-    return b ? (uint32_t)__builtin_ctzll(b) : 0u;
+    // lanes 32-63 repeat lanes 0-31 and only the low half of the ballot is
+    // read; bitwise, not short-circuit, conditions keep it branch-free
+    const uint32_t l = threadIdx.x & 31u;
+    const bool hit = (((m >> l) & 1u) != 0u) & (__builtin_amdgcn_mbcnt_lo(m, 0u) == k);
+    const uint32_t b = (uint32_t)__ballot(hit);
+    return b ? (uint32_t)__builtin_ctz(b) : 0u;
 }
 
 // a uniformly drawn set bit of m (word w), as kth_bit_wave
@@ -527,6 +528,7 @@ mcts_tree_kernel(MctsArgs a)
     constexpr bool ESAMPLE = PIPE && VALUE;
     __shared__ uint8_t tab[kKthTableBytes];
     __shared__ uint32_t legal_all[TG][73];
+    __shared__ uint32_t legal_root_all[TG][73];   // the root's, the same in every world
     constexpr uint32_t BM = TreeGroup<VALUE, PIPE>::kPass;
     __shared__ uint32_t path_all[TG][NBUF][BM][kMaxPath];
     __shared__ uint4 leaf_all[TG][NBUF][BM];
@@ -618,12 +620,17 @@ mcts_tree_kernel(MctsArgs a)
     // names an opponent's row slot and a value; which slots are hidden, their
     // colours, the revealed tiles around them and the mover's own tiles are
     // what the searching player sees, and the sampler keeps them all.
-    const uint32_t rc_l0 = legal_values(R, lane, tab);
-    uint32_t rc_l1 = 0u;
-    if (__builtin_amdgcn_readfirstlane(
-            (uint32_t)(R.P == 4u && __popc(hand_of(R, (R.m + 3u) & 3u)) > 16)) != 0u &&
-        lane < 8u)
-        rc_l1 = legal_values(R, 64u + lane, tab);
+    // Kept in LDS (registers are scarce across the playouts).
+    uint32_t *legal_root = legal_root_all[wv];
+    if (role == 0u) {   // the wavefront that descends
+        legal_root[lane] = legal_values(R, lane, tab);
+        uint32_t l1 = 0u;
+        if (__builtin_amdgcn_readfirstlane(
+                (uint32_t)(R.P == 4u && __popc(hand_of(R, (R.m + 3u) & 3u)) > 16)) != 0u &&
+            lane < 8u)
+            l1 = legal_values(R, 64u + lane, tab);
+        if (lane < 9u) legal_root[64u + lane] = l1;   // [72]: no stop at the root
+    }
     uint4 rc_e0 = make_uint4(0u, 0u, 0u, 0u), rc_e1 = make_uint4(0u, 0u, 0u, 0u);
     uint32_t rc_cb0 = 0u, rc_cb1 = 0u, rc_nc = 0u, rc_nx0 = kNoBlock, rc_nx1 = kNoBlock;
     // root child slot (0 .. 127, else not cached) of the entry at word offset e
@@ -705,10 +712,10 @@ mcts_tree_kernel(MctsArgs a)
         }
         const uint4 fr = fb_rows[wv];
         S = R;
-        S.h0 = fr.x;
-        S.h1 = fr.y;
-        S.h2 = fr.z;
-        S.h3 = fr.w;
+        S.h0 = __builtin_amdgcn_readfirstlane(fr.x);
+        S.h1 = __builtin_amdgcn_readfirstlane(fr.y);
+        S.h2 = __builtin_amdgcn_readfirstlane(fr.z);
+        S.h3 = __builtin_amdgcn_readfirstlane(fr.w);
         ++n_sampler_fallback;
         return true;
     };
@@ -927,11 +934,12 @@ mcts_tree_kernel(MctsArgs a)
                     failed = true;
                     break;
                 }
+                // the same in every lane: scalar registers, scalar branches
                 S = R;
-                S.h0 = wr.x;
-                S.h1 = wr.y;
-                S.h2 = wr.z;
-                S.h3 = wr.w;
+                S.h0 = __builtin_amdgcn_readfirstlane(wr.x);
+                S.h1 = __builtin_amdgcn_readfirstlane(wr.y);
+                S.h2 = __builtin_amdgcn_readfirstlane(wr.z);
+                S.h3 = __builtin_amdgcn_readfirstlane(wr.w);
             } else if (!sample_world(it, S)) {
                 failed = true;
                 break;
@@ -1027,8 +1035,8 @@ mcts_tree_kernel(MctsArgs a)
                 const float lp = a.ln[node_n];
                 uint32_t l0, l1;
                 if (at_root) {
-                    l0 = rc_l0;
-                    l1 = rc_l1;
+                    l0 = legal_root[lane];
+                    l1 = lane < 9u ? legal_root[64u + lane] : 0u;
                 } else {
                     l0 = legal_values(S, lane, tab);
                     // pairs 64-71 are slots 16-23 of the third opponent: only
@@ -1038,8 +1046,12 @@ mcts_tree_kernel(MctsArgs a)
                     if (__builtin_amdgcn_readfirstlane((uint32_t)wide) != 0u && lane < 8u)
                         l1 = legal_values(S, 64u + lane, tab);
                 }
-                legal_s[lane] = l0;
-                if (lane < 9u) legal_s[64u + lane] = l1;
+                // the legal table the scoring reads: the root's as it is
+                const uint32_t *legal_t = at_root ? legal_root : legal_s;
+                if (!at_root) {
+                    legal_s[lane] = l0;
+                    if (lane < 9u) legal_s[64u + lane] = l1;
+                }
                 const uint32_t cb0 = (cbw0 >> ((lane & 1u) * 16u)) & 0xFFFu;
                 const uint32_t cb1 = lane == 8u ? (cbw1 & 1u) : (cbw1 >> ((lane & 1u) * 16u)) & 0xFFFu;
                 const uint32_t u0 = l0 & ~cb0, u1 = l1 & ~cb1;
@@ -1129,7 +1141,7 @@ mcts_tree_kernel(MctsArgs a)
                     const bool after_right = key > kStopKey;
                     const uint32_t act = after_right ? key - kStopKey - 1u : key;
                     const uint32_t pr = act / 12u < 72u ? act / 12u : 72u;
-                    const bool legal = (legal_s[pr] >> ((act - pr * 12u) & 31u)) & 1u;
+                    const bool legal = (legal_t[pr] >> ((act - pr * 12u) & 31u)) & 1u;
                     const bool playable =
                         (ci < nchild) & (key == kStopKey ? cont : (after_right == cont) & legal);
                     const float n = (float)ent.y;
