@@ -529,6 +529,7 @@ mcts_tree_kernel(MctsArgs a)
     __shared__ uint8_t tab[kKthTableBytes];
     __shared__ uint32_t legal_all[TG][73];
     __shared__ uint32_t legal_root_all[TG][73];   // the root's, the same in every world
+    __shared__ uint4 rcache_all[TG][2 * kBlockEntries];   // the root's first two child blocks
     constexpr uint32_t BM = TreeGroup<VALUE, PIPE>::kPass;
     __shared__ uint32_t path_all[TG][NBUF][BM][kMaxPath];
     __shared__ uint4 leaf_all[TG][NBUF][BM];
@@ -574,11 +575,11 @@ mcts_tree_kernel(MctsArgs a)
     uint32_t *bnext = W + ovf_base + a.sh.ovf_cap * kBlockWords;
     // word offset (from W) of child block b: blocks below nodes_cap are the
     // nodes' inline blocks, the rest overflow blocks
-    auto block_off = [&](uint32_t b) -> uint32_t {
+    auto block_off = [&](uint32_t b) __attribute__((always_inline)) -> uint32_t {
         return b < nodes_cap ? kTreeHeaderWords + b * node_stride + node_words
                              : ovf_base + (b - nodes_cap) * kBlockWords;
     };
-    auto rec_off = [&](uint32_t nd) -> uint32_t { return kTreeHeaderWords + nd * node_stride; };
+    auto rec_off = [&](uint32_t nd) __attribute__((always_inline)) -> uint32_t { return kTreeHeaderWords + nd * node_stride; };
 
     const uint4 rs = a.roots[t / a.trees_per_root];
     State R;
@@ -609,12 +610,12 @@ mcts_tree_kernel(MctsArgs a)
     // successful attempt is the same one either way.
     uint32_t wpl0 = 0u, wpl1 = 0u, wpl2 = 0u;
     uint64_t wok = 0u;
-    // The root's first two child blocks (lane l: children l and 64 + l), its
-    // guess bitmap words (laid out as the descent loads them), child count
-    // and next two block ids, kept in registers: the wavefront that owns the
-    // tree makes every change to them, to memory and here at the same points,
-    // so the root level of a descent issues no loads.  Not for vanilla trees,
-    // whose root children are worlds.
+    // The root's first two child blocks (in LDS), its guess bitmap words
+    // (laid out as the descent loads them), child count and next two block
+    // ids (in registers), kept on chip: the wavefront that owns the tree
+    // makes every change to them, to memory and here at the same points, so
+    // the root level of a descent issues no global loads.  Not for vanilla
+    // trees, whose root children are worlds.
     const bool rc_on = !a.vanilla;
     // The root's legal guesses, the same in every sampled world: a guess
     // names an opponent's row slot and a value; which slots are hidden, their
@@ -631,10 +632,15 @@ mcts_tree_kernel(MctsArgs a)
             l1 = legal_values(R, 64u + lane, tab);
         if (lane < 9u) legal_root[64u + lane] = l1;   // [72]: no stop at the root
     }
-    uint4 rc_e0 = make_uint4(0u, 0u, 0u, 0u), rc_e1 = make_uint4(0u, 0u, 0u, 0u);
+    // (the 128 entries in LDS, the rest in registers)
+    uint4 *rc_ent = rcache_all[wv];
+    if (role == 0u) {
+        rc_ent[lane] = make_uint4(0u, 0u, 0u, 0u);
+        rc_ent[kBlockEntries + lane] = make_uint4(0u, 0u, 0u, 0u);
+    }
     uint32_t rc_cb0 = 0u, rc_cb1 = 0u, rc_nc = 0u, rc_nx0 = kNoBlock, rc_nx1 = kNoBlock;
     // root child slot (0 .. 127, else not cached) of the entry at word offset e
-    auto rc_slot = [&](uint32_t e) -> uint32_t {
+    auto rc_slot = [&](uint32_t e) __attribute__((always_inline)) -> uint32_t {
         const uint32_t b0 = block_off(0u);
         if (e - b0 < kBlockWords) return (e - b0) / kEntryWords;
         if (rc_nx0 != kNoBlock && e - block_off(rc_nx0) < kBlockWords)
@@ -642,14 +648,11 @@ mcts_tree_kernel(MctsArgs a)
         return 0xFFFFFFFFu;
     };
     // visits dn for cached slot `slot`; its W word set to wbits when set_w
-    auto rc_update = [&](uint32_t slot, uint32_t dn, bool set_w, uint32_t wbits) {
-        if (slot == lane) {
-            rc_e0.y += dn;
-            if (set_w) rc_e0.z = wbits;
-        }
-        if (slot == kBlockEntries + lane) {
-            rc_e1.y += dn;
-            if (set_w) rc_e1.z = wbits;
+    auto rc_update = [&](uint32_t slot, uint32_t dn, bool set_w, uint32_t wbits) __attribute__((always_inline)) {
+        if (slot < 2u * kBlockEntries && lane == 0u) {
+            uint4 &en = rc_ent[slot];
+            en.y += dn;
+            if (set_w) en.z = wbits;
         }
     };
     tree_sync<WS>();
@@ -667,7 +670,7 @@ mcts_tree_kernel(MctsArgs a)
     // runs all 64 attempts on its own (the lowest successful one is the same
     // either way), and one with none left takes the fallback world.  Returns
     // false when the fallback search gives up.
-    auto sample_world = [&](uint32_t it, State &S) -> bool {
+    auto sample_world = [&](uint32_t it, State &S) __attribute__((always_inline)) -> bool {
         if ((it & 63u) == 0u) {
             State Sw;
             const bool got0 = det_attempt(R, 0u, it + lane, tr, a.k0, a.k1, Sw, tab);
@@ -723,7 +726,7 @@ mcts_tree_kernel(MctsArgs a)
     // i0 + nb - 1): playouts packed into the 64 lanes, or network rows; the
     // decided leaves get their winner's share.  Results in vals_all[wv][buf].
     auto eval_pass = [&](uint32_t buf, uint32_t i0, uint32_t nb, uint32_t term_mask,
-                     uint32_t winners) {
+                     uint32_t winners) __attribute__((always_inline)) {
         uint32_t play_mask = ((1u << nb) - 1u) & ~term_mask;   // leaves to play out
         if (VALUE && play_mask) {
             // rows 4b + q: leaf b, seat perspective q < P
@@ -838,7 +841,7 @@ mcts_tree_kernel(MctsArgs a)
 
     };
     // ---- 4. back-propagation of a pass: each path gets its leaf's wins, in order
-    auto backprop_pass = [&](uint32_t buf, uint32_t nb) {
+    auto backprop_pass = [&](uint32_t buf, uint32_t nb) __attribute__((always_inline)) {
         for (uint32_t b = 0; b < nb; ++b) {
             const uint32_t npb = np_all[wv][buf][b];
             uint32_t e = 0u, nw = 0u;
@@ -870,7 +873,7 @@ mcts_tree_kernel(MctsArgs a)
         // the worlds of pass kp into world buffer kp & 1 (in iteration
         // order); after a world the sampler gave up on, none
         bool gave_up = false;
-        auto sample_pass = [&](uint32_t kp) {
+        auto sample_pass = [&](uint32_t kp) __attribute__((always_inline)) {
             if (!ESAMPLE || kp >= n_pass || gave_up) return;
             const uint32_t ip = kp * a.lpp, nbp = a.iters - ip < a.lpp ? a.iters - ip : a.lpp;
             const uint64_t t0 = clock64();
@@ -951,7 +954,7 @@ mcts_tree_kernel(MctsArgs a)
             // Append a child {ex | ..., 0, ez, id} to `parent` (child count nc);
             // returns its id and its entry's word offset.
             auto append_child = [&](uint32_t parent, uint32_t nc, uint32_t ex, uint32_t ez,
-                                    uint32_t &e_out) -> uint32_t {
+                                    uint32_t &e_out) __attribute__((always_inline)) -> uint32_t {
                 const uint32_t rec = rec_off(parent);
                 const uint32_t c = n_nodes++;
                 uint32_t blk = parent;
@@ -1023,7 +1026,7 @@ mcts_tree_kernel(MctsArgs a)
                     cbw0 = rc_cb0;
                     cbw1 = rc_cb1;
                     nchild_v = rc_nc;
-                    ent0 = rc_e0;
+                    ent0 = rc_ent[lane];
                     next0_v = rc_nx0;
                 } else {
                     cbw0 = W[rec + 4u + half + (lane >> 1)];
@@ -1095,8 +1098,7 @@ mcts_tree_kernel(MctsArgs a)
                     if (lane == 0) W[rec + word] = old | bit;
                     if (at_root) {
                         const uint4 ne = make_uint4(key | (S.m << 16), 0u, 0u, c);
-                        if (nchild == lane) rc_e0 = ne;
-                        if (nchild == kBlockEntries + lane) rc_e1 = ne;
+                        if (nchild < 2u * kBlockEntries && lane == 0u) rc_ent[nchild] = ne;
                         // a new overflow block starts at child 64 and at child 128
                         if (nchild == kBlockEntries) rc_nx0 = nodes_cap + n_ovf - 1u;
                         if (nchild == 2u * kBlockEntries) rc_nx1 = nodes_cap + n_ovf - 1u;
@@ -1124,7 +1126,7 @@ mcts_tree_kernel(MctsArgs a)
                     uint32_t nxt_n = kNoBlock;
                     if (more) {
                         if (at_root && base == 0u) {
-                            ent_n = rc_e1;
+                            ent_n = rc_ent[kBlockEntries + lane];
                             nxt_n = rc_nx1;
                         } else {
                             ent_n = *reinterpret_cast<const uint4 *>(W + block_off(nxt) + lane * kEntryWords);

@@ -183,3 +183,35 @@ def test_search_autotune_argument_errors_without_device(lib):
                        (D.mcts_params(iterations=64, playouts_per_leaf=8, leaf_eval=1), 4, 0.0)]:
         assert L.dvc_mcts_autotune(vp(16), n, C.byref(mp), 1, 0, vp(16), 1 << 30, tol, vp(16),
                                    C.byref(res), None) == -1
+
+
+def test_kernels_use_no_scratch(lib, tmp_path):
+    """Every kernel of the library runs without private (scratch) memory: no
+    register spills, so a launch needs no scratch allocation by the runtime
+    (the allocation-free search relies on it).  Read from the gfx950 code
+    object's metadata, extracted from the built library."""
+    import shutil
+    import subprocess
+    tools = "/opt/rocm/llvm/bin"
+    objdump, readelf = os.path.join(tools, "llvm-objdump"), os.path.join(tools, "llvm-readelf")
+    if not (os.path.exists(objdump) and os.path.exists(readelf)):
+        pytest.skip("llvm-objdump / llvm-readelf not installed")
+    import paper_2403_10720_amd as D
+    so = tmp_path / "libdvc.so"
+    shutil.copy(D.LIB_PATH, so)
+    subprocess.run([objdump, "--offloading", str(so)], cwd=tmp_path, check=True,
+                   capture_output=True)
+    co = [p for p in tmp_path.iterdir() if "amdgcn" in p.name and "gfx950" in p.name]
+    assert len(co) == 1, list(tmp_path.iterdir())
+    notes = subprocess.run([readelf, "--notes", str(co[0])], check=True, capture_output=True,
+                           text=True).stdout
+    kernels, name = {}, None
+    for line in notes.splitlines():
+        line = line.strip()
+        if line.startswith(".name:"):
+            name = line.split(":", 1)[1].strip()
+        elif line.startswith(".private_segment_fixed_size:") and name is not None:
+            kernels[name] = int(line.split(":", 1)[1])
+            name = None
+    assert any("mcts_tree_kernel" in k for k in kernels) and any("rollout" in k for k in kernels)
+    assert {k: v for k, v in kernels.items() if v} == {}
