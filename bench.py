@@ -59,9 +59,9 @@ OPS_PER_GUESS = 222
 # scaled by what the same counter reads for a plain 256 MiB device copy
 # (FETCH_SIZE reads half the bytes moved, WRITE_SIZE all of them).  Valid
 # only for the kernel sources it was taken on: reported as null otherwise.
-PROFILED_TRAFFIC = {"fetch_kib": 385.0, "fetch_scale": 2.0, "write_kib": 3200.0,
+PROFILED_TRAFFIC = {"fetch_kib": 381.5, "fetch_scale": 2.0, "write_kib": 3200.0,
                     "write_scale": 1.0,
-                    "sources_sha256": "1ef06c6e657b94f29901b98acbfd9f4b322126ad2fb7d20a4b4189dad4abb21a"}
+                    "sources_sha256": "18356cf6d0a7abfed40d7ec5de1177ccb58936d0bb59b2b2409cec9588156adb"}
 KERNEL_SOURCES = ["paper_2403_10720_amd/csrc/dvc_core.hpp",
                   "paper_2403_10720_amd/csrc/dvc_internal.hpp",
                   "paper_2403_10720_amd/csrc/rollout.hip"]
