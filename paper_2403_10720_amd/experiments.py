@@ -10,9 +10,12 @@ searched three times with the library's tree-search kernel:
     `ppl` playouts instead.
 Reported: root-move agreement of the value search with the playout search,
 the self-agreement ceiling, GPU time per decision of both (HIP events around
-one launch each), the share of leaves that fell back to playouts, and the
-network's mean squared error against many-playout estimates on held-out
-positions next to the noise floor of those estimates.
+one launch each; sequential and pipelined passes), the share of leaves that
+fell back to playouts, the network's mean squared error against many-playout
+estimates on held-out positions next to the noise floor of those estimates,
+and the agreement of each search with a high-budget reference (a playout
+search with four times the iterations) next to a playout search with half
+the iterations, whose GPU time is about the value search's.
 
 root_parallel_vs_single(): K independent trees per root amalgamated at the
 root (the paper's decomposition) against one tree with K times the
@@ -144,6 +147,32 @@ def compare(n_trees=1024, iterations=4096, ppl=64, band=0.05, train_cfg: TrainCo
     best_val3, t_val3 = median_search(roots, mp_val3, seed, ws, reps)
     mp_roll3 = mcts_params(iterations=iterations, playouts_per_leaf=ppl, max_depth=4, pipeline=1)
     best_roll3, t_roll3 = median_search(roots, mp_roll3, seed, ws, reps)
+    # against a high-budget reference (a playout search with four times the
+    # iterations, another seed): the value search next to a playout search
+    # with half the iterations, which costs about as much GPU time
+    ws_ref = torch.empty(dvc_mcts_workspace_bytes(n_trees, mcts_params(
+        iterations=4 * iterations, playouts_per_leaf=ppl, max_depth=4)), dtype=torch.uint8,
+        device=roots.device)
+    best_ref, t_ref = timed_search(roots, mcts_params(iterations=4 * iterations, playouts_per_leaf=ppl,
+                                                      max_depth=4), seed + 996, ws_ref)
+    del ws_ref
+    half = [mcts_params(iterations=iterations // 2, playouts_per_leaf=ppl, max_depth=4,
+                        pipeline=p) for p in (0, 1)]
+    best_h0, t_h0 = median_search(roots, half[0], seed, ws, reps)
+    best_h1, t_h1 = median_search(roots, half[1], seed, ws, reps)
+    vs_ref = lambda b: float((b == best_ref).float().mean().item())
+    matched = {
+        "reference": f"playout search, {4 * iterations} iterations x {ppl} playouts, seed "
+                     f"{seed + 996} ({t_ref * 1e3:.0f} ms)",
+        "value_pipelined": {"gpu_s_per_decision": t_val3 / n_trees,
+                            "agreement_with_reference": vs_ref(best_val3)},
+        "playout": {"gpu_s_per_decision": t_roll / n_trees,
+                    "agreement_with_reference": vs_ref(best_roll)},
+        f"playout_{iterations // 2}_iterations": {"gpu_s_per_decision": t_h0 / n_trees,
+                                                   "agreement_with_reference": vs_ref(best_h0)},
+        f"playout_{iterations // 2}_iterations_pipelined": {
+            "gpu_s_per_decision": t_h1 / n_trees, "agreement_with_reference": vs_ref(best_h1)},
+    }
     # the playout search's phases (its trees are overwritten above)
     timed_search(roots, mp_roll, seed, ws)
     phases_roll = tree_phases(ws, n_trees, mp_roll)
@@ -186,6 +215,7 @@ def compare(n_trees=1024, iterations=4096, ppl=64, band=0.05, train_cfg: TrainCo
             "rollout_agreement_with_sequential": float((best_roll3 == best_roll).float()
                                                        .mean().item())},
         "rollout_phases": phases_roll,
+        "against_high_budget_reference": matched,
         "gpu_seconds_ratio_fastest": ratio,
         "targets": {"root_move_agreement": {"target": TARGET_AGREEMENT, "measured": agree,
                                             "met": agree >= TARGET_AGREEMENT},
