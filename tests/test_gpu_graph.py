@@ -56,10 +56,11 @@ def test_graph_rollout_step(dvc):
 
 
 @pytest.mark.parametrize("kw", [dict(), dict(leaves_per_pass=2, playouts_per_leaf=32),
+                                dict(leaves_per_pass=2, playouts_per_leaf=32, pipeline=1),
                                 dict(continue_choice=1, max_depth=0, vanilla=1)])
 def test_graph_batched_search(dvc, kw):
-    """A captured search (sequential, leaf-batched, un-simplified variants)
-    replays to the eager result every time."""
+    """A captured search (sequential, leaf-batched, pipelined, un-simplified
+    variants) replays to the eager result every time."""
     n = 64
     roots = dvc.dvc_init_states(n, dvc.deal_params(p_min=2, p_max=4, hand=(0, 0, 4, 4, 3),
                                                    pile_min=0, pile_max=16, revealed_max=8,

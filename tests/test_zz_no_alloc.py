@@ -35,7 +35,7 @@ def _roots(dvc, n, seed):
 
 def _same(dvc, roots, mp, seed, base):
     print(f"n={roots.shape[0]} iterations={mp.iterations} ppl={mp.playouts_per_leaf} "
-          f"leaf_eval={mp.leaf_eval} lpp={mp.leaves_per_pass}", flush=True)
+          f"leaf_eval={mp.leaf_eval} lpp={mp.leaves_per_pass} pipeline={mp.pipeline}", flush=True)
     b_ref, k_ref = dvc.mcts_search(roots, mp, seed, base)
     b_got, k_got = dvc.mcts_search_noalloc(roots, mp, seed, base,
                                            kids=torch.full_like(k_ref, -7))
@@ -62,6 +62,11 @@ def test_noalloc_value_mode(dvc):
                          fallback_band=0.05, fallback_playouts=64, valuenet=net)
     _same(dvc, roots, mp, 8, 0)
     _same(dvc, roots[:3].contiguous(), mp, 9, 40)
+    # pipelined passes: two wavefronts per tree, the same static trees
+    mp4 = dvc.mcts_params(iterations=300, playouts_per_leaf=1, max_depth=4, leaf_eval=1,
+                          fallback_band=0.05, fallback_playouts=64, valuenet=net,
+                          leaves_per_pass=4, pipeline=1)
+    _same(dvc, roots[:7].contiguous(), mp4, 10, 3)
 
 
 def test_noalloc_limits(dvc):
