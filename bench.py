@@ -14,8 +14,10 @@ size) against the integer-VALU issue peak of the chip; `cpu_baseline` is the
 CPU oracle timed on this host's cores on a bounded sample of the same
 workload.  Side figures: batched search (as configured, with two leaves per
 pass, also pipelined, and with the shape the library's search autotuner
-picks under its agreement guard), root-parallel search and a single tree
-(also four leaves per pass, plain and pipelined), timed with HIP events;
+picks under its agreement guard, each with its `critical_path`: the launch
+against the per-wavefront instruction-issue bound), root-parallel search and
+a single tree (also four leaves per pass, plain and pipelined), timed with
+HIP events;
 `value_vs_rollout`: value-network training on
 pairs the rollout kernel labels (step time, TFLOP/s) and the value-network
 search against the pure-playout search on 1024 fresh deals x 4096 iterations
@@ -62,18 +64,47 @@ OPS_PER_GUESS = 222
 PROFILED_TRAFFIC = {"fetch_kib": 381.5, "fetch_scale": 2.0, "write_kib": 3200.0,
                     "write_scale": 1.0,
                     "sources_sha256": "18356cf6d0a7abfed40d7ec5de1177ccb58936d0bb59b2b2409cec9588156adb"}
+# Instructions one tree issues per iteration in the batched search (both
+# wavefronts of a pipelined tree), from the SQ instruction counters of a
+# profiler pass over `experiments --what phases` (VALU + SALU + LDS + SMEM +
+# VMEM + branch), keyed by (playouts per leaf, leaves per pass, pipeline);
+# valid only for the tree-kernel sources they were taken on.
+PROFILED_SEARCH = {"instructions_per_tree_iteration": {(32, 1, 0): 4920, (32, 2, 1): 3545},
+                   "sources_sha256": "59ac89b9ff88eed947e4de8b13e26727a1b4b17f758ec3aa20f4bca2336a6f5b"}
+SEARCH_SOURCES = ["paper_2403_10720_amd/csrc/dvc_core.hpp",
+                  "paper_2403_10720_amd/csrc/dvc_internal.hpp",
+                  "paper_2403_10720_amd/csrc/search.hip"]
 KERNEL_SOURCES = ["paper_2403_10720_amd/csrc/dvc_core.hpp",
                   "paper_2403_10720_amd/csrc/dvc_internal.hpp",
                   "paper_2403_10720_amd/csrc/rollout.hip"]
 
 
-def sources_sha256():
+def sources_sha256(files=None):
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in files or KERNEL_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
+
+
+def search_critical_path(ms, iterations, ppl, lpp, pipeline):
+    """The tree kernel against its bound: a wavefront issues at most one
+    instruction per 4-cycle slot, so a tree whose W wavefronts issued every
+    slot would need instructions x 4 / W cycles per iteration; the launch
+    takes ms x 2.4 GHz / iterations (every tree runs concurrently, the
+    slowest sets the time).  frac = the first over the second.  None when
+    the profiled count does not cover this shape or these sources."""
+    n_inst = PROFILED_SEARCH["instructions_per_tree_iteration"].get((ppl, lpp, pipeline))
+    if n_inst is None or sources_sha256(SEARCH_SOURCES) != PROFILED_SEARCH["sources_sha256"]:
+        return None
+    waves = 2 if pipeline else 1
+    bound = n_inst * 4.0 / waves
+    launch = ms * 1e-3 * 2.4e9 / iterations
+    return {"bound": "per-wavefront instruction issue (one per 4-cycle slot)",
+            "instructions_per_tree_iteration": n_inst, "wavefronts_per_tree": waves,
+            "issue_bound_cycles_per_iteration": bound,
+            "launch_cycles_per_iteration_at_2.4GHz": launch, "frac": bound / launch}
 
 
 def profiled_traffic_bytes():
@@ -129,7 +160,8 @@ def batched_search(D, torch, reps=3, leaves_per_pass=1, pipeline=0):
         torch.cuda.synchronize()
         ms.append(e0.elapsed_time(e1))
     best = min(ms)
-    return {"workload": "2048 trees (2-4 players, mid-game, root draw) x 1024 iterations x 32 "
+    return {"critical_path": search_critical_path(best, iters, ppl, leaves_per_pass, pipeline),
+            "workload": "2048 trees (2-4 players, mid-game, root draw) x 1024 iterations x 32 "
                         "playouts, depth 4" + (f", {leaves_per_pass} leaves per pass"
                                                if leaves_per_pass > 1 else "") +
                         (", pipelined passes" if pipeline else ""),
@@ -163,7 +195,9 @@ def autotuned_search(D, torch, reps=3, tolerance=0.02):
         torch.cuda.synchronize()
         ms.append(e0.elapsed_time(e1))
     best = min(ms)
-    return {"workload": "2048 trees (2-4 players, mid-game, root draw) x 1024 iterations, depth 4, "
+    return {"critical_path": search_critical_path(best, iters, choice["playouts_per_leaf"],
+                                                  choice["leaves_per_pass"], choice["pipeline"]),
+            "workload": "2048 trees (2-4 players, mid-game, root draw) x 1024 iterations, depth 4, "
                         "autotuned playouts per leaf x leaves per pass x pipelined passes "
                         "(agreement guard: within "
                         f"{tolerance} of the 32-playout search's seed-to-seed agreement)",
