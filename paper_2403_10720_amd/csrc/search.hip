@@ -865,8 +865,11 @@ mcts_tree_kernel(MctsArgs a)
     };
 
     // Pipelined passes, the evaluating wavefront: step k evaluates pass
-    // k - 1 while the other wavefront descends pass k; both then meet at the
-    // step's workgroup barrier.  The two run the same number of steps (or
+    // k - 1 (and, with network leaves, samples the worlds of pass k + 1)
+    // while the other wavefront descends pass k; both then meet at the
+    // step's workgroup barrier (after one more barrier before the first
+    // step), and the descending wavefront backs up pass k - 1 while this one
+    // goes on with step k + 1.  The two run the same number of steps (or
     // both stop at the step where the descending wavefront gave up).
     const uint32_t n_pass = (a.iters + a.lpp - 1u) / a.lpp;
     if (PIPE && role == 1u) {
