@@ -70,7 +70,7 @@ PROFILED_TRAFFIC = {"fetch_kib": 381.5, "fetch_scale": 2.0, "write_kib": 3200.0,
 # VMEM + branch), keyed by (playouts per leaf, leaves per pass, pipeline);
 # valid only for the tree-kernel sources they were taken on.
 PROFILED_SEARCH = {"instructions_per_tree_iteration": {(32, 1, 0): 4920, (32, 2, 1): 3545},
-                   "sources_sha256": "59ac89b9ff88eed947e4de8b13e26727a1b4b17f758ec3aa20f4bca2336a6f5b"}
+                   "sources_sha256": "351f440d67b0c53ee4fb769060584eafb3db47f38e67fd29162111f717e00f9f"}
 SEARCH_SOURCES = ["paper_2403_10720_amd/csrc/dvc_core.hpp",
                   "paper_2403_10720_amd/csrc/dvc_internal.hpp",
                   "paper_2403_10720_amd/csrc/search.hip"]
