@@ -18,8 +18,14 @@
  *
  * Functions whose result is pinned by tests: Philox (library routine), the
  * uniform pick (closed form), the rules (invariants, closed form, exact
- * enumeration), the UCT tree at depth 1 (textbook UCB1).  The determinization
- * sampler's distribution is parity unpinned (see oracle_determinize).
+ * enumeration), the legal guesses and one guess played in the tree (a
+ * reference written from the rules), the UCT tree at depth 1 (textbook UCB1)
+ * and whole searched trees, playout and value leaves, plain, batched and
+ * pipelined passes (a reference loop written from Sec. II-B / III-A), the
+ * value network's forward pass, gradient and Adam step (closed forms and an
+ * independent numpy forward).  The determinization sampler is pinned against
+ * its own exact law, enumerated in the tests from its stated procedure; the
+ * paper fixes no distribution, so that law is itself a reading of it.
  */
 #ifndef DVC_ORACLE_H
 #define DVC_ORACLE_H
