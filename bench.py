@@ -395,11 +395,11 @@ def main():
     length = torch.empty(total, dtype=torch.int16, device=dev)
     wins = torch.empty((N_LEAVES, 4), dtype=torch.int32, device=dev)
 
-    # The automatic shape (variant 7) stores each leaf's seat wins over the
-    # table, 256 playouts being one workgroup; other shapes add to a table
-    # zeroed here first.  Either way the events bracket the rollout kernel
-    # alone.
-    stores_wins = args.variant in (0, 7)
+    # The automatic shape at this size (variant 7) stores each leaf's seat
+    # wins over the table, as variants 7 and 9 do when a workgroup holds
+    # whole leaves; other shapes add to a table zeroed here first.  Either
+    # way the events bracket the rollout kernel alone.
+    stores_wins = args.variant in (0, 7, 9)
 
     def step(ev=None):
         D.dvc_init_states(N_LEAVES, params, SEED, out=states)

@@ -138,8 +138,9 @@ int dvc_rollout(const dvc_state_t *leaves, int64_t n_leaves, int32_t playouts_pe
 
 /* dvc_rollout with a choice of kernel, for measurement.  variant: 0 =
  * automatic (the shape dvc_rollout_autotune chose for this size class, else
- * up to 4M playouts variant 7 with steps 5, 8, 11, 14; above, variant 5 if
- * playouts_per_leaf >= 256, else variant 1), 1 = one lane per playout,
+ * up to 2M playouts variant 7 with steps 5, 8, 11, 14, up to 4M variant 9
+ * with 512 playouts per workgroup; above, variant 5 if playouts_per_leaf >=
+ * 256, else variant 9 with 512), 1 = one lane per playout,
  * 2 = lane refill + work stealing over LDS-staged leaf chunks, 3 = lane
  * refill + work stealing over single-leaf items, 4 = several playouts per
  * lane back to back (`grid` then gives the playouts per lane, 1/2/4),
@@ -151,7 +152,9 @@ int dvc_rollout(const dvc_state_t *leaves, int64_t n_leaves, int32_t playouts_pe
  * fixed step counts (Sec. IV-B's divergence: wavefronts left without a game
  * stop issuing; `grid` 0/1 = steps 6, 9, 12, 2 = steps 5, 8, 11, 14),
  * 8 = variant 7 (steps 5, 8, 11, 14) with two games per lane advanced
- * together, 512 playouts per workgroup.
+ * together, 512 playouts per workgroup, 9 = variant 7's packing every four
+ * guesses, the lanes it frees starting the workgroup's next playouts
+ * (`grid` gives the workgroup's 256-playout batches, 1 or 2, default 2).
  * block/grid 0 = automatic.  Same outputs for every variant and shape.
  * flags: DVC_ROLLOUT_ACCUMULATE adds the wins to seat_wins instead of
  * overwriting it (the caller zeroes it once; several calls then tally into
@@ -164,9 +167,10 @@ int dvc_rollout_ex(const dvc_state_t *leaves, int64_t n_leaves, int32_t playouts
                    int32_t variant, int32_t block, int32_t grid, int32_t flags, void *stream);
 
 /* dvc_rollout_autotune -- runs this batch with every rollout kernel shape in
- * a fixed candidate list (variant 7 with steps 5, 8, 11, 14, variant 8,
- * variant 4 with 1 or 2 playouts per lane, variant 1, variant 5 with
- * 128/256/512-playout items), each launched twice with the
+ * a fixed candidate list (variant 7 with steps 5, 8, 11, 14, variant 9
+ * with 512 and 256 playouts per workgroup, variant 8, variant 4 with 1 or 2
+ * playouts per lane, variant 1, variant 5 with 128/256/512-playout items),
+ * each launched twice with the
  * second launch timed by HIP events on `stream`, and remembers the fastest
  * for batches of the same size class (device, floor(log2(n_leaves *
  * playouts_per_leaf)), playouts_per_leaf >= 256 / >= 64 / smaller): later

@@ -291,15 +291,20 @@ static Shape automatic_shape(uint64_t total, int32_t ppl)
         auto it = g_tuned.find(tune_key(total, ppl));
         if (it != g_tuned.end()) return it->second;
     }
-    // measured on gfx950: up to 4M playouts one playout per lane with the
-    // workgroup's unfinished games compacted at steps 5, 8, 11, 14 (variant
-    // 7; 0.108 ms vs 0.122 ms for variant 4 at 1M playouts, 0.339-0.393 ms vs
-    // 0.343-0.424 ms for variant 5 at 4M); beyond that in-wave refill over
-    // 256-playout items when leaves have at least 256 playouts (variant 5;
-    // 1.15-1.36 ms vs 1.27-1.42 ms at 16M, 4.38 ms vs 5.01 ms at 64M), else
-    // one lane per playout (variant 1)
-    if (total <= (4ull << 20)) return Shape{7, 0, 2};
-    return ppl >= 256 ? Shape{5, 0, 4} : Shape{1, 0, 0};
+    // measured on gfx950 (two-player mid-game leaves): up to 2M playouts one
+    // playout per lane with the workgroup's unfinished games packed at steps
+    // 5, 8, 11, 14 (variant 7; 0.107 ms at 1M in the bench step, the same as
+    // variant 9 with 256 playouts per workgroup, 0.122 ms for variant 4); up
+    // to 4M the games packed every four guesses and the freed lanes refilled,
+    // 512 playouts per workgroup (variant 9; 0.339 vs 0.357 ms for variant 7);
+    // beyond that in-wave refill over 256-playout items when leaves have at
+    // least 256 playouts (variant 5; 1.18 ms vs 1.21 ms for variant 9 and
+    // 1.29 ms for variant 7 at 16M), else variant 9 with 512 playouts per
+    // workgroup (1.24 ms vs 1.38 ms for variant 7 and 1.63 ms for variant 5
+    // at 262,144 leaves x 64)
+    if (total <= (2ull << 20)) return Shape{7, 0, 2};
+    if (total <= (4ull << 20)) return Shape{9, 0, 2};
+    return ppl >= 256 ? Shape{5, 0, 4} : Shape{9, 0, 2};
 }
 
 static int rollout_impl(const dvc_state_t *leaves, int64_t n_leaves, int32_t ppl, uint64_t seed,
@@ -335,11 +340,13 @@ static int rollout_impl(const dvc_state_t *leaves, int64_t n_leaves, int32_t ppl
     a.length = length;
     a.seat_wins = seat_wins;
     a.stats = nullptr;
-    // variants 7 and 8 with whole leaves per workgroup (256 and 512
-    // playouts) store each leaf's sums themselves: no zeroing launch
-    const uint32_t per_group = v == 8 ? 512u : 256u;   // playouts per workgroup
-    a.store_wins = (seat_wins && !(flags & DVC_ROLLOUT_ACCUMULATE) && (v == 7 || v == 8) &&
-                    (uint32_t)ppl <= per_group && per_group % (uint32_t)ppl == 0u) ? 1u : 0u;
+    // variants 7, 8 and 9 with whole leaves per workgroup (256, 512 and
+    // 256 K playouts; variant 9 at most 16 leaves) store each leaf's sums
+    // themselves: no zeroing launch
+    const uint32_t per_group = v == 8 ? 512u : v == 9 ? 256u * (grid == 1 ? 1u : 2u) : 256u;
+    a.store_wins = (seat_wins && !(flags & DVC_ROLLOUT_ACCUMULATE) && (v == 7 || v == 8 || v == 9) &&
+                    (uint32_t)ppl <= per_group && per_group % (uint32_t)ppl == 0u &&
+                    (v != 9 || per_group / (uint32_t)ppl <= 16u)) ? 1u : 0u;
     if (a.total == 0) return DVC_OK;
     if (seat_wins && !(flags & DVC_ROLLOUT_ACCUMULATE) && !a.store_wins) {
         hipError_t e = launch_fill_u32(seat_wins, (uint64_t)n_leaves * 4u, 0u, st);
@@ -363,9 +370,9 @@ int dvc_rollout_ex(const dvc_state_t *leaves, int64_t n_leaves, int32_t ppl, uin
     if ((flags & ~DVC_ROLLOUT_ACCUMULATE) != 0) return DVC_EINVAL;
     const int ok = rollout_args_ok(leaves, n_leaves, ppl);
     if (ok != DVC_OK) return ok;
-    if (variant < 0 || variant > 8) return DVC_EINVAL;
+    if (variant < 0 || variant > 9) return DVC_EINVAL;
     if (block != 0 && block != 64 && block != 128 && block != 256 && block != 512) return DVC_EINVAL;
-    if (grid < 0) return DVC_EINVAL;
+    if (grid < 0 || (variant == 9 && grid > 2)) return DVC_EINVAL;
     const Shape sh = variant != 0 ? Shape{variant, block, grid}
                                   : automatic_shape((uint64_t)n_leaves * (uint64_t)ppl, ppl);
     return rollout_impl(leaves, n_leaves, ppl, seed, tree_id, leaf_id_base, winner, length,
@@ -380,8 +387,8 @@ int dvc_rollout_autotune(const dvc_state_t *leaves, int64_t n_leaves, int32_t pp
     if (ok != DVC_OK) return ok;
     const uint64_t total = (uint64_t)n_leaves * (uint64_t)ppl;
     if (total == 0) return DVC_EINVAL;
-    static const Shape kCandidates[] = {{7, 0, 2}, {8, 0, 0}, {4, 0, 1}, {1, 0, 0}, {4, 0, 2},
-                                        {5, 0, 2}, {5, 0, 4}, {5, 0, 8}};
+    static const Shape kCandidates[] = {{7, 0, 2}, {9, 0, 2}, {9, 0, 1}, {8, 0, 0}, {4, 0, 1},
+                                        {1, 0, 0}, {4, 0, 2}, {5, 0, 2}, {5, 0, 4}, {5, 0, 8}};
     hipStream_t st = (hipStream_t)stream;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {

@@ -901,6 +901,146 @@ __global__ void __launch_bounds__(256) rollout_compact2(RolloutArgs a)
 }
 
 // ---------------------------------------------------------------------------
+// Variant 9: variant 7's compaction, with the lanes it frees refilled.
+//
+// Compaction alone retires a wavefront once its workgroup's games fit in
+// fewer lanes, and a new workgroup starts only when a whole workgroup's
+// wavefront slots are free: at 1M playouts the SIMDs held 4.4 wavefronts on
+// average against the 8 their registers allow.  Here a workgroup owns `span`
+// consecutive playouts (256 K): its lanes start on the first 256, and every
+// kRefillCheck steps the unfinished games are packed into the first lanes
+// (in lane order, through LDS) and the lanes behind them start the range's
+// next playouts, so the wavefronts stay full until the range runs out and
+// the whole grid can be resident at once.  Each game carries its own number
+// of guesses, which sets its Philox step counter and its length.  Outcomes
+// are kept per playout of the range in LDS and written out as variant 7
+// writes them, so every output equals the other variants'.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kRefillCheck = 4u;        // guesses between checkpoints
+constexpr uint32_t kRefillMaxSpan = 512u;    // playouts per workgroup
+constexpr uint32_t kRefillLeafCache = 16u;   // leaf states of the range kept in LDS
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8)))
+rollout_compact_refill(RolloutArgs a, uint32_t span)
+{
+    __shared__ uint8_t tab[kKthTableBytes];
+    __shared__ uint32_t mig[8][256];   // packed state, playout id, round-1 key words, guesses
+    __shared__ uint8_t outc[kRefillMaxSpan];
+    __shared__ uint4 leafst[kRefillLeafCache];
+    __shared__ uint32_t lsum[kRefillLeafCache * 4u];   // store_wins: seat wins per leaf
+    __shared__ uint32_t wcnt[4];
+    fill_kth_table(tab);
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
+    const uint32_t base = blockIdx.x * span;          // < total: the grid covers it exactly
+    const uint32_t end = a.total - base < span ? a.total : base + span;
+    const uint32_t leaf0 = base / a.ppl, nleaf = (end - 1u) / a.ppl - leaf0 + 1u;
+    const bool cached = nleaf <= kRefillLeafCache;    // else leaf states from memory
+    if (cached && tid < nleaf) leafst[tid] = a.leaves[leaf0 + tid];
+    for (uint32_t i = tid; i < span; i += 256u) outc[i] = (uint8_t)kOutError;
+    if (tid < 4u * kRefillLeafCache) lsum[tid] = 0u;
+    const uint32_t trk1 = a.tree ^ a.k1;
+    __syncthreads();   // table, leaf states, outcomes
+
+    uint32_t j = 0u, winner = 0u, len = 0u;
+    bool live = false;
+    State s;
+    s.h0 = s.h1 = s.h2 = s.h3 = s.rev = 0u;
+    s.m = 0u; s.P = 2u; s.phase = 1u; s.drawn = -1;
+    PlayoutKey pk = {0u, 0u, 0u, 0u};
+    // playout jj of the range starts in this lane (a game decided before any
+    // guess is recorded at once; a malformed leaf keeps the error outcome)
+    auto start = [&](uint32_t jj) __attribute__((always_inline)) {
+        j = jj;
+        len = 0u;
+        const uint32_t leaf = jj / a.ppl;
+        const uint4 st = cached ? leafst[leaf - leaf0] : a.leaves[leaf];
+        if (!decode(st.x, st.y, st.z, st.w, s)) {
+            atomicOr(&g_error_word, kErrState);
+            return;
+        }
+        const uint32_t alive = alive_mask(s);
+        winner = (uint32_t)__builtin_ctz(alive | 16u);
+        if (__popc(alive) == 1) {
+            outc[jj - base] = (uint8_t)winner;
+            return;
+        }
+        live = true;
+        pk = playout_key(jj - leaf * a.ppl, a.leaf_base + leaf, a.k0);
+    };
+    if (base + tid < end) start(base + tid);
+    uint32_t next = base + 256u;   // the range's next playout to start
+    for (;;) {
+        for (uint32_t c = 0; c < kRefillCheck; ++c) {
+            if (__ballot(live) == 0ull) break;
+            if (live) {
+                const Words w = step_words(pk, trk1, a.k0, a.k1);
+                const bool over = guess_step(s, w, winner, tab);
+                next_step(pk);
+                ++len;
+                if (over) {
+                    outc[j - base] = (uint8_t)(winner | (len << 2));
+                    live = false;
+                } else if (len >= kMaxGuesses) {
+                    // still undecided after the most guesses a valid game can take
+                    atomicOr(&g_error_word, kErrLimit);
+                    live = false;
+                }
+            }
+        }
+        // pack the unfinished games into the first lanes, refill the rest
+        const uint64_t lm = __ballot(live);
+        if (lane == 0u) wcnt[wv] = (uint32_t)__popcll(lm);
+        __syncthreads();
+        uint32_t before = 0u, n_live = 0u;
+#pragma unroll
+        for (uint32_t w = 0; w < 4u; ++w) {
+            const uint32_t c = wcnt[w];
+            before += w < wv ? c : 0u;
+            n_live += c;
+        }
+        if (n_live == 0u && next >= end) break;   // the same in every lane
+        if (live) {
+            const uint32_t dst = before + __builtin_amdgcn_mbcnt_hi(
+                (uint32_t)(lm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)lm, 0u));
+            uint32_t e0, e1, e2, e3;
+            encode(s, e0, e1, e2, e3);
+            mig[0][dst] = e0;
+            mig[1][dst] = e1;
+            mig[2][dst] = e2;
+            mig[3][dst] = e3;
+            mig[4][dst] = j;
+            mig[5][dst] = pk.a;
+            mig[6][dst] = pk.b;
+            mig[7][dst] = len;
+        }
+        __syncthreads();
+        live = tid < n_live;
+        if (live) {
+            unpack_valid(mig[0][tid], mig[1][tid], mig[2][tid], mig[3][tid], s);
+            j = mig[4][tid];
+            pk.a = mig[5][tid];
+            pk.b = mig[6][tid];
+            len = mig[7][tid];
+            const uint64_t gm = (uint64_t)len * kPhiloxM0;   // the step counter times M0
+            pk.gm_lo = (uint32_t)gm;
+            pk.gm_hi = (uint32_t)(gm >> 32);
+        } else if (next + (tid - n_live) < end) {
+            start(next + (tid - n_live));
+        }
+        next += 256u - n_live;
+    }
+    __syncthreads();   // every game's outcome is in outc
+    const bool store = a.store_wins != 0u && cached;
+    for (uint32_t i = tid; i < span; i += 256u)
+        emit_outcome(a, base + i, outc[i], lane, store ? lsum : nullptr, leaf0);
+    if (!store) return;
+    // the workgroup holds whole leaves: store each leaf's four counts once,
+    // over whatever the table held
+    __syncthreads();
+    if (a.seat_wins && tid < 4u * nleaf) a.seat_wins[(size_t)leaf0 * 4u + tid] = lsum[tid];
+}
+
+// ---------------------------------------------------------------------------
 // Variant 5: one wavefront per single-leaf item of up to 64*K playouts.  A
 // lane whose game ended takes the item's next playout at once (ballot +
 // mbcnt prefix over the lanes that finished); the leaf's start state stays
@@ -1066,6 +1206,14 @@ hipError_t launch_rollout(const RolloutArgs &a, int variant, int block, int grid
         // two games per lane, compacted at steps 5, 8, 11, 14
         const uint32_t blocks = (a.total + 511u) / 512u;
         hipLaunchKernelGGL(rollout_compact2, dim3(blocks), dim3(256), 0, st, a);
+        return hipGetLastError();
+    }
+    if (variant == 9) {
+        // K = grid (1 or 2, default 2) batches of 256 playouts per workgroup,
+        // compacted and refilled every four guesses
+        const uint32_t span = 256u * (grid == 1 ? 1u : 2u);
+        const uint32_t blocks = (uint32_t)((a.total + span - 1u) / span);
+        hipLaunchKernelGGL(rollout_compact_refill, dim3(blocks), dim3(256), 0, st, a, span);
         return hipGetLastError();
     }
     if (variant == 5) {

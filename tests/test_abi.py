@@ -57,10 +57,12 @@ def test_argument_errors_without_device(lib):
     assert lib.dvc_rollout_ex(None, 0, 0, 0, 0, 0, None, None, None, 0, 0, 0, 0, None) == -1
     # unknown flag
     assert lib.dvc_rollout_ex(vp(16), 1, 8, 0, 0, 0, None, None, None, 0, 0, 0, 2, None) == -1
-    # kernel variants 0-8 exist; 9 and negative ones do not
-    for bad in (9, -1):
+    # kernel variants 0-9 exist; 10 and negative ones do not; variant 9 takes
+    # one or two 256-playout batches per workgroup
+    for bad in (10, -1):
         assert lib.dvc_rollout_ex(vp(16), 1, 8, 0, 0, 0, None, None, None, bad, 0, 0, 0,
                                   None) == -1
+    assert lib.dvc_rollout_ex(vp(16), 1, 8, 0, 0, 0, None, None, None, 9, 0, 3, 0, None) == -1
     # n * ppl must stay below 2^32
     assert lib.dvc_rollout_ex(vp(16), 1 << 20, 1 << 12, 0, 0, 0, None, None, None, 0, 0, 0, 0,
                               None) == -1

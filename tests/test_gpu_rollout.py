@@ -70,7 +70,7 @@ def _compare(dvc, states_np, ppl, seed, tree, base, ref, **kw):
     assert np.array_equal(sw.cpu().numpy().view(np.uint32), rs), "seat wins"
 
 
-@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6, 7, 8, 9])
 @pytest.mark.parametrize("P", [2, 3, 4])
 def test_rollout_bit_exact_small(orc, dvc, variant, P):
     po = orc.deal_params(p_min=P, p_max=P, pile_min=0, pile_max=16, revealed_max=8, phase_mix=1)
@@ -92,7 +92,7 @@ def test_rollout_schedule_invariance(orc, dvc, variant, block, grid):
     _compare(dvc, S, ppl, 77, 3, 0, ref, variant=variant, block=block, grid=grid)
 
 
-@pytest.mark.parametrize("variant", [2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("variant", [2, 3, 4, 5, 6, 7, 8, 9])
 @pytest.mark.parametrize("ppl", [1, 2, 63, 64, 65, 129, 1000])
 def test_rollout_ppl_edges(orc, dvc, variant, ppl):
     po = orc.deal_params(p_min=2, p_max=3, pile_min=0, pile_max=16, revealed_max=8)
@@ -122,6 +122,21 @@ def test_rollout_compacted_long_games(orc, dvc, sched, ppl):
     ref = _rollout_ref(orc, S, ppl, 6, 2, 40)
     assert ref[1].max() >= 15, "the batch should reach past the last checkpoint"
     _compare(dvc, S, ppl, 6, 2, 40, ref, variant=7, grid=sched)
+
+
+@pytest.mark.parametrize("K", [1, 2])
+@pytest.mark.parametrize("ppl", [1, 16, 37, 100, 256, 512, 700])
+def test_rollout_compacted_refilled_long_games(orc, dvc, K, ppl):
+    """Variant 9 packs unfinished games every four guesses and starts the
+    workgroup's next playouts in the lanes it frees (workgroups of 256 and 512
+    playouts): games of up to 23 guesses, leaves spanning workgroups, several
+    leaves per workgroup, more leaves than the workgroup keeps in LDS (ppl
+    1 and 16), a ragged last workgroup."""
+    po, _ = deal_pair(orc, dvc, p_min=2, p_max=4, fresh=1, root_draw=1)
+    S = orc.init_states(37, po, seed=7)
+    ref = _rollout_ref(orc, S, ppl, 6, 2, 40)
+    assert ref[1].max() >= 15, "the batch should reach past several checkpoints"
+    _compare(dvc, S, ppl, 6, 2, 40, ref, variant=9, grid=K)
 
 
 @pytest.mark.parametrize("K", [1, 2, 4, 8])
@@ -176,7 +191,8 @@ def test_rollout_autotune(orc, dvc):
     assert dvc.dvc_check() == 0
 
 
-@pytest.mark.parametrize("variant,ppl", [(0, 24), (7, 64), (7, 256), (8, 64), (8, 512)])
+@pytest.mark.parametrize("variant,ppl", [(0, 24), (7, 64), (7, 256), (8, 64), (8, 512), (9, 32),
+                                         (9, 256)])
 def test_rollout_accumulate(orc, dvc, variant, ppl):
     """Two calls with different seeds tally into one seat-win table (variant 7
     with whole leaves per workgroup, which stores its sums when overwriting,
@@ -194,7 +210,7 @@ def test_rollout_accumulate(orc, dvc, variant, ppl):
     assert np.array_equal(sw.cpu().numpy().view(np.uint32), r1 + r2)
 
 
-@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6, 7, 8, 9])
 def test_rollout_decided_and_malformed_leaves(orc, dvc, variant):
     import positions as POS
     rng = np.random.default_rng(9)
@@ -225,7 +241,9 @@ def test_rollout_argument_errors(dvc):
     with pytest.raises(dvc.DvcError):
         dvc.dvc_rollout(st, 0, 1)
     with pytest.raises(dvc.DvcError):
-        dvc.dvc_rollout(st, 8, 1, variant=9)
+        dvc.dvc_rollout(st, 8, 1, variant=10)
+    with pytest.raises(dvc.DvcError):
+        dvc.dvc_rollout(st, 8, 1, variant=9, grid=3)
     with pytest.raises(dvc.DvcError):
         dvc.dvc_rollout(st, 8, 1, variant=3, block=96)
     with pytest.raises(dvc.DvcError):
@@ -245,7 +263,8 @@ def test_rollout_full_leaf_parallel_workload(orc, dvc):
     st = dvc.dvc_init_states(4096, pd, seed=2)
     assert np.array_equal(to_np(st), S)
     ref = _rollout_ref(orc, S, 256, 2, 0, 0)
-    for variant, grid in [(1, 0), (2, 0), (3, 0), (4, 0), (5, 0), (6, 0), (7, 0), (7, 2), (8, 0)]:
+    for variant, grid in [(1, 0), (2, 0), (3, 0), (4, 0), (5, 0), (6, 0), (7, 0), (7, 2), (8, 0),
+                          (9, 1), (9, 2)]:
         w, ln, sw = dvc.dvc_rollout(st, 256, 2, 0, 0, variant=variant, grid=grid)
         torch.cuda.synchronize()
         assert np.array_equal(w.cpu().numpy(), ref[0])
@@ -271,8 +290,8 @@ def test_valu_probe(dvc):
         measure.probe_valu(6, 2, 3, sink)
 
 
-@pytest.mark.parametrize("variant", [4, 6, 7, 8])
-@pytest.mark.parametrize("ppl", [1, 3, 64, 100, 256, 300])
+@pytest.mark.parametrize("variant", [4, 6, 7, 8, 9])
+@pytest.mark.parametrize("ppl", [1, 3, 32, 64, 100, 256, 300])
 def test_rollout_seat_wins_overwrite_the_table(orc, dvc, variant, ppl):
     """Without accumulate the seat-win table is overwritten (zeroed, then
     added to; variant 7 with playouts per leaf dividing 256 stores each leaf's
