@@ -61,9 +61,9 @@ OPS_PER_GUESS = 222
 # scaled by what the same counter reads for a plain 256 MiB device copy
 # (FETCH_SIZE reads half the bytes moved, WRITE_SIZE all of them).  Valid
 # only for the kernel sources it was taken on: reported as null otherwise.
-PROFILED_TRAFFIC = {"fetch_kib": 381.5, "fetch_scale": 2.0, "write_kib": 3200.0,
+PROFILED_TRAFFIC = {"fetch_kib": 389.0, "fetch_scale": 2.0, "write_kib": 3200.0,
                     "write_scale": 1.0,
-                    "sources_sha256": "18356cf6d0a7abfed40d7ec5de1177ccb58936d0bb59b2b2409cec9588156adb"}
+                    "sources_sha256": "4a5602a6a9b36d960a77f1f55cb6796c32ec8d0035adf9a5417c391051190a14"}
 # Instructions one tree issues per iteration in the batched search (both
 # wavefronts of a pipelined tree), from the SQ instruction counters of a
 # profiler pass over `experiments --what phases` (VALU + SALU + LDS + SMEM +
