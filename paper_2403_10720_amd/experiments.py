@@ -336,10 +336,10 @@ def tree_variants(n_roots=512, iterations=1024, ppl=32, seed=3, ref_trees=32):
 
 
 def leaf_batching(seed=3):
-    """Leaves evaluated together (leaves_per_pass B) on the batched and the
-    single-tree workloads: time per launch, and how often the decisions agree
-    with B = 1 next to how often two B = 1 searches with different seeds
-    agree."""
+    """Leaves evaluated together (leaves_per_pass B), sequential and
+    pipelined passes, on the batched and the single-tree workloads: time per
+    launch, and how often the decisions agree with B = 1 (sequential) next to
+    how often two B = 1 searches with different seeds agree."""
     out = {}
     for name, (n, deal, iters, ppl, sd) in SEARCH_WORKLOADS.items():
         if "4096" in name:
@@ -347,10 +347,11 @@ def leaf_batching(seed=3):
         roots = dvc_init_states(n, deal_params(**deal), sd)
         rows = {}
         ref = ref2 = None
-        for B in (1, 2, 4, 8):
+        for B, pipe in ((1, 0), (2, 0), (4, 0), (8, 0), (1, 1), (2, 1), (4, 1), (8, 1)):
             if B * ppl > 256:
                 continue
-            mp = mcts_params(iterations=iters, playouts_per_leaf=ppl, max_depth=4, leaves_per_pass=B)
+            mp = mcts_params(iterations=iters, playouts_per_leaf=ppl, max_depth=4, leaves_per_pass=B,
+                             pipeline=pipe)
             ws = torch.empty(dvc_mcts_workspace_bytes(n, mp), dtype=torch.uint8, device=roots.device)
             mcts_search(roots, mp, sd + 1, workspace=ws, want_children=False)   # warm-up
             reps = 3 if n > 1 else 5
@@ -360,10 +361,11 @@ def leaf_batching(seed=3):
                                                           want_children=False))
                 times.append(t)
             times.sort()
-            if B == 1:
+            if B == 1 and not pipe:
                 ref = best
                 ref2, _ = mcts_search(roots, mp, sd + 1000, workspace=ws, want_children=False)
-            rows[f"B{B}"] = {"ms_per_launch": times[len(times) // 2] * 1e3,
+            rows[f"B{B}" + ("_pipelined" if pipe else "")] = {
+                             "ms_per_launch": times[len(times) // 2] * 1e3,
                              "decisions_per_s": n / times[len(times) // 2],
                              "agreement_with_B1": float((best == ref).float().mean().item())}
         rows["B1_two_seeds_agree"] = float((ref2 == ref).float().mean().item())
