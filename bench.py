@@ -205,13 +205,15 @@ def autotuned_search(D, torch, reps=3, tolerance=0.02):
             "playouts_per_s": n * iters * choice["playouts_per_leaf"] / (best / 1e3)}
 
 
-def root_parallel_search(D, torch, reps=3):
+def root_parallel_search(D, torch, reps=3, leaves_per_pass=1, pipeline=0):
     """The paper's decomposition: 64 fresh 2-4 player deals, 32 independent
-    trees each (1024 iterations x 32 playouts, depth 4), amalgamated at the root."""
+    trees each (1024 iterations x 32 playouts, depth 4), amalgamated at the
+    root; optionally each tree with two leaves per pass, pipelined."""
     n, K, iters, ppl = 64, 32, 1024, 32
     roots = D.dvc_init_states(n, D.deal_params(p_min=2, p_max=4, hand=(0, 0, 4, 4, 3), fresh=1,
                                                root_draw=1), 6)
-    mp = D.mcts_params(iterations=iters, playouts_per_leaf=ppl, max_depth=4)
+    mp = D.mcts_params(iterations=iters, playouts_per_leaf=ppl, max_depth=4,
+                       leaves_per_pass=leaves_per_pass, pipeline=pipeline)
     ws = torch.empty(D.dvc_mcts_workspace_bytes(n * K, mp), dtype=torch.uint8, device=roots.device)
     D.mcts_search_root_parallel(roots, K, mp, 6, workspace=ws, want_children=False)
     torch.cuda.synchronize()
@@ -225,7 +227,9 @@ def root_parallel_search(D, torch, reps=3):
         ms.append(e0.elapsed_time(e1))
     best = min(ms)
     return {"workload": "64 fresh 2-4 player deals x 32 trees x 1024 iterations x 32 playouts, "
-                        "depth 4, merged at the root", "ms_per_launch": best,
+                        "depth 4, merged at the root" +
+                        (f", {leaves_per_pass} leaves per pass" if leaves_per_pass > 1 else "") +
+                        (", pipelined passes" if pipeline else ""), "ms_per_launch": best,
             "decisions_per_s": n / (best / 1e3), "playouts_per_s": n * K * iters * ppl / (best / 1e3)}
 
 
@@ -481,6 +485,8 @@ def main():
         out["batched_search_pipelined"] = batched_search(D, torch, leaves_per_pass=2, pipeline=1)
         out["batched_search_autotuned"] = autotuned_search(D, torch)
         out["root_parallel_search"] = root_parallel_search(D, torch)
+        out["root_parallel_search_pipelined"] = root_parallel_search(D, torch, leaves_per_pass=2,
+                                                                     pipeline=1)
         out["single_tree_search"] = single_tree_search(D, torch)
         out["single_tree_search_leaf_batched"] = single_tree_search(D, torch, leaves_per_pass=4)
         out["single_tree_search_pipelined"] = single_tree_search(D, torch, leaves_per_pass=4,

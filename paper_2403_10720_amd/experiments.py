@@ -25,7 +25,8 @@ search_phases(): where the iterations of the three search workloads spend
 their cycles (sampling a world, descending, evaluating, back-propagating).
 
 gpu_scaling(): playouts/s against the number of wavefronts (the paper's
-GPU thread sweep).
+GPU thread sweep); search_scaling(): decisions/s of the batched search
+against the number of trees.
 
 ppl_autotune(): playouts per leaf of the batched search picked by
 measurement, with its root-move agreement.
@@ -430,6 +431,27 @@ def search_phases(net=None):
     return out
 
 
+def search_scaling(counts=(64, 256, 1024, 2048, 4096, 8192), iterations=1024, ppl=32, seed=3,
+                   reps=3):
+    """Decisions/s of the batched search against the number of trees (mid-game
+    2-4 player roots, 1024 iterations x 32 playouts, depth 4), sequential
+    passes and two leaves per pass pipelined: where the GPU fills up."""
+    deal = SEARCH_WORKLOADS["batched, 2048 mid-game roots, 1024 x 32"][1]
+    out = {}
+    for n in counts:
+        roots = dvc_init_states(n, deal_params(**deal), seed)
+        row = {}
+        for name, kw in (("sequential", dict()), ("pipelined", dict(leaves_per_pass=2, pipeline=1))):
+            mp = mcts_params(iterations=iterations, playouts_per_leaf=ppl, max_depth=4, **kw)
+            ws = torch.empty(dvc_mcts_workspace_bytes(n, mp), dtype=torch.uint8,
+                             device=roots.device)
+            _, t = median_search(roots, mp, seed, ws, reps)
+            row[name] = {"ms_per_launch": t * 1e3, "decisions_per_s": n / t}
+            del ws
+        out[str(n)] = row
+    return out
+
+
 def gpu_scaling(waves=(1, 4, 16, 64, 256, 1024, 2048, 4096, 8192), games_per_lane=16, reps=3):
     """Playouts/s against the number of wavefronts running playouts (the
     paper's simulations/s against GPU threads, Sec. IV): the persistent
@@ -500,7 +522,7 @@ def main(argv=None):
     import json
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--what", choices=["value", "root-parallel", "phases", "scaling", "ppl",
-                                       "variants", "batching", "all"],
+                                       "variants", "batching", "search-scaling", "all"],
                     default="all")
     ap.add_argument("--trees", type=int, default=1024)
     ap.add_argument("--iterations", type=int, default=4096)
@@ -521,6 +543,8 @@ def main(argv=None):
         print(json.dumps({"gpu_scaling": gpu_scaling()}), flush=True)
     if args.what in ("batching", "all"):
         print(json.dumps({"leaf_batching": leaf_batching()}), flush=True)
+    if args.what in ("search-scaling", "all"):
+        print(json.dumps({"search_scaling": search_scaling()}), flush=True)
     if args.what in ("variants", "all"):
         print(json.dumps({"tree_variants": tree_variants()}), flush=True)
     if args.what in ("phases", "all"):
