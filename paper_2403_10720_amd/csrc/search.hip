@@ -539,6 +539,7 @@ mcts_tree_kernel(MctsArgs a)
     __shared__ float vals_all[TG][NBUF][BM][4];
     __shared__ DfsSlots dfs_all[TG];
     __shared__ uint4 fb_rows[TG];   // rows of the sampler's fallback world
+    __shared__ uint8_t fslot_all[TG][64];   // the sampler's failed iterations of a batch
     // worlds of a pass sampled by the evaluating wavefront (rows; flag 1:
     // the sampler gave up)
     __shared__ uint4 wrows_all[ESAMPLE ? 2 : 1][ESAMPLE ? BM : 1];
@@ -673,11 +674,57 @@ mcts_tree_kernel(MctsArgs a)
     auto sample_world = [&](uint32_t it, State &S) __attribute__((always_inline)) -> bool {
         if ((it & 63u) == 0u) {
             State Sw;
+            const bool valid = it + lane < a.iters;
             const bool got0 = det_attempt(R, 0u, it + lane, tr, a.k0, a.k1, Sw, tab);
-            wok = __ballot(got0 && it + lane < a.iters);
+            wok = __ballot(got0 && valid);
             wpl0 = Sw.h0 | Sw.h2;
             wpl1 = Sw.h1 | Sw.h2;
             wpl2 = Sw.h3;
+            // Second stage: the iterations whose attempt 0 failed try attempts
+            // 1 .. K side by side, 64 / K iterations per pass, K set by the
+            // batch's attempt-0 success rate (4 from 30 %, 8 from 10 %, 16
+            // from 4 %, 32 from 2 %; below that none).  Each keeps its lowest
+            // successful attempt; one still without any runs all 64 attempts
+            // on its own below, whose lowest success lies past K.
+            const uint64_t vmask = __ballot(valid);
+            const uint64_t fail = vmask & ~wok;
+            const uint32_t nok = (uint32_t)__popcll(wok), nval = (uint32_t)__popcll(vmask);
+            const uint32_t K = (fail == 0ull || nok * 50u < nval) ? 0u
+                             : nok * 10u >= nval * 3u ? 4u
+                             : nok * 10u >= nval ? 8u
+                             : nok * 25u >= nval ? 16u : 32u;
+            if (K != 0u) {
+                uint8_t *fslot = fslot_all[wv];   // slot r: the lane of the r-th failed iteration
+                if ((fail >> lane) & 1ull)
+                    fslot[__builtin_amdgcn_mbcnt_hi((uint32_t)(fail >> 32),
+                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)fail, 0u))] =
+                        (uint8_t)lane;
+                tree_sync<WS>();
+                const uint32_t nf = (uint32_t)__popcll(fail), G = 64u / K;
+                const uint32_t g = lane / K, att = 1u + lane % K;
+                for (uint32_t p0 = 0; p0 < nf; p0 += G) {
+                    const bool act = p0 + g < nf;
+                    const uint32_t fl = act ? fslot[p0 + g] : 0u;
+                    State Sa;
+                    const bool got = act && det_attempt(R, att, it + fl, tr, a.k0, a.k1, Sa, tab);
+                    const uint64_t gotm = __ballot(got);
+                    const uint32_t q0 = Sa.h0 | Sa.h2, q1 = Sa.h1 | Sa.h2, q2 = Sa.h3;
+                    for (uint32_t gg = 0; gg < G && p0 + gg < nf; ++gg) {
+                        const uint64_t m = (gotm >> (gg * K)) & ((1ull << K) - 1ull);
+                        if (m == 0ull) continue;
+                        const uint32_t src = gg * K + (uint32_t)__builtin_ctzll(m);
+                        const uint32_t dst = fslot[p0 + gg];
+                        const uint32_t v0 = __builtin_amdgcn_readlane(q0, src);
+                        const uint32_t v1 = __builtin_amdgcn_readlane(q1, src);
+                        const uint32_t v2 = __builtin_amdgcn_readlane(q2, src);
+                        wpl0 = lane == dst ? v0 : wpl0;
+                        wpl1 = lane == dst ? v1 : wpl1;
+                        wpl2 = lane == dst ? v2 : wpl2;
+                        wok |= 1ull << dst;
+                    }
+                }
+                tree_sync<WS>();   // the slots are read; the next batch may write them
+            }
         }
         const uint32_t wl = it & 63u;
         if ((wok >> wl) & 1u) {
