@@ -604,11 +604,10 @@ mcts_tree_kernel(MctsArgs a)
     uint32_t n_net = 0u, n_played = 0u, n_sampler_fallback = 0u, deepest = 0u;   // statistics
     bool failed = false, have_fallback = false;
     uint64_t cyc[4] = {0u, 0u, 0u, 0u};   // shader clock per phase (statistics)
-    // Worlds of iterations ib .. ib + 63 by attempt 0, sampled together (lane
-    // l: iteration ib + l) at every 64th iteration: the world's rows as owner
-    // bit-planes, and the lanes whose attempt succeeded.  An iteration whose
-    // attempt 0 failed runs all 64 attempts on its own below; its lowest
-    // successful attempt is the same one either way.
+    // Worlds of iterations ib .. ib + 63, sampled together (lane l: iteration
+    // ib + l) at every 64th iteration: the world's rows as owner bit-planes,
+    // and the lanes whose iteration has a world (the others take the
+    // fallback world).
     uint32_t wpl0 = 0u, wpl1 = 0u, wpl2 = 0u;
     uint64_t wok = 0u;
     // The root's first two child blocks (in LDS), its guess bitmap words
@@ -666,11 +665,13 @@ mcts_tree_kernel(MctsArgs a)
     // iteration order.  B = 1 is the plain sequential search.
     const uint32_t nplay = VALUE ? a.fb_ppl : a.ppl;   // visits of every leaf
     // ---- 1. sample the world of iteration `it`: its lowest successful
-    // attempt.  Worlds of iterations ib .. ib + 63 by attempt 0 are sampled
-    // together at every 64th iteration; an iteration whose attempt 0 failed
-    // runs all 64 attempts on its own (the lowest successful one is the same
-    // either way), and one with none left takes the fallback world.  Returns
-    // false when the fallback search gives up.
+    // attempt, else the fallback world.  The worlds of iterations ib .. ib +
+    // 63 are sampled together at every 64th iteration: attempt 0 of each in
+    // its own lane, then rounds in which the iterations still without a world
+    // try attempts a0 .. a0 + K - 1 side by side, 64 / K iterations per pass,
+    // for K = 4, 8, 16, 32 and the last 3 (attempts 1 .. 63 in five rounds).
+    // Every iteration keeps its lowest successful attempt.  Returns false
+    // when the fallback search gives up.
     auto sample_world = [&](uint32_t it, State &S) __attribute__((always_inline)) -> bool {
         if ((it & 63u) == 0u) {
             State Sw;
@@ -680,39 +681,33 @@ mcts_tree_kernel(MctsArgs a)
             wpl0 = Sw.h0 | Sw.h2;
             wpl1 = Sw.h1 | Sw.h2;
             wpl2 = Sw.h3;
-            // Second stage: the iterations whose attempt 0 failed try attempts
-            // 1 .. K side by side, 64 / K iterations per pass, K set by the
-            // batch's attempt-0 success rate (4 from 30 %, 8 from 10 %, 16
-            // from 4 %, 32 from 2 %; below that none).  Each keeps its lowest
-            // successful attempt; one still without any runs all 64 attempts
-            // on its own below, whose lowest success lies past K.
             const uint64_t vmask = __ballot(valid);
-            const uint64_t fail = vmask & ~wok;
-            const uint32_t nok = (uint32_t)__popcll(wok), nval = (uint32_t)__popcll(vmask);
-            const uint32_t K = (fail == 0ull || nok * 50u < nval) ? 0u
-                             : nok * 10u >= nval * 3u ? 4u
-                             : nok * 10u >= nval ? 8u
-                             : nok * 25u >= nval ? 16u : 32u;
-            if (K != 0u) {
-                uint8_t *fslot = fslot_all[wv];   // slot r: the lane of the r-th failed iteration
-                if ((fail >> lane) & 1ull)
-                    fslot[__builtin_amdgcn_mbcnt_hi((uint32_t)(fail >> 32),
-                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)fail, 0u))] =
+            uint8_t *fslot = fslot_all[wv];   // slot r: the lane of the r-th iteration left
+            uint32_t a0 = 1u;
+            for (uint32_t K = 4u; a0 < kDetAttempts; K *= 2u) {
+                const uint64_t left = vmask & ~wok;
+                if (left == 0ull) break;
+                const uint32_t Kr = kDetAttempts - a0 < K ? kDetAttempts - a0 : K;
+                tree_sync<WS>();   // the previous round has read its slots
+                if ((left >> lane) & 1ull)
+                    fslot[__builtin_amdgcn_mbcnt_hi((uint32_t)(left >> 32),
+                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)left, 0u))] =
                         (uint8_t)lane;
                 tree_sync<WS>();
-                const uint32_t nf = (uint32_t)__popcll(fail), G = 64u / K;
-                const uint32_t g = lane / K, att = 1u + lane % K;
-                for (uint32_t p0 = 0; p0 < nf; p0 += G) {
-                    const bool act = p0 + g < nf;
+                const uint32_t nl = (uint32_t)__popcll(left), G = 64u / Kr;
+                const uint32_t g = lane / Kr, att = a0 + lane % Kr;
+                const uint64_t gmask = (1ull << Kr) - 1ull;
+                for (uint32_t p0 = 0; p0 < nl; p0 += G) {
+                    const bool act = g < G && p0 + g < nl;
                     const uint32_t fl = act ? fslot[p0 + g] : 0u;
                     State Sa;
                     const bool got = act && det_attempt(R, att, it + fl, tr, a.k0, a.k1, Sa, tab);
                     const uint64_t gotm = __ballot(got);
                     const uint32_t q0 = Sa.h0 | Sa.h2, q1 = Sa.h1 | Sa.h2, q2 = Sa.h3;
-                    for (uint32_t gg = 0; gg < G && p0 + gg < nf; ++gg) {
-                        const uint64_t m = (gotm >> (gg * K)) & ((1ull << K) - 1ull);
+                    for (uint32_t gg = 0; gg < G && p0 + gg < nl; ++gg) {
+                        const uint64_t m = (gotm >> (gg * Kr)) & gmask;
                         if (m == 0ull) continue;
-                        const uint32_t src = gg * K + (uint32_t)__builtin_ctzll(m);
+                        const uint32_t src = gg * Kr + (uint32_t)__builtin_ctzll(m);
                         const uint32_t dst = fslot[p0 + gg];
                         const uint32_t v0 = __builtin_amdgcn_readlane(q0, src);
                         const uint32_t v1 = __builtin_amdgcn_readlane(q1, src);
@@ -723,7 +718,7 @@ mcts_tree_kernel(MctsArgs a)
                         wok |= 1ull << dst;
                     }
                 }
-                tree_sync<WS>();   // the slots are read; the next batch may write them
+                a0 += Kr;
             }
         }
         const uint32_t wl = it & 63u;
@@ -736,13 +731,6 @@ mcts_tree_kernel(MctsArgs a)
             S.h1 = ~p0 & p1 & ~p2 & kAll;
             S.h2 = p0 & p1 & ~p2;
             S.h3 = p2;
-            return true;
-        }
-        // attempt `lane` of this iteration (attempt 0 fails again)
-        const bool got = det_attempt(R, lane, it, tr, a.k0, a.k1, S, tab);
-        const uint64_t okm = __ballot(got);
-        if (okm) {
-            S = readlane_state(S, (uint32_t)__builtin_ctzll(okm));
             return true;
         }
         // the fallback world depends on the root only: search it once (it
