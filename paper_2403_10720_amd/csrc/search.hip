@@ -389,6 +389,15 @@ __device__ __forceinline__ void world_key(const State &S, uint32_t m, uint32_t &
     hi = (uint32_t)(key >> 32);
 }
 
+// v itself, in a vector register: the compiler keeps values computed from it
+// there as well, out of the scarce scalar registers
+__device__ __forceinline__ uint32_t in_vgpr(uint32_t v)
+{
+    uint32_t r;
+    asm("v_mov_b32 %0, %1" : "=v"(r) : "v"(v));
+    return r;
+}
+
 __device__ __forceinline__ State readlane_state(const State &s, uint32_t lane)
 {
     State r;
@@ -539,7 +548,8 @@ mcts_tree_kernel(MctsArgs a)
     __shared__ float vals_all[TG][NBUF][BM][4];
     __shared__ DfsSlots dfs_all[TG];
     __shared__ uint4 fb_rows[TG];   // rows of the sampler's fallback world
-    __shared__ uint8_t fslot_all[TG][64];   // the sampler's failed iterations of a batch
+    __shared__ uint8_t fslot_all[TG][64];   // the sampler's iterations left in a round
+    __shared__ uint4 wres_all[TG][64];      // and their worlds found in the round
     // worlds of a pass sampled by the evaluating wavefront (rows; flag 1:
     // the sampler gave up)
     __shared__ uint4 wrows_all[ESAMPLE ? 2 : 1][ESAMPLE ? BM : 1];
@@ -677,48 +687,46 @@ mcts_tree_kernel(MctsArgs a)
             State Sw;
             const bool valid = it + lane < a.iters;
             const bool got0 = det_attempt(R, 0u, it + lane, tr, a.k0, a.k1, Sw, tab);
-            wok = __ballot(got0 && valid);
+            wok = __ballot(got0 || !valid);   // lanes past the last iteration count as done
             wpl0 = Sw.h0 | Sw.h2;
             wpl1 = Sw.h1 | Sw.h2;
             wpl2 = Sw.h3;
-            const uint64_t vmask = __ballot(valid);
-            uint8_t *fslot = fslot_all[wv];   // slot r: the lane of the r-th iteration left
-            uint32_t a0 = 1u;
-            for (uint32_t K = 4u; a0 < kDetAttempts; K *= 2u) {
-                const uint64_t left = vmask & ~wok;
+            // round K: attempts K - 3 .. K - 3 + Kr - 1 (Kr = K, or 3 for the last)
+            uint8_t *fslot = fslot_all[wv];   // slot n: the lane of the n-th iteration left
+            uint4 *wres = wres_all[wv];       // lane l's world from this round (w = 1: found)
+            for (uint32_t K = 4u; K <= 64u; K *= 2u) {
+                const uint64_t left = ~wok;
                 if (left == 0ull) break;
-                const uint32_t Kr = kDetAttempts - a0 < K ? kDetAttempts - a0 : K;
-                tree_sync<WS>();   // the previous round has read its slots
+                const uint32_t Kr = K == 64u ? 3u : K;
+                tree_sync<WS>();   // the previous round has read its slots and worlds
                 if ((left >> lane) & 1ull)
                     fslot[__builtin_amdgcn_mbcnt_hi((uint32_t)(left >> 32),
                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)left, 0u))] =
                         (uint8_t)lane;
+                wres[lane].w = 0u;
                 tree_sync<WS>();
                 const uint32_t nl = (uint32_t)__popcll(left), G = 64u / Kr;
-                const uint32_t g = lane / Kr, att = a0 + lane % Kr;
-                const uint64_t gmask = (1ull << Kr) - 1ull;
+                const uint32_t g = lane / Kr, r = lane - g * Kr;
                 for (uint32_t p0 = 0; p0 < nl; p0 += G) {
                     const bool act = g < G && p0 + g < nl;
                     const uint32_t fl = act ? fslot[p0 + g] : 0u;
                     State Sa;
-                    const bool got = act && det_attempt(R, att, it + fl, tr, a.k0, a.k1, Sa, tab);
+                    const bool got = act && det_attempt(R, K - 3u + r, it + fl, tr, a.k0, a.k1, Sa,
+                                                        tab);
                     const uint64_t gotm = __ballot(got);
-                    const uint32_t q0 = Sa.h0 | Sa.h2, q1 = Sa.h1 | Sa.h2, q2 = Sa.h3;
-                    for (uint32_t gg = 0; gg < G && p0 + gg < nl; ++gg) {
-                        const uint64_t m = (gotm >> (gg * Kr)) & gmask;
-                        if (m == 0ull) continue;
-                        const uint32_t src = gg * Kr + (uint32_t)__builtin_ctzll(m);
-                        const uint32_t dst = fslot[p0 + gg];
-                        const uint32_t v0 = __builtin_amdgcn_readlane(q0, src);
-                        const uint32_t v1 = __builtin_amdgcn_readlane(q1, src);
-                        const uint32_t v2 = __builtin_amdgcn_readlane(q2, src);
-                        wpl0 = lane == dst ? v0 : wpl0;
-                        wpl1 = lane == dst ? v1 : wpl1;
-                        wpl2 = lane == dst ? v2 : wpl2;
-                        wok |= 1ull << dst;
-                    }
+                    // the group's lowest successful attempt hands its world to the iteration
+                    const uint64_t below = (gotm >> (act ? g * Kr : 0u)) & ((1ull << r) - 1ull);
+                    if (got && below == 0ull)
+                        wres[fl] = make_uint4(Sa.h0 | Sa.h2, Sa.h1 | Sa.h2, Sa.h3, 1u);
                 }
-                a0 += Kr;
+                tree_sync<WS>();
+                const uint4 wr = wres[lane];
+                if (wr.w != 0u) {
+                    wpl0 = wr.x;
+                    wpl1 = wr.y;
+                    wpl2 = wr.z;
+                }
+                wok |= __ballot(wr.w != 0u);
             }
         }
         const uint32_t wl = it & 63u;
@@ -984,6 +992,20 @@ mcts_tree_kernel(MctsArgs a)
             } else if (!sample_world(it, S)) {
                 failed = true;
                 break;
+            }
+            if (!PIPE) {
+                // the descent's state in vector registers: held in scalar
+                // ones it pushes other scalars out to spill slots (measured
+                // slower); the pipelined kernels run faster without this
+                S.h0 = in_vgpr(S.h0);
+                S.h1 = in_vgpr(S.h1);
+                S.h2 = in_vgpr(S.h2);
+                S.h3 = in_vgpr(S.h3);
+                S.rev = in_vgpr(S.rev);
+                S.m = in_vgpr(S.m);
+                S.P = in_vgpr(S.P);
+                S.phase = in_vgpr(S.phase);
+                S.drawn = in_vgpr(S.drawn);
             }
             const uint64_t t1 = clock64();
             cyc[0] += t1 - t0;
