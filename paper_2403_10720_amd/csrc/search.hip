@@ -614,6 +614,14 @@ mcts_tree_kernel(MctsArgs a)
     uint32_t n_net = 0u, n_played = 0u, n_sampler_fallback = 0u, deepest = 0u;   // statistics
     bool failed = false, have_fallback = false;
     uint64_t cyc[4] = {0u, 0u, 0u, 0u};   // shader clock per phase (statistics)
+    // with network leaves the statistics stay in vector registers, out of
+    // the scalar ones, which the network's evaluation also needs (the playout
+    // kernels have no vector registers to spare)
+    auto cyc_add = [&](uint32_t k, uint64_t d) __attribute__((always_inline)) {
+        const uint64_t v = cyc[k] + d;
+        cyc[k] = VALUE ? (uint64_t)in_vgpr((uint32_t)v) | ((uint64_t)in_vgpr((uint32_t)(v >> 32)) << 32)
+                       : v;
+    };
     // Worlds of iterations ib .. ib + 63, sampled together (lane l: iteration
     // ib + l) at every 64th iteration: the world's rows as owner bit-planes,
     // and the lanes whose iteration has a world (the others take the
@@ -935,7 +943,7 @@ mcts_tree_kernel(MctsArgs a)
                     break;
                 }
             }
-            cyc[0] += clock64() - t0;
+            cyc_add(0u, clock64() - t0);
         };
         sample_pass(0u);
         __syncthreads();   // the first pass's worlds
@@ -945,7 +953,7 @@ mcts_tree_kernel(MctsArgs a)
                 const uint64_t t2 = clock64();
                 eval_pass(buf, ip, a.iters - ip < a.lpp ? a.iters - ip : a.lpp,
                           meta_all[wv][buf][0], meta_all[wv][buf][1]);
-                cyc[2] += clock64() - t2;
+                cyc_add(2u, clock64() - t2);
             }
             sample_pass(k + 1u);
             __syncthreads();
@@ -1008,7 +1016,7 @@ mcts_tree_kernel(MctsArgs a)
                 S.drawn = in_vgpr(S.drawn);
             }
             const uint64_t t1 = clock64();
-            cyc[0] += t1 - t0;
+            cyc_add(0u, t1 - t0);
             // ---- 2. descend ----------------------------------------------------
             const Words cw = philox(lane, 0xC0000000u, it, tr, a.k0, a.k1);
             // Append a child {ex | ..., 0, ez, id} to `parent` (child count nc);
@@ -1239,7 +1247,7 @@ mcts_tree_kernel(MctsArgs a)
             }
             if (!term && cont) leaf_continue_coin(S, chance_at(cw, last_block));
             deepest = np - a.vanilla > deepest ? np - a.vanilla : deepest;
-            cyc[1] += clock64() - t1;
+            cyc_add(1u, clock64() - t1);
             if (!PIPE && a.lpp == 1u) {
                 // the sequential search: the leaf is evaluated and backed up
                 // before the next descent
@@ -1323,7 +1331,7 @@ mcts_tree_kernel(MctsArgs a)
                 }
 
                 const uint64_t t3 = clock64();
-                cyc[2] += t3 - t2;
+                cyc_add(2u, t3 - t2);
                 // ---- 4. back-propagation --------------------------------------------
                 n_root += nplay;
                 uint32_t e = 0u, nw = 0u;
@@ -1343,7 +1351,7 @@ mcts_tree_kernel(MctsArgs a)
                     rc_update(rc_slot(__builtin_amdgcn_readlane(e, 0)), nplay, true,
                               __builtin_amdgcn_readlane(nw, 0));
                 tree_sync<WS>();
-                cyc[3] += clock64() - t3;
+                cyc_add(3u, clock64() - t3);
                 continue;
             }
             // the leaf and its path, for the evaluation and the wins
@@ -1377,7 +1385,7 @@ mcts_tree_kernel(MctsArgs a)
                 const uint32_t ip = (k - 1u) * a.lpp;
                 const uint64_t t3 = clock64();
                 backprop_pass(buf ^ 1u, a.iters - ip < a.lpp ? a.iters - ip : a.lpp);
-                cyc[3] += clock64() - t3;
+                cyc_add(3u, clock64() - t3);
             }
             continue;
         }
@@ -1386,9 +1394,9 @@ mcts_tree_kernel(MctsArgs a)
         const uint64_t t2 = clock64();
         eval_pass(0u, i0, nb, term_mask, winners);
         const uint64_t t3 = clock64();
-        cyc[2] += t3 - t2;
+        cyc_add(2u, t3 - t2);
         backprop_pass(0u, nb);
-        cyc[3] += clock64() - t3;
+        cyc_add(3u, clock64() - t3);
     }
     if (PIPE) {
         __syncthreads();   // the evaluating wavefront's statistics
