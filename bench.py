@@ -10,7 +10,9 @@ synthetic and resident in HBM before timing starts.
 
 Prints one JSON line.  `value` is playouts/s of the whole step; `roofline`
 prices the dominant kernel (the rollout kernel, one playout per lane at this
-size) against the integer-VALU issue peak of the chip; `cpu_baseline` is the
+size) against the integer-VALU issue peak of the chip, from its average
+duration between HIP events around it in every fourth timed step
+(`--event-every`: a pair of events costs a step a few microseconds); `cpu_baseline` is the
 CPU oracle timed on this host's cores on a bounded sample of the same
 workload.  Side figures: batched search (as configured, with two leaves per
 pass, also pipelined, and with the shape the library's search autotuner
@@ -127,6 +129,9 @@ def parse():
     ap.add_argument("--no-value", action="store_true",
                     help="skip value-network training and the value-vs-playout search")
     ap.add_argument("--copy-mib", type=int, default=0, help="copy a buffer of this size (MiB)")
+    ap.add_argument("--event-every", type=int, default=4,
+                    help="bracket the rollout kernel of every N-th timed step with HIP events "
+                         "(each pair costs the step a few microseconds of GPU time)")
     ap.add_argument("--valu-probe", action="store_true",
                     help="also measure the issue rate of the integer operations of a guess step")
     ap.add_argument("--cpu-sweep", action="store_true",
@@ -428,8 +433,9 @@ def main():
         dst = torch.empty_like(src)
     guesses = int(length.to(torch.int64).sum().item())
     lens = length.float()
+    every = max(1, args.event_every)
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(args.steps)]
+           if k % every == 0 else None for k in range(args.steps)]
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     start.record(stream)
@@ -444,7 +450,7 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
     ms_total = start.elapsed_time(stop)
-    kern_ms = [a.elapsed_time(b) for a, b in evs]
+    kern_ms = [e[0].elapsed_time(e[1]) for e in evs if e is not None]
     ms_step = ms_total / args.steps
     kern_avg_s = sum(kern_ms) / len(kern_ms) / 1e3
     value = total / (ms_step / 1e3)
@@ -473,6 +479,8 @@ def main():
                      "unit": "TOP/s", "frac": achieved / INT_VALU_PEAK,
                      "traffic": profiled_traffic_bytes()},
         "rollout_kernel_ms": kern_avg_s * 1e3,
+        "rollout_kernel_timing": f"HIP events on the launch stream around the rollout kernel of "
+                                 f"{len(kern_ms)} of the {args.steps} timed steps (every {every}th)",
         "guess_steps_per_launch": guesses,
         "mean_game_length": float(lens.mean().item()),
         "wall_s": wall,
