@@ -277,6 +277,23 @@ def value_vs_rollout():
     return out
 
 
+def gpu_info(torch):
+    """The device and its clocks as rocm-smi reports them after the timed steps
+    (best effort: None where the tool is missing or prints something else)."""
+    import subprocess
+    p = torch.cuda.get_device_properties(0)
+    out = {"name": p.name, "compute_units": p.multi_processor_count,
+           "gcn_arch": getattr(p, "gcnArchName", None), "clocks": None}
+    try:
+        r = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True, text=True,
+                           timeout=20)
+        card = next(iter(json.loads(r.stdout).values()))
+        out["clocks"] = {k: v for k, v in card.items() if "clock" in k.lower()}
+    except Exception:
+        pass
+    return out
+
+
 def host_cpu():
     """(CPU model, physical cores among the CPUs this process may run on)."""
     model, cores, phys, core = "unknown", set(), None, None
@@ -484,6 +501,7 @@ def main():
         "guess_steps_per_launch": guesses,
         "mean_game_length": float(lens.mean().item()),
         "wall_s": wall,
+        "gpu": gpu_info(torch),
     }
     if args.valu_probe:
         out["roofline"]["probe_TOPs"] = valu_probe(torch)
