@@ -56,12 +56,19 @@ FLOP_PER_ROW_TRAIN = 2 * (160 * 256 + 256 * 256 + 256) + 2 * 256 * 256 * 2 + 2 *
 ROOT_DEAL = dict(p_min=2, p_max=4, hand=(0, 0, 4, 4, 3), fresh=1, root_draw=1)
 
 
-def timed_search(roots, mp, seed, ws):
+def timed_search(roots, mp, seed, ws, wall=None):
+    """One launch: (decisions, GPU seconds between HIP events around it).  With
+    a list `wall`, also appends the host seconds from the call to the decisions
+    read back to host memory."""
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
+    t0 = time.perf_counter()
     e0.record()
     best, _ = mcts_search(roots, mp, seed, workspace=ws, want_children=False)
     e1.record()
+    if wall is not None:
+        best.cpu()
+        wall.append(time.perf_counter() - t0)
     torch.cuda.synchronize()
     return best, e0.elapsed_time(e1) / 1e3
 
@@ -77,12 +84,12 @@ def value_mse(net, n=4096, playouts=4096, seed=99, index_base=1 << 28):
     return mse, floor
 
 
-def median_search(roots, mp, seed, ws, reps=3):
+def median_search(roots, mp, seed, ws, reps=3, wall=None):
     """One warm-up launch, then `reps` timed launches: (decisions, median seconds)."""
     mcts_search(roots, mp, seed, workspace=ws, want_children=False)
     ts, best = [], None
     for _ in range(reps):
-        best, t = timed_search(roots, mp, seed, ws)
+        best, t = timed_search(roots, mp, seed, ws, wall)
         ts.append(t)
     return best, sorted(ts)[len(ts) // 2]
 
@@ -145,7 +152,8 @@ def compare(n_trees=1024, iterations=4096, ppl=64, band=0.05, train_cfg: TrainCo
     mp_val3 = mcts_params(iterations=iterations, playouts_per_leaf=1, max_depth=4, leaf_eval=1,
                           fallback_band=band, fallback_playouts=ppl, valuenet=net,
                           leaves_per_pass=lpp, pipeline=1)
-    best_val3, t_val3 = median_search(roots, mp_val3, seed, ws, reps)
+    wall_val3 = []
+    best_val3, t_val3 = median_search(roots, mp_val3, seed, ws, reps, wall_val3)
     mp_roll3 = mcts_params(iterations=iterations, playouts_per_leaf=ppl, max_depth=4, pipeline=1)
     best_roll3, t_roll3 = median_search(roots, mp_roll3, seed, ws, reps)
     # against a high-budget reference (a playout search with four times the
@@ -211,6 +219,7 @@ def compare(n_trees=1024, iterations=4096, ppl=64, band=0.05, train_cfg: TrainCo
             "root_move_agreement": float((best_val3 == best_roll).float().mean().item()),
             "decisions_per_s": n_trees / t_val3,
             "gpu_s_per_decision": t_val3 / n_trees, "speedup": t_roll / t_val3,
+            "wall_s_per_decision": sorted(wall_val3)[len(wall_val3) // 2] / n_trees,
             "rollout_decisions_per_s": n_trees / t_roll3,
             "rollout_gpu_s_per_decision": t_roll3 / n_trees,
             "rollout_agreement_with_sequential": float((best_roll3 == best_roll).float()
