@@ -8,6 +8,11 @@ pass of the hot path over that batch: generate the leaf states on the GPU
 game length (int16) and per-leaf seat wins (dvc_rollout).  Inputs are
 synthetic and resident in HBM before timing starts.
 
+By default 400 steps (about 45 ms) are timed: the first milliseconds after
+the synchronize before the timed region run slower (a 50-step region
+measures about 4 % less throughput, with the kernel itself slower), so a
+longer region measures the steady state.
+
 Prints one JSON line.  `value` is playouts/s of the whole step; `roofline`
 prices the dominant kernel (the rollout kernel, one playout per lane at this
 size) against the integer-VALU issue peak of the chip, from its average
@@ -119,7 +124,7 @@ def profiled_traffic_bytes():
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--variant", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
@@ -463,6 +468,11 @@ def main():
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            if k % every == 0 else None for k in range(args.steps)]
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    # torch creates a HIP event at its first record: create them all here,
+    # outside the timed region
+    for e in [(start, stop)] + [e for e in evs if e is not None]:
+        e[0].record(stream)
+        e[1].record(stream)
     torch.cuda.synchronize()
     start.record(stream)
     t0 = time.perf_counter()
