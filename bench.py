@@ -77,7 +77,7 @@ PROFILED_TRAFFIC = {"fetch_kib": 389.0, "fetch_scale": 2.0, "write_kib": 3200.0,
 # VMEM + branch), keyed by (playouts per leaf, leaves per pass, pipeline);
 # valid only for the tree-kernel sources they were taken on.
 PROFILED_SEARCH = {"instructions_per_tree_iteration": {(32, 1, 0): 4749, (32, 2, 1): 3465},
-                   "sources_sha256": "93a3dd76a4b1ca581c47717998599481ea8b892a6af3a210e8d7f9c5515417af"}
+                   "sources_sha256": "eeecd58f2c4c6f297fc5597b0d03fd7363da26774ab592b43d6eada116c10273"}
 SEARCH_SOURCES = ["paper_2403_10720_amd/csrc/dvc_core.hpp",
                   "paper_2403_10720_amd/csrc/dvc_internal.hpp",
                   "paper_2403_10720_amd/csrc/search.hip"]

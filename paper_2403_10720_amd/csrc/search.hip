@@ -398,21 +398,6 @@ __device__ __forceinline__ uint32_t in_vgpr(uint32_t v)
     return r;
 }
 
-__device__ __forceinline__ State readlane_state(const State &s, uint32_t lane)
-{
-    State r;
-    r.h0 = __builtin_amdgcn_readlane(s.h0, lane);
-    r.h1 = __builtin_amdgcn_readlane(s.h1, lane);
-    r.h2 = __builtin_amdgcn_readlane(s.h2, lane);
-    r.h3 = __builtin_amdgcn_readlane(s.h3, lane);
-    r.rev = __builtin_amdgcn_readlane(s.rev, lane);
-    r.m = __builtin_amdgcn_readlane(s.m, lane);
-    r.P = __builtin_amdgcn_readlane(s.P, lane);
-    r.phase = __builtin_amdgcn_readlane(s.phase, lane);
-    r.drawn = __builtin_amdgcn_readlane(s.drawn, lane);
-    return r;
-}
-
 // greater of two scores (no NaN arises: every visited child has N >= 1)
 __device__ __forceinline__ float score_max(float a, float b) { return a > b ? a : b; }
 
@@ -615,8 +600,9 @@ mcts_tree_kernel(MctsArgs a)
     bool failed = false, have_fallback = false;
     uint64_t cyc[4] = {0u, 0u, 0u, 0u};   // shader clock per phase (statistics)
     // with network leaves the statistics stay in vector registers, out of
-    // the scalar ones, which the network's evaluation also needs (the playout
-    // kernels have no vector registers to spare)
+    // the scalar ones, which the network's evaluation also needs (measured
+    // faster); the playout kernels keep them scalar (in vector registers they
+    // pushed the sequential kernel past 128 registers, into scratch)
     auto cyc_add = [&](uint32_t k, uint64_t d) __attribute__((always_inline)) {
         const uint64_t v = cyc[k] + d;
         cyc[k] = VALUE ? (uint64_t)in_vgpr((uint32_t)v) | ((uint64_t)in_vgpr((uint32_t)(v >> 32)) << 32)
