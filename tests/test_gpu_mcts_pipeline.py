@@ -194,3 +194,30 @@ def test_pipelined_root_parallel(orc, dvc):
     assert np.array_equal(act.numpy(), m_ref["action"].astype(np.int64))
     assert np.array_equal(n.numpy(), m_ref["n"].astype(np.int64))
     assert np.array_equal(w.numpy().view(np.uint32), m_ref["w"].view(np.uint32))
+
+
+def test_full_batch_in_the_timed_launch_sampled(orc, dvc):
+    """The launch the benchmark times: all 2048 roots of the batched workload
+    (2-4 players, hands 4/4/3, pool 0-16, 0-8 revealed, root draw), 1024
+    iterations x 32 playouts, depth 4, two leaves per pass, pipelined.  Every
+    64th tree, and the four slowest (the most fallback worlds: 1610, 1983;
+    descents that reach the depth threshold: 1440, 1545), node by node
+    against the oracle's search of that tree alone."""
+    roots = _roots(orc, 2048, 3, pile_max=16, revealed_max=8)
+    kw = dict(iterations=1024, playouts_per_leaf=32, max_depth=4, leaves_per_pass=2, pipeline=1)
+    md, mo = dvc.mcts_params(**kw), orc.mcts_params(**kw)
+    per_tree = dvc.dvc_mcts_workspace_bytes(1, md)
+    ws = torch.empty(per_tree * len(roots), dtype=torch.uint8, device="cuda")
+    best, _ = dvc.mcts_search(dev_states(roots), md, 3, 0, workspace=ws, want_children=False)
+    torch.cuda.synchronize()
+    assert dvc.dvc_check() == 0
+    best = best.cpu().numpy()
+    fallbacks = 0
+    for t in sorted(set(range(0, 2048, 64)) | {1440, 1545, 1610, 1983}):
+        got = gpu_tree.trees(ws[t * per_tree:(t + 1) * per_tree], 1, per_tree, 1024)[0]
+        ref_best, ref = orc.mcts_tree(roots[t], mo, 3, t)
+        print(f"tree {t}: {len(ref)} nodes", flush=True)
+        gpu_tree.assert_same_tree(got, ref)
+        assert int(best[t]) == ref_best
+        fallbacks += sum(1 for i in (0, 511, 1023) if orc.determinize(roots[t], 3, t, i)[1] == 64)
+    assert fallbacks > 0   # the sample reaches the sampler's fallback world
