@@ -221,3 +221,32 @@ def test_full_batch_in_the_timed_launch_sampled(orc, dvc):
         assert int(best[t]) == ref_best
         fallbacks += sum(1 for i in (0, 511, 1023) if orc.determinize(roots[t], 3, t, i)[1] == 64)
     assert fallbacks > 0   # the sample reaches the sampler's fallback world
+
+
+def test_value_search_full_batch_in_the_timed_launch_sampled(orc, dvc):
+    """The value search as the benchmark times it: 1024 fresh 2-4 player deals
+    with the root draw, 4096 iterations, depth 4, network leaves with the
+    0.05 playout band (64 playouts), four leaves per pass, pipelined; the
+    integer network makes the GPU's and the oracle's values equal.  Trees 0,
+    341, 682 and 1023 node by node against the oracle's search of each alone."""
+    p = exact_net.params()
+    net = dvc.dvc_valuenet_init(0)
+    dvc.dvc_valuenet_set_params(net, torch.from_numpy(p).cuda())
+    roots = orc.init_states(1024, orc.deal_params(p_min=2, p_max=4, hand=(0, 0, 4, 4, 3),
+                                                  fresh=1, root_draw=1), seed=5)
+    mo = orc.mcts_params(**_value_kw(p, 0.05, 4096, 4, 4))
+    md = dvc.mcts_params(**_value_kw(net, 0.05, 4096, 4, 4))
+    per_tree = dvc.dvc_mcts_workspace_bytes(1, md)
+    ws = torch.empty(per_tree * len(roots), dtype=torch.uint8, device="cuda")
+    best, _ = dvc.mcts_search(dev_states(roots), md, 5, 0, workspace=ws, want_children=False)
+    torch.cuda.synchronize()
+    assert dvc.dvc_check() == 0
+    best = best.cpu().numpy()
+    stats = dvc.mcts_tree_stats(ws, len(roots), md)
+    assert int(stats["played_leaves"].sum()) > 0 and int(stats["net_leaves"].sum()) > 0
+    for t in (0, 341, 682, 1023):
+        got = gpu_tree.trees(ws[t * per_tree:(t + 1) * per_tree], 1, per_tree, 4096)[0]
+        ref_best, ref = orc.mcts_tree(roots[t], mo, 5, t)
+        print(f"tree {t}: {len(ref)} nodes", flush=True)
+        gpu_tree.assert_same_tree(got, ref)
+        assert int(best[t]) == ref_best
