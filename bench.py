@@ -68,9 +68,9 @@ OPS_PER_GUESS = 222
 # scaled by what the same counter reads for a plain 256 MiB device copy
 # (FETCH_SIZE reads half the bytes moved, WRITE_SIZE all of them).  Valid
 # only for the kernel sources it was taken on: reported as null otherwise.
-PROFILED_TRAFFIC = {"fetch_kib": 389.0, "fetch_scale": 2.0, "write_kib": 3200.0,
+PROFILED_TRAFFIC = {"fetch_kib": 400.5, "fetch_scale": 2.0, "write_kib": 3200.0,
                     "write_scale": 1.0,
-                    "sources_sha256": "4a5602a6a9b36d960a77f1f55cb6796c32ec8d0035adf9a5417c391051190a14"}
+                    "sources_sha256": "8f5c798da1bdf421cc7236fcff008f8315034d9863134c491d75a1da3f598c77"}
 # Instructions one tree issues per iteration in the batched search (both
 # wavefronts of a pipelined tree), from the SQ instruction counters of a
 # profiler pass over `experiments --what phases` (VALU + SALU + LDS + SMEM +
@@ -508,7 +508,7 @@ def main():
                                "playouts (pool 0-16, 0-8 revealed per row)",
                    "leaves": N_LEAVES, "playouts_per_leaf": PPL, "seed": SEED,
                    # 0/0/0 is the library's automatic shape at this size: variant 7
-                   # (compacted at steps 5, 8, 11, 14)
+                   # (compacted at steps 5, 8, 11, 14, 17)
                    "variant": args.variant or 7, "block": args.block,
                    "grid": args.grid if args.variant else 2},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": INT_VALU_PEAK / 1e12,

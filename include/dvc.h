@@ -138,7 +138,7 @@ int dvc_rollout(const dvc_state_t *leaves, int64_t n_leaves, int32_t playouts_pe
 
 /* dvc_rollout with a choice of kernel, for measurement.  variant: 0 =
  * automatic (the shape dvc_rollout_autotune chose for this size class, else
- * up to 2M playouts variant 7 with steps 5, 8, 11, 14, up to 4M variant 9
+ * up to 2M playouts variant 7 with steps 5, 8, 11, 14, 17, up to 4M variant 9
  * with 512 playouts per workgroup; above, variant 5 if playouts_per_leaf >=
  * 256, else variant 9 with 512), 1 = one lane per playout,
  * 2 = lane refill + work stealing over LDS-staged leaf chunks, 3 = lane
@@ -150,8 +150,8 @@ int dvc_rollout(const dvc_state_t *leaves, int64_t n_leaves, int32_t playouts_pe
  * random words computed during the step before, 7 = one playout per lane
  * with the workgroup's unfinished games packed into its first lanes at
  * fixed step counts (Sec. IV-B's divergence: wavefronts left without a game
- * stop issuing; `grid` 0/1 = steps 6, 9, 12, 2 = steps 5, 8, 11, 14),
- * 8 = variant 7 (steps 5, 8, 11, 14) with two games per lane advanced
+ * stop issuing; `grid` 0/1 = steps 6, 9, 12, 2 = steps 5, 8, 11, 14, 17),
+ * 8 = variant 7 (steps 5, 8, 11, 14, 17) with two games per lane advanced
  * together, 512 playouts per workgroup, 9 = variant 7's packing every four
  * guesses, the lanes it frees starting the workgroup's next playouts
  * (`grid` gives the workgroup's 256-playout batches, 1 or 2, default 2).
@@ -167,7 +167,7 @@ int dvc_rollout_ex(const dvc_state_t *leaves, int64_t n_leaves, int32_t playouts
                    int32_t variant, int32_t block, int32_t grid, int32_t flags, void *stream);
 
 /* dvc_rollout_autotune -- runs this batch with every rollout kernel shape in
- * a fixed candidate list (variant 7 with steps 5, 8, 11, 14, variant 9
+ * a fixed candidate list (variant 7 with steps 5, 8, 11, 14, 17, variant 9
  * with 512 and 256 playouts per workgroup, variant 8, variant 4 with 1 or 2
  * playouts per lane, variant 1, variant 5 with 128/256/512-playout items),
  * each launched twice with the

@@ -293,7 +293,7 @@ static Shape automatic_shape(uint64_t total, int32_t ppl)
     }
     // measured on gfx950 (two-player mid-game leaves): up to 2M playouts one
     // playout per lane with the workgroup's unfinished games packed at steps
-    // 5, 8, 11, 14 (variant 7; 0.107 ms at 1M in the bench step, the same as
+    // 5, 8, 11, 14, 17 (variant 7; 0.107 ms at 1M in the bench step, the same as
     // variant 9 with 256 playouts per workgroup, 0.122 ms for variant 4); up
     // to 4M the games packed every four guesses and the freed lanes refilled,
     // 512 playouts per workgroup (variant 9; 0.339 vs 0.357 ms for variant 7);

@@ -608,8 +608,8 @@ __global__ void __launch_bounds__(256) rollout_static(RolloutArgs a)
 // and seat wins are written per original slot exactly as variant 4 writes
 // them, so every output equals the other variants'.
 // ---------------------------------------------------------------------------
-constexpr uint32_t kCompactSched[2][4] = {{6u, 9u, 12u, 0u}, {5u, 8u, 11u, 14u}};
-constexpr int kCompactCount[2] = {3, 4};
+constexpr uint32_t kCompactSched[2][5] = {{6u, 9u, 12u, 0u, 0u}, {5u, 8u, 11u, 14u, 17u}};
+constexpr int kCompactCount[2] = {3, 5};
 
 // the packed format of a state already checked by decode()
 __device__ __forceinline__ void unpack_valid(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3,
@@ -753,7 +753,7 @@ __global__ void __launch_bounds__(256) rollout_compact(RolloutArgs a)
 // lives in lane k / 2 (k even: first game, odd: second).  Both games of a
 // lane run every step; a finished game's step is computed and discarded (its
 // outcome was recorded when it ended), so the step needs no branch.  At
-// steps 5, 8, 11, 14 the workgroup packs its unfinished games into its first
+// steps 5, 8, 11, 14, 17 the workgroup packs its unfinished games into its first
 // slots, in slot order, exactly as variant 7 does with one game per lane, so
 // a wavefront whose 128 slots are empty stops issuing.  Outputs per original
 // slot, identical to every other variant's.
@@ -1194,7 +1194,7 @@ hipError_t launch_rollout(const RolloutArgs &a, int variant, int block, int grid
     }
     if (variant == 7) {
         // one playout per lane, compacted at steps 6, 9, 12 (grid 0 or 1) or
-        // 5, 8, 11, 14 (grid 2)
+        // 5, 8, 11, 14, 17 (grid 2)
         const uint32_t blocks = (a.total + 255u) / 256u;
         if (grid == 2)
             hipLaunchKernelGGL(rollout_compact<1>, dim3(blocks), dim3(256), 0, st, a);
@@ -1203,7 +1203,7 @@ hipError_t launch_rollout(const RolloutArgs &a, int variant, int block, int grid
         return hipGetLastError();
     }
     if (variant == 8) {
-        // two games per lane, compacted at steps 5, 8, 11, 14
+        // two games per lane, compacted at steps 5, 8, 11, 14, 17
         const uint32_t blocks = (a.total + 511u) / 512u;
         hipLaunchKernelGGL(rollout_compact2, dim3(blocks), dim3(256), 0, st, a);
         return hipGetLastError();
